@@ -1,0 +1,239 @@
+/*
+ * slm.h -- C ABI of libslm.so, the MI355X (gfx950) per-node split search of
+ * the accelerated Subspace Learning Machine (Fu et al., "Acceleration of
+ * Subspace Learning Machine via Particle Swarm Optimization and Parallel
+ * Processing", arXiv 2208.07023).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array arguments are DEVICE pointers owned by the caller, unless marked
+ *   [host].  The library never frees, retains or reallocates caller memory.
+ * - Matrices are row-major and densely packed.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *   are asynchronous on that stream unless documented as synchronous.
+ * - Every call validates its arguments on the host before launching anything;
+ *   on failure it returns a non-zero slm_status, launches nothing and leaves a
+ *   message for slm_last_error().  Nothing throws across the ABI.
+ * - Segments: node j owns rows row_off[j] .. row_off[j+1]-1 of X / Z / target
+ *   and particles j*P .. j*P+P-1 of W / x / v / pbest.  Offsets are int64
+ *   device arrays; kernels clamp every offset to [0, N] and treat an inverted
+ *   range as empty, so bad offsets cannot cause out-of-bounds accesses.
+ * - Sizes: N < 2^31 rows, 1 <= D <= 4096, 1 <= P <= 4096, n_nodes >= 0.
+ */
+#ifndef SLM_H
+#define SLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SLM_OK = 0,
+  SLM_E_INVALID = 1,     /* null pointer, negative size, bad enum value     */
+  SLM_E_SHAPE = 2,       /* inconsistent or out-of-range sizes              */
+  SLM_E_DTYPE = 3,       /* unsupported dtype or dtype combination          */
+  SLM_E_NOMEM = 4,       /* workspace too small / device allocation failed  */
+  SLM_E_HIP = 5,         /* a HIP runtime call failed (message has details) */
+  SLM_E_UNSUPPORTED = 6  /* valid request this build does not implement     */
+} slm_status;
+
+typedef enum { SLM_F32 = 0, SLM_BF16 = 1, SLM_F64 = 2, SLM_I32 = 3 } slm_dtype;
+
+/* Split criteria (the loss of the best threshold of a projected feature,
+ * Sec. III-B): weighted Gini impurity, weighted base-2 entropy, weighted
+ * squared error.  The loss of a split is the children's impurity weighted by
+ * their sample counts and divided by the node's count. */
+typedef enum { SLM_GINI = 0, SLM_ENTROPY = 1, SLM_MSE = 2 } slm_criterion;
+
+/* Library version string (static storage). */
+const char *slm_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  Valid until
+ * the next slm_* call on the same thread. */
+const char *slm_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * slm_project -- projected features Z = X W^T per node (Sec. II-A, Eq. (1)).
+ *
+ *   Z[i, p] = sum_d X[i, d] * W[j*P + p, d]   for every row i of node j,
+ *   zmin[j*P + p] = min over node j's rows of Z[i, p], zmax likewise.
+ *
+ * X [N, D] and W [n_nodes*P, D] are both F32 or both BF16; products are
+ * accumulated in FP32 on the matrix cores.  Z [N, P] is FP32.  Rows outside
+ * every segment are not written.  For an empty node zmin = +inf, zmax = -inf.
+ * A -0.0 projection is recorded in zmin/zmax as +0.0 (the two compare equal
+ * and give identical bin edges).  Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D,
+                       const void *W, int32_t w_dtype,
+                       const int64_t *row_off, int32_t n_nodes, int32_t P,
+                       float *Z, float *zmin, float *zmax, void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_split_scan -- best threshold of every projected feature (Sec. II-A,
+ * Eqs. (3)-(4): samples with z >= t go right, z < t go left; Sec. III-B: the
+ * loss of a direction is the loss of its best threshold).
+ *
+ * bins = 0: exact scan.  Candidates are the boundaries between consecutive
+ *   distinct sorted values of a node's column; the threshold is the smallest
+ *   value sent right and best_split is the number of samples sent left.
+ *   Synchronous (reads row_off back); nodes must hold <= 8192 rows.
+ * bins in [2, 256]: histogram scan.  With r = zmax - zmin and
+ *   delta = r / bins (float32, each operation rounded once), the edges are
+ *   e_j = zmin + j * delta for j = 1..bins-1 and a sample's bin is the number
+ *   of edges <= z.  Split b (1..bins-1) sends bins < b left; threshold = e_b;
+ *   best_split = b.  zmin/zmax are those written by slm_project.
+ *   Asynchronous.
+ * Ties between candidates go to the smallest split; a candidate needs a
+ * sample on each side.  Without one: best_split = -1, best_loss = +inf,
+ * threshold = +inf.
+ *
+ * target: I32 labels in [0, K) for SLM_GINI / SLM_ENTROPY (rows with labels
+ *   outside [0, K) are ignored), 2 <= K <= 16; F64 y with K = 0 for SLM_MSE.
+ * Outputs [n_nodes*P]: best_split (i32), best_loss (f64), threshold (f32).
+ * hist_out (optional, histogram mode): per (node, particle) the bin counts,
+ *   [n_nodes*P, bins, K] u32 for classification or [n_nodes*P, bins] for MSE.
+ * sums_out (optional, MSE histogram mode): [n_nodes*P, bins, 2] f64
+ *   (sum y, sum y^2 per bin; FP64 atomics, last bits order-dependent).
+ * workspace: device scratch of at least slm_split_scan_workspace(...) bytes.
+ *   It must be zero-filled before its first use; every call leaves it
+ *   zero-filled again, so it can be reused across calls on one stream.
+ * ------------------------------------------------------------------------ */
+size_t slm_split_scan_workspace(int64_t N, int32_t n_nodes, int32_t P, int32_t bins,
+                                int32_t K, int32_t crit);
+slm_status slm_split_scan(const float *Z, const float *zmin, const float *zmax,
+                          const void *target, int32_t t_dtype, int32_t K, int64_t N,
+                          const int64_t *row_off, int32_t n_nodes, int32_t P,
+                          int32_t bins, int32_t crit,
+                          int32_t *best_split, double *best_loss, float *threshold,
+                          uint32_t *hist_out, double *sums_out,
+                          void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_pso_init -- initial swarm of every node (Sec. III-A: particles start
+ * at random positions; this build draws N(0, I) directions and scales them to
+ * unit norm, Eq. (2), with zero velocity).
+ *
+ * For particle p of node j, dimension pair m = d/2 uses one Philox4x32-10
+ * call (key = seed; counter = (p*ceil(D/2) + m, 0xFFFFFFFF, node_id[j],
+ * tree)); u1 = (w0 + 1/2) 2^-32, u2 = w1 2^-32 and the pair is
+ * sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).  Rows are then divided by their
+ * norm (squared norm summed in dimension order).
+ * Writes x, v = 0, pbest = x, pbest_loss = +inf, gbest = x of particle 0,
+ * gbest_loss = +inf, gbest_p = -1, and W_out = x rounded to w_dtype (F32 or
+ * BF16, round to nearest even).  Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss,
+                        double *gbest, double *gbest_loss, int32_t *gbest_p,
+                        const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
+                        uint64_t seed, uint32_t tree, void *W_out, int32_t w_dtype,
+                        void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_pso_step -- one synchronous swarm step for every node (Sec. III-A,
+ * Eqs. (11)-(12), Alg. 1).
+ *
+ * (1) Bests from `loss` (the losses of the current positions): pbest_p <- x_p
+ *     iff loss_p < pbest_loss_p; then p* = argmin_p loss_p (lowest p on ties)
+ *     replaces the global best iff loss_p* < gbest_loss.  When split/thr are
+ *     given, the winner's split and threshold are copied to gbest_split /
+ *     gbest_thr.
+ * (2) If move != 0: for every particle, with r1, r2 drawn per dimension from
+ *     Philox4x32-10 (key = seed, counter = (p*ceil(D/2) + d/2, iter,
+ *     node_id[j], tree); words 0,1 -> r1,r2 of dimension 2m, words 2,3 -> of
+ *     2m+1; r = (w >> 8) 2^-24):
+ *       v <- ((omega v) + ((c1 r1)(pbest - x))) + ((c2 r2)(gbest - x))
+ *       x <- (x + v) / ||x + v||   (x kept if the norm is 0)
+ *     each operation rounded once in FP64; W_out <- x rounded to w_dtype.
+ * Shapes: x, v, pbest [n_nodes*P, D]; pbest_loss, loss [n_nodes*P];
+ * gbest [n_nodes, D]; gbest_loss, gbest_p, node_id [n_nodes].
+ * split, thr, gbest_split, gbest_thr: optional ([n_nodes*P] / [n_nodes]).
+ * Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss,
+                        double *gbest, double *gbest_loss, int32_t *gbest_p,
+                        const double *loss, const int32_t *split, const float *thr,
+                        int32_t *gbest_split, float *gbest_thr,
+                        const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
+                        double omega, double c1, double c2, uint64_t seed, uint32_t tree,
+                        uint32_t iter, int32_t move, void *W_out, int32_t w_dtype,
+                        void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_grow_tree -- one binary SLM tree (Sec. III-B, Alg. 2) grown breadth
+ * first, all frontier nodes of a depth searched together.
+ *
+ * A node is split when depth < max_depth, it holds >= min_node rows and it is
+ * impure (classification: impurity > 0; regression: targets not all equal).
+ * Its swarm (P particles, T moves, T+1 evaluations; keyed by the node's heap
+ * id: root 0, children 2j+1 / 2j+2) searches directions; the split is kept
+ * iff the global-best loss is strictly below the node's impurity.  Rows with
+ * a^T x >= t go to the right child.  Leaves hold class counts or the mean.
+ *
+ * X [N, D] F32 (BF16 with precision = 1); target as in slm_split_scan.
+ * Output arrays are [host], sized for max_nodes nodes; nodes are numbered in
+ * breadth-first order (left child before right).  Synchronous: the host
+ * reads a few bytes of frontier state back once per depth.
+ * workspace: device scratch >= slm_grow_tree_workspace(prm, N, D) bytes; its
+ * contents on entry are ignored.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t crit;        /* slm_criterion                                 */
+  int32_t K;           /* classes (0 for SLM_MSE)                       */
+  int32_t max_depth;
+  int32_t min_node;
+  int32_t P;           /* particles per node                            */
+  int32_t T;           /* moves (T+1 evaluations)                       */
+  int32_t bins;        /* 2..256 (histogram scan); 0 = exact scan       */
+  int32_t precision;   /* 0 = FP32 projection                           */
+  double omega, c1, c2;
+  uint64_t seed;
+  uint32_t tree;
+  int32_t use_graph;   /* 1 = replay each depth's swarm loop as a HIP graph */
+  int32_t profile;     /* 1 = time every projection / scan / step launch with
+                          HIP events (fills timing[3..7]; no graph replay)    */
+} slm_tree_params;
+
+typedef struct {
+  int32_t max_nodes;   /* capacity of every array below                 */
+  int32_t n_nodes;     /* [out] nodes written                           */
+  float *w;            /* [max_nodes, D] split direction (FP32 image)   */
+  float *thr;          /* [max_nodes] threshold (+inf for leaves)       */
+  int32_t *left, *right;     /* child indices, -1 for leaves           */
+  double *leaf;        /* [max_nodes, max(K,1)] class counts or mean    */
+  int64_t *n;          /* rows per node                                 */
+  double *impurity;    /* node impurity                                 */
+  double *split_loss;  /* global-best loss (+inf if not searched)       */
+  int32_t *depth, *heap;
+  double *timing;      /* optional [8]: [0] whole call, [1] swarm loops,
+                          [2] partitions (ms); with profile = 1 also the
+                          summed kernel times of [3] projections, [4] scans,
+                          [5] swarm steps (ms), [6] projection launches,
+                          [7] scan launches                                */
+  int64_t *sample_splits;    /* optional [1]: sum over evaluations of n_j * P */
+} slm_tree_out;
+
+size_t slm_grow_tree_workspace(const slm_tree_params *prm, int64_t N, int32_t D);
+slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D,
+                         const void *target, int32_t t_dtype,
+                         const slm_tree_params *prm, void *workspace, size_t ws_bytes,
+                         slm_tree_out *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_predict -- route rows through a tree (Sec. II-A, Eqs. (3)-(4)):
+ * right iff float32(w . x) >= thr, the dot product accumulated in FP32 in
+ * dimension order.  Tree arrays are device copies of slm_tree_out's w, thr,
+ * left, right (n_tree nodes).  leaf_out [N] receives the index of the leaf
+ * reached.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_predict(const float *w, const float *thr, const int32_t *left,
+                       const int32_t *right, int32_t n_tree, int32_t D,
+                       const float *X, int64_t N, int32_t *leaf_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLM_H */

@@ -1,0 +1,336 @@
+"""Python binding of libslm.so (C ABI in include/slm.h).
+
+Argument marshalling only: every step of the split search runs in the HIP
+kernels of the library.  Tensors are torch device tensors (torch provides the
+device memory and the current HIP stream).  If the library is missing or no
+GPU is visible the calls raise; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslm.so")
+
+F32, BF16, F64, I32 = 0, 1, 2, 3
+GINI, ENTROPY, MSE = 0, 1, 2
+STATUS = {0: "SLM_OK", 1: "SLM_E_INVALID", 2: "SLM_E_SHAPE", 3: "SLM_E_DTYPE",
+          4: "SLM_E_NOMEM", 5: "SLM_E_HIP", 6: "SLM_E_UNSUPPORTED"}
+
+
+class SlmError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class TreeParams(ctypes.Structure):
+    _fields_ = [("crit", ctypes.c_int32), ("K", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("min_node", ctypes.c_int32), ("P", ctypes.c_int32), ("T", ctypes.c_int32),
+                ("bins", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("omega", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("tree", ctypes.c_uint32), ("use_graph", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
+
+
+class TreeOut(ctypes.Structure):
+    _fields_ = [("max_nodes", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
+                ("w", ctypes.c_void_p), ("thr", ctypes.c_void_p), ("left", ctypes.c_void_p),
+                ("right", ctypes.c_void_p), ("leaf", ctypes.c_void_p), ("n", ctypes.c_void_p),
+                ("impurity", ctypes.c_void_p), ("split_loss", ctypes.c_void_p),
+                ("depth", ctypes.c_void_p), ("heap", ctypes.c_void_p),
+                ("timing", ctypes.c_void_p), ("sample_splits", ctypes.c_void_p)]
+
+
+_lib = None
+_VP, _I32, _I64, _U32, _U64, _D, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                        ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
+                                        ctypes.c_size_t)
+
+_SIGS = {
+    "slm_version": ([], ctypes.c_char_p),
+    "slm_last_error": ([], ctypes.c_char_p),
+    "slm_project": ([_VP, _I32, _I64, _I32, _VP, _I32, _VP, _I32, _I32, _VP, _VP, _VP, _VP], _I32),
+    "slm_split_scan_workspace": ([_I64, _I32, _I32, _I32, _I32, _I32], _SZ),
+    "slm_split_scan": ([_VP, _VP, _VP, _VP, _I32, _I32, _I64, _VP, _I32, _I32, _I32, _I32,
+                        _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], _I32),
+    "slm_pso_init": ([_VP] * 7 + [_VP, _I32, _I32, _I32, _U64, _U32, _VP, _I32, _VP], _I32),
+    "slm_pso_step": ([_VP] * 7 + [_VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _I32, _D, _D, _D,
+                                  _U64, _U32, _U32, _I32, _VP, _I32, _VP], _I32),
+    "slm_grow_tree_workspace": ([ctypes.POINTER(TreeParams), _I64, _I32], _SZ),
+    "slm_grow_tree": ([_VP, _I32, _I64, _I32, _VP, _I32, ctypes.POINTER(TreeParams), _VP, _SZ,
+                       ctypes.POINTER(TreeOut), _VP], _I32),
+    "slm_predict": ([_VP, _VP, _VP, _VP, _I32, _I32, _VP, _I64, _VP, _VP], _I32),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libslm.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise SlmError(st, where, _lib.slm_last_error().decode())
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _xdtype(X):
+    if X.dtype == torch.float32:
+        return F32
+    if X.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError("X must be float32 or bfloat16")
+
+
+# ------------------------------------------------------------------ project
+def project(X, W, row_off, P: int):
+    """Z [N, P] = per-node X W^T, zmin/zmax [n_nodes*P] (Eq. (1))."""
+    load()
+    xt = _xdtype(X)
+    _dev(X, X.dtype, "X")
+    _dev(W, X.dtype, "W")
+    _dev(row_off, torch.int64, "row_off")
+    N, D = X.shape
+    nn = row_off.numel() - 1
+    Z = torch.empty((N, P), dtype=torch.float32, device=X.device)
+    zmin = torch.empty(nn * P, dtype=torch.float32, device=X.device)
+    zmax = torch.empty_like(zmin)
+    _check(_lib.slm_project(_p(X), xt, N, D, _p(W), xt, _p(row_off), nn, P, _p(Z), _p(zmin),
+                            _p(zmax), _stream()), "slm_project")
+    return Z, zmin, zmax
+
+
+# ------------------------------------------------------------------ split scan
+_ws_cache: dict = {}
+
+
+def scan_workspace(nbytes: int, device) -> torch.Tensor:
+    """A zero-filled scratch buffer reused across calls (each call leaves it
+    zero-filled again)."""
+    key = (str(device),)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def split_scan(Z, zmin, zmax, target, K: int, row_off, P: int, bins: int, crit: int,
+               hist: bool = False, sums: bool = False):
+    """Best threshold per (node, particle); see slm_split_scan."""
+    load()
+    _dev(Z, torch.float32, "Z")
+    _dev(row_off, torch.int64, "row_off")
+    N = Z.shape[0]
+    nn = row_off.numel() - 1
+    if crit == MSE:
+        _dev(target, torch.float64, "target")
+        tt = F64
+    else:
+        _dev(target, torch.int32, "target")
+        tt = I32
+    dev = Z.device
+    split = torch.empty(nn * P, dtype=torch.int32, device=dev)
+    loss = torch.empty(nn * P, dtype=torch.float64, device=dev)
+    thr = torch.empty(nn * P, dtype=torch.float32, device=dev)
+    kk = max(K, 1)
+    hist_t = torch.empty(nn * P * bins * kk, dtype=torch.int32, device=dev) if (hist and bins) else None
+    sums_t = torch.empty(nn * P * bins * 2, dtype=torch.float64, device=dev) if (sums and bins) else None
+    need = _lib.slm_split_scan_workspace(N, nn, P, bins, K, crit)
+    ws = scan_workspace(need, dev)
+    _check(_lib.slm_split_scan(_p(Z), _p(zmin) if bins else None, _p(zmax) if bins else None,
+                               _p(target), tt, K, N, _p(row_off), nn, P, bins, crit, _p(split),
+                               _p(loss), _p(thr), _p(hist_t), _p(sums_t), _p(ws), ws.numel(),
+                               _stream()), "slm_split_scan")
+    out = dict(split=split, loss=loss, thr=thr)
+    if hist_t is not None:
+        out["counts"] = hist_t.view(nn * P, bins, kk) if crit != MSE else hist_t.view(nn * P, bins)
+    if sums_t is not None:
+        out["sums"] = sums_t.view(nn * P, bins, 2)
+    return out
+
+
+# ------------------------------------------------------------------ swarm
+@dataclass
+class Swarm:
+    x: torch.Tensor
+    v: torch.Tensor
+    pbest: torch.Tensor
+    pbest_loss: torch.Tensor
+    gbest: torch.Tensor
+    gbest_loss: torch.Tensor
+    gbest_p: torch.Tensor
+    gbest_split: torch.Tensor
+    gbest_thr: torch.Tensor
+    W: torch.Tensor
+    node_id: torch.Tensor
+    P: int
+    D: int
+
+
+def pso_alloc(n_nodes: int, P: int, D: int, node_id, w_dtype=torch.float32, device="cuda"):
+    f = dict(dtype=torch.float64, device=device)
+    return Swarm(x=torch.empty(n_nodes * P, D, **f), v=torch.empty(n_nodes * P, D, **f),
+                 pbest=torch.empty(n_nodes * P, D, **f), pbest_loss=torch.empty(n_nodes * P, **f),
+                 gbest=torch.empty(n_nodes, D, **f), gbest_loss=torch.empty(n_nodes, **f),
+                 gbest_p=torch.empty(n_nodes, dtype=torch.int32, device=device),
+                 gbest_split=torch.full((n_nodes,), -1, dtype=torch.int32, device=device),
+                 gbest_thr=torch.full((n_nodes,), float("inf"), dtype=torch.float32, device=device),
+                 W=torch.empty(n_nodes * P, D, dtype=w_dtype, device=device),
+                 node_id=torch.as_tensor(node_id, dtype=torch.int32).to(device).contiguous(),
+                 P=P, D=D)
+
+
+def pso_init(sw: Swarm, seed: int, tree: int):
+    load()
+    nn = sw.node_id.numel()
+    wt = BF16 if sw.W.dtype == torch.bfloat16 else F32
+    _check(_lib.slm_pso_init(_p(sw.x), _p(sw.v), _p(sw.pbest), _p(sw.pbest_loss), _p(sw.gbest),
+                             _p(sw.gbest_loss), _p(sw.gbest_p), _p(sw.node_id), nn, sw.P, sw.D,
+                             seed, tree, _p(sw.W), wt, _stream()), "slm_pso_init")
+
+
+def pso_step(sw: Swarm, loss, omega, c1, c2, seed, tree, it, move, split=None, thr=None):
+    load()
+    nn = sw.node_id.numel()
+    wt = BF16 if sw.W.dtype == torch.bfloat16 else F32
+    _dev(loss, torch.float64, "loss")
+    _check(_lib.slm_pso_step(_p(sw.x), _p(sw.v), _p(sw.pbest), _p(sw.pbest_loss), _p(sw.gbest),
+                             _p(sw.gbest_loss), _p(sw.gbest_p), _p(loss), _p(split), _p(thr),
+                             _p(sw.gbest_split) if split is not None else None,
+                             _p(sw.gbest_thr) if thr is not None else None,
+                             _p(sw.node_id), nn, sw.P, sw.D, omega, c1, c2, seed, tree, it,
+                             int(bool(move)), _p(sw.W), wt, _stream()), "slm_pso_step")
+
+
+# ------------------------------------------------------------------ tree
+@dataclass
+class TreeConfig:
+    crit: int = ENTROPY
+    K: int = 3
+    max_depth: int = 8
+    min_node: int = 32
+    P: int = 256
+    T: int = 50
+    bins: int = 256
+    omega: float = 0.7
+    c1: float = 1.5
+    c2: float = 1.5
+    seed: int = 0
+    tree: int = 0
+    use_graph: bool = False
+    profile: bool = False
+
+    def c_params(self) -> TreeParams:
+        return TreeParams(self.crit, self.K, self.max_depth, self.min_node, self.P, self.T,
+                          self.bins, 0, self.omega, self.c1, self.c2, self.seed, self.tree,
+                          int(self.use_graph), int(self.profile))
+
+
+_tree_ws: dict = {}
+
+
+def tree_workspace(cfg: TreeConfig, N: int, D: int, device) -> torch.Tensor:
+    load()
+    prm = cfg.c_params()
+    need = _lib.slm_grow_tree_workspace(ctypes.byref(prm), N, D)
+    if need == 0:
+        raise SlmError(1, "slm_grow_tree_workspace", _lib.slm_last_error().decode())
+    key = str(device)
+    buf = _tree_ws.get(key)
+    if buf is None or buf.numel() < need:
+        _tree_ws.pop(key, None)
+        buf = torch.empty(need, dtype=torch.uint8, device=device)
+        _tree_ws[key] = buf
+    return buf
+
+
+def grow_tree(X, target, cfg: TreeConfig, workspace=None):
+    """One tree (Alg. 2); returns host numpy arrays of the nodes."""
+    load()
+    _dev(X, torch.float32, "X")
+    N, D = X.shape
+    if cfg.crit == MSE:
+        _dev(target, torch.float64, "target")
+        tt = F64
+    else:
+        _dev(target, torch.int32, "target")
+        tt = I32
+    ws = workspace if workspace is not None else tree_workspace(cfg, N, D, X.device)
+    maxn = 2 ** (cfg.max_depth + 1) - 1
+    maxn = int(min(maxn, 2 * max(1, N) + 1))
+    kk = max(cfg.K, 1)
+    arr = dict(w=np.zeros((maxn, D), np.float32), thr=np.zeros(maxn, np.float32),
+               left=np.zeros(maxn, np.int32), right=np.zeros(maxn, np.int32),
+               leaf=np.zeros((maxn, kk), np.float64), n=np.zeros(maxn, np.int64),
+               impurity=np.zeros(maxn), split_loss=np.zeros(maxn),
+               depth=np.zeros(maxn, np.int32), heap=np.zeros(maxn, np.int32),
+               timing=np.zeros(8), sample_splits=np.zeros(1, np.int64))
+    out = TreeOut(maxn, 0, *[arr[k].ctypes.data for k in
+                             ("w", "thr", "left", "right", "leaf", "n", "impurity", "split_loss",
+                              "depth", "heap", "timing", "sample_splits")])
+    prm = cfg.c_params()
+    _check(_lib.slm_grow_tree(_p(X), F32, N, D, _p(target), tt, ctypes.byref(prm), _p(ws),
+                              ws.numel(), ctypes.byref(out), _stream()), "slm_grow_tree")
+    n = out.n_nodes
+    res = {k: (v[:n] if k not in ("timing", "sample_splits") else v) for k, v in arr.items()}
+    res["n_nodes"] = n
+    res["K"] = cfg.K
+    return res
+
+
+def predict_leaves(tree: dict, X):
+    """Leaf index reached by each row (right iff float32 w.x >= thr)."""
+    load()
+    _dev(X, torch.float32, "X")
+    dev = X.device
+    w = torch.from_numpy(np.ascontiguousarray(tree["w"])).to(dev)
+    thr = torch.from_numpy(np.ascontiguousarray(tree["thr"])).to(dev)
+    left = torch.from_numpy(np.ascontiguousarray(tree["left"])).to(dev)
+    right = torch.from_numpy(np.ascontiguousarray(tree["right"])).to(dev)
+    out = torch.empty(X.shape[0], dtype=torch.int32, device=dev)
+    _check(_lib.slm_predict(_p(w), _p(thr), _p(left), _p(right), int(tree["n_nodes"]), X.shape[1],
+                            _p(X), X.shape[0], _p(out), _stream()), "slm_predict")
+    return out
+
+
+def predict(tree: dict, X):
+    """Class ids (argmax of the leaf counts) or regression means."""
+    leaves = predict_leaves(tree, X).cpu().numpy()
+    leaf = tree["leaf"][leaves]
+    if tree["K"] > 1:
+        return np.argmax(leaf, axis=1)
+    return leaf[:, 0]

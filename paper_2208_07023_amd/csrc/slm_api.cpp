@@ -1,0 +1,780 @@
+// C ABI of libslm.so: argument validation, workspace carving and the
+// breadth-first tree driver (Sec. III-B, Alg. 2).  Every numeric step runs in
+// the HIP kernels of this library; the host only sequences launches and reads
+// a few bytes of frontier state back per depth.
+#include "slm_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace slm {
+
+static thread_local char g_err[512] = "";
+static thread_local bool g_capturing = false;
+bool capturing() { return g_capturing; }
+void set_capturing(bool on) { g_capturing = on; }
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+
+namespace {
+
+constexpr int DMAX = 4096;
+constexpr int PMAX = 4096;
+
+inline hipStream_t S(void *s) { return static_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- workspace carving
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) / 256 * 256;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int64_t max_active(const slm_tree_params &p, int64_t N) {
+  if (p.max_depth <= 0) return 0;
+  const int64_t by_depth = p.max_depth - 1 >= 30 ? (1ll << 30) : (1ll << (p.max_depth - 1));
+  const int64_t by_size = std::max<int64_t>(1, N / std::max(1, p.min_node));
+  return std::max<int64_t>(1, std::min(by_depth, by_size));
+}
+
+struct TreeWS {
+  void *Xa, *Xb;
+  void *ta, *tb;
+  float *Z, *zsel, *zmin, *zmax;
+  double *x, *v, *pbest, *pbest_loss, *loss, *gbest, *gbest_loss;
+  void *W, *gW;
+  int32_t *split, *gbest_p, *gbest_split, *node_id, *do_split;
+  float *thr, *gbest_thr;
+  int64_t *beg, *end, *n_left, *off_left, *off_right;
+  uint64_t *seed_tree;
+  uint32_t *cnt_left;
+  TreeStats st;
+  void *scan_ws;
+  size_t scan_ws_bytes;
+  size_t total;
+};
+
+TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base) {
+  Carver c{static_cast<char *>(base)};
+  TreeWS w{};
+  const int64_t F = max_active(p, N);
+  const bool mse = p.crit == SLM_MSE;
+  const size_t xb = p.precision == 1 ? 2 : 4;
+  const int Kc = mse ? 1 : p.K;
+  w.Xa = c.take<char>((size_t)N * D * xb);
+  w.Xb = c.take<char>((size_t)N * D * xb);
+  w.ta = c.take<char>((size_t)N * (mse ? 8 : 4));
+  w.tb = c.take<char>((size_t)N * (mse ? 8 : 4));
+  w.Z = c.take<float>((size_t)N * p.P);
+  w.zsel = c.take<float>((size_t)N);
+  w.zmin = c.take<float>((size_t)F * p.P);
+  w.zmax = c.take<float>((size_t)F * p.P);
+  w.x = c.take<double>((size_t)F * p.P * D);
+  w.v = c.take<double>((size_t)F * p.P * D);
+  w.pbest = c.take<double>((size_t)F * p.P * D);
+  w.W = c.take<char>((size_t)F * p.P * D * xb);
+  w.pbest_loss = c.take<double>((size_t)F * p.P);
+  w.loss = c.take<double>((size_t)F * p.P);
+  w.split = c.take<int32_t>((size_t)F * p.P);
+  w.thr = c.take<float>((size_t)F * p.P);
+  w.gbest = c.take<double>((size_t)F * D);
+  w.gbest_loss = c.take<double>((size_t)F);
+  w.gbest_p = c.take<int32_t>((size_t)F);
+  w.gbest_split = c.take<int32_t>((size_t)F);
+  w.gbest_thr = c.take<float>((size_t)F);
+  w.gW = c.take<char>((size_t)F * D * xb);
+  w.beg = c.take<int64_t>((size_t)F);
+  w.end = c.take<int64_t>((size_t)F);
+  w.node_id = c.take<int32_t>((size_t)F);
+  w.do_split = c.take<int32_t>((size_t)F);
+  w.n_left = c.take<int64_t>((size_t)F);
+  w.seed_tree = c.take<uint64_t>(2);
+  const int64_t items = partition_items((int)F, N);
+  w.cnt_left = c.take<uint32_t>((size_t)items);
+  w.off_left = c.take<int64_t>((size_t)items);
+  w.off_right = c.take<int64_t>((size_t)items);
+  w.st.counts = c.take<uint32_t>((size_t)2 * F * Kc);
+  w.st.cnt = c.take<uint32_t>((size_t)2 * F);
+  w.st.s1 = c.take<double>((size_t)2 * F);
+  w.st.s2 = c.take<double>((size_t)2 * F);
+  w.st.ymin = c.take<unsigned long long>((size_t)2 * F);
+  w.st.ymax = c.take<unsigned long long>((size_t)2 * F);
+  w.scan_ws_bytes = p.bins ? scan_workspace_bytes(N, (int)F, p.P, p.bins, p.K, p.crit) : 256;
+  w.scan_ws = c.take<char>(w.scan_ws_bytes);
+  w.total = c.off + 256;
+  return w;
+}
+
+slm_status check_tree_params(const slm_tree_params *p, int64_t N, int32_t D) {
+  SLM_CHECK(p != nullptr, SLM_E_INVALID, "slm_grow_tree: params is NULL");
+  SLM_CHECK(N >= 1 && N < (1ll << 31), SLM_E_SHAPE, "slm_grow_tree: N = %lld out of range",
+            (long long)N);
+  SLM_CHECK(D >= 1 && D <= DMAX, SLM_E_SHAPE, "slm_grow_tree: D = %d out of range", D);
+  SLM_CHECK(p->crit >= 0 && p->crit <= 2, SLM_E_INVALID, "slm_grow_tree: bad criterion %d",
+            p->crit);
+  if (p->crit == SLM_MSE)
+    SLM_CHECK(p->K == 0, SLM_E_SHAPE, "slm_grow_tree: K must be 0 for SLM_MSE");
+  else
+    SLM_CHECK(p->K >= 2 && p->K <= 16, SLM_E_SHAPE, "slm_grow_tree: K = %d not in [2,16]", p->K);
+  SLM_CHECK(p->P >= 1 && p->P <= PMAX, SLM_E_SHAPE, "slm_grow_tree: P = %d out of range", p->P);
+  SLM_CHECK(p->T >= 0 && p->T <= 100000, SLM_E_SHAPE, "slm_grow_tree: T = %d out of range", p->T);
+  SLM_CHECK(p->bins == 0 || (p->bins >= 2 && p->bins <= 256), SLM_E_SHAPE,
+            "slm_grow_tree: bins = %d (0 or 2..256)", p->bins);
+  SLM_CHECK(p->max_depth >= 0 && p->max_depth <= 30, SLM_E_SHAPE,
+            "slm_grow_tree: max_depth = %d out of range", p->max_depth);
+  SLM_CHECK(p->min_node >= 1, SLM_E_SHAPE, "slm_grow_tree: min_node must be >= 1");
+  SLM_CHECK(p->precision == 0, SLM_E_UNSUPPORTED,
+            "slm_grow_tree: precision %d not supported by this build", p->precision);
+  return SLM_OK;
+}
+
+double nlog2n(double x) { return x > 0 ? x * std::log2(x) : 0.0; }
+
+// ---------------------------------------------------------------- host tree state
+struct HNode {
+  int idx;
+  int64_t beg, end;
+  int depth, heap;
+  double impurity;
+  bool impure;
+};
+
+struct StatsHost {
+  std::vector<uint32_t> counts, cnt;
+  std::vector<double> s1, s2;
+  std::vector<unsigned long long> ymin, ymax;
+};
+
+double dec_f64(unsigned long long e) {
+  const unsigned long long u = (e >> 63) ? (e & 0x7FFFFFFFFFFFFFFFull) : ~e;
+  double d;
+  std::memcpy(&d, &u, 8);
+  return d;
+}
+
+// impurity, purity flag and leaf value of stats entry i (same formulas as the
+// criteria: Gini (n - A/n)/n, entropy (n log2 n - sum n_k log2 n_k)/n,
+// squared error (S2 - S1^2/n)/n)
+void summarize(const StatsHost &h, int i, int crit, int K, double *imp, bool *impure,
+               double *leaf, int64_t *n) {
+  if (crit == SLM_MSE) {
+    const double cnt = h.cnt[i];
+    *n = h.cnt[i];
+    if (cnt == 0) {
+      *imp = 0;
+      *impure = false;
+      leaf[0] = 0;
+      return;
+    }
+    *imp = (h.s2[i] - h.s1[i] * h.s1[i] / cnt) / cnt;
+    *impure = dec_f64(h.ymax[i]) > dec_f64(h.ymin[i]);
+    leaf[0] = h.s1[i] / cnt;
+    return;
+  }
+  int64_t tot = 0;
+  uint64_t A = 0;
+  double sl = 0;
+  for (int k = 0; k < K; ++k) {
+    const uint64_t c = h.counts[(size_t)i * K + k];
+    tot += c;
+    A += c * c;
+    sl += nlog2n((double)c);
+    leaf[k] = (double)c;
+  }
+  *n = tot;
+  if (tot == 0) {
+    *imp = 0;
+    *impure = false;
+    return;
+  }
+  const double dn = (double)tot;
+  *imp = crit == SLM_GINI ? (dn - (double)A / dn) / dn : (nlog2n(dn) - sl) / dn;
+  *impure = *imp > 0;
+}
+
+slm_status read_stats(const TreeWS &w, int n, int crit, int K, StatsHost &h, hipStream_t s) {
+  if (crit == SLM_MSE) {
+    h.cnt.resize(n);
+    h.s1.resize(n);
+    h.s2.resize(n);
+    h.ymin.resize(n);
+    h.ymax.resize(n);
+    SLM_HIP(hipMemcpyAsync(h.cnt.data(), w.st.cnt, n * 4, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.s1.data(), w.st.s1, n * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.s2.data(), w.st.s2, n * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.ymin.data(), w.st.ymin, n * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.ymax.data(), w.st.ymax, n * 8, hipMemcpyDeviceToHost, s));
+  } else {
+    h.counts.resize((size_t)n * K);
+    SLM_HIP(hipMemcpyAsync(h.counts.data(), w.st.counts, (size_t)n * K * 4,
+                           hipMemcpyDeviceToHost, s));
+  }
+  return SLM_OK;
+}
+
+slm_status clear_stats(const TreeWS &w, int n, int crit, int K, hipStream_t s) {
+  if (crit == SLM_MSE) {
+    SLM_HIP(hipMemsetAsync(w.st.cnt, 0, (size_t)n * 4, s));
+    SLM_HIP(hipMemsetAsync(w.st.s1, 0, (size_t)n * 8, s));
+    SLM_HIP(hipMemsetAsync(w.st.s2, 0, (size_t)n * 8, s));
+    SLM_HIP(hipMemsetAsync(w.st.ymin, 0xFF, (size_t)n * 8, s));
+    SLM_HIP(hipMemsetAsync(w.st.ymax, 0, (size_t)n * 8, s));
+  } else {
+    SLM_HIP(hipMemsetAsync(w.st.counts, 0, (size_t)n * K * 4, s));
+  }
+  return SLM_OK;
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool on = false;
+  double *acc = nullptr;
+  slm_status start(double *target, hipStream_t s) {
+    acc = target;
+    on = target != nullptr;
+    if (!on) return SLM_OK;
+    if (!a) {
+      SLM_HIP(hipEventCreate(&a));
+      SLM_HIP(hipEventCreate(&b));
+    }
+    SLM_HIP(hipEventRecord(a, s));
+    return SLM_OK;
+  }
+  slm_status stop(hipStream_t s) {
+    if (!on) return SLM_OK;
+    SLM_HIP(hipEventRecord(b, s));
+    SLM_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    SLM_HIP(hipEventElapsedTime(&ms, a, b));
+    *acc += ms;
+    return SLM_OK;
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// ---------------------------------------------------------------- graph cache
+// One captured swarm loop (T+1 evaluations) per distinct launch signature.
+struct GraphKey {
+  std::vector<uint64_t> k;
+  bool operator<(const GraphKey &o) const { return k < o.k; }
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+}  // namespace
+
+// Optional per-launch timing: event pairs recorded around launches on the
+// launch stream, read after the depth's synchronisation.
+struct LaunchTimes {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, size_t>> marks;   // (kind, index of the start event)
+  size_t used = 0;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  slm_status begin(int kind, hipStream_t s) {
+    hipEvent_t e = next();
+    SLM_CHECK(e != nullptr, SLM_E_HIP, "hipEventCreate failed");
+    marks.push_back({kind, used - 1});
+    SLM_HIP(hipEventRecord(e, s));
+    return SLM_OK;
+  }
+  slm_status end(hipStream_t s) {
+    hipEvent_t e = next();
+    SLM_CHECK(e != nullptr, SLM_E_HIP, "hipEventCreate failed");
+    SLM_HIP(hipEventRecord(e, s));
+    return SLM_OK;
+  }
+  // after a stream sync: add each kind's elapsed time to acc[kind], counts to cnt[kind]
+  slm_status collect(double *acc, double *cnt) {
+    for (auto &m : marks) {
+      float ms = 0;
+      SLM_HIP(hipEventElapsedTime(&ms, pool[m.second], pool[m.second + 1]));
+      acc[m.first] += ms;
+      if (cnt) cnt[m.first] += 1;
+    }
+    marks.clear();
+    used = 0;
+    return SLM_OK;
+  }
+  ~LaunchTimes() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// swarm loop of one depth: T+1 evaluations (project, scan, step)
+static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const void *Xc,
+                             const void *tc, int64_t N, int32_t D, int na, hipStream_t s,
+                             LaunchTimes *lt = nullptr) {
+  const bool mse = p.crit == SLM_MSE;
+  PsoArgs pa{};
+  pa.x = w.x; pa.v = w.v; pa.pbest = w.pbest; pa.pbest_loss = w.pbest_loss;
+  pa.gbest = w.gbest; pa.gbest_loss = w.gbest_loss; pa.gbest_p = w.gbest_p;
+  pa.loss = w.loss; pa.split = w.split; pa.thr = w.thr;
+  pa.gbest_split = w.gbest_split; pa.gbest_thr = w.gbest_thr;
+  pa.node_id = w.node_id; pa.n_nodes = na; pa.P = p.P; pa.D = D;
+  pa.omega = p.omega; pa.c1 = p.c1; pa.c2 = p.c2; pa.seed = p.seed; pa.tree = p.tree;
+  pa.W_out = w.W; pa.w_bf16 = 0;
+  pa.zmin_reset = w.zmin; pa.zmax_reset = w.zmax;
+  pa.seed_tree_dev = w.seed_tree;
+  slm_status st = launch_pso_init(pa, s);
+  if (st) return st;
+  ProjectArgs pr{};
+  pr.X = Xc; pr.bf16 = 0; pr.N = N; pr.D = D; pr.W = w.W; pr.beg = w.beg; pr.end = w.end;
+  pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
+  ScanArgs sa{};
+  sa.Z = w.Z; sa.zmin = w.zmin; sa.zmax = w.zmax;
+  sa.labels = mse ? nullptr : static_cast<const int32_t *>(tc);
+  sa.y = mse ? static_cast<const double *>(tc) : nullptr;
+  sa.K = p.K; sa.N = N; sa.beg = w.beg; sa.end = w.end; sa.n_nodes = na; sa.P = p.P;
+  sa.bins = p.bins; sa.crit = p.crit; sa.best_split = w.split; sa.best_loss = w.loss;
+  sa.threshold = w.thr; sa.ws = w.scan_ws; sa.ws_bytes = w.scan_ws_bytes;
+  for (int t = 0; t <= p.T; ++t) {
+    if (lt && (st = lt->begin(0, s))) return st;
+    if ((st = launch_project(pr, s))) return st;
+    if (lt && (st = lt->end(s))) return st;
+    if (lt && (st = lt->begin(1, s))) return st;
+    if (p.bins) {
+      if ((st = launch_scan_hist(sa, s))) return st;
+    } else {
+      if ((st = launch_scan_exact(sa, 8192, s))) return st;
+    }
+    if (lt && (st = lt->end(s))) return st;
+    pa.move = t < p.T;
+    pa.iter = (uint32_t)(t + 1);
+    if (lt && (st = lt->begin(2, s))) return st;
+    if ((st = launch_pso_step(pa, s))) return st;
+    if (lt && (st = lt->end(s))) return st;
+  }
+  return SLM_OK;
+}
+
+static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, const void *Xc,
+                                   const void *tc, int64_t N, int32_t D, int na, hipStream_t s) {
+  GraphKey key;
+  key.k = {(uint64_t)(uintptr_t)Xc, (uint64_t)(uintptr_t)tc, (uint64_t)(uintptr_t)w.Z,
+           (uint64_t)N, (uint64_t)D, (uint64_t)na, (uint64_t)p.P, (uint64_t)p.T,
+           (uint64_t)p.bins, (uint64_t)p.crit, (uint64_t)p.K,
+           (uint64_t)(uintptr_t)w.scan_ws};
+  uint64_t om, c1, c2;
+  std::memcpy(&om, &p.omega, 8);
+  std::memcpy(&c1, &p.c1, 8);
+  std::memcpy(&c2, &p.c2, 8);
+  key.k.push_back(om);
+  key.k.push_back(c1);
+  key.k.push_back(c2);
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) exec = it->second;
+  }
+  if (!exec) {
+    // Capture on a private stream (the null stream cannot be captured); the
+    // graph is then launched on the caller's stream.
+    static thread_local hipStream_t cs = nullptr;
+    if (!cs) SLM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    SLM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    set_capturing(true);
+    slm_status st = swarm_loop(p, w, Xc, tc, N, D, na, cs);
+    set_capturing(false);
+    hipGraph_t gcap = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &gcap);
+    if (st || e != hipSuccess) {
+      if (gcap) (void)hipGraphDestroy(gcap);
+      (void)hipGetLastError();
+      if (!st) set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+      return st ? st : SLM_E_HIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&exec, gcap, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gcap);
+    if (ei != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+      return SLM_E_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    g_graphs[key] = exec;
+  }
+  SLM_HIP(hipGraphLaunch(exec, s));
+  return SLM_OK;
+}
+
+}  // namespace slm
+
+using namespace slm;
+
+extern "C" {
+
+const char *slm_version(void) { return "slm-mi355x 0.1 (gfx950)"; }
+
+const char *slm_last_error(void) { return g_err; }
+
+slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, const void *W,
+                       int32_t w_dtype, const int64_t *row_off, int32_t n_nodes, int32_t P,
+                       float *Z, float *zmin, float *zmax, void *stream) {
+  clear_error();
+  SLM_CHECK(N >= 0 && N < (1ll << 31), SLM_E_SHAPE, "slm_project: N = %lld out of range",
+            (long long)N);
+  SLM_CHECK(D >= 1 && D <= DMAX, SLM_E_SHAPE, "slm_project: D = %d out of range", D);
+  SLM_CHECK(P >= 1 && P <= PMAX, SLM_E_SHAPE, "slm_project: P = %d out of range", P);
+  SLM_CHECK(n_nodes >= 0, SLM_E_SHAPE, "slm_project: n_nodes < 0");
+  SLM_CHECK(x_dtype == w_dtype && (x_dtype == SLM_F32 || x_dtype == SLM_BF16), SLM_E_DTYPE,
+            "slm_project: X and W must both be F32 or both BF16");
+  if (N == 0 || n_nodes == 0) return SLM_OK;
+  SLM_CHECK(X && W && row_off && Z && zmin && zmax, SLM_E_INVALID, "slm_project: NULL pointer");
+  slm_status st = launch_fill_minmax(zmin, zmax, (int64_t)n_nodes * P, S(stream));
+  if (st) return st;
+  ProjectArgs a{};
+  a.X = X; a.bf16 = x_dtype == SLM_BF16; a.N = N; a.D = D; a.W = W;
+  a.beg = row_off; a.end = row_off + 1; a.n_nodes = n_nodes; a.P = P;
+  a.Z = Z; a.zmin = zmin; a.zmax = zmax;
+  return launch_project(a, S(stream));
+}
+
+size_t slm_split_scan_workspace(int64_t N, int32_t n_nodes, int32_t P, int32_t bins, int32_t K,
+                                int32_t crit) {
+  if (N <= 0 || P <= 0 || bins < 0 || bins > 256) return 256;
+  return scan_workspace_bytes(N, n_nodes, P, bins, crit == SLM_MSE ? 0 : K, crit);
+}
+
+slm_status slm_split_scan(const float *Z, const float *zmin, const float *zmax,
+                          const void *target, int32_t t_dtype, int32_t K, int64_t N,
+                          const int64_t *row_off, int32_t n_nodes, int32_t P, int32_t bins,
+                          int32_t crit, int32_t *best_split, double *best_loss, float *threshold,
+                          uint32_t *hist_out, double *sums_out, void *workspace, size_t ws_bytes,
+                          void *stream) {
+  clear_error();
+  SLM_CHECK(N >= 0 && N < (1ll << 31), SLM_E_SHAPE, "slm_split_scan: N out of range");
+  SLM_CHECK(P >= 1 && P <= PMAX, SLM_E_SHAPE, "slm_split_scan: P = %d out of range", P);
+  SLM_CHECK(n_nodes >= 0, SLM_E_SHAPE, "slm_split_scan: n_nodes < 0");
+  SLM_CHECK(bins == 0 || (bins >= 2 && bins <= 256), SLM_E_SHAPE,
+            "slm_split_scan: bins = %d (0 or 2..256)", bins);
+  SLM_CHECK(crit >= 0 && crit <= 2, SLM_E_INVALID, "slm_split_scan: bad criterion %d", crit);
+  if (crit == SLM_MSE) {
+    SLM_CHECK(t_dtype == SLM_F64, SLM_E_DTYPE, "slm_split_scan: SLM_MSE needs an F64 target");
+    SLM_CHECK(K == 0, SLM_E_SHAPE, "slm_split_scan: K must be 0 for SLM_MSE");
+  } else {
+    SLM_CHECK(t_dtype == SLM_I32, SLM_E_DTYPE, "slm_split_scan: classification needs I32 labels");
+    SLM_CHECK(K >= 2 && K <= 16, SLM_E_SHAPE, "slm_split_scan: K = %d not in [2, 16]", K);
+  }
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(row_off && best_split && best_loss && threshold, SLM_E_INVALID,
+            "slm_split_scan: NULL pointer");
+  SLM_CHECK(N == 0 || (Z && target), SLM_E_INVALID, "slm_split_scan: NULL pointer");
+  if (bins) {
+    SLM_CHECK(zmin && zmax, SLM_E_INVALID, "slm_split_scan: zmin/zmax required for bins > 0");
+    const size_t need = scan_workspace_bytes(N, n_nodes, P, bins, K, crit);
+    SLM_CHECK(workspace && ws_bytes >= need, SLM_E_NOMEM,
+              "slm_split_scan: workspace of %zu bytes, %zu needed", ws_bytes, need);
+    SLM_CHECK(crit == SLM_MSE || sums_out == nullptr, SLM_E_INVALID,
+              "slm_split_scan: sums_out is only for SLM_MSE");
+  } else {
+    SLM_CHECK(hist_out == nullptr && sums_out == nullptr, SLM_E_INVALID,
+              "slm_split_scan: hist_out/sums_out need histogram mode");
+  }
+  slm_status pst = prepare_kernels();
+  if (pst) return pst;
+  ScanArgs a{};
+  a.Z = Z; a.zmin = zmin; a.zmax = zmax;
+  a.labels = crit == SLM_MSE ? nullptr : static_cast<const int32_t *>(target);
+  a.y = crit == SLM_MSE ? static_cast<const double *>(target) : nullptr;
+  a.K = K; a.N = N; a.beg = row_off; a.end = row_off + 1; a.n_nodes = n_nodes; a.P = P;
+  a.bins = bins; a.crit = crit; a.best_split = best_split; a.best_loss = best_loss;
+  a.threshold = threshold; a.hist_out = hist_out; a.sums_out = sums_out;
+  a.ws = workspace; a.ws_bytes = ws_bytes;
+  if (bins) {
+    if ((pst = launch_scan_empty_nodes(a, S(stream)))) return pst;
+    if (N == 0) return SLM_OK;
+    return launch_scan_hist(a, S(stream));
+  }
+  // exact scan: node sizes decide whether the LDS sort applies
+  std::vector<int64_t> off(n_nodes + 1);
+  SLM_HIP(hipMemcpyAsync(off.data(), row_off, (n_nodes + 1) * 8, hipMemcpyDeviceToHost, S(stream)));
+  SLM_HIP(hipStreamSynchronize(S(stream)));
+  int64_t mx = 0;
+  for (int j = 0; j < n_nodes; ++j) {
+    int64_t b = std::min<int64_t>(std::max<int64_t>(off[j], 0), N);
+    int64_t e = std::min<int64_t>(std::max<int64_t>(off[j + 1], b), N);
+    mx = std::max(mx, e - b);
+  }
+  return launch_scan_exact(a, (int)std::min<int64_t>(mx, 1 << 30), S(stream));
+}
+
+slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,
+                        double *gbest_loss, int32_t *gbest_p, const int32_t *node_id,
+                        int32_t n_nodes, int32_t P, int32_t D, uint64_t seed, uint32_t tree,
+                        void *W_out, int32_t w_dtype, void *stream) {
+  clear_error();
+  SLM_CHECK(n_nodes >= 0 && P >= 1 && P <= PMAX && D >= 1 && D <= DMAX, SLM_E_SHAPE,
+            "slm_pso_init: bad sizes");
+  SLM_CHECK(w_dtype == SLM_F32 || w_dtype == SLM_BF16, SLM_E_DTYPE,
+            "slm_pso_init: W_out must be F32 or BF16");
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(x && v && pbest && pbest_loss && gbest && gbest_loss && gbest_p && node_id && W_out,
+            SLM_E_INVALID, "slm_pso_init: NULL pointer");
+  PsoArgs a{};
+  a.x = x; a.v = v; a.pbest = pbest; a.pbest_loss = pbest_loss; a.gbest = gbest;
+  a.gbest_loss = gbest_loss; a.gbest_p = gbest_p; a.node_id = node_id;
+  a.n_nodes = n_nodes; a.P = P; a.D = D; a.seed = seed; a.tree = tree;
+  a.W_out = W_out; a.w_bf16 = w_dtype == SLM_BF16;
+  return launch_pso_init(a, S(stream));
+}
+
+slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,
+                        double *gbest_loss, int32_t *gbest_p, const double *loss,
+                        const int32_t *split, const float *thr, int32_t *gbest_split,
+                        float *gbest_thr, const int32_t *node_id, int32_t n_nodes, int32_t P,
+                        int32_t D, double omega, double c1, double c2, uint64_t seed,
+                        uint32_t tree, uint32_t iter, int32_t move, void *W_out, int32_t w_dtype,
+                        void *stream) {
+  clear_error();
+  SLM_CHECK(n_nodes >= 0 && P >= 1 && P <= PMAX && D >= 1 && D <= DMAX, SLM_E_SHAPE,
+            "slm_pso_step: bad sizes");
+  SLM_CHECK(w_dtype == SLM_F32 || w_dtype == SLM_BF16, SLM_E_DTYPE,
+            "slm_pso_step: W_out must be F32 or BF16");
+  SLM_CHECK(std::isfinite(omega) && std::isfinite(c1) && std::isfinite(c2), SLM_E_INVALID,
+            "slm_pso_step: non-finite coefficient");
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(x && v && pbest && pbest_loss && gbest && gbest_loss && gbest_p && loss && node_id,
+            SLM_E_INVALID, "slm_pso_step: NULL pointer");
+  SLM_CHECK(!move || W_out, SLM_E_INVALID, "slm_pso_step: W_out required when moving");
+  SLM_CHECK((split == nullptr) == (gbest_split == nullptr) &&
+                (thr == nullptr) == (gbest_thr == nullptr),
+            SLM_E_INVALID, "slm_pso_step: split/gbest_split and thr/gbest_thr go in pairs");
+  PsoArgs a{};
+  a.x = x; a.v = v; a.pbest = pbest; a.pbest_loss = pbest_loss; a.gbest = gbest;
+  a.gbest_loss = gbest_loss; a.gbest_p = gbest_p; a.loss = loss; a.split = split; a.thr = thr;
+  a.gbest_split = gbest_split; a.gbest_thr = gbest_thr; a.node_id = node_id;
+  a.n_nodes = n_nodes; a.P = P; a.D = D; a.omega = omega; a.c1 = c1; a.c2 = c2;
+  a.seed = seed; a.tree = tree; a.iter = iter; a.move = move;
+  a.W_out = W_out; a.w_bf16 = w_dtype == SLM_BF16;
+  return launch_pso_step(a, S(stream));
+}
+
+slm_status slm_predict(const float *w, const float *thr, const int32_t *left,
+                       const int32_t *right, int32_t n_tree, int32_t D, const float *X, int64_t N,
+                       int32_t *leaf_out, void *stream) {
+  clear_error();
+  SLM_CHECK(n_tree >= 1 && D >= 1 && D <= DMAX && N >= 0 && N < (1ll << 31), SLM_E_SHAPE,
+            "slm_predict: bad sizes");
+  if (N == 0) return SLM_OK;
+  SLM_CHECK(w && thr && left && right && X && leaf_out, SLM_E_INVALID, "slm_predict: NULL pointer");
+  return launch_predict(w, thr, left, right, n_tree, D, X, N, leaf_out, S(stream));
+}
+
+size_t slm_grow_tree_workspace(const slm_tree_params *prm, int64_t N, int32_t D) {
+  if (check_tree_params(prm, N, D) != SLM_OK) return 0;
+  return carve(*prm, N, D, nullptr).total;
+}
+
+slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, const void *target,
+                         int32_t t_dtype, const slm_tree_params *prm, void *workspace,
+                         size_t ws_bytes, slm_tree_out *out, void *stream) {
+  clear_error();
+  slm_status st = check_tree_params(prm, N, D);
+  if (st) return st;
+  const slm_tree_params &p = *prm;
+  const bool mse = p.crit == SLM_MSE;
+  SLM_CHECK(x_dtype == SLM_F32, SLM_E_DTYPE, "slm_grow_tree: X must be F32");
+  SLM_CHECK(t_dtype == (mse ? SLM_F64 : SLM_I32), SLM_E_DTYPE,
+            "slm_grow_tree: target dtype does not match the criterion");
+  SLM_CHECK(X && target && workspace && out, SLM_E_INVALID, "slm_grow_tree: NULL pointer");
+  SLM_CHECK(out->w && out->thr && out->left && out->right && out->leaf && out->n &&
+                out->impurity && out->split_loss && out->depth && out->heap,
+            SLM_E_INVALID, "slm_grow_tree: NULL output array");
+  SLM_CHECK(out->max_nodes >= 1, SLM_E_SHAPE, "slm_grow_tree: max_nodes < 1");
+  const TreeWS w = carve(p, N, D, workspace);
+  SLM_CHECK(ws_bytes >= w.total, SLM_E_NOMEM, "slm_grow_tree: workspace of %zu bytes, %zu needed",
+            ws_bytes, w.total);
+  if ((st = prepare_kernels())) return st;
+  hipStream_t s = S(stream);
+  const int K = mse ? 0 : p.K;
+  const int Kc = mse ? 1 : p.K;
+  const size_t tb = mse ? 8 : 4;
+  const int64_t F = max_active(p, N);
+  double *timing = out->timing;
+  if (timing) std::fill(timing, timing + 8, 0.0);
+  Timer tm_all, tm_swarm, tm_part;
+  const bool prof = p.profile && timing;
+  LaunchTimes lt;
+  if ((st = tm_all.start(timing ? &timing[0] : nullptr, s))) return st;
+  int64_t ss = 0;
+
+  // scan accumulators start (and stay) zero; RNG key and tree id on the
+  // device; root statistics
+  SLM_HIP(hipMemsetAsync(w.scan_ws, 0, w.scan_ws_bytes, s));
+  const uint64_t seed_tree[2] = {p.seed, (uint64_t)p.tree};
+  SLM_HIP(hipMemcpyAsync(w.seed_tree, seed_tree, 16, hipMemcpyHostToDevice, s));
+  std::vector<int64_t> hb(F), he(F), hnl(F);
+  std::vector<int32_t> hid(F), hsplit(F);
+  hb[0] = 0;
+  he[0] = N;
+  SLM_HIP(hipMemcpyAsync(w.beg, hb.data(), 8, hipMemcpyHostToDevice, s));
+  SLM_HIP(hipMemcpyAsync(w.end, he.data(), 8, hipMemcpyHostToDevice, s));
+  if ((st = clear_stats(w, 1, p.crit, Kc, s))) return st;
+  if ((st = launch_node_stats(w.beg, w.end, 1, N, mse ? nullptr : (const int32_t *)target,
+                              mse ? (const double *)target : nullptr, Kc, w.st, s)))
+    return st;
+  StatsHost sh;
+  if ((st = read_stats(w, 1, p.crit, Kc, sh, s))) return st;
+  SLM_HIP(hipStreamSynchronize(s));
+
+  int nn = 0;
+  auto new_node = [&](int depth, int heap, int stat_i, int64_t b, int64_t e, HNode *hn) -> bool {
+    if (nn >= out->max_nodes) return false;
+    const int i = nn++;
+    double imp;
+    bool impure;
+    int64_t cnt;
+    summarize(sh, stat_i, p.crit, Kc, &imp, &impure, out->leaf + (size_t)i * Kc, &cnt);
+    out->n[i] = e - b;
+    out->impurity[i] = imp;
+    out->split_loss[i] = INFINITY;
+    out->thr[i] = INFINITY;
+    out->left[i] = -1;
+    out->right[i] = -1;
+    out->depth[i] = depth;
+    out->heap[i] = heap;
+    std::fill(out->w + (size_t)i * D, out->w + (size_t)(i + 1) * D, 0.0f);
+    *hn = HNode{i, b, e, depth, heap, imp, impure};
+    return true;
+  };
+  std::vector<HNode> frontier(1);
+  SLM_CHECK(new_node(0, 0, 0, 0, N, &frontier[0]), SLM_E_SHAPE, "slm_grow_tree: max_nodes = 0");
+
+  const void *Xc = X;
+  const void *tc = target;
+  void *Xbuf[2] = {w.Xa, w.Xb};
+  void *tbuf[2] = {w.ta, w.tb};
+  int nb = 0;
+  std::vector<double> hgl(F), hgb((size_t)F * D);
+  std::vector<float> hgt(F), hgw((size_t)F * D);
+
+  for (int depth = 0; !frontier.empty(); ++depth) {
+    std::vector<HNode> active;
+    for (const HNode &f : frontier)
+      if (f.depth < p.max_depth && f.end - f.beg >= p.min_node && f.impure) active.push_back(f);
+    if (active.empty()) break;
+    const int na = (int)active.size();
+    SLM_CHECK(na <= F, SLM_E_SHAPE, "slm_grow_tree: frontier of %d nodes exceeds %lld", na,
+              (long long)F);
+    for (int j = 0; j < na; ++j) {
+      hb[j] = active[j].beg;
+      he[j] = active[j].end;
+      hid[j] = active[j].heap;
+      ss += (active[j].end - active[j].beg) * (int64_t)p.P * (p.T + 1);
+    }
+    SLM_HIP(hipMemcpyAsync(w.beg, hb.data(), na * 8, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(w.end, he.data(), na * 8, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(w.node_id, hid.data(), na * 4, hipMemcpyHostToDevice, s));
+    if ((st = tm_swarm.start(timing ? &timing[1] : nullptr, s))) return st;
+    if (prof)
+      st = swarm_loop(p, w, Xc, tc, N, D, na, s, &lt);
+    else
+      st = p.use_graph ? swarm_loop_graph(p, w, Xc, tc, N, D, na, s)
+                       : swarm_loop(p, w, Xc, tc, N, D, na, s);
+    if (st) return st;
+    if ((st = tm_swarm.stop(s))) return st;
+    if (prof) {
+      SLM_HIP(hipStreamSynchronize(s));
+      double cnt[3] = {0, 0, 0};
+      if ((st = lt.collect(timing + 3, cnt))) return st;
+      timing[6] += cnt[0];
+      timing[7] += cnt[1];
+    }
+    SLM_HIP(hipMemcpyAsync(hgl.data(), w.gbest_loss, na * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(hgt.data(), w.gbest_thr, na * 4, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(hgb.data(), w.gbest, (size_t)na * D * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipStreamSynchronize(s));
+    int nsplit = 0;
+    for (int j = 0; j < na; ++j) {
+      out->split_loss[active[j].idx] = hgl[j];
+      hsplit[j] = hgl[j] < active[j].impurity ? 1 : 0;
+      nsplit += hsplit[j];
+      for (int d = 0; d < D; ++d) hgw[(size_t)j * D + d] = (float)hgb[(size_t)j * D + d];
+    }
+    if (nsplit == 0) break;
+    if ((st = tm_part.start(timing ? &timing[2] : nullptr, s))) return st;
+    SLM_HIP(hipMemcpyAsync(w.do_split, hsplit.data(), na * 4, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(w.gW, hgw.data(), (size_t)na * D * 4, hipMemcpyHostToDevice, s));
+    ProjectArgs pr{};
+    pr.X = Xc; pr.bf16 = 0; pr.N = N; pr.D = D; pr.W = w.gW; pr.beg = w.beg; pr.end = w.end;
+    pr.n_nodes = na; pr.P = 1; pr.Z = w.zsel; pr.zmin = nullptr; pr.zmax = nullptr;
+    if ((st = launch_project(pr, s))) return st;
+    if ((st = clear_stats(w, 2 * na, p.crit, Kc, s))) return st;
+    PartArgs pa{};
+    pa.X = static_cast<const float *>(Xc); pa.Xn = static_cast<float *>(Xbuf[nb]);
+    pa.lab = mse ? nullptr : static_cast<const int32_t *>(tc);
+    pa.labn = mse ? nullptr : static_cast<int32_t *>(tbuf[nb]);
+    pa.y = mse ? static_cast<const double *>(tc) : nullptr;
+    pa.yn = mse ? static_cast<double *>(tbuf[nb]) : nullptr;
+    pa.zsel = w.zsel; pa.thr = w.gbest_thr; pa.do_split = w.do_split;
+    pa.beg = w.beg; pa.end = w.end; pa.n_nodes = na; pa.D = D; pa.K = Kc; pa.N = N;
+    pa.cnt_left = w.cnt_left; pa.off_left = w.off_left; pa.off_right = w.off_right;
+    pa.n_left = w.n_left; pa.child = w.st;
+    if ((st = launch_partition(pa, s))) return st;
+    SLM_HIP(hipMemcpyAsync(hnl.data(), w.n_left, na * 8, hipMemcpyDeviceToHost, s));
+    if ((st = read_stats(w, 2 * na, p.crit, Kc, sh, s))) return st;
+    SLM_HIP(hipStreamSynchronize(s));
+    if ((st = tm_part.stop(s))) return st;
+    std::vector<HNode> next;
+    for (int j = 0; j < na; ++j) {
+      if (!hsplit[j]) continue;
+      const HNode &a = active[j];
+      const int i = a.idx;
+      std::copy(hgw.begin() + (size_t)j * D, hgw.begin() + (size_t)(j + 1) * D,
+                out->w + (size_t)i * D);
+      out->thr[i] = hgt[j];
+      HNode l, r;
+      const int64_t mid = a.beg + hnl[j];
+      SLM_CHECK(new_node(a.depth + 1, 2 * a.heap + 1, 2 * j, a.beg, mid, &l), SLM_E_SHAPE,
+                "slm_grow_tree: more than max_nodes = %d nodes", out->max_nodes);
+      SLM_CHECK(new_node(a.depth + 1, 2 * a.heap + 2, 2 * j + 1, mid, a.end, &r), SLM_E_SHAPE,
+                "slm_grow_tree: more than max_nodes = %d nodes", out->max_nodes);
+      out->left[i] = l.idx;
+      out->right[i] = r.idx;
+      next.push_back(l);
+      next.push_back(r);
+    }
+    Xc = Xbuf[nb];
+    tc = tbuf[nb];
+    nb ^= 1;
+    frontier.swap(next);
+  }
+  (void)K;
+  (void)tb;
+  SLM_HIP(hipStreamSynchronize(s));
+  if ((st = tm_all.stop(s))) return st;
+  out->n_nodes = nn;
+  if (out->sample_splits) out->sample_splits[0] = ss;
+  return SLM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+// Internal declarations shared by the HIP translation units of libslm.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "../../include/slm.h"
+
+namespace slm {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define SLM_HIP(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ::slm::set_error("%s failed: %s", #expr, hipGetErrorString(e_));         \
+      return SLM_E_HIP;                                                        \
+    }                                                                          \
+  } while (0)
+
+// Launch errors are read with hipGetLastError, which is not allowed while the
+// stream is being captured into a graph; during capture they surface at
+// instantiation instead.
+bool capturing();
+void set_capturing(bool on);
+#define SLM_LAUNCHED()                                                         \
+  do {                                                                         \
+    if (!::slm::capturing()) SLM_HIP(hipGetLastError());                       \
+  } while (0)
+
+#define SLM_CHECK(cond, code, ...)                                             \
+  do {                                                                         \
+    if (!(cond)) {                                                             \
+      ::slm::set_error(__VA_ARGS__);                                           \
+      return code;                                                             \
+    }                                                                          \
+  } while (0)
+
+// ---------------------------------------------------------------- segments
+// Node j owns rows [beg[j], end[j]).  Offsets are clamped into [0, N] and an
+// inverted range is empty, so kernels stay in bounds for any offset values.
+struct Range {
+  int64_t lo, hi;
+};
+
+__device__ __forceinline__ Range load_range(const int64_t *beg, const int64_t *end, int j,
+                                            int64_t N) {
+  int64_t b = beg[j], e = end[j];
+  b = b < 0 ? 0 : (b > N ? N : b);
+  e = e < b ? b : (e > N ? N : e);
+  return {b, e};
+}
+
+// Work items are "chunk of CH global rows  x  node": node j's items start at
+// TS(j) = floor(beg_j / CH) + j and cover the global chunks its rows touch.
+// TS is strictly increasing for non-decreasing offsets; the total number of
+// items is at most n_nodes + floor((N - 1) / CH) + 1.
+struct Item {
+  int node;       // -1: no work
+  int64_t lo, hi; // rows of this item
+  int chunk;      // index of this item within its node
+  int nchunks;    // items of this node
+};
+
+__device__ __forceinline__ int64_t item_start(const int64_t *beg, int j, int64_t N, int64_t CH) {
+  int64_t b = beg[j];
+  b = b < 0 ? 0 : (b > N ? N : b);
+  return b / CH + j;
+}
+
+__device__ __forceinline__ Item find_item(const int64_t *beg, const int64_t *end, int n_nodes,
+                                          int64_t N, int64_t CH, int64_t v) {
+  Item it{-1, 0, 0, 0, 0};
+  if (n_nodes <= 0) return it;
+  // largest j with TS(j) <= v
+  int lo = 0, hi = n_nodes - 1;
+  if (item_start(beg, 0, N, CH) > v) return it;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (item_start(beg, mid, N, CH) <= v) lo = mid; else hi = mid - 1;
+  }
+  Range r = load_range(beg, end, lo, N);
+  if (r.hi <= r.lo) return it;
+  int64_t g0 = r.lo / CH, g1 = (r.hi - 1) / CH;
+  int64_t c = v - (g0 + lo);
+  if (c < 0 || g0 + c > g1) return it;
+  int64_t g = g0 + c;
+  it.node = lo;
+  it.lo = r.lo > g * CH ? r.lo : g * CH;
+  it.hi = r.hi < (g + 1) * CH ? r.hi : (g + 1) * CH;
+  it.chunk = (int)c;
+  it.nchunks = (int)(g1 - g0 + 1);
+  return it;
+}
+
+__host__ __device__ __forceinline__ int64_t num_items(int n_nodes, int64_t N, int64_t CH) {
+  return N > 0 ? (int64_t)n_nodes + (N - 1) / CH + 1 : 0;
+}
+
+// ---------------------------------------------------------------- float atomics
+// Order-preserving min/max on float via integer atomics.  -0.0 is folded to
+// +0.0 first (they compare equal), NaN is not expected.
+__device__ __forceinline__ void atomic_min_f32(float *a, float v) {
+  v = v + 0.0f;
+  if (v >= 0.0f) atomicMin(reinterpret_cast<int *>(a), __float_as_int(v));
+  else atomicMax(reinterpret_cast<unsigned *>(a), __float_as_uint(v));
+}
+__device__ __forceinline__ void atomic_max_f32(float *a, float v) {
+  v = v + 0.0f;
+  if (v >= 0.0f) atomicMax(reinterpret_cast<int *>(a), __float_as_int(v));
+  else atomicMin(reinterpret_cast<unsigned *>(a), __float_as_uint(v));
+}
+
+// bfloat16 (bit pattern in uint16) <-> float
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+// The BF16 image of an FP64 position is the RNE bfloat16 of its RNE float32.
+__device__ __forceinline__ uint16_t f64_to_bf16(double d) {
+  return f32_to_bf16_rne(static_cast<float>(d));
+}
+
+// ---------------------------------------------------------------- launchers
+struct ProjectArgs {
+  const void *X;
+  int bf16;
+  int64_t N;
+  int D;
+  const void *W;
+  const int64_t *beg, *end;
+  int n_nodes, P;
+  float *Z;
+  float *zmin, *zmax;
+  int w_row_stride;  // rows of W per node (P normally)
+};
+slm_status launch_project(const ProjectArgs &a, hipStream_t s);
+slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s);
+
+struct ScanArgs {
+  const float *Z;
+  const float *zmin, *zmax;
+  const int32_t *labels;
+  const double *y;
+  int K;
+  int64_t N;
+  const int64_t *beg, *end;
+  int n_nodes, P, bins, crit;
+  int32_t *best_split;
+  double *best_loss;
+  float *threshold;
+  uint32_t *hist_out;
+  double *sums_out;
+  void *ws;
+  size_t ws_bytes;
+};
+size_t scan_workspace_bytes(int64_t N, int n_nodes, int P, int bins, int K, int crit);
+slm_status launch_scan_hist(const ScanArgs &a, hipStream_t s);
+// "no split" outputs for nodes without rows (the histogram scan skips them)
+slm_status launch_scan_empty_nodes(const ScanArgs &a, hipStream_t s);
+slm_status launch_scan_exact(const ScanArgs &a, int max_rows, hipStream_t s);
+
+struct PsoArgs {
+  double *x, *v, *pbest, *pbest_loss, *gbest, *gbest_loss;
+  int32_t *gbest_p;
+  const double *loss;
+  const int32_t *split;
+  const float *thr;
+  int32_t *gbest_split;
+  float *gbest_thr;
+  const int32_t *node_id;
+  int n_nodes, P, D;
+  double omega, c1, c2;
+  uint64_t seed;
+  uint32_t tree, iter;
+  int move;
+  void *W_out;
+  int w_bf16;
+  // optional: reset zmin/zmax of every (node, particle) for the next projection
+  float *zmin_reset, *zmax_reset;
+  // optional device copy of (seed, tree): lets one captured graph serve every tree
+  const uint64_t *seed_tree_dev;
+};
+slm_status launch_pso_init(const PsoArgs &a, hipStream_t s);
+slm_status launch_pso_step(const PsoArgs &a, hipStream_t s);
+
+slm_status launch_predict(const float *w, const float *thr, const int32_t *left,
+                          const int32_t *right, int n_tree, int D, const float *X, int64_t N,
+                          int32_t *leaf_out, hipStream_t s);
+
+struct TreeStats {
+  uint32_t *counts;   // [n * K] classification
+  uint32_t *cnt;      // [n] regression
+  double *s1, *s2;    // [n]
+  unsigned long long *ymin, *ymax;  // [n] order-preserving encodings of double
+};
+
+struct PartArgs {
+  const float *X;       // current rows [N, D]
+  float *Xn;            // destination rows
+  const int32_t *lab;   // labels (classification) or null
+  int32_t *labn;
+  const double *y;      // targets (regression) or null
+  double *yn;
+  const float *zsel;    // projection of each row on its node's split direction
+  const float *thr;     // [n] threshold per node
+  const int32_t *do_split;  // [n] 1 = split this node
+  const int64_t *beg, *end;
+  int n_nodes, D, K;
+  int64_t N, CH;
+  uint32_t *cnt_left;   // [items]
+  int64_t *off_left, *off_right;  // [items]
+  int64_t *n_left;      // [n]
+  TreeStats child;      // children stats at index 2*j + side
+};
+
+slm_status launch_node_stats(const int64_t *beg, const int64_t *end, int n_nodes, int64_t N,
+                             const int32_t *lab, const double *y, int K, TreeStats st,
+                             hipStream_t s);
+slm_status launch_partition(const PartArgs &a, hipStream_t s);
+int64_t partition_items(int n_nodes, int64_t N);
+// sets kernel attributes once per process (call outside stream capture)
+slm_status prepare_kernels();
+
+}  // namespace slm

@@ -1,0 +1,122 @@
+"""The C ABI library loads, exports every declared entry point and rejects bad
+arguments on the host before any launch (CPU only: no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2208_07023_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slm.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(api.LIB_PATH),
+                                reason="libslm.so not built (run __graft_entry__.build())")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(slm_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(api.LIB_PATH)
+    syms = declared_symbols()
+    assert {"slm_project", "slm_split_scan", "slm_pso_step", "slm_grow_tree"} <= set(syms)
+    for s in syms:
+        assert hasattr(lib, s), s
+    # and the binding declares a signature for each of them
+    assert set(syms) == set(api._SIGS)
+
+
+def test_version_and_error_strings():
+    lib = api.load()
+    assert b"gfx950" in lib.slm_version()
+    assert lib.slm_last_error() is not None
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation
+
+
+def _err(lib):
+    return lib.slm_last_error().decode()
+
+
+def test_project_validation():
+    lib = api.load()
+    st = lib.slm_project(FAKE, api.F32, 10, 0, FAKE, api.F32, FAKE, 1, 4, FAKE, FAKE, FAKE, None)
+    assert st == 2 and "D" in _err(lib)
+    st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.BF16, FAKE, 1, 4, FAKE, FAKE, FAKE, None)
+    assert st == 3
+    st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 0, FAKE, FAKE, FAKE, None)
+    assert st == 2
+    st = lib.slm_project(None, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 4, FAKE, FAKE, FAKE, None)
+    assert st == 1 and "NULL" in _err(lib)
+    # nothing to do: returns OK without touching the device
+    st = lib.slm_project(None, api.F32, 0, 4, None, api.F32, None, 0, 4, None, None, None, None)
+    assert st == 0
+
+
+def test_split_scan_validation():
+    lib = api.load()
+    args = lambda **kw: dict(dict(Z=FAKE, zmin=FAKE, zmax=FAKE, t=FAKE, tt=api.I32, K=3, N=100,
+                                  off=FAKE, nn=1, P=8, bins=16, crit=api.GINI, ws=FAKE,
+                                  wsb=1 << 30), **kw)
+
+    def call(a):
+        return lib.slm_split_scan(a["Z"], a["zmin"], a["zmax"], a["t"], a["tt"], a["K"], a["N"],
+                                  a["off"], a["nn"], a["P"], a["bins"], a["crit"], FAKE, FAKE,
+                                  FAKE, None, None, a["ws"], a["wsb"], None)
+    assert call(args(bins=1)) == 2
+    assert call(args(bins=257)) == 2
+    assert call(args(K=1)) == 2
+    assert call(args(K=17)) == 2
+    assert call(args(crit=3)) == 1
+    assert call(args(tt=api.F64)) == 3                      # classification needs I32
+    assert call(args(crit=api.MSE, tt=api.I32, K=0)) == 3   # MSE needs F64
+    assert call(args(crit=api.MSE, tt=api.F64, K=3)) == 2
+    assert call(args(wsb=16)) == 4 and "workspace" in _err(lib)
+    assert call(args(zmin=None)) == 1
+    need = lib.slm_split_scan_workspace(100, 1, 8, 16, 3, api.GINI)
+    assert need > 0
+    assert lib.slm_split_scan_workspace(4_000_000, 2048, 1024, 256, 10, api.GINI) < 8 << 30
+
+
+def test_pso_validation():
+    lib = api.load()
+    st = lib.slm_pso_init(*([FAKE] * 7), FAKE, 1, 8, 5000, 1, 0, FAKE, api.F32, None)
+    assert st == 2
+    st = lib.slm_pso_init(*([FAKE] * 7), FAKE, 1, 8, 4, 1, 0, FAKE, api.F64, None)
+    assert st == 3
+    # loss, split, thr, gbest_split, gbest_thr: split given without gbest_split
+    st = lib.slm_pso_step(*([FAKE] * 7), FAKE, FAKE, None, None, None, FAKE, 1, 8, 4,
+                          0.7, 1.5, 1.5, 1, 0, 1, 1, FAKE, api.F32, None)
+    assert st == 1
+    st = lib.slm_pso_step(*([FAKE] * 7), FAKE, None, None, None, None, FAKE, 1, 8, 4,
+                          float("nan"), 1.5, 1.5, 1, 0, 1, 1, FAKE, api.F32, None)
+    assert st == 1
+
+
+def test_grow_tree_params_validation():
+    lib = api.load()
+    ok = api.TreeConfig(crit=api.ENTROPY, K=3, max_depth=8, P=256, T=50, bins=256).c_params()
+    assert lib.slm_grow_tree_workspace(ctypes.byref(ok), 100_000, 64) > 100_000 * 256 * 4
+    for bad in (dict(K=1), dict(bins=1), dict(P=0), dict(crit=api.MSE, K=3), dict(min_node=0)):
+        cfg = api.TreeConfig(crit=api.ENTROPY, K=3, P=8, T=2, bins=16)
+        for k, v in bad.items():
+            setattr(cfg, k, v)
+        prm = cfg.c_params()
+        assert lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) == 0
+        out = api.TreeOut()
+        st = lib.slm_grow_tree(FAKE, api.F32, 1000, 8, FAKE, api.I32, ctypes.byref(prm), FAKE,
+                               1 << 30, ctypes.byref(out), None)
+        assert st in (1, 2), bad
+        assert _err(lib)
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+    with pytest.raises(TypeError):
+        api.project(torch.zeros(4, 2), torch.zeros(1, 2), torch.tensor([0, 4]), 1)

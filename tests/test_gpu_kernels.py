@@ -1,0 +1,242 @@
+"""GPU parity of the HIP kernels against the FP64 oracle, through the C ABI.
+
+Bars: integer/index results (counts, chosen splits, thresholds, RNG draws,
+swarm updates) bit-exact; FP32 projections within the forward error bound of
+an FP32 dot product; losses within 1e-5 relative (in practice far tighter,
+stated per test).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import pso as OP
+from oracle import split as OS
+from paper_2208_07023_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _t(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+# ------------------------------------------------------------------ projection
+@pytest.mark.parametrize("D,P,sizes", [
+    (8, 32, [1000]),
+    (64, 256, [0, 1, 130, 777, 2]),
+    (70, 48, [300, 0, 129]),
+    (130, 1, [257, 64]),
+    (256, 130, [17, 200]),
+])
+def test_project_integer_inputs_bit_exact(gpu_lib, D, P, sizes):
+    api = gpu_lib
+    off = inputs.segment_offsets(sizes)
+    N, nn = int(off[-1]), len(sizes)
+    X = inputs.integer_matrix(N, D, -8, 8, seed=D + P)
+    W = inputs.integer_matrix(nn * P, D, -4, 4, seed=D * P + 1)
+    Z, zmin, zmax = api.project(_t(X), _t(W), _t(off), P)
+    torch.cuda.synchronize()
+    Z, zmin, zmax = Z.cpu().numpy(), zmin.cpu().numpy(), zmax.cpu().numpy()
+    for j in range(nn):
+        r0, r1 = off[j], off[j + 1]
+        ref = OS.project(X[r0:r1], W[j * P:(j + 1) * P])
+        assert np.array_equal(Z[r0:r1], ref.astype(np.float32))
+        if r1 > r0:
+            assert np.array_equal(zmin[j * P:(j + 1) * P], ref.min(0).astype(np.float32))
+            assert np.array_equal(zmax[j * P:(j + 1) * P], ref.max(0).astype(np.float32))
+        else:
+            assert np.all(np.isposinf(zmin[j * P:(j + 1) * P]))
+            assert np.all(np.isneginf(zmax[j * P:(j + 1) * P]))
+
+
+@pytest.mark.parametrize("D,P", [(8, 32), (64, 256), (128, 64), (200, 33)])
+def test_project_gaussian_within_fp32_bound(gpu_lib, D, P):
+    api = gpu_lib
+    sizes = [513, 1, 1200]
+    off = inputs.segment_offsets(sizes)
+    rng = np.random.default_rng(D)
+    X = rng.standard_normal((int(off[-1]), D)).astype(np.float32)
+    W = inputs.random_unit_rows(len(sizes) * P, D, seed=P).astype(np.float32)
+    Z, _, _ = api.project(_t(X), _t(W), _t(off), P)
+    Z = Z.cpu().numpy().astype(np.float64)
+    u = 2.0 ** -24
+    gam = D * u / (1 - D * u)
+    for j in range(len(sizes)):
+        r0, r1 = off[j], off[j + 1]
+        Wj = W[j * P:(j + 1) * P]
+        ref = OS.project(X[r0:r1], Wj)
+        mag = np.abs(X[r0:r1].astype(np.float64)) @ np.abs(Wj.astype(np.float64)).T
+        assert np.all(np.abs(Z[r0:r1] - ref) <= gam * mag + 1e-30)
+
+
+def test_project_column_recomputed_alone_is_bit_identical(gpu_lib):
+    """The partition recomputes the winning particle's column with P = 1; it
+    must reproduce the bits the scan binned."""
+    api = gpu_lib
+    sizes = [3000, 1777]
+    off = inputs.segment_offsets(sizes)
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((int(off[-1]), 64)).astype(np.float32)
+    P = 256
+    W = inputs.random_unit_rows(2 * P, 64, seed=2).astype(np.float32)
+    Z, _, _ = api.project(_t(X), _t(W), _t(off), P)
+    for p in (0, 31, 32, 200, 255):
+        W1 = np.stack([W[p], W[P + p]])
+        Z1, _, _ = api.project(_t(X), _t(W1), _t(off), 1)
+        assert torch.equal(Z1[:, 0], Z[:, p])
+
+
+# ------------------------------------------------------------------ histogram scan
+def _scan_case(api, sizes, P, B, crit, K, kind, seed):
+    off = inputs.segment_offsets(sizes)
+    N = int(off[-1])
+    Z = inputs.projected_features(N, P, seed=seed, kind=kind)
+    rng = np.random.default_rng(seed + 1)
+    if crit == OS.MSE:
+        tgt = rng.normal(2.0, 1.5, size=N)
+        tt = torch.float64
+    else:
+        tgt = rng.integers(0, K, size=N).astype(np.int32)
+        tt = torch.int32
+    # zmin / zmax are inputs of the scan (the projection writes them)
+    zmin = np.full(len(sizes) * P, np.inf, np.float32)
+    zmax = np.full(len(sizes) * P, -np.inf, np.float32)
+    for j in range(len(sizes)):
+        if sizes[j]:
+            zmin[j * P:(j + 1) * P] = Z[off[j]:off[j + 1]].min(0)
+            zmax[j * P:(j + 1) * P] = Z[off[j]:off[j + 1]].max(0)
+    out = api.split_scan(_t(Z), _t(zmin), _t(zmax), _t(tgt, tt), K if crit != OS.MSE else 0,
+                         _t(off), P, B, crit, hist=True, sums=crit == OS.MSE)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    ref = OS.split_scan(Z, tgt, off, P, B, crit, K)
+    return got, ref
+
+
+@pytest.mark.parametrize("crit", [OS.GINI, OS.ENTROPY])
+@pytest.mark.parametrize("B,K,P,kind", [
+    (256, 3, 32, "gauss"), (256, 2, 8, "dups"), (16, 10, 20, "gauss"), (2, 3, 5, "gauss"),
+    (3, 4, 64, "dups"), (256, 3, 40, "const"), (100, 16, 3, "gauss"),
+])
+def test_hist_scan_classification_exact(gpu_lib, crit, B, K, P, kind):
+    # nodes: empty, single row, small, one spanning several 2048-row chunks, ragged tail
+    sizes = [0, 1, 37, 5000, 301]
+    got, ref = _scan_case(gpu_lib, sizes, P, B, crit, K, kind, seed=B * 7 + K)
+    assert np.array_equal(got["counts"].astype(np.int64), ref["counts"])
+    assert np.array_equal(got["split"], ref["split"])
+    assert np.array_equal(got["thr"], ref["thr"])
+    fin = np.isfinite(ref["loss"])
+    assert np.array_equal(np.isfinite(got["loss"]), fin)
+    if crit == OS.GINI:
+        assert np.array_equal(got["loss"][fin], ref["loss"][fin])          # bit-exact Gini
+    else:
+        assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("B,P,kind", [(256, 16, "gauss"), (64, 33, "dups"), (7, 4, "gauss")])
+def test_hist_scan_regression(gpu_lib, B, P, kind):
+    sizes = [0, 2, 45, 4500, 600]
+    got, ref = _scan_case(gpu_lib, sizes, P, B, OS.MSE, 0, kind, seed=B + P)
+    assert np.array_equal(got["counts"].astype(np.int64), ref["counts"])
+    # per-bin FP64 sums: atomics in any order, error ~ n * u * sum|y|
+    assert np.allclose(got["sums"], ref["sums"], rtol=1e-12, atol=1e-9)
+    fin = np.isfinite(ref["loss"])
+    assert np.array_equal(np.isfinite(got["loss"]), fin)
+    assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-9, atol=1e-12)
+    mism = np.nonzero(got["split"] != ref["split"])[0]
+    # a different split only where the oracle's best and the GPU's pick are a near-tie
+    for i in mism:
+        assert abs(got["loss"][i] - ref["loss"][i]) <= 1e-9 * abs(ref["loss"][i])
+
+
+def test_hist_scan_reuses_zeroed_workspace(gpu_lib):
+    """Two calls in a row on the same workspace (multi-chunk nodes) agree."""
+    a, ref = _scan_case(gpu_lib, [9000, 3000], 32, 256, OS.GINI, 3, "gauss", seed=5)
+    b, _ = _scan_case(gpu_lib, [9000, 3000], 32, 256, OS.GINI, 3, "gauss", seed=5)
+    for k in ("counts", "split", "loss", "thr"):
+        assert np.array_equal(a[k], b[k])
+    assert np.array_equal(a["split"], ref["split"])
+
+
+# ------------------------------------------------------------------ exact scan
+@pytest.mark.parametrize("crit,K", [(OS.GINI, 2), (OS.ENTROPY, 5), (OS.MSE, 0)])
+@pytest.mark.parametrize("kind", ["gauss", "dups"])
+def test_exact_scan(gpu_lib, crit, K, kind):
+    sizes = [1000, 0, 1, 2, 333]
+    P = 32
+    got, ref = _scan_case(gpu_lib, sizes, P, 0, crit, K, kind, seed=17 + crit)
+    fin = np.isfinite(ref["loss"])
+    assert np.array_equal(np.isfinite(got["loss"]), fin)
+    if crit == OS.MSE:
+        assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-9, atol=1e-12)
+        for i in np.nonzero(got["split"] != ref["split"])[0]:
+            assert abs(got["loss"][i] - ref["loss"][i]) <= 1e-9 * abs(ref["loss"][i])
+    else:
+        assert np.array_equal(got["split"], ref["split"])
+        assert np.array_equal(got["thr"], ref["thr"])
+        if crit == OS.GINI:
+            assert np.array_equal(got["loss"][fin], ref["loss"][fin])
+        else:
+            assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-12)
+
+
+# ------------------------------------------------------------------ swarm
+def test_pso_init_matches_oracle(gpu_lib):
+    api = gpu_lib
+    nodes = [0, 5, 12]
+    P, D = 40, 9
+    sw = api.pso_alloc(3, P, D, nodes)
+    api.pso_init(sw, seed=123, tree=2)
+    x = sw.x.cpu().numpy()
+    for j, nid in enumerate(nodes):
+        ref = OP.init_positions(123, 2, nid, P, D)
+        # device libm (log, cos, sin) vs host: a few ulps
+        assert np.allclose(x[j * P:(j + 1) * P], ref, rtol=0, atol=4e-15)
+    W = sw.W.cpu().numpy()
+    assert np.mean(W == x.astype(np.float32)) == 1.0
+    assert torch.equal(sw.pbest, sw.x) and torch.all(sw.v == 0)
+    assert torch.all(torch.isinf(sw.pbest_loss)) and torch.all(sw.gbest_p == -1)
+    assert torch.equal(sw.gbest, sw.x.view(3, P, D)[:, 0])
+
+
+@pytest.mark.parametrize("ties", [False, True])
+@pytest.mark.parametrize("P,D", [(32, 8), (300, 17), (1024, 256)])
+def test_pso_step_bit_exact(gpu_lib, ties, P, D):
+    api = gpu_lib
+    nn = 3
+    st = inputs.random_pso_state(nn, P, D, seed=P + D, ties=ties)
+    node_id = np.array([1, 4, 9], dtype=np.int32)
+    sw = api.pso_alloc(nn, P, D, node_id)
+    for name in ("x", "v", "pbest", "pbest_loss", "gbest", "gbest_loss"):
+        getattr(sw, name).copy_(_t(getattr(st, name)).view_as(getattr(sw, name)))
+    sw.gbest_p.copy_(_t(st.gbest_p))
+    loss = _t(st.loss)
+    api.pso_step(sw, loss, 0.7, 1.5, 1.5, seed=77, tree=3, it=5, move=True)
+    ref = OP.pso_step(st.x, st.v, st.pbest, st.pbest_loss, st.gbest, st.gbest_loss, st.gbest_p,
+                      st.loss, node_id, nn, P, D, 0.7, 1.5, 1.5, 77, 3, 5, True)
+    torch.cuda.synchronize()
+    for name in ("x", "v", "pbest", "pbest_loss", "gbest", "gbest_loss"):
+        assert np.array_equal(getattr(sw, name).cpu().numpy().reshape(ref[name].shape), ref[name]), name
+    improved = ref["gbest_loss"] < st.gbest_loss
+    gp = sw.gbest_p.cpu().numpy()
+    assert np.array_equal(gp[improved], ref["gbest_p"][improved])
+    assert np.array_equal(sw.W.cpu().numpy(), ref["x"].astype(np.float32))
+
+
+def test_pso_step_without_move_only_updates_bests(gpu_lib):
+    api = gpu_lib
+    st = inputs.random_pso_state(2, 16, 4, seed=3)
+    sw = api.pso_alloc(2, 16, 4, [0, 1])
+    for name in ("x", "v", "pbest", "pbest_loss", "gbest", "gbest_loss"):
+        getattr(sw, name).copy_(_t(getattr(st, name)).view_as(getattr(sw, name)))
+    x0 = sw.x.clone()
+    api.pso_step(sw, _t(st.loss), 0.7, 1.5, 1.5, 1, 0, 1, move=False)
+    assert torch.equal(sw.x, x0)
+    ref = OP.pso_step(st.x, st.v, st.pbest, st.pbest_loss, st.gbest, st.gbest_loss, st.gbest_p,
+                      st.loss, np.array([0, 1]), 2, 16, 4, 0.7, 1.5, 1.5, 1, 0, 1, False)
+    assert np.array_equal(sw.pbest_loss.cpu().numpy(), ref["pbest_loss"])
+    assert np.array_equal(sw.gbest.cpu().numpy(), ref["gbest"])

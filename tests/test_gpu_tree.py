@@ -1,0 +1,131 @@
+"""GPU tree build (Alg. 2) against the oracle tree, through slm_grow_tree.
+
+The swarm trajectories of the two sides diverge once an FP32 projection lands
+on the other side of a bin edge than the FP64 one (a chaotic map), so trees
+are compared by held-out accuracy / error and by internal consistency; the
+split of every node must agree with its own histogram (the partition
+recomputes the winning column bit-identically).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import split as OS
+from oracle import tree as OT
+from paper_2208_07023_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_tree(api, X, y, cfg):
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    yd = torch.from_numpy(np.ascontiguousarray(y)).cuda()
+    return api.grow_tree(Xd, yd, cfg)
+
+
+def _oracle_params(cfg):
+    return OT.TreeParams(crit=cfg.crit, K=cfg.K, max_depth=cfg.max_depth, min_node=cfg.min_node,
+                         P=cfg.P, T=cfg.T, bins=cfg.bins, omega=cfg.omega, c1=cfg.c1, c2=cfg.c2,
+                         seed=cfg.seed, tree=cfg.tree)
+
+
+def _consistency(tr, crit, K):
+    n = tr["n"]
+    for i in range(tr["n_nodes"]):
+        l, r = tr["left"][i], tr["right"][i]
+        if l < 0:
+            assert r < 0
+            continue
+        assert n[l] + n[r] == n[i] and n[l] > 0 and n[r] > 0
+        assert tr["split_loss"][i] < tr["impurity"][i]
+        # children impurities weighted by size reproduce the histogram's loss:
+        # the partition saw exactly the rows the scan binned
+        w = (n[l] * tr["impurity"][l] + n[r] * tr["impurity"][r]) / n[i]
+        assert w == pytest.approx(tr["split_loss"][i], rel=1e-9, abs=1e-12)
+        if crit != OS.MSE:
+            assert np.array_equal(tr["leaf"][l] + tr["leaf"][r], tr["leaf"][i])
+
+
+def test_tree_classification_matches_oracle(gpu_lib):
+    api = gpu_lib
+    Xa, ya = inputs.cluster_mixture(40000, 16, 3, seed=11)
+    X, y, Xt, yt = Xa[:20000], ya[:20000], Xa[20000:], ya[20000:]
+    cfg = api.TreeConfig(crit=api.ENTROPY, K=3, max_depth=4, min_node=32, P=32, T=10, bins=64,
+                         seed=5)
+    g = _gpu_tree(api, X, y, cfg)
+    _consistency(g, OS.ENTROPY, 3)
+    o = OT.grow_tree(X, y, _oracle_params(cfg))
+    acc_g = float((api.predict(g, torch.from_numpy(Xt).cuda()) == yt).mean())
+    acc_o = float((OT.predict(o, Xt) == yt).mean())
+    print(f"held-out accuracy gpu {acc_g:.4f} oracle {acc_o:.4f}; nodes {g['n_nodes']} / {len(o.thr)}")
+    assert abs(acc_g - acc_o) <= 0.005 + 1e-12
+    # root: same initial swarm, same data -> nearly the same best loss
+    assert g["split_loss"][0] == pytest.approx(o.split_loss[0], rel=2e-3)
+    assert g["impurity"][0] == pytest.approx(o.impurity[0], rel=1e-12)
+
+
+def test_tree_regression_matches_oracle(gpu_lib):
+    api = gpu_lib
+    Xa, ya = inputs.abs_direction_regression(24000, 8, n_dirs=2, seed=4)
+    X, y, Xt, yt = Xa[:12000], ya[:12000], Xa[12000:], ya[12000:]
+    cfg = api.TreeConfig(crit=api.MSE, K=0, max_depth=4, min_node=32, P=16, T=8, bins=64, seed=2)
+    g = _gpu_tree(api, X, y, cfg)
+    _consistency(g, OS.MSE, 0)
+    o = OT.grow_tree(X, y, _oracle_params(cfg))
+    mse_g = float(np.mean((api.predict(g, torch.from_numpy(Xt).cuda()) - yt) ** 2))
+    mse_o = float(np.mean((OT.predict(o, Xt) - yt) ** 2))
+    print(f"held-out MSE gpu {mse_g:.5f} oracle {mse_o:.5f}")
+    assert mse_g <= mse_o * 1.03
+    assert g["leaf"][0][0] == pytest.approx(y.mean(), rel=1e-12)
+
+
+def test_single_node_exact_gini_c1(gpu_lib):
+    """Config 1: N=1000, D=8, 2 classes, P=32, T=20, exact scan, Gini."""
+    api = gpu_lib
+    X, y, means = inputs.two_class_gaussian(1000, 8, seed=0)
+    cfg = api.TreeConfig(crit=api.GINI, K=2, max_depth=1, min_node=2, P=32, T=20, bins=0, seed=0)
+    g = _gpu_tree(api, X, y, cfg)
+    o = OT.grow_tree(X, y, _oracle_params(cfg))
+    w = means[1] - means[0]
+    w /= np.linalg.norm(w)
+    z = OS.project(X, w[None, :].astype(np.float32))[:, 0].astype(np.float32)
+    l_lda = OS.scan_exact(z, y, OS.GINI, 2)["loss"]
+    print(f"gbest loss gpu {g['split_loss'][0]:.6f} oracle {o.split_loss[0]:.6f} lda {l_lda:.6f}")
+    assert g["split_loss"][0] <= l_lda + 0.01
+    assert abs(g["split_loss"][0] - o.split_loss[0]) <= 0.01
+    _consistency(g, OS.GINI, 2)
+    assert g["sample_splits"][0] == 21 * 32 * 1000
+
+
+def test_tree_is_deterministic_and_graph_replay_matches(gpu_lib):
+    api = gpu_lib
+    X, y = inputs.cluster_mixture(30000, 32, 3, seed=3)
+    cfg = api.TreeConfig(crit=api.GINI, K=3, max_depth=5, min_node=32, P=64, T=6, bins=256, seed=9)
+    a = _gpu_tree(api, X, y, cfg)
+    b = _gpu_tree(api, X, y, cfg)
+    cfg.use_graph = True
+    c = _gpu_tree(api, X, y, cfg)
+    d = _gpu_tree(api, X, y, cfg)       # replay of the cached graphs
+    for other in (b, c, d):
+        assert a["n_nodes"] == other["n_nodes"]
+        for k in ("w", "thr", "left", "right", "leaf", "n", "split_loss"):
+            assert np.array_equal(a[k], other[k]), k
+    _consistency(a, OS.GINI, 3)
+
+
+def test_predict_routes_like_the_float32_rule(gpu_lib):
+    api = gpu_lib
+    X, y = inputs.cluster_mixture(5000, 12, 3, seed=8)
+    cfg = api.TreeConfig(crit=api.GINI, K=3, max_depth=3, P=16, T=4, bins=32, seed=1)
+    g = _gpu_tree(api, X, y, cfg)
+    leaves = api.predict_leaves(g, torch.from_numpy(X).cuda()).cpu().numpy()
+    # reference routing: float32 dot product summed in dimension order
+    node = np.zeros(len(X), dtype=np.int64)
+    for _ in range(4):
+        internal = g["left"][node] >= 0
+        z = np.zeros(len(X), np.float32)
+        for d in range(X.shape[1]):
+            z = (z + (g["w"][node, d] * X[:, d]).astype(np.float32)).astype(np.float32)
+        nxt = np.where(z >= g["thr"][node], g["right"][node], g["left"][node])
+        node = np.where(internal, nxt, node)
+    assert np.array_equal(leaves, node)
