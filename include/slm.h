@@ -99,8 +99,10 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D,
  * sums_out (optional, MSE histogram mode): [n_nodes*P, bins, 2] f64
  *   (sum y, sum y^2 per bin; FP64 atomics, last bits order-dependent).
  * workspace: device scratch of at least slm_split_scan_workspace(...) bytes.
- *   It must be zero-filled before its first use; every call leaves it
- *   zero-filled again, so it can be reused across calls on one stream.
+ *   It must be zero-filled before its first use and not modified by the
+ *   caller between calls: every call leaves its accumulator part zero-filled
+ *   again (its tail holds a table the call rewrites), so one workspace can be
+ *   reused by consecutive calls on one stream.
  * ------------------------------------------------------------------------ */
 size_t slm_split_scan_workspace(int64_t N, int32_t n_nodes, int32_t P, int32_t bins,
                                 int32_t K, int32_t crit);

@@ -15,7 +15,6 @@ constexpr uint32_t PH_M0 = 0xD2511F53u, PH_M1 = 0xCD9E8D57u;
 constexpr uint32_t PH_W0 = 0x9E3779B9u, PH_W1 = 0xBB67AE85u;
 constexpr uint32_t INIT_STREAM = 0xFFFFFFFFu;
 constexpr int DMAX = 4096;
-constexpr int STEP_WG = 256;
 
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 #pragma unroll
@@ -44,78 +43,100 @@ __device__ __forceinline__ void store_w(void *W, int bf16, int64_t i, double x) 
   else static_cast<float *>(W)[i] = static_cast<float>(x);
 }
 
-__global__ void k_pso_init(PsoArgs a) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)a.n_nodes * a.P;
-  if (gid >= total) return;
-  const int j = (int)(gid / a.P), p = (int)(gid % a.P);
+// Work-group of 256 threads covering PPB = 256 / Dp particles of one node,
+// Dp = D rounded up to a power of two (<= 256); thread (pl, d) owns dimension
+// d (and d + 256k for D > 256) of particle pl.  Norms are summed in
+// dimension order by one thread per particle from LDS, so every operation
+// happens in the same order as the sequential definition.
+constexpr int MOVE_WG = 256;
+
+struct MoveGeom {
+  int Dp, PPB;
+};
+__host__ __device__ __forceinline__ MoveGeom move_geom(int D) {
+  int Dp = 1;
+  while (Dp < D && Dp < MOVE_WG) Dp <<= 1;
+  return {Dp, MOVE_WG / Dp};
+}
+
+__global__ __launch_bounds__(MOVE_WG) void k_pso_init(PsoArgs a) {
+  extern __shared__ double buf[];          // [PPB][D]
+  __shared__ double nrm_s[MOVE_WG];
+  const MoveGeom g = move_geom(a.D);
+  const int bpn = (a.P + g.PPB - 1) / g.PPB; // blocks per node
+  const int j = blockIdx.x / bpn;
+  const int pl = threadIdx.x / g.Dp, dl = threadIdx.x % g.Dp;
+  const int p = (blockIdx.x % bpn) * g.PPB + pl;
+  const bool pv = p < a.P;
   const int D = a.D, dh = (D + 1) / 2;
   uint2 key;
   uint32_t tree;
   rng_key(a, &key, &tree);
   const uint32_t node = (uint32_t)a.node_id[j];
-  double *x = a.x + gid * D;
-  double s = 0.0;
-  for (int m = 0; m < dh; ++m) {
-    const uint4 w = philox4x32_10(make_uint4((uint32_t)(p * dh + m), INIT_STREAM, node, tree), key);
-    const double u1 = ((double)w.x + 0.5) * 0x1p-32;
-    const double u2 = (double)w.y * 0x1p-32;
-    const double rad = sqrt(-2.0 * log(u1));
-    const double ang = 6.283185307179586 * u2;
-    const double g0 = rad * cos(ang);
-    x[2 * m] = g0;
-    s = s + g0 * g0;
-    if (2 * m + 1 < D) {
-      const double g1 = rad * sin(ang);
-      x[2 * m + 1] = g1;
-      s = s + g1 * g1;
+  const int64_t gid = (int64_t)j * a.P + p;
+  if (pv) {
+    for (int d = dl; d < D; d += g.Dp) {
+      const int m = d >> 1;
+      const uint4 w = philox4x32_10(make_uint4((uint32_t)(p * dh + m), INIT_STREAM, node, tree), key);
+      const double u1 = ((double)w.x + 0.5) * 0x1p-32;
+      const double u2 = (double)w.y * 0x1p-32;
+      const double rad = sqrt(-2.0 * log(u1));
+      const double ang = 6.283185307179586 * u2;
+      buf[pl * D + d] = (d & 1) ? rad * sin(ang) : rad * cos(ang);
     }
   }
-  const double nrm = sqrt(s);
-  for (int d = 0; d < D; ++d) {
-    const double xv = nrm > 0.0 ? x[d] / nrm : x[d];
-    x[d] = xv;
+  __syncthreads();
+  if (pv && dl == 0) {
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) s = s + buf[pl * D + d] * buf[pl * D + d];
+    nrm_s[pl] = sqrt(s);
+  }
+  __syncthreads();
+  if (!pv) return;
+  const double nrm = nrm_s[pl];
+  for (int d = dl; d < D; d += g.Dp) {
+    const double xv = nrm > 0.0 ? buf[pl * D + d] / nrm : buf[pl * D + d];
+    a.x[gid * D + d] = xv;
     a.v[gid * D + d] = 0.0;
     a.pbest[gid * D + d] = xv;
     store_w(a.W_out, a.w_bf16, gid * D + d, xv);
     if (p == 0) a.gbest[(int64_t)j * D + d] = xv;
   }
-  a.pbest_loss[gid] = __builtin_huge_val();
-  if (p == 0) {
-    a.gbest_loss[j] = __builtin_huge_val();
-    a.gbest_p[j] = -1;
-    if (a.gbest_split) a.gbest_split[j] = -1;
-    if (a.gbest_thr) a.gbest_thr[j] = __builtin_huge_valf();
-  }
-  if (a.zmin_reset) {
-    a.zmin_reset[gid] = __builtin_huge_valf();
-    a.zmax_reset[gid] = -__builtin_huge_valf();
+  if (dl == 0) {
+    a.pbest_loss[gid] = __builtin_huge_val();
+    if (a.zmin_reset) {
+      a.zmin_reset[gid] = __builtin_huge_valf();
+      a.zmax_reset[gid] = -__builtin_huge_valf();
+    }
+    if (p == 0) {
+      a.gbest_loss[j] = __builtin_huge_val();
+      a.gbest_p[j] = -1;
+      if (a.gbest_split) a.gbest_split[j] = -1;
+      if (a.gbest_thr) a.gbest_thr[j] = __builtin_huge_valf();
+    }
   }
 }
 
-// One work-group per node; threads stride over the node's particles.
-__global__ __launch_bounds__(STEP_WG) void k_pso_step(PsoArgs a) {
-  __shared__ double gb[DMAX];
-  __shared__ double red_l[STEP_WG];
-  __shared__ int red_p[STEP_WG];
-  __shared__ int s_improved, s_pstar;
+// (1) of the step: one work-group per node.  Personal bests (strict <), the
+// argmin of the current losses (lowest p on ties) and the global best.
+constexpr int BEST_WG = 256;
+constexpr int PMAX_STEP = 4096;
 
-  const int j = blockIdx.x;
-  const int tid = threadIdx.x;
+__global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
+  __shared__ double red_l[BEST_WG];
+  __shared__ int red_p[BEST_WG];
+  __shared__ unsigned char imp[PMAX_STEP];
+  __shared__ int s_pstar, s_improved;
+  const int j = blockIdx.x, tid = threadIdx.x;
   const int P = a.P, D = a.D;
   const int64_t base = (int64_t)j * P;
-
-  // (1) personal bests; argmin of the current losses (lowest p on ties)
   double bl = __builtin_huge_val();
   int bp = 0x7fffffff;
-  for (int p = tid; p < P; p += STEP_WG) {
+  for (int p = tid; p < P; p += BEST_WG) {
     const double l = a.loss[base + p];
-    if (l < a.pbest_loss[base + p]) {
-      a.pbest_loss[base + p] = l;
-      const double *xs = a.x + (base + p) * D;
-      double *pb = a.pbest + (base + p) * D;
-      for (int d = 0; d < D; ++d) pb[d] = xs[d];
-    }
+    const bool better = l < a.pbest_loss[base + p];
+    imp[p] = better;
+    if (better) a.pbest_loss[base + p] = l;
     if (l < bl) {
       bl = l;
       bp = p;
@@ -124,7 +145,7 @@ __global__ __launch_bounds__(STEP_WG) void k_pso_step(PsoArgs a) {
   red_l[tid] = bl;
   red_p[tid] = bp;
   __syncthreads();
-  for (int o = STEP_WG / 2; o > 0; o >>= 1) {
+  for (int o = BEST_WG / 2; o > 0; o >>= 1) {
     if (tid < o) {
       const double l2 = red_l[tid + o];
       const int p2 = red_p[tid + o];
@@ -137,10 +158,10 @@ __global__ __launch_bounds__(STEP_WG) void k_pso_step(PsoArgs a) {
   }
   if (tid == 0) {
     const int ps = red_p[0];
-    const bool imp = ps != 0x7fffffff && red_l[0] < a.gbest_loss[j];
-    s_improved = imp;
+    const bool g = ps != 0x7fffffff && red_l[0] < a.gbest_loss[j];
     s_pstar = ps;
-    if (imp) {
+    s_improved = g;
+    if (g) {
       a.gbest_loss[j] = red_l[0];
       a.gbest_p[j] = ps;
       if (a.gbest_split && a.split) a.gbest_split[j] = a.split[base + ps];
@@ -148,59 +169,74 @@ __global__ __launch_bounds__(STEP_WG) void k_pso_step(PsoArgs a) {
     }
   }
   __syncthreads();
-  const bool improved = s_improved;
-  const int pstar = s_pstar;
-  for (int d = tid; d < D; d += STEP_WG) {
-    const double g = improved ? a.x[(base + pstar) * D + d] : a.gbest[(int64_t)j * D + d];
-    gb[d] = g;
-    if (improved) a.gbest[(int64_t)j * D + d] = g;
+  // copy the improved positions into the personal bests (coalesced over p*D + d)
+  const int64_t tot = (int64_t)P * D;
+  for (int64_t e = tid; e < tot; e += BEST_WG) {
+    const int p = (int)(e / D);
+    if (imp[p]) a.pbest[base * D + e] = a.x[base * D + e];
   }
-  __syncthreads();
+  if (s_improved) {
+    const int ps = s_pstar;
+    for (int d = tid; d < D; d += BEST_WG) a.gbest[(int64_t)j * D + d] = a.x[(base + ps) * D + d];
+  }
   if (a.zmin_reset) {
-    for (int p = tid; p < P; p += STEP_WG) {
+    for (int p = tid; p < P; p += BEST_WG) {
       a.zmin_reset[base + p] = __builtin_huge_valf();
       a.zmax_reset[base + p] = -__builtin_huge_valf();
     }
   }
-  if (!a.move) return;
+}
 
-  // (2) move: Eq. (11), Eq. (12), unit-norm rescale
-  const int dh = (D + 1) / 2;
+// (2) of the step: Eq. (11), Eq. (12) and the unit-norm rescale.
+__global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
+  extern __shared__ double buf[];          // [PPB][D] then gbest [D]
+  __shared__ double nrm_s[MOVE_WG];
+  const MoveGeom g = move_geom(a.D);
+  const int bpn = (a.P + g.PPB - 1) / g.PPB;
+  const int j = blockIdx.x / bpn;
+  const int pl = threadIdx.x / g.Dp, dl = threadIdx.x % g.Dp;
+  const int p = (blockIdx.x % bpn) * g.PPB + pl;
+  const bool pv = p < a.P;
+  const int D = a.D, dh = (D + 1) / 2;
+  double *gb = buf + (size_t)g.PPB * D;
+  for (int d = threadIdx.x; d < D; d += MOVE_WG) gb[d] = a.gbest[(int64_t)j * D + d];
   uint2 key;
   uint32_t tree;
   rng_key(a, &key, &tree);
   const uint32_t node = (uint32_t)a.node_id[j];
-  for (int p = tid; p < P; p += STEP_WG) {
-    double *xs = a.x + (base + p) * D;
-    double *vs = a.v + (base + p) * D;
-    const double *pb = a.pbest + (base + p) * D;
-    double s = 0.0;
-    for (int m = 0; m < dh; ++m) {
+  const int64_t gid = (int64_t)j * a.P + p;
+  lds_barrier();
+  if (pv) {
+    for (int d = dl; d < D; d += g.Dp) {
+      const int m = d >> 1, h = d & 1;
       const uint4 w = philox4x32_10(make_uint4((uint32_t)(p * dh + m), a.iter, node, tree), key);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int d = 2 * m + h;
-        if (d >= D) break;
-        const double r1 = u24(h ? w.z : w.x);
-        const double r2 = u24(h ? w.w : w.y);
-        const double xv = xs[d];
-        const double t0 = a.omega * vs[d];
-        const double t1 = (a.c1 * r1) * (pb[d] - xv);
-        const double t2 = (a.c2 * r2) * (gb[d] - xv);
-        const double vn = (t0 + t1) + t2;
-        const double xn = xv + vn;
-        vs[d] = vn;
-        xs[d] = xn;
-        s = s + xn * xn;
-      }
+      const double r1 = u24(h ? w.z : w.x);
+      const double r2 = u24(h ? w.w : w.y);
+      const int64_t e = gid * D + d;
+      const double xv = a.x[e];
+      const double t0 = a.omega * a.v[e];
+      const double t1 = (a.c1 * r1) * (a.pbest[e] - xv);
+      const double t2 = (a.c2 * r2) * (gb[d] - xv);
+      const double vn = (t0 + t1) + t2;
+      a.v[e] = vn;
+      buf[pl * D + d] = xv + vn;
     }
-    const double nrm = sqrt(s);
-    for (int d = 0; d < D; ++d) {
-      // x + v == 0 exactly means x == -v: restore the previous position
-      const double xv = nrm > 0.0 ? xs[d] / nrm : -vs[d];
-      xs[d] = xv;
-      store_w(a.W_out, a.w_bf16, (base + p) * D + d, xv);
-    }
+  }
+  lds_barrier();
+  if (pv && dl == 0) {
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) s = s + buf[pl * D + d] * buf[pl * D + d];
+    nrm_s[pl] = sqrt(s);
+  }
+  lds_barrier();
+  if (!pv) return;
+  const double nrm = nrm_s[pl];
+  for (int d = dl; d < D; d += g.Dp) {
+    const int64_t e = gid * D + d;
+    // x + v == 0 exactly means x == -v: keep the previous position
+    const double xv = nrm > 0.0 ? buf[pl * D + d] / nrm : -a.v[e];
+    a.x[e] = xv;
+    store_w(a.W_out, a.w_bf16, e, xv);
   }
 }
 
@@ -224,18 +260,38 @@ __global__ void k_predict(const float *w, const float *thr, const int32_t *left,
 
 }  // namespace
 
+void prepare_pso_kernels(int lds_max) {
+  const int dyn = lds_max - 4096;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_pso_move),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess)
+    (void)hipGetLastError();
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_pso_init),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess)
+    (void)hipGetLastError();
+}
+
 slm_status launch_pso_init(const PsoArgs &a, hipStream_t s) {
-  const int64_t total = (int64_t)a.n_nodes * a.P;
-  if (total == 0) return SLM_OK;
-  hipLaunchKernelGGL(k_pso_init, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, a);
+  SLM_CHECK(a.D <= DMAX, SLM_E_SHAPE, "slm_pso_init: D = %d exceeds %d", a.D, DMAX);
+  if ((int64_t)a.n_nodes * a.P == 0) return SLM_OK;
+  const MoveGeom g = move_geom(a.D);
+  const int64_t grid = (int64_t)a.n_nodes * ((a.P + g.PPB - 1) / g.PPB);
+  const size_t lds = (size_t)g.PPB * a.D * sizeof(double);
+  hipLaunchKernelGGL(k_pso_init, dim3((unsigned)grid), dim3(MOVE_WG), lds, s, a);
   SLM_LAUNCHED();
   return SLM_OK;
 }
 
 slm_status launch_pso_step(const PsoArgs &a, hipStream_t s) {
   SLM_CHECK(a.D <= DMAX, SLM_E_SHAPE, "slm_pso_step: D = %d exceeds %d", a.D, DMAX);
+  SLM_CHECK(a.P <= PMAX_STEP, SLM_E_SHAPE, "slm_pso_step: P = %d exceeds %d", a.P, PMAX_STEP);
   if (a.n_nodes == 0) return SLM_OK;
-  hipLaunchKernelGGL(k_pso_step, dim3((unsigned)a.n_nodes), dim3(STEP_WG), 0, s, a);
+  hipLaunchKernelGGL(k_pso_bests, dim3((unsigned)a.n_nodes), dim3(BEST_WG), 0, s, a);
+  SLM_LAUNCHED();
+  if (!a.move) return SLM_OK;
+  const MoveGeom g = move_geom(a.D);
+  const int64_t grid = (int64_t)a.n_nodes * ((a.P + g.PPB - 1) / g.PPB);
+  const size_t lds = ((size_t)g.PPB * a.D + a.D) * sizeof(double);
+  hipLaunchKernelGGL(k_pso_move, dim3((unsigned)grid), dim3(MOVE_WG), lds, s, a);
   SLM_LAUNCHED();
   return SLM_OK;
 }

@@ -25,6 +25,8 @@
 #include "slm_internal.hpp"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
 
 namespace slm {
@@ -37,8 +39,15 @@ struct BinRule {
   float zmin, delta, inv;
   int B;
   bool flat;   // delta == 0 (zmax == zmin or underflow): every edge equals zmin
+  bool fast;   // the guess below is provably within one bin of the count
 };
 
+// The guess floor((z - zmin) * B / r) differs from the exact count by less
+// than 1 + eps bins, with eps <= B u (6 + |zmin| / r) (u = 2^-24: rounding of
+// z - zmin, j * delta, zmin + j * delta, delta and the product); for
+// |zmin| <= 64 r and B <= 256 that is below 1.1e-3, so one step down or up
+// against the exact edges always lands on the count.  Otherwise (a range
+// tiny next to its offset) the exact edges are searched step by step.
 __device__ __forceinline__ BinRule make_rule(float zmin, float zmax, int B) {
   BinRule r;
   const float range = __fsub_rn(zmax, zmin);
@@ -47,6 +56,7 @@ __device__ __forceinline__ BinRule make_rule(float zmin, float zmax, int B) {
   r.inv = (float)B / range;
   r.B = B;
   r.flat = !(r.delta > 0.0f);
+  r.fast = !r.flat && range < __builtin_huge_valf() && fabsf(zmin) <= 64.0f * range;
   return r;
 }
 
@@ -54,13 +64,16 @@ __device__ __forceinline__ float edge(const BinRule &r, int j) {
   return __fadd_rn(r.zmin, __fmul_rn((float)j, r.delta));
 }
 
-// bin(z) = #{ j in 1..B-1 : e_j <= z }.  A guess from (z - zmin) / delta is
-// corrected against the exact float32 edges; the edges are non-decreasing,
-// so the loops stop at the exact count.
+// bin(z) = #{ j in 1..B-1 : e_j <= z } (the edges are non-decreasing).
 __device__ __forceinline__ int bin_of(const BinRule &r, float z) {
-  if (r.flat) return r.B - 1;
   int g = (int)((z - r.zmin) * r.inv);
   g = g < 0 ? 0 : (g > r.B - 1 ? r.B - 1 : g);
+  if (r.fast) {
+    g -= (g >= 1 && edge(r, g) > z) ? 1 : 0;
+    g += (g + 1 <= r.B - 1 && edge(r, g + 1) <= z) ? 1 : 0;
+    return g;
+  }
+  if (r.flat) return r.B - 1;
   while (g >= 1 && edge(r, g) > z) --g;
   while (g + 1 <= r.B - 1 && edge(r, g + 1) <= z) ++g;
   return g;
@@ -91,70 +104,167 @@ __device__ __forceinline__ void wave_argmin(double &l, int &b) {
 
 __device__ __forceinline__ double nlog2n(double x) { return x > 0.0 ? x * log2(x) : 0.0; }
 
+// Out of line: the criterion evaluates it at many call sites, and inlining the
+// FP64 log2 into each of them multiplies the kernel's code size.
+__device__ __noinline__ double nlog2n_big(uint32_t n) { return nlog2n((double)n); }
+
+// n log2 n for integer counts: small counts come from an LDS table filled with
+// the same device log2 (so the values are identical), larger ones are computed.
+constexpr int NL_TBL = 1024;
+__device__ __forceinline__ double nlog2n_cnt(uint32_t n, const double *tbl) {
+  return n < (uint32_t)NL_TBL ? tbl[n] : nlog2n_big(n);
+}
+
+__global__ void k_fill_nlog2n(double *tbl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NL_TBL) tbl[i] = nlog2n((double)i);
+}
+
 // ---------------------------------------------------------------- plan
 struct Plan {
   int PT;       // particles per work-group
-  int64_t CH;   // rows per global chunk
+  int64_t CH;   // rows per global chunk (<= 65472: 16-bit LDS counters)
   int G;        // particle tiles sharing one 128-byte line of a Z row
+  int WG;       // threads per work-group
+  int KT;       // class count rounded up (4 or 16)
 };
 
+constexpr int64_t CH_MAX = 65472;
+
 int64_t chunk_min(int64_t N) {
-  int64_t c = std::max<int64_t>(2048, (N + 255) / 256);
+  int64_t c = std::max<int64_t>(1024, (N + 255) / 256);
   return (c + 63) / 64 * 64;
 }
 
-Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
-  const int64_t per_particle = crit == SLM_MSE ? (int64_t)B * 20 : (int64_t)B * K * 4;
+// Histogram layout.  LDS holds 16-bit counters packed in pairs: bins b and
+// b + 128 share a 32-bit word (low / high half), so a work-group's counts
+// must stay below 2^16 (chunks of at most CH_MAX rows).  Within a bin row the
+// PT particles of a (bin, class) are consecutive words, so the accumulation
+// (lanes = consecutive particles) and the finish (lanes = consecutive
+// particles walking bins) both touch 32 distinct banks per half-wave.  The
+// global accumulator of a multi-chunk node holds plain 32-bit counters in the
+// unfolded layout.
+//   classification: count(b, k, q) in word (b & 127) * SB + k * PT + q, SB = K PT
+//   regression:     count(b, q) in word (b & 127) * SB + q, SB = PT; sum y and
+//                   sum y^2 at b * PT + q in two double arrays
+// The finish splits the bins into NSEG = 2 * waves segments of BSEG bins; its
+// scratch holds per-segment totals and per-segment best splits.
+struct HistLayout {
+  int SB, BH;
+  int nwords;        // packed LDS count words
+  int ncnt;          // unfolded 32-bit counters (global accumulator)
+  size_t lds_cnt;    // packed count region in LDS, 16-byte aligned
+  size_t glob_cnt;   // unfolded count region in the accumulator, 256-byte aligned
+  size_t sums;       // regression sums (both arrays)
+};
+
+__host__ __device__ __forceinline__ HistLayout hist_layout(int PT, int B, int K, bool mse) {
+  HistLayout h;
+  h.SB = mse ? PT : K * PT;
+  h.BH = B < 128 ? B : 128;
+  h.nwords = h.BH * h.SB;
+  h.ncnt = B * h.SB;
+  h.lds_cnt = ((size_t)h.nwords * 4 + 15) / 16 * 16;
+  h.glob_cnt = ((size_t)h.ncnt * 4 + 255) / 256 * 256;
+  h.sums = mse ? (size_t)2 * B * PT * 8 : 0;
+  return h;
+}
+
+constexpr int MAX_SEG = 16;   // 8 waves x 2 halves (work-groups of <= 512 threads)
+// finish scratch: segment totals [NSEG][KT][PT] (u32, or 3 doubles for
+// regression) and segment bests [NSEG][PT] (double + int)
+__host__ __device__ __forceinline__ size_t finish_bytes(int PT, int K, bool mse) {
+  const size_t tot = mse ? (size_t)MAX_SEG * PT * (4 + 16) : (size_t)MAX_SEG * K * PT * 4;
+  return (tot + 15) / 16 * 16 + (size_t)MAX_SEG * PT * 12 + 16;
+}
+
+size_t lds_bytes(int PT, int B, int K, bool mse, bool table) {
+  const HistLayout h = hist_layout(PT, B, K, mse);
+  return h.lds_cnt + h.sums + finish_bytes(PT, K, mse) + (table ? (size_t)NL_TBL * 8 : 0);
+}
+size_t slot_bytes(int PT, int B, int K, bool mse) {
+  const HistLayout h = hist_layout(PT, B, K, mse);
+  return (h.glob_cnt + h.sums + 255) / 256 * 256;
+}
+
+int pick_pt(int P, int B, int K, int crit) {
   int PT = 32;
-  while (PT > 4 && PT * per_particle > 96 * 1024) PT >>= 1;
+  while (PT > 4 && lds_bytes(PT, B, crit == SLM_MSE ? 1 : K, crit == SLM_MSE, crit == SLM_ENTROPY) >
+                       80 * 1024)
+    PT >>= 1;
   while (PT > 4 && PT / 2 >= P) PT >>= 1;
-  // few, large nodes: narrower particle tiles give more work-groups
-  const int64_t n_pt = (P + PT - 1) / PT;
-  const int64_t cmin = chunk_min(N);
-  int64_t CH = cmin;
-  const int64_t blocks = (num_items(n_nodes, N, CH)) * n_pt;
-  if (blocks > 4096) {
-    // plenty of parallelism: larger chunks cut accumulator traffic
-    CH = std::min<int64_t>(65536, cmin * std::max<int64_t>(1, blocks / 4096));
-    CH = (CH + 63) / 64 * 64;
+  return PT;
+}
+
+int num_cus() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+      (void)hipGetLastError();
+      n = 256;
+    }
   }
-  Plan pl{PT, CH, std::max(1, 32 / PT)};
+  return n;
+}
+
+// Plan: 32-particle tiles (a Z row segment is one 128-byte line) when the
+// histograms fit in 80 KB of LDS (two work-groups per CU), 512-thread
+// work-groups, and a chunk length that makes the number of work-groups a
+// whole number of rounds over the CUs.  SLM_SCAN_PLAN="PT:CH:WG" overrides
+// it (tuning sweeps).
+Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
+  Plan pl{pick_pt(P, B, K, crit), chunk_min(N), 1, 512, K <= 4 ? 4 : 16};
+  const char *env = getenv("SLM_SCAN_PLAN");
+  int pt = 0, wg = 0;
+  long long ch = 0;
+  if (env && sscanf(env, "%d:%lld:%d", &pt, &ch, &wg) == 3 &&
+      (pt == 4 || pt == 8 || pt == 16 || pt == 32) && (wg == 256 || wg == 512) &&
+      ch >= chunk_min(N) && ch <= CH_MAX) {
+    pl.PT = pt;
+    pl.CH = (ch + 63) / 64 * 64;
+    pl.WG = wg;
+  } else {
+    const int64_t n_pt = (P + pl.PT - 1) / pl.PT;
+    const int64_t slots = 2 * (int64_t)num_cus();
+    const int64_t cmin = std::max<int64_t>(chunk_min(N), 2048);
+    int64_t CH = cmin;
+    for (int64_t m = 1; m <= 64; ++m) {
+      const int64_t c = (N * n_pt + slots * m - 1) / (slots * m);
+      if (c < cmin) break;
+      CH = c;
+      if (num_items(n_nodes, N, c) * n_pt >= slots * m) break;
+    }
+    pl.CH = std::min<int64_t>(CH_MAX, (CH + 63) / 64 * 64);
+  }
+  pl.G = std::max(1, 32 / pl.PT);
   return pl;
 }
 
-size_t lds_bytes(int PT, int B, int K, bool mse) {
-  if (mse) return (size_t)B * PT * 4 + (size_t)B * PT * 16 + 16;
-  return (size_t)B * K * PT * 4;
-}
-
-size_t slot_bytes(int PT, int B, int K, bool mse) {
-  size_t b = mse ? (size_t)B * PT * 4 : (size_t)B * K * PT * 4;
-  b = (b + 255) / 256 * 256;
-  if (mse) b += (size_t)B * PT * 16;
-  return (b + 255) / 256 * 256;
-}
-
 // ---------------------------------------------------------------- histogram kernel
-template <int PT, bool MSE>
-__global__ __launch_bounds__(WG) void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G,
-                                                  int64_t total_blocks, size_t slot_sz,
-                                                  int64_t n_slots) {
+template <int PT, int KT, bool MSE>
+__global__ __launch_bounds__(512) void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G,
+                                                    int64_t total_blocks, size_t slot_sz,
+                                                    int64_t n_slots, const double *gtbl) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_last;
+  const int WGS = blockDim.x;
   const int B = a.bins;
   const int K = MSE ? 1 : a.K;
-  const int HB = B * K;
+  const HistLayout hl = hist_layout(PT, B, K, MSE);
+  const int SB = hl.SB, SD = PT;
   uint32_t *hc = reinterpret_cast<uint32_t *>(smem);
-  double *hs1 = nullptr, *hs2 = nullptr;
-  if constexpr (MSE) {
-    hs1 = reinterpret_cast<double *>(smem + (((size_t)B * PT * 4 + 15) / 16) * 16);
-    hs2 = hs1 + (size_t)B * PT;
-  }
+  double *hs1 = reinterpret_cast<double *>(smem + hl.lds_cnt);
+  double *hs2 = hs1 + (size_t)B * SD;
+  unsigned char *fin = smem + hl.lds_cnt + hl.sums;
+  double *tbl = reinterpret_cast<double *>(fin + finish_bytes(PT, K, MSE));
+  const bool use_tbl = !MSE && a.crit == SLM_ENTROPY;
 
   // XCD-aware order: the G particle tiles that share a Z cache line get
   // block ids congruent modulo 8, dispatched close together.
-  const int64_t b = blockIdx.x;
-  const int64_t hi8 = b / (8 * G), rem = b % (8 * G);
+  const int64_t bid = blockIdx.x;
+  const int64_t hi8 = bid / (8 * G), rem = bid % (8 * G);
   const int64_t L = ((hi8 * 8 + rem % 8) * G) + rem / 8;
   if (L >= total_blocks) return;
   const int64_t v = L / n_pt;
@@ -163,13 +273,15 @@ __global__ __launch_bounds__(WG) void k_scan_hist(ScanArgs a, int64_t CH, int n_
   if (it.node < 0) return;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < HB * PT; i += WG) hc[i] = 0u;
+  for (int i = tid; i < hl.nwords; i += WGS) hc[i] = 0u;
   if constexpr (MSE) {
-    for (int i = tid; i < B * PT; i += WG) {
+    for (int i = tid; i < B * SD; i += WGS) {
       hs1[i] = 0.0;
       hs2[i] = 0.0;
     }
   }
+  if (use_tbl)
+    for (int i = tid; i < NL_TBL; i += WGS) tbl[i] = gtbl[i];
 
   constexpr int RPW = 64 / PT;                 // rows per wave step
   const int pl = lane % PT, rsub = lane / PT;
@@ -177,220 +289,325 @@ __global__ __launch_bounds__(WG) void k_scan_hist(ScanArgs a, int64_t CH, int n_
   const int p = pt * PT + pl;
   const bool pv = p < P;
   const int64_t np = (int64_t)it.node * P;
-  BinRule rule = make_rule(pv ? a.zmin[np + p] : 0.f, pv ? a.zmax[np + p] : 0.f, B);
-  __syncthreads();
+  const BinRule rule = make_rule(pv ? a.zmin[np + p] : 0.f, pv ? a.zmax[np + p] : 0.f, B);
+  lds_barrier();
 
-  // ---- accumulate
-  const int64_t step = (int64_t)(WG / 64) * RPW;
-  int64_t row = it.lo + wave * RPW + rsub;
-  constexpr int U = 4;
-  for (; row + (U - 1) * step < it.hi; row += U * step) {
-    float z[U];
-    int lab[U];
-    double yv[U];
+  // ---- accumulate.  Straight-line code for the common case: every lane's
+  // particle exists and its edges are well conditioned (the guess is within
+  // one bin), so the bin is computed without branches; 16 rows are in flight
+  // per lane.  Bin b adds 1 << 16 (b >> 7) to word (b & 127); a lane without a
+  // particle, or a row whose label is out of range, adds 0.
+  const int64_t step = (int64_t)(WGS / 64) * RPW;
+  const int64_t row0 = it.lo + wave * RPW + rsub;
+  const int pcl = pv ? p : P - 1;                        // always a valid column
+  const float *zp = a.Z + row0 * P + pcl;
+  const int64_t zstep = step * P;
+  const bool wave_fast = __all(rule.fast || !pv);
+  uint32_t *hrow = hc + pl;
+  auto add_cls = [&](int bn, int lab) {
+    const bool ok = pv && (unsigned)lab < (unsigned)K;
+    const uint32_t inc = ok ? (1u << ((bn >> 7) << 4)) : 0u;
+    const int lb = ok ? lab : 0;
+    atomicAdd(&hrow[(bn & 127) * SB + lb * PT], inc);
+  };
+  auto add_mse = [&](int bn, double yv) {
+    if (!pv) return;
+    atomicAdd(&hrow[(bn & 127) * SB], 1u << ((bn >> 7) << 4));
+    unsafeAtomicAdd(&hs1[bn * SD + pl], yv);
+    unsafeAtomicAdd(&hs2[bn * SD + pl], yv * yv);
+  };
+  const int nrows = (int)((it.hi - row0 + step - 1) / step);   // rows of this lane (may be <= 0)
+  constexpr int U = 16;
+  int i = 0;
+  if (wave_fast) {
+    const float zmin = rule.zmin, delta = rule.delta, inv = rule.inv;
+    const int bmax = B - 1;
+    for (; i + U <= nrows; i += U) {
+      float z[U];
+      int lab[U];
+      double yv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t rr = row + u * step;
-      z[u] = pv ? a.Z[rr * P + p] : 0.f;
-      if constexpr (MSE) yv[u] = a.y[rr];
-      else lab[u] = a.labels[rr];
-    }
+      for (int u = 0; u < U; ++u) {
+        z[u] = zp[(int64_t)(i + u) * zstep];
+        if constexpr (MSE) yv[u] = a.y[row0 + (int64_t)(i + u) * step];
+        else lab[u] = a.labels[row0 + (int64_t)(i + u) * step];
+      }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (!pv) continue;
-      const int bn = bin_of(rule, z[u]);
-      if constexpr (MSE) {
-        atomicAdd(&hc[bn * PT + pl], 1u);
-        unsafeAtomicAdd(&hs1[bn * PT + pl], yv[u]);
-        unsafeAtomicAdd(&hs2[bn * PT + pl], yv[u] * yv[u]);
-      } else {
-        if ((unsigned)lab[u] < (unsigned)K) atomicAdd(&hc[(bn * K + lab[u]) * PT + pl], 1u);
+      for (int u = 0; u < U; ++u) {
+        int g = (int)((z[u] - zmin) * inv);
+        g = min(max(g, 0), bmax);
+        const float fg = (float)g;
+        const float e0 = __fadd_rn(zmin, __fmul_rn(fg, delta));
+        const float e1 = __fadd_rn(zmin, __fmul_rn(fg + 1.0f, delta));
+        g = g - ((g >= 1 && e0 > z[u]) ? 1 : 0) + ((g < bmax && e1 <= z[u]) ? 1 : 0);
+        if constexpr (MSE) add_mse(g, yv[u]);
+        else add_cls(g, lab[u]);
       }
     }
   }
-  for (; row < it.hi; row += step) {
-    if (!pv) continue;
-    const float z = a.Z[row * P + p];
+  for (; i < nrows; ++i) {
+    const float z = zp[(int64_t)i * zstep];
     const int bn = bin_of(rule, z);
-    if constexpr (MSE) {
-      const double yv = a.y[row];
-      atomicAdd(&hc[bn * PT + pl], 1u);
-      unsafeAtomicAdd(&hs1[bn * PT + pl], yv);
-      unsafeAtomicAdd(&hs2[bn * PT + pl], yv * yv);
-    } else {
-      const int lab = a.labels[row];
-      if ((unsigned)lab < (unsigned)K) atomicAdd(&hc[(bn * K + lab) * PT + pl], 1u);
-    }
+    if constexpr (MSE) add_mse(bn, a.y[row0 + (int64_t)i * step]);
+    else add_cls(bn, a.labels[row0 + (int64_t)i * step]);
   }
-  __syncthreads();
+  lds_barrier();
 
-  // ---- merge chunks of a node spanning several of them
+  // ---- nodes spanning several chunks: add into the node's accumulator slot;
+  // the last work-group to arrive finishes from it
+  const uint32_t *gsrc = nullptr;
+  uint32_t *gc = nullptr;
+  double *g1 = nullptr, *g2 = nullptr;
+  uint32_t *ticket = nullptr;
   if (it.nchunks > 1) {
     const Range nr = load_range(a.beg, a.end, it.node, a.N);
     const int64_t slot = nr.lo / CH;
     if (slot >= n_slots) return;   // cannot happen with a workspace sized by the plan
     unsigned char *base = static_cast<unsigned char *>(a.ws) + (size_t)(slot * n_pt + pt) * slot_sz;
-    uint32_t *gc = reinterpret_cast<uint32_t *>(base);
-    const size_t cnt_bytes = ((MSE ? (size_t)B * PT * 4 : (size_t)HB * PT * 4) + 255) / 256 * 256;
-    double *gs = reinterpret_cast<double *>(base + cnt_bytes);
-    uint32_t *tickets = reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(a.ws) +
-                                                     (size_t)n_slots * n_pt * slot_sz);
-    const int ncnt = MSE ? B * PT : HB * PT;
-    for (int i = tid; i < ncnt; i += WG) {
-      const uint32_t c = hc[i];
-      if (c) {
-        atomicAdd(&gc[i], c);
-        if constexpr (MSE) {
-          unsafeAtomicAdd(&gs[i], hs1[i]);
-          unsafeAtomicAdd(&gs[(size_t)B * PT + i], hs2[i]);
-        }
+    gc = reinterpret_cast<uint32_t *>(base);
+    g1 = reinterpret_cast<double *>(base + hl.glob_cnt);
+    g2 = g1 + (size_t)B * SD;
+    ticket = reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(a.ws) +
+                                          (size_t)n_slots * n_pt * slot_sz) + slot * n_pt + pt;
+    for (int i = tid; i < hl.nwords; i += WGS) {
+      const uint32_t w = hc[i];
+      if (w) {
+        const int bl = i / SB, r = i - bl * SB;
+        if (w & 0xFFFFu) atomicAdd(&gc[bl * SB + r], w & 0xFFFFu);
+        if (w >> 16) atomicAdd(&gc[(bl + 128) * SB + r], w >> 16);
+      }
+    }
+    if constexpr (MSE) {
+      for (int i = tid; i < B * SD; i += WGS) {
+        if (hs1[i] != 0.0) unsafeAtomicAdd(&g1[i], hs1[i]);
+        if (hs2[i] != 0.0) unsafeAtomicAdd(&g2[i], hs2[i]);
       }
     }
     __threadfence();
     __syncthreads();
     if (tid == 0) {
-      const unsigned t = atomicAdd(&tickets[slot * n_pt + pt], 1u);
+      const unsigned t = atomicAdd(ticket, 1u);
       s_last = (t == (unsigned)(it.nchunks - 1));
     }
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    for (int i = tid; i < ncnt; i += WG) {
-      hc[i] = __hip_atomic_load(&gc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      gc[i] = 0u;
-      if constexpr (MSE) {
-        hs1[i] = __hip_atomic_load(&gs[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        hs2[i] = __hip_atomic_load(&gs[(size_t)B * PT + i], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        gs[i] = 0.0;
-        gs[(size_t)B * PT + i] = 0.0;
-      }
-    }
-    if (tid == 0) tickets[slot * n_pt + pt] = 0u;
-    __syncthreads();
+    gsrc = gc;
   }
 
-  // ---- finish: one wave per particle
-  for (int q = wave; q < PT; q += WG / 64) {
-    const int pp = pt * PT + q;
-    const bool active = pp < P;
-    const int64_t out = np + pp;
-    const BinRule rr = make_rule(active ? a.zmin[out] : 0.f, active ? a.zmax[out] : 0.f, B);
-    const int b0 = lane * 4;
-    if (active && a.hist_out) {
-      for (int bb = b0; bb < b0 + 4 && bb < B; ++bb)
-        for (int k = 0; k < K; ++k)
-          a.hist_out[(out * B + bb) * K + k] = hc[(bb * K + k) * PT + q];
-    }
-    if constexpr (MSE) {
-      if (active && a.sums_out) {
-        for (int bb = b0; bb < b0 + 4 && bb < B; ++bb) {
-          a.sums_out[(out * B + bb) * 2] = hs1[bb * PT + q];
-          a.sums_out[(out * B + bb) * 2 + 1] = hs2[bb * PT + q];
-        }
-      }
-    }
-    // inclusive prefixes over bins, in place
-    for (int k = 0; k < K; ++k) {
-      uint32_t c[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) c[u] = (b0 + u < B) ? hc[((b0 + u) * K + k) * PT + q] : 0u;
-      c[1] += c[0];
-      c[2] += c[1];
-      c[3] += c[2];
-      const uint32_t excl = wave_incl_scan(c[3], lane) - c[3];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (b0 + u < B) hc[((b0 + u) * K + k) * PT + q] = c[u] + excl;
-    }
-    if constexpr (MSE) {
-      double s1[4], s2[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        s1[u] = (b0 + u < B) ? hs1[(b0 + u) * PT + q] : 0.0;
-        s2[u] = (b0 + u < B) ? hs2[(b0 + u) * PT + q] : 0.0;
-      }
-      s1[1] += s1[0]; s1[2] += s1[1]; s1[3] += s1[2];
-      s2[1] += s2[0]; s2[2] += s2[1]; s2[3] += s2[2];
-      const double e1 = wave_incl_scan(s1[3], lane) - s1[3];
-      const double e2 = wave_incl_scan(s2[3], lane) - s2[3];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (b0 + u < B) {
-          hs1[(b0 + u) * PT + q] = s1[u] + e1;
-          hs2[(b0 + u) * PT + q] = s2[u] + e2;
-        }
-    }
-    __syncthreads();
-    double best = __builtin_huge_val();
-    int bestb = 0x7fffffff;
-    if (active) {
-      for (int u = 0; u < 4; ++u) {
-        const int cand = b0 + u;          // split: bins < cand go left
-        if (cand < 1 || cand > B - 1) continue;
-        double loss;
+  // ---- finish.  Lanes = particles: lane (wave w, half h, q) walks the BSEG
+  // bins of segment s = 2 w + h for particle q.  Pass 1 sums the segment per
+  // class; pass 2 turns the segment totals into the left counts at the
+  // segment start, walks the segment evaluating every candidate split, and
+  // keeps the first minimum; pass 3 takes the minimum over segments in bin
+  // order (ties keep the smaller split).
+  {
+    const int nwv = WGS / 64;
+    const int NSEG = 2 * nwv;
+    const int BSEG = (B + NSEG - 1) / NSEG;
+    constexpr int HP = 32;                       // lanes per half-wave
+    const int half = lane / HP, ql = lane % HP;
+    const int seg = 2 * wave + half;
+    const int b_lo = seg * BSEG, b_hi = min(B, b_lo + BSEG);
+    uint32_t *stot = reinterpret_cast<uint32_t *>(fin);                    // [NSEG][K][PT]
+    double *stot1 = reinterpret_cast<double *>(fin + (size_t)MAX_SEG * PT * 4);  // regression
+    double *stot2 = stot1 + (size_t)MAX_SEG * PT;
+    const size_t tot_bytes = MSE ? (size_t)MAX_SEG * PT * 20 : (size_t)MAX_SEG * K * PT * 4;
+    double *sbl = reinterpret_cast<double *>(fin + (tot_bytes + 15) / 16 * 16);       // [NSEG][PT]
+    int *sbb = reinterpret_cast<int *>(sbl + (size_t)MAX_SEG * PT);
+    auto count = [&](int b, int k, int q) -> uint32_t {
+      const int r = k * PT + q;
+      if (gsrc) return gsrc[b * SB + r];
+      return (hc[(b & 127) * SB + r] >> ((b >> 7) << 4)) & 0xFFFFu;
+    };
+    auto sum1 = [&](int b, int q) -> double { return gsrc ? g1[b * PT + q] : hs1[b * PT + q]; };
+    auto sum2 = [&](int b, int q) -> double { return gsrc ? g2[b * PT + q] : hs2[b * PT + q]; };
+    // particles are handled HP at a time (PT <= 32: one pass)
+    for (int q0 = 0; q0 < PT; q0 += HP) {
+      const int q = q0 + ql;
+      const bool qv = q < PT && pt * PT + q < P;
+      // pass 1: segment totals
+      if (q < PT) {
         if constexpr (MSE) {
-          const uint32_t nL = hc[(cand - 1) * PT + q];
-          const uint32_t n = hc[(B - 1) * PT + q];
-          const uint32_t nR = n - nL;
-          if (nL == 0 || nR == 0) continue;
-          const double S1L = hs1[(cand - 1) * PT + q], S2L = hs2[(cand - 1) * PT + q];
-          const double S1 = hs1[(B - 1) * PT + q], S2 = hs2[(B - 1) * PT + q];
-          const double S1R = S1 - S1L, S2R = S2 - S2L;
-          const double dL = (double)nL, dR = (double)nR;
-          const double sseL = S2L - (S1L * S1L) / dL;
-          const double sseR = S2R - (S1R * S1R) / dR;
-          loss = (sseL + sseR) / (dL + dR);
+          uint32_t c = 0;
+          double t1 = 0.0, t2 = 0.0;
+          for (int b = b_lo; b < b_hi; ++b) {
+            c += count(b, 0, q);
+            t1 += sum1(b, q);
+            t2 += sum2(b, q);
+          }
+          stot[seg * PT + q] = c;
+          stot1[seg * PT + q] = t1;
+          stot2[seg * PT + q] = t2;
         } else {
-          uint64_t AL = 0, AR = 0;
-          int64_t nL = 0, n = 0;
-          double sL = 0.0, sR = 0.0;
-          for (int k = 0; k < K; ++k) {
-            const uint32_t l = hc[((cand - 1) * K + k) * PT + q];
-            const uint32_t t = hc[((B - 1) * K + k) * PT + q];
-            const uint32_t r = t - l;
-            nL += l;
-            n += t;
-            if (a.crit == SLM_GINI) {
-              AL += (uint64_t)l * l;
-              AR += (uint64_t)r * r;
-            } else {
-              sL += nlog2n((double)l);
-              sR += nlog2n((double)r);
+          uint32_t t[KT];
+#pragma unroll
+          for (int k = 0; k < KT; ++k) t[k] = 0;
+          for (int b = b_lo; b < b_hi; ++b)
+#pragma unroll
+            for (int k = 0; k < KT; ++k)
+              if (k < K) t[k] += count(b, k, q);
+#pragma unroll
+          for (int k = 0; k < KT; ++k)
+            if (k < K) stot[(seg * K + k) * PT + q] = t[k];
+        }
+      }
+      __syncthreads();
+      // pass 2: left counts at the segment start, then walk the segment
+      double best = __builtin_huge_val();
+      int bestb = 0x7fffffff;
+      if (q < PT) {
+        if constexpr (MSE) {
+          uint32_t left = 0, tot = 0;
+          double l1 = 0.0, l2 = 0.0, T1 = 0.0, T2 = 0.0;
+          for (int s2 = 0; s2 < NSEG; ++s2) {
+            const uint32_t c = stot[s2 * PT + q];
+            const double x1 = stot1[s2 * PT + q], x2 = stot2[s2 * PT + q];
+            if (s2 < seg) {
+              left += c;
+              l1 += x1;
+              l2 += x2;
             }
+            tot += c;
+            T1 += x1;
+            T2 += x2;
           }
-          const int64_t nR = n - nL;
-          if (nL == 0 || nR == 0) continue;
+          for (int b = b_lo; b < b_hi; ++b) {
+            if (b >= 1) {                        // split b: bins < b go left
+              const uint32_t nL = left, nR = tot - left;
+              if (nL != 0 && nR != 0) {
+                const double dL = (double)nL, dR = (double)nR;
+                const double S1R = T1 - l1, S2R = T2 - l2;
+                const double sseL = l2 - (l1 * l1) / dL;
+                const double sseR = S2R - (S1R * S1R) / dR;
+                const double loss = (sseL + sseR) / (dL + dR);
+                if (loss < best) {
+                  best = loss;
+                  bestb = b;
+                }
+              }
+            }
+            left += count(b, 0, q);
+            l1 += sum1(b, q);
+            l2 += sum2(b, q);
+          }
+        } else {
+          uint32_t left[KT], tot[KT];
+#pragma unroll
+          for (int k = 0; k < KT; ++k) {
+            left[k] = 0;
+            tot[k] = 0;
+          }
+          for (int s2 = 0; s2 < NSEG; ++s2)
+#pragma unroll
+            for (int k = 0; k < KT; ++k)
+              if (k < K) {
+                const uint32_t c = stot[(s2 * K + k) * PT + q];
+                if (s2 < seg) left[k] += c;
+                tot[k] += c;
+              }
+          int64_t n = 0;
+          double TL0 = 0.0;
+#pragma unroll
+          for (int k = 0; k < KT; ++k) n += tot[k];
+          (void)TL0;
           const double dn = (double)n;
-          if (a.crit == SLM_GINI) {
-            const double s = (double)AL / (double)nL + (double)AR / (double)nR;
-            loss = (dn - s) / dn;
-          } else {
-            const double TL = nlog2n((double)nL) - sL;
-            const double TR = nlog2n((double)nR) - sR;
-            loss = (TL + TR) / dn;
+          for (int b = b_lo; b < b_hi; ++b) {
+            if (b >= 1) {
+              uint64_t AL = 0, AR = 0;
+              int64_t nL = 0;
+              double sL = 0.0, sR = 0.0;
+#pragma unroll
+              for (int k = 0; k < KT; ++k) {
+                if (k < K) {
+                  const uint32_t l = left[k], r = tot[k] - l;
+                  nL += l;
+                  if (a.crit == SLM_GINI) {
+                    AL += (uint64_t)l * l;
+                    AR += (uint64_t)r * r;
+                  } else {
+                    sL += nlog2n_cnt(l, tbl);
+                    sR += nlog2n_cnt(r, tbl);
+                  }
+                }
+              }
+              const int64_t nR = n - nL;
+              if (nL != 0 && nR != 0) {
+                double loss;
+                if (a.crit == SLM_GINI) {
+                  const double sv = (double)AL / (double)nL + (double)AR / (double)nR;
+                  loss = (dn - sv) / dn;
+                } else {
+                  const double TL = nlog2n_cnt((uint32_t)nL, tbl) - sL;
+                  const double TR = nlog2n_cnt((uint32_t)nR, tbl) - sR;
+                  loss = (TL + TR) / dn;
+                }
+                if (loss < best) {
+                  best = loss;
+                  bestb = b;
+                }
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < KT; ++k)
+              if (k < K) left[k] += count(b, k, q);
           }
         }
-        if (loss < best) {
-          best = loss;
-          bestb = cand;
+        sbl[seg * PT + q] = best;
+        sbb[seg * PT + q] = bestb;
+      }
+      // optional raw histogram / sums output: lanes = particles, segment bins
+      if (qv && a.hist_out) {
+        const int64_t out = np + pt * PT + q;
+        for (int b = b_lo; b < b_hi; ++b)
+          for (int k = 0; k < K; ++k) a.hist_out[(out * B + b) * K + k] = count(b, k, q);
+      }
+      if constexpr (MSE) {
+        if (qv && a.sums_out) {
+          const int64_t out = np + pt * PT + q;
+          for (int b = b_lo; b < b_hi; ++b) {
+            a.sums_out[(out * B + b) * 2] = sum1(b, q);
+            a.sums_out[(out * B + b) * 2 + 1] = sum2(b, q);
+          }
         }
       }
-    }
-    wave_argmin(best, bestb);
-    if (active && lane == 0) {
-      if (bestb == 0x7fffffff) {
-        a.best_split[out] = -1;
-        a.best_loss[out] = __builtin_huge_val();
-        a.threshold[out] = __builtin_huge_valf();
-      } else {
-        a.best_split[out] = bestb;
-        a.best_loss[out] = best;
-        a.threshold[out] = edge(rr, bestb);
+      __syncthreads();
+      // pass 3: minimum over segments in bin order
+      if (wave == 0 && half == 0 && qv) {
+        double bl = __builtin_huge_val();
+        int bb = 0x7fffffff;
+        for (int s2 = 0; s2 < NSEG; ++s2) {
+          const double l = sbl[s2 * PT + q];
+          if (l < bl) {
+            bl = l;
+            bb = sbb[s2 * PT + q];
+          }
+        }
+        const int64_t out = np + pt * PT + q;
+        if (bb == 0x7fffffff) {
+          a.best_split[out] = -1;
+          a.best_loss[out] = __builtin_huge_val();
+          a.threshold[out] = __builtin_huge_valf();
+        } else {
+          const BinRule rr = make_rule(a.zmin[out], a.zmax[out], B);
+          a.best_split[out] = bb;
+          a.best_loss[out] = bl;
+          a.threshold[out] = edge(rr, bb);
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
+    // leave a multi-chunk slot zero-filled for the next call
+    if (gsrc) {
+      for (int i = tid; i < hl.ncnt; i += WGS) gc[i] = 0u;
+      if constexpr (MSE)
+        for (int i = tid; i < B * PT; i += WGS) {
+          g1[i] = 0.0;
+          g2[i] = 0.0;
+        }
+    }
   }
+  if (gsrc && tid == 0) *ticket = 0u;
 }
 
 // Nodes without rows get no work item in the histogram scan: report "no
@@ -620,41 +837,63 @@ __global__ __launch_bounds__(WG) void k_scan_exact(ScanArgs a) {
   }
 }
 
-template <int PT, bool MSE>
-slm_status launch_hist_pt(const ScanArgs &a, const Plan &pl, hipStream_t s) {
+template <int PT, int KT, bool MSE>
+slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
   const int n_pt = (a.P + PT - 1) / PT;
   const int64_t items = num_items(a.n_nodes, a.N, pl.CH);
   const int64_t total = items * n_pt;
   if (total == 0) return SLM_OK;
   const int64_t grid = (total + 8 * pl.G - 1) / (8 * pl.G) * (8 * pl.G);
   SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_split_scan: grid too large");
-  const size_t lds = lds_bytes(PT, a.bins, a.K, MSE);
-  const size_t slot = slot_bytes(PT, a.bins, MSE ? 1 : a.K, MSE);
+  const int Kc = MSE ? 1 : a.K;
+  const bool table = !MSE && a.crit == SLM_ENTROPY;
+  const size_t lds = lds_bytes(PT, a.bins, Kc, MSE, table);
+  const size_t slot = slot_bytes(PT, a.bins, Kc, MSE);
   const int64_t n_slots = (a.N - 1) / chunk_min(a.N) + 1;
-  auto kern = k_scan_hist<PT, MSE>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(WG), lds, s, a, pl.CH, n_pt, pl.G, total,
-                     slot, n_slots);
+  double *gtbl = nullptr;
+  if (table) {
+    // the table sits at the (256-byte aligned) end of the workspace
+    uintptr_t e = reinterpret_cast<uintptr_t>(a.ws) + a.ws_bytes - (size_t)NL_TBL * 8;
+    gtbl = reinterpret_cast<double *>(e & ~(uintptr_t)255);
+    hipLaunchKernelGGL(k_fill_nlog2n, dim3(NL_TBL / 256), dim3(256), 0, s, gtbl);
+    SLM_LAUNCHED();
+  }
+  hipLaunchKernelGGL((k_scan_hist<PT, KT, MSE>), dim3((unsigned)grid), dim3(pl.WG), lds, s, a, pl.CH,
+                     n_pt, pl.G, total, slot, n_slots, gtbl);
   SLM_LAUNCHED();
   return SLM_OK;
 }
 
-template <bool MSE>
+template <int PT>
+slm_status launch_hist_pt(const ScanArgs &a, const Plan &pl, hipStream_t s) {
+  if (a.crit == SLM_MSE) return launch_hist_cfg<PT, 1, true>(a, pl, s);
+  if (pl.KT == 4) return launch_hist_cfg<PT, 4, false>(a, pl, s);
+  return launch_hist_cfg<PT, 16, false>(a, pl, s);
+}
+
 slm_status launch_hist(const ScanArgs &a, const Plan &pl, hipStream_t s) {
   switch (pl.PT) {
-    case 32: return launch_hist_pt<32, MSE>(a, pl, s);
-    case 16: return launch_hist_pt<16, MSE>(a, pl, s);
-    case 8: return launch_hist_pt<8, MSE>(a, pl, s);
-    default: return launch_hist_pt<4, MSE>(a, pl, s);
+    case 32: return launch_hist_pt<32>(a, pl, s);
+    case 16: return launch_hist_pt<16>(a, pl, s);
+    case 8: return launch_hist_pt<8>(a, pl, s);
+    default: return launch_hist_pt<4>(a, pl, s);
   }
 }
 
-template <int PT, bool MSE>
+template <int PT, int KT, bool MSE>
 void set_lds_attr(int bytes) {
   // Best effort: raise the dynamic-LDS limit for the large-histogram tiles.
   // A refusal is cleared and left to the launch, which then reports it.
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_scan_hist<PT, MSE>),
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_scan_hist<PT, KT, MSE>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
     (void)hipGetLastError();
+}
+
+template <int PT>
+void set_lds_attr_pt(int bytes) {
+  set_lds_attr<PT, 1, true>(bytes);
+  set_lds_attr<PT, 4, false>(bytes);
+  set_lds_attr<PT, 16, false>(bytes);
 }
 
 }  // namespace
@@ -669,14 +908,11 @@ slm_status prepare_kernels() {
       return;
     }
     const int dyn = lds - 1024;   // room for the kernels' static LDS
-    set_lds_attr<32, false>(dyn);
-    set_lds_attr<16, false>(dyn);
-    set_lds_attr<8, false>(dyn);
-    set_lds_attr<4, false>(dyn);
-    set_lds_attr<32, true>(dyn);
-    set_lds_attr<16, true>(dyn);
-    set_lds_attr<8, true>(dyn);
-    set_lds_attr<4, true>(dyn);
+    set_lds_attr_pt<32>(dyn);
+    set_lds_attr_pt<16>(dyn);
+    set_lds_attr_pt<8>(dyn);
+    set_lds_attr_pt<4>(dyn);
+    prepare_pso_kernels(lds);
   });
   return SLM_OK;
 }
@@ -690,11 +926,10 @@ size_t scan_workspace_bytes(int64_t N, int n_nodes, int P, int bins, int K, int 
   size_t worst = 0;
   for (int PT = 4; PT <= 32; PT <<= 1) {
     const int64_t n_pt = (P + PT - 1) / PT;
-    worst = std::max(worst, (size_t)n_pt * slot_bytes(PT, bins, Kc, mse) +
-                                (size_t)n_pt * 4);
+    worst = std::max(worst, (size_t)n_pt * slot_bytes(PT, bins, Kc, mse) + (size_t)n_pt * 4);
   }
   const int64_t n_slots = (N - 1) / chunk_min(N) + 1;
-  return (size_t)n_slots * worst + 256;
+  return (size_t)n_slots * worst + 256 + (size_t)NL_TBL * 8 + 256;
 }
 
 slm_status launch_scan_empty_nodes(const ScanArgs &a, hipStream_t s) {
@@ -709,8 +944,7 @@ slm_status launch_scan_empty_nodes(const ScanArgs &a, hipStream_t s) {
 slm_status launch_scan_hist(const ScanArgs &a, hipStream_t s) {
   if (a.N <= 0 || a.n_nodes <= 0) return SLM_OK;
   const Plan pl = make_plan(a.N, a.n_nodes, a.P, a.bins, a.crit == SLM_MSE ? 1 : a.K, a.crit);
-  if (a.crit == SLM_MSE) return launch_hist<true>(a, pl, s);
-  return launch_hist<false>(a, pl, s);
+  return launch_hist(a, pl, s);
 }
 
 slm_status launch_scan_exact(const ScanArgs &a, int max_rows, hipStream_t s) {

@@ -16,7 +16,7 @@ namespace slm {
 namespace {
 
 constexpr int WG = 256;
-constexpr int64_t PART_CH = 4096;
+constexpr int64_t PART_CH = 1024;
 
 __device__ __forceinline__ unsigned long long enc_f64(double d) {
   unsigned long long u = (unsigned long long)__double_as_longlong(d);
@@ -172,9 +172,23 @@ __global__ __launch_bounds__(WG) void k_part_scatter(PartArgs a) {
     }
     __syncthreads();
     // coalesced copy of the round's rows to their destinations
-    for (int64_t e = tid; e < nin * a.D; e += WG) {
-      const int64_t q = e / a.D, c = e - q * a.D;
-      a.Xn[dest[q] * a.D + c] = a.X[(r0 + q) * a.D + c];
+    // 8 loads in flight per thread, then the stores
+    const int ne = (int)nin * a.D;
+    for (int e0 = tid; e0 < ne; e0 += 8 * WG) {
+      float vals[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * WG;
+        vals[u] = e < ne ? a.X[r0 * a.D + e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * WG;
+        if (e < ne) {
+          const int q = e / a.D, c = e - q * a.D;
+          a.Xn[dest[q] * a.D + c] = vals[u];
+        }
+      }
     }
     if (in) {
       if (a.lab) a.labn[dest[tid]] = a.lab[r];
@@ -182,7 +196,7 @@ __global__ __launch_bounds__(WG) void k_part_scatter(PartArgs a) {
     }
     base_l += tot_l;
     base_r += (uint32_t)nin - tot_l;
-    __syncthreads();
+    lds_barrier();
   }
   // children statistics: index 2*j (left), 2*j+1 (right)
   for (int side = 0; side < 2; ++side) {

@@ -539,6 +539,8 @@ slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss,
   if (n_nodes == 0) return SLM_OK;
   SLM_CHECK(x && v && pbest && pbest_loss && gbest && gbest_loss && gbest_p && node_id && W_out,
             SLM_E_INVALID, "slm_pso_init: NULL pointer");
+  slm_status pst = prepare_kernels();
+  if (pst) return pst;
   PsoArgs a{};
   a.x = x; a.v = v; a.pbest = pbest; a.pbest_loss = pbest_loss; a.gbest = gbest;
   a.gbest_loss = gbest_loss; a.gbest_p = gbest_p; a.node_id = node_id;
@@ -568,6 +570,8 @@ slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss,
   SLM_CHECK((split == nullptr) == (gbest_split == nullptr) &&
                 (thr == nullptr) == (gbest_thr == nullptr),
             SLM_E_INVALID, "slm_pso_step: split/gbest_split and thr/gbest_thr go in pairs");
+  slm_status pst = prepare_kernels();
+  if (pst) return pst;
   PsoArgs a{};
   a.x = x; a.v = v; a.pbest = pbest; a.pbest_loss = pbest_loss; a.gbest = gbest;
   a.gbest_loss = gbest_loss; a.gbest_p = gbest_p; a.loss = loss; a.split = split; a.thr = thr;

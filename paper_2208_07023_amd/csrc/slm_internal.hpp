@@ -103,6 +103,15 @@ __host__ __device__ __forceinline__ int64_t num_items(int n_nodes, int64_t N, in
   return N > 0 ? (int64_t)n_nodes + (N - 1) / CH + 1 : 0;
 }
 
+// Work-group barrier that orders LDS only.  __syncthreads() also waits for
+// the group's outstanding global stores, which stalls loops that stream
+// results out while staging the next tile in LDS.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------- float atomics
 // Order-preserving min/max on float via integer atomics.  -0.0 is folded to
 // +0.0 first (they compare equal), NaN is not expected.
@@ -192,6 +201,7 @@ struct PsoArgs {
   const uint64_t *seed_tree_dev;
 };
 slm_status launch_pso_init(const PsoArgs &a, hipStream_t s);
+void prepare_pso_kernels(int lds_max);
 slm_status launch_pso_step(const PsoArgs &a, hipStream_t s);
 
 slm_status launch_predict(const float *w, const float *thr, const int32_t *left,
