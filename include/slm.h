@@ -48,6 +48,15 @@ typedef enum { SLM_F32 = 0, SLM_BF16 = 1, SLM_F64 = 2, SLM_I32 = 3 } slm_dtype;
  * their sample counts and divided by the node's count. */
 typedef enum { SLM_GINI = 0, SLM_ENTROPY = 1, SLM_MSE = 2 } slm_criterion;
 
+/* Layout of a projected-feature matrix Z (N rows, P particles per node):
+ *   SLM_Z_ROWS  : row-major [N, P]; Z[i, p] at i * P + p.
+ *   SLM_Z_TILED : particle-tiled [ceil(P/32), N, 32]; Z[i, p] at
+ *                 ((p / 32) * N + i) * 32 + p % 32.  Each 32-particle tile is
+ *                 one contiguous [N, 32] block (the scan streams it), and the
+ *                 buffer holds ceil(P/32) * 32 * N floats; columns p >= P of
+ *                 the last tile are not written. */
+typedef enum { SLM_Z_ROWS = 0, SLM_Z_TILED = 1 } slm_z_layout;
+
 /* Library version string (static storage). */
 const char *slm_version(void);
 
@@ -62,7 +71,8 @@ const char *slm_last_error(void);
  *   zmin[j*P + p] = min over node j's rows of Z[i, p], zmax likewise.
  *
  * X [N, D] and W [n_nodes*P, D] are both F32 or both BF16; products are
- * accumulated in FP32 on the matrix cores.  Z [N, P] is FP32.  Rows outside
+ * accumulated in FP32 on the matrix cores.  Z is FP32 in z_layout
+ * (slm_z_layout; [N, P] for SLM_Z_ROWS).  Rows outside
  * every segment are not written.  For an empty node zmin = +inf, zmax = -inf.
  * A -0.0 projection is recorded in zmin/zmax as +0.0 (the two compare equal
  * and give identical bin edges).  Asynchronous.
@@ -70,13 +80,14 @@ const char *slm_last_error(void);
 slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D,
                        const void *W, int32_t w_dtype,
                        const int64_t *row_off, int32_t n_nodes, int32_t P,
-                       float *Z, float *zmin, float *zmax, void *stream);
+                       float *Z, int32_t z_layout, float *zmin, float *zmax, void *stream);
 
 /* ------------------------------------------------------------------------
  * slm_split_scan -- best threshold of every projected feature (Sec. II-A,
  * Eqs. (3)-(4): samples with z >= t go right, z < t go left; Sec. III-B: the
  * loss of a direction is the loss of its best threshold).
  *
+ * Z is read in z_layout (slm_z_layout), as written by slm_project.
  * bins = 0: exact scan.  Candidates are the boundaries between consecutive
  *   distinct sorted values of a node's column; the threshold is the smallest
  *   value sent right and best_split is the number of samples sent left.
@@ -100,13 +111,12 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D,
  *   (sum y, sum y^2 per bin; FP64 atomics, last bits order-dependent).
  * workspace: device scratch of at least slm_split_scan_workspace(...) bytes.
  *   It must be zero-filled before its first use and not modified by the
- *   caller between calls: every call leaves its accumulator part zero-filled
- *   again (its tail holds a table the call rewrites), so one workspace can be
- *   reused by consecutive calls on one stream.
+ *   caller between calls: every call leaves it zero-filled again, so one
+ *   workspace can be reused by consecutive calls on one stream.
  * ------------------------------------------------------------------------ */
 size_t slm_split_scan_workspace(int64_t N, int32_t n_nodes, int32_t P, int32_t bins,
                                 int32_t K, int32_t crit);
-slm_status slm_split_scan(const float *Z, const float *zmin, const float *zmax,
+slm_status slm_split_scan(const float *Z, int32_t z_layout, const float *zmin, const float *zmax,
                           const void *target, int32_t t_dtype, int32_t K, int64_t N,
                           const int64_t *row_off, int32_t n_nodes, int32_t P,
                           int32_t bins, int32_t crit,

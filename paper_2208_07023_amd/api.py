@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libslm.so")
 
 F32, BF16, F64, I32 = 0, 1, 2, 3
 GINI, ENTROPY, MSE = 0, 1, 2
+Z_ROWS, Z_TILED = 0, 1
 STATUS = {0: "SLM_OK", 1: "SLM_E_INVALID", 2: "SLM_E_SHAPE", 3: "SLM_E_DTYPE",
           4: "SLM_E_NOMEM", 5: "SLM_E_HIP", 6: "SLM_E_UNSUPPORTED"}
 
@@ -55,9 +56,10 @@ _VP, _I32, _I64, _U32, _U64, _D, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.
 _SIGS = {
     "slm_version": ([], ctypes.c_char_p),
     "slm_last_error": ([], ctypes.c_char_p),
-    "slm_project": ([_VP, _I32, _I64, _I32, _VP, _I32, _VP, _I32, _I32, _VP, _VP, _VP, _VP], _I32),
+    "slm_project": ([_VP, _I32, _I64, _I32, _VP, _I32, _VP, _I32, _I32, _VP, _I32, _VP, _VP, _VP],
+                    _I32),
     "slm_split_scan_workspace": ([_I64, _I32, _I32, _I32, _I32, _I32], _SZ),
-    "slm_split_scan": ([_VP, _VP, _VP, _VP, _I32, _I32, _I64, _VP, _I32, _I32, _I32, _I32,
+    "slm_split_scan": ([_VP, _I32, _VP, _VP, _VP, _I32, _I32, _I64, _VP, _I32, _I32, _I32, _I32,
                         _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], _I32),
     "slm_pso_init": ([_VP] * 7 + [_VP, _I32, _I32, _I32, _U64, _U32, _VP, _I32, _VP], _I32),
     "slm_pso_step": ([_VP] * 7 + [_VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _I32, _D, _D, _D,
@@ -116,8 +118,9 @@ def _xdtype(X):
 
 
 # ------------------------------------------------------------------ project
-def project(X, W, row_off, P: int):
-    """Z [N, P] = per-node X W^T, zmin/zmax [n_nodes*P] (Eq. (1))."""
+def project(X, W, row_off, P: int, tiled: bool = False):
+    """Z = per-node X W^T, zmin/zmax [n_nodes*P] (Eq. (1)).  Z is [N, P], or
+    with tiled=True the particle-tiled [ceil(P/32), N, 32] (SLM_Z_TILED)."""
     load()
     xt = _xdtype(X)
     _dev(X, X.dtype, "X")
@@ -125,12 +128,31 @@ def project(X, W, row_off, P: int):
     _dev(row_off, torch.int64, "row_off")
     N, D = X.shape
     nn = row_off.numel() - 1
-    Z = torch.empty((N, P), dtype=torch.float32, device=X.device)
+    if tiled:
+        Z = torch.empty(((P + 31) // 32, N, 32), dtype=torch.float32, device=X.device)
+    else:
+        Z = torch.empty((N, P), dtype=torch.float32, device=X.device)
     zmin = torch.empty(nn * P, dtype=torch.float32, device=X.device)
     zmax = torch.empty_like(zmin)
-    _check(_lib.slm_project(_p(X), xt, N, D, _p(W), xt, _p(row_off), nn, P, _p(Z), _p(zmin),
-                            _p(zmax), _stream()), "slm_project")
+    _check(_lib.slm_project(_p(X), xt, N, D, _p(W), xt, _p(row_off), nn, P, _p(Z),
+                            Z_TILED if tiled else Z_ROWS, _p(zmin), _p(zmax), _stream()),
+           "slm_project")
     return Z, zmin, zmax
+
+
+def tile_z(Z, P: int):
+    """[N, P] -> particle-tiled [ceil(P/32), N, 32] (padding columns zero)."""
+    N = Z.shape[0]
+    T = (P + 31) // 32
+    out = Z.new_zeros((N, T * 32))
+    out[:, :P] = Z
+    return out.view(N, T, 32).permute(1, 0, 2).contiguous()
+
+
+def untile_z(Zt, P: int):
+    """Particle-tiled [ceil(P/32), N, 32] -> [N, P]."""
+    T, N, _ = Zt.shape
+    return Zt.permute(1, 0, 2).reshape(N, T * 32)[:, :P].contiguous()
 
 
 # ------------------------------------------------------------------ split scan
@@ -150,11 +172,19 @@ def scan_workspace(nbytes: int, device) -> torch.Tensor:
 
 def split_scan(Z, zmin, zmax, target, K: int, row_off, P: int, bins: int, crit: int,
                hist: bool = False, sums: bool = False):
-    """Best threshold per (node, particle); see slm_split_scan."""
+    """Best threshold per (node, particle); see slm_split_scan.  Z is [N, P]
+    or particle-tiled [ceil(P/32), N, 32]."""
     load()
     _dev(Z, torch.float32, "Z")
     _dev(row_off, torch.int64, "row_off")
-    N = Z.shape[0]
+    if Z.dim() == 3:
+        if Z.shape[0] != (P + 31) // 32 or Z.shape[2] != 32:
+            raise ValueError("tiled Z must be [ceil(P/32), N, 32]")
+        N, zl = Z.shape[1], Z_TILED
+    else:
+        if Z.dim() != 2 or Z.shape[1] != P:
+            raise ValueError("Z must be [N, P]")
+        N, zl = Z.shape[0], Z_ROWS
     nn = row_off.numel() - 1
     if crit == MSE:
         _dev(target, torch.float64, "target")
@@ -171,7 +201,7 @@ def split_scan(Z, zmin, zmax, target, K: int, row_off, P: int, bins: int, crit: 
     sums_t = torch.empty(nn * P * bins * 2, dtype=torch.float64, device=dev) if (sums and bins) else None
     need = _lib.slm_split_scan_workspace(N, nn, P, bins, K, crit)
     ws = scan_workspace(need, dev)
-    _check(_lib.slm_split_scan(_p(Z), _p(zmin) if bins else None, _p(zmax) if bins else None,
+    _check(_lib.slm_split_scan(_p(Z), zl, _p(zmin) if bins else None, _p(zmax) if bins else None,
                                _p(target), tt, K, N, _p(row_off), nn, P, bins, crit, _p(split),
                                _p(loss), _p(thr), _p(hist_t), _p(sums_t), _p(ws), ws.numel(),
                                _stream()), "slm_split_scan")

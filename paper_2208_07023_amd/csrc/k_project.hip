@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         const int64_t row = r0 + rr;
         if (p < P && row >= it.lo && row < it.hi) {
           const float z = acc[i][k][r];
-          a.Z[row * P + p] = z;
+          a.Z[z_col(a.zl, p) + row * a.zl.rs] = z;
           mn = fminf(mn, z);
           mx = fmaxf(mx, z);
         }
@@ -239,12 +239,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
       const int p = pw + f * 32 + li;
-      float *zc = a.Z + (r0 + 4 * kh) * P + p;
+      const int64_t rs = a.zl.rs;
+      float *zc = a.Z + z_col(a.zl, p) + (r0 + 4 * kh) * rs;
       if (interior) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const float z = acc[f][r];
-          zc[(int64_t)(8 * (r >> 2) + (r & 3)) * P] = z;
+          zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = z;
           mn[f] = fminf(mn[f], z);
           mx[f] = fmaxf(mx[f], z);
         }
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
           const int64_t row = r0 + 8 * (r >> 2) + 4 * kh + (r & 3);
           if (p < P && row >= it.lo && row < it.hi) {
             const float z = acc[f][r];
-            zc[(int64_t)(8 * (r >> 2) + (r & 3)) * P] = z;
+            zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = z;
             mn[f] = fminf(mn[f], z);
             mx[f] = fmaxf(mx[f], z);
           }

@@ -104,20 +104,39 @@ __device__ __forceinline__ void wave_argmin(double &l, int &b) {
 
 __device__ __forceinline__ double nlog2n(double x) { return x > 0.0 ? x * log2(x) : 0.0; }
 
-// Out of line: the criterion evaluates it at many call sites, and inlining the
-// FP64 log2 into each of them multiplies the kernel's code size.
-__device__ __noinline__ double nlog2n_big(uint32_t n) { return nlog2n((double)n); }
-
-// n log2 n for integer counts: small counts come from an LDS table filled with
-// the same device log2 (so the values are identical), larger ones are computed.
-constexpr int NL_TBL = 1024;
-__device__ __forceinline__ double nlog2n_cnt(uint32_t n, const double *tbl) {
-  return n < (uint32_t)NL_TBL ? tbl[n] : nlog2n_big(n);
+// n log2 n of an integer count without a library call (the finish evaluates
+// it 2K + 2 times per candidate split, inside fully unrolled code where a
+// call would spill the register-resident histogram).  With n = m 2^e,
+// m in [1, 2), and c = 1 + j/128 the largest grid point <= m:
+//   log2 n = e + log2 c + log1p(r) / ln 2,   r = (m - c) / c in [0, 2^-7),
+// m - c is exact, 1/c and log2 c come from a 128-entry table (lg[j], rc[j])
+// filled by the work-group with the device log2, and log1p(r) is its Taylor
+// series to r^8 (truncation < 2^-63 / 9).  Relative error is a few ulp.
+constexpr int LG_TBL = 128;
+__device__ __forceinline__ double nlog2n_cnt(uint32_t n, const double *lg, const double *rc) {
+  const double x = (double)n;
+  int e;
+  const double m = 2.0 * frexp(x, &e);            // x = m 2^(e - 1), m in [1, 2)
+  const int j = (int)((m - 1.0) * 128.0) & (LG_TBL - 1);   // n = 0 gives m = 0: any j
+  const double r = (m - (1.0 + (double)j * (1.0 / 128.0))) * rc[j];
+  double q = -1.0 / 8.0;
+  q = fma(q, r, 1.0 / 7.0);
+  q = fma(q, r, -1.0 / 6.0);
+  q = fma(q, r, 1.0 / 5.0);
+  q = fma(q, r, -1.0 / 4.0);
+  q = fma(q, r, 1.0 / 3.0);
+  q = fma(q, r, -1.0 / 2.0);
+  q = fma(q, r, 1.0);
+  const double l2 = (double)(e - 1) + fma(q * r, 1.4426950408889634, lg[j]);
+  return n ? x * l2 : 0.0;
 }
 
-__global__ void k_fill_nlog2n(double *tbl) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < NL_TBL) tbl[i] = nlog2n((double)i);
+__device__ __forceinline__ void fill_log_table(double *lg, double *rc, int tid) {
+  if (tid < LG_TBL) {
+    const double c = 1.0 + (double)tid * (1.0 / 128.0);
+    lg[tid] = log2(c);
+    rc[tid] = 1.0 / c;
+  }
 }
 
 // ---------------------------------------------------------------- plan
@@ -125,8 +144,7 @@ struct Plan {
   int PT;       // particles per work-group
   int64_t CH;   // rows per global chunk (<= 65472: 16-bit LDS counters)
   int G;        // particle tiles sharing one 128-byte line of a Z row
-  int WG;       // threads per work-group
-  int KT;       // class count rounded up (4 or 16)
+  int KT;       // class register tile: K for K <= 4, else 8 or 16; 1 for regression
 };
 
 constexpr int64_t CH_MAX = 65472;
@@ -140,21 +158,18 @@ int64_t chunk_min(int64_t N) {
 // b + 128 share a 32-bit word (low / high half), so a work-group's counts
 // must stay below 2^16 (chunks of at most CH_MAX rows).  Within a bin row the
 // PT particles of a (bin, class) are consecutive words, so the accumulation
-// (lanes = consecutive particles) and the finish (lanes = consecutive
-// particles walking bins) both touch 32 distinct banks per half-wave.  The
-// global accumulator of a multi-chunk node holds plain 32-bit counters in the
-// unfolded layout.
+// (lanes = consecutive particles) touches 32 distinct banks per half-wave.
+// The global accumulator of a multi-chunk node mirrors the LDS words with
+// 64-bit words holding two 32-bit counters (bin b low, bin b + 128 high), so
+// one 64-bit atomic merges both halves of an LDS word.
 //   classification: count(b, k, q) in word (b & 127) * SB + k * PT + q, SB = K PT
 //   regression:     count(b, q) in word (b & 127) * SB + q, SB = PT; sum y and
 //                   sum y^2 at b * PT + q in two double arrays
-// The finish splits the bins into NSEG = 2 * waves segments of BSEG bins; its
-// scratch holds per-segment totals and per-segment best splits.
 struct HistLayout {
   int SB, BH;
-  int nwords;        // packed LDS count words
-  int ncnt;          // unfolded 32-bit counters (global accumulator)
+  int nwords;        // packed count words (LDS u32, accumulator u64)
   size_t lds_cnt;    // packed count region in LDS, 16-byte aligned
-  size_t glob_cnt;   // unfolded count region in the accumulator, 256-byte aligned
+  size_t glob_cnt;   // count region of an accumulator slot, 256-byte aligned
   size_t sums;       // regression sums (both arrays)
 };
 
@@ -163,34 +178,54 @@ __host__ __device__ __forceinline__ HistLayout hist_layout(int PT, int B, int K,
   h.SB = mse ? PT : K * PT;
   h.BH = B < 128 ? B : 128;
   h.nwords = h.BH * h.SB;
-  h.ncnt = B * h.SB;
   h.lds_cnt = ((size_t)h.nwords * 4 + 15) / 16 * 16;
-  h.glob_cnt = ((size_t)h.ncnt * 4 + 255) / 256 * 256;
+  h.glob_cnt = ((size_t)h.nwords * 8 + 255) / 256 * 256;
   h.sums = mse ? (size_t)2 * B * PT * 8 : 0;
   return h;
 }
 
-constexpr int MAX_SEG = 16;   // 8 waves x 2 halves (work-groups of <= 512 threads)
-// finish scratch: segment totals [NSEG][KT][PT] (u32, or 3 doubles for
-// regression) and segment bests [NSEG][PT] (double + int)
-__host__ __device__ __forceinline__ size_t finish_bytes(int PT, int K, bool mse) {
-  const size_t tot = mse ? (size_t)MAX_SEG * PT * (4 + 16) : (size_t)MAX_SEG * K * PT * 4;
-  return (tot + 15) / 16 * 16 + (size_t)MAX_SEG * PT * 12 + 16;
+// Work-groups are 512 threads; the finish gives thread t particle t % PT and
+// bin segment t / PT, so there are 512 / PT segments of at most PT / 2 bins.
+constexpr int HIST_WG = 512;
+
+// Class counts rounded up to the register tile of the finish.
+__host__ __device__ __forceinline__ int class_tile(int K, bool mse) {
+  return mse ? 1 : (K <= 4 ? K : (K <= 8 ? 8 : 16));
+}
+
+// Finish scratch (aliases the histogram once it is in registers): segment
+// totals [NSEG][KT][PT] u32 (regression: counts, then sum y and sum y^2 as
+// [NSEG][PT] doubles) and segment bests [NSEG][PT] (double, then int).
+__host__ __device__ __forceinline__ size_t finish_tot_bytes(int KT, bool mse) {
+  return mse ? (size_t)HIST_WG * (4 + 16) : (size_t)HIST_WG * KT * 4;
+}
+__host__ __device__ __forceinline__ size_t finish_bytes(int KT, bool mse) {
+  return (finish_tot_bytes(KT, mse) + 15) / 16 * 16 + (size_t)HIST_WG * 12;
+}
+// Offset of the n log2 n table: after the histogram or the finish scratch.
+__host__ __device__ __forceinline__ size_t table_offset(int PT, int B, int K, bool mse) {
+  const HistLayout h = hist_layout(PT, B, K, mse);
+  const size_t a = h.lds_cnt + h.sums, f = finish_bytes(class_tile(K, mse), mse);
+  return ((a > f ? a : f) + 15) / 16 * 16;
 }
 
 size_t lds_bytes(int PT, int B, int K, bool mse, bool table) {
-  const HistLayout h = hist_layout(PT, B, K, mse);
-  return h.lds_cnt + h.sums + finish_bytes(PT, K, mse) + (table ? (size_t)NL_TBL * 8 : 0);
+  return table_offset(PT, B, K, mse) + (table ? (size_t)2 * LG_TBL * 8 : 0);
 }
 size_t slot_bytes(int PT, int B, int K, bool mse) {
   const HistLayout h = hist_layout(PT, B, K, mse);
   return (h.glob_cnt + h.sums + 255) / 256 * 256;
 }
 
+// Largest particle tile whose histograms fit in 80 KB of LDS (two
+// work-groups per CU) and whose finish registers (PT / 2 bins x KT classes)
+// stay at 64 per thread.
 int pick_pt(int P, int B, int K, int crit) {
+  const bool mse = crit == SLM_MSE;
+  const int KT = class_tile(K, mse);
   int PT = 32;
-  while (PT > 4 && lds_bytes(PT, B, crit == SLM_MSE ? 1 : K, crit == SLM_MSE, crit == SLM_ENTROPY) >
-                       80 * 1024)
+  while (PT > 4 && (lds_bytes(PT, B, mse ? 1 : K, mse, crit == SLM_ENTROPY) > 80 * 1024 ||
+                    PT * (mse ? 5 : KT) > 128))
     PT >>= 1;
   while (PT > 4 && PT / 2 >= P) PT >>= 1;
   return PT;
@@ -209,22 +244,22 @@ int num_cus() {
   return n;
 }
 
-// Plan: 32-particle tiles (a Z row segment is one 128-byte line) when the
-// histograms fit in 80 KB of LDS (two work-groups per CU), 512-thread
-// work-groups, and a chunk length that makes the number of work-groups a
-// whole number of rounds over the CUs.  SLM_SCAN_PLAN="PT:CH:WG" overrides
-// it (tuning sweeps).
+// Plan: the largest particle tile that fits (a 32-particle Z row segment is
+// one 128-byte line) and a chunk length that makes the number of work-groups
+// a whole number of rounds over the CUs (two resident per CU).
+// SLM_SCAN_PLAN="PT:CH" overrides it (tuning sweeps).
 Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
-  Plan pl{pick_pt(P, B, K, crit), chunk_min(N), 1, 512, K <= 4 ? 4 : 16};
+  const bool mse = crit == SLM_MSE;
+  Plan pl{pick_pt(P, B, K, crit), chunk_min(N), 1, class_tile(K, mse)};
   const char *env = getenv("SLM_SCAN_PLAN");
-  int pt = 0, wg = 0;
+  int pt = 0;
   long long ch = 0;
-  if (env && sscanf(env, "%d:%lld:%d", &pt, &ch, &wg) == 3 &&
-      (pt == 4 || pt == 8 || pt == 16 || pt == 32) && (wg == 256 || wg == 512) &&
+  if (env && sscanf(env, "%d:%lld", &pt, &ch) == 2 &&
+      (pt == 4 || pt == 8 || pt == 16 || pt == 32) && pt * (mse ? 5 : pl.KT) <= 128 &&
+      lds_bytes(pt, B, mse ? 1 : K, mse, crit == SLM_ENTROPY) <= 160 * 1024 - 1024 &&
       ch >= chunk_min(N) && ch <= CH_MAX) {
     pl.PT = pt;
     pl.CH = (ch + 63) / 64 * 64;
-    pl.WG = wg;
   } else {
     const int64_t n_pt = (P + pl.PT - 1) / pl.PT;
     const int64_t slots = 2 * (int64_t)num_cus();
@@ -243,13 +278,14 @@ Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
 }
 
 // ---------------------------------------------------------------- histogram kernel
+// Two 512-thread work-groups per CU: at most 128 VGPRs per thread.
 template <int PT, int KT, bool MSE>
-__global__ __launch_bounds__(512) void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G,
-                                                    int64_t total_blocks, size_t slot_sz,
-                                                    int64_t n_slots, const double *gtbl) {
+__global__ __launch_bounds__(HIST_WG) __attribute__((amdgpu_waves_per_eu(4)))
+void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, size_t slot_sz,
+                 int64_t n_slots) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_last;
-  const int WGS = blockDim.x;
+  constexpr int WGS = HIST_WG;
   const int B = a.bins;
   const int K = MSE ? 1 : a.K;
   const HistLayout hl = hist_layout(PT, B, K, MSE);
@@ -257,8 +293,9 @@ __global__ __launch_bounds__(512) void k_scan_hist(ScanArgs a, int64_t CH, int n
   uint32_t *hc = reinterpret_cast<uint32_t *>(smem);
   double *hs1 = reinterpret_cast<double *>(smem + hl.lds_cnt);
   double *hs2 = hs1 + (size_t)B * SD;
-  unsigned char *fin = smem + hl.lds_cnt + hl.sums;
-  double *tbl = reinterpret_cast<double *>(fin + finish_bytes(PT, K, MSE));
+  unsigned char *fin = smem;   // finish scratch, used once the counts are in registers
+  double *lg = reinterpret_cast<double *>(smem + table_offset(PT, B, K, MSE));
+  double *rc = lg + LG_TBL;
   const bool use_tbl = !MSE && a.crit == SLM_ENTROPY;
 
   // XCD-aware order: the G particle tiles that share a Z cache line get
@@ -280,8 +317,7 @@ __global__ __launch_bounds__(512) void k_scan_hist(ScanArgs a, int64_t CH, int n
       hs2[i] = 0.0;
     }
   }
-  if (use_tbl)
-    for (int i = tid; i < NL_TBL; i += WGS) tbl[i] = gtbl[i];
+  if (use_tbl) fill_log_table(lg, rc, tid);
 
   constexpr int RPW = 64 / PT;                 // rows per wave step
   const int pl = lane % PT, rsub = lane / PT;
@@ -300,8 +336,8 @@ __global__ __launch_bounds__(512) void k_scan_hist(ScanArgs a, int64_t CH, int n
   const int64_t step = (int64_t)(WGS / 64) * RPW;
   const int64_t row0 = it.lo + wave * RPW + rsub;
   const int pcl = pv ? p : P - 1;                        // always a valid column
-  const float *zp = a.Z + row0 * P + pcl;
-  const int64_t zstep = step * P;
+  const float *zp = a.Z + z_col(a.zl, pcl) + row0 * a.zl.rs;
+  const int64_t zstep = step * a.zl.rs;
   const bool wave_fast = __all(rule.fast || !pv);
   uint32_t *hrow = hc + pl;
   auto add_cls = [&](int bn, int lab) {
@@ -355,8 +391,8 @@ __global__ __launch_bounds__(512) void k_scan_hist(ScanArgs a, int64_t CH, int n
 
   // ---- nodes spanning several chunks: add into the node's accumulator slot;
   // the last work-group to arrive finishes from it
-  const uint32_t *gsrc = nullptr;
-  uint32_t *gc = nullptr;
+  const unsigned long long *gsrc = nullptr;
+  unsigned long long *gc = nullptr;
   double *g1 = nullptr, *g2 = nullptr;
   uint32_t *ticket = nullptr;
   if (it.nchunks > 1) {
@@ -364,18 +400,15 @@ __global__ __launch_bounds__(512) void k_scan_hist(ScanArgs a, int64_t CH, int n
     const int64_t slot = nr.lo / CH;
     if (slot >= n_slots) return;   // cannot happen with a workspace sized by the plan
     unsigned char *base = static_cast<unsigned char *>(a.ws) + (size_t)(slot * n_pt + pt) * slot_sz;
-    gc = reinterpret_cast<uint32_t *>(base);
+    gc = reinterpret_cast<unsigned long long *>(base);
     g1 = reinterpret_cast<double *>(base + hl.glob_cnt);
     g2 = g1 + (size_t)B * SD;
     ticket = reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(a.ws) +
                                           (size_t)n_slots * n_pt * slot_sz) + slot * n_pt + pt;
     for (int i = tid; i < hl.nwords; i += WGS) {
       const uint32_t w = hc[i];
-      if (w) {
-        const int bl = i / SB, r = i - bl * SB;
-        if (w & 0xFFFFu) atomicAdd(&gc[bl * SB + r], w & 0xFFFFu);
-        if (w >> 16) atomicAdd(&gc[(bl + 128) * SB + r], w >> 16);
-      }
+      if (w)
+        atomicAdd(&gc[i], (unsigned long long)(w & 0xFFFFu) | ((unsigned long long)(w >> 16) << 32));
     }
     if constexpr (MSE) {
       for (int i = tid; i < B * SD; i += WGS) {
@@ -395,216 +428,235 @@ __global__ __launch_bounds__(512) void k_scan_hist(ScanArgs a, int64_t CH, int n
     gsrc = gc;
   }
 
-  // ---- finish.  Lanes = particles: lane (wave w, half h, q) walks the BSEG
-  // bins of segment s = 2 w + h for particle q.  Pass 1 sums the segment per
-  // class; pass 2 turns the segment totals into the left counts at the
-  // segment start, walks the segment evaluating every candidate split, and
-  // keeps the first minimum; pass 3 takes the minimum over segments in bin
-  // order (ties keep the smaller split).
-  {
-    const int nwv = WGS / 64;
-    const int NSEG = 2 * nwv;
-    const int BSEG = (B + NSEG - 1) / NSEG;
-    constexpr int HP = 32;                       // lanes per half-wave
-    const int half = lane / HP, ql = lane % HP;
-    const int seg = 2 * wave + half;
-    const int b_lo = seg * BSEG, b_hi = min(B, b_lo + BSEG);
-    uint32_t *stot = reinterpret_cast<uint32_t *>(fin);                    // [NSEG][K][PT]
-    double *stot1 = reinterpret_cast<double *>(fin + (size_t)MAX_SEG * PT * 4);  // regression
-    double *stot2 = stot1 + (size_t)MAX_SEG * PT;
-    const size_t tot_bytes = MSE ? (size_t)MAX_SEG * PT * 20 : (size_t)MAX_SEG * K * PT * 4;
-    double *sbl = reinterpret_cast<double *>(fin + (tot_bytes + 15) / 16 * 16);       // [NSEG][PT]
-    int *sbb = reinterpret_cast<int *>(sbl + (size_t)MAX_SEG * PT);
-    auto count = [&](int b, int k, int q) -> uint32_t {
-      const int r = k * PT + q;
-      if (gsrc) return gsrc[b * SB + r];
-      return (hc[(b & 127) * SB + r] >> ((b >> 7) << 4)) & 0xFFFFu;
-    };
-    auto sum1 = [&](int b, int q) -> double { return gsrc ? g1[b * PT + q] : hs1[b * PT + q]; };
-    auto sum2 = [&](int b, int q) -> double { return gsrc ? g2[b * PT + q] : hs2[b * PT + q]; };
-    // particles are handled HP at a time (PT <= 32: one pass)
-    for (int q0 = 0; q0 < PT; q0 += HP) {
-      const int q = q0 + ql;
-      const bool qv = q < PT && pt * PT + q < P;
-      // pass 1: segment totals
-      if (q < PT) {
-        if constexpr (MSE) {
-          uint32_t c = 0;
-          double t1 = 0.0, t2 = 0.0;
-          for (int b = b_lo; b < b_hi; ++b) {
-            c += count(b, 0, q);
-            t1 += sum1(b, q);
-            t2 += sum2(b, q);
-          }
-          stot[seg * PT + q] = c;
-          stot1[seg * PT + q] = t1;
-          stot2[seg * PT + q] = t2;
-        } else {
-          uint32_t t[KT];
+  // ---- finish.  Thread t takes particle q = t % PT and the segment
+  // s = t / PT of SEGB consecutive bins (NSEG = 512 / PT segments).  The
+  // segment's counts are loaded into registers; pass 1 stores the segment's
+  // class totals in LDS; pass 2 forms the left counts at the segment start
+  // from the totals of the segments before it and evaluates every candidate
+  // split of the segment in bin order, keeping the first minimum; pass 3
+  // takes the minimum over segments in segment order (ties keep the smaller
+  // split).
+  constexpr int NSEG = WGS / PT;
+  constexpr int SEGMAX = 256 / NSEG;
+  const int SEGB = (B + NSEG - 1) / NSEG;
+  const int seg = tid / PT, q = tid % PT;
+  const int b_lo = seg * SEGB;
+  const int nb = max(0, min(SEGB, B - b_lo));
+  const bool qv = pt * PT + q < P;
+  const int64_t out = np + (int64_t)pt * PT + q;
+
+  // Loads are unconditional from clamped (always valid) addresses and the
+  // out-of-range ones are discarded afterwards, so all of a thread's loads
+  // are in flight together.
+  uint32_t c[SEGMAX][KT];
+  double s1[MSE ? SEGMAX : 1], s2[MSE ? SEGMAX : 1];
+  if (gsrc) {
 #pragma unroll
-          for (int k = 0; k < KT; ++k) t[k] = 0;
-          for (int b = b_lo; b < b_hi; ++b)
+    for (int i = 0; i < SEGMAX; ++i) {
+      const int b = min(b_lo + i, B - 1);
+      const int w = (b & 127) * SB + q, sh = (b >> 7) << 5;
 #pragma unroll
-            for (int k = 0; k < KT; ++k)
-              if (k < K) t[k] += count(b, k, q);
-#pragma unroll
-          for (int k = 0; k < KT; ++k)
-            if (k < K) stot[(seg * K + k) * PT + q] = t[k];
-        }
-      }
-      __syncthreads();
-      // pass 2: left counts at the segment start, then walk the segment
-      double best = __builtin_huge_val();
-      int bestb = 0x7fffffff;
-      if (q < PT) {
-        if constexpr (MSE) {
-          uint32_t left = 0, tot = 0;
-          double l1 = 0.0, l2 = 0.0, T1 = 0.0, T2 = 0.0;
-          for (int s2 = 0; s2 < NSEG; ++s2) {
-            const uint32_t c = stot[s2 * PT + q];
-            const double x1 = stot1[s2 * PT + q], x2 = stot2[s2 * PT + q];
-            if (s2 < seg) {
-              left += c;
-              l1 += x1;
-              l2 += x2;
-            }
-            tot += c;
-            T1 += x1;
-            T2 += x2;
-          }
-          for (int b = b_lo; b < b_hi; ++b) {
-            if (b >= 1) {                        // split b: bins < b go left
-              const uint32_t nL = left, nR = tot - left;
-              if (nL != 0 && nR != 0) {
-                const double dL = (double)nL, dR = (double)nR;
-                const double S1R = T1 - l1, S2R = T2 - l2;
-                const double sseL = l2 - (l1 * l1) / dL;
-                const double sseR = S2R - (S1R * S1R) / dR;
-                const double loss = (sseL + sseR) / (dL + dR);
-                if (loss < best) {
-                  best = loss;
-                  bestb = b;
-                }
-              }
-            }
-            left += count(b, 0, q);
-            l1 += sum1(b, q);
-            l2 += sum2(b, q);
-          }
-        } else {
-          uint32_t left[KT], tot[KT];
-#pragma unroll
-          for (int k = 0; k < KT; ++k) {
-            left[k] = 0;
-            tot[k] = 0;
-          }
-          for (int s2 = 0; s2 < NSEG; ++s2)
-#pragma unroll
-            for (int k = 0; k < KT; ++k)
-              if (k < K) {
-                const uint32_t c = stot[(s2 * K + k) * PT + q];
-                if (s2 < seg) left[k] += c;
-                tot[k] += c;
-              }
-          int64_t n = 0;
-          double TL0 = 0.0;
-#pragma unroll
-          for (int k = 0; k < KT; ++k) n += tot[k];
-          (void)TL0;
-          const double dn = (double)n;
-          for (int b = b_lo; b < b_hi; ++b) {
-            if (b >= 1) {
-              uint64_t AL = 0, AR = 0;
-              int64_t nL = 0;
-              double sL = 0.0, sR = 0.0;
-#pragma unroll
-              for (int k = 0; k < KT; ++k) {
-                if (k < K) {
-                  const uint32_t l = left[k], r = tot[k] - l;
-                  nL += l;
-                  if (a.crit == SLM_GINI) {
-                    AL += (uint64_t)l * l;
-                    AR += (uint64_t)r * r;
-                  } else {
-                    sL += nlog2n_cnt(l, tbl);
-                    sR += nlog2n_cnt(r, tbl);
-                  }
-                }
-              }
-              const int64_t nR = n - nL;
-              if (nL != 0 && nR != 0) {
-                double loss;
-                if (a.crit == SLM_GINI) {
-                  const double sv = (double)AL / (double)nL + (double)AR / (double)nR;
-                  loss = (dn - sv) / dn;
-                } else {
-                  const double TL = nlog2n_cnt((uint32_t)nL, tbl) - sL;
-                  const double TR = nlog2n_cnt((uint32_t)nR, tbl) - sR;
-                  loss = (TL + TR) / dn;
-                }
-                if (loss < best) {
-                  best = loss;
-                  bestb = b;
-                }
-              }
-            }
-#pragma unroll
-            for (int k = 0; k < KT; ++k)
-              if (k < K) left[k] += count(b, k, q);
-          }
-        }
-        sbl[seg * PT + q] = best;
-        sbb[seg * PT + q] = bestb;
-      }
-      // optional raw histogram / sums output: lanes = particles, segment bins
-      if (qv && a.hist_out) {
-        const int64_t out = np + pt * PT + q;
-        for (int b = b_lo; b < b_hi; ++b)
-          for (int k = 0; k < K; ++k) a.hist_out[(out * B + b) * K + k] = count(b, k, q);
+      for (int k = 0; k < KT; ++k) {
+        const uint32_t x = (uint32_t)(gsrc[w + min(k, K - 1) * PT] >> sh);
+        c[i][k] = (i < nb && k < K) ? x : 0u;
       }
       if constexpr (MSE) {
-        if (qv && a.sums_out) {
-          const int64_t out = np + pt * PT + q;
-          for (int b = b_lo; b < b_hi; ++b) {
-            a.sums_out[(out * B + b) * 2] = sum1(b, q);
-            a.sums_out[(out * B + b) * 2 + 1] = sum2(b, q);
-          }
-        }
+        const double x1 = g1[b * PT + q], x2 = g2[b * PT + q];
+        s1[i] = i < nb ? x1 : 0.0;
+        s2[i] = i < nb ? x2 : 0.0;
       }
-      __syncthreads();
-      // pass 3: minimum over segments in bin order
-      if (wave == 0 && half == 0 && qv) {
-        double bl = __builtin_huge_val();
-        int bb = 0x7fffffff;
-        for (int s2 = 0; s2 < NSEG; ++s2) {
-          const double l = sbl[s2 * PT + q];
-          if (l < bl) {
-            bl = l;
-            bb = sbb[s2 * PT + q];
-          }
-        }
-        const int64_t out = np + pt * PT + q;
-        if (bb == 0x7fffffff) {
-          a.best_split[out] = -1;
-          a.best_loss[out] = __builtin_huge_val();
-          a.threshold[out] = __builtin_huge_valf();
-        } else {
-          const BinRule rr = make_rule(a.zmin[out], a.zmax[out], B);
-          a.best_split[out] = bb;
-          a.best_loss[out] = bl;
-          a.threshold[out] = edge(rr, bb);
-        }
-      }
-      __syncthreads();
     }
-    // leave a multi-chunk slot zero-filled for the next call
-    if (gsrc) {
-      for (int i = tid; i < hl.ncnt; i += WGS) gc[i] = 0u;
-      if constexpr (MSE)
-        for (int i = tid; i < B * PT; i += WGS) {
-          g1[i] = 0.0;
-          g2[i] = 0.0;
+  } else {
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i) {
+      const int b = min(b_lo + i, B - 1);
+      const int w = (b & 127) * SB + q, sh = (b >> 7) << 4;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const uint32_t x = (hc[w + min(k, K - 1) * PT] >> sh) & 0xFFFFu;
+        c[i][k] = (i < nb && k < K) ? x : 0u;
+      }
+      if constexpr (MSE) {
+        const double x1 = hs1[b * PT + q], x2 = hs2[b * PT + q];
+        s1[i] = i < nb ? x1 : 0.0;
+        s2[i] = i < nb ? x2 : 0.0;
+      }
+    }
+  }
+  lds_barrier();   // the histogram region becomes finish scratch
+
+  uint32_t *stot = reinterpret_cast<uint32_t *>(fin);                             // [NSEG][KT][PT]
+  double *stot1 = reinterpret_cast<double *>(fin + (size_t)WGS * 4);             // regression
+  double *stot2 = stot1 + WGS;
+  double *sbl = reinterpret_cast<double *>(fin + (finish_tot_bytes(KT, MSE) + 15) / 16 * 16);
+  int *sbb = reinterpret_cast<int *>(sbl + WGS);
+
+  // pass 1: segment totals
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i) t += c[i][k];
+    stot[(seg * KT + k) * PT + q] = t;
+  }
+  if constexpr (MSE) {
+    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i) {
+      t1 += s1[i];
+      t2 += s2[i];
+    }
+    stot1[seg * PT + q] = t1;
+    stot2[seg * PT + q] = t2;
+  }
+  lds_barrier();
+
+  // pass 2: left totals at the segment start, then the segment's candidates
+  uint32_t left[KT], tot[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) left[k] = tot[k] = 0;
+  double l1 = 0.0, l2 = 0.0, T1 = 0.0, T2 = 0.0;
+#pragma unroll 16
+  for (int s2i = 0; s2i < NSEG; ++s2i) {
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const uint32_t x = stot[(s2i * KT + k) * PT + q];
+      tot[k] += x;
+      left[k] += s2i < seg ? x : 0u;
+    }
+    if constexpr (MSE) {
+      const double x1 = stot1[s2i * PT + q], x2 = stot2[s2i * PT + q];
+      if (s2i < seg) {
+        l1 += x1;
+        l2 += x2;
+      }
+      T1 += x1;
+      T2 += x2;
+    }
+  }
+  int64_t n = 0;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) n += tot[k];
+  const double dn = (double)n;
+  double best = __builtin_huge_val();
+  int bestb = 0x7fffffff;
+#pragma unroll
+  for (int i = 0; i < SEGMAX; ++i) {
+    const int b = b_lo + i;
+    if (i < nb) {
+      if (b >= 1) {                                  // split b: bins < b go left
+        double loss = __builtin_huge_val();
+        bool valid;
+        if constexpr (MSE) {
+          const uint32_t nL = left[0], nR = tot[0] - left[0];
+          valid = nL != 0 && nR != 0;
+          if (valid) {
+            const double dL = (double)nL, dR = (double)nR;
+            const double S1R = T1 - l1, S2R = T2 - l2;
+            const double sseL = l2 - (l1 * l1) / dL;
+            const double sseR = S2R - (S1R * S1R) / dR;
+            loss = (sseL + sseR) / (dL + dR);
+          }
+        } else {
+          int64_t nL = 0;
+#pragma unroll
+          for (int k = 0; k < KT; ++k) nL += left[k];
+          const int64_t nR = n - nL;
+          valid = nL != 0 && nR != 0;
+          if (valid) {
+            if (a.crit == SLM_GINI) {
+              uint64_t AL = 0, AR = 0;
+#pragma unroll
+              for (int k = 0; k < KT; ++k) {
+                const uint64_t l = left[k], r = tot[k] - left[k];
+                AL += l * l;
+                AR += r * r;
+              }
+              const double sv = (double)AL / (double)nL + (double)AR / (double)nR;
+              loss = (dn - sv) / dn;
+            } else {
+              double sL = 0.0, sR = 0.0;
+#pragma unroll
+              for (int k = 0; k < KT; ++k)
+                if (k < K) {
+                  sL += nlog2n_cnt(left[k], lg, rc);
+                  sR += nlog2n_cnt(tot[k] - left[k], lg, rc);
+                }
+              const double TL = nlog2n_cnt((uint32_t)nL, lg, rc) - sL;
+              const double TR = nlog2n_cnt((uint32_t)nR, lg, rc) - sR;
+              loss = (TL + TR) / dn;
+            }
+          }
         }
+        if (valid && loss < best) {
+          best = loss;
+          bestb = b;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KT; ++k) left[k] += c[i][k];
+      if constexpr (MSE) {
+        l1 += s1[i];
+        l2 += s2[i];
+      }
+    }
+  }
+  sbl[seg * PT + q] = best;
+  sbb[seg * PT + q] = bestb;
+
+  // optional raw histogram / sums output
+  if (qv && a.hist_out) {
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i)
+      if (i < nb)
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+          if (k < K) a.hist_out[(out * B + b_lo + i) * K + k] = c[i][k];
+  }
+  if constexpr (MSE) {
+    if (qv && a.sums_out) {
+#pragma unroll
+      for (int i = 0; i < SEGMAX; ++i)
+        if (i < nb) {
+          a.sums_out[(out * B + b_lo + i) * 2] = s1[i];
+          a.sums_out[(out * B + b_lo + i) * 2 + 1] = s2[i];
+        }
+    }
+  }
+  // leave a multi-chunk slot zero-filled for the next call (every thread's
+  // loads from it completed before pass 1's barrier)
+  if (gsrc) {
+    for (int i = tid; i < hl.nwords; i += WGS) gc[i] = 0ull;
+    if constexpr (MSE)
+      for (int i = tid; i < B * PT; i += WGS) {
+        g1[i] = 0.0;
+        g2[i] = 0.0;
+      }
+  }
+  lds_barrier();
+
+  // pass 3: minimum over segments in bin order
+  if (tid < PT && pt * PT + tid < P) {
+    double bl = __builtin_huge_val();
+    int bb = 0x7fffffff;
+#pragma unroll 16
+    for (int s2i = 0; s2i < NSEG; ++s2i) {
+      const double l = sbl[s2i * PT + tid];
+      if (l < bl) {
+        bl = l;
+        bb = sbb[s2i * PT + tid];
+      }
+    }
+    const int64_t o = np + (int64_t)pt * PT + tid;
+    if (bb == 0x7fffffff) {
+      a.best_split[o] = -1;
+      a.best_loss[o] = __builtin_huge_val();
+      a.threshold[o] = __builtin_huge_valf();
+    } else {
+      const BinRule rr = make_rule(a.zmin[o], a.zmax[o], B);
+      a.best_split[o] = bb;
+      a.best_loss[o] = bl;
+      a.threshold[o] = edge(rr, bb);
     }
   }
   if (gsrc && tid == 0) *ticket = 0u;
@@ -660,7 +712,7 @@ __global__ __launch_bounds__(WG) void k_scan_exact(ScanArgs a) {
   while (np2 < n) np2 <<= 1;
   for (int i = tid; i < np2; i += WG) {
     if (i < n) {
-      key[i] = a.Z[(rg.lo + i) * a.P + p];
+      key[i] = a.Z[z_col(a.zl, p) + (rg.lo + i) * a.zl.rs];
       idx[i] = i;
     } else {
       key[i] = __builtin_huge_valf();
@@ -850,25 +902,30 @@ slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
   const size_t lds = lds_bytes(PT, a.bins, Kc, MSE, table);
   const size_t slot = slot_bytes(PT, a.bins, Kc, MSE);
   const int64_t n_slots = (a.N - 1) / chunk_min(a.N) + 1;
-  double *gtbl = nullptr;
-  if (table) {
-    // the table sits at the (256-byte aligned) end of the workspace
-    uintptr_t e = reinterpret_cast<uintptr_t>(a.ws) + a.ws_bytes - (size_t)NL_TBL * 8;
-    gtbl = reinterpret_cast<double *>(e & ~(uintptr_t)255);
-    hipLaunchKernelGGL(k_fill_nlog2n, dim3(NL_TBL / 256), dim3(256), 0, s, gtbl);
-    SLM_LAUNCHED();
-  }
-  hipLaunchKernelGGL((k_scan_hist<PT, KT, MSE>), dim3((unsigned)grid), dim3(pl.WG), lds, s, a, pl.CH,
-                     n_pt, pl.G, total, slot, n_slots, gtbl);
+  hipLaunchKernelGGL((k_scan_hist<PT, KT, MSE>), dim3((unsigned)grid), dim3(HIST_WG), lds, s, a, pl.CH,
+                     n_pt, pl.G, total, slot, n_slots);
   SLM_LAUNCHED();
   return SLM_OK;
 }
 
+// Only tiles whose finish registers fit (PT x KT <= 128; regression
+// PT <= 16) are instantiated; the plan never picks another.
 template <int PT>
 slm_status launch_hist_pt(const ScanArgs &a, const Plan &pl, hipStream_t s) {
-  if (a.crit == SLM_MSE) return launch_hist_cfg<PT, 1, true>(a, pl, s);
-  if (pl.KT == 4) return launch_hist_cfg<PT, 4, false>(a, pl, s);
-  return launch_hist_cfg<PT, 16, false>(a, pl, s);
+  if (a.crit == SLM_MSE) {
+    if constexpr (PT <= 16) return launch_hist_cfg<PT, 1, true>(a, pl, s);
+  } else if (pl.KT == 2) {
+    return launch_hist_cfg<PT, 2, false>(a, pl, s);
+  } else if (pl.KT == 3) {
+    return launch_hist_cfg<PT, 3, false>(a, pl, s);
+  } else if (pl.KT == 4) {
+    return launch_hist_cfg<PT, 4, false>(a, pl, s);
+  } else if (pl.KT == 8) {
+    if constexpr (PT <= 16) return launch_hist_cfg<PT, 8, false>(a, pl, s);
+  } else {
+    if constexpr (PT <= 8) return launch_hist_cfg<PT, 16, false>(a, pl, s);
+  }
+  SLM_CHECK(false, SLM_E_UNSUPPORTED, "slm_split_scan: no histogram kernel for PT=%d KT=%d", PT, pl.KT);
 }
 
 slm_status launch_hist(const ScanArgs &a, const Plan &pl, hipStream_t s) {
@@ -891,9 +948,12 @@ void set_lds_attr(int bytes) {
 
 template <int PT>
 void set_lds_attr_pt(int bytes) {
-  set_lds_attr<PT, 1, true>(bytes);
+  if constexpr (PT <= 16) set_lds_attr<PT, 1, true>(bytes);
+  set_lds_attr<PT, 2, false>(bytes);
+  set_lds_attr<PT, 3, false>(bytes);
   set_lds_attr<PT, 4, false>(bytes);
-  set_lds_attr<PT, 16, false>(bytes);
+  if constexpr (PT <= 16) set_lds_attr<PT, 8, false>(bytes);
+  if constexpr (PT <= 8) set_lds_attr<PT, 16, false>(bytes);
 }
 
 }  // namespace
@@ -929,7 +989,7 @@ size_t scan_workspace_bytes(int64_t N, int n_nodes, int P, int bins, int K, int 
     worst = std::max(worst, (size_t)n_pt * slot_bytes(PT, bins, Kc, mse) + (size_t)n_pt * 4);
   }
   const int64_t n_slots = (N - 1) / chunk_min(N) + 1;
-  return (size_t)n_slots * worst + 256 + (size_t)NL_TBL * 8 + 256;
+  return (size_t)n_slots * worst + 256;
 }
 
 slm_status launch_scan_empty_nodes(const ScanArgs &a, hipStream_t s) {

@@ -83,7 +83,7 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base) {
   w.Xb = c.take<char>((size_t)N * D * xb);
   w.ta = c.take<char>((size_t)N * (mse ? 8 : 4));
   w.tb = c.take<char>((size_t)N * (mse ? 8 : 4));
-  w.Z = c.take<float>((size_t)N * p.P);
+  w.Z = c.take<float>((size_t)N * ((p.P + 31) / 32 * 32));   // particle-tiled
   w.zsel = c.take<float>((size_t)N);
   w.zmin = c.take<float>((size_t)F * p.P);
   w.zmax = c.take<float>((size_t)F * p.P);
@@ -348,8 +348,9 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   ProjectArgs pr{};
   pr.X = Xc; pr.bf16 = 0; pr.N = N; pr.D = D; pr.W = w.W; pr.beg = w.beg; pr.end = w.end;
   pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
+  pr.zl = zlayout_of(1, N, p.P);
   ScanArgs sa{};
-  sa.Z = w.Z; sa.zmin = w.zmin; sa.zmax = w.zmax;
+  sa.Z = w.Z; sa.zl = pr.zl; sa.zmin = w.zmin; sa.zmax = w.zmax;
   sa.labels = mse ? nullptr : static_cast<const int32_t *>(tc);
   sa.y = mse ? static_cast<const double *>(tc) : nullptr;
   sa.K = p.K; sa.N = N; sa.beg = w.beg; sa.end = w.end; sa.n_nodes = na; sa.P = p.P;
@@ -438,7 +439,7 @@ const char *slm_last_error(void) { return g_err; }
 
 slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, const void *W,
                        int32_t w_dtype, const int64_t *row_off, int32_t n_nodes, int32_t P,
-                       float *Z, float *zmin, float *zmax, void *stream) {
+                       float *Z, int32_t z_layout, float *zmin, float *zmax, void *stream) {
   clear_error();
   SLM_CHECK(N >= 0 && N < (1ll << 31), SLM_E_SHAPE, "slm_project: N = %lld out of range",
             (long long)N);
@@ -447,6 +448,8 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, con
   SLM_CHECK(n_nodes >= 0, SLM_E_SHAPE, "slm_project: n_nodes < 0");
   SLM_CHECK(x_dtype == w_dtype && (x_dtype == SLM_F32 || x_dtype == SLM_BF16), SLM_E_DTYPE,
             "slm_project: X and W must both be F32 or both BF16");
+  SLM_CHECK(z_layout == SLM_Z_ROWS || z_layout == SLM_Z_TILED, SLM_E_INVALID,
+            "slm_project: bad Z layout %d", z_layout);
   if (N == 0 || n_nodes == 0) return SLM_OK;
   SLM_CHECK(X && W && row_off && Z && zmin && zmax, SLM_E_INVALID, "slm_project: NULL pointer");
   slm_status st = launch_fill_minmax(zmin, zmax, (int64_t)n_nodes * P, S(stream));
@@ -454,7 +457,7 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, con
   ProjectArgs a{};
   a.X = X; a.bf16 = x_dtype == SLM_BF16; a.N = N; a.D = D; a.W = W;
   a.beg = row_off; a.end = row_off + 1; a.n_nodes = n_nodes; a.P = P;
-  a.Z = Z; a.zmin = zmin; a.zmax = zmax;
+  a.Z = Z; a.zl = zlayout_of(z_layout == SLM_Z_TILED, N, P); a.zmin = zmin; a.zmax = zmax;
   return launch_project(a, S(stream));
 }
 
@@ -464,7 +467,7 @@ size_t slm_split_scan_workspace(int64_t N, int32_t n_nodes, int32_t P, int32_t b
   return scan_workspace_bytes(N, n_nodes, P, bins, crit == SLM_MSE ? 0 : K, crit);
 }
 
-slm_status slm_split_scan(const float *Z, const float *zmin, const float *zmax,
+slm_status slm_split_scan(const float *Z, int32_t z_layout, const float *zmin, const float *zmax,
                           const void *target, int32_t t_dtype, int32_t K, int64_t N,
                           const int64_t *row_off, int32_t n_nodes, int32_t P, int32_t bins,
                           int32_t crit, int32_t *best_split, double *best_loss, float *threshold,
@@ -477,6 +480,8 @@ slm_status slm_split_scan(const float *Z, const float *zmin, const float *zmax,
   SLM_CHECK(bins == 0 || (bins >= 2 && bins <= 256), SLM_E_SHAPE,
             "slm_split_scan: bins = %d (0 or 2..256)", bins);
   SLM_CHECK(crit >= 0 && crit <= 2, SLM_E_INVALID, "slm_split_scan: bad criterion %d", crit);
+  SLM_CHECK(z_layout == SLM_Z_ROWS || z_layout == SLM_Z_TILED, SLM_E_INVALID,
+            "slm_split_scan: bad Z layout %d", z_layout);
   if (crit == SLM_MSE) {
     SLM_CHECK(t_dtype == SLM_F64, SLM_E_DTYPE, "slm_split_scan: SLM_MSE needs an F64 target");
     SLM_CHECK(K == 0, SLM_E_SHAPE, "slm_split_scan: K must be 0 for SLM_MSE");
@@ -502,7 +507,7 @@ slm_status slm_split_scan(const float *Z, const float *zmin, const float *zmax,
   slm_status pst = prepare_kernels();
   if (pst) return pst;
   ScanArgs a{};
-  a.Z = Z; a.zmin = zmin; a.zmax = zmax;
+  a.Z = Z; a.zl = zlayout_of(z_layout == SLM_Z_TILED, N, P); a.zmin = zmin; a.zmax = zmax;
   a.labels = crit == SLM_MSE ? nullptr : static_cast<const int32_t *>(target);
   a.y = crit == SLM_MSE ? static_cast<const double *>(target) : nullptr;
   a.K = K; a.N = N; a.beg = row_off; a.end = row_off + 1; a.n_nodes = n_nodes; a.P = P;
@@ -731,6 +736,7 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
     ProjectArgs pr{};
     pr.X = Xc; pr.bf16 = 0; pr.N = N; pr.D = D; pr.W = w.gW; pr.beg = w.beg; pr.end = w.end;
     pr.n_nodes = na; pr.P = 1; pr.Z = w.zsel; pr.zmin = nullptr; pr.zmax = nullptr;
+    pr.zl = zlayout_of(0, N, 1);
     if ((st = launch_project(pr, s))) return st;
     if ((st = clear_stats(w, 2 * na, p.crit, Kc, s))) return st;
     PartArgs pa{};

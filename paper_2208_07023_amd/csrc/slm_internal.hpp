@@ -141,6 +141,19 @@ __device__ __forceinline__ uint16_t f64_to_bf16(double d) {
 }
 
 // ---------------------------------------------------------------- launchers
+// Placement of Z[i, p] (row i, particle p): (p / 32) * ts + i * rs + p % 32.
+// Row-major [N, P]: ts = 32, rs = P.  Particle-tiled [ceil(P/32), N, 32]:
+// ts = 32 N, rs = 32 (each 32-particle tile is a contiguous [N, 32] block).
+struct ZLayout {
+  int64_t ts, rs;
+};
+__host__ __device__ __forceinline__ int64_t z_col(const ZLayout &l, int p) {
+  return (int64_t)(p >> 5) * l.ts + (p & 31);
+}
+__host__ __device__ __forceinline__ ZLayout zlayout_of(int tiled, int64_t N, int P) {
+  return tiled ? ZLayout{32 * N, 32} : ZLayout{32, P};
+}
+
 struct ProjectArgs {
   const void *X;
   int bf16;
@@ -152,12 +165,14 @@ struct ProjectArgs {
   float *Z;
   float *zmin, *zmax;
   int w_row_stride;  // rows of W per node (P normally)
+  ZLayout zl;
 };
 slm_status launch_project(const ProjectArgs &a, hipStream_t s);
 slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s);
 
 struct ScanArgs {
   const float *Z;
+  ZLayout zl;
   const float *zmin, *zmax;
   const int32_t *labels;
   const double *y;

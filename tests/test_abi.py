@@ -46,27 +46,29 @@ def _err(lib):
 
 def test_project_validation():
     lib = api.load()
-    st = lib.slm_project(FAKE, api.F32, 10, 0, FAKE, api.F32, FAKE, 1, 4, FAKE, FAKE, FAKE, None)
+    st = lib.slm_project(FAKE, api.F32, 10, 0, FAKE, api.F32, FAKE, 1, 4, FAKE, 0, FAKE, FAKE, None)
     assert st == 2 and "D" in _err(lib)
-    st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.BF16, FAKE, 1, 4, FAKE, FAKE, FAKE, None)
+    st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.BF16, FAKE, 1, 4, FAKE, 0, FAKE, FAKE, None)
     assert st == 3
-    st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 0, FAKE, FAKE, FAKE, None)
+    st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 0, FAKE, 0, FAKE, FAKE, None)
     assert st == 2
-    st = lib.slm_project(None, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 4, FAKE, FAKE, FAKE, None)
+    st = lib.slm_project(None, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 4, FAKE, 0, FAKE, FAKE, None)
     assert st == 1 and "NULL" in _err(lib)
     # nothing to do: returns OK without touching the device
-    st = lib.slm_project(None, api.F32, 0, 4, None, api.F32, None, 0, 4, None, None, None, None)
+    st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 4, FAKE, 2, FAKE, FAKE, None)
+    assert st == 1 and "layout" in _err(lib)
+    st = lib.slm_project(None, api.F32, 0, 4, None, api.F32, None, 0, 4, None, 0, None, None, None)
     assert st == 0
 
 
 def test_split_scan_validation():
     lib = api.load()
-    args = lambda **kw: dict(dict(Z=FAKE, zmin=FAKE, zmax=FAKE, t=FAKE, tt=api.I32, K=3, N=100,
+    args = lambda **kw: dict(dict(Z=FAKE, zl=api.Z_ROWS, zmin=FAKE, zmax=FAKE, t=FAKE, tt=api.I32, K=3, N=100,
                                   off=FAKE, nn=1, P=8, bins=16, crit=api.GINI, ws=FAKE,
                                   wsb=1 << 30), **kw)
 
     def call(a):
-        return lib.slm_split_scan(a["Z"], a["zmin"], a["zmax"], a["t"], a["tt"], a["K"], a["N"],
+        return lib.slm_split_scan(a["Z"], a["zl"], a["zmin"], a["zmax"], a["t"], a["tt"], a["K"], a["N"],
                                   a["off"], a["nn"], a["P"], a["bins"], a["crit"], FAKE, FAKE,
                                   FAKE, None, None, a["ws"], a["wsb"], None)
     assert call(args(bins=1)) == 2
@@ -79,6 +81,7 @@ def test_split_scan_validation():
     assert call(args(crit=api.MSE, tt=api.F64, K=3)) == 2
     assert call(args(wsb=16)) == 4 and "workspace" in _err(lib)
     assert call(args(zmin=None)) == 1
+    assert call(args(zl=2)) == 1 and "layout" in _err(lib)
     need = lib.slm_split_scan_workspace(100, 1, 8, 16, 3, api.GINI)
     assert need > 0
     assert lib.slm_split_scan_workspace(4_000_000, 2048, 1024, 256, 10, api.GINI) < 8 << 30

@@ -25,6 +25,7 @@ def _t(a, dtype=None):
 
 
 # ------------------------------------------------------------------ projection
+@pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("D,P,sizes", [
     (8, 32, [1000]),
     (64, 256, [0, 1, 130, 777, 2]),
@@ -32,13 +33,16 @@ def _t(a, dtype=None):
     (130, 1, [257, 64]),
     (256, 130, [17, 200]),
 ])
-def test_project_integer_inputs_bit_exact(gpu_lib, D, P, sizes):
+def test_project_integer_inputs_bit_exact(gpu_lib, D, P, sizes, tiled):
     api = gpu_lib
     off = inputs.segment_offsets(sizes)
     N, nn = int(off[-1]), len(sizes)
     X = inputs.integer_matrix(N, D, -8, 8, seed=D + P)
     W = inputs.integer_matrix(nn * P, D, -4, 4, seed=D * P + 1)
-    Z, zmin, zmax = api.project(_t(X), _t(W), _t(off), P)
+    Z, zmin, zmax = api.project(_t(X), _t(W), _t(off), P, tiled=tiled)
+    if tiled:
+        assert Z.shape == ((P + 31) // 32, N, 32)
+        Z = api.untile_z(Z, P)
     torch.cuda.synchronize()
     Z, zmin, zmax = Z.cpu().numpy(), zmin.cpu().numpy(), zmax.cpu().numpy()
     for j in range(nn):
@@ -91,7 +95,7 @@ def test_project_column_recomputed_alone_is_bit_identical(gpu_lib):
 
 
 # ------------------------------------------------------------------ histogram scan
-def _scan_case(api, sizes, P, B, crit, K, kind, seed):
+def _scan_case(api, sizes, P, B, crit, K, kind, seed, tiled=False):
     off = inputs.segment_offsets(sizes)
     N = int(off[-1])
     Z = inputs.projected_features(N, P, seed=seed, kind=kind)
@@ -109,7 +113,8 @@ def _scan_case(api, sizes, P, B, crit, K, kind, seed):
         if sizes[j]:
             zmin[j * P:(j + 1) * P] = Z[off[j]:off[j + 1]].min(0)
             zmax[j * P:(j + 1) * P] = Z[off[j]:off[j + 1]].max(0)
-    out = api.split_scan(_t(Z), _t(zmin), _t(zmax), _t(tgt, tt), K if crit != OS.MSE else 0,
+    Zd = api.tile_z(_t(Z), P) if tiled else _t(Z)
+    out = api.split_scan(Zd, _t(zmin), _t(zmax), _t(tgt, tt), K if crit != OS.MSE else 0,
                          _t(off), P, B, crit, hist=True, sums=crit == OS.MSE)
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy() for k, v in out.items()}
@@ -117,15 +122,16 @@ def _scan_case(api, sizes, P, B, crit, K, kind, seed):
     return got, ref
 
 
+@pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("crit", [OS.GINI, OS.ENTROPY])
 @pytest.mark.parametrize("B,K,P,kind", [
     (256, 3, 32, "gauss"), (256, 2, 8, "dups"), (16, 10, 20, "gauss"), (2, 3, 5, "gauss"),
     (3, 4, 64, "dups"), (256, 3, 40, "const"), (100, 16, 3, "gauss"),
 ])
-def test_hist_scan_classification_exact(gpu_lib, crit, B, K, P, kind):
+def test_hist_scan_classification_exact(gpu_lib, crit, B, K, P, kind, tiled):
     # nodes: empty, single row, small, one spanning several 2048-row chunks, ragged tail
     sizes = [0, 1, 37, 5000, 301]
-    got, ref = _scan_case(gpu_lib, sizes, P, B, crit, K, kind, seed=B * 7 + K)
+    got, ref = _scan_case(gpu_lib, sizes, P, B, crit, K, kind, seed=B * 7 + K, tiled=tiled)
     assert np.array_equal(got["counts"].astype(np.int64), ref["counts"])
     assert np.array_equal(got["split"], ref["split"])
     assert np.array_equal(got["thr"], ref["thr"])
@@ -137,10 +143,11 @@ def test_hist_scan_classification_exact(gpu_lib, crit, B, K, P, kind):
         assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("B,P,kind", [(256, 16, "gauss"), (64, 33, "dups"), (7, 4, "gauss")])
-def test_hist_scan_regression(gpu_lib, B, P, kind):
+def test_hist_scan_regression(gpu_lib, B, P, kind, tiled):
     sizes = [0, 2, 45, 4500, 600]
-    got, ref = _scan_case(gpu_lib, sizes, P, B, OS.MSE, 0, kind, seed=B + P)
+    got, ref = _scan_case(gpu_lib, sizes, P, B, OS.MSE, 0, kind, seed=B + P, tiled=tiled)
     assert np.array_equal(got["counts"].astype(np.int64), ref["counts"])
     # per-bin FP64 sums: atomics in any order, error ~ n * u * sum|y|
     assert np.allclose(got["sums"], ref["sums"], rtol=1e-12, atol=1e-9)
@@ -164,11 +171,11 @@ def test_hist_scan_reuses_zeroed_workspace(gpu_lib):
 
 # ------------------------------------------------------------------ exact scan
 @pytest.mark.parametrize("crit,K", [(OS.GINI, 2), (OS.ENTROPY, 5), (OS.MSE, 0)])
-@pytest.mark.parametrize("kind", ["gauss", "dups"])
-def test_exact_scan(gpu_lib, crit, K, kind):
+@pytest.mark.parametrize("kind,P,tiled", [("gauss", 32, False), ("dups", 32, False),
+                                          ("gauss", 40, True)])
+def test_exact_scan(gpu_lib, crit, K, kind, P, tiled):
     sizes = [1000, 0, 1, 2, 333]
-    P = 32
-    got, ref = _scan_case(gpu_lib, sizes, P, 0, crit, K, kind, seed=17 + crit)
+    got, ref = _scan_case(gpu_lib, sizes, P, 0, crit, K, kind, seed=17 + crit, tiled=tiled)
     fin = np.isfinite(ref["loss"])
     assert np.array_equal(np.isfinite(got["loss"]), fin)
     if crit == OS.MSE:
