@@ -1,22 +1,20 @@
 // Best threshold of every projected feature (Sec. II-A, Eqs. (3)-(4);
 // Sec. III-B: a direction's loss is the loss of its best threshold).
 //
-// Histogram scan.  A work-group owns (item, particle tile): the rows of one
-// node inside one global chunk of CH rows, and PT particles of that node.
-// Lanes map to (row, particle): lane = rsub * PT + pl, so a wave reads
-// 64 / PT row segments of PT consecutive floats of Z (row-major [N, P]) and
-// each lane bins its own particle's value.  Counts go to LDS histograms laid
-// out [bin][class][PT], so lanes of one row touch PT consecutive words.
-//   * A node inside one chunk is finished by the same work-group: it scans
-//     the histogram in LDS and writes (split, loss, threshold) per particle.
+// Histogram scan.  k_scan_hist: a work-group owns (item, particle tile): the
+// rows of one node inside one global chunk of CH rows, and PT particles of
+// that node.  Lanes map to (row, particle): lane = rsub * PT + pl, so a wave
+// reads 64 / PT row segments of PT consecutive floats of Z (with the
+// particle-tiled layout, consecutive rows of a tile are contiguous) and each
+// lane bins its own particle's value.  Counts go to LDS histograms laid out
+// [bin][class][PT], so lanes of one row touch PT consecutive words.
+//   * A node inside one chunk is finished by the same work-group from the
+//     LDS histogram (finish_scan below).
 //   * A node spanning several chunks adds its histogram into a global
-//     accumulator slot (the node's first chunk index identifies the slot),
-//     and the last work-group to arrive (atomic ticket) loads the total,
-//     zeroes the slot and ticket for the next call, and finishes the scan.
-// Finishing one particle is one wave: each lane holds 4 consecutive bins,
-// class prefixes come from wave shuffles, each lane evaluates the criterion
-// at its 4 candidate splits in FP64 and a butterfly argmin (smallest split on
-// ties) picks the best.
+//     accumulator slot (the node's first chunk index identifies the slot);
+//     k_scan_finish, launched next on the same stream, spreads each such
+//     node's finish over many work-groups (groups of particles) and clears
+//     the slot for the next call.
 //
 // Exact scan.  One work-group per (node, particle): bitonic sort of the
 // node's (z, row) pairs in LDS (stable through the row tie-break), then a
@@ -277,6 +275,261 @@ Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
   return pl;
 }
 
+// ---------------------------------------------------------------- finish
+// Best split of NQ particles (q0 .. q0 + NQ - 1 of a PT-particle tile) of one
+// node from its complete histogram, by NT threads.  Thread t takes particle
+// q = t % NQ and the segment s = t / NQ of SEGB consecutive bins (NSEG =
+// NT / NQ segments).  The segment's counts are loaded into registers (all
+// loads in flight together: clamped addresses, out-of-range values discarded
+// afterwards); pass 1 stores the segment's class totals in LDS; pass 2 forms
+// the left counts at the segment start from the totals of the segments before
+// it and evaluates every candidate split of the segment in bin order,
+// keeping the first minimum; pass 3 takes the minimum over segments in
+// segment order (ties keep the smaller split).
+// Source: the work-group's packed 16-bit LDS histogram (GSRC = false) or a
+// multi-chunk accumulator slot (GSRC = true: 64-bit words holding bins b and
+// b + 128, zeroed here after reading).
+template <int NT, int KT, bool MSE>
+__host__ __device__ constexpr size_t finish_tot_bytes() {
+  return MSE ? (size_t)NT * (4 + 16) : (size_t)NT * KT * 4;
+}
+template <int NT, int KT, bool MSE>
+__host__ __device__ constexpr size_t finish_scratch_bytes() {
+  return (finish_tot_bytes<NT, KT, MSE>() + 15) / 16 * 16 + (size_t)NT * 12;
+}
+
+struct FinishSrc {
+  const void *cnt;               // u32 LDS words or u64 slot words
+  const double *s1, *s2;         // regression sums [B][PT]
+  unsigned long long *gzero;     // slot words to clear after reading (GSRC)
+  double *gz1, *gz2;
+};
+
+template <int NQ, int NT, int KT, bool MSE, bool GSRC>
+__device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &src, int PT,
+                                            int pt, int q0, int64_t np, unsigned char *fin,
+                                            const double *lg, const double *rc, int tid) {
+  constexpr int NSEG = NT / NQ;
+  constexpr int SEGMAX = (256 + NSEG - 1) / NSEG;
+  const int B = a.bins;
+  const int K = MSE ? 1 : a.K;
+  const int SB = MSE ? PT : K * PT;
+  const int P = a.P;
+  const int SEGB = (B + NSEG - 1) / NSEG;
+  const int seg = tid / NQ, q = tid % NQ, qt = q0 + q;   // qt: particle within the tile
+  const int b_lo = seg * SEGB;
+  const int nb = max(0, min(SEGB, B - b_lo));
+  const bool qv = pt * PT + qt < P;
+  const int64_t out = np + (int64_t)pt * PT + qt;
+
+  uint32_t c[SEGMAX][KT];
+  double s1[MSE ? SEGMAX : 1], s2[MSE ? SEGMAX : 1];
+#pragma unroll
+  for (int i = 0; i < SEGMAX; ++i) {
+    const int b = min(b_lo + i, B - 1);
+    const int w = (b & 127) * SB + qt;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      uint32_t x;
+      if constexpr (GSRC)
+        x = (uint32_t)(static_cast<const unsigned long long *>(src.cnt)[w + min(k, K - 1) * PT] >>
+                       ((b >> 7) << 5));
+      else
+        x = (static_cast<const uint32_t *>(src.cnt)[w + min(k, K - 1) * PT] >> ((b >> 7) << 4)) &
+            0xFFFFu;
+      c[i][k] = (i < nb && k < K) ? x : 0u;
+    }
+    if constexpr (MSE) {
+      const double x1 = src.s1[b * PT + qt], x2 = src.s2[b * PT + qt];
+      s1[i] = i < nb ? x1 : 0.0;
+      s2[i] = i < nb ? x2 : 0.0;
+    }
+  }
+  if constexpr (!GSRC) lds_barrier();   // the histogram region becomes finish scratch
+
+  uint32_t *stot = reinterpret_cast<uint32_t *>(fin);                       // [NSEG][KT][NQ]
+  double *stot1 = reinterpret_cast<double *>(fin + (size_t)NT * 4);        // regression
+  double *stot2 = stot1 + NT;
+  double *sbl = reinterpret_cast<double *>(fin + (finish_tot_bytes<NT, KT, MSE>() + 15) / 16 * 16);
+  int *sbb = reinterpret_cast<int *>(sbl + NT);
+
+  // pass 1: segment totals
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i) t += c[i][k];
+    stot[(seg * KT + k) * NQ + q] = t;
+  }
+  if constexpr (MSE) {
+    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i) {
+      t1 += s1[i];
+      t2 += s2[i];
+    }
+    stot1[seg * NQ + q] = t1;
+    stot2[seg * NQ + q] = t2;
+  }
+  lds_barrier();
+  if constexpr (GSRC) {
+    // every thread's loads completed before the barrier: clear what was read
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i) {
+      if (i < nb) {
+        const int b = b_lo + i;
+        const int w = (b & 127) * SB + qt;
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+          if (k < K) src.gzero[w + k * PT] = 0ull;
+        if constexpr (MSE) {
+          src.gz1[b * PT + qt] = 0.0;
+          src.gz2[b * PT + qt] = 0.0;
+        }
+      }
+    }
+  }
+
+  // pass 2: left totals at the segment start, then the segment's candidates
+  uint32_t left[KT], tot[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) left[k] = tot[k] = 0;
+  double l1 = 0.0, l2 = 0.0, T1 = 0.0, T2 = 0.0;
+#pragma unroll 16
+  for (int s2i = 0; s2i < NSEG; ++s2i) {
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const uint32_t x = stot[(s2i * KT + k) * NQ + q];
+      tot[k] += x;
+      left[k] += s2i < seg ? x : 0u;
+    }
+    if constexpr (MSE) {
+      const double x1 = stot1[s2i * NQ + q], x2 = stot2[s2i * NQ + q];
+      if (s2i < seg) {
+        l1 += x1;
+        l2 += x2;
+      }
+      T1 += x1;
+      T2 += x2;
+    }
+  }
+  int64_t n = 0;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) n += tot[k];
+  const double dn = (double)n;
+  double best = __builtin_huge_val();
+  int bestb = 0x7fffffff;
+#pragma unroll
+  for (int i = 0; i < SEGMAX; ++i) {
+    const int b = b_lo + i;
+    if (i < nb) {
+      if (b >= 1) {                                  // split b: bins < b go left
+        double loss = __builtin_huge_val();
+        bool valid;
+        if constexpr (MSE) {
+          const uint32_t nL = left[0], nR = tot[0] - left[0];
+          valid = nL != 0 && nR != 0;
+          if (valid) {
+            const double dL = (double)nL, dR = (double)nR;
+            const double S1R = T1 - l1, S2R = T2 - l2;
+            const double sseL = l2 - (l1 * l1) / dL;
+            const double sseR = S2R - (S1R * S1R) / dR;
+            loss = (sseL + sseR) / (dL + dR);
+          }
+        } else {
+          int64_t nL = 0;
+#pragma unroll
+          for (int k = 0; k < KT; ++k) nL += left[k];
+          const int64_t nR = n - nL;
+          valid = nL != 0 && nR != 0;
+          if (valid) {
+            if (a.crit == SLM_GINI) {
+              uint64_t AL = 0, AR = 0;
+#pragma unroll
+              for (int k = 0; k < KT; ++k) {
+                const uint64_t l = left[k], r = tot[k] - left[k];
+                AL += l * l;
+                AR += r * r;
+              }
+              const double sv = (double)AL / (double)nL + (double)AR / (double)nR;
+              loss = (dn - sv) / dn;
+            } else {
+              double sL = 0.0, sR = 0.0;
+#pragma unroll
+              for (int k = 0; k < KT; ++k)
+                if (k < K) {
+                  sL += nlog2n_cnt(left[k], lg, rc);
+                  sR += nlog2n_cnt(tot[k] - left[k], lg, rc);
+                }
+              const double TL = nlog2n_cnt((uint32_t)nL, lg, rc) - sL;
+              const double TR = nlog2n_cnt((uint32_t)nR, lg, rc) - sR;
+              loss = (TL + TR) / dn;
+            }
+          }
+        }
+        if (valid && loss < best) {
+          best = loss;
+          bestb = b;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KT; ++k) left[k] += c[i][k];
+      if constexpr (MSE) {
+        l1 += s1[i];
+        l2 += s2[i];
+      }
+    }
+  }
+  sbl[seg * NQ + q] = best;
+  sbb[seg * NQ + q] = bestb;
+
+  // optional raw histogram / sums output
+  if (qv && a.hist_out) {
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i)
+      if (i < nb)
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+          if (k < K) a.hist_out[(out * B + b_lo + i) * K + k] = c[i][k];
+  }
+  if constexpr (MSE) {
+    if (qv && a.sums_out) {
+#pragma unroll
+      for (int i = 0; i < SEGMAX; ++i)
+        if (i < nb) {
+          a.sums_out[(out * B + b_lo + i) * 2] = s1[i];
+          a.sums_out[(out * B + b_lo + i) * 2 + 1] = s2[i];
+        }
+    }
+  }
+  lds_barrier();
+
+  // pass 3: minimum over segments in bin order
+  if (tid < NQ && pt * PT + q0 + tid < P) {
+    double bl = __builtin_huge_val();
+    int bb = 0x7fffffff;
+#pragma unroll 16
+    for (int s2i = 0; s2i < NSEG; ++s2i) {
+      const double l = sbl[s2i * NQ + tid];
+      if (l < bl) {
+        bl = l;
+        bb = sbb[s2i * NQ + tid];
+      }
+    }
+    const int64_t o = np + (int64_t)pt * PT + q0 + tid;
+    if (bb == 0x7fffffff) {
+      a.best_split[o] = -1;
+      a.best_loss[o] = __builtin_huge_val();
+      a.threshold[o] = __builtin_huge_valf();
+    } else {
+      const BinRule rr = make_rule(a.zmin[o], a.zmax[o], B);
+      a.best_split[o] = bb;
+      a.best_loss[o] = bl;
+      a.threshold[o] = edge(rr, bb);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- histogram kernel
 // Two 512-thread work-groups per CU: at most 128 VGPRs per thread.
 template <int PT, int KT, bool MSE>
@@ -284,7 +537,6 @@ __global__ __launch_bounds__(HIST_WG) __attribute__((amdgpu_waves_per_eu(4)))
 void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, size_t slot_sz,
                  int64_t n_slots) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_last;
   constexpr int WGS = HIST_WG;
   const int B = a.bins;
   const int K = MSE ? 1 : a.K;
@@ -293,7 +545,6 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   uint32_t *hc = reinterpret_cast<uint32_t *>(smem);
   double *hs1 = reinterpret_cast<double *>(smem + hl.lds_cnt);
   double *hs2 = hs1 + (size_t)B * SD;
-  unsigned char *fin = smem;   // finish scratch, used once the counts are in registers
   double *lg = reinterpret_cast<double *>(smem + table_offset(PT, B, K, MSE));
   double *rc = lg + LG_TBL;
   const bool use_tbl = !MSE && a.crit == SLM_ENTROPY;
@@ -389,277 +640,78 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   }
   lds_barrier();
 
-  // ---- nodes spanning several chunks: add into the node's accumulator slot;
-  // the last work-group to arrive finishes from it
-  const unsigned long long *gsrc = nullptr;
-  unsigned long long *gc = nullptr;
-  double *g1 = nullptr, *g2 = nullptr;
-  uint32_t *ticket = nullptr;
+  // ---- a node spanning several chunks: add into its accumulator slot (the
+  // node's first chunk index); k_scan_finish completes it
   if (it.nchunks > 1) {
     const Range nr = load_range(a.beg, a.end, it.node, a.N);
     const int64_t slot = nr.lo / CH;
     if (slot >= n_slots) return;   // cannot happen with a workspace sized by the plan
     unsigned char *base = static_cast<unsigned char *>(a.ws) + (size_t)(slot * n_pt + pt) * slot_sz;
-    gc = reinterpret_cast<unsigned long long *>(base);
-    g1 = reinterpret_cast<double *>(base + hl.glob_cnt);
-    g2 = g1 + (size_t)B * SD;
-    ticket = reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(a.ws) +
-                                          (size_t)n_slots * n_pt * slot_sz) + slot * n_pt + pt;
+    unsigned long long *gc = reinterpret_cast<unsigned long long *>(base);
     for (int i = tid; i < hl.nwords; i += WGS) {
       const uint32_t w = hc[i];
       if (w)
         atomicAdd(&gc[i], (unsigned long long)(w & 0xFFFFu) | ((unsigned long long)(w >> 16) << 32));
     }
     if constexpr (MSE) {
+      double *g1 = reinterpret_cast<double *>(base + hl.glob_cnt);
+      double *g2 = g1 + (size_t)B * SD;
       for (int i = tid; i < B * SD; i += WGS) {
         if (hs1[i] != 0.0) unsafeAtomicAdd(&g1[i], hs1[i]);
         if (hs2[i] != 0.0) unsafeAtomicAdd(&g2[i], hs2[i]);
       }
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-      const unsigned t = atomicAdd(ticket, 1u);
-      s_last = (t == (unsigned)(it.nchunks - 1));
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    gsrc = gc;
+    return;
   }
 
-  // ---- finish.  Thread t takes particle q = t % PT and the segment
-  // s = t / PT of SEGB consecutive bins (NSEG = 512 / PT segments).  The
-  // segment's counts are loaded into registers; pass 1 stores the segment's
-  // class totals in LDS; pass 2 forms the left counts at the segment start
-  // from the totals of the segments before it and evaluates every candidate
-  // split of the segment in bin order, keeping the first minimum; pass 3
-  // takes the minimum over segments in segment order (ties keep the smaller
-  // split).
-  constexpr int NSEG = WGS / PT;
-  constexpr int SEGMAX = 256 / NSEG;
-  const int SEGB = (B + NSEG - 1) / NSEG;
-  const int seg = tid / PT, q = tid % PT;
-  const int b_lo = seg * SEGB;
-  const int nb = max(0, min(SEGB, B - b_lo));
-  const bool qv = pt * PT + q < P;
-  const int64_t out = np + (int64_t)pt * PT + q;
+  // ---- a node inside one chunk: finish from the LDS histogram
+  const FinishSrc src{hc, hs1, hs2, nullptr, nullptr, nullptr};
+  finish_scan<PT, WGS, KT, MSE, false>(a, src, PT, pt, 0, np, smem, lg, rc, tid);
+}
 
-  // Loads are unconditional from clamped (always valid) addresses and the
-  // out-of-range ones are discarded afterwards, so all of a thread's loads
-  // are in flight together.
-  uint32_t c[SEGMAX][KT];
-  double s1[MSE ? SEGMAX : 1], s2[MSE ? SEGMAX : 1];
-  if (gsrc) {
-#pragma unroll
-    for (int i = 0; i < SEGMAX; ++i) {
-      const int b = min(b_lo + i, B - 1);
-      const int w = (b & 127) * SB + q, sh = (b >> 7) << 5;
-#pragma unroll
-      for (int k = 0; k < KT; ++k) {
-        const uint32_t x = (uint32_t)(gsrc[w + min(k, K - 1) * PT] >> sh);
-        c[i][k] = (i < nb && k < K) ? x : 0u;
-      }
-      if constexpr (MSE) {
-        const double x1 = g1[b * PT + q], x2 = g2[b * PT + q];
-        s1[i] = i < nb ? x1 : 0.0;
-        s2[i] = i < nb ? x2 : 0.0;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < SEGMAX; ++i) {
-      const int b = min(b_lo + i, B - 1);
-      const int w = (b & 127) * SB + q, sh = (b >> 7) << 4;
-#pragma unroll
-      for (int k = 0; k < KT; ++k) {
-        const uint32_t x = (hc[w + min(k, K - 1) * PT] >> sh) & 0xFFFFu;
-        c[i][k] = (i < nb && k < K) ? x : 0u;
-      }
-      if constexpr (MSE) {
-        const double x1 = hs1[b * PT + q], x2 = hs2[b * PT + q];
-        s1[i] = i < nb ? x1 : 0.0;
-        s2[i] = i < nb ? x2 : 0.0;
-      }
-    }
+// Completes the nodes that span several chunks, once every chunk's histogram
+// is in the node's accumulator slot.  Work-group (slot s, particle tile,
+// group of NQ particles); slots without such a node exit at once.
+template <int PT, int KT, bool MSE>
+__global__ __launch_bounds__(256) void k_scan_finish(ScanArgs a, int64_t CH, int n_pt,
+                                                     size_t slot_sz, int64_t n_slots) {
+  constexpr int NQ = PT < (KT <= 8 ? 8 : 4) ? PT : (KT <= 8 ? 8 : 4);
+  constexpr int NGRP = PT / NQ;
+  __shared__ __align__(16) unsigned char fin[finish_scratch_bytes<256, KT, MSE>()];
+  __shared__ double lgt[2 * LG_TBL];
+  const int64_t bid = blockIdx.x;
+  const int grp = (int)(bid % NGRP);
+  const int pt = (int)((bid / NGRP) % n_pt);
+  const int64_t slot = bid / ((int64_t)NGRP * n_pt);
+  if (slot >= n_slots) return;
+  // the node whose rows start in chunk `slot` and continue past it
+  const int64_t lim = (slot + 1) * CH;
+  auto beg_of = [&](int j) {
+    const int64_t x = a.beg[j];
+    return x < 0 ? (int64_t)0 : (x > a.N ? a.N : x);
+  };
+  if (a.n_nodes <= 0 || beg_of(0) >= lim) return;
+  int lo = 0, hi = a.n_nodes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (beg_of(mid) < lim) lo = mid; else hi = mid - 1;
   }
-  lds_barrier();   // the histogram region becomes finish scratch
-
-  uint32_t *stot = reinterpret_cast<uint32_t *>(fin);                             // [NSEG][KT][PT]
-  double *stot1 = reinterpret_cast<double *>(fin + (size_t)WGS * 4);             // regression
-  double *stot2 = stot1 + WGS;
-  double *sbl = reinterpret_cast<double *>(fin + (finish_tot_bytes(KT, MSE) + 15) / 16 * 16);
-  int *sbb = reinterpret_cast<int *>(sbl + WGS);
-
-  // pass 1: segment totals
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    uint32_t t = 0;
-#pragma unroll
-    for (int i = 0; i < SEGMAX; ++i) t += c[i][k];
-    stot[(seg * KT + k) * PT + q] = t;
-  }
-  if constexpr (MSE) {
-    double t1 = 0.0, t2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < SEGMAX; ++i) {
-      t1 += s1[i];
-      t2 += s2[i];
-    }
-    stot1[seg * PT + q] = t1;
-    stot2[seg * PT + q] = t2;
-  }
+  const Range r = load_range(a.beg, a.end, lo, a.N);
+  if (r.hi <= r.lo || r.lo / CH != slot || (r.hi - 1) / CH == slot) return;
+  const int B = a.bins;
+  const int K = MSE ? 1 : a.K;
+  const HistLayout hl = hist_layout(PT, B, K, MSE);
+  unsigned char *base = static_cast<unsigned char *>(a.ws) + (size_t)(slot * n_pt + pt) * slot_sz;
+  unsigned long long *gc = reinterpret_cast<unsigned long long *>(base);
+  double *g1 = reinterpret_cast<double *>(base + hl.glob_cnt);
+  double *g2 = g1 + (size_t)B * PT;
+  const int tid = threadIdx.x;
+  double *lg = lgt, *rc = lgt + LG_TBL;
+  if (!MSE && a.crit == SLM_ENTROPY) fill_log_table(lg, rc, tid);
   lds_barrier();
-
-  // pass 2: left totals at the segment start, then the segment's candidates
-  uint32_t left[KT], tot[KT];
-#pragma unroll
-  for (int k = 0; k < KT; ++k) left[k] = tot[k] = 0;
-  double l1 = 0.0, l2 = 0.0, T1 = 0.0, T2 = 0.0;
-#pragma unroll 16
-  for (int s2i = 0; s2i < NSEG; ++s2i) {
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      const uint32_t x = stot[(s2i * KT + k) * PT + q];
-      tot[k] += x;
-      left[k] += s2i < seg ? x : 0u;
-    }
-    if constexpr (MSE) {
-      const double x1 = stot1[s2i * PT + q], x2 = stot2[s2i * PT + q];
-      if (s2i < seg) {
-        l1 += x1;
-        l2 += x2;
-      }
-      T1 += x1;
-      T2 += x2;
-    }
-  }
-  int64_t n = 0;
-#pragma unroll
-  for (int k = 0; k < KT; ++k) n += tot[k];
-  const double dn = (double)n;
-  double best = __builtin_huge_val();
-  int bestb = 0x7fffffff;
-#pragma unroll
-  for (int i = 0; i < SEGMAX; ++i) {
-    const int b = b_lo + i;
-    if (i < nb) {
-      if (b >= 1) {                                  // split b: bins < b go left
-        double loss = __builtin_huge_val();
-        bool valid;
-        if constexpr (MSE) {
-          const uint32_t nL = left[0], nR = tot[0] - left[0];
-          valid = nL != 0 && nR != 0;
-          if (valid) {
-            const double dL = (double)nL, dR = (double)nR;
-            const double S1R = T1 - l1, S2R = T2 - l2;
-            const double sseL = l2 - (l1 * l1) / dL;
-            const double sseR = S2R - (S1R * S1R) / dR;
-            loss = (sseL + sseR) / (dL + dR);
-          }
-        } else {
-          int64_t nL = 0;
-#pragma unroll
-          for (int k = 0; k < KT; ++k) nL += left[k];
-          const int64_t nR = n - nL;
-          valid = nL != 0 && nR != 0;
-          if (valid) {
-            if (a.crit == SLM_GINI) {
-              uint64_t AL = 0, AR = 0;
-#pragma unroll
-              for (int k = 0; k < KT; ++k) {
-                const uint64_t l = left[k], r = tot[k] - left[k];
-                AL += l * l;
-                AR += r * r;
-              }
-              const double sv = (double)AL / (double)nL + (double)AR / (double)nR;
-              loss = (dn - sv) / dn;
-            } else {
-              double sL = 0.0, sR = 0.0;
-#pragma unroll
-              for (int k = 0; k < KT; ++k)
-                if (k < K) {
-                  sL += nlog2n_cnt(left[k], lg, rc);
-                  sR += nlog2n_cnt(tot[k] - left[k], lg, rc);
-                }
-              const double TL = nlog2n_cnt((uint32_t)nL, lg, rc) - sL;
-              const double TR = nlog2n_cnt((uint32_t)nR, lg, rc) - sR;
-              loss = (TL + TR) / dn;
-            }
-          }
-        }
-        if (valid && loss < best) {
-          best = loss;
-          bestb = b;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < KT; ++k) left[k] += c[i][k];
-      if constexpr (MSE) {
-        l1 += s1[i];
-        l2 += s2[i];
-      }
-    }
-  }
-  sbl[seg * PT + q] = best;
-  sbb[seg * PT + q] = bestb;
-
-  // optional raw histogram / sums output
-  if (qv && a.hist_out) {
-#pragma unroll
-    for (int i = 0; i < SEGMAX; ++i)
-      if (i < nb)
-#pragma unroll
-        for (int k = 0; k < KT; ++k)
-          if (k < K) a.hist_out[(out * B + b_lo + i) * K + k] = c[i][k];
-  }
-  if constexpr (MSE) {
-    if (qv && a.sums_out) {
-#pragma unroll
-      for (int i = 0; i < SEGMAX; ++i)
-        if (i < nb) {
-          a.sums_out[(out * B + b_lo + i) * 2] = s1[i];
-          a.sums_out[(out * B + b_lo + i) * 2 + 1] = s2[i];
-        }
-    }
-  }
-  // leave a multi-chunk slot zero-filled for the next call (every thread's
-  // loads from it completed before pass 1's barrier)
-  if (gsrc) {
-    for (int i = tid; i < hl.nwords; i += WGS) gc[i] = 0ull;
-    if constexpr (MSE)
-      for (int i = tid; i < B * PT; i += WGS) {
-        g1[i] = 0.0;
-        g2[i] = 0.0;
-      }
-  }
-  lds_barrier();
-
-  // pass 3: minimum over segments in bin order
-  if (tid < PT && pt * PT + tid < P) {
-    double bl = __builtin_huge_val();
-    int bb = 0x7fffffff;
-#pragma unroll 16
-    for (int s2i = 0; s2i < NSEG; ++s2i) {
-      const double l = sbl[s2i * PT + tid];
-      if (l < bl) {
-        bl = l;
-        bb = sbb[s2i * PT + tid];
-      }
-    }
-    const int64_t o = np + (int64_t)pt * PT + tid;
-    if (bb == 0x7fffffff) {
-      a.best_split[o] = -1;
-      a.best_loss[o] = __builtin_huge_val();
-      a.threshold[o] = __builtin_huge_valf();
-    } else {
-      const BinRule rr = make_rule(a.zmin[o], a.zmax[o], B);
-      a.best_split[o] = bb;
-      a.best_loss[o] = bl;
-      a.threshold[o] = edge(rr, bb);
-    }
-  }
-  if (gsrc && tid == 0) *ticket = 0u;
+  const FinishSrc src{gc, g1, g2, gc, g1, g2};
+  finish_scan<NQ, 256, KT, MSE, true>(a, src, PT, pt, grp * NQ, (int64_t)lo * a.P, fin, lg, rc,
+                                      tid);
 }
 
 // Nodes without rows get no work item in the histogram scan: report "no
@@ -905,6 +957,16 @@ slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
   hipLaunchKernelGGL((k_scan_hist<PT, KT, MSE>), dim3((unsigned)grid), dim3(HIST_WG), lds, s, a, pl.CH,
                      n_pt, pl.G, total, slot, n_slots);
   SLM_LAUNCHED();
+  if (a.N > pl.CH) {   // some node may span several chunks
+    constexpr int NQ = PT < (KT <= 8 ? 8 : 4) ? PT : (KT <= 8 ? 8 : 4);
+    const int64_t used = (a.N - 1) / pl.CH + 1;
+    const int64_t grid_f = used * n_pt * (PT / NQ);
+    SLM_CHECK(used <= n_slots && grid_f < (1ll << 31), SLM_E_SHAPE,
+              "slm_split_scan: finish grid too large");
+    hipLaunchKernelGGL((k_scan_finish<PT, KT, MSE>), dim3((unsigned)grid_f), dim3(256), 0, s, a,
+                       pl.CH, n_pt, slot, n_slots);
+    SLM_LAUNCHED();
+  }
   return SLM_OK;
 }
 
@@ -986,7 +1048,7 @@ size_t scan_workspace_bytes(int64_t N, int n_nodes, int P, int bins, int K, int 
   size_t worst = 0;
   for (int PT = 4; PT <= 32; PT <<= 1) {
     const int64_t n_pt = (P + PT - 1) / PT;
-    worst = std::max(worst, (size_t)n_pt * slot_bytes(PT, bins, Kc, mse) + (size_t)n_pt * 4);
+    worst = std::max(worst, (size_t)n_pt * slot_bytes(PT, bins, Kc, mse));
   }
   const int64_t n_slots = (N - 1) / chunk_min(N) + 1;
   return (size_t)n_slots * worst + 256;
