@@ -111,14 +111,18 @@ def main():
     total_ss = 0
     trees = []
     t0 = time.perf_counter()
+    host_ms = []
     for k in range(args.steps):
         cfg.tree = k
+        t1 = time.perf_counter()
         tr = api.grow_tree(Xd, yd, cfg, workspace=ws)
+        host_ms.append(1e3 * (time.perf_counter() - t1))
         total_ss += int(tr["sample_splits"][0])
         trees.append(tr)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    log(f"timed {args.steps} trees in {dt:.3f} s")
+    log(f"timed {args.steps} trees in {dt:.3f} s; per tree host ms "
+        f"{[round(h, 2) for h in host_ms]}, device ms {[round(t['timing'][0], 2) for t in trees]}")
 
     # instrumented tree: per-launch HIP events on the launch stream
     cfg.tree = 0

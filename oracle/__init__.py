@@ -9,10 +9,12 @@ Particle Swarm Optimization and Parallel Processing", arXiv 2208.07023):
   threshold of each projected 1-D feature (Sec. III-B), under the Gini,
   entropy or MSE criterion;
 * the particle swarm update and loop (Sec. III-A, Eqs. (11)-(12), Alg. 1);
-* the binary tree built on the global-best split (Sec. III-B, Alg. 2).
+* the binary tree built on the global-best split (Sec. III-B, Alg. 2);
+* bfloat16 screening of a swarm evaluation with float32 re-scoring of the
+  best few particles (oracle.screen).
 
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It shares no code with the GPU path and imports nothing
 from it; both sides take inputs from the seeded generators only.
 """
-from . import philox, split, pso, tree, brute  # noqa: F401
+from . import philox, split, pso, screen, tree, brute  # noqa: F401

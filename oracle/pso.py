@@ -80,17 +80,20 @@ def init_positions(seed, tree, node, P, D):
     return x
 
 
-def update_bests(x, loss, pbest, pbest_loss, gbest, gbest_loss, gbest_p):
+def update_bests(x, loss, pbest, pbest_loss, gbest, gbest_loss, gbest_p, gloss=None):
     """Personal bests (strict <) then the global best (argmin, lowest p on ties,
     taken only if strictly below the current global best).  One node; in place.
+    gloss, if given, holds the losses eligible for the global best (a screened
+    evaluation admits only its re-scored particles); by default it is loss.
     Returns True if the global best changed."""
     better = loss < pbest_loss
     pbest[better] = x[better]
     pbest_loss[better] = loss[better]
-    p = int(np.argmin(loss))
-    if loss[p] < gbest_loss[0]:
+    g = loss if gloss is None else np.asarray(gloss, dtype=np.float64)
+    p = int(np.argmin(g))
+    if g[p] < gbest_loss[0]:
         gbest[:] = x[p]
-        gbest_loss[0] = loss[p]
+        gbest_loss[0] = g[p]
         gbest_p[0] = p
         return True
     return False
@@ -111,9 +114,10 @@ def move(x, v, pbest, gbest, r1, r2, omega, c1, c2):
 
 
 def pso_step(x, v, pbest, pbest_loss, gbest, gbest_loss, gbest_p, loss, node_id,
-             n_nodes, P, D, omega, c1, c2, seed, tree, it, do_move):
+             n_nodes, P, D, omega, c1, c2, seed, tree, it, do_move, gloss=None):
     """Batched step over n_nodes swarms laid out [n_nodes * P, D]; returns new
-    arrays (inputs are not modified)."""
+    arrays (inputs are not modified).  gloss [n_nodes * P]: optional losses
+    eligible for the global best (see update_bests)."""
     x, v, pbest = x.copy(), v.copy(), pbest.copy()
     pbest_loss, gbest = pbest_loss.copy(), gbest.copy()
     gbest_loss, gbest_p = gbest_loss.copy(), gbest_p.copy()
@@ -121,7 +125,7 @@ def pso_step(x, v, pbest, pbest_loss, gbest, gbest_loss, gbest_p, loss, node_id,
         s = slice(j * P, (j + 1) * P)
         xs, vs, pbs, pbl = x[s], v[s], pbest[s], pbest_loss[s]
         gb, gbl, gp = gbest[j], gbest_loss[j:j + 1], gbest_p[j:j + 1]
-        update_bests(xs, loss[s], pbs, pbl, gb, gbl, gp)
+        update_bests(xs, loss[s], pbs, pbl, gb, gbl, gp, None if gloss is None else gloss[s])
         if do_move:
             r1, r2 = uniforms(seed, tree, int(node_id[j]), it, P, D)
             x[s], v[s] = move(xs, vs, pbs, gb, r1, r2, omega, c1, c2)
@@ -132,9 +136,13 @@ def pso_step(x, v, pbest, pbest_loss, gbest, gbest_loss, gbest_p, loss, node_id,
 def run_pso(evaluate, P, D, T, omega, c1, c2, seed, tree, node, x0=None, target_loss=None):
     """Alg. 1 for one node.
 
-    evaluate(W32 [P, D] float32) -> (loss [P], split [P], thr [P]).  The
-    directions handed to the evaluation are the float32 images of the FP64
-    positions.  Returns dict(gbest, loss, split, thr, p, evals, history)."""
+    evaluate(W32 [P, D] float32) -> (loss [P], split [P], thr [P]) or
+    (loss, split, thr, gloss) where gloss holds the losses eligible for the
+    global best.  The directions handed to the evaluation are the float32
+    images of the FP64 positions.  x0 replaces the random initial positions
+    (rows are used as given).  With target_loss the loop stops after the
+    first evaluation whose global-best loss is <= target_loss.
+    Returns dict(gbest, loss, split, thr, p, evals, history)."""
     x = init_positions(seed, tree, node, P, D) if x0 is None else np.array(x0, dtype=np.float64)
     v = np.zeros_like(x)
     pbest = x.copy()
@@ -146,10 +154,12 @@ def run_pso(evaluate, P, D, T, omega, c1, c2, seed, tree, node, x0=None, target_
     history = []
     evals = 0
     for t in range(T + 1):
-        loss, split, thr = evaluate(x.astype(np.float32))
+        out = evaluate(x.astype(np.float32))
+        loss, split, thr = out[:3]
+        gloss = out[3] if len(out) > 3 else None
         evals += 1
         loss = np.asarray(loss, dtype=np.float64)
-        if update_bests(x, loss, pbest, pbest_loss, gbest, gbest_loss, gbest_p):
+        if update_bests(x, loss, pbest, pbest_loss, gbest, gbest_loss, gbest_p, gloss):
             g_split, g_thr = int(split[gbest_p[0]]), np.float32(thr[gbest_p[0]])
         history.append(float(gbest_loss[0]))
         if target_loss is not None and gbest_loss[0] <= target_loss:

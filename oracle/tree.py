@@ -22,6 +22,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import screen
 from . import split as S
 from .pso import run_pso
 
@@ -40,6 +41,8 @@ class TreeParams:
     c2: float = 1.5
     seed: int = 0
     tree: int = 0
+    precision: int = 0         # 1 = bfloat16 screening, float32 re-scoring
+    rescore_k: int = 32
 
 
 @dataclass
@@ -87,7 +90,12 @@ def node_summary(target, crit, K):
 
 def evaluate_node(Xn, tn, prm: TreeParams):
     """Evaluation closure for run_pso: project the node's rows on the float32
-    directions, round the FP64 projections to float32 and scan each column."""
+    directions, round the FP64 projections to float32 and scan each column.
+    With precision = 1 the evaluation is the screened one of oracle.screen
+    (X then holds bfloat16 values)."""
+    if prm.precision == 1:
+        return screen.evaluate_screened(Xn, tn, prm.crit, prm.K, prm.bins, prm.rescore_k)
+
     def ev(W32):
         Z = S.project(Xn, W32).astype(np.float32)
         loss = np.empty(W32.shape[0])

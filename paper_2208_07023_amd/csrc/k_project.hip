@@ -19,6 +19,19 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+int num_cus_proj() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+      (void)hipGetLastError();
+      n = 256;
+    }
+  }
+  return n;
+}
+
 constexpr int KC = 64;          // dimensions staged per LDS round
 constexpr int LDSTR = KC + 1;   // odd stride: the 32 rows a fragment reads hit 32 banks
 
@@ -141,174 +154,222 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   }
 }
 
-// Short projections (D <= 64): each wave keeps the B fragments of its 32*FN
-// particles for all KSP k-steps in registers for the whole work item, and
-// 32-row sub-tiles of X stream through a double-buffered LDS tile.  A work
-// item is (node, chunk of RT global rows) x (particle tile of 32*FN*WAVES).
-// D is padded with zeros to 2*KSP; the extra steps add exact zeros, so each
-// output element is the same MFMA sequence whatever FN / WAVES / KSP.
+// Short projections (D <= 64), without LDS.  Lane (i, h) of a wave supplies
+// row i of a 32-row sub-tile and k = h KSP + s at MFMA step s (s < KSP), so a
+// lane's A operand is a contiguous run of its X row and its B operand a
+// contiguous run of its W row, both read with 16-byte loads straight from
+// global memory (scalar loads when D is not a multiple of 4).  Each wave
+// keeps the B fragments of its 32 FN particles in registers while the node
+// stays the same and double-buffers the A operand in registers: the next
+// sub-tile is loaded while the current one's MFMAs run.  A work-group walks a
+// contiguous range of rows across node boundaries (rows of no node are
+// skipped); its waves take different particle blocks of the same rows.  D is
+// padded with zeros to 2 KSP; the accumulation order over k depends on KSP
+// alone, so every output element is the same MFMA sequence whatever FN,
+// WAVES and the split of the rows.
 constexpr int SR = 32;             // rows per sub-tile
-constexpr int XS = 64 + 1;         // LDS row stride of a sub-tile (odd)
 
-template <int FN, int WAVES, int KSP, bool BF16>
-__global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int64_t RT) {
-  __shared__ float Xs[2][SR * XS];
+struct SubTile {
+  int j;                           // node (-1: none left)
+  int64_t lo, hi;                  // rows lo .. hi-1 of node j, hi - lo <= SR
+};
+
+// First sub-tile of rows >= r inside [.., r_end), starting the search at node j.
+__device__ __forceinline__ SubTile next_subtile(const ProjectArgs &a, int j, int64_t r,
+                                                int64_t r_end) {
+  for (; j < a.n_nodes; ++j) {
+    const Range nr = load_range(a.beg, a.end, j, a.N);
+    const int64_t lo = r > nr.lo ? r : nr.lo;
+    if (lo >= r_end) break;
+    if (lo < nr.hi) {
+      const int64_t hi = nr.hi < r_end ? nr.hi : r_end;
+      return {j, lo, hi < lo + SR ? hi : lo + SR};
+    }
+  }
+  return {-1, 0, 0};
+}
+
+template <int KSP, bool BF16, bool VEC>
+__device__ __forceinline__ void load_run(const void *base, int64_t row, int D, int k0, bool ok,
+                                         float (&v)[KSP]) {
+  if constexpr (VEC) {
+#pragma unroll
+    for (int q = 0; q < KSP / 4; ++q) {
+      const int kk = k0 + 4 * q;
+      const bool in = ok && kk < D;
+      const int64_t idx = row * D + (kk < D ? kk : 0);
+      float t[4];
+      if constexpr (BF16) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(base) + idx);
+        t[0] = bf16_to_f32((uint16_t)(u.x & 0xFFFFu));
+        t[1] = bf16_to_f32((uint16_t)(u.x >> 16));
+        t[2] = bf16_to_f32((uint16_t)(u.y & 0xFFFFu));
+        t[3] = bf16_to_f32((uint16_t)(u.y >> 16));
+      } else {
+        const float4 f = *reinterpret_cast<const float4 *>(static_cast<const float *>(base) + idx);
+        t[0] = f.x;
+        t[1] = f.y;
+        t[2] = f.z;
+        t[3] = f.w;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[4 * q + e] = in ? t[e] : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < KSP; ++s) {
+      const int kk = k0 + s;
+      const float t = load_x<BF16>(base, row * D + (kk < D ? kk : D - 1));
+      v[s] = (ok && kk < D) ? t : 0.f;
+    }
+  }
+}
+
+template <int FN, int WAVES, int KSP, bool BF16, bool VEC>
+__global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int64_t RB,
+                                                               int blocks_per_pt) {
   constexpr int PTILE = 32 * FN * WAVES;
-  constexpr int NT = 64 * WAVES;
-  constexpr int DP = 2 * KSP;              // padded dimensions staged per row
-  constexpr int PER = SR * DP / NT;        // floats per thread per sub-tile
-  static_assert(PER >= 1 && SR * DP % NT == 0, "sub-tile must divide evenly");
-  const int n_pt = (a.P + PTILE - 1) / PTILE;
-  const int64_t v = blockIdx.x / n_pt;
-  const int pt = blockIdx.x % n_pt;
-  const Item it = find_item(a.beg, a.end, a.n_nodes, a.N, RT, v);
-  if (it.node < 0) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int pt = blockIdx.x / blocks_per_pt;
+  const int64_t r_begin = (int64_t)(blockIdx.x % blocks_per_pt) * RB;
+  const int64_t r_end = r_begin + RB < a.N ? r_begin + RB : a.N;
+  if (r_begin >= r_end || a.n_nodes <= 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int D = a.D, P = a.P;
-  const int li = lane & 31, kh = lane >> 5;
-  const int64_t wbase = (int64_t)it.node * P;
+  const int li = lane & 31, kh = lane >> 5, k0 = kh * KSP;
   const int pw = pt * PTILE + wave * 32 * FN;   // first particle of this wave
   const bool wave_full = pw + 32 * FN <= P;     // every column of the wave exists
+  const int64_t rs = a.zl.rs;
+  const bool do_mm = a.zmin != nullptr;
 
-  // B fragments: lane holds W[p = pw + f*32 + li][k = 2 ks + kh]
+  // first node whose rows reach past r_begin (ends are non-decreasing)
+  int j0 = 0;
+  {
+    int lo = 0, hi = a.n_nodes;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (load_range(a.beg, a.end, mid, a.N).hi <= r_begin) lo = mid + 1; else hi = mid;
+    }
+    j0 = lo;
+  }
+  SubTile cur = next_subtile(a, j0, r_begin, r_end);
+  if (cur.j < 0) return;
+
   float bfrag[FN][KSP];
-#pragma unroll
-  for (int f = 0; f < FN; ++f) {
-    const int p = pw + f * 32 + li;
-#pragma unroll
-    for (int ks = 0; ks < KSP; ++ks) {
-      const int k = 2 * ks + kh;
-      bfrag[f][ks] = (k < D && p < P) ? load_x<BF16>(a.W, (wbase + p) * D + k) : 0.f;
-    }
-  }
   float mn[FN], mx[FN];
-#pragma unroll
-  for (int f = 0; f < FN; ++f) {
-    mn[f] = __builtin_huge_valf();
-    mx[f] = -__builtin_huge_valf();
-  }
-  const int64_t r_first = (it.lo / SR) * SR;
-  const int nsub = (int)((it.hi - r_first + SR - 1) / SR);
-  // X sub-tile staging: every thread prefetches its share into registers
-  // before the current sub-tile's MFMAs and writes it to LDS after them, so
-  // global latency overlaps the matrix work.
-  float pre[PER];
-  // Branch-free: rows and columns outside the item read a clamped in-bounds
-  // address and are replaced by zero.
-  auto fetch = [&](int64_t r0) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      const int r = e / DP, c = e % DP;
-      const int64_t row = r0 + r;
-      const bool ok = c < D && row >= it.lo && row < it.hi;
-      const int64_t rc = row < it.lo ? it.lo : (row >= it.hi ? it.hi - 1 : row);
-      const float x = load_x<BF16>(a.X, rc * D + (c < D ? c : D - 1));
-      pre[u] = ok ? x : 0.f;
-    }
-  };
-  auto commit = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      Xs[buf][(e / DP) * XS + (e % DP)] = pre[u];
-    }
-  };
-  fetch(r_first);
-  commit(0);
-  lds_barrier();
-  for (int sidx = 0; sidx < nsub; ++sidx) {
-    const int cur = sidx & 1;
-    const int64_t r0 = r_first + (int64_t)sidx * SR;
-    const bool more = sidx + 1 < nsub;
-    if (more) fetch(r0 + SR);
-    f32x16 acc[FN];
-#pragma unroll
-    for (int f = 0; f < FN; ++f) acc[f] = f32x16{};
-#pragma unroll
-    for (int ks = 0; ks < KSP; ++ks) {
-      const float af = Xs[cur][li * XS + 2 * ks + kh];
-#pragma unroll
-      for (int f = 0; f < FN; ++f)
-        acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(af, bfrag[f][ks], acc[f], 0, 0, 0);
-    }
-    if (more) commit(cur ^ 1);
-    // Epilogue.  Lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4 of the
-    // sub-tile and particle column l%32 of block f.
-    const bool interior = wave_full && r0 >= it.lo && r0 + SR <= it.hi;
-#pragma unroll
-    for (int f = 0; f < FN; ++f) {
-      const int p = pw + f * 32 + li;
-      const int64_t rs = a.zl.rs;
-      float *zc = a.Z + z_col(a.zl, p) + (r0 + 4 * kh) * rs;
-      if (interior) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float z = acc[f][r];
-          zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = z;
-          mn[f] = fminf(mn[f], z);
-          mx[f] = fmaxf(mx[f], z);
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int64_t row = r0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-          if (p < P && row >= it.lo && row < it.hi) {
-            const float z = acc[f][r];
-            zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = z;
-            mn[f] = fminf(mn[f], z);
-            mx[f] = fmaxf(mx[f], z);
-          }
-        }
-      }
-    }
-    lds_barrier();
-  }
-  if (a.zmin != nullptr) {
+  int node_c = -1;
+  auto flush = [&]() {
+    if (node_c < 0 || !do_mm) return;
+    const int64_t wb = (int64_t)node_c * P;
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
       const int p = pw + f * 32 + li;
       const float m0 = fminf(mn[f], __shfl_xor(mn[f], 32));
       const float m1 = fmaxf(mx[f], __shfl_xor(mx[f], 32));
       if (lane < 32 && p < P && m0 <= m1) {
-        atomic_min_f32(&a.zmin[wbase + p], m0);
-        atomic_max_f32(&a.zmax[wbase + p], m1);
+        atomic_min_f32(&a.zmin[wb + p], m0);
+        atomic_max_f32(&a.zmax[wb + p], m1);
       }
     }
+  };
+
+  float acur[KSP], anext[KSP];
+  load_run<KSP, BF16, VEC>(a.X, cur.lo + li < cur.hi ? cur.lo + li : cur.hi - 1, D, k0,
+                           cur.lo + li < cur.hi, acur);
+  while (cur.j >= 0) {
+    if (cur.j != node_c) {
+      flush();
+      node_c = cur.j;
+      const int64_t wb = (int64_t)node_c * P;
+#pragma unroll
+      for (int f = 0; f < FN; ++f) {
+        const int p = pw + f * 32 + li;
+        load_run<KSP, BF16, VEC>(a.W, wb + (p < P ? p : P - 1), D, k0, p < P, bfrag[f]);
+        mn[f] = __builtin_huge_valf();
+        mx[f] = -__builtin_huge_valf();
+      }
+    }
+    const SubTile nxt = next_subtile(a, cur.j, cur.hi, r_end);
+    if (nxt.j >= 0)
+      load_run<KSP, BF16, VEC>(a.X, nxt.lo + li < nxt.hi ? nxt.lo + li : nxt.hi - 1, D, k0,
+                               nxt.lo + li < nxt.hi, anext);
+    f32x16 acc[FN];
+#pragma unroll
+    for (int f = 0; f < FN; ++f) acc[f] = f32x16{};
+#pragma unroll
+    for (int ks = 0; ks < KSP; ++ks)
+#pragma unroll
+      for (int f = 0; f < FN; ++f)
+        acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[ks], bfrag[f][ks], acc[f], 0, 0, 0);
+    // Epilogue.  Lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4 of the
+    // sub-tile and particle column l%32 of block f.
+    const bool interior = wave_full && cur.hi - cur.lo == SR;
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+      const int p = pw + f * 32 + li;
+      float *zc = a.Z + z_col(a.zl, p < P ? p : P - 1) + (cur.lo + 4 * kh) * rs;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rr = 8 * (r >> 2) + (r & 3);
+        const bool ok = interior || (p < P && cur.lo + 4 * kh + rr < cur.hi);
+        if (ok) {
+          const float z = acc[f][r];
+          zc[(int64_t)rr * rs] = z;
+          mn[f] = fminf(mn[f], z);
+          mx[f] = fmaxf(mx[f], z);
+        }
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KSP; ++ks) acur[ks] = anext[ks];
+    cur = nxt;
   }
+  flush();
 }
 
-template <int FN, int WAVES, int KSP>
-slm_status launch_short_k(const ProjectArgs &a, int64_t RT, int64_t grid, hipStream_t s) {
+template <int FN, int WAVES, int KSP, bool VEC>
+slm_status launch_short_k(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
   if (a.bf16)
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true>), dim3((unsigned)grid),
-                       dim3(64 * WAVES), 0, s, a, RT);
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true, VEC>), dim3((unsigned)grid),
+                       dim3(64 * WAVES), 0, s, a, RB, bpp);
   else
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false>), dim3((unsigned)grid),
-                       dim3(64 * WAVES), 0, s, a, RT);
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, VEC>), dim3((unsigned)grid),
+                       dim3(64 * WAVES), 0, s, a, RB, bpp);
   SLM_LAUNCHED();
   return SLM_OK;
+}
+
+template <int FN, int WAVES, bool VEC>
+slm_status launch_short_v(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
+  if (a.D <= 8) return launch_short_k<FN, WAVES, 4, VEC>(a, RB, bpp, grid, s);
+  if (a.D <= 16) return launch_short_k<FN, WAVES, 8, VEC>(a, RB, bpp, grid, s);
+  if (a.D <= 32) return launch_short_k<FN, WAVES, 16, VEC>(a, RB, bpp, grid, s);
+  return launch_short_k<FN, WAVES, 32, VEC>(a, RB, bpp, grid, s);
 }
 
 template <int FN, int WAVES>
 slm_status launch_short(const ProjectArgs &a, hipStream_t s) {
   constexpr int PTILE = 32 * FN * WAVES;
   const int64_t n_pt = (a.P + PTILE - 1) / PTILE;
-  // rows per work item: about 4 work-groups per CU over the whole matrix
-  // (SLM_PROJ_RT overrides it for tuning sweeps)
-  int64_t RT = (a.N * n_pt + 1023) / 1024;
-  RT = std::max<int64_t>(256, std::min<int64_t>(4096, (RT + SR - 1) / SR * SR));
+  // about two resident waves per SIMD over the whole launch; each work-group
+  // takes a contiguous run of rows (SLM_PROJ_RT overrides the run length)
+  const int64_t cap = (int64_t)num_cus_proj() * 8 / WAVES;
+  int64_t bpp = std::max<int64_t>(1, std::min<int64_t>((a.N + SR - 1) / SR, cap / n_pt));
+  int64_t RB = (a.N + bpp - 1) / bpp;
   if (const char *env = getenv("SLM_PROJ_RT")) {
     const long long v = atoll(env);
-    if (v >= SR && v <= 65536) RT = (v + SR - 1) / SR * SR;
+    if (v >= 1 && v <= (1 << 24)) {
+      RB = v;
+      bpp = (a.N + RB - 1) / RB;
+    }
   }
-  const int64_t grid = num_items(a.n_nodes, a.N, RT) * n_pt;
+  const int64_t grid = bpp * n_pt;
   if (grid == 0) return SLM_OK;
   SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_project: grid too large");
-  if (a.D <= 8) return launch_short_k<FN, WAVES, 4>(a, RT, grid, s);
-  if (a.D <= 16) return launch_short_k<FN, WAVES, 8>(a, RT, grid, s);
-  if (a.D <= 32) return launch_short_k<FN, WAVES, 16>(a, RT, grid, s);
-  return launch_short_k<FN, WAVES, 32>(a, RT, grid, s);
+  const size_t es = a.bf16 ? 8 : 16;   // bytes of one vector load
+  const bool vec = a.D % 4 == 0 && reinterpret_cast<uintptr_t>(a.X) % es == 0 &&
+                   reinterpret_cast<uintptr_t>(a.W) % es == 0;
+  if (vec) return launch_short_v<FN, WAVES, true>(a, RB, (int)bpp, grid, s);
+  return launch_short_v<FN, WAVES, false>(a, RB, (int)bpp, grid, s);
 }
 
 __global__ void k_fill_minmax(float *zmin, float *zmax, int64_t n) {

@@ -117,15 +117,16 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_init(PsoArgs a) {
   }
 }
 
-// (1) of the step: one work-group per node.  Personal bests (strict <), the
-// argmin of the current losses (lowest p on ties) and the global best.
+// (1) of the step: one work-group per node.  The argmin of the current losses
+// (lowest p on ties) replaces the global best iff strictly better; the
+// position is copied before the move kernel changes x.  The personal bests
+// are updated by the move kernel, where every particle's threads are.
 constexpr int BEST_WG = 256;
 constexpr int PMAX_STEP = 4096;
 
 __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
   __shared__ double red_l[BEST_WG];
   __shared__ int red_p[BEST_WG];
-  __shared__ unsigned char imp[PMAX_STEP];
   __shared__ int s_pstar, s_improved;
   const int j = blockIdx.x, tid = threadIdx.x;
   const int P = a.P, D = a.D;
@@ -134,9 +135,6 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
   int bp = 0x7fffffff;
   for (int p = tid; p < P; p += BEST_WG) {
     const double l = a.loss[base + p];
-    const bool better = l < a.pbest_loss[base + p];
-    imp[p] = better;
-    if (better) a.pbest_loss[base + p] = l;
     if (l < bl) {
       bl = l;
       bp = p;
@@ -169,12 +167,6 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
     }
   }
   __syncthreads();
-  // copy the improved positions into the personal bests (coalesced over p*D + d)
-  const int64_t tot = (int64_t)P * D;
-  for (int64_t e = tid; e < tot; e += BEST_WG) {
-    const int p = (int)(e / D);
-    if (imp[p]) a.pbest[base * D + e] = a.x[base * D + e];
-  }
   if (s_improved) {
     const int ps = s_pstar;
     for (int d = tid; d < D; d += BEST_WG) a.gbest[(int64_t)j * D + d] = a.x[(base + ps) * D + d];
@@ -187,7 +179,8 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
   }
 }
 
-// (2) of the step: Eq. (11), Eq. (12) and the unit-norm rescale.
+// (2) of the step: personal bests (strict <), then with move != 0 Eq. (11),
+// Eq. (12) and the unit-norm rescale.
 __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   extern __shared__ double buf[];          // [PPB][D] then gbest [D]
   __shared__ double nrm_s[MOVE_WG];
@@ -198,31 +191,45 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   const int p = (blockIdx.x % bpn) * g.PPB + pl;
   const bool pv = p < a.P;
   const int D = a.D, dh = (D + 1) / 2;
+  const bool move = a.move != 0;
   double *gb = buf + (size_t)g.PPB * D;
-  for (int d = threadIdx.x; d < D; d += MOVE_WG) gb[d] = a.gbest[(int64_t)j * D + d];
+  if (move)
+    for (int d = threadIdx.x; d < D; d += MOVE_WG) gb[d] = a.gbest[(int64_t)j * D + d];
   uint2 key;
   uint32_t tree;
   rng_key(a, &key, &tree);
   const uint32_t node = (uint32_t)a.node_id[j];
   const int64_t gid = (int64_t)j * a.P + p;
+  const double lp = pv ? a.loss[gid] : 0.0;
+  const bool imp = pv && lp < a.pbest_loss[gid];
   lds_barrier();
   if (pv) {
     for (int d = dl; d < D; d += g.Dp) {
+      const int64_t e = gid * D + d;
+      const double xv = a.x[e];
+      double pb;
+      if (imp) {
+        a.pbest[e] = xv;
+        pb = xv;
+      } else {
+        pb = a.pbest[e];
+      }
+      if (!move) continue;
       const int m = d >> 1, h = d & 1;
       const uint4 w = philox4x32_10(make_uint4((uint32_t)(p * dh + m), a.iter, node, tree), key);
       const double r1 = u24(h ? w.z : w.x);
       const double r2 = u24(h ? w.w : w.y);
-      const int64_t e = gid * D + d;
-      const double xv = a.x[e];
       const double t0 = a.omega * a.v[e];
-      const double t1 = (a.c1 * r1) * (a.pbest[e] - xv);
+      const double t1 = (a.c1 * r1) * (pb - xv);
       const double t2 = (a.c2 * r2) * (gb[d] - xv);
       const double vn = (t0 + t1) + t2;
       a.v[e] = vn;
       buf[pl * D + d] = xv + vn;
     }
   }
-  lds_barrier();
+  lds_barrier();   // every thread of the particle has read pbest_loss
+  if (imp && dl == 0) a.pbest_loss[gid] = lp;
+  if (!move) return;
   if (pv && dl == 0) {
     double s = 0.0;
     for (int d = 0; d < D; ++d) s = s + buf[pl * D + d] * buf[pl * D + d];
@@ -287,7 +294,7 @@ slm_status launch_pso_step(const PsoArgs &a, hipStream_t s) {
   if (a.n_nodes == 0) return SLM_OK;
   hipLaunchKernelGGL(k_pso_bests, dim3((unsigned)a.n_nodes), dim3(BEST_WG), 0, s, a);
   SLM_LAUNCHED();
-  if (!a.move) return SLM_OK;
+  if (a.bests_only) return SLM_OK;
   const MoveGeom g = move_geom(a.D);
   const int64_t grid = (int64_t)a.n_nodes * ((a.P + g.PPB - 1) / g.PPB);
   const size_t lds = ((size_t)g.PPB * a.D + a.D) * sizeof(double);

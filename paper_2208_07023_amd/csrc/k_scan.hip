@@ -214,6 +214,24 @@ size_t slot_bytes(int PT, int B, int K, bool mse) {
   const HistLayout h = hist_layout(PT, B, K, mse);
   return (h.glob_cnt + h.sums + 255) / 256 * 256;
 }
+// Accumulator slots of one replica: one per possible first chunk of a
+// multi-chunk node, sized for the largest footprint of any tile width.
+size_t slot_set_bytes(int64_t N, int P, int B, int K, bool mse) {
+  size_t worst = 0;
+  for (int PT = 4; PT <= 32; PT <<= 1) {
+    const int64_t n_pt = (P + PT - 1) / PT;
+    worst = std::max(worst, (size_t)n_pt * slot_bytes(PT, B, K, mse));
+  }
+  const int64_t n_slots = (N - 1) / chunk_min(N) + 1;
+  return (size_t)n_slots * worst;
+}
+// Replicas of every slot: the work-groups of a node spread their atomic
+// merges over R copies (chunk % R), which k_scan_finish adds up; 4 while the
+// accumulator stays within 1 GiB.
+int slot_replicas(int64_t N, int P, int B, int K, bool mse) {
+  const size_t one = slot_set_bytes(N, P, B, K, mse);
+  return one * 4 <= ((size_t)1 << 30) ? 4 : (one * 2 <= ((size_t)1 << 30) ? 2 : 1);
+}
 
 // Largest particle tile whose histograms fit in 80 KB of LDS (two
 // work-groups per CU) and whose finish registers (PT / 2 bins x KT classes)
@@ -303,6 +321,8 @@ struct FinishSrc {
   const double *s1, *s2;         // regression sums [B][PT]
   unsigned long long *gzero;     // slot words to clear after reading (GSRC)
   double *gz1, *gz2;
+  int R;                         // GSRC: replicas of the slot, rstride bytes apart
+  size_t rstride;
 };
 
 template <int NQ, int NT, int KT, bool MSE, bool GSRC>
@@ -326,23 +346,36 @@ __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &
   double s1[MSE ? SEGMAX : 1], s2[MSE ? SEGMAX : 1];
 #pragma unroll
   for (int i = 0; i < SEGMAX; ++i) {
-    const int b = min(b_lo + i, B - 1);
-    const int w = (b & 127) * SB + qt;
 #pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      uint32_t x;
-      if constexpr (GSRC)
-        x = (uint32_t)(static_cast<const unsigned long long *>(src.cnt)[w + min(k, K - 1) * PT] >>
-                       ((b >> 7) << 5));
-      else
-        x = (static_cast<const uint32_t *>(src.cnt)[w + min(k, K - 1) * PT] >> ((b >> 7) << 4)) &
-            0xFFFFu;
-      c[i][k] = (i < nb && k < K) ? x : 0u;
-    }
-    if constexpr (MSE) {
-      const double x1 = src.s1[b * PT + qt], x2 = src.s2[b * PT + qt];
-      s1[i] = i < nb ? x1 : 0.0;
-      s2[i] = i < nb ? x2 : 0.0;
+    for (int k = 0; k < KT; ++k) c[i][k] = 0u;
+    if constexpr (MSE) s1[i] = s2[i] = 0.0;
+  }
+  for (int r = 0; r < (GSRC ? src.R : 1); ++r) {
+    const unsigned char *rb = static_cast<const unsigned char *>(src.cnt) + (size_t)r * src.rstride;
+    const double *r1 = reinterpret_cast<const double *>(
+        reinterpret_cast<const unsigned char *>(src.s1) + (size_t)r * src.rstride);
+    const double *r2 = reinterpret_cast<const double *>(
+        reinterpret_cast<const unsigned char *>(src.s2) + (size_t)r * src.rstride);
+#pragma unroll
+    for (int i = 0; i < SEGMAX; ++i) {
+      const int b = min(b_lo + i, B - 1);
+      const int w = (b & 127) * SB + qt;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        uint32_t x;
+        if constexpr (GSRC)
+          x = (uint32_t)(reinterpret_cast<const unsigned long long *>(rb)[w + min(k, K - 1) * PT] >>
+                         ((b >> 7) << 5));
+        else
+          x = (reinterpret_cast<const uint32_t *>(rb)[w + min(k, K - 1) * PT] >> ((b >> 7) << 4)) &
+              0xFFFFu;
+        c[i][k] += (i < nb && k < K) ? x : 0u;
+      }
+      if constexpr (MSE) {
+        const double x1 = r1[b * PT + qt], x2 = r2[b * PT + qt];
+        s1[i] += i < nb ? x1 : 0.0;
+        s2[i] += i < nb ? x2 : 0.0;
+      }
     }
   }
   if constexpr (!GSRC) lds_barrier();   // the histogram region becomes finish scratch
@@ -374,17 +407,25 @@ __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &
   lds_barrier();
   if constexpr (GSRC) {
     // every thread's loads completed before the barrier: clear what was read
+    for (int r = 0; r < src.R; ++r) {
+      unsigned long long *zc = reinterpret_cast<unsigned long long *>(
+          reinterpret_cast<unsigned char *>(src.gzero) + (size_t)r * src.rstride);
+      double *z1 = reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(src.gz1) +
+                                              (size_t)r * src.rstride);
+      double *z2 = reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(src.gz2) +
+                                              (size_t)r * src.rstride);
 #pragma unroll
-    for (int i = 0; i < SEGMAX; ++i) {
-      if (i < nb) {
-        const int b = b_lo + i;
-        const int w = (b & 127) * SB + qt;
+      for (int i = 0; i < SEGMAX; ++i) {
+        if (i < nb) {
+          const int b = b_lo + i;
+          const int w = (b & 127) * SB + qt;
 #pragma unroll
-        for (int k = 0; k < KT; ++k)
-          if (k < K) src.gzero[w + k * PT] = 0ull;
-        if constexpr (MSE) {
-          src.gz1[b * PT + qt] = 0.0;
-          src.gz2[b * PT + qt] = 0.0;
+          for (int k = 0; k < KT; ++k)
+            if (k < K) zc[w + k * PT] = 0ull;
+          if constexpr (MSE) {
+            z1[b * PT + qt] = 0.0;
+            z2[b * PT + qt] = 0.0;
+          }
         }
       }
     }
@@ -535,7 +576,7 @@ __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &
 template <int PT, int KT, bool MSE>
 __global__ __launch_bounds__(HIST_WG) __attribute__((amdgpu_waves_per_eu(4)))
 void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, size_t slot_sz,
-                 int64_t n_slots) {
+                 int64_t n_slots, int R) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int WGS = HIST_WG;
   const int B = a.bins;
@@ -607,8 +648,26 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   constexpr int U = 16;
   int i = 0;
   if (wave_fast) {
+    // Binning without branches.  The guess t = z B / r - (zmin B / r + 0.005)
+    // (one fused multiply-add) is within B u (6 + 3 |zmin| / r) <= 3.1e-3
+    // bins of the count of edges <= z when |zmin| <= 64 r and B <= 256 (the
+    // rounding of the edges, of B / r, of the constant and of the result), so
+    // g = trunc(t) is the bin or the one below it, never negative: one
+    // comparison with the exact edge e_{g+1} settles it.  The unsigned clamp
+    // keeps any input in range.  Bin b adds 1 << 16 (b >> 7) to word (b & 127)
+    // of the lane's (class) column; a lane without a particle, or a label
+    // outside [0, K), adds 0.
     const float zmin = rule.zmin, delta = rule.delta, inv = rule.inv;
-    const int bmax = B - 1;
+    const float off0 = -fmaf(zmin, inv, 0.005f);
+    const unsigned bmax = (unsigned)B - 1u;
+    const unsigned labk = pv ? (unsigned)K : 0u;
+    const uint32_t pt4 = PT * 4u, pl4 = (uint32_t)pl * 4u;
+    unsigned char *hb = reinterpret_cast<unsigned char *>(hc);
+    auto bin_fast = [&](float zu) -> unsigned {
+      const int g0 = (int)fmaf(zu, inv, off0);
+      const float e1 = __fadd_rn(zmin, __fmul_rn((float)(g0 + 1), delta));
+      return min((unsigned)(g0 + (e1 <= zu ? 1 : 0)), bmax);
+    };
     for (; i + U <= nrows; i += U) {
       float z[U];
       int lab[U];
@@ -621,14 +680,15 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        int g = (int)((z[u] - zmin) * inv);
-        g = min(max(g, 0), bmax);
-        const float fg = (float)g;
-        const float e0 = __fadd_rn(zmin, __fmul_rn(fg, delta));
-        const float e1 = __fadd_rn(zmin, __fmul_rn(fg + 1.0f, delta));
-        g = g - ((g >= 1 && e0 > z[u]) ? 1 : 0) + ((g < bmax && e1 <= z[u]) ? 1 : 0);
-        if constexpr (MSE) add_mse(g, yv[u]);
-        else add_cls(g, lab[u]);
+        const unsigned g = bin_fast(z[u]);
+        if constexpr (MSE) {
+          add_mse((int)g, yv[u]);
+        } else {
+          const unsigned lb = min((unsigned)lab[u], (unsigned)K - 1u);
+          const uint32_t inc = (unsigned)lab[u] < labk ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
+          const uint32_t off = __umul24(__umul24(g & 127u, (unsigned)K) + lb, pt4) + pl4;
+          atomicAdd(reinterpret_cast<uint32_t *>(hb + off), inc);
+        }
       }
     }
   }
@@ -646,7 +706,9 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
     const Range nr = load_range(a.beg, a.end, it.node, a.N);
     const int64_t slot = nr.lo / CH;
     if (slot >= n_slots) return;   // cannot happen with a workspace sized by the plan
-    unsigned char *base = static_cast<unsigned char *>(a.ws) + (size_t)(slot * n_pt + pt) * slot_sz;
+    // replica it.chunk % R of the slot: fewer atomics on each address
+    unsigned char *base = static_cast<unsigned char *>(a.ws) +
+                          ((size_t)(slot * R + it.chunk % R) * n_pt + pt) * slot_sz;
     unsigned long long *gc = reinterpret_cast<unsigned long long *>(base);
     for (int i = tid; i < hl.nwords; i += WGS) {
       const uint32_t w = hc[i];
@@ -665,7 +727,7 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   }
 
   // ---- a node inside one chunk: finish from the LDS histogram
-  const FinishSrc src{hc, hs1, hs2, nullptr, nullptr, nullptr};
+  const FinishSrc src{hc, hs1, hs2, nullptr, nullptr, nullptr, 1, 0};
   finish_scan<PT, WGS, KT, MSE, false>(a, src, PT, pt, 0, np, smem, lg, rc, tid);
 }
 
@@ -674,7 +736,7 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
 // group of NQ particles); slots without such a node exit at once.
 template <int PT, int KT, bool MSE>
 __global__ __launch_bounds__(256) void k_scan_finish(ScanArgs a, int64_t CH, int n_pt,
-                                                     size_t slot_sz, int64_t n_slots) {
+                                                     size_t slot_sz, int64_t n_slots, int R) {
   constexpr int NQ = PT < (KT <= 8 ? 8 : 4) ? PT : (KT <= 8 ? 8 : 4);
   constexpr int NGRP = PT / NQ;
   __shared__ __align__(16) unsigned char fin[finish_scratch_bytes<256, KT, MSE>()];
@@ -701,7 +763,8 @@ __global__ __launch_bounds__(256) void k_scan_finish(ScanArgs a, int64_t CH, int
   const int B = a.bins;
   const int K = MSE ? 1 : a.K;
   const HistLayout hl = hist_layout(PT, B, K, MSE);
-  unsigned char *base = static_cast<unsigned char *>(a.ws) + (size_t)(slot * n_pt + pt) * slot_sz;
+  unsigned char *base =
+      static_cast<unsigned char *>(a.ws) + ((size_t)slot * R * n_pt + pt) * slot_sz;
   unsigned long long *gc = reinterpret_cast<unsigned long long *>(base);
   double *g1 = reinterpret_cast<double *>(base + hl.glob_cnt);
   double *g2 = g1 + (size_t)B * PT;
@@ -709,7 +772,7 @@ __global__ __launch_bounds__(256) void k_scan_finish(ScanArgs a, int64_t CH, int
   double *lg = lgt, *rc = lgt + LG_TBL;
   if (!MSE && a.crit == SLM_ENTROPY) fill_log_table(lg, rc, tid);
   lds_barrier();
-  const FinishSrc src{gc, g1, g2, gc, g1, g2};
+  const FinishSrc src{gc, g1, g2, gc, g1, g2, R, (size_t)n_pt * slot_sz};
   finish_scan<NQ, 256, KT, MSE, true>(a, src, PT, pt, grp * NQ, (int64_t)lo * a.P, fin, lg, rc,
                                       tid);
 }
@@ -954,8 +1017,9 @@ slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
   const size_t lds = lds_bytes(PT, a.bins, Kc, MSE, table);
   const size_t slot = slot_bytes(PT, a.bins, Kc, MSE);
   const int64_t n_slots = (a.N - 1) / chunk_min(a.N) + 1;
+  const int R = slot_replicas(a.N, a.P, a.bins, Kc, MSE);
   hipLaunchKernelGGL((k_scan_hist<PT, KT, MSE>), dim3((unsigned)grid), dim3(HIST_WG), lds, s, a, pl.CH,
-                     n_pt, pl.G, total, slot, n_slots);
+                     n_pt, pl.G, total, slot, n_slots, R);
   SLM_LAUNCHED();
   if (a.N > pl.CH) {   // some node may span several chunks
     constexpr int NQ = PT < (KT <= 8 ? 8 : 4) ? PT : (KT <= 8 ? 8 : 4);
@@ -964,7 +1028,7 @@ slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
     SLM_CHECK(used <= n_slots && grid_f < (1ll << 31), SLM_E_SHAPE,
               "slm_split_scan: finish grid too large");
     hipLaunchKernelGGL((k_scan_finish<PT, KT, MSE>), dim3((unsigned)grid_f), dim3(256), 0, s, a,
-                       pl.CH, n_pt, slot, n_slots);
+                       pl.CH, n_pt, slot, n_slots, R);
     SLM_LAUNCHED();
   }
   return SLM_OK;
@@ -1044,14 +1108,7 @@ size_t scan_workspace_bytes(int64_t N, int n_nodes, int P, int bins, int K, int 
   if (bins == 0 || N <= 0) return 256;
   const bool mse = crit == SLM_MSE;
   const int Kc = mse ? 1 : K;
-  // the plan may pick any PT in {4, 8, 16, 32}; size for the largest footprint
-  size_t worst = 0;
-  for (int PT = 4; PT <= 32; PT <<= 1) {
-    const int64_t n_pt = (P + PT - 1) / PT;
-    worst = std::max(worst, (size_t)n_pt * slot_bytes(PT, bins, Kc, mse));
-  }
-  const int64_t n_slots = (N - 1) / chunk_min(N) + 1;
-  return (size_t)n_slots * worst + 256;
+  return slot_set_bytes(N, P, bins, Kc, mse) * slot_replicas(N, P, bins, Kc, mse) + 256;
 }
 
 slm_status launch_scan_empty_nodes(const ScanArgs &a, hipStream_t s) {

@@ -368,6 +368,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
     }
     if (lt && (st = lt->end(s))) return st;
     pa.move = t < p.T;
+    pa.bests_only = t == p.T;   // the swarm ends: only the global best is read
     pa.iter = (uint32_t)(t + 1);
     if (lt && (st = lt->begin(2, s))) return st;
     if ((st = launch_pso_step(pa, s))) return st;

@@ -214,6 +214,9 @@ struct PsoArgs {
   float *zmin_reset, *zmax_reset;
   // optional device copy of (seed, tree): lets one captured graph serve every tree
   const uint64_t *seed_tree_dev;
+  // internal: only the global best (a final evaluation whose personal bests
+  // are never read again)
+  int bests_only;
 };
 slm_status launch_pso_init(const PsoArgs &a, hipStream_t s);
 void prepare_pso_kernels(int lds_max);
