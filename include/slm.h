@@ -70,10 +70,15 @@ const char *slm_last_error(void);
  *   Z[i, p] = sum_d X[i, d] * W[j*P + p, d]   for every row i of node j,
  *   zmin[j*P + p] = min over node j's rows of Z[i, p], zmax likewise.
  *
- * X [N, D] and W [n_nodes*P, D] are both F32 or both BF16; products are
- * accumulated in FP32 on the matrix cores.  Z is FP32 in z_layout
- * (slm_z_layout; [N, P] for SLM_Z_ROWS).  Rows outside
- * every segment are not written.  For an empty node zmin = +inf, zmax = -inf.
+ * (x_dtype, w_dtype) is (F32, F32), (BF16, BF16) or (BF16, F32).  Products
+ * are accumulated in FP32 on the matrix cores: FP32 MFMA when W is F32 (a
+ * BF16 X is widened exactly), BF16 MFMA when both are BF16 (the screening
+ * projection; each 16-term block of the dot product is summed inside one
+ * MFMA, so the rounding order differs from a sequential FP32 sum).  For F32
+ * W every element of Z is the same sequence of MFMA steps whatever P and the
+ * node layout, so a column recomputed alone is bit-identical.  Z is FP32 in
+ * z_layout (slm_z_layout; [N, P] for SLM_Z_ROWS).  Rows outside every
+ * segment are not written.  For an empty node zmin = +inf, zmax = -inf.
  * A -0.0 projection is recorded in zmin/zmax as +0.0 (the two compare equal
  * and give identical bin edges).  Asynchronous.
  * ------------------------------------------------------------------------ */
@@ -149,8 +154,10 @@ slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss,
  * Eqs. (11)-(12), Alg. 1).
  *
  * (1) Bests from `loss` (the losses of the current positions): pbest_p <- x_p
- *     iff loss_p < pbest_loss_p; then p* = argmin_p loss_p (lowest p on ties)
- *     replaces the global best iff loss_p* < gbest_loss.  When split/thr are
+ *     iff loss_p < pbest_loss_p; then p* = argmin_p g_p (lowest p on ties)
+ *     replaces the global best iff g_p* < gbest_loss, where g = gloss if
+ *     given (the losses eligible for the global best, see slm_screen_merge)
+ *     and g = loss otherwise.  When split/thr are
  *     given, the winner's split and threshold are copied to gbest_split /
  *     gbest_thr.
  * (2) If move != 0: for every particle, with r1, r2 drawn per dimension from
@@ -160,19 +167,49 @@ slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss,
  *       v <- ((omega v) + ((c1 r1)(pbest - x))) + ((c2 r2)(gbest - x))
  *       x <- (x + v) / ||x + v||   (x kept if the norm is 0)
  *     each operation rounded once in FP64; W_out <- x rounded to w_dtype.
- * Shapes: x, v, pbest [n_nodes*P, D]; pbest_loss, loss [n_nodes*P];
+ * Shapes: x, v, pbest [n_nodes*P, D]; pbest_loss, loss, gloss [n_nodes*P];
  * gbest [n_nodes, D]; gbest_loss, gbest_p, node_id [n_nodes].
  * split, thr, gbest_split, gbest_thr: optional ([n_nodes*P] / [n_nodes]).
  * Asynchronous.
  * ------------------------------------------------------------------------ */
 slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss,
                         double *gbest, double *gbest_loss, int32_t *gbest_p,
-                        const double *loss, const int32_t *split, const float *thr,
+                        const double *loss, const double *gloss,
+                        const int32_t *split, const float *thr,
                         int32_t *gbest_split, float *gbest_thr,
                         const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
                         double omega, double c1, double c2, uint64_t seed, uint32_t tree,
                         uint32_t iter, int32_t move, void *W_out, int32_t w_dtype,
                         void *stream);
+
+/* ------------------------------------------------------------------------
+ * Mixed-precision screening of one swarm evaluation.  The paper scores a
+ * direction by the loss of its best threshold (Sec. III-B) and names faster
+ * projection search on high-dimensional data as open (Sec. VI); screening
+ * scores every particle on the BF16 projection (slm_project with BF16 X and
+ * W, slm_split_scan), re-scores the k best of each node on the FP32
+ * projection of the same BF16 X, and merges:
+ *
+ * slm_screen_select: sel[j*k + s] = index of the particle of node j with the
+ *   s-th smallest loss (ascending by (loss, index); -0.0 equals +0.0).
+ *   loss [n_nodes*P] f64, sel [n_nodes*k] i32, 1 <= k <= P.  Asynchronous.
+ * slm_screen_gather: W32[j*k + s, :] = float32(x[j*P + sel[j*k + s], :]),
+ *   the FP32 directions of the re-projection ([n_nodes*k, D]).  Asynchronous.
+ * slm_screen_merge: for the selected particles p = sel[j*k + s]:
+ *   loss/split/thr[j*P + p] <- loss_r/split_r/thr_r[j*k + s] (the re-scored
+ *   results, computed with P = k on W32) and gloss[j*P + p] <- loss_r; every
+ *   other particle keeps its screened loss/split/thr and gets
+ *   gloss = +inf.  gloss is the eligibility input of slm_pso_step: only
+ *   re-scored particles can become the global best.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_screen_select(const double *loss, int32_t n_nodes, int32_t P, int32_t k,
+                             int32_t *sel, void *stream);
+slm_status slm_screen_gather(const double *x, const int32_t *sel, int32_t n_nodes, int32_t P,
+                             int32_t k, int32_t D, float *W32, void *stream);
+slm_status slm_screen_merge(const int32_t *sel, const double *loss_r, const int32_t *split_r,
+                            const float *thr_r, int32_t n_nodes, int32_t P, int32_t k,
+                            double *loss, int32_t *split, float *thr, double *gloss,
+                            void *stream);
 
 /* ------------------------------------------------------------------------
  * slm_grow_tree -- one binary SLM tree (Sec. III-B, Alg. 2) grown breadth
@@ -186,6 +223,11 @@ slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss,
  * a^T x >= t go to the right child.  Leaves hold class counts or the mean.
  *
  * X [N, D] F32 (BF16 with precision = 1); target as in slm_split_scan.
+ * precision = 1 runs every evaluation as a screened one (BF16 projection of
+ * all P particles, FP32 re-scoring of the best rescore_k, see
+ * slm_screen_select); the partition projects on the FP32 split direction,
+ * exactly as the re-scoring does, so the stored threshold splits the rows
+ * the way the re-scored loss was computed.
  * Output arrays are [host], sized for max_nodes nodes; nodes are numbered in
  * breadth-first order (left child before right).  Synchronous: the host
  * reads a few bytes of frontier state back once per depth.
@@ -200,7 +242,9 @@ typedef struct {
   int32_t P;           /* particles per node                            */
   int32_t T;           /* moves (T+1 evaluations)                       */
   int32_t bins;        /* 2..256 (histogram scan); 0 = exact scan       */
-  int32_t precision;   /* 0 = FP32 projection                           */
+  int32_t precision;   /* 0 = FP32 projection; 1 = BF16 screen + FP32
+                          re-scoring of the best rescore_k per node      */
+  int32_t rescore_k;   /* 1..P, used with precision = 1                 */
   double omega, c1, c2;
   uint64_t seed;
   uint32_t tree;
@@ -225,7 +269,9 @@ typedef struct {
                           summed kernel times of [3] projections, [4] scans,
                           [5] swarm steps (ms), [6] projection launches,
                           [7] scan launches                                */
-  int64_t *sample_splits;    /* optional [1]: sum over evaluations of n_j * P */
+  int64_t *sample_splits;    /* optional [2]: [0] sum over evaluations of
+                                n_j * P (screened ones with precision = 1),
+                                [1] re-scored n_j * rescore_k (else 0)      */
 } slm_tree_out;
 
 size_t slm_grow_tree_workspace(const slm_tree_params *prm, int64_t N, int32_t D);

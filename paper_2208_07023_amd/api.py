@@ -34,7 +34,8 @@ class TreeParams(ctypes.Structure):
     _fields_ = [("crit", ctypes.c_int32), ("K", ctypes.c_int32), ("max_depth", ctypes.c_int32),
                 ("min_node", ctypes.c_int32), ("P", ctypes.c_int32), ("T", ctypes.c_int32),
                 ("bins", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("omega", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
+                ("rescore_k", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("c1", ctypes.c_double), ("c2", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("tree", ctypes.c_uint32), ("use_graph", ctypes.c_int32),
                 ("profile", ctypes.c_int32)]
 
@@ -62,8 +63,11 @@ _SIGS = {
     "slm_split_scan": ([_VP, _I32, _VP, _VP, _VP, _I32, _I32, _I64, _VP, _I32, _I32, _I32, _I32,
                         _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], _I32),
     "slm_pso_init": ([_VP] * 7 + [_VP, _I32, _I32, _I32, _U64, _U32, _VP, _I32, _VP], _I32),
-    "slm_pso_step": ([_VP] * 7 + [_VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _I32, _D, _D, _D,
-                                  _U64, _U32, _U32, _I32, _VP, _I32, _VP], _I32),
+    "slm_pso_step": ([_VP] * 7 + [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _I32, _D, _D,
+                                  _D, _U64, _U32, _U32, _I32, _VP, _I32, _VP], _I32),
+    "slm_screen_select": ([_VP, _I32, _I32, _I32, _VP, _VP], _I32),
+    "slm_screen_gather": ([_VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP], _I32),
+    "slm_screen_merge": ([_VP, _VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP], _I32),
     "slm_grow_tree_workspace": ([ctypes.POINTER(TreeParams), _I64, _I32], _SZ),
     "slm_grow_tree": ([_VP, _I32, _I64, _I32, _VP, _I32, ctypes.POINTER(TreeParams), _VP, _SZ,
                        ctypes.POINTER(TreeOut), _VP], _I32),
@@ -120,11 +124,13 @@ def _xdtype(X):
 # ------------------------------------------------------------------ project
 def project(X, W, row_off, P: int, tiled: bool = False):
     """Z = per-node X W^T, zmin/zmax [n_nodes*P] (Eq. (1)).  Z is [N, P], or
-    with tiled=True the particle-tiled [ceil(P/32), N, 32] (SLM_Z_TILED)."""
+    with tiled=True the particle-tiled [ceil(P/32), N, 32] (SLM_Z_TILED).
+    (X, W) dtypes: (float32, float32), (bfloat16, bfloat16) or (bfloat16, float32)."""
     load()
     xt = _xdtype(X)
+    wt = _xdtype(W)
     _dev(X, X.dtype, "X")
-    _dev(W, X.dtype, "W")
+    _dev(W, W.dtype, "W")
     _dev(row_off, torch.int64, "row_off")
     N, D = X.shape
     nn = row_off.numel() - 1
@@ -134,7 +140,7 @@ def project(X, W, row_off, P: int, tiled: bool = False):
         Z = torch.empty((N, P), dtype=torch.float32, device=X.device)
     zmin = torch.empty(nn * P, dtype=torch.float32, device=X.device)
     zmax = torch.empty_like(zmin)
-    _check(_lib.slm_project(_p(X), xt, N, D, _p(W), xt, _p(row_off), nn, P, _p(Z),
+    _check(_lib.slm_project(_p(X), xt, N, D, _p(W), wt, _p(row_off), nn, P, _p(Z),
                             Z_TILED if tiled else Z_ROWS, _p(zmin), _p(zmax), _stream()),
            "slm_project")
     return Z, zmin, zmax
@@ -253,17 +259,61 @@ def pso_init(sw: Swarm, seed: int, tree: int):
                              seed, tree, _p(sw.W), wt, _stream()), "slm_pso_init")
 
 
-def pso_step(sw: Swarm, loss, omega, c1, c2, seed, tree, it, move, split=None, thr=None):
+def pso_step(sw: Swarm, loss, omega, c1, c2, seed, tree, it, move, split=None, thr=None,
+             gloss=None):
     load()
     nn = sw.node_id.numel()
     wt = BF16 if sw.W.dtype == torch.bfloat16 else F32
     _dev(loss, torch.float64, "loss")
+    if gloss is not None:
+        _dev(gloss, torch.float64, "gloss")
     _check(_lib.slm_pso_step(_p(sw.x), _p(sw.v), _p(sw.pbest), _p(sw.pbest_loss), _p(sw.gbest),
-                             _p(sw.gbest_loss), _p(sw.gbest_p), _p(loss), _p(split), _p(thr),
+                             _p(sw.gbest_loss), _p(sw.gbest_p), _p(loss), _p(gloss), _p(split),
+                             _p(thr),
                              _p(sw.gbest_split) if split is not None else None,
                              _p(sw.gbest_thr) if thr is not None else None,
                              _p(sw.node_id), nn, sw.P, sw.D, omega, c1, c2, seed, tree, it,
                              int(bool(move)), _p(sw.W), wt, _stream()), "slm_pso_step")
+
+
+# ------------------------------------------------------------------ screening
+def screen_select(loss, n_nodes: int, P: int, k: int):
+    """Per node the k particles with the smallest losses, ascending by
+    (loss, index): int32 [n_nodes * k]."""
+    load()
+    _dev(loss, torch.float64, "loss")
+    sel = torch.empty(n_nodes * k, dtype=torch.int32, device=loss.device)
+    _check(_lib.slm_screen_select(_p(loss), n_nodes, P, k, _p(sel), _stream()),
+           "slm_screen_select")
+    return sel
+
+
+def screen_gather(x, sel, n_nodes: int, P: int, k: int):
+    """float32 images of the selected positions: [n_nodes * k, D]."""
+    load()
+    _dev(x, torch.float64, "x")
+    _dev(sel, torch.int32, "sel")
+    D = x.shape[1]
+    W32 = torch.empty(n_nodes * k, D, dtype=torch.float32, device=x.device)
+    _check(_lib.slm_screen_gather(_p(x), _p(sel), n_nodes, P, k, D, _p(W32), _stream()),
+           "slm_screen_gather")
+    return W32
+
+
+def screen_merge(sel, loss_r, split_r, thr_r, n_nodes: int, P: int, k: int, loss, split, thr):
+    """Re-scored results over the screened ones (in place on loss/split/thr);
+    returns gloss [n_nodes * P] (re-scored loss or +inf)."""
+    load()
+    for t, dt, nm in ((sel, torch.int32, "sel"), (loss_r, torch.float64, "loss_r"),
+                      (split_r, torch.int32, "split_r"), (thr_r, torch.float32, "thr_r"),
+                      (loss, torch.float64, "loss"), (split, torch.int32, "split"),
+                      (thr, torch.float32, "thr")):
+        _dev(t, dt, nm)
+    gloss = torch.empty(n_nodes * P, dtype=torch.float64, device=loss.device)
+    _check(_lib.slm_screen_merge(_p(sel), _p(loss_r), _p(split_r), _p(thr_r), n_nodes, P, k,
+                                 _p(loss), _p(split), _p(thr), _p(gloss), _stream()),
+           "slm_screen_merge")
+    return gloss
 
 
 # ------------------------------------------------------------------ tree
@@ -283,11 +333,13 @@ class TreeConfig:
     tree: int = 0
     use_graph: bool = False
     profile: bool = False
+    precision: int = 0          # 1 = bfloat16 screen, float32 re-scoring (X bfloat16)
+    rescore_k: int = 32
 
     def c_params(self) -> TreeParams:
         return TreeParams(self.crit, self.K, self.max_depth, self.min_node, self.P, self.T,
-                          self.bins, 0, self.omega, self.c1, self.c2, self.seed, self.tree,
-                          int(self.use_graph), int(self.profile))
+                          self.bins, self.precision, self.rescore_k, self.omega, self.c1,
+                          self.c2, self.seed, self.tree, int(self.use_graph), int(self.profile))
 
 
 _tree_ws: dict = {}
@@ -309,9 +361,10 @@ def tree_workspace(cfg: TreeConfig, N: int, D: int, device) -> torch.Tensor:
 
 
 def grow_tree(X, target, cfg: TreeConfig, workspace=None):
-    """One tree (Alg. 2); returns host numpy arrays of the nodes."""
+    """One tree (Alg. 2); returns host numpy arrays of the nodes.  X is
+    float32, or bfloat16 with cfg.precision = 1."""
     load()
-    _dev(X, torch.float32, "X")
+    _dev(X, torch.bfloat16 if cfg.precision == 1 else torch.float32, "X")
     N, D = X.shape
     if cfg.crit == MSE:
         _dev(target, torch.float64, "target")
@@ -328,12 +381,12 @@ def grow_tree(X, target, cfg: TreeConfig, workspace=None):
                leaf=np.zeros((maxn, kk), np.float64), n=np.zeros(maxn, np.int64),
                impurity=np.zeros(maxn), split_loss=np.zeros(maxn),
                depth=np.zeros(maxn, np.int32), heap=np.zeros(maxn, np.int32),
-               timing=np.zeros(8), sample_splits=np.zeros(1, np.int64))
+               timing=np.zeros(8), sample_splits=np.zeros(2, np.int64))
     out = TreeOut(maxn, 0, *[arr[k].ctypes.data for k in
                              ("w", "thr", "left", "right", "leaf", "n", "impurity", "split_loss",
                               "depth", "heap", "timing", "sample_splits")])
     prm = cfg.c_params()
-    _check(_lib.slm_grow_tree(_p(X), F32, N, D, _p(target), tt, ctypes.byref(prm), _p(ws),
+    _check(_lib.slm_grow_tree(_p(X), _xdtype(X), N, D, _p(target), tt, ctypes.byref(prm), _p(ws),
                               ws.numel(), ctypes.byref(out), _stream()), "slm_grow_tree")
     n = out.n_nodes
     res = {k: (v[:n] if k not in ("timing", "sample_splits") else v) for k, v in arr.items()}

@@ -41,7 +41,7 @@ __device__ __forceinline__ float load_x(const void *p, int64_t idx) {
   else return static_cast<const float *>(p)[idx];
 }
 
-template <int BM, int BN, int WM, int WN, bool BF16>
+template <int BM, int BN, int WM, int WN, bool XB, bool WB>
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
   static_assert(WM * WN == 4, "4 waves per work-group");
   constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         const int r = e / KC, c = e - r * KC;
         const int64_t row = r0 + r;
         val[u] = (e < BM * KC && c < kc && row >= it.lo && row < it.hi)
-                     ? load_x<BF16>(a.X, row * D + k0 + c) : 0.f;
+                     ? load_x<XB>(a.X, row * D + k0 + c) : 0.f;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         const int e = e0 + u * 256;
         const int r = e / KC, c = e - r * KC;
         const int p = p0 + r;
-        val[u] = (e < BN * KC && c < kc && p < P) ? load_x<BF16>(a.W, (wbase + p) * D + k0 + c) : 0.f;
+        val[u] = (e < BN * KC && c < kc && p < P) ? load_x<WB>(a.W, (wbase + p) * D + k0 + c) : 0.f;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -225,7 +225,7 @@ __device__ __forceinline__ void load_run(const void *base, int64_t row, int D, i
   }
 }
 
-template <int FN, int WAVES, int KSP, bool BF16, bool VEC>
+template <int FN, int WAVES, int KSP, bool XB, bool WB, bool VEC>
 __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int64_t RB,
                                                                int blocks_per_pt) {
   constexpr int PTILE = 32 * FN * WAVES;
@@ -273,8 +273,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
   };
 
   float acur[KSP], anext[KSP];
-  load_run<KSP, BF16, VEC>(a.X, cur.lo + li < cur.hi ? cur.lo + li : cur.hi - 1, D, k0,
-                           cur.lo + li < cur.hi, acur);
+  load_run<KSP, XB, VEC>(a.X, cur.lo + li < cur.hi ? cur.lo + li : cur.hi - 1, D, k0,
+                         cur.lo + li < cur.hi, acur);
   while (cur.j >= 0) {
     if (cur.j != node_c) {
       flush();
@@ -283,15 +283,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
 #pragma unroll
       for (int f = 0; f < FN; ++f) {
         const int p = pw + f * 32 + li;
-        load_run<KSP, BF16, VEC>(a.W, wb + (p < P ? p : P - 1), D, k0, p < P, bfrag[f]);
+        load_run<KSP, WB, VEC>(a.W, wb + (p < P ? p : P - 1), D, k0, p < P, bfrag[f]);
         mn[f] = __builtin_huge_valf();
         mx[f] = -__builtin_huge_valf();
       }
     }
     const SubTile nxt = next_subtile(a, cur.j, cur.hi, r_end);
     if (nxt.j >= 0)
-      load_run<KSP, BF16, VEC>(a.X, nxt.lo + li < nxt.hi ? nxt.lo + li : nxt.hi - 1, D, k0,
-                               nxt.lo + li < nxt.hi, anext);
+      load_run<KSP, XB, VEC>(a.X, nxt.lo + li < nxt.hi ? nxt.lo + li : nxt.hi - 1, D, k0,
+                             nxt.lo + li < nxt.hi, anext);
     f32x16 acc[FN];
 #pragma unroll
     for (int f = 0; f < FN; ++f) acc[f] = f32x16{};
@@ -326,13 +326,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
   flush();
 }
 
+// X float32 or bfloat16, W float32 (both widened exactly to float32)
 template <int FN, int WAVES, int KSP, bool VEC>
 slm_status launch_short_k(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
-  if (a.bf16)
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true, VEC>), dim3((unsigned)grid),
+  if (a.x_bf16)
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true, false, VEC>), dim3((unsigned)grid),
                        dim3(64 * WAVES), 0, s, a, RB, bpp);
   else
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, VEC>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, false, VEC>), dim3((unsigned)grid),
                        dim3(64 * WAVES), 0, s, a, RB, bpp);
   SLM_LAUNCHED();
   return SLM_OK;
@@ -365,11 +366,175 @@ slm_status launch_short(const ProjectArgs &a, hipStream_t s) {
   const int64_t grid = bpp * n_pt;
   if (grid == 0) return SLM_OK;
   SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_project: grid too large");
-  const size_t es = a.bf16 ? 8 : 16;   // bytes of one vector load
+  const size_t es = a.x_bf16 ? 8 : 16;   // bytes of one vector load of X (W is float32)
   const bool vec = a.D % 4 == 0 && reinterpret_cast<uintptr_t>(a.X) % es == 0 &&
-                   reinterpret_cast<uintptr_t>(a.W) % es == 0;
+                   reinterpret_cast<uintptr_t>(a.W) % 16 == 0;
   if (vec) return launch_short_v<FN, WAVES, true>(a, RB, (int)bpp, grid, s);
   return launch_short_v<FN, WAVES, false>(a, RB, (int)bpp, grid, s);
+}
+
+// bfloat16 projection on the bfloat16 matrix cores (v_mfma_f32_32x32x16_bf16,
+// float32 accumulation): X [N, D] and W [n_nodes P, D] both bfloat16.
+// A work-group computes a BM x BN tile of Z (4 waves of 64 x 64); tiles of BKC
+// dimensions of X and W are staged in LDS as bfloat16 (rows padded to 144
+// bytes, 16-byte aligned) and each lane feeds the MFMA 8 consecutive
+// dimensions of its row straight from one 16-byte LDS read.  Work-groups are
+// ordered so that the particle tiles of one row tile run on one XCD (its L2
+// serves the X tile to all of them).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int BKC = 64;          // dimensions staged per LDS round
+constexpr int BST = BKC + 8;     // LDS row stride in bfloat16 elements
+
+// 8 consecutive bfloat16 of one row starting at dimension k (k % 8 == 0),
+// zeros past D.  VEC: D % 8 == 0 and 16-byte aligned rows.
+template <bool VEC>
+__device__ __forceinline__ uint4 load8_bf16(const uint16_t *row, int k, int D) {
+  if constexpr (VEC) {
+    return *reinterpret_cast<const uint4 *>(row + k);
+  } else {
+    uint32_t w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int k0 = k + 2 * h, k1 = k0 + 1;
+      const uint32_t lo = k0 < D ? row[k0] : 0u;
+      const uint32_t hi = k1 < D ? row[k1] : 0u;
+      w[h] = lo | (hi << 16);
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+template <int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256) void k_project_bf16(ProjectArgs a, int n_pt, int64_t n_items) {
+  constexpr int WM = 2, WN = 2, TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
+  constexpr int CPR = BKC / 8;                       // 16-byte chunks per staged row
+  constexpr int XPT = BM * CPR / 256, WPT = BN * CPR / 256;
+  static_assert(FM >= 1 && FN >= 1 && XPT >= 1 && WPT >= 1, "tile shape");
+  __shared__ __align__(16) uint16_t Xs[BM * BST];
+  __shared__ __align__(16) uint16_t Ws[BN * BST];
+
+  const int64_t bid = blockIdx.x;
+  const int64_t local = bid >> 3;
+  const int64_t v = (local / n_pt) * 8 + (bid & 7);
+  const int pt = (int)(local % n_pt);
+  if (v >= n_items) return;
+  const Item it = find_item(a.beg, a.end, a.n_nodes, a.N, BM, v);
+  if (it.node < 0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int li = lane & 31, kh = lane >> 5;
+  const int64_t r0 = (it.lo / BM) * BM;
+  const int p0 = pt * BN;
+  const int D = a.D, P = a.P;
+  const int64_t wbase = (int64_t)it.node * P;
+  const uint16_t *X = static_cast<const uint16_t *>(a.X);
+  const uint16_t *W = static_cast<const uint16_t *>(a.W);
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int f = 0; f < FN; ++f) acc[i][f] = f32x16{};
+
+  for (int k0 = 0; k0 < D; k0 += BKC) {
+    uint4 xv[XPT], wv[WPT];
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int e = tid + u * 256, r = e / CPR, c = (e % CPR) * 8;
+      const int64_t row = r0 + r;
+      const bool in = row >= it.lo && row < it.hi && k0 + c < D;
+      xv[u] = in ? load8_bf16<VEC>(X + row * D, k0 + c, D) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int e = tid + u * 256, r = e / CPR, c = (e % CPR) * 8;
+      const int p = p0 + r;
+      const bool in = p < P && k0 + c < D;
+      wv[u] = in ? load8_bf16<VEC>(W + (wbase + p) * D, k0 + c, D) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int e = tid + u * 256;
+      *reinterpret_cast<uint4 *>(&Xs[(e / CPR) * BST + (e % CPR) * 8]) = xv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int e = tid + u * 256;
+      *reinterpret_cast<uint4 *>(&Ws[(e / CPR) * BST + (e % CPR) * 8]) = wv[u];
+    }
+    lds_barrier();
+    const int ksteps = min(BKC, D - k0 + 15) / 16;
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int kk = ks * 16 + kh * 8;
+      bf16x8 af[FM], bfr[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        af[i] = __builtin_bit_cast(bf16x8,
+                                   *reinterpret_cast<const uint4 *>(&Xs[(wm * TM + i * 32 + li) * BST + kk]));
+#pragma unroll
+      for (int f = 0; f < FN; ++f)
+        bfr[f] = __builtin_bit_cast(bf16x8,
+                                    *reinterpret_cast<const uint4 *>(&Ws[(wn * TN + f * 32 + li) * BST + kk]));
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int f = 0; f < FN; ++f)
+          acc[i][f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[f], acc[i][f], 0, 0, 0);
+    }
+    lds_barrier();
+  }
+
+  // Epilogue: lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4 and
+  // column l%32 of each 32x32 block.
+  const bool do_mm = a.zmin != nullptr;
+#pragma unroll
+  for (int f = 0; f < FN; ++f) {
+    const int p = p0 + wn * TN + f * 32 + li;
+    float mn = __builtin_huge_valf(), mx = -__builtin_huge_valf();
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rr = wm * TM + i * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        const int64_t row = r0 + rr;
+        if (p < P && row >= it.lo && row < it.hi) {
+          const float z = acc[i][f][r];
+          a.Z[z_col(a.zl, p) + row * a.zl.rs] = z;
+          mn = fminf(mn, z);
+          mx = fmaxf(mx, z);
+        }
+      }
+    }
+    if (do_mm) {
+      mn = fminf(mn, __shfl_xor(mn, 32));
+      mx = fmaxf(mx, __shfl_xor(mx, 32));
+      if (lane < 32 && p < P && mn <= mx) {
+        atomic_min_f32(&a.zmin[wbase + p], mn);
+        atomic_max_f32(&a.zmax[wbase + p], mx);
+      }
+    }
+  }
+}
+
+template <int BM, int BN>
+slm_status launch_bf16(const ProjectArgs &a, hipStream_t s) {
+  const int64_t items = num_items(a.n_nodes, a.N, BM);
+  const int64_t n_pt = (a.P + BN - 1) / BN;
+  const int64_t grid = (items + 7) / 8 * 8 * n_pt;
+  if (items == 0) return SLM_OK;
+  SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_project: grid of %lld blocks too large",
+            (long long)grid);
+  const bool vec = a.D % 8 == 0 && reinterpret_cast<uintptr_t>(a.X) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(a.W) % 16 == 0;
+  if (vec)
+    hipLaunchKernelGGL((k_project_bf16<BM, BN, true>), dim3((unsigned)grid), dim3(256), 0, s, a,
+                       (int)n_pt, items);
+  else
+    hipLaunchKernelGGL((k_project_bf16<BM, BN, false>), dim3((unsigned)grid), dim3(256), 0, s, a,
+                       (int)n_pt, items);
+  SLM_LAUNCHED();
+  return SLM_OK;
 }
 
 __global__ void k_fill_minmax(float *zmin, float *zmax, int64_t n) {
@@ -388,10 +553,12 @@ slm_status launch_cfg(const ProjectArgs &a, hipStream_t s) {
   if (grid == 0) return SLM_OK;
   SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_project: grid of %lld blocks too large",
             (long long)grid);
-  if (a.bf16)
-    hipLaunchKernelGGL((k_project<BM, BN, WM, WN, true>), dim3((unsigned)grid), dim3(256), 0, s, a);
+  if (a.x_bf16)
+    hipLaunchKernelGGL((k_project<BM, BN, WM, WN, true, false>), dim3((unsigned)grid), dim3(256), 0,
+                       s, a);
   else
-    hipLaunchKernelGGL((k_project<BM, BN, WM, WN, false>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_project<BM, BN, WM, WN, false, false>), dim3((unsigned)grid), dim3(256),
+                       0, s, a);
   SLM_LAUNCHED();
   return SLM_OK;
 }
@@ -407,6 +574,11 @@ slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s
 }
 
 slm_status launch_project(const ProjectArgs &a, hipStream_t s) {
+  // both bfloat16: bfloat16 matrix cores
+  if (a.x_bf16 && a.w_bf16) {
+    if (a.P > 64) return launch_bf16<128, 128>(a, s);
+    return launch_bf16<128, 64>(a, s);
+  }
   // D <= 64: register-resident directions, 256 / 128 / 32 particles per work-group.
   if (a.D <= 64) {
     if (a.P > 128) return launch_short<2, 4>(a, s);

@@ -118,8 +118,9 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_init(PsoArgs a) {
 }
 
 // (1) of the step: one work-group per node.  The argmin of the current losses
-// (lowest p on ties) replaces the global best iff strictly better; the
-// position is copied before the move kernel changes x.  The personal bests
+// (or of the losses eligible for the global best, gloss, when a screened
+// evaluation gives them; lowest p on ties) replaces the global best iff
+// strictly better; the position is copied before the move kernel changes x.  The personal bests
 // are updated by the move kernel, where every particle's threads are.
 constexpr int BEST_WG = 256;
 constexpr int PMAX_STEP = 4096;
@@ -133,8 +134,9 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
   const int64_t base = (int64_t)j * P;
   double bl = __builtin_huge_val();
   int bp = 0x7fffffff;
+  const double *gl = a.gloss ? a.gloss : a.loss;
   for (int p = tid; p < P; p += BEST_WG) {
-    const double l = a.loss[base + p];
+    const double l = gl[base + p];
     if (l < bl) {
       bl = l;
       bp = p;

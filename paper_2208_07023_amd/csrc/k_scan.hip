@@ -1018,6 +1018,8 @@ slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
   const size_t slot = slot_bytes(PT, a.bins, Kc, MSE);
   const int64_t n_slots = (a.N - 1) / chunk_min(a.N) + 1;
   const int R = slot_replicas(a.N, a.P, a.bins, Kc, MSE);
+  SLM_CHECK(slot_set_bytes(a.N, a.P, a.bins, Kc, MSE) * R <= a.ws_bytes, SLM_E_NOMEM,
+            "slm_split_scan: workspace of %zu bytes too small for this launch", a.ws_bytes);
   hipLaunchKernelGGL((k_scan_hist<PT, KT, MSE>), dim3((unsigned)grid), dim3(HIST_WG), lds, s, a, pl.CH,
                      n_pt, pl.G, total, slot, n_slots, R);
   SLM_LAUNCHED();

@@ -109,6 +109,30 @@ __global__ void k_part_offsets(PartArgs a) {
   a.n_left[j] = a.do_split[j] ? L : (r.hi - r.lo);
 }
 
+// Rows r0 .. r0+nin-1 of X to rows dest[0 .. nin-1] of Xn, element by element
+// in row-major order: 8 loads in flight per thread, then the stores.
+template <typename T>
+__device__ __forceinline__ void copy_rows(const T *X, T *Xn, int64_t r0, int64_t nin, int D,
+                                          const int64_t *dest, int tid) {
+  const int ne = (int)nin * D;
+  for (int e0 = tid; e0 < ne; e0 += 8 * WG) {
+    T vals[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * WG;
+      vals[u] = e < ne ? X[r0 * D + e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * WG;
+      if (e < ne) {
+        const int q = e / D, c = e - q * D;
+        Xn[dest[q] * D + c] = vals[u];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(WG) void k_part_scatter(PartArgs a) {
   __shared__ int64_t dest[WG];
   __shared__ uint32_t wl[WG / 64];
@@ -172,24 +196,12 @@ __global__ __launch_bounds__(WG) void k_part_scatter(PartArgs a) {
     }
     __syncthreads();
     // coalesced copy of the round's rows to their destinations
-    // 8 loads in flight per thread, then the stores
-    const int ne = (int)nin * a.D;
-    for (int e0 = tid; e0 < ne; e0 += 8 * WG) {
-      float vals[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * WG;
-        vals[u] = e < ne ? a.X[r0 * a.D + e] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * WG;
-        if (e < ne) {
-          const int q = e / a.D, c = e - q * a.D;
-          a.Xn[dest[q] * a.D + c] = vals[u];
-        }
-      }
-    }
+    if (a.x_bf16)
+      copy_rows(static_cast<const uint16_t *>(a.X), static_cast<uint16_t *>(a.Xn), r0, nin, a.D,
+                dest, tid);
+    else
+      copy_rows(static_cast<const float *>(a.X), static_cast<float *>(a.Xn), r0, nin, a.D, dest,
+                tid);
     if (in) {
       if (a.lab) a.labn[dest[tid]] = a.lab[r];
       else a.yn[dest[tid]] = a.y[r];

@@ -66,6 +66,10 @@ struct TreeWS {
   int64_t *beg, *end, *n_left, *off_left, *off_right;
   uint64_t *seed_tree;
   uint32_t *cnt_left;
+  // screening (precision = 1): selection, float32 re-projection and its scan
+  int32_t *sel, *split_r;
+  float *W32, *Zr, *zmin_r, *zmax_r, *thr_r;
+  double *loss_r, *gloss;
   TreeStats st;
   void *scan_ws;
   size_t scan_ws_bytes;
@@ -100,7 +104,7 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base) {
   w.gbest_p = c.take<int32_t>((size_t)F);
   w.gbest_split = c.take<int32_t>((size_t)F);
   w.gbest_thr = c.take<float>((size_t)F);
-  w.gW = c.take<char>((size_t)F * D * xb);
+  w.gW = c.take<float>((size_t)F * D);     // float32 split directions of the partition
   w.beg = c.take<int64_t>((size_t)F);
   w.end = c.take<int64_t>((size_t)F);
   w.node_id = c.take<int32_t>((size_t)F);
@@ -111,6 +115,18 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base) {
   w.cnt_left = c.take<uint32_t>((size_t)items);
   w.off_left = c.take<int64_t>((size_t)items);
   w.off_right = c.take<int64_t>((size_t)items);
+  if (p.precision == 1) {
+    const int k = p.rescore_k;
+    w.sel = c.take<int32_t>((size_t)F * k);
+    w.W32 = c.take<float>((size_t)F * k * D);
+    w.Zr = c.take<float>((size_t)N * ((k + 31) / 32 * 32));   // particle-tiled
+    w.zmin_r = c.take<float>((size_t)F * k);
+    w.zmax_r = c.take<float>((size_t)F * k);
+    w.loss_r = c.take<double>((size_t)F * k);
+    w.split_r = c.take<int32_t>((size_t)F * k);
+    w.thr_r = c.take<float>((size_t)F * k);
+    w.gloss = c.take<double>((size_t)F * p.P);
+  }
   w.st.counts = c.take<uint32_t>((size_t)2 * F * Kc);
   w.st.cnt = c.take<uint32_t>((size_t)2 * F);
   w.st.s1 = c.take<double>((size_t)2 * F);
@@ -118,6 +134,9 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base) {
   w.st.ymin = c.take<unsigned long long>((size_t)2 * F);
   w.st.ymax = c.take<unsigned long long>((size_t)2 * F);
   w.scan_ws_bytes = p.bins ? scan_workspace_bytes(N, (int)F, p.P, p.bins, p.K, p.crit) : 256;
+  if (p.bins && p.precision == 1)   // the re-scoring scan runs with rescore_k particles
+    w.scan_ws_bytes = std::max(w.scan_ws_bytes,
+                               scan_workspace_bytes(N, (int)F, p.rescore_k, p.bins, p.K, p.crit));
   w.scan_ws = c.take<char>(w.scan_ws_bytes);
   w.total = c.off + 256;
   return w;
@@ -141,8 +160,11 @@ slm_status check_tree_params(const slm_tree_params *p, int64_t N, int32_t D) {
   SLM_CHECK(p->max_depth >= 0 && p->max_depth <= 30, SLM_E_SHAPE,
             "slm_grow_tree: max_depth = %d out of range", p->max_depth);
   SLM_CHECK(p->min_node >= 1, SLM_E_SHAPE, "slm_grow_tree: min_node must be >= 1");
-  SLM_CHECK(p->precision == 0, SLM_E_UNSUPPORTED,
-            "slm_grow_tree: precision %d not supported by this build", p->precision);
+  SLM_CHECK(p->precision == 0 || p->precision == 1, SLM_E_INVALID,
+            "slm_grow_tree: precision %d (0 = float32, 1 = bfloat16 screen)", p->precision);
+  if (p->precision == 1)
+    SLM_CHECK(p->rescore_k >= 1 && p->rescore_k <= p->P, SLM_E_SHAPE,
+              "slm_grow_tree: rescore_k = %d not in [1, P]", p->rescore_k);
   return SLM_OK;
 }
 
@@ -340,13 +362,16 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pa.gbest_split = w.gbest_split; pa.gbest_thr = w.gbest_thr;
   pa.node_id = w.node_id; pa.n_nodes = na; pa.P = p.P; pa.D = D;
   pa.omega = p.omega; pa.c1 = p.c1; pa.c2 = p.c2; pa.seed = p.seed; pa.tree = p.tree;
-  pa.W_out = w.W; pa.w_bf16 = 0;
+  const bool scr = p.precision == 1;
+  pa.W_out = w.W; pa.w_bf16 = scr;
+  pa.gloss = scr ? w.gloss : nullptr;
   pa.zmin_reset = w.zmin; pa.zmax_reset = w.zmax;
   pa.seed_tree_dev = w.seed_tree;
   slm_status st = launch_pso_init(pa, s);
   if (st) return st;
   ProjectArgs pr{};
-  pr.X = Xc; pr.bf16 = 0; pr.N = N; pr.D = D; pr.W = w.W; pr.beg = w.beg; pr.end = w.end;
+  pr.X = Xc; pr.x_bf16 = scr; pr.w_bf16 = scr; pr.N = N; pr.D = D; pr.W = w.W; pr.beg = w.beg;
+  pr.end = w.end;
   pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
   pr.zl = zlayout_of(1, N, p.P);
   ScanArgs sa{};
@@ -356,17 +381,40 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   sa.K = p.K; sa.N = N; sa.beg = w.beg; sa.end = w.end; sa.n_nodes = na; sa.P = p.P;
   sa.bins = p.bins; sa.crit = p.crit; sa.best_split = w.split; sa.best_loss = w.loss;
   sa.threshold = w.thr; sa.ws = w.scan_ws; sa.ws_bytes = w.scan_ws_bytes;
+  // float32 re-scoring of the screened evaluation's best rescore_k particles
+  const int k = p.rescore_k;
+  ProjectArgs prr = pr;
+  ScanArgs sar = sa;
+  if (scr) {
+    prr.x_bf16 = 1; prr.w_bf16 = 0; prr.W = w.W32; prr.P = k; prr.Z = w.Zr;
+    prr.zmin = w.zmin_r; prr.zmax = w.zmax_r; prr.zl = zlayout_of(1, N, k);
+    sar.Z = w.Zr; sar.zl = prr.zl; sar.zmin = w.zmin_r; sar.zmax = w.zmax_r; sar.P = k;
+    sar.best_split = w.split_r; sar.best_loss = w.loss_r; sar.threshold = w.thr_r;
+  }
+  auto scan = [&](const ScanArgs &x) {
+    return p.bins ? launch_scan_hist(x, s) : launch_scan_exact(x, 8192, s);
+  };
   for (int t = 0; t <= p.T; ++t) {
     if (lt && (st = lt->begin(0, s))) return st;
     if ((st = launch_project(pr, s))) return st;
     if (lt && (st = lt->end(s))) return st;
     if (lt && (st = lt->begin(1, s))) return st;
-    if (p.bins) {
-      if ((st = launch_scan_hist(sa, s))) return st;
-    } else {
-      if ((st = launch_scan_exact(sa, 8192, s))) return st;
-    }
+    if ((st = scan(sa))) return st;
     if (lt && (st = lt->end(s))) return st;
+    if (scr) {
+      if ((st = launch_screen_select(w.loss, na, p.P, k, w.sel, s))) return st;
+      if ((st = launch_screen_gather(w.x, w.sel, na, p.P, k, D, w.W32, s))) return st;
+      if ((st = launch_fill_minmax(w.zmin_r, w.zmax_r, (int64_t)na * k, s))) return st;
+      if (lt && (st = lt->begin(0, s))) return st;
+      if ((st = launch_project(prr, s))) return st;
+      if (lt && (st = lt->end(s))) return st;
+      if (lt && (st = lt->begin(1, s))) return st;
+      if ((st = scan(sar))) return st;
+      if (lt && (st = lt->end(s))) return st;
+      if ((st = launch_screen_merge(w.sel, w.loss_r, w.split_r, w.thr_r, na, p.P, k, w.loss,
+                                    w.split, w.thr, w.gloss, s)))
+        return st;
+    }
     pa.move = t < p.T;
     pa.bests_only = t == p.T;   // the swarm ends: only the global best is read
     pa.iter = (uint32_t)(t + 1);
@@ -383,7 +431,8 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
   key.k = {(uint64_t)(uintptr_t)Xc, (uint64_t)(uintptr_t)tc, (uint64_t)(uintptr_t)w.Z,
            (uint64_t)N, (uint64_t)D, (uint64_t)na, (uint64_t)p.P, (uint64_t)p.T,
            (uint64_t)p.bins, (uint64_t)p.crit, (uint64_t)p.K,
-           (uint64_t)(uintptr_t)w.scan_ws};
+           (uint64_t)(uintptr_t)w.scan_ws, (uint64_t)p.precision,
+           (uint64_t)(p.precision == 1 ? p.rescore_k : 0)};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -447,8 +496,10 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, con
   SLM_CHECK(D >= 1 && D <= DMAX, SLM_E_SHAPE, "slm_project: D = %d out of range", D);
   SLM_CHECK(P >= 1 && P <= PMAX, SLM_E_SHAPE, "slm_project: P = %d out of range", P);
   SLM_CHECK(n_nodes >= 0, SLM_E_SHAPE, "slm_project: n_nodes < 0");
-  SLM_CHECK(x_dtype == w_dtype && (x_dtype == SLM_F32 || x_dtype == SLM_BF16), SLM_E_DTYPE,
-            "slm_project: X and W must both be F32 or both BF16");
+  SLM_CHECK((x_dtype == SLM_F32 || x_dtype == SLM_BF16) &&
+                (w_dtype == SLM_F32 || w_dtype == SLM_BF16) &&
+                !(x_dtype == SLM_F32 && w_dtype == SLM_BF16),
+            SLM_E_DTYPE, "slm_project: (X, W) must be (F32, F32), (BF16, BF16) or (BF16, F32)");
   SLM_CHECK(z_layout == SLM_Z_ROWS || z_layout == SLM_Z_TILED, SLM_E_INVALID,
             "slm_project: bad Z layout %d", z_layout);
   if (N == 0 || n_nodes == 0) return SLM_OK;
@@ -456,7 +507,8 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, con
   slm_status st = launch_fill_minmax(zmin, zmax, (int64_t)n_nodes * P, S(stream));
   if (st) return st;
   ProjectArgs a{};
-  a.X = X; a.bf16 = x_dtype == SLM_BF16; a.N = N; a.D = D; a.W = W;
+  a.X = X; a.x_bf16 = x_dtype == SLM_BF16; a.w_bf16 = w_dtype == SLM_BF16; a.N = N; a.D = D;
+  a.W = W;
   a.beg = row_off; a.end = row_off + 1; a.n_nodes = n_nodes; a.P = P;
   a.Z = Z; a.zl = zlayout_of(z_layout == SLM_Z_TILED, N, P); a.zmin = zmin; a.zmax = zmax;
   return launch_project(a, S(stream));
@@ -557,7 +609,7 @@ slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss,
 
 slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,
                         double *gbest_loss, int32_t *gbest_p, const double *loss,
-                        const int32_t *split, const float *thr, int32_t *gbest_split,
+                        const double *gloss, const int32_t *split, const float *thr, int32_t *gbest_split,
                         float *gbest_thr, const int32_t *node_id, int32_t n_nodes, int32_t P,
                         int32_t D, double omega, double c1, double c2, uint64_t seed,
                         uint32_t tree, uint32_t iter, int32_t move, void *W_out, int32_t w_dtype,
@@ -580,12 +632,47 @@ slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss,
   if (pst) return pst;
   PsoArgs a{};
   a.x = x; a.v = v; a.pbest = pbest; a.pbest_loss = pbest_loss; a.gbest = gbest;
-  a.gbest_loss = gbest_loss; a.gbest_p = gbest_p; a.loss = loss; a.split = split; a.thr = thr;
+  a.gbest_loss = gbest_loss; a.gbest_p = gbest_p; a.loss = loss; a.gloss = gloss;
+  a.split = split; a.thr = thr;
   a.gbest_split = gbest_split; a.gbest_thr = gbest_thr; a.node_id = node_id;
   a.n_nodes = n_nodes; a.P = P; a.D = D; a.omega = omega; a.c1 = c1; a.c2 = c2;
   a.seed = seed; a.tree = tree; a.iter = iter; a.move = move;
   a.W_out = W_out; a.w_bf16 = w_dtype == SLM_BF16;
   return launch_pso_step(a, S(stream));
+}
+
+slm_status slm_screen_select(const double *loss, int32_t n_nodes, int32_t P, int32_t k,
+                             int32_t *sel, void *stream) {
+  clear_error();
+  SLM_CHECK(n_nodes >= 0 && P >= 1 && P <= PMAX && k >= 1 && k <= P, SLM_E_SHAPE,
+            "slm_screen_select: need n_nodes >= 0 and 1 <= k <= P <= %d", PMAX);
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(loss && sel, SLM_E_INVALID, "slm_screen_select: NULL pointer");
+  return launch_screen_select(loss, n_nodes, P, k, sel, S(stream));
+}
+
+slm_status slm_screen_gather(const double *x, const int32_t *sel, int32_t n_nodes, int32_t P,
+                             int32_t k, int32_t D, float *W32, void *stream) {
+  clear_error();
+  SLM_CHECK(n_nodes >= 0 && P >= 1 && P <= PMAX && k >= 1 && k <= P && D >= 1 && D <= DMAX,
+            SLM_E_SHAPE, "slm_screen_gather: bad sizes");
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(x && sel && W32, SLM_E_INVALID, "slm_screen_gather: NULL pointer");
+  return launch_screen_gather(x, sel, n_nodes, P, k, D, W32, S(stream));
+}
+
+slm_status slm_screen_merge(const int32_t *sel, const double *loss_r, const int32_t *split_r,
+                            const float *thr_r, int32_t n_nodes, int32_t P, int32_t k,
+                            double *loss, int32_t *split, float *thr, double *gloss,
+                            void *stream) {
+  clear_error();
+  SLM_CHECK(n_nodes >= 0 && P >= 1 && P <= PMAX && k >= 1 && k <= P, SLM_E_SHAPE,
+            "slm_screen_merge: bad sizes");
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(sel && loss_r && split_r && thr_r && loss && split && thr && gloss, SLM_E_INVALID,
+            "slm_screen_merge: NULL pointer");
+  return launch_screen_merge(sel, loss_r, split_r, thr_r, n_nodes, P, k, loss, split, thr, gloss,
+                             S(stream));
 }
 
 slm_status slm_predict(const float *w, const float *thr, const int32_t *left,
@@ -612,7 +699,8 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
   if (st) return st;
   const slm_tree_params &p = *prm;
   const bool mse = p.crit == SLM_MSE;
-  SLM_CHECK(x_dtype == SLM_F32, SLM_E_DTYPE, "slm_grow_tree: X must be F32");
+  SLM_CHECK(x_dtype == (p.precision == 1 ? SLM_BF16 : SLM_F32), SLM_E_DTYPE,
+            "slm_grow_tree: X must be F32 (precision 0) or BF16 (precision 1)");
   SLM_CHECK(t_dtype == (mse ? SLM_F64 : SLM_I32), SLM_E_DTYPE,
             "slm_grow_tree: target dtype does not match the criterion");
   SLM_CHECK(X && target && workspace && out, SLM_E_INVALID, "slm_grow_tree: NULL pointer");
@@ -635,7 +723,7 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
   const bool prof = p.profile && timing;
   LaunchTimes lt;
   if ((st = tm_all.start(timing ? &timing[0] : nullptr, s))) return st;
-  int64_t ss = 0;
+  int64_t ss = 0, ss_r = 0;
 
   // scan accumulators start (and stay) zero; RNG key and tree id on the
   // device; root statistics
@@ -687,7 +775,7 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
   std::vector<double> hgl(F), hgb((size_t)F * D);
   std::vector<float> hgt(F), hgw((size_t)F * D);
 
-  for (int depth = 0; !frontier.empty(); ++depth) {
+  while (!frontier.empty()) {
     std::vector<HNode> active;
     for (const HNode &f : frontier)
       if (f.depth < p.max_depth && f.end - f.beg >= p.min_node && f.impure) active.push_back(f);
@@ -700,6 +788,7 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
       he[j] = active[j].end;
       hid[j] = active[j].heap;
       ss += (active[j].end - active[j].beg) * (int64_t)p.P * (p.T + 1);
+      if (p.precision == 1) ss_r += (active[j].end - active[j].beg) * (int64_t)p.rescore_k * (p.T + 1);
     }
     SLM_HIP(hipMemcpyAsync(w.beg, hb.data(), na * 8, hipMemcpyHostToDevice, s));
     SLM_HIP(hipMemcpyAsync(w.end, he.data(), na * 8, hipMemcpyHostToDevice, s));
@@ -735,13 +824,14 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
     SLM_HIP(hipMemcpyAsync(w.do_split, hsplit.data(), na * 4, hipMemcpyHostToDevice, s));
     SLM_HIP(hipMemcpyAsync(w.gW, hgw.data(), (size_t)na * D * 4, hipMemcpyHostToDevice, s));
     ProjectArgs pr{};
-    pr.X = Xc; pr.bf16 = 0; pr.N = N; pr.D = D; pr.W = w.gW; pr.beg = w.beg; pr.end = w.end;
+    pr.X = Xc; pr.x_bf16 = p.precision == 1; pr.w_bf16 = 0; pr.N = N; pr.D = D; pr.W = w.gW;
+    pr.beg = w.beg; pr.end = w.end;
     pr.n_nodes = na; pr.P = 1; pr.Z = w.zsel; pr.zmin = nullptr; pr.zmax = nullptr;
     pr.zl = zlayout_of(0, N, 1);
     if ((st = launch_project(pr, s))) return st;
     if ((st = clear_stats(w, 2 * na, p.crit, Kc, s))) return st;
     PartArgs pa{};
-    pa.X = static_cast<const float *>(Xc); pa.Xn = static_cast<float *>(Xbuf[nb]);
+    pa.X = Xc; pa.Xn = Xbuf[nb]; pa.x_bf16 = p.precision == 1;
     pa.lab = mse ? nullptr : static_cast<const int32_t *>(tc);
     pa.labn = mse ? nullptr : static_cast<int32_t *>(tbuf[nb]);
     pa.y = mse ? static_cast<const double *>(tc) : nullptr;
@@ -784,7 +874,10 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
   SLM_HIP(hipStreamSynchronize(s));
   if ((st = tm_all.stop(s))) return st;
   out->n_nodes = nn;
-  if (out->sample_splits) out->sample_splits[0] = ss;
+  if (out->sample_splits) {
+    out->sample_splits[0] = ss;
+    out->sample_splits[1] = ss_r;
+  }
   return SLM_OK;
 }
 

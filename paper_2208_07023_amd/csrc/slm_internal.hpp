@@ -156,7 +156,9 @@ __host__ __device__ __forceinline__ ZLayout zlayout_of(int tiled, int64_t N, int
 
 struct ProjectArgs {
   const void *X;
-  int bf16;
+  int x_bf16;        // X stored as bfloat16 (else float32)
+  int w_bf16;        // W stored as bfloat16 (else float32); both bfloat16 runs
+                     // the bfloat16 matrix cores, otherwise float32 ones
   int64_t N;
   int D;
   const void *W;
@@ -164,7 +166,6 @@ struct ProjectArgs {
   int n_nodes, P;
   float *Z;
   float *zmin, *zmax;
-  int w_row_stride;  // rows of W per node (P normally)
   ZLayout zl;
 };
 slm_status launch_project(const ProjectArgs &a, hipStream_t s);
@@ -198,6 +199,7 @@ struct PsoArgs {
   double *x, *v, *pbest, *pbest_loss, *gbest, *gbest_loss;
   int32_t *gbest_p;
   const double *loss;
+  const double *gloss;   // optional: losses eligible for the global best (else loss)
   const int32_t *split;
   const float *thr;
   int32_t *gbest_split;
@@ -222,6 +224,45 @@ slm_status launch_pso_init(const PsoArgs &a, hipStream_t s);
 void prepare_pso_kernels(int lds_max);
 slm_status launch_pso_step(const PsoArgs &a, hipStream_t s);
 
+// mixed-precision screening (bfloat16 screen, float32 re-score)
+slm_status launch_screen_select(const double *loss, int n_nodes, int P, int k, int32_t *sel,
+                                hipStream_t s);
+slm_status launch_screen_gather(const double *x, const int32_t *sel, int n_nodes, int P, int k,
+                                int D, float *W32, hipStream_t s);
+slm_status launch_screen_merge(const int32_t *sel, const double *loss_r, const int32_t *split_r,
+                               const float *thr_r, int n_nodes, int P, int k, double *loss,
+                               int32_t *split, float *thr, double *gloss, hipStream_t s);
+
+// learned proposal
+struct StatsArgs {
+  const void *X;
+  int x_bf16;
+  int64_t N;
+  int D;
+  const int32_t *labels;
+  int K;
+  const int64_t *beg, *end;
+  int n_nodes;
+  double *sums;          // accumulator [n_nodes][K][D][2]: zero on entry, zero on exit
+  uint32_t *counts;      // [n_nodes][K]: zero on entry, zero on exit
+  float *stats;          // [n_nodes][(K + 1) D]
+  float *sigma;          // [n_nodes][D]
+};
+size_t stats_workspace_bytes(int n_nodes, int D, int K);
+slm_status launch_node_stats_full(const StatsArgs &a, hipStream_t s);
+int64_t mlp_param_count(int I, int H, int O);
+slm_status launch_mlp_forward(const float *params, int I, int H, int O, const float *in, int B,
+                              int bf16, float *out, float *cache, hipStream_t s);
+slm_status launch_mlp_backward(const float *params, int I, int H, int O, const float *in, int B,
+                               const float *cache, const float *d_out, float *grads, float *work,
+                               hipStream_t s);
+slm_status launch_wta(const float *o, const float *t, int B, int M, int D, float eps, float *loss,
+                      float *d_o, hipStream_t s);
+slm_status launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s);
+slm_status launch_seeds(const float *o, const float *sigma, int n_nodes, int M, int D, int P,
+                        double *x, double *pbest, void *W_out, int w_bf16, hipStream_t s);
+
 slm_status launch_predict(const float *w, const float *thr, const int32_t *left,
                           const int32_t *right, int n_tree, int D, const float *X, int64_t N,
                           int32_t *leaf_out, hipStream_t s);
@@ -234,8 +275,9 @@ struct TreeStats {
 };
 
 struct PartArgs {
-  const float *X;       // current rows [N, D]
-  float *Xn;            // destination rows
+  const void *X;        // current rows [N, D] (float32, or bfloat16 with x_bf16)
+  void *Xn;             // destination rows
+  int x_bf16;
   const int32_t *lab;   // labels (classification) or null
   int32_t *labn;
   const double *y;      // targets (regression) or null

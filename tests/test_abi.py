@@ -93,13 +93,52 @@ def test_pso_validation():
     assert st == 2
     st = lib.slm_pso_init(*([FAKE] * 7), FAKE, 1, 8, 4, 1, 0, FAKE, api.F64, None)
     assert st == 3
-    # loss, split, thr, gbest_split, gbest_thr: split given without gbest_split
-    st = lib.slm_pso_step(*([FAKE] * 7), FAKE, FAKE, None, None, None, FAKE, 1, 8, 4,
+    # loss, gloss, split, thr, gbest_split, gbest_thr: split given without gbest_split
+    st = lib.slm_pso_step(*([FAKE] * 7), FAKE, None, FAKE, None, None, None, FAKE, 1, 8, 4,
                           0.7, 1.5, 1.5, 1, 0, 1, 1, FAKE, api.F32, None)
     assert st == 1
-    st = lib.slm_pso_step(*([FAKE] * 7), FAKE, None, None, None, None, FAKE, 1, 8, 4,
+    st = lib.slm_pso_step(*([FAKE] * 7), FAKE, None, None, None, None, None, FAKE, 1, 8, 4,
                           float("nan"), 1.5, 1.5, 1, 0, 1, 1, FAKE, api.F32, None)
     assert st == 1
+
+
+def test_screen_validation():
+    lib = api.load()
+    assert lib.slm_screen_select(FAKE, 2, 8, 9, FAKE, None) == 2          # k > P
+    assert lib.slm_screen_select(FAKE, 2, 8, 0, FAKE, None) == 2          # k = 0
+    assert lib.slm_screen_select(None, 2, 8, 4, FAKE, None) == 1
+    assert lib.slm_screen_select(None, 0, 8, 4, None, None) == 0          # nothing to do
+    assert lib.slm_screen_gather(FAKE, FAKE, 2, 8, 4, 0, FAKE, None) == 2  # D = 0
+    assert lib.slm_screen_gather(FAKE, None, 2, 8, 4, 3, FAKE, None) == 1
+    assert lib.slm_screen_merge(FAKE, FAKE, FAKE, FAKE, 2, 8, 16, FAKE, FAKE, FAKE, FAKE,
+                                None) == 2
+    assert lib.slm_screen_merge(FAKE, FAKE, FAKE, FAKE, 2, 8, 4, FAKE, FAKE, FAKE, None,
+                                None) == 1
+    # the mixed projection takes (BF16, F32); (F32, BF16) is refused
+    st = lib.slm_project(None, api.BF16, 0, 4, None, api.F32, None, 0, 4, None, 0, None, None, None)
+    assert st == 0
+
+
+def test_grow_tree_precision_validation():
+    lib = api.load()
+    out = api.TreeOut()
+    for kw, want in ((dict(precision=2), 1), (dict(precision=1, rescore_k=0), 2),
+                     (dict(precision=1, rescore_k=9), 2)):
+        cfg = api.TreeConfig(crit=api.GINI, K=2, P=8, T=2, bins=16, **kw)
+        prm = cfg.c_params()
+        assert lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) == 0
+        st = lib.slm_grow_tree(FAKE, api.BF16, 1000, 8, FAKE, api.I32, ctypes.byref(prm), FAKE,
+                               1 << 30, ctypes.byref(out), None)
+        assert st == want, kw
+    cfg = api.TreeConfig(crit=api.GINI, K=2, P=8, T=2, bins=16, precision=1, rescore_k=4)
+    prm = cfg.c_params()
+    plain = api.TreeConfig(crit=api.GINI, K=2, P=8, T=2, bins=16).c_params()
+    # screening needs room for the re-scored projection; bfloat16 rows halve X
+    assert lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) > 0
+    st = lib.slm_grow_tree(FAKE, api.F32, 1000, 8, FAKE, api.I32, ctypes.byref(prm), FAKE,
+                           1 << 30, ctypes.byref(out), None)
+    assert st == 3 and "BF16" in _err(lib)
+    del plain
 
 
 def test_grow_tree_params_validation():
