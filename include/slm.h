@@ -251,6 +251,14 @@ typedef struct {
   int32_t use_graph;   /* 1 = replay each depth's swarm loop as a HIP graph */
   int32_t profile;     /* 1 = time every projection / scan / step launch with
                           HIP events (fills timing[3..7]; no graph replay)    */
+  int32_t proposal;    /* 0 = random start (Sec. III-A); 1 = learned start:
+                          the first min(n_seeds, P) particles of every node
+                          start at the network's seeds (slm_node_stats,
+                          slm_mlp_forward with BF16 inference,
+                          slm_proposal_seeds); classification only        */
+  int32_t n_seeds;     /* M seeds per node (network output M * D)        */
+  int32_t mlp_hidden;  /* hidden width H (network input (K + 1) * D)     */
+  const float *mlp;    /* [device] packed parameters, slm_mlp_param_count */
 } slm_tree_params;
 
 typedef struct {
@@ -272,6 +280,9 @@ typedef struct {
   int64_t *sample_splits;    /* optional [2]: [0] sum over evaluations of
                                 n_j * P (screened ones with precision = 1),
                                 [1] re-scored n_j * rescore_k (else 0)      */
+  float *stats;        /* optional [max_nodes, (K + 1) D]: node statistics
+                          (slm_node_stats) of every searched node          */
+  float *sigma;        /* optional [max_nodes, D], with stats               */
 } slm_tree_out;
 
 size_t slm_grow_tree_workspace(const slm_tree_params *prm, int64_t N, int32_t D);
@@ -290,6 +301,99 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D,
 slm_status slm_predict(const float *w, const float *thr, const int32_t *left,
                        const int32_t *right, int32_t n_tree, int32_t D,
                        const float *X, int64_t N, int32_t *leaf_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_search_nodes -- the swarm search of a batch of nodes (Alg. 1 for every
+ * node, all evaluated together), without partitioning: the per-depth step of
+ * slm_grow_tree on caller-given node row sets.
+ *
+ * Node j owns rows row_off[j] .. row_off[j+1]-1 of X / target ([device]
+ * int64, non-decreasing); node_id[j] ([device]) keys its random numbers as
+ * the heap id does in slm_grow_tree.  prm supplies the criterion, P, T,
+ * bins, precision, proposal and seed (max_depth and min_node are ignored).
+ * target_loss ([device] [n_nodes] or NULL): a node stops after the first
+ * evaluation whose global-best loss is <= target_loss[j] (its rows are
+ * skipped from then on); the search ends when every node has stopped or
+ * after T moves.  Outputs ([device]): gbest [n_nodes, D], gbest_loss,
+ * gbest_split, gbest_thr [n_nodes] and evals [n_nodes] (evaluations run for
+ * the node: the one that reached its target, else T + 1).  Synchronous (one
+ * host read per evaluation when target_loss is given).
+ * ------------------------------------------------------------------------ */
+size_t slm_search_nodes_workspace(const slm_tree_params *prm, int64_t N, int32_t D,
+                                  int32_t n_nodes);
+slm_status slm_search_nodes(const void *X, int32_t x_dtype, int64_t N, int32_t D,
+                            const void *target, int32_t t_dtype, const int64_t *row_off,
+                            const int32_t *node_id, int32_t n_nodes, const slm_tree_params *prm,
+                            const double *target_loss, double *gbest, double *gbest_loss,
+                            int32_t *gbest_split, float *gbest_thr, int32_t *evals,
+                            void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned proposal of initial swarm positions.  The paper starts every swarm
+ * at random (Sec. III-A); these calls only replace that start, so the swarm
+ * and its loss stay the judge of every direction and random starts remain the
+ * fallback.  Not in the paper: the definitions below are this library's.
+ *
+ * slm_node_stats: per node j (rows as in slm_split_scan, labels in [0, K),
+ *   1 <= K <= 16, K * D <= 4096), with feature mean mu, population standard
+ *   deviation sigma, class proportions pi_k and class means m_k, classes
+ *   ordered by count (largest first, ties to the lower id):
+ *     stats[j, c*D + d] = pi_k (m_k,d - mu_d) / sigma_d  (c-th class k),
+ *     stats[j, K*D + d] = sum_k pi_k Var_k(x_d) / sigma_d^2,
+ *   0 where sigma_d = 0; sigma[j, d] = sigma_d.  Sums in FP64 (atomics: the
+ *   last bits depend on the order), outputs FP32.  workspace: >=
+ *   slm_node_stats_workspace bytes, zero-filled before first use, left
+ *   zero-filled.  Asynchronous.
+ * slm_mlp_forward: o = W3 GELU(W2 GELU(W1 s + b1) + b2) + b3 for a batch of
+ *   inputs s [batch, n_in]; GELU(x) = x Phi(x).  params packed as W1
+ *   [hidden, n_in], b1 [hidden], W2 [hidden, hidden], b2, W3 [n_out, hidden],
+ *   b3 (FP32, slm_mlp_param_count floats).  bf16 = 1 rounds both operands
+ *   of every product to BF16 (BF16 inference; FP32 accumulation).  cache
+ *   (4 batch hidden floats) receives four consecutive [batch, hidden]
+ *   blocks z1, h1, z2, h2 (pre- and post-GELU of both hidden layers; the
+ *   backward reads them).
+ *   out [batch, n_out].  Asynchronous.
+ * slm_mlp_backward: gradient of sum(d_out * o) with respect to the packed
+ *   parameters (grads, same layout), from the forward's cache; work [batch,
+ *   2 hidden] scratch.  Asynchronous.
+ * slm_wta_loss: per sample b, with M seeds of D values o[b] (unit seeds
+ *   u_i = o_i / |o_i|) and a unit target t[b]: q_i = (u_i . t)^2, winner =
+ *   first argmax, loss[b] = sum_i w_i (1 - q_i) with w = 1 - eps for the
+ *   winner and eps / (M - 1) otherwise; d_out = scale * d loss[b] / d o[b]
+ *   (scale = 1 / batch gives the gradient of the batch mean).  Asynchronous.
+ * slm_proposal_targets: training target of a raw unit direction g (a swarm's
+ *   global best) with the node's sigma: t = g sigma / |g sigma|, the
+ *   standardised-space direction the seeds are compared with.  [n, D] each.
+ *   Asynchronous.
+ * slm_adam_step: Adam (Kingma and Ba) on n floats, step counted from 1.
+ * slm_proposal_seeds: seed i of node j (o [n_nodes, M * D], standardised
+ *   space) -> raw direction a_d = u_d / sigma_d scaled to unit norm, written
+ *   as position, personal best and projection copy (w_dtype F32 or BF16) of
+ *   particle i < min(M, P) of node j; a seed of zero norm leaves the particle
+ *   as it was.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+size_t slm_node_stats_workspace(int32_t n_nodes, int32_t D, int32_t K);
+slm_status slm_node_stats(const void *X, int32_t x_dtype, int64_t N, int32_t D,
+                          const int32_t *labels, int32_t K, const int64_t *row_off,
+                          int32_t n_nodes, float *stats, float *sigma, void *workspace,
+                          size_t ws_bytes, void *stream);
+int64_t slm_mlp_param_count(int32_t n_in, int32_t hidden, int32_t n_out);
+slm_status slm_mlp_forward(const float *params, int32_t n_in, int32_t hidden, int32_t n_out,
+                           const float *in, int32_t batch, int32_t bf16, float *out, float *cache,
+                           void *stream);
+slm_status slm_mlp_backward(const float *params, int32_t n_in, int32_t hidden, int32_t n_out,
+                            const float *in, int32_t batch, const float *cache,
+                            const float *d_out, float *grads, float *work, void *stream);
+slm_status slm_wta_loss(const float *out, const float *target, int32_t batch, int32_t M,
+                        int32_t D, float eps, float scale, float *loss, float *d_out,
+                        void *stream);
+slm_status slm_proposal_targets(const float *g, const float *sigma, int32_t n, int32_t D,
+                                float *t, void *stream);
+slm_status slm_adam_step(float *params, const float *grads, float *m, float *v, int64_t n,
+                         float lr, float b1, float b2, float eps, int32_t step, void *stream);
+slm_status slm_proposal_seeds(const float *out, const float *sigma, int32_t n_nodes, int32_t M,
+                              int32_t D, int32_t P, double *x, double *pbest, void *W_out,
+                              int32_t w_dtype, void *stream);
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,9 @@ class TreeParams(ctypes.Structure):
                 ("rescore_k", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("c1", ctypes.c_double), ("c2", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("tree", ctypes.c_uint32), ("use_graph", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("proposal", ctypes.c_int32),
+                ("n_seeds", ctypes.c_int32), ("mlp_hidden", ctypes.c_int32),
+                ("mlp", ctypes.c_void_p)]
 
 
 class TreeOut(ctypes.Structure):
@@ -46,7 +48,8 @@ class TreeOut(ctypes.Structure):
                 ("right", ctypes.c_void_p), ("leaf", ctypes.c_void_p), ("n", ctypes.c_void_p),
                 ("impurity", ctypes.c_void_p), ("split_loss", ctypes.c_void_p),
                 ("depth", ctypes.c_void_p), ("heap", ctypes.c_void_p),
-                ("timing", ctypes.c_void_p), ("sample_splits", ctypes.c_void_p)]
+                ("timing", ctypes.c_void_p), ("sample_splits", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p), ("sigma", ctypes.c_void_p)]
 
 
 _lib = None
@@ -72,6 +75,21 @@ _SIGS = {
     "slm_grow_tree": ([_VP, _I32, _I64, _I32, _VP, _I32, ctypes.POINTER(TreeParams), _VP, _SZ,
                        ctypes.POINTER(TreeOut), _VP], _I32),
     "slm_predict": ([_VP, _VP, _VP, _VP, _I32, _I32, _VP, _I64, _VP, _VP], _I32),
+    "slm_search_nodes_workspace": ([ctypes.POINTER(TreeParams), _I64, _I32, _I32], _SZ),
+    "slm_search_nodes": ([_VP, _I32, _I64, _I32, _VP, _I32, _VP, _VP, _I32,
+                          ctypes.POINTER(TreeParams), _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP],
+                         _I32),
+    "slm_node_stats_workspace": ([_I32, _I32, _I32], _SZ),
+    "slm_node_stats": ([_VP, _I32, _I64, _I32, _VP, _I32, _VP, _I32, _VP, _VP, _VP, _SZ, _VP], _I32),
+    "slm_mlp_param_count": ([_I32, _I32, _I32], _I64),
+    "slm_mlp_forward": ([_VP, _I32, _I32, _I32, _VP, _I32, _I32, _VP, _VP, _VP], _I32),
+    "slm_mlp_backward": ([_VP, _I32, _I32, _I32, _VP, _I32, _VP, _VP, _VP, _VP, _VP], _I32),
+    "slm_wta_loss": ([_VP, _VP, _I32, _I32, _I32, ctypes.c_float, ctypes.c_float, _VP, _VP, _VP],
+                     _I32),
+    "slm_proposal_targets": ([_VP, _VP, _I32, _I32, _VP, _VP], _I32),
+    "slm_adam_step": ([_VP, _VP, _VP, _VP, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                       ctypes.c_float, _I32, _VP], _I32),
+    "slm_proposal_seeds": ([_VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP, _I32, _VP], _I32),
 }
 
 
@@ -335,11 +353,20 @@ class TreeConfig:
     profile: bool = False
     precision: int = 0          # 1 = bfloat16 screen, float32 re-scoring (X bfloat16)
     rescore_k: int = 32
+    proposal: int = 0           # 1 = learned start from `mlp` (a device float32 tensor)
+    n_seeds: int = 64
+    mlp_hidden: int = 256
+    mlp: object = None
 
     def c_params(self) -> TreeParams:
+        mlp = None
+        if self.proposal == 1:
+            _dev(self.mlp, torch.float32, "mlp")
+            mlp = self.mlp.data_ptr()
         return TreeParams(self.crit, self.K, self.max_depth, self.min_node, self.P, self.T,
                           self.bins, self.precision, self.rescore_k, self.omega, self.c1,
-                          self.c2, self.seed, self.tree, int(self.use_graph), int(self.profile))
+                          self.c2, self.seed, self.tree, int(self.use_graph), int(self.profile),
+                          int(self.proposal), self.n_seeds, self.mlp_hidden, mlp)
 
 
 _tree_ws: dict = {}
@@ -360,9 +387,10 @@ def tree_workspace(cfg: TreeConfig, N: int, D: int, device) -> torch.Tensor:
     return buf
 
 
-def grow_tree(X, target, cfg: TreeConfig, workspace=None):
+def grow_tree(X, target, cfg: TreeConfig, workspace=None, stats: bool = False):
     """One tree (Alg. 2); returns host numpy arrays of the nodes.  X is
-    float32, or bfloat16 with cfg.precision = 1."""
+    float32, or bfloat16 with cfg.precision = 1.  stats=True also returns each
+    searched node's statistics ("stats", "sigma"; classification)."""
     load()
     _dev(X, torch.bfloat16 if cfg.precision == 1 else torch.float32, "X")
     N, D = X.shape
@@ -382,9 +410,14 @@ def grow_tree(X, target, cfg: TreeConfig, workspace=None):
                impurity=np.zeros(maxn), split_loss=np.zeros(maxn),
                depth=np.zeros(maxn, np.int32), heap=np.zeros(maxn, np.int32),
                timing=np.zeros(8), sample_splits=np.zeros(2, np.int64))
+    if stats:
+        arr["stats"] = np.zeros((maxn, (cfg.K + 1) * D), np.float32)
+        arr["sigma"] = np.zeros((maxn, D), np.float32)
     out = TreeOut(maxn, 0, *[arr[k].ctypes.data for k in
                              ("w", "thr", "left", "right", "leaf", "n", "impurity", "split_loss",
-                              "depth", "heap", "timing", "sample_splits")])
+                              "depth", "heap", "timing", "sample_splits")],
+                  arr["stats"].ctypes.data if stats else None,
+                  arr["sigma"].ctypes.data if stats else None)
     prm = cfg.c_params()
     _check(_lib.slm_grow_tree(_p(X), _xdtype(X), N, D, _p(target), tt, ctypes.byref(prm), _p(ws),
                               ws.numel(), ctypes.byref(out), _stream()), "slm_grow_tree")
@@ -393,6 +426,139 @@ def grow_tree(X, target, cfg: TreeConfig, workspace=None):
     res["n_nodes"] = n
     res["K"] = cfg.K
     return res
+
+
+# ------------------------------------------------------------------ node-batch search
+def search_nodes(X, target, row_off, node_id, cfg: TreeConfig, target_loss=None, workspace=None):
+    """Swarm search of a batch of nodes (rows grouped by node, row_off int64
+    [n+1] on the device); optional per-node stop targets.  Returns device
+    tensors gbest [n, D], gbest_loss, gbest_split, gbest_thr, evals."""
+    load()
+    _dev(X, torch.bfloat16 if cfg.precision == 1 else torch.float32, "X")
+    _dev(row_off, torch.int64, "row_off")
+    _dev(node_id, torch.int32, "node_id")
+    N, D = X.shape
+    nn = row_off.numel() - 1
+    if cfg.crit == MSE:
+        _dev(target, torch.float64, "target")
+        tt = F64
+    else:
+        _dev(target, torch.int32, "target")
+        tt = I32
+    if target_loss is not None:
+        _dev(target_loss, torch.float64, "target_loss")
+    prm = cfg.c_params()
+    need = _lib.slm_search_nodes_workspace(ctypes.byref(prm), N, D, nn)
+    if need == 0:
+        raise SlmError(1, "slm_search_nodes_workspace", _lib.slm_last_error().decode())
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
+    dev = X.device
+    out = dict(gbest=torch.empty(nn, D, dtype=torch.float64, device=dev),
+               gbest_loss=torch.empty(nn, dtype=torch.float64, device=dev),
+               gbest_split=torch.empty(nn, dtype=torch.int32, device=dev),
+               gbest_thr=torch.empty(nn, dtype=torch.float32, device=dev),
+               evals=torch.empty(nn, dtype=torch.int32, device=dev))
+    _check(_lib.slm_search_nodes(_p(X), _xdtype(X), N, D, _p(target), tt, _p(row_off),
+                                 _p(node_id), nn, ctypes.byref(prm), _p(target_loss),
+                                 _p(out["gbest"]), _p(out["gbest_loss"]), _p(out["gbest_split"]),
+                                 _p(out["gbest_thr"]), _p(out["evals"]), _p(workspace),
+                                 workspace.numel(), _stream()), "slm_search_nodes")
+    return out
+
+
+# ------------------------------------------------------------------ learned proposal
+def node_stats(X, labels, K: int, row_off):
+    """Per-node statistics [n, (K+1) D] and deviations [n, D] (float32)."""
+    load()
+    _dev(X, X.dtype, "X")
+    _dev(labels, torch.int32, "labels")
+    _dev(row_off, torch.int64, "row_off")
+    N, D = X.shape
+    nn = row_off.numel() - 1
+    stats = torch.empty(nn, (K + 1) * D, dtype=torch.float32, device=X.device)
+    sigma = torch.empty(nn, D, dtype=torch.float32, device=X.device)
+    need = _lib.slm_node_stats_workspace(nn, D, K)
+    ws = torch.zeros(need, dtype=torch.uint8, device=X.device)
+    _check(_lib.slm_node_stats(_p(X), _xdtype(X), N, D, _p(labels), K, _p(row_off), nn,
+                               _p(stats), _p(sigma), _p(ws), ws.numel(), _stream()),
+           "slm_node_stats")
+    return stats, sigma
+
+
+def mlp_param_count(n_in: int, hidden: int, n_out: int) -> int:
+    load()
+    return int(_lib.slm_mlp_param_count(n_in, hidden, n_out))
+
+
+def mlp_forward(params, n_in: int, hidden: int, n_out: int, inp, bf16: bool = False):
+    """(out [B, n_out], cache [4, B, hidden]: z1, h1, z2, h2)."""
+    load()
+    _dev(params, torch.float32, "params")
+    _dev(inp, torch.float32, "in")
+    B = inp.shape[0]
+    out = torch.empty(B, n_out, dtype=torch.float32, device=inp.device)
+    cache = torch.empty(4, B, hidden, dtype=torch.float32, device=inp.device)
+    _check(_lib.slm_mlp_forward(_p(params), n_in, hidden, n_out, _p(inp), B, int(bool(bf16)),
+                                _p(out), _p(cache), _stream()), "slm_mlp_forward")
+    return out, cache
+
+
+def mlp_backward(params, n_in: int, hidden: int, n_out: int, inp, cache, d_out):
+    load()
+    for t, nm in ((params, "params"), (inp, "in"), (cache, "cache"), (d_out, "d_out")):
+        _dev(t, torch.float32, nm)
+    B = inp.shape[0]
+    grads = torch.empty_like(params)
+    work = torch.empty(B, 2 * hidden, dtype=torch.float32, device=inp.device)
+    _check(_lib.slm_mlp_backward(_p(params), n_in, hidden, n_out, _p(inp), B, _p(cache),
+                                 _p(d_out), _p(grads), _p(work), _stream()), "slm_mlp_backward")
+    return grads
+
+
+def wta_loss(out, target, M: int, eps: float, scale: float = 1.0):
+    """(loss [B], scale * d_out [B, M D]) of the relaxed winner-take-all loss."""
+    load()
+    _dev(out, torch.float32, "out")
+    _dev(target, torch.float32, "target")
+    B, D = target.shape
+    loss = torch.empty(B, dtype=torch.float32, device=out.device)
+    d_out = torch.empty_like(out)
+    _check(_lib.slm_wta_loss(_p(out), _p(target), B, M, D, float(eps), float(scale), _p(loss),
+                             _p(d_out), _stream()), "slm_wta_loss")
+    return loss, d_out
+
+
+def proposal_targets(g, sigma):
+    """Standardised unit targets t = g sigma / |g sigma| ([n, D] float32)."""
+    load()
+    _dev(g, torch.float32, "g")
+    _dev(sigma, torch.float32, "sigma")
+    n, D = g.shape
+    t = torch.empty_like(g)
+    _check(_lib.slm_proposal_targets(_p(g), _p(sigma), n, D, _p(t), _stream()),
+           "slm_proposal_targets")
+    return t
+
+
+def adam_step(params, grads, m, v, lr: float, step: int, b1=0.9, b2=0.999, eps=1e-8):
+    load()
+    for t, nm in ((params, "params"), (grads, "grads"), (m, "m"), (v, "v")):
+        _dev(t, torch.float32, nm)
+    _check(_lib.slm_adam_step(_p(params), _p(grads), _p(m), _p(v), params.numel(), float(lr),
+                              float(b1), float(b2), float(eps), int(step), _stream()),
+           "slm_adam_step")
+
+
+def proposal_seeds(out, sigma, M: int, sw: "Swarm"):
+    """Write the network's seeds into the first min(M, P) particles of sw."""
+    load()
+    _dev(out, torch.float32, "out")
+    _dev(sigma, torch.float32, "sigma")
+    nn = sigma.shape[0]
+    wt = BF16 if sw.W.dtype == torch.bfloat16 else F32
+    _check(_lib.slm_proposal_seeds(_p(out), _p(sigma), nn, M, sw.D, sw.P, _p(sw.x), _p(sw.pbest),
+                                   _p(sw.W), wt, _stream()), "slm_proposal_seeds")
 
 
 def predict_leaves(tree: dict, X):

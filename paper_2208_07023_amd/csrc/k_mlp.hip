@@ -250,7 +250,7 @@ __global__ void k_colsum(const float *d, int rows, int cols, float *out) {
 // b = first argmax, L = sum_i w_i (1 - q_i), d o_i = -2 w_i c_i (t - c_i u_i) / r_i.
 constexpr int WTA_WG = 256;
 __global__ __launch_bounds__(WTA_WG) void k_wta(const float *o, const float *t, int M, int D,
-                                                float eps, float *loss, float *d_o) {
+                                                float eps, float scale, float *loss, float *d_o) {
   __shared__ float sr[256], sc[256];
   __shared__ int s_best;
   const int b = blockIdx.x, tid = threadIdx.x;
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(WTA_WG) void k_wta(const float *o, const float *t, 
     if (r > 0.f) {
       const float c = sc[i], w = i == s_best ? wb : wo;
       const float u = ob[e] / r;
-      gv = -2.f * w * c * (tb[d] - c * u) / r;
+      gv = -2.f * w * c * (tb[d] - c * u) / r * scale;
     }
     d_o[(int64_t)b * M * D + e] = gv;
   }
@@ -346,9 +346,34 @@ __global__ __launch_bounds__(64) void k_seeds(const float *o, const float *sigma
   }
 }
 
+// Raw unit direction g -> standardised unit target t = g sigma / |g sigma|
+// (zero where the product has zero norm).  One wave per row.
+__global__ __launch_bounds__(64) void k_targets(const float *g, const float *sigma, int D,
+                                                float *t) {
+  const int64_t row = blockIdx.x;
+  const int lane = threadIdx.x;
+  double ss = 0.0;
+  for (int d = lane; d < D; d += 64) {
+    const double v = (double)g[row * D + d] * (double)sigma[row * D + d];
+    ss += v * v;
+  }
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+  const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+  for (int d = lane; d < D; d += 64)
+    t[row * D + d] = (float)((double)g[row * D + d] * (double)sigma[row * D + d] * inv);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+slm_status launch_targets(const float *g, const float *sigma, int n, int D, float *t,
+                          hipStream_t s) {
+  if (n <= 0) return SLM_OK;
+  hipLaunchKernelGGL(k_targets, dim3((unsigned)n), dim3(64), 0, s, g, sigma, D, t);
+  SLM_LAUNCHED();
+  return SLM_OK;
+}
+
 size_t stats_workspace_bytes(int n_nodes, int D, int K) {
   return ((size_t)n_nodes * K * D * 2 * 8 + 255) / 256 * 256 + (size_t)n_nodes * K * 4 + 256;
 }
@@ -445,10 +470,11 @@ slm_status launch_mlp_backward(const float *params, int I, int H, int O, const f
   return SLM_OK;
 }
 
-slm_status launch_wta(const float *o, const float *t, int B, int M, int D, float eps, float *loss,
-                      float *d_o, hipStream_t s) {
+slm_status launch_wta(const float *o, const float *t, int B, int M, int D, float eps, float scale,
+                      float *loss, float *d_o, hipStream_t s) {
   if (B <= 0) return SLM_OK;
-  hipLaunchKernelGGL(k_wta, dim3((unsigned)B), dim3(WTA_WG), 0, s, o, t, M, D, eps, loss, d_o);
+  hipLaunchKernelGGL(k_wta, dim3((unsigned)B), dim3(WTA_WG), 0, s, o, t, M, D, eps, scale, loss,
+                     d_o);
   SLM_LAUNCHED();
   return SLM_OK;
 }

@@ -257,4 +257,48 @@ slm_status launch_partition(const PartArgs &a0, hipStream_t s) {
   return SLM_OK;
 }
 
+// ---------------------------------------------------------------- node-batch search
+namespace {
+// Stop state after evaluation number evals_now: a node whose global-best
+// loss reached its target stops (its active row range collapses to empty and
+// evals = evals_now); on the last evaluation every node still searching gets
+// evals = evals_now.  remaining = nodes still searching.  One work-group.
+__global__ __launch_bounds__(1024) void k_search_stop(const double *gbest_loss,
+                                                      const double *target, const int64_t *beg,
+                                                      int64_t *end_act, int32_t *done,
+                                                      int32_t *evals, int n, int evals_now,
+                                                      int last, uint32_t *remaining) {
+  __shared__ uint32_t cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  uint32_t c = 0;
+  for (int j = threadIdx.x; j < n; j += 1024) {
+    if (done[j]) continue;
+    if (target && gbest_loss[j] <= target[j]) {
+      done[j] = 1;
+      evals[j] = evals_now;
+      end_act[j] = beg[j];
+    } else if (last) {
+      done[j] = 1;
+      evals[j] = evals_now;
+    } else {
+      ++c;
+    }
+  }
+  atomicAdd(&cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0) *remaining = cnt;
+}
+}  // namespace
+
+slm_status launch_search_stop(const double *gbest_loss, const double *target, const int64_t *beg,
+                              int64_t *end_act, int32_t *done, int32_t *evals, int n,
+                              int evals_now, bool last, uint32_t *remaining, hipStream_t s) {
+  if (n <= 0) return SLM_OK;
+  hipLaunchKernelGGL(k_search_stop, dim3(1), dim3(1024), 0, s, gbest_loss, target, beg, end_act,
+                     done, evals, n, evals_now, (int)last, remaining);
+  SLM_LAUNCHED();
+  return SLM_OK;
+}
+
 }  // namespace slm

@@ -70,25 +70,39 @@ struct TreeWS {
   int32_t *sel, *split_r;
   float *W32, *Zr, *zmin_r, *zmax_r, *thr_r;
   double *loss_r, *gloss;
+  // node statistics and learned proposal
+  double *stat_sums;
+  uint32_t *stat_counts;
+  float *stats, *sigma, *mlp_cache, *mlp_out;
+  // node-batch search: active row ends, stop state
+  int64_t *end_act;
+  int32_t *done;
+  uint32_t *remaining;
   TreeStats st;
   void *scan_ws;
   size_t scan_ws_bytes;
   size_t total;
 };
 
-TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base) {
+// Workspace of a tree build (search_nodes = 0) or of one node-batch search of
+// search_nodes nodes (no partition buffers).  stats: node statistics wanted.
+TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base, int search_nodes = 0,
+             bool stats = false) {
   Carver c{static_cast<char *>(base)};
   TreeWS w{};
-  const int64_t F = max_active(p, N);
+  const bool search = search_nodes > 0;
+  const int64_t F = search ? search_nodes : max_active(p, N);
   const bool mse = p.crit == SLM_MSE;
   const size_t xb = p.precision == 1 ? 2 : 4;
   const int Kc = mse ? 1 : p.K;
-  w.Xa = c.take<char>((size_t)N * D * xb);
-  w.Xb = c.take<char>((size_t)N * D * xb);
-  w.ta = c.take<char>((size_t)N * (mse ? 8 : 4));
-  w.tb = c.take<char>((size_t)N * (mse ? 8 : 4));
+  if (!search) {
+    w.Xa = c.take<char>((size_t)N * D * xb);
+    w.Xb = c.take<char>((size_t)N * D * xb);
+    w.ta = c.take<char>((size_t)N * (mse ? 8 : 4));
+    w.tb = c.take<char>((size_t)N * (mse ? 8 : 4));
+  }
   w.Z = c.take<float>((size_t)N * ((p.P + 31) / 32 * 32));   // particle-tiled
-  w.zsel = c.take<float>((size_t)N);
+  if (!search) w.zsel = c.take<float>((size_t)N);
   w.zmin = c.take<float>((size_t)F * p.P);
   w.zmax = c.take<float>((size_t)F * p.P);
   w.x = c.take<double>((size_t)F * p.P * D);
@@ -111,10 +125,29 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base) {
   w.do_split = c.take<int32_t>((size_t)F);
   w.n_left = c.take<int64_t>((size_t)F);
   w.seed_tree = c.take<uint64_t>(2);
-  const int64_t items = partition_items((int)F, N);
-  w.cnt_left = c.take<uint32_t>((size_t)items);
-  w.off_left = c.take<int64_t>((size_t)items);
-  w.off_right = c.take<int64_t>((size_t)items);
+  if (!search) {
+    const int64_t items = partition_items((int)F, N);
+    w.cnt_left = c.take<uint32_t>((size_t)items);
+    w.off_left = c.take<int64_t>((size_t)items);
+    w.off_right = c.take<int64_t>((size_t)items);
+  } else {
+    w.end_act = c.take<int64_t>((size_t)F);
+    w.done = c.take<int32_t>((size_t)F);
+    w.remaining = c.take<uint32_t>(1);
+  }
+  if (stats || p.proposal == 1) {
+    const size_t sws = stats_workspace_bytes((int)F, D, Kc);
+    char *sb = c.take<char>(sws);
+    w.stat_sums = reinterpret_cast<double *>(sb);
+    w.stat_counts = sb ? reinterpret_cast<uint32_t *>(sb + ((size_t)F * Kc * D * 2 * 8 + 255) / 256 * 256)
+                       : nullptr;
+    w.stats = c.take<float>((size_t)F * (Kc + 1) * D);
+    w.sigma = c.take<float>((size_t)F * D);
+  }
+  if (p.proposal == 1) {
+    w.mlp_cache = c.take<float>((size_t)F * 4 * p.mlp_hidden);
+    w.mlp_out = c.take<float>((size_t)F * p.n_seeds * D);
+  }
   if (p.precision == 1) {
     const int k = p.rescore_k;
     w.sel = c.take<int32_t>((size_t)F * k);
@@ -165,6 +198,19 @@ slm_status check_tree_params(const slm_tree_params *p, int64_t N, int32_t D) {
   if (p->precision == 1)
     SLM_CHECK(p->rescore_k >= 1 && p->rescore_k <= p->P, SLM_E_SHAPE,
               "slm_grow_tree: rescore_k = %d not in [1, P]", p->rescore_k);
+  SLM_CHECK(p->proposal == 0 || p->proposal == 1, SLM_E_INVALID,
+            "slm_grow_tree: proposal %d (0 = random, 1 = learned)", p->proposal);
+  if (p->proposal == 1) {
+    SLM_CHECK(p->crit != SLM_MSE, SLM_E_UNSUPPORTED,
+              "slm_grow_tree: the learned proposal needs class labels");
+    SLM_CHECK(p->mlp != nullptr, SLM_E_INVALID, "slm_grow_tree: proposal 1 needs mlp parameters");
+    SLM_CHECK(p->n_seeds >= 1 && p->n_seeds <= 4096 && p->mlp_hidden >= 1 &&
+                  p->mlp_hidden <= 4096,
+              SLM_E_SHAPE, "slm_grow_tree: n_seeds = %d / mlp_hidden = %d out of range",
+              p->n_seeds, p->mlp_hidden);
+    SLM_CHECK(p->K * D <= 4096, SLM_E_SHAPE, "slm_grow_tree: K * D = %d too large for the proposal",
+              p->K * D);
+  }
   return SLM_OK;
 }
 
@@ -350,10 +396,37 @@ struct LaunchTimes {
   }
 };
 
+// Stop control of a node-batch search: per-node loss targets, evaluation
+// counts, and the host copy of the number of nodes still searching.
+struct SearchCtl {
+  const double *target;   // [device] per-node targets or null (run all T + 1)
+  int32_t *evals;         // [device] evaluations per node
+  uint32_t *h_remaining;  // [host]
+};
+
+// Learned start: node statistics, BF16 network inference, seeds written over
+// the first min(n_seeds, P) particles of every node (after the random start).
+static slm_status learned_start(const slm_tree_params &p, const TreeWS &w, const void *Xc,
+                                const void *tc, int64_t N, int32_t D, int na, hipStream_t s) {
+  StatsArgs sa{};
+  sa.X = Xc; sa.x_bf16 = p.precision == 1; sa.N = N; sa.D = D;
+  sa.labels = static_cast<const int32_t *>(tc); sa.K = p.K; sa.beg = w.beg; sa.end = w.end;
+  sa.n_nodes = na; sa.sums = w.stat_sums; sa.counts = w.stat_counts; sa.stats = w.stats;
+  sa.sigma = w.sigma;
+  slm_status st = launch_node_stats_full(sa, s);
+  if (st) return st;
+  const int I = (p.K + 1) * D, O = p.n_seeds * D;
+  if ((st = launch_mlp_forward(p.mlp, I, p.mlp_hidden, O, w.stats, na, 1, w.mlp_out, w.mlp_cache,
+                               s)))
+    return st;
+  return launch_seeds(w.mlp_out, w.sigma, na, p.n_seeds, D, p.P, w.x, w.pbest, w.W,
+                      p.precision == 1, s);
+}
+
 // swarm loop of one depth: T+1 evaluations (project, scan, step)
 static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const void *Xc,
                              const void *tc, int64_t N, int32_t D, int na, hipStream_t s,
-                             LaunchTimes *lt = nullptr) {
+                             LaunchTimes *lt = nullptr, const SearchCtl *sc = nullptr) {
   const bool mse = p.crit == SLM_MSE;
   PsoArgs pa{};
   pa.x = w.x; pa.v = w.v; pa.pbest = w.pbest; pa.pbest_loss = w.pbest_loss;
@@ -369,16 +442,20 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pa.seed_tree_dev = w.seed_tree;
   slm_status st = launch_pso_init(pa, s);
   if (st) return st;
+  if (p.proposal == 1 && (st = learned_start(p, w, Xc, tc, N, D, na, s))) return st;
+  // a search skips the rows of stopped nodes: their active end collapses to
+  // their start, and their scan results read "no split"
+  const int64_t *ends = sc ? w.end_act : w.end;
   ProjectArgs pr{};
   pr.X = Xc; pr.x_bf16 = scr; pr.w_bf16 = scr; pr.N = N; pr.D = D; pr.W = w.W; pr.beg = w.beg;
-  pr.end = w.end;
+  pr.end = ends;
   pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
   pr.zl = zlayout_of(1, N, p.P);
   ScanArgs sa{};
   sa.Z = w.Z; sa.zl = pr.zl; sa.zmin = w.zmin; sa.zmax = w.zmax;
   sa.labels = mse ? nullptr : static_cast<const int32_t *>(tc);
   sa.y = mse ? static_cast<const double *>(tc) : nullptr;
-  sa.K = p.K; sa.N = N; sa.beg = w.beg; sa.end = w.end; sa.n_nodes = na; sa.P = p.P;
+  sa.K = p.K; sa.N = N; sa.beg = w.beg; sa.end = ends; sa.n_nodes = na; sa.P = p.P;
   sa.bins = p.bins; sa.crit = p.crit; sa.best_split = w.split; sa.best_loss = w.loss;
   sa.threshold = w.thr; sa.ws = w.scan_ws; sa.ws_bytes = w.scan_ws_bytes;
   // float32 re-scoring of the screened evaluation's best rescore_k particles
@@ -392,7 +469,9 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
     sar.best_split = w.split_r; sar.best_loss = w.loss_r; sar.threshold = w.thr_r;
   }
   auto scan = [&](const ScanArgs &x) {
-    return p.bins ? launch_scan_hist(x, s) : launch_scan_exact(x, 8192, s);
+    slm_status r = p.bins ? launch_scan_hist(x, s) : launch_scan_exact(x, 8192, s);
+    if (!r && sc && p.bins) r = launch_scan_empty_nodes(x, s);
+    return r;
   };
   for (int t = 0; t <= p.T; ++t) {
     if (lt && (st = lt->begin(0, s))) return st;
@@ -421,6 +500,16 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
     if (lt && (st = lt->begin(2, s))) return st;
     if ((st = launch_pso_step(pa, s))) return st;
     if (lt && (st = lt->end(s))) return st;
+    if (sc) {
+      if ((st = launch_search_stop(w.gbest_loss, sc->target, w.beg, w.end_act, w.done, sc->evals,
+                                   na, t + 1, t == p.T, w.remaining, s)))
+        return st;
+      if (sc->target) {
+        SLM_HIP(hipMemcpyAsync(sc->h_remaining, w.remaining, 4, hipMemcpyDeviceToHost, s));
+        SLM_HIP(hipStreamSynchronize(s));
+        if (*sc->h_remaining == 0) break;
+      }
+    }
   }
   return SLM_OK;
 }
@@ -432,7 +521,10 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)N, (uint64_t)D, (uint64_t)na, (uint64_t)p.P, (uint64_t)p.T,
            (uint64_t)p.bins, (uint64_t)p.crit, (uint64_t)p.K,
            (uint64_t)(uintptr_t)w.scan_ws, (uint64_t)p.precision,
-           (uint64_t)(p.precision == 1 ? p.rescore_k : 0)};
+           (uint64_t)(p.precision == 1 ? p.rescore_k : 0), (uint64_t)p.proposal,
+           (uint64_t)(uintptr_t)(p.proposal == 1 ? p.mlp : nullptr),
+           (uint64_t)(p.proposal == 1 ? p.n_seeds : 0),
+           (uint64_t)(p.proposal == 1 ? p.mlp_hidden : 0)};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -675,6 +767,186 @@ slm_status slm_screen_merge(const int32_t *sel, const double *loss_r, const int3
                              S(stream));
 }
 
+// ---------------------------------------------------------------- node-batch search
+size_t slm_search_nodes_workspace(const slm_tree_params *prm, int64_t N, int32_t D,
+                                  int32_t n_nodes) {
+  if (check_tree_params(prm, N, D) != SLM_OK || n_nodes < 1) return 0;
+  return carve(*prm, N, D, nullptr, n_nodes, prm->proposal == 1).total;
+}
+
+slm_status slm_search_nodes(const void *X, int32_t x_dtype, int64_t N, int32_t D,
+                            const void *target, int32_t t_dtype, const int64_t *row_off,
+                            const int32_t *node_id, int32_t n_nodes, const slm_tree_params *prm,
+                            const double *target_loss, double *gbest, double *gbest_loss,
+                            int32_t *gbest_split, float *gbest_thr, int32_t *evals,
+                            void *workspace, size_t ws_bytes, void *stream) {
+  clear_error();
+  slm_status st = check_tree_params(prm, N, D);
+  if (st) return st;
+  const slm_tree_params &p = *prm;
+  const bool mse = p.crit == SLM_MSE;
+  SLM_CHECK(n_nodes >= 1 && n_nodes <= (1 << 24), SLM_E_SHAPE,
+            "slm_search_nodes: n_nodes = %d out of range", n_nodes);
+  SLM_CHECK(x_dtype == (p.precision == 1 ? SLM_BF16 : SLM_F32), SLM_E_DTYPE,
+            "slm_search_nodes: X must be F32 (precision 0) or BF16 (precision 1)");
+  SLM_CHECK(t_dtype == (mse ? SLM_F64 : SLM_I32), SLM_E_DTYPE,
+            "slm_search_nodes: target dtype does not match the criterion");
+  SLM_CHECK(X && target && row_off && node_id && gbest && gbest_loss && gbest_split && gbest_thr &&
+                evals && workspace,
+            SLM_E_INVALID, "slm_search_nodes: NULL pointer");
+  const TreeWS w = carve(p, N, D, workspace, n_nodes, p.proposal == 1);
+  SLM_CHECK(ws_bytes >= w.total, SLM_E_NOMEM,
+            "slm_search_nodes: workspace of %zu bytes, %zu needed", ws_bytes, w.total);
+  if (p.bins == 0) {
+    std::vector<int64_t> ho((size_t)n_nodes + 1);
+    SLM_HIP(hipMemcpy(ho.data(), row_off, ho.size() * 8, hipMemcpyDeviceToHost));
+    for (int j = 0; j < n_nodes; ++j)
+      SLM_CHECK(ho[j + 1] - ho[j] <= 8192, SLM_E_UNSUPPORTED,
+                "slm_search_nodes: the exact scan takes nodes of at most 8192 rows");
+  }
+  if ((st = prepare_kernels())) return st;
+  hipStream_t s = S(stream);
+  const int Kc = mse ? 1 : p.K;
+  SLM_HIP(hipMemsetAsync(w.scan_ws, 0, w.scan_ws_bytes, s));
+  if (w.stat_sums)
+    SLM_HIP(hipMemsetAsync(w.stat_sums, 0, stats_workspace_bytes(n_nodes, D, Kc), s));
+  const uint64_t seed_tree[2] = {p.seed, (uint64_t)p.tree};
+  SLM_HIP(hipMemcpyAsync(w.seed_tree, seed_tree, 16, hipMemcpyHostToDevice, s));
+  SLM_HIP(hipMemcpyAsync(w.beg, row_off, (size_t)n_nodes * 8, hipMemcpyDeviceToDevice, s));
+  SLM_HIP(hipMemcpyAsync(w.end, row_off + 1, (size_t)n_nodes * 8, hipMemcpyDeviceToDevice, s));
+  SLM_HIP(hipMemcpyAsync(w.end_act, row_off + 1, (size_t)n_nodes * 8, hipMemcpyDeviceToDevice, s));
+  SLM_HIP(hipMemcpyAsync(w.node_id, node_id, (size_t)n_nodes * 4, hipMemcpyDeviceToDevice, s));
+  SLM_HIP(hipMemsetAsync(w.done, 0, (size_t)n_nodes * 4, s));
+  uint32_t h_remaining = 0;
+  const SearchCtl sc{target_loss, evals, &h_remaining};
+  if ((st = swarm_loop(p, w, X, target, N, D, n_nodes, s, nullptr, &sc))) return st;
+  SLM_HIP(hipMemcpyAsync(gbest, w.gbest, (size_t)n_nodes * D * 8, hipMemcpyDeviceToDevice, s));
+  SLM_HIP(hipMemcpyAsync(gbest_loss, w.gbest_loss, (size_t)n_nodes * 8, hipMemcpyDeviceToDevice, s));
+  SLM_HIP(hipMemcpyAsync(gbest_split, w.gbest_split, (size_t)n_nodes * 4, hipMemcpyDeviceToDevice,
+                         s));
+  SLM_HIP(hipMemcpyAsync(gbest_thr, w.gbest_thr, (size_t)n_nodes * 4, hipMemcpyDeviceToDevice, s));
+  SLM_HIP(hipStreamSynchronize(s));
+  return SLM_OK;
+}
+
+// ---------------------------------------------------------------- learned proposal
+size_t slm_node_stats_workspace(int32_t n_nodes, int32_t D, int32_t K) {
+  if (n_nodes < 0 || D < 1 || K < 1) return 256;
+  return stats_workspace_bytes(n_nodes, D, K);
+}
+
+slm_status slm_node_stats(const void *X, int32_t x_dtype, int64_t N, int32_t D,
+                          const int32_t *labels, int32_t K, const int64_t *row_off,
+                          int32_t n_nodes, float *stats, float *sigma, void *workspace,
+                          size_t ws_bytes, void *stream) {
+  clear_error();
+  SLM_CHECK(N >= 0 && N < (1ll << 31) && D >= 1 && D <= DMAX && n_nodes >= 0, SLM_E_SHAPE,
+            "slm_node_stats: bad sizes");
+  SLM_CHECK(K >= 1 && K <= 16 && K * D <= 4096, SLM_E_SHAPE,
+            "slm_node_stats: need 1 <= K <= 16 and K * D <= 4096");
+  SLM_CHECK(x_dtype == SLM_F32 || x_dtype == SLM_BF16, SLM_E_DTYPE,
+            "slm_node_stats: X must be F32 or BF16");
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(row_off && stats && sigma && workspace && (N == 0 || (X && labels)), SLM_E_INVALID,
+            "slm_node_stats: NULL pointer");
+  const size_t need = stats_workspace_bytes(n_nodes, D, K);
+  SLM_CHECK(ws_bytes >= need, SLM_E_NOMEM, "slm_node_stats: workspace of %zu bytes, %zu needed",
+            ws_bytes, need);
+  StatsArgs a{};
+  a.X = X; a.x_bf16 = x_dtype == SLM_BF16; a.N = N; a.D = D; a.labels = labels; a.K = K;
+  a.beg = row_off; a.end = row_off + 1; a.n_nodes = n_nodes;
+  a.sums = static_cast<double *>(workspace);
+  a.counts = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) +
+                                          ((size_t)n_nodes * K * D * 2 * 8 + 255) / 256 * 256);
+  a.stats = stats; a.sigma = sigma;
+  return launch_node_stats_full(a, S(stream));
+}
+
+int64_t slm_mlp_param_count(int32_t n_in, int32_t hidden, int32_t n_out) {
+  if (n_in < 1 || hidden < 1 || n_out < 1) return 0;
+  return mlp_param_count(n_in, hidden, n_out);
+}
+
+static slm_status check_mlp(int32_t n_in, int32_t hidden, int32_t n_out, int32_t batch,
+                            const char *who) {
+  SLM_CHECK(n_in >= 1 && n_in <= (1 << 20) && hidden >= 1 && hidden <= 4096 && n_out >= 1 &&
+                n_out <= (1 << 20) && batch >= 0 && batch <= (1 << 21),
+            SLM_E_SHAPE, "%s: bad sizes", who);
+  SLM_CHECK((int64_t)batch * n_out < (1ll << 40), SLM_E_SHAPE, "%s: batch too large", who);
+  return SLM_OK;
+}
+
+slm_status slm_mlp_forward(const float *params, int32_t n_in, int32_t hidden, int32_t n_out,
+                           const float *in, int32_t batch, int32_t bf16, float *out, float *cache,
+                           void *stream) {
+  clear_error();
+  slm_status st = check_mlp(n_in, hidden, n_out, batch, "slm_mlp_forward");
+  if (st) return st;
+  if (batch == 0) return SLM_OK;
+  SLM_CHECK(params && in && out && cache, SLM_E_INVALID, "slm_mlp_forward: NULL pointer");
+  return launch_mlp_forward(params, n_in, hidden, n_out, in, batch, bf16 != 0, out, cache,
+                            S(stream));
+}
+
+slm_status slm_mlp_backward(const float *params, int32_t n_in, int32_t hidden, int32_t n_out,
+                            const float *in, int32_t batch, const float *cache,
+                            const float *d_out, float *grads, float *work, void *stream) {
+  clear_error();
+  slm_status st = check_mlp(n_in, hidden, n_out, batch, "slm_mlp_backward");
+  if (st) return st;
+  SLM_CHECK(batch >= 1, SLM_E_SHAPE, "slm_mlp_backward: empty batch");
+  SLM_CHECK(params && in && cache && d_out && grads && work, SLM_E_INVALID,
+            "slm_mlp_backward: NULL pointer");
+  return launch_mlp_backward(params, n_in, hidden, n_out, in, batch, cache, d_out, grads, work,
+                             S(stream));
+}
+
+slm_status slm_wta_loss(const float *out, const float *target, int32_t batch, int32_t M,
+                        int32_t D, float eps, float scale, float *loss, float *d_out,
+                        void *stream) {
+  clear_error();
+  SLM_CHECK(batch >= 0 && M >= 1 && M <= 256 && D >= 1 && D <= DMAX, SLM_E_SHAPE,
+            "slm_wta_loss: need 1 <= M <= 256, 1 <= D <= %d", DMAX);
+  SLM_CHECK(eps >= 0.f && eps <= 1.f, SLM_E_INVALID, "slm_wta_loss: eps not in [0, 1]");
+  if (batch == 0) return SLM_OK;
+  SLM_CHECK(out && target && loss && d_out, SLM_E_INVALID, "slm_wta_loss: NULL pointer");
+  return launch_wta(out, target, batch, M, D, eps, scale, loss, d_out, S(stream));
+}
+
+slm_status slm_proposal_targets(const float *g, const float *sigma, int32_t n, int32_t D,
+                                float *t, void *stream) {
+  clear_error();
+  SLM_CHECK(n >= 0 && D >= 1 && D <= DMAX, SLM_E_SHAPE, "slm_proposal_targets: bad sizes");
+  if (n == 0) return SLM_OK;
+  SLM_CHECK(g && sigma && t, SLM_E_INVALID, "slm_proposal_targets: NULL pointer");
+  return launch_targets(g, sigma, n, D, t, S(stream));
+}
+
+slm_status slm_adam_step(float *params, const float *grads, float *m, float *v, int64_t n,
+                         float lr, float b1, float b2, float eps, int32_t step, void *stream) {
+  clear_error();
+  SLM_CHECK(n >= 0 && step >= 1, SLM_E_SHAPE, "slm_adam_step: need n >= 0 and step >= 1");
+  SLM_CHECK(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps >= 0.f, SLM_E_INVALID,
+            "slm_adam_step: bad coefficients");
+  if (n == 0) return SLM_OK;
+  SLM_CHECK(params && grads && m && v, SLM_E_INVALID, "slm_adam_step: NULL pointer");
+  return launch_adam(params, grads, m, v, n, lr, b1, b2, eps, step, S(stream));
+}
+
+slm_status slm_proposal_seeds(const float *out, const float *sigma, int32_t n_nodes, int32_t M,
+                              int32_t D, int32_t P, double *x, double *pbest, void *W_out,
+                              int32_t w_dtype, void *stream) {
+  clear_error();
+  SLM_CHECK(n_nodes >= 0 && M >= 1 && M <= 4096 && D >= 1 && D <= DMAX && P >= 1 && P <= PMAX,
+            SLM_E_SHAPE, "slm_proposal_seeds: bad sizes");
+  SLM_CHECK(w_dtype == SLM_F32 || w_dtype == SLM_BF16, SLM_E_DTYPE,
+            "slm_proposal_seeds: W_out must be F32 or BF16");
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(out && sigma && x && pbest && W_out, SLM_E_INVALID, "slm_proposal_seeds: NULL pointer");
+  return launch_seeds(out, sigma, n_nodes, M, D, P, x, pbest, W_out, w_dtype == SLM_BF16,
+                      S(stream));
+}
+
 slm_status slm_predict(const float *w, const float *thr, const int32_t *left,
                        const int32_t *right, int32_t n_tree, int32_t D, const float *X, int64_t N,
                        int32_t *leaf_out, void *stream) {
@@ -686,9 +958,15 @@ slm_status slm_predict(const float *w, const float *thr, const int32_t *left,
   return launch_predict(w, thr, left, right, n_tree, D, X, N, leaf_out, S(stream));
 }
 
+// node statistics are kept for classification trees (the learned start, and
+// the optional per-node statistics output)
+static bool tree_stats(const slm_tree_params &p, int32_t D) {
+  return p.crit != SLM_MSE && p.K * D <= 4096;
+}
+
 size_t slm_grow_tree_workspace(const slm_tree_params *prm, int64_t N, int32_t D) {
   if (check_tree_params(prm, N, D) != SLM_OK) return 0;
-  return carve(*prm, N, D, nullptr).total;
+  return carve(*prm, N, D, nullptr, 0, tree_stats(*prm, D)).total;
 }
 
 slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, const void *target,
@@ -708,9 +986,14 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
                 out->impurity && out->split_loss && out->depth && out->heap,
             SLM_E_INVALID, "slm_grow_tree: NULL output array");
   SLM_CHECK(out->max_nodes >= 1, SLM_E_SHAPE, "slm_grow_tree: max_nodes < 1");
-  const TreeWS w = carve(p, N, D, workspace);
+  const TreeWS w = carve(p, N, D, workspace, 0, tree_stats(p, D));
   SLM_CHECK(ws_bytes >= w.total, SLM_E_NOMEM, "slm_grow_tree: workspace of %zu bytes, %zu needed",
             ws_bytes, w.total);
+  SLM_CHECK(!out->stats || tree_stats(p, D), SLM_E_UNSUPPORTED,
+            "slm_grow_tree: node statistics need class labels and K * D <= 4096");
+  const bool want_stats = out->stats != nullptr;
+  const int KD1 = (p.K + 1) * D;
+  std::vector<float> hst, hsg;
   if ((st = prepare_kernels())) return st;
   hipStream_t s = S(stream);
   const int K = mse ? 0 : p.K;
@@ -728,6 +1011,8 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
   // scan accumulators start (and stay) zero; RNG key and tree id on the
   // device; root statistics
   SLM_HIP(hipMemsetAsync(w.scan_ws, 0, w.scan_ws_bytes, s));
+  if (w.stat_sums)
+    SLM_HIP(hipMemsetAsync(w.stat_sums, 0, stats_workspace_bytes((int)F, D, Kc), s));
   const uint64_t seed_tree[2] = {p.seed, (uint64_t)p.tree};
   SLM_HIP(hipMemcpyAsync(w.seed_tree, seed_tree, 16, hipMemcpyHostToDevice, s));
   std::vector<int64_t> hb(F), he(F), hnl(F);
@@ -761,6 +1046,10 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
     out->depth[i] = depth;
     out->heap[i] = heap;
     std::fill(out->w + (size_t)i * D, out->w + (size_t)(i + 1) * D, 0.0f);
+    if (out->stats)
+      std::fill(out->stats + (size_t)i * KD1, out->stats + (size_t)(i + 1) * KD1, 0.0f);
+    if (out->stats && out->sigma)
+      std::fill(out->sigma + (size_t)i * D, out->sigma + (size_t)(i + 1) * D, 0.0f);
     *hn = HNode{i, b, e, depth, heap, imp, impure};
     return true;
   };
@@ -793,6 +1082,14 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
     SLM_HIP(hipMemcpyAsync(w.beg, hb.data(), na * 8, hipMemcpyHostToDevice, s));
     SLM_HIP(hipMemcpyAsync(w.end, he.data(), na * 8, hipMemcpyHostToDevice, s));
     SLM_HIP(hipMemcpyAsync(w.node_id, hid.data(), na * 4, hipMemcpyHostToDevice, s));
+    if (want_stats && p.proposal != 1) {
+      StatsArgs sa{};
+      sa.X = Xc; sa.x_bf16 = p.precision == 1; sa.N = N; sa.D = D;
+      sa.labels = static_cast<const int32_t *>(tc); sa.K = p.K; sa.beg = w.beg; sa.end = w.end;
+      sa.n_nodes = na; sa.sums = w.stat_sums; sa.counts = w.stat_counts; sa.stats = w.stats;
+      sa.sigma = w.sigma;
+      if ((st = launch_node_stats_full(sa, s))) return st;
+    }
     if ((st = tm_swarm.start(timing ? &timing[1] : nullptr, s))) return st;
     if (prof)
       st = swarm_loop(p, w, Xc, tc, N, D, na, s, &lt);
@@ -811,7 +1108,23 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
     SLM_HIP(hipMemcpyAsync(hgl.data(), w.gbest_loss, na * 8, hipMemcpyDeviceToHost, s));
     SLM_HIP(hipMemcpyAsync(hgt.data(), w.gbest_thr, na * 4, hipMemcpyDeviceToHost, s));
     SLM_HIP(hipMemcpyAsync(hgb.data(), w.gbest, (size_t)na * D * 8, hipMemcpyDeviceToHost, s));
+    if (want_stats) {
+      hst.resize((size_t)na * KD1);
+      hsg.resize((size_t)na * D);
+      SLM_HIP(hipMemcpyAsync(hst.data(), w.stats, hst.size() * 4, hipMemcpyDeviceToHost, s));
+      SLM_HIP(hipMemcpyAsync(hsg.data(), w.sigma, hsg.size() * 4, hipMemcpyDeviceToHost, s));
+    }
     SLM_HIP(hipStreamSynchronize(s));
+    if (want_stats) {
+      for (int j = 0; j < na; ++j) {
+        const int i = active[j].idx;
+        std::copy(hst.begin() + (size_t)j * KD1, hst.begin() + (size_t)(j + 1) * KD1,
+                  out->stats + (size_t)i * KD1);
+        if (out->sigma)
+          std::copy(hsg.begin() + (size_t)j * D, hsg.begin() + (size_t)(j + 1) * D,
+                    out->sigma + (size_t)i * D);
+      }
+    }
     int nsplit = 0;
     for (int j = 0; j < na; ++j) {
       out->split_loss[active[j].idx] = hgl[j];

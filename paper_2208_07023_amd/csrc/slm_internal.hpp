@@ -256,8 +256,10 @@ slm_status launch_mlp_forward(const float *params, int I, int H, int O, const fl
 slm_status launch_mlp_backward(const float *params, int I, int H, int O, const float *in, int B,
                                const float *cache, const float *d_out, float *grads, float *work,
                                hipStream_t s);
-slm_status launch_wta(const float *o, const float *t, int B, int M, int D, float eps, float *loss,
-                      float *d_o, hipStream_t s);
+slm_status launch_wta(const float *o, const float *t, int B, int M, int D, float eps, float scale,
+                      float *loss, float *d_o, hipStream_t s);
+slm_status launch_targets(const float *g, const float *sigma, int n, int D, float *t,
+                          hipStream_t s);
 slm_status launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
                        float b2, float eps, int step, hipStream_t s);
 slm_status launch_seeds(const float *o, const float *sigma, int n_nodes, int M, int D, int P,
@@ -298,6 +300,9 @@ slm_status launch_node_stats(const int64_t *beg, const int64_t *end, int n_nodes
                              const int32_t *lab, const double *y, int K, TreeStats st,
                              hipStream_t s);
 slm_status launch_partition(const PartArgs &a, hipStream_t s);
+slm_status launch_search_stop(const double *gbest_loss, const double *target, const int64_t *beg,
+                              int64_t *end_act, int32_t *done, int32_t *evals, int n,
+                              int evals_now, bool last, uint32_t *remaining, hipStream_t s);
 int64_t partition_items(int n_nodes, int64_t N);
 // sets kernel attributes once per process (call outside stream capture)
 slm_status prepare_kernels();
