@@ -10,7 +10,9 @@ Synthetic seeded data, resident in HBM before the timed region.
 Prints one JSON line.  `value` = sum over evaluations of n_node * P divided by
 the timed wall time.  `roofline` is the dominant kernel's achieved rate from
 HIP-event timings of every launch in one extra (instrumented) tree of the same
-workload; `cpu_baseline` times the FP64 oracle on a bounded sample.
+workload; `learned_vs_plain` compares learned and random swarm starts at equal
+node loss (the second half of the metric); `cpu_baseline` times the FP64
+oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -61,12 +63,44 @@ def cpu_baseline(X, y, P, bins, seconds=12.0):
                        f"{bins}-bin entropy) incl. FP64 projection, {dt:.1f} s, 1 thread")
 
 
+def learned_vs_plain():
+    """Learned against random swarm starts at equal node loss: harvest pairs
+    from plain-PSO trees (D = 128, K = 5 class mixtures), train the proposal
+    network with the library's kernels, then search the nodes of a held-out
+    tree (N = 200 000) with P = 64 particles from random and from learned
+    starts until each node's global-best loss is within 1% of a reference
+    search (P = 256, T = 200), at most 50 moves.  Smaller than the 16-tree,
+    N = 2e6 forest of the full evaluation so that the benchmark stays short."""
+    from paper_2208_07023_amd import inputs
+    from paper_2208_07023_amd import proposal as PL
+    D, K, M, H = 128, 5, 64, 256
+    t0 = time.perf_counter()
+    S, G, T = PL.harvest(100, D, K, 10000, 100000, seed=7, P=64, T=50, max_depth=8)
+    t_h = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, hist = PL.train(S, T, D, K, n_seeds=M, hidden=H, epochs=20, batch=1024)
+    t_t = time.perf_counter() - t0
+    X, y = inputs.cluster_mixture(200_000, D, K, clusters_per_class=4, mean_std=0.8, seed=999)
+    res = PL.compare_starts(net, X, y, K, ref_P=256, ref_T=200, P=64, T_max=50)
+    r, l = res["random"], res["learned"]
+    log(f"learned vs plain: {res}")
+    return {"workload": "held-out tree N=200000, D=128, K=5 (4 clusters/class, spread 0.8); "
+                        "reference P=256, T=200; arms P=64, T_max=50, target 1.01 L_ref",
+            "pairs": int(S.shape[0]), "train_loss_first_last": [hist[0], hist[-1]],
+            "harvest_s": t_h, "train_s": t_t,
+            "plain": r, "learned": l,
+            "speedup_wall": r["ms"] / max(1e-9, l["ms"]),
+            "speedup_evals": r["evals"] / max(1, l["evals"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain start comparison")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--N", type=int, default=100_000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -178,6 +212,8 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if not args.no_learned:
+        out["learned_vs_plain"] = learned_vs_plain()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, y, cfg.P, cfg.bins)
     print(json.dumps(out), flush=True)

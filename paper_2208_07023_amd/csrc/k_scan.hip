@@ -225,13 +225,12 @@ size_t slot_set_bytes(int64_t N, int P, int B, int K, bool mse) {
   const int64_t n_slots = (N - 1) / chunk_min(N) + 1;
   return (size_t)n_slots * worst;
 }
-// Replicas of every slot: the work-groups of a node spread their atomic
-// merges over R copies (chunk % R), which k_scan_finish adds up; 4 while the
-// accumulator stays within 1 GiB.
-int slot_replicas(int64_t N, int P, int B, int K, bool mse) {
-  const size_t one = slot_set_bytes(N, P, B, K, mse);
-  return one * 4 <= ((size_t)1 << 30) ? 4 : (one * 2 <= ((size_t)1 << 30) ? 2 : 1);
-}
+// Replicas of every slot: the work-groups of a node can spread their atomic
+// merges over R copies (chunk % R), which k_scan_finish adds up.  Measured on
+// MI355X (plain-tree shapes, N = 1e5, P = 256), every extra replica costs the
+// finish more than it saves the merges (root scan 72 / 80 / 97 us for R = 1 /
+// 2 / 4), so one copy is used.
+int slot_replicas(int64_t, int, int, int, bool) { return 1; }
 
 // Largest particle tile whose histograms fit in 80 KB of LDS (two
 // work-groups per CU) and whose finish registers (PT / 2 bins x KT classes)

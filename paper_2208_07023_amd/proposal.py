@@ -66,9 +66,10 @@ def cluster_mixture_gpu(n: int, d: int, k: int, clusters_per_class: int, mean_st
 
 
 def harvest(n_trees: int, D: int, K: int, n_lo: int, n_hi: int, seed: int, P: int = 64,
-            T: int = 50, max_depth: int = 8, mean_std=(0.4, 1.5), device="cuda", log=None):
-    """Grow plain-PSO trees on seeded class mixtures (K classes x 4 clusters,
-    N log-uniform in [n_lo, n_hi], cluster spread uniform in mean_std) and
+            T: int = 50, max_depth: int = 8, mean_std=(0.4, 1.5), clusters: int = 4,
+            device="cuda", log=None):
+    """Grow plain-PSO trees on seeded class mixtures (K classes x `clusters`
+    clusters, N log-uniform in [n_lo, n_hi], cluster spread uniform in mean_std) and
     return the pairs of every split node: stats [n, (K+1) D], sigma [n, D],
     targets [n, D] (device float32)."""
     rng = np.random.default_rng(seed)
@@ -76,7 +77,7 @@ def harvest(n_trees: int, D: int, K: int, n_lo: int, n_hi: int, seed: int, P: in
     for t in range(n_trees):
         n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
         ms = float(rng.uniform(*mean_std))
-        X, y = cluster_mixture_gpu(n, D, K, 4, ms, int(rng.integers(1 << 31)), device)
+        X, y = cluster_mixture_gpu(n, D, K, clusters, ms, int(rng.integers(1 << 31)), device)
         cfg = api.TreeConfig(crit=api.ENTROPY, K=K, max_depth=max_depth, min_node=32, P=P, T=T,
                              bins=256, seed=seed, tree=t)
         tr = api.grow_tree(X, y, cfg, stats=True)
