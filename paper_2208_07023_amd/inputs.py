@@ -27,9 +27,10 @@ def f32_to_bf16_bits(a: np.ndarray) -> np.ndarray:
     Returns the 16-bit patterns as uint16.  NaNs are not produced by any
     generator here, so no NaN special case is needed.
     """
-    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    rounding_bias = ((u >> 16) & 1) + 0x7FFF
-    return ((u + rounding_bias) >> 16).astype(np.uint16)
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+    # finite inputs: u + 0x8000 cannot wrap below 0xFFFF8000 (a NaN pattern)
+    r = u + (np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1)))
+    return (r >> np.uint32(16)).astype(np.uint16)
 
 
 def bf16_bits_to_f32(b: np.ndarray) -> np.ndarray:
@@ -93,8 +94,8 @@ def lowrank_mixture(n: int, d: int = 256, k: int = 10, rank: int = 16, seed: int
     out = np.empty((n, d), dtype=np.uint16)
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
-        g = rng.standard_normal((e - s, rank)).astype(np.float32)
-        h = rng.standard_normal((e - s, d)).astype(np.float32)
+        g = rng.standard_normal((e - s, rank), dtype=np.float32)
+        h = rng.standard_normal((e - s, d), dtype=np.float32)
         x = means[y[s:e]] + g @ L.T + h * np.sqrt(delta)
         out[s:e] = f32_to_bf16_bits(x)
     return out, y
