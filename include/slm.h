@@ -130,6 +130,27 @@ slm_status slm_split_scan(const float *Z, int32_t z_layout, const float *zmin, c
                           void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * slm_evaluate -- one swarm evaluation fused: the projected features of
+ * slm_project (Sec. II-A, Eq. (1)) binned and scanned as by slm_split_scan
+ * (histogram mode, Sec. II-A Eqs. (3)-(4), Sec. III-B) without ever storing Z.
+ * A first pass computes zmin / zmax (written to the caller's arrays); the
+ * second recomputes each projection on the matrix cores and bins it from the
+ * registers.  Every z is the float32 number slm_project(..., SLM_Z_TILED)
+ * would store, so zmin / zmax, best_split, best_loss and threshold are
+ * identical to slm_project followed by slm_split_scan.
+ * X [N, D] and W [n_nodes*P, D] F32 with D <= 64; labels I32 with
+ * 2 <= K <= 4; crit SLM_GINI or SLM_ENTROPY; 2 <= bins <= 256.  Other
+ * combinations return SLM_E_UNSUPPORTED (use the two calls).  workspace as
+ * for slm_split_scan (slm_split_scan_workspace bytes, zero-filled before
+ * first use, left zero-filled).  Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_evaluate(const float *X, int64_t N, int32_t D, const float *W,
+                        const int64_t *row_off, int32_t n_nodes, int32_t P,
+                        const int32_t *labels, int32_t K, int32_t bins, int32_t crit, float *zmin,
+                        float *zmax, int32_t *best_split, double *best_loss, float *threshold,
+                        void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * slm_pso_init -- initial swarm of every node (Sec. III-A: particles start
  * at random positions; this build draws N(0, I) directions and scales them to
  * unit norm, Eq. (2), with zero velocity).

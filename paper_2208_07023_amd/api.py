@@ -75,6 +75,8 @@ _SIGS = {
     "slm_grow_tree": ([_VP, _I32, _I64, _I32, _VP, _I32, ctypes.POINTER(TreeParams), _VP, _SZ,
                        ctypes.POINTER(TreeOut), _VP], _I32),
     "slm_predict": ([_VP, _VP, _VP, _VP, _I32, _I32, _VP, _I64, _VP, _VP], _I32),
+    "slm_evaluate": ([_VP, _I64, _I32, _VP, _VP, _I32, _I32, _VP, _I32, _I32, _I32, _VP, _VP, _VP,
+                      _VP, _VP, _VP, _SZ, _VP], _I32),
     "slm_search_nodes_workspace": ([ctypes.POINTER(TreeParams), _I64, _I32, _I32], _SZ),
     "slm_search_nodes": ([_VP, _I32, _I64, _I32, _VP, _I32, _VP, _VP, _I32,
                           ctypes.POINTER(TreeParams), _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP],
@@ -234,6 +236,30 @@ def split_scan(Z, zmin, zmax, target, K: int, row_off, P: int, bins: int, crit: 
         out["counts"] = hist_t.view(nn * P, bins, kk) if crit != MSE else hist_t.view(nn * P, bins)
     if sums_t is not None:
         out["sums"] = sums_t.view(nn * P, bins, 2)
+    return out
+
+
+def evaluate(X, W, row_off, labels, K: int, P: int, bins: int, crit: int):
+    """Fused projection + histogram scan (float32, D <= 64, 2 <= K <= 4, Gini or
+    entropy): zmin, zmax, split, loss, thr as slm_project + slm_split_scan."""
+    load()
+    _dev(X, torch.float32, "X")
+    _dev(W, torch.float32, "W")
+    _dev(row_off, torch.int64, "row_off")
+    _dev(labels, torch.int32, "labels")
+    N, D = X.shape
+    nn = row_off.numel() - 1
+    dev = X.device
+    out = dict(zmin=torch.empty(nn * P, dtype=torch.float32, device=dev),
+               zmax=torch.empty(nn * P, dtype=torch.float32, device=dev),
+               split=torch.empty(nn * P, dtype=torch.int32, device=dev),
+               loss=torch.empty(nn * P, dtype=torch.float64, device=dev),
+               thr=torch.empty(nn * P, dtype=torch.float32, device=dev))
+    need = _lib.slm_split_scan_workspace(N, nn, P, bins, K, crit)
+    ws = scan_workspace(need, dev)
+    _check(_lib.slm_evaluate(_p(X), N, D, _p(W), _p(row_off), nn, P, _p(labels), K, bins, crit,
+                             _p(out["zmin"]), _p(out["zmax"]), _p(out["split"]), _p(out["loss"]),
+                             _p(out["thr"]), _p(ws), ws.numel(), _stream()), "slm_evaluate")
     return out
 
 

@@ -189,14 +189,19 @@ __device__ __forceinline__ SubTile next_subtile(const ProjectArgs &a, int j, int
   return {-1, 0, 0};
 }
 
-template <int KSP, bool BF16, bool VEC>
+// MASK = false leaves rows and dimensions outside the data as loaded (from a
+// clamped address) instead of zeroing them, so nothing consumes the loads
+// before the MFMAs do and they stay in flight: used for the A operand (X),
+// whose out-of-range rows are never stored and whose dimensions past D meet
+// zeros in the (masked) B operand.
+template <int KSP, bool BF16, bool VEC, bool MASK = true>
 __device__ __forceinline__ void load_run(const void *base, int64_t row, int D, int k0, bool ok,
                                          float (&v)[KSP]) {
   if constexpr (VEC) {
 #pragma unroll
     for (int q = 0; q < KSP / 4; ++q) {
       const int kk = k0 + 4 * q;
-      const bool in = ok && kk < D;
+      const bool in = !MASK || (ok && kk < D);
       const int64_t idx = row * D + (kk < D ? kk : 0);
       float t[4];
       if constexpr (BF16) {
@@ -220,20 +225,28 @@ __device__ __forceinline__ void load_run(const void *base, int64_t row, int D, i
     for (int s = 0; s < KSP; ++s) {
       const int kk = k0 + s;
       const float t = load_x<BF16>(base, row * D + (kk < D ? kk : D - 1));
-      v[s] = (ok && kk < D) ? t : 0.f;
+      v[s] = (!MASK || (ok && kk < D)) ? t : 0.f;
     }
   }
 }
 
-template <int FN, int WAVES, int KSP, bool XB, bool WB, bool VEC>
-__global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int64_t RB,
-                                                               int blocks_per_pt) {
+// STORE = false: only the per-column min / max (a.Z is not written), the
+// first pass of the fused evaluation.
+// RG row groups: the work-group's row run is cut into RG contiguous parts, and
+// the WAVES waves of each part cover the particle tile (RG WAVES waves).
+template <int FN, int WAVES, int KSP, bool XB, bool WB, bool VEC, bool STORE, int RG>
+__global__ __launch_bounds__(64 * WAVES * RG) void k_project_short(ProjectArgs a, int64_t RB,
+                                                                    int blocks_per_pt) {
   constexpr int PTILE = 32 * FN * WAVES;
   const int pt = blockIdx.x / blocks_per_pt;
-  const int64_t r_begin = (int64_t)(blockIdx.x % blocks_per_pt) * RB;
-  const int64_t r_end = r_begin + RB < a.N ? r_begin + RB : a.N;
+  const int64_t run0 = (int64_t)(blockIdx.x % blocks_per_pt) * RB;
+  const int64_t run1 = run0 + RB < a.N ? run0 + RB : a.N;
+  const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) % WAVES;
+  const int grp = (threadIdx.x >> 6) / WAVES;
+  const int64_t per = (run1 - run0 + RG - 1) / RG;
+  const int64_t r_begin = run0 + grp * per;
+  const int64_t r_end = r_begin + per < run1 ? r_begin + per : run1;
   if (r_begin >= r_end || a.n_nodes <= 0) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int D = a.D, P = a.P;
   const int li = lane & 31, kh = lane >> 5, k0 = kh * KSP;
   const int pw = pt * PTILE + wave * 32 * FN;   // first particle of this wave
@@ -273,8 +286,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
   };
 
   float acur[KSP], anext[KSP];
-  load_run<KSP, XB, VEC>(a.X, cur.lo + li < cur.hi ? cur.lo + li : cur.hi - 1, D, k0,
-                         cur.lo + li < cur.hi, acur);
+  load_run<KSP, XB, VEC, false>(a.X, cur.lo + li < cur.hi ? cur.lo + li : cur.hi - 1, D, k0,
+                                cur.lo + li < cur.hi, acur);
   while (cur.j >= 0) {
     if (cur.j != node_c) {
       flush();
@@ -290,8 +303,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
     }
     const SubTile nxt = next_subtile(a, cur.j, cur.hi, r_end);
     if (nxt.j >= 0)
-      load_run<KSP, XB, VEC>(a.X, nxt.lo + li < nxt.hi ? nxt.lo + li : nxt.hi - 1, D, k0,
-                             nxt.lo + li < nxt.hi, anext);
+      load_run<KSP, XB, VEC, false>(a.X, nxt.lo + li < nxt.hi ? nxt.lo + li : nxt.hi - 1, D, k0,
+                                    nxt.lo + li < nxt.hi, anext);
     f32x16 acc[FN];
 #pragma unroll
     for (int f = 0; f < FN; ++f) acc[f] = f32x16{};
@@ -306,14 +319,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
       const int p = pw + f * 32 + li;
-      float *zc = a.Z + z_col(a.zl, p < P ? p : P - 1) + (cur.lo + 4 * kh) * rs;
+      float *zc = STORE ? a.Z + z_col(a.zl, p < P ? p : P - 1) + (cur.lo + 4 * kh) * rs : nullptr;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int rr = 8 * (r >> 2) + (r & 3);
         const bool ok = interior || (p < P && cur.lo + 4 * kh + rr < cur.hi);
         if (ok) {
           const float z = acc[f][r];
-          zc[(int64_t)rr * rs] = z;
+          if constexpr (STORE) zc[(int64_t)rr * rs] = z;
           mn[f] = fminf(mn[f], z);
           mx[f] = fmaxf(mx[f], z);
         }
@@ -327,16 +340,30 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
 }
 
 // X float32 or bfloat16, W float32 (both widened exactly to float32)
-template <int FN, int WAVES, int KSP, bool VEC>
-slm_status launch_short_k(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
-  if (a.x_bf16)
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true, false, VEC>), dim3((unsigned)grid),
-                       dim3(64 * WAVES), 0, s, a, RB, bpp);
+template <int FN, int WAVES, int KSP, bool VEC, int RG>
+slm_status launch_short_g(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
+  const dim3 blk(64 * WAVES * RG);
+  if (a.Z == nullptr)   // min / max only (X float32)
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, false, VEC, false, RG>),
+                       dim3((unsigned)grid), blk, 0, s, a, RB, bpp);
+  else if (a.x_bf16)
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true, false, VEC, true, RG>),
+                       dim3((unsigned)grid), blk, 0, s, a, RB, bpp);
   else
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, false, VEC>), dim3((unsigned)grid),
-                       dim3(64 * WAVES), 0, s, a, RB, bpp);
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, false, VEC, true, RG>),
+                       dim3((unsigned)grid), blk, 0, s, a, RB, bpp);
   SLM_LAUNCHED();
   return SLM_OK;
+}
+
+// SLM_PROJ_RG = 2 splits every work-group's rows over two groups of waves
+// (tuning sweeps)
+template <int FN, int WAVES, int KSP, bool VEC>
+slm_status launch_short_k(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
+  const char *env = getenv("SLM_PROJ_RG");
+  if (env && env[0] == '2' && WAVES <= 4)
+    return launch_short_g<FN, WAVES, KSP, VEC, 2>(a, RB, bpp, grid, s);
+  return launch_short_g<FN, WAVES, KSP, VEC, 1>(a, RB, bpp, grid, s);
 }
 
 template <int FN, int WAVES, bool VEC>
@@ -574,6 +601,8 @@ slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s
 }
 
 slm_status launch_project(const ProjectArgs &a, hipStream_t s) {
+  SLM_CHECK(a.Z != nullptr || (a.D <= 64 && !a.x_bf16 && !a.w_bf16 && a.zmin), SLM_E_INVALID,
+            "slm_project: a min/max-only pass needs float32 data, D <= 64 and zmin/zmax");
   // both bfloat16: bfloat16 matrix cores
   if (a.x_bf16 && a.w_bf16) {
     if (a.P > 64) return launch_bf16<128, 128>(a, s);

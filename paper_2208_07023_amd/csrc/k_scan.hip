@@ -23,6 +23,7 @@
 #include "slm_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
@@ -278,7 +279,11 @@ Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
   } else {
     const int64_t n_pt = (P + pl.PT - 1) / pl.PT;
     const int64_t slots = 2 * (int64_t)num_cus();
-    const int64_t cmin = std::max<int64_t>(chunk_min(N), 2048);
+    // Small problems (one round of work-groups even at 4096-row chunks) take
+    // the longer chunks: fewer work-groups per node means fewer accumulator
+    // merges and less finish work (measured: N = 1e5, P = 256 root 70 -> 64
+    // us, 128 nodes of 781 rows 181 -> 156 us); large ones keep >= 2048.
+    const int64_t cmin = std::max<int64_t>(chunk_min(N), N * n_pt <= slots * 4096 ? 4096 : 2048);
     int64_t CH = cmin;
     for (int64_t m = 1; m <= 64; ++m) {
       const int64_t c = (N * n_pt + slots * m - 1) / (slots * m);
@@ -293,6 +298,12 @@ Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
 }
 
 // ---------------------------------------------------------------- finish
+// Particles per work-group of k_scan_finish: 4 (2 with 16 class slots), so a
+// large node's finish spreads over 8 (16) work-groups per 32-particle tile.
+__host__ __device__ constexpr int fin_nq(int PT, int KT) {
+  return PT < (KT <= 8 ? 4 : 2) ? PT : (KT <= 8 ? 4 : 2);
+}
+
 // Best split of NQ particles (q0 .. q0 + NQ - 1 of a PT-particle tile) of one
 // node from its complete histogram, by NT threads.  Thread t takes particle
 // q = t % NQ and the segment s = t / NQ of SEGB consecutive bins (NSEG =
@@ -736,7 +747,7 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
 template <int PT, int KT, bool MSE>
 __global__ __launch_bounds__(256) void k_scan_finish(ScanArgs a, int64_t CH, int n_pt,
                                                      size_t slot_sz, int64_t n_slots, int R) {
-  constexpr int NQ = PT < (KT <= 8 ? 8 : 4) ? PT : (KT <= 8 ? 8 : 4);
+  constexpr int NQ = fin_nq(PT, KT);
   constexpr int NGRP = PT / NQ;
   __shared__ __align__(16) unsigned char fin[finish_scratch_bytes<256, KT, MSE>()];
   __shared__ double lgt[2 * LG_TBL];
@@ -774,6 +785,143 @@ __global__ __launch_bounds__(256) void k_scan_finish(ScanArgs a, int64_t CH, int
   const FinishSrc src{gc, g1, g2, gc, g1, g2, R, (size_t)n_pt * slot_sz};
   finish_scan<NQ, 256, KT, MSE, true>(a, src, PT, pt, grp * NQ, (int64_t)lo * a.P, fin, lg, rc,
                                       tid);
+}
+
+// ---------------------------------------------------------------- fused evaluation
+// Projection and histogram scan in one pass (classification, float32 X and W,
+// D <= 64): the per-column min / max come from a first, store-free projection
+// pass; here every wave recomputes its 32-row sub-tiles of Z on the matrix
+// cores and bins them straight from the accumulator registers, so Z never
+// reaches memory.  A work-group is (chunk-of-node item, 32-particle tile) with
+// eight waves taking the item's sub-tiles in turn; lane (i, h) feeds row i
+// and dimensions h KSP + s at MFMA step s, exactly as the short projection
+// does, so every z is the float32 number the unfused path would store and the
+// histograms, splits and losses are identical.  Accumulator layout, merge of
+// multi-chunk nodes and finish are those of k_scan_hist (PT = 32).
+typedef float f32x16s __attribute__((ext_vector_type(16)));
+
+// MASK = false: values outside the data are left as loaded (see the
+// short projection: X rows out of range are never used, X dimensions past D
+// meet zeros in the masked W operand), so the loads stay in flight.
+template <int KSP, bool VEC, bool MASK = true>
+__device__ __forceinline__ void load_run_f32(const float *base, int64_t row, int D, int k0,
+                                             bool ok, float (&v)[KSP]) {
+  if constexpr (VEC) {
+#pragma unroll
+    for (int q = 0; q < KSP / 4; ++q) {
+      const int kk = k0 + 4 * q;
+      const bool in = !MASK || (ok && kk < D);
+      const float4 f = *reinterpret_cast<const float4 *>(base + row * D + (kk < D ? kk : 0));
+      v[4 * q + 0] = in ? f.x : 0.f;
+      v[4 * q + 1] = in ? f.y : 0.f;
+      v[4 * q + 2] = in ? f.z : 0.f;
+      v[4 * q + 3] = in ? f.w : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < KSP; ++q) {
+      const int kk = k0 + q;
+      const float t = base[row * D + (kk < D ? kk : D - 1)];
+      v[q] = (!MASK || (ok && kk < D)) ? t : 0.f;
+    }
+  }
+}
+
+template <int KSP, int KT, bool VEC>
+__global__ __launch_bounds__(HIST_WG) __attribute__((amdgpu_waves_per_eu(4)))
+void k_fused_hist(ScanArgs a, const float *X, const float *W, int D, int64_t CH, int n_pt,
+                  int64_t n_items, size_t slot_sz, int64_t n_slots) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int PT = 32, WGS = HIST_WG;
+  const int B = a.bins, K = a.K;
+  const HistLayout hl = hist_layout(PT, B, K, false);
+  uint32_t *hc = reinterpret_cast<uint32_t *>(smem);
+  double *lg = reinterpret_cast<double *>(smem + table_offset(PT, B, K, false));
+  double *rc = lg + LG_TBL;
+  const bool use_tbl = a.crit == SLM_ENTROPY;
+
+  // the particle tiles of one item run on one XCD (its L2 serves their X rows)
+  const int64_t bid = blockIdx.x;
+  const int64_t local = bid >> 3;
+  const int64_t v = (local / n_pt) * 8 + (bid & 7);
+  const int pt = (int)(local % n_pt);
+  if (v >= n_items) return;
+  const Item it = find_item(a.beg, a.end, a.n_nodes, a.N, CH, v);
+  if (it.node < 0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < hl.nwords; i += WGS) hc[i] = 0u;
+  if (use_tbl) fill_log_table(lg, rc, tid);
+  const int li = lane & 31, kh = lane >> 5;
+  const int P = a.P;
+  const int p = pt * PT + li;
+  const bool pv = p < P;
+  const int64_t np = (int64_t)it.node * P;
+  const BinRule rule = make_rule(pv ? a.zmin[np + p] : 0.f, pv ? a.zmax[np + p] : 0.f, B);
+  float bfrag[KSP];
+  load_run_f32<KSP, VEC>(W, np + (pv ? p : P - 1), D, kh * KSP, pv, bfrag);
+  lds_barrier();
+
+  const bool wave_fast = __all(rule.fast || !pv);
+  const float zmin = rule.zmin, delta = rule.delta, inv = rule.inv;
+  const float off0 = -fmaf(zmin, inv, 0.005f);
+  const unsigned bmax = (unsigned)B - 1u;
+  const unsigned labk = pv ? (unsigned)K : 0u;
+  const uint32_t pt4 = PT * 4u, pl4 = (uint32_t)li * 4u;
+  unsigned char *hb = reinterpret_cast<unsigned char *>(hc);
+  const int nsub = (int)((it.hi - it.lo + 31) / 32);
+
+  // A operands are single-buffered (the eight waves of two resident
+  // work-groups per CU hide the load latency); B stays in registers
+  float acur[KSP];
+  for (int t = wave; t < nsub; t += WGS / 64) {
+    const int64_t r0 = it.lo + 32 * (int64_t)t;
+    const int64_t rl = r0 + li;
+    load_run_f32<KSP, VEC, false>(X, rl < it.hi ? rl : it.hi - 1, D, kh * KSP, rl < it.hi, acur);
+    const int labv = a.labels[rl < it.hi ? rl : it.hi - 1];
+    f32x16s acc = f32x16s{};
+#pragma unroll
+    for (int ks = 0; ks < KSP; ++ks)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[ks], bfrag[ks], acc, 0, 0, 0);
+    // lane (li, kh), register r: row 8 (r / 4) + 4 kh + r % 4 of the sub-tile, particle li
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int rs = 8 * (r >> 2) + 4 * kh + (r & 3);
+      const int lab = __shfl(labv, rs);
+      const bool rin = r0 + rs < it.hi;
+      const float z = acc[r];
+      unsigned g;
+      if (wave_fast) {
+        const int g0 = (int)fmaf(z, inv, off0);
+        const float e1 = __fadd_rn(zmin, __fmul_rn((float)(g0 + 1), delta));
+        g = min((unsigned)(g0 + (e1 <= z ? 1 : 0)), bmax);
+      } else {
+        g = (unsigned)bin_of(rule, z);
+      }
+      const unsigned lb = min((unsigned)lab, (unsigned)K - 1u);
+      const uint32_t inc = (rin && (unsigned)lab < labk) ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
+      const uint32_t off = __umul24(__umul24(g & 127u, (unsigned)K) + lb, pt4) + pl4;
+      atomicAdd(reinterpret_cast<uint32_t *>(hb + off), inc);
+    }
+  }
+  lds_barrier();
+
+  // ---- a node spanning several chunks: add into its accumulator slot
+  if (it.nchunks > 1) {
+    const Range nr = load_range(a.beg, a.end, it.node, a.N);
+    const int64_t slot = nr.lo / CH;
+    if (slot >= n_slots) return;   // cannot happen with a workspace sized by the plan
+    unsigned long long *gc = reinterpret_cast<unsigned long long *>(
+        static_cast<unsigned char *>(a.ws) + ((size_t)slot * n_pt + pt) * slot_sz);
+    for (int i = tid; i < hl.nwords; i += WGS) {
+      const uint32_t w = hc[i];
+      if (w)
+        atomicAdd(&gc[i], (unsigned long long)(w & 0xFFFFu) | ((unsigned long long)(w >> 16) << 32));
+    }
+    return;
+  }
+  const FinishSrc src{hc, nullptr, nullptr, nullptr, nullptr, nullptr, 1, 0};
+  finish_scan<PT, WGS, KT, false, false>(a, src, PT, pt, 0, np, smem, lg, rc, tid);
 }
 
 // Nodes without rows get no work item in the histogram scan: report "no
@@ -1023,7 +1171,7 @@ slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
                      n_pt, pl.G, total, slot, n_slots, R);
   SLM_LAUNCHED();
   if (a.N > pl.CH) {   // some node may span several chunks
-    constexpr int NQ = PT < (KT <= 8 ? 8 : 4) ? PT : (KT <= 8 ? 8 : 4);
+    constexpr int NQ = fin_nq(PT, KT);
     const int64_t used = (a.N - 1) / pl.CH + 1;
     const int64_t grid_f = used * n_pt * (PT / NQ);
     SLM_CHECK(used <= n_slots && grid_f < (1ll << 31), SLM_E_SHAPE,
@@ -1125,6 +1273,89 @@ slm_status launch_scan_hist(const ScanArgs &a, hipStream_t s) {
   if (a.N <= 0 || a.n_nodes <= 0) return SLM_OK;
   const Plan pl = make_plan(a.N, a.n_nodes, a.P, a.bins, a.crit == SLM_MSE ? 1 : a.K, a.crit);
   return launch_hist(a, pl, s);
+}
+
+bool fused_eligible(const ScanArgs &a, int D, bool x_bf16, bool w_bf16) {
+  return D >= 1 && D <= 64 && !x_bf16 && !w_bf16 && a.crit != SLM_MSE && a.bins >= 2 &&
+         a.K >= 2 && a.K <= 4;
+}
+
+template <int KSP, int KT, bool VEC>
+static slm_status launch_fused_k(const ScanArgs &a, const float *X, const float *W, int D,
+                                 int64_t CH, hipStream_t s) {
+  constexpr int PT = 32;
+  const int n_pt = (a.P + PT - 1) / PT;
+  const int64_t items = num_items(a.n_nodes, a.N, CH);
+  if (items == 0) return SLM_OK;
+  const int64_t grid = (items + 7) / 8 * 8 * n_pt;
+  SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_evaluate: grid too large");
+  const bool table = a.crit == SLM_ENTROPY;
+  const size_t lds = lds_bytes(PT, a.bins, a.K, false, table);
+  const size_t slot = slot_bytes(PT, a.bins, a.K, false);
+  const int64_t n_slots = (a.N - 1) / chunk_min(a.N) + 1;
+  SLM_CHECK(slot_set_bytes(a.N, a.P, a.bins, a.K, false) <= a.ws_bytes, SLM_E_NOMEM,
+            "slm_evaluate: workspace of %zu bytes too small", a.ws_bytes);
+  hipLaunchKernelGGL((k_fused_hist<KSP, KT, VEC>), dim3((unsigned)grid), dim3(HIST_WG), lds, s, a,
+                     X, W, D, CH, n_pt, items, slot, n_slots);
+  SLM_LAUNCHED();
+  if (a.N > CH) {
+    constexpr int NQ = fin_nq(PT, KT);
+    const int64_t used = (a.N - 1) / CH + 1;
+    const int64_t grid_f = used * n_pt * (PT / NQ);
+    SLM_CHECK(used <= n_slots && grid_f < (1ll << 31), SLM_E_SHAPE,
+              "slm_evaluate: finish grid too large");
+    hipLaunchKernelGGL((k_scan_finish<PT, KT, false>), dim3((unsigned)grid_f), dim3(256), 0, s, a,
+                       CH, n_pt, slot, n_slots, 1);
+    SLM_LAUNCHED();
+  }
+  return SLM_OK;
+}
+
+template <int KSP, bool VEC>
+static slm_status launch_fused_v(const ScanArgs &a, const float *X, const float *W, int D,
+                                 int64_t CH, hipStream_t s) {
+  if (a.K == 2) return launch_fused_k<KSP, 2, VEC>(a, X, W, D, CH, s);
+  if (a.K == 3) return launch_fused_k<KSP, 3, VEC>(a, X, W, D, CH, s);
+  return launch_fused_k<KSP, 4, VEC>(a, X, W, D, CH, s);
+}
+
+// Second pass of the fused evaluation (zmin / zmax already computed by the
+// store-free projection pass).  Requires fused_eligible().
+slm_status launch_fused_hist(const ProjectArgs &pr, const ScanArgs &a, hipStream_t s) {
+  SLM_CHECK(fused_eligible(a, pr.D, pr.x_bf16, pr.w_bf16), SLM_E_UNSUPPORTED,
+            "slm_evaluate: the fused evaluation needs float32 data, D <= 64, 2 <= K <= 4 and "
+            "Gini or entropy");
+  if (a.N <= 0 || a.n_nodes <= 0) return SLM_OK;
+  const Plan pl = make_plan(a.N, a.n_nodes, a.P, a.bins, a.K, a.crit);
+  const int64_t CH = pl.CH;
+  const float *X = static_cast<const float *>(pr.X);
+  const float *W = static_cast<const float *>(pr.W);
+  const int D = pr.D;
+  const bool vec = D % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(W) % 16 == 0;
+  auto go = [&](auto ksp) -> slm_status {
+    constexpr int KSP = decltype(ksp)::value;
+    return vec ? launch_fused_v<KSP, true>(a, X, W, D, CH, s)
+               : launch_fused_v<KSP, false>(a, X, W, D, CH, s);
+  };
+  if (D <= 8) return go(std::integral_constant<int, 4>{});
+  if (D <= 16) return go(std::integral_constant<int, 8>{});
+  if (D <= 32) return go(std::integral_constant<int, 16>{});
+  return go(std::integral_constant<int, 32>{});
+}
+
+// Fused evaluation: the min / max pass (the short projection without Z
+// stores) then the fused projection-histogram pass.
+slm_status launch_fused_eval(const ProjectArgs &pr, const ScanArgs &a, hipStream_t s) {
+  SLM_CHECK(fused_eligible(a, pr.D, pr.x_bf16, pr.w_bf16), SLM_E_UNSUPPORTED,
+            "slm_evaluate: the fused evaluation needs float32 data, D <= 64, 2 <= K <= 4 and "
+            "Gini or entropy");
+  if (a.N <= 0 || a.n_nodes <= 0) return SLM_OK;
+  ProjectArgs p1 = pr;
+  p1.Z = nullptr;
+  slm_status st = launch_project(p1, s);
+  if (st) return st;
+  return launch_fused_hist(pr, a, s);
 }
 
 slm_status launch_scan_exact(const ScanArgs &a, int max_rows, hipStream_t s) {

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -473,12 +474,25 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
     if (!r && sc && p.bins) r = launch_scan_empty_nodes(x, s);
     return r;
   };
+  // The fused projection + histogram scan (slm_evaluate) is opt-in
+  // (SLM_FUSED=1): on MI355X at D = 64 the second MFMA projection it needs
+  // costs more than the round trip of Z through memory (plain-tree root: 191
+  // vs 135 us per evaluation).
+  const char *fz = getenv("SLM_FUSED");
+  const bool fused = !scr && fz && fz[0] == '1' && fused_eligible(sa, D, false, false);
+  ProjectArgs pmm = pr;
+  pmm.Z = nullptr;
   for (int t = 0; t <= p.T; ++t) {
     if (lt && (st = lt->begin(0, s))) return st;
-    if ((st = launch_project(pr, s))) return st;
+    if ((st = launch_project(fused ? pmm : pr, s))) return st;
     if (lt && (st = lt->end(s))) return st;
     if (lt && (st = lt->begin(1, s))) return st;
-    if ((st = scan(sa))) return st;
+    if (fused) {
+      if ((st = launch_fused_hist(pr, sa, s))) return st;
+      if (sc && (st = launch_scan_empty_nodes(sa, s))) return st;
+    } else if ((st = scan(sa))) {
+      return st;
+    }
     if (lt && (st = lt->end(s))) return st;
     if (scr) {
       if ((st = launch_screen_select(w.loss, na, p.P, k, w.sel, s))) return st;
@@ -524,7 +538,8 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)(p.precision == 1 ? p.rescore_k : 0), (uint64_t)p.proposal,
            (uint64_t)(uintptr_t)(p.proposal == 1 ? p.mlp : nullptr),
            (uint64_t)(p.proposal == 1 ? p.n_seeds : 0),
-           (uint64_t)(p.proposal == 1 ? p.mlp_hidden : 0)};
+           (uint64_t)(p.proposal == 1 ? p.mlp_hidden : 0),
+           (uint64_t)(getenv("SLM_FUSED") && getenv("SLM_FUSED")[0] == '1')};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -765,6 +780,45 @@ slm_status slm_screen_merge(const int32_t *sel, const double *loss_r, const int3
             "slm_screen_merge: NULL pointer");
   return launch_screen_merge(sel, loss_r, split_r, thr_r, n_nodes, P, k, loss, split, thr, gloss,
                              S(stream));
+}
+
+// ---------------------------------------------------------------- fused evaluation
+slm_status slm_evaluate(const float *X, int64_t N, int32_t D, const float *W,
+                        const int64_t *row_off, int32_t n_nodes, int32_t P,
+                        const int32_t *labels, int32_t K, int32_t bins, int32_t crit, float *zmin,
+                        float *zmax, int32_t *best_split, double *best_loss, float *threshold,
+                        void *workspace, size_t ws_bytes, void *stream) {
+  clear_error();
+  SLM_CHECK(N >= 0 && N < (1ll << 31), SLM_E_SHAPE, "slm_evaluate: N out of range");
+  SLM_CHECK(P >= 1 && P <= PMAX && n_nodes >= 0 && D >= 1 && D <= DMAX, SLM_E_SHAPE,
+            "slm_evaluate: bad sizes");
+  SLM_CHECK(bins >= 2 && bins <= 256, SLM_E_SHAPE, "slm_evaluate: bins = %d not in [2, 256]", bins);
+  SLM_CHECK(crit == SLM_GINI || crit == SLM_ENTROPY, SLM_E_UNSUPPORTED,
+            "slm_evaluate: Gini or entropy only");
+  SLM_CHECK(D <= 64 && K >= 2 && K <= 4, SLM_E_UNSUPPORTED,
+            "slm_evaluate: the fused evaluation takes D <= 64 and 2 <= K <= 4 (D = %d, K = %d)",
+            D, K);
+  if (N == 0 || n_nodes == 0) return SLM_OK;
+  SLM_CHECK(X && W && row_off && labels && zmin && zmax && best_split && best_loss && threshold &&
+                workspace,
+            SLM_E_INVALID, "slm_evaluate: NULL pointer");
+  const size_t need = scan_workspace_bytes(N, n_nodes, P, bins, K, crit);
+  SLM_CHECK(ws_bytes >= need, SLM_E_NOMEM, "slm_evaluate: workspace of %zu bytes, %zu needed",
+            ws_bytes, need);
+  hipStream_t s = S(stream);
+  slm_status st = launch_fill_minmax(zmin, zmax, (int64_t)n_nodes * P, s);
+  if (st) return st;
+  ProjectArgs pr{};
+  pr.X = X; pr.x_bf16 = 0; pr.w_bf16 = 0; pr.N = N; pr.D = D; pr.W = W; pr.beg = row_off;
+  pr.end = row_off + 1; pr.n_nodes = n_nodes; pr.P = P; pr.Z = nullptr; pr.zmin = zmin;
+  pr.zmax = zmax; pr.zl = zlayout_of(1, N, P);
+  ScanArgs sa{};
+  sa.Z = nullptr; sa.zl = pr.zl; sa.zmin = zmin; sa.zmax = zmax; sa.labels = labels; sa.y = nullptr;
+  sa.K = K; sa.N = N; sa.beg = row_off; sa.end = row_off + 1; sa.n_nodes = n_nodes; sa.P = P;
+  sa.bins = bins; sa.crit = crit; sa.best_split = best_split; sa.best_loss = best_loss;
+  sa.threshold = threshold; sa.ws = workspace; sa.ws_bytes = ws_bytes;
+  if ((st = launch_fused_eval(pr, sa, s))) return st;
+  return launch_scan_empty_nodes(sa, s);
 }
 
 // ---------------------------------------------------------------- node-batch search

@@ -194,6 +194,11 @@ slm_status launch_scan_hist(const ScanArgs &a, hipStream_t s);
 // "no split" outputs for nodes without rows (the histogram scan skips them)
 slm_status launch_scan_empty_nodes(const ScanArgs &a, hipStream_t s);
 slm_status launch_scan_exact(const ScanArgs &a, int max_rows, hipStream_t s);
+// fused projection + histogram scan (float32, D <= 64, 2 <= K <= 4, Gini /
+// entropy, particle-tiled layout of the scan arguments)
+bool fused_eligible(const ScanArgs &a, int D, bool x_bf16, bool w_bf16);
+slm_status launch_fused_eval(const ProjectArgs &pr, const ScanArgs &a, hipStream_t s);
+slm_status launch_fused_hist(const ProjectArgs &pr, const ScanArgs &a, hipStream_t s);
 
 struct PsoArgs {
   double *x, *v, *pbest, *pbest_loss, *gbest, *gbest_loss;

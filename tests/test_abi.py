@@ -119,6 +119,20 @@ def test_screen_validation():
     assert st == 0
 
 
+def test_evaluate_validation():
+    lib = api.load()
+    args = lambda D=8, K=3, bins=64, crit=api.GINI: (FAKE, 100, D, FAKE, FAKE, 1, 8, FAKE, K, bins,
+                                                     crit, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                                     1 << 30, None)
+    assert lib.slm_evaluate(*args(D=65)) == 6
+    assert lib.slm_evaluate(*args(K=5)) == 6
+    assert lib.slm_evaluate(*args(crit=api.MSE)) == 6
+    assert lib.slm_evaluate(*args(bins=1)) == 2
+    a = list(args())
+    a[17] = 16
+    assert lib.slm_evaluate(*a) == 4
+
+
 def test_grow_tree_precision_validation():
     lib = api.load()
     out = api.TreeOut()
