@@ -168,10 +168,13 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
 // alone, so every output element is the same MFMA sequence whatever FN,
 // WAVES and the split of the rows.
 constexpr int SR = 32;             // rows per sub-tile
+// Word 3 of a gfx9 raw buffer resource (32-bit data format, no swizzle).
+constexpr int BUF_DW3 = 0x00020000;
 
 struct SubTile {
   int j;                           // node (-1: none left)
   int64_t lo, hi;                  // rows lo .. hi-1 of node j, hi - lo <= SR
+  int64_t end;                     // end of node j's rows inside the run
 };
 
 // First sub-tile of rows >= r inside [.., r_end), starting the search at node j.
@@ -183,10 +186,17 @@ __device__ __forceinline__ SubTile next_subtile(const ProjectArgs &a, int j, int
     if (lo >= r_end) break;
     if (lo < nr.hi) {
       const int64_t hi = nr.hi < r_end ? nr.hi : r_end;
-      return {j, lo, hi < lo + SR ? hi : lo + SR};
+      return {j, lo, hi < lo + SR ? hi : lo + SR, hi};
     }
   }
-  return {-1, 0, 0};
+  return {-1, 0, 0, 0};
+}
+
+// The sub-tile after c: the next rows of the same node without touching
+// memory, else the first sub-tile of a later node.
+__device__ __forceinline__ SubTile advance(const ProjectArgs &a, const SubTile &c, int64_t r_end) {
+  if (c.hi < c.end) return {c.j, c.hi, c.hi + SR < c.end ? c.hi + SR : c.end, c.end};
+  return next_subtile(a, c.j + 1, c.hi, r_end);
 }
 
 // MASK = false leaves rows and dimensions outside the data as loaded (from a
@@ -231,27 +241,29 @@ __device__ __forceinline__ void load_run(const void *base, int64_t row, int D, i
 }
 
 // STORE = false: only the per-column min / max (a.Z is not written), the
-// first pass of the fused evaluation.
-// RG row groups: the work-group's row run is cut into RG contiguous parts, and
-// the WAVES waves of each part cover the particle tile (RG WAVES waves).
-template <int FN, int WAVES, int KSP, bool XB, bool WB, bool VEC, bool STORE, int RG>
-__global__ __launch_bounds__(64 * WAVES * RG) void k_project_short(ProjectArgs a, int64_t RB,
-                                                                    int blocks_per_pt) {
+// first pass of the fused evaluation.  TILED: Z in the particle-tiled layout,
+// whose row stride (32 floats) is then a constant, so the 16 stores of an
+// accumulator block use immediate offsets from one address.
+// The row loop is unrolled twice over two A buffers: the loads of the next
+// sub-tile go to the buffer the current MFMAs do not read.  A node change
+// (flush of the min / max, B fragments of the new node) happens before the
+// next sub-tile's loads are issued, so the MFMAs only wait for the B loads.
+// Full sub-tiles take a straight-line epilogue; sub-tiles cut by a node end or
+// columns past P take a masked one.
+template <int FN, int WAVES, int KSP, bool XB, bool VEC, bool STORE, bool TILED>
+__global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int64_t RB,
+                                                              int blocks_per_pt) {
   constexpr int PTILE = 32 * FN * WAVES;
   const int pt = blockIdx.x / blocks_per_pt;
-  const int64_t run0 = (int64_t)(blockIdx.x % blocks_per_pt) * RB;
-  const int64_t run1 = run0 + RB < a.N ? run0 + RB : a.N;
-  const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) % WAVES;
-  const int grp = (threadIdx.x >> 6) / WAVES;
-  const int64_t per = (run1 - run0 + RG - 1) / RG;
-  const int64_t r_begin = run0 + grp * per;
-  const int64_t r_end = r_begin + per < run1 ? r_begin + per : run1;
+  const int64_t r_begin = (int64_t)(blockIdx.x % blocks_per_pt) * RB;
+  const int64_t r_end = r_begin + RB < a.N ? r_begin + RB : a.N;
   if (r_begin >= r_end || a.n_nodes <= 0) return;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int D = a.D, P = a.P;
   const int li = lane & 31, kh = lane >> 5, k0 = kh * KSP;
   const int pw = pt * PTILE + wave * 32 * FN;   // first particle of this wave
   const bool wave_full = pw + 32 * FN <= P;     // every column of the wave exists
-  const int64_t rs = a.zl.rs;
+  const int64_t rs = TILED ? (int64_t)32 : a.zl.rs;
   const bool do_mm = a.zmin != nullptr;
 
   // first node whose rows reach past r_begin (ends are non-decreasing)
@@ -284,27 +296,33 @@ __global__ __launch_bounds__(64 * WAVES * RG) void k_project_short(ProjectArgs a
       }
     }
   };
-
-  float acur[KSP], anext[KSP];
-  load_run<KSP, XB, VEC, false>(a.X, cur.lo + li < cur.hi ? cur.lo + li : cur.hi - 1, D, k0,
-                                cur.lo + li < cur.hi, acur);
-  while (cur.j >= 0) {
-    if (cur.j != node_c) {
-      flush();
-      node_c = cur.j;
-      const int64_t wb = (int64_t)node_c * P;
+  // node change: publish the finished node's min / max, load the new node's
+  // directions
+  auto prep = [&](const SubTile &c) {
+    if (c.j == node_c) return;
+    flush();
+    node_c = c.j;
+    const int64_t wb = (int64_t)node_c * P;
 #pragma unroll
-      for (int f = 0; f < FN; ++f) {
-        const int p = pw + f * 32 + li;
-        load_run<KSP, WB, VEC>(a.W, wb + (p < P ? p : P - 1), D, k0, p < P, bfrag[f]);
-        mn[f] = __builtin_huge_valf();
-        mx[f] = -__builtin_huge_valf();
-      }
+    for (int f = 0; f < FN; ++f) {
+      const int p = pw + f * 32 + li;
+      load_run<KSP, false, VEC>(a.W, wb + (p < P ? p : P - 1), D, k0, p < P, bfrag[f]);
+      mn[f] = __builtin_huge_valf();
+      mx[f] = -__builtin_huge_valf();
     }
-    const SubTile nxt = next_subtile(a, cur.j, cur.hi, r_end);
-    if (nxt.j >= 0)
-      load_run<KSP, XB, VEC, false>(a.X, nxt.lo + li < nxt.hi ? nxt.lo + li : nxt.hi - 1, D, k0,
-                                    nxt.lo + li < nxt.hi, anext);
+    // Wait for the B loads here, on this rare path: a wait placed after the
+    // paths merge would also hold the common path until its stores drain
+    // (the vector memory counter counts stores too).
+#pragma unroll
+    for (int f = 0; f < FN; ++f)
+#pragma unroll
+      for (int k = 0; k < KSP; ++k) asm volatile("" ::"v"(bfrag[f][k]));
+  };
+  auto load_a = [&](const SubTile &c, float (&A)[KSP]) {
+    const bool ok = c.lo + li < c.hi;
+    load_run<KSP, XB, VEC, false>(a.X, ok ? c.lo + li : c.hi - 1, D, k0, ok, A);
+  };
+  auto compute = [&](const SubTile &c, const float (&A)[KSP]) {
     f32x16 acc[FN];
 #pragma unroll
     for (int f = 0; f < FN; ++f) acc[f] = f32x16{};
@@ -312,58 +330,105 @@ __global__ __launch_bounds__(64 * WAVES * RG) void k_project_short(ProjectArgs a
     for (int ks = 0; ks < KSP; ++ks)
 #pragma unroll
       for (int f = 0; f < FN; ++f)
-        acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[ks], bfrag[f][ks], acc[f], 0, 0, 0);
-    // Epilogue.  Lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4 of the
-    // sub-tile and particle column l%32 of block f.
-    const bool interior = wave_full && cur.hi - cur.lo == SR;
+        acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[ks], bfrag[f][ks], acc[f], 0, 0, 0);
+    // Lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4 of the sub-tile
+    // and particle column l%32 of block f.
+    if (wave_full && c.hi - c.lo == SR) {
 #pragma unroll
-    for (int f = 0; f < FN; ++f) {
-      const int p = pw + f * 32 + li;
-      float *zc = STORE ? a.Z + z_col(a.zl, p < P ? p : P - 1) + (cur.lo + 4 * kh) * rs : nullptr;
+      for (int f = 0; f < FN; ++f) {
+        if constexpr (STORE) {
+          float *zc = a.Z + z_col(a.zl, pw + f * 32 + li) + (c.lo + 4 * kh) * rs;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int rr = 8 * (r >> 2) + (r & 3);
-        const bool ok = interior || (p < P && cur.lo + 4 * kh + rr < cur.hi);
-        if (ok) {
-          const float z = acc[f][r];
-          if constexpr (STORE) zc[(int64_t)rr * rs] = z;
-          mn[f] = fminf(mn[f], z);
-          mx[f] = fmaxf(mx[f], z);
+          for (int r = 0; r < 16; ++r) zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = acc[f][r];
         }
+        float lo = acc[f][0], hi = acc[f][0];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) {
+          lo = fminf(lo, acc[f][r]);
+          hi = fmaxf(hi, acc[f][r]);
+        }
+        mn[f] = fminf(mn[f], lo);
+        mx[f] = fmaxf(mx[f], hi);
+      }
+    } else {
+      // Buffer stores whose offset is out of range (rows past the sub-tile,
+      // columns past P) are dropped by the hardware: the same 16 stores per
+      // block as above, with no branches, so the store count between the
+      // loads and their waits is the same on both paths.
+      const int nrow = (int)(c.hi - c.lo);
+      const uint32_t nb = (uint32_t)(nrow * rs * 4);
+#pragma unroll
+      for (int f = 0; f < FN; ++f) {
+        const bool pin = pw + f * 32 + li < P;
+        if constexpr (STORE) {
+          const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
+              a.Z + (int64_t)((pw >> 5) + f) * a.zl.ts + c.lo * rs, 0, nb, BUF_DW3);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
+            const uint32_t off =
+                pin && row < nrow ? (uint32_t)((row * rs + li) * 4) : 0x80000000u;
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(acc[f][r]), zr, (int)off, 0, 0);
+          }
+        }
+        float lo = __builtin_nanf(""), hi = __builtin_nanf("");
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
+          const float z = pin && row < nrow ? acc[f][r] : __builtin_nanf("");
+          lo = fminf(lo, z);
+          hi = fmaxf(hi, z);
+        }
+        mn[f] = fminf(mn[f], lo);
+        mx[f] = fmaxf(mx[f], hi);
       }
     }
+  };
+
+  float A0[KSP], A1[KSP];
+  load_a(cur, A0);
+  // Wait for the first tile before the loop, so that on entering the loop no
+  // load is newer than the stores the steady state has in flight.
 #pragma unroll
-    for (int ks = 0; ks < KSP; ++ks) acur[ks] = anext[ks];
+  for (int k = 0; k < KSP; ++k) asm volatile("" ::"v"(A0[k]));
+  while (true) {
+    prep(cur);
+    SubTile nxt = advance(a, cur, r_end);
+    load_a(nxt.j >= 0 ? nxt : cur, A1);
+    compute(cur, A0);
+    if (nxt.j < 0) break;
+    cur = nxt;
+    prep(cur);
+    nxt = advance(a, cur, r_end);
+    load_a(nxt.j >= 0 ? nxt : cur, A0);
+    compute(cur, A1);
+    if (nxt.j < 0) break;
     cur = nxt;
   }
   flush();
 }
 
 // X float32 or bfloat16, W float32 (both widened exactly to float32)
-template <int FN, int WAVES, int KSP, bool VEC, int RG>
+template <int FN, int WAVES, int KSP, bool VEC, bool TILED>
 slm_status launch_short_g(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
-  const dim3 blk(64 * WAVES * RG);
+  const dim3 blk(64 * WAVES);
   if (a.Z == nullptr)   // min / max only (X float32)
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, false, VEC, false, RG>),
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, VEC, false, TILED>),
                        dim3((unsigned)grid), blk, 0, s, a, RB, bpp);
   else if (a.x_bf16)
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true, false, VEC, true, RG>),
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true, VEC, true, TILED>),
                        dim3((unsigned)grid), blk, 0, s, a, RB, bpp);
   else
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, false, VEC, true, RG>),
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, VEC, true, TILED>),
                        dim3((unsigned)grid), blk, 0, s, a, RB, bpp);
   SLM_LAUNCHED();
   return SLM_OK;
 }
 
-// SLM_PROJ_RG = 2 splits every work-group's rows over two groups of waves
-// (tuning sweeps)
 template <int FN, int WAVES, int KSP, bool VEC>
 slm_status launch_short_k(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
-  const char *env = getenv("SLM_PROJ_RG");
-  if (env && env[0] == '2' && WAVES <= 4)
-    return launch_short_g<FN, WAVES, KSP, VEC, 2>(a, RB, bpp, grid, s);
-  return launch_short_g<FN, WAVES, KSP, VEC, 1>(a, RB, bpp, grid, s);
+  if (a.zl.rs == 32) return launch_short_g<FN, WAVES, KSP, VEC, true>(a, RB, bpp, grid, s);
+  return launch_short_g<FN, WAVES, KSP, VEC, false>(a, RB, bpp, grid, s);
 }
 
 template <int FN, int WAVES, bool VEC>
@@ -378,11 +443,14 @@ template <int FN, int WAVES>
 slm_status launch_short(const ProjectArgs &a, hipStream_t s) {
   constexpr int PTILE = 32 * FN * WAVES;
   const int64_t n_pt = (a.P + PTILE - 1) / PTILE;
-  // about two resident waves per SIMD over the whole launch; each work-group
-  // takes a contiguous run of rows (SLM_PROJ_RT overrides the run length)
-  const int64_t cap = (int64_t)num_cus_proj() * 8 / WAVES;
+  // One wave per SIMD over the whole launch (measured faster than two: a
+  // wave keeps its SIMD's matrix core busy on its own, and longer runs
+  // amortise its prologue); each work-group takes a contiguous run of whole
+  // 32-row sub-tiles (SLM_PROJ_RT overrides the run length).
+  const int64_t cap = std::max<int64_t>(1, (int64_t)num_cus_proj() * 4 / WAVES);
   int64_t bpp = std::max<int64_t>(1, std::min<int64_t>((a.N + SR - 1) / SR, cap / n_pt));
-  int64_t RB = (a.N + bpp - 1) / bpp;
+  int64_t RB = ((a.N + bpp - 1) / bpp + SR - 1) / SR * SR;
+  bpp = (a.N + RB - 1) / RB;
   if (const char *env = getenv("SLM_PROJ_RT")) {
     const long long v = atoll(env);
     if (v >= 1 && v <= (1 << 24)) {

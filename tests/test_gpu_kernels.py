@@ -28,6 +28,8 @@ def _t(a, dtype=None):
 @pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("D,P,sizes", [
     (8, 32, [1000]),
+    (16, 20, [45, 64, 0, 3]),
+    (40, 48, [100, 33, 0, 70]),
     (64, 256, [0, 1, 130, 777, 2]),
     (70, 48, [300, 0, 129]),
     (130, 1, [257, 64]),
