@@ -335,10 +335,13 @@ struct FinishSrc {
   size_t rstride;
 };
 
+// ntab / tn: when tn > 0, ntab[n] = nlog2n_cnt(n) for n < tn is filled here
+// (entropy), and counts below tn are looked up instead of evaluated.
 template <int NQ, int NT, int KT, bool MSE, bool GSRC>
 __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &src, int PT,
                                             int pt, int q0, int64_t np, unsigned char *fin,
-                                            const double *lg, const double *rc, int tid) {
+                                            const double *lg, const double *rc, int tid,
+                                            double *ntab = nullptr, int tn = 0) {
   constexpr int NSEG = NT / NQ;
   constexpr int SEGMAX = (256 + NSEG - 1) / NSEG;
   const int B = a.bins;
@@ -414,6 +417,7 @@ __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &
     stot1[seg * NQ + q] = t1;
     stot2[seg * NQ + q] = t2;
   }
+  for (int i = tid; i < tn; i += NT) ntab[i] = nlog2n_cnt((uint32_t)i, lg, rc);
   lds_barrier();
   if constexpr (GSRC) {
     // every thread's loads completed before the barrier: clear what was read
@@ -505,15 +509,18 @@ __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &
               const double sv = (double)AL / (double)nL + (double)AR / (double)nR;
               loss = (dn - sv) / dn;
             } else {
+              auto nl = [&](uint32_t v) {
+                return v < (uint32_t)tn ? ntab[v] : nlog2n_cnt(v, lg, rc);
+              };
               double sL = 0.0, sR = 0.0;
 #pragma unroll
               for (int k = 0; k < KT; ++k)
                 if (k < K) {
-                  sL += nlog2n_cnt(left[k], lg, rc);
-                  sR += nlog2n_cnt(tot[k] - left[k], lg, rc);
+                  sL += nl(left[k]);
+                  sR += nl(tot[k] - left[k]);
                 }
-              const double TL = nlog2n_cnt((uint32_t)nL, lg, rc) - sL;
-              const double TR = nlog2n_cnt((uint32_t)nR, lg, rc) - sR;
+              const double TL = nl((uint32_t)nL) - sL;
+              const double TR = nl((uint32_t)nR) - sR;
               loss = (TL + TR) / dn;
             }
           }
@@ -737,8 +744,16 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   }
 
   // ---- a node inside one chunk: finish from the LDS histogram
+  // n log2 n table for the node's counts (at most its row count) in the LDS
+  // between the finish scratch and the end of the histogram region
   const FinishSrc src{hc, hs1, hs2, nullptr, nullptr, nullptr, 1, 0};
-  finish_scan<PT, WGS, KT, MSE, false>(a, src, PT, pt, 0, np, smem, lg, rc, tid);
+  const size_t t0 = (finish_scratch_bytes<WGS, KT, MSE>() + 15) / 16 * 16;
+  const size_t t1 = table_offset(PT, B, K, MSE);
+  const int64_t tcap = t1 > t0 ? (int64_t)((t1 - t0) / 8) : 0;
+  const int64_t rows1 = it.hi - it.lo + 1;
+  const int tn = use_tbl ? (int)(rows1 < tcap ? rows1 : tcap) : 0;
+  finish_scan<PT, WGS, KT, MSE, false>(a, src, PT, pt, 0, np, smem, lg, rc, tid,
+                                       reinterpret_cast<double *>(smem + t0), tn);
 }
 
 // Completes the nodes that span several chunks, once every chunk's histogram
