@@ -145,6 +145,26 @@ def test_hist_scan_classification_exact(gpu_lib, crit, B, K, P, kind, tiled):
         assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("crit", [OS.GINI, OS.ENTROPY])
+@pytest.mark.parametrize("B,K,P,kind,tiled", [
+    (256, 3, 32, "gauss", True), (16, 10, 20, "gauss", False), (3, 4, 64, "dups", True),
+    (100, 16, 3, "gauss", True), (256, 2, 40, "const", False),
+])
+def test_hist_scan_classification_large_node(gpu_lib, crit, B, K, P, kind, tiled):
+    # a node of many chunks among few nodes: finished one bin per thread
+    sizes = [45000, 7]
+    got, ref = _scan_case(gpu_lib, sizes, P, B, crit, K, kind, seed=B + K + P, tiled=tiled)
+    assert np.array_equal(got["counts"].astype(np.int64), ref["counts"])
+    assert np.array_equal(got["split"], ref["split"])
+    assert np.array_equal(got["thr"], ref["thr"])
+    fin = np.isfinite(ref["loss"])
+    assert np.array_equal(np.isfinite(got["loss"]), fin)
+    if crit == OS.GINI:
+        assert np.array_equal(got["loss"][fin], ref["loss"][fin])
+    else:
+        assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-12, atol=1e-15)
+
+
 @pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("B,P,kind", [(256, 16, "gauss"), (64, 33, "dups"), (7, 4, "gauss")])
 def test_hist_scan_regression(gpu_lib, B, P, kind, tiled):
@@ -162,10 +182,12 @@ def test_hist_scan_regression(gpu_lib, B, P, kind, tiled):
         assert abs(got["loss"][i] - ref["loss"][i]) <= 1e-9 * abs(ref["loss"][i])
 
 
-def test_hist_scan_reuses_zeroed_workspace(gpu_lib):
-    """Two calls in a row on the same workspace (multi-chunk nodes) agree."""
-    a, ref = _scan_case(gpu_lib, [9000, 3000], 32, 256, OS.GINI, 3, "gauss", seed=5)
-    b, _ = _scan_case(gpu_lib, [9000, 3000], 32, 256, OS.GINI, 3, "gauss", seed=5)
+@pytest.mark.parametrize("sizes", [[9000, 3000], [40000]])
+def test_hist_scan_reuses_zeroed_workspace(gpu_lib, sizes):
+    """Two calls in a row on the same workspace (multi-chunk nodes, both
+    finish kernels) agree."""
+    a, ref = _scan_case(gpu_lib, sizes, 32, 256, OS.GINI, 3, "gauss", seed=5)
+    b, _ = _scan_case(gpu_lib, sizes, 32, 256, OS.GINI, 3, "gauss", seed=5)
     for k in ("counts", "split", "loss", "thr"):
         assert np.array_equal(a[k], b[k])
     assert np.array_equal(a["split"], ref["split"])
