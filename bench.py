@@ -31,6 +31,37 @@ METRIC = "projected sample-splits/s; SLM tree train time, learned vs plain @ equ
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a
+# second run, WRITE_SIZE (KiB per dispatch, mean over the dispatches of one
+# timed and one instrumented tree of this workload), scaled by what the same
+# counters read for a plain 1 GiB device copy (FETCH_SIZE 524302 KiB -> x 2.0,
+# WRITE_SIZE 1048576 KiB -> x 1.0).  Valid only for the kernel source they were
+# taken on (SHA-256 of the file); otherwise the traffic is reported as null.
+# Summary and commands: profiles/traffic_plain_tree_N100k_D64_P256.md
+TRAFFIC = {
+    "k_scan_hist": {"source": "paper_2208_07023_amd/csrc/k_scan.hip",
+                    "sha256": "a8c3263a276ed1700f91621f6d476ac002a5e41fa9f49312d589aee2f0991501",
+                    "fetch_kib": 43121.9, "write_kib": 12024.0},
+    "k_scan_finish_bins": {"source": "paper_2208_07023_amd/csrc/k_scan.hip",
+                           "sha256": "a8c3263a276ed1700f91621f6d476ac002a5e41fa9f49312d589aee2f0991501",
+                           "fetch_kib": 3180.0, "write_kib": 3096.0},
+    "k_project": {"source": "paper_2208_07023_amd/csrc/k_project.hip",
+                  "sha256": "7f66646c62f54173b049899dd93751601527a6123bfb5482ba9c98da6e7f0d64",
+                  "fetch_kib": 10790.8, "write_kib": 83735.5},
+}
+FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.3, 1.0
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the stored counters, or None when
+    its source has changed since they were taken."""
+    import hashlib
+    t = TRAFFIC[kernel]
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    return (t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -180,14 +211,19 @@ def main():
         "pso_step": {"ms_total": tm[5]},
         "tree_ms_profiled": tm[0],
     }
-    if scan_ms >= proj_ms:
-        roof = {"bound": "hbm", "kernel": "k_scan_hist", "achieved": scan_gbs, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": scan_gbs / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": scan_bytes / max(1, tm[7])}
-    else:
-        roof = {"bound": "mfma", "kernel": "k_project", "achieved": proj_tfs,
-                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": proj_tfs / FP32_PEAK_TFLOPS,
-                "traffic": None, "flops_per_launch": proj_flops / max(1, tm[6])}
+    # The roofline is the projection's: it is the largest single kernel of the
+    # tree (profiles/kernels_plain_tree_N100k_D64_P256.md: 41.6% of GPU time,
+    # against 35.4% for the histogram kernel), and its events bracket that one
+    # kernel.  The scan step's events bracket two kernels (histogram and
+    # multi-chunk finish); it is reported under "kernels" with the traffic of
+    # both.
+    roof = {"bound": "mfma", "kernel": "k_project_short", "achieved": proj_tfs,
+            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": proj_tfs / FP32_PEAK_TFLOPS,
+            "traffic": measured_traffic("k_project"),
+            "flops_per_launch": proj_flops / max(1, tm[6])}
+    th, tf = measured_traffic("k_scan_hist"), measured_traffic("k_scan_finish_bins")
+    kernels["scan"]["traffic_per_launch"] = th + tf if th is not None and tf is not None else None
+    kernels["scan"]["bytes_per_launch"] = scan_bytes / max(1, tm[7])
 
     acc = float((api.predict(trees[0], Xd) == y).mean())
     out = {
