@@ -63,11 +63,14 @@ def normalize_rows(x):
     return out, ok
 
 
-def init_positions(seed, tree, node, P, D):
+def init_positions(seed, tree, node, P, D, mask=None):
     """x0 [P, D]: Box-Muller normals from the INIT_STREAM words, unit rows.
 
     u1 = (w0 + 1/2) 2^-32, u2 = w1 2^-32; the pair is
-    sqrt(-2 ln u1) * (cos(2 pi u2), sin(2 pi u2)) for dimensions 2m, 2m+1."""
+    sqrt(-2 ln u1) * (cos(2 pi u2), sin(2 pi u2)) for dimensions 2m, 2m+1.
+    mask [D] bool, if given: the normals of dimensions outside it are set to
+    zero before the rows are scaled (a start in the span of the masked-in
+    unit vectors, oracle.dft)."""
     w = _words(seed, tree, node, INIT_STREAM, P, D)
     u1 = (w[..., 0].astype(np.float64) + 0.5) * (2.0 ** -32)
     u2 = w[..., 1].astype(np.float64) * (2.0 ** -32)
@@ -76,7 +79,10 @@ def init_positions(seed, tree, node, P, D):
     g = np.empty((P, 2 * w.shape[1]))
     g[:, 0::2] = rad * np.cos(ang)
     g[:, 1::2] = rad * np.sin(ang)
-    x, _ = normalize_rows(g[:, :D])
+    g = g[:, :D]
+    if mask is not None:
+        g = np.where(np.asarray(mask, dtype=bool)[None, :], g, 0.0)
+    x, _ = normalize_rows(g)
     return x
 
 

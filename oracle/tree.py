@@ -6,8 +6,9 @@ Readings of the paper used here:
   at least min_node samples and is impure (classification: impurity > 0;
   regression: not all targets equal) -- the paper's "pure enough" and "small
   enough" stopping rule (Sec. II-A);
-* the swarm runs in all D input dimensions (the top-n channel selection of
-  Alg. 2 uses n = D);
+* the swarm runs in all D input dimensions unless dft_top_n = n with
+  0 < n < D: then every searched node first runs the DFT and the swarm
+  starts in the span of its top n channels (oracle.dft; Alg. 2);
 * the split is kept only if the global-best loss is strictly below the node's
   own impurity; the children are the samples with a^T x >= t (right) and
   a^T x < t (left), in their original order;
@@ -22,6 +23,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import dft
 from . import screen
 from . import split as S
 from .pso import run_pso
@@ -43,6 +45,7 @@ class TreeParams:
     tree: int = 0
     precision: int = 0         # 1 = bfloat16 screening, float32 re-scoring
     rescore_k: int = 32
+    dft_top_n: int = 0         # 0 < n < D: swarm in the node's top n DFT channels
 
 
 @dataclass
@@ -138,8 +141,12 @@ def grow_tree(X, target, prm: TreeParams, rows=None, keep_rows=False):
                 continue
             Xn = X[rws]
             tn = target[rws]
+            x0 = None
+            if 0 < prm.dft_top_n < D:
+                sel = dft.top_n(dft.dft_losses(Xn, tn, prm.crit, prm.K, prm.bins), prm.dft_top_n)
+                x0 = dft.subspace_start(prm.seed, prm.tree, hid, prm.P, D, sel)
             res = run_pso(evaluate_node(Xn, tn, prm), prm.P, D, prm.T, prm.omega,
-                          prm.c1, prm.c2, prm.seed, prm.tree, hid)
+                          prm.c1, prm.c2, prm.seed, prm.tree, hid, x0=x0)
             tr.split_loss[idx] = res["loss"]
             if not res["loss"] < imp:
                 continue
