@@ -171,6 +171,48 @@ slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss,
                         void *stream);
 
 /* ------------------------------------------------------------------------
+ * slm_pso_init_subspace -- slm_pso_init with each node's swarm started in
+ * the span of n_sel of its input dimensions (Alg. 2: the swarm runs in the
+ * node's top n channels).  sel [n_nodes, n_sel] ([device] int32) lists the
+ * dimensions of node j in row j; the same normals as slm_pso_init are drawn,
+ * those of unlisted dimensions are replaced by zero before each row is
+ * divided by its norm.  The swarm steps keep the unlisted coordinates at zero
+ * (x, v and the bests are zero there).  1 <= n_sel <= D; indices outside
+ * [0, D) are ignored.  Other arguments and outputs as slm_pso_init.
+ * ------------------------------------------------------------------------ */
+slm_status slm_pso_init_subspace(double *x, double *v, double *pbest, double *pbest_loss,
+                                 double *gbest, double *gbest_loss, int32_t *gbest_p,
+                                 const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
+                                 uint64_t seed, uint32_t tree, void *W_out, int32_t w_dtype,
+                                 const int32_t *sel, int32_t n_sel, void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_dft_select -- discriminant feature test of every node and its top n
+ * channels (Sec. II-A: the DFT selects the threshold of a 1-D subspace;
+ * Alg. 2: run the DFT for the node, select the top n channels).
+ *
+ * The DFT loss of input feature d of node j is the loss of the best
+ * threshold of x_d over the node's rows: x_d is the projection on the unit
+ * vector e_d, so it is binned and scanned exactly as slm_split_scan treats a
+ * projected feature (histogram edges over the node's [min, max] of x_d, or
+ * the exact scan with bins = 0; +inf when no threshold splits the node).
+ * X [N, D] F32 row-major, row_off [n_nodes + 1] (int64, non-decreasing),
+ * target: I32 labels (K classes, Gini / entropy) or F64 y (SLM_MSE, K = 0);
+ * all [device].  Outputs [device]: dft_loss [n_nodes, D]; sel [n_nodes, n]:
+ * the n features of smallest loss of each node, ascending by (loss, index).
+ * workspace: slm_dft_select_workspace bytes ([device], zero-filled before
+ * first use and left zero-filled; it holds the scan's accumulators and the
+ * per-node column min / max).  1 <= n <= D <= 4096; the exact scan needs
+ * nodes of at most 8192 rows.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+size_t slm_dft_select_workspace(int64_t N, int32_t D, int32_t n_nodes, int32_t bins, int32_t K,
+                                int32_t crit);
+slm_status slm_dft_select(const float *X, int64_t N, int32_t D, const int64_t *row_off,
+                          int32_t n_nodes, const void *target, int32_t t_dtype, int32_t K,
+                          int32_t bins, int32_t crit, int32_t n, double *dft_loss, int32_t *sel,
+                          void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * slm_pso_step -- one synchronous swarm step for every node (Sec. III-A,
  * Eqs. (11)-(12), Alg. 1).
  *
@@ -280,6 +322,11 @@ typedef struct {
   int32_t n_seeds;     /* M seeds per node (network output M * D)        */
   int32_t mlp_hidden;  /* hidden width H (network input (K + 1) * D)     */
   const float *mlp;    /* [device] packed parameters, slm_mlp_param_count */
+  int32_t dft_top_n;   /* 0 or D: the swarm searches all D dimensions;
+                          1..D-1: every searched node first runs the DFT
+                          (slm_dft_select) and its swarm starts in the span
+                          of its top dft_top_n channels (Alg. 2);
+                          float32 data (precision 0) only                  */
 } slm_tree_params;
 
 typedef struct {

@@ -39,7 +39,7 @@ class TreeParams(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("tree", ctypes.c_uint32), ("use_graph", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("proposal", ctypes.c_int32),
                 ("n_seeds", ctypes.c_int32), ("mlp_hidden", ctypes.c_int32),
-                ("mlp", ctypes.c_void_p)]
+                ("mlp", ctypes.c_void_p), ("dft_top_n", ctypes.c_int32)]
 
 
 class TreeOut(ctypes.Structure):
@@ -66,6 +66,11 @@ _SIGS = {
     "slm_split_scan": ([_VP, _I32, _VP, _VP, _VP, _I32, _I32, _I64, _VP, _I32, _I32, _I32, _I32,
                         _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], _I32),
     "slm_pso_init": ([_VP] * 7 + [_VP, _I32, _I32, _I32, _U64, _U32, _VP, _I32, _VP], _I32),
+    "slm_pso_init_subspace": ([_VP] * 7 + [_VP, _I32, _I32, _I32, _U64, _U32, _VP, _I32, _VP,
+                                           _I32, _VP], _I32),
+    "slm_dft_select_workspace": ([_I64, _I32, _I32, _I32, _I32, _I32], _SZ),
+    "slm_dft_select": ([_VP, _I64, _I32, _VP, _I32, _VP, _I32, _I32, _I32, _I32, _I32, _VP, _VP,
+                        _VP, _SZ, _VP], _I32),
     "slm_pso_step": ([_VP] * 7 + [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _I32, _D, _D,
                                   _D, _U64, _U32, _U32, _I32, _VP, _I32, _VP], _I32),
     "slm_screen_select": ([_VP, _I32, _I32, _I32, _VP, _VP], _I32),
@@ -294,13 +299,49 @@ def pso_alloc(n_nodes: int, P: int, D: int, node_id, w_dtype=torch.float32, devi
                  P=P, D=D)
 
 
-def pso_init(sw: Swarm, seed: int, tree: int):
+def pso_init(sw: Swarm, seed: int, tree: int, sel=None):
+    """Initial swarm of every node; with sel (device int32 [n_nodes, n]) each
+    node's swarm starts in the span of its listed dimensions
+    (slm_pso_init_subspace)."""
     load()
     nn = sw.node_id.numel()
     wt = BF16 if sw.W.dtype == torch.bfloat16 else F32
-    _check(_lib.slm_pso_init(_p(sw.x), _p(sw.v), _p(sw.pbest), _p(sw.pbest_loss), _p(sw.gbest),
-                             _p(sw.gbest_loss), _p(sw.gbest_p), _p(sw.node_id), nn, sw.P, sw.D,
-                             seed, tree, _p(sw.W), wt, _stream()), "slm_pso_init")
+    if sel is None:
+        _check(_lib.slm_pso_init(_p(sw.x), _p(sw.v), _p(sw.pbest), _p(sw.pbest_loss),
+                                 _p(sw.gbest), _p(sw.gbest_loss), _p(sw.gbest_p), _p(sw.node_id),
+                                 nn, sw.P, sw.D, seed, tree, _p(sw.W), wt, _stream()),
+               "slm_pso_init")
+        return
+    _dev(sel, torch.int32, "sel")
+    if sel.dim() != 2 or sel.shape[0] != nn:
+        raise ValueError("sel must be [n_nodes, n]")
+    _check(_lib.slm_pso_init_subspace(_p(sw.x), _p(sw.v), _p(sw.pbest), _p(sw.pbest_loss),
+                                      _p(sw.gbest), _p(sw.gbest_loss), _p(sw.gbest_p),
+                                      _p(sw.node_id), nn, sw.P, sw.D, seed, tree, _p(sw.W), wt,
+                                      _p(sel), sel.shape[1], _stream()), "slm_pso_init_subspace")
+
+
+def dft_select(X, target, K: int, row_off, bins: int, crit: int, n: int):
+    """Discriminant feature test of every node and its top n channels
+    (slm_dft_select): (dft_loss float64 [n_nodes, D], sel int32 [n_nodes, n])."""
+    load()
+    _dev(X, torch.float32, "X")
+    _dev(row_off, torch.int64, "row_off")
+    N, D = X.shape
+    nn = row_off.numel() - 1
+    if crit == MSE:
+        _dev(target, torch.float64, "target")
+        tt = F64
+    else:
+        _dev(target, torch.int32, "target")
+        tt = I32
+    loss = torch.empty(nn, D, dtype=torch.float64, device=X.device)
+    sel = torch.empty(nn, n, dtype=torch.int32, device=X.device)
+    ws = scan_workspace(_lib.slm_dft_select_workspace(N, D, nn, bins, K, crit), X.device)
+    _check(_lib.slm_dft_select(_p(X), N, D, _p(row_off), nn, _p(target), tt, K, bins, crit, n,
+                               _p(loss), _p(sel), _p(ws), ws.numel(), _stream()),
+           "slm_dft_select")
+    return loss, sel
 
 
 def pso_step(sw: Swarm, loss, omega, c1, c2, seed, tree, it, move, split=None, thr=None,
@@ -383,6 +424,7 @@ class TreeConfig:
     n_seeds: int = 64
     mlp_hidden: int = 256
     mlp: object = None
+    dft_top_n: int = 0          # 1..D-1: swarm in each node's top n DFT channels
 
     def c_params(self) -> TreeParams:
         mlp = None
@@ -392,7 +434,8 @@ class TreeConfig:
         return TreeParams(self.crit, self.K, self.max_depth, self.min_node, self.P, self.T,
                           self.bins, self.precision, self.rescore_k, self.omega, self.c1,
                           self.c2, self.seed, self.tree, int(self.use_graph), int(self.profile),
-                          int(self.proposal), self.n_seeds, self.mlp_hidden, mlp)
+                          int(self.proposal), self.n_seeds, self.mlp_hidden, mlp,
+                          int(self.dft_top_n))
 
 
 _tree_ws: dict = {}

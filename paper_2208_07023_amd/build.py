@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libslm.so")
 
-SOURCES = ["k_project.hip", "k_scan.hip", "k_pso.hip", "k_screen.hip", "k_mlp.hip", "k_tree.hip",
+SOURCES = ["k_project.hip", "k_scan.hip", "k_pso.hip", "k_screen.hip", "k_mlp.hip", "k_tree.hip", "k_dft.hip",
            "slm_api.cpp"]
 HEADERS = ["slm_internal.hpp"]
 

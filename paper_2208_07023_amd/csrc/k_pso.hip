@@ -62,6 +62,7 @@ __host__ __device__ __forceinline__ MoveGeom move_geom(int D) {
 __global__ __launch_bounds__(MOVE_WG) void k_pso_init(PsoArgs a) {
   extern __shared__ double buf[];          // [PPB][D]
   __shared__ double nrm_s[MOVE_WG];
+  __shared__ unsigned char keep[DMAX];     // with dim_sel: dimensions drawn
   const MoveGeom g = move_geom(a.D);
   const int bpn = (a.P + g.PPB - 1) / g.PPB; // blocks per node
   const int j = blockIdx.x / bpn;
@@ -74,6 +75,16 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_init(PsoArgs a) {
   rng_key(a, &key, &tree);
   const uint32_t node = (uint32_t)a.node_id[j];
   const int64_t gid = (int64_t)j * a.P + p;
+  const bool masked = a.dim_sel != nullptr;
+  if (masked) {
+    for (int d = threadIdx.x; d < D; d += MOVE_WG) keep[d] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.n_sel; i += MOVE_WG) {
+      const int d = a.dim_sel[(int64_t)j * a.n_sel + i];
+      if (d >= 0 && d < D) keep[d] = 1;
+    }
+    __syncthreads();
+  }
   if (pv) {
     for (int d = dl; d < D; d += g.Dp) {
       const int m = d >> 1;
@@ -82,7 +93,9 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_init(PsoArgs a) {
       const double u2 = (double)w.y * 0x1p-32;
       const double rad = sqrt(-2.0 * log(u1));
       const double ang = 6.283185307179586 * u2;
-      buf[pl * D + d] = (d & 1) ? rad * sin(ang) : rad * cos(ang);
+      const double gv = (d & 1) ? rad * sin(ang) : rad * cos(ang);
+      // outside the selected channels the normal is replaced by zero
+      buf[pl * D + d] = masked && !keep[d] ? 0.0 : gv;
     }
   }
   __syncthreads();

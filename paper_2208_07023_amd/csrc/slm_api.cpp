@@ -75,6 +75,11 @@ struct TreeWS {
   double *stat_sums;
   uint32_t *stat_counts;
   float *stats, *sigma, *mlp_cache, *mlp_out;
+  // top-n DFT channels (dft_top_n): losses, selection, scan scratch
+  double *dft_loss;
+  int32_t *dft_sel;
+  void *dft_ws;
+  size_t dft_ws_bytes;
   // node-batch search: active row ends, stop state
   int64_t *end_act;
   int32_t *done;
@@ -161,6 +166,12 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base, int sea
     w.thr_r = c.take<float>((size_t)F * k);
     w.gloss = c.take<double>((size_t)F * p.P);
   }
+  if (p.dft_top_n > 0 && p.dft_top_n < D) {
+    w.dft_loss = c.take<double>((size_t)F * D);
+    w.dft_sel = c.take<int32_t>((size_t)F * p.dft_top_n);
+    w.dft_ws_bytes = dft_workspace_bytes(N, (int)F, D, p.bins, p.K, p.crit);
+    w.dft_ws = c.take<char>(w.dft_ws_bytes);
+  }
   w.st.counts = c.take<uint32_t>((size_t)2 * F * Kc);
   w.st.cnt = c.take<uint32_t>((size_t)2 * F);
   w.st.s1 = c.take<double>((size_t)2 * F);
@@ -199,6 +210,11 @@ slm_status check_tree_params(const slm_tree_params *p, int64_t N, int32_t D) {
   if (p->precision == 1)
     SLM_CHECK(p->rescore_k >= 1 && p->rescore_k <= p->P, SLM_E_SHAPE,
               "slm_grow_tree: rescore_k = %d not in [1, P]", p->rescore_k);
+  SLM_CHECK(p->dft_top_n >= 0 && p->dft_top_n <= D, SLM_E_SHAPE,
+            "slm_grow_tree: dft_top_n = %d not in [0, D]", p->dft_top_n);
+  if (p->dft_top_n > 0 && p->dft_top_n < D)
+    SLM_CHECK(p->precision == 0, SLM_E_UNSUPPORTED,
+              "slm_grow_tree: dft_top_n needs float32 data (precision 0)");
   SLM_CHECK(p->proposal == 0 || p->proposal == 1, SLM_E_INVALID,
             "slm_grow_tree: proposal %d (0 = random, 1 = learned)", p->proposal);
   if (p->proposal == 1) {
@@ -441,8 +457,25 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pa.gloss = scr ? w.gloss : nullptr;
   pa.zmin_reset = w.zmin; pa.zmax_reset = w.zmax;
   pa.seed_tree_dev = w.seed_tree;
-  slm_status st = launch_pso_init(pa, s);
+  slm_status st;
+  if (p.dft_top_n > 0 && p.dft_top_n < D) {
+    // Alg. 2: the DFT of every node, then the swarm starts in the span of
+    // its top dft_top_n channels
+    DftArgs da{};
+    da.X = static_cast<const float *>(Xc); da.N = N; da.D = D; da.beg = w.beg;
+    da.end = sc ? w.end_act : w.end; da.n_nodes = na;
+    da.labels = mse ? nullptr : static_cast<const int32_t *>(tc);
+    da.y = mse ? static_cast<const double *>(tc) : nullptr;
+    da.K = p.K; da.bins = p.bins; da.crit = p.crit; da.n = p.dft_top_n;
+    da.loss = w.dft_loss; da.sel = w.dft_sel; da.ws = w.dft_ws; da.ws_bytes = w.dft_ws_bytes;
+    if ((st = launch_dft_select(da, s))) return st;
+    pa.dim_sel = w.dft_sel;
+    pa.n_sel = p.dft_top_n;
+  }
+  st = launch_pso_init(pa, s);
   if (st) return st;
+  pa.dim_sel = nullptr;
+  pa.n_sel = 0;
   if (p.proposal == 1 && (st = learned_start(p, w, Xc, tc, N, D, na, s))) return st;
   // a search skips the rows of stopped nodes: their active end collapses to
   // their start, and their scan results read "no split"
@@ -539,7 +572,8 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)(uintptr_t)(p.proposal == 1 ? p.mlp : nullptr),
            (uint64_t)(p.proposal == 1 ? p.n_seeds : 0),
            (uint64_t)(p.proposal == 1 ? p.mlp_hidden : 0),
-           (uint64_t)(getenv("SLM_FUSED") && getenv("SLM_FUSED")[0] == '1')};
+           (uint64_t)(getenv("SLM_FUSED") && getenv("SLM_FUSED")[0] == '1'),
+           (uint64_t)p.dft_top_n, (uint64_t)(uintptr_t)w.dft_ws};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -692,15 +726,18 @@ slm_status slm_split_scan(const float *Z, int32_t z_layout, const float *zmin, c
   return launch_scan_exact(a, (int)std::min<int64_t>(mx, 1 << 30), S(stream));
 }
 
-slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,
-                        double *gbest_loss, int32_t *gbest_p, const int32_t *node_id,
-                        int32_t n_nodes, int32_t P, int32_t D, uint64_t seed, uint32_t tree,
-                        void *W_out, int32_t w_dtype, void *stream) {
+static slm_status pso_init_impl(double *x, double *v, double *pbest, double *pbest_loss,
+                                double *gbest, double *gbest_loss, int32_t *gbest_p,
+                                const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
+                                uint64_t seed, uint32_t tree, void *W_out, int32_t w_dtype,
+                                const int32_t *sel, int32_t n_sel, void *stream) {
   clear_error();
   SLM_CHECK(n_nodes >= 0 && P >= 1 && P <= PMAX && D >= 1 && D <= DMAX, SLM_E_SHAPE,
             "slm_pso_init: bad sizes");
   SLM_CHECK(w_dtype == SLM_F32 || w_dtype == SLM_BF16, SLM_E_DTYPE,
             "slm_pso_init: W_out must be F32 or BF16");
+  SLM_CHECK(sel == nullptr || (n_sel >= 1 && n_sel <= D), SLM_E_SHAPE,
+            "slm_pso_init_subspace: n_sel = %d not in [1, D]", n_sel);
   if (n_nodes == 0) return SLM_OK;
   SLM_CHECK(x && v && pbest && pbest_loss && gbest && gbest_loss && gbest_p && node_id && W_out,
             SLM_E_INVALID, "slm_pso_init: NULL pointer");
@@ -711,7 +748,66 @@ slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss,
   a.gbest_loss = gbest_loss; a.gbest_p = gbest_p; a.node_id = node_id;
   a.n_nodes = n_nodes; a.P = P; a.D = D; a.seed = seed; a.tree = tree;
   a.W_out = W_out; a.w_bf16 = w_dtype == SLM_BF16;
+  a.dim_sel = sel; a.n_sel = sel ? n_sel : 0;
   return launch_pso_init(a, S(stream));
+}
+
+slm_status slm_pso_init(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,
+                        double *gbest_loss, int32_t *gbest_p, const int32_t *node_id,
+                        int32_t n_nodes, int32_t P, int32_t D, uint64_t seed, uint32_t tree,
+                        void *W_out, int32_t w_dtype, void *stream) {
+  return pso_init_impl(x, v, pbest, pbest_loss, gbest, gbest_loss, gbest_p, node_id, n_nodes, P,
+                       D, seed, tree, W_out, w_dtype, nullptr, 0, stream);
+}
+
+slm_status slm_pso_init_subspace(double *x, double *v, double *pbest, double *pbest_loss,
+                                 double *gbest, double *gbest_loss, int32_t *gbest_p,
+                                 const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
+                                 uint64_t seed, uint32_t tree, void *W_out, int32_t w_dtype,
+                                 const int32_t *sel, int32_t n_sel, void *stream) {
+  if (!sel) {
+    clear_error();
+    SLM_CHECK(false, SLM_E_INVALID, "slm_pso_init_subspace: sel is NULL");
+  }
+  return pso_init_impl(x, v, pbest, pbest_loss, gbest, gbest_loss, gbest_p, node_id, n_nodes, P,
+                       D, seed, tree, W_out, w_dtype, sel, n_sel, stream);
+}
+
+size_t slm_dft_select_workspace(int64_t N, int32_t D, int32_t n_nodes, int32_t bins, int32_t K,
+                                int32_t crit) {
+  if (N <= 0 || D <= 0 || n_nodes < 0 || bins < 0 || bins > 256) return 256;
+  return dft_workspace_bytes(N, n_nodes, D, bins, K, crit);
+}
+
+slm_status slm_dft_select(const float *X, int64_t N, int32_t D, const int64_t *row_off,
+                          int32_t n_nodes, const void *target, int32_t t_dtype, int32_t K,
+                          int32_t bins, int32_t crit, int32_t n, double *dft_loss, int32_t *sel,
+                          void *workspace, size_t ws_bytes, void *stream) {
+  clear_error();
+  SLM_CHECK(N >= 0 && N < (1ll << 31) && n_nodes >= 0 && D >= 1 && D <= DFT_DMAX && n >= 1 &&
+                n <= D,
+            SLM_E_SHAPE, "slm_dft_select: N = %lld, D = %d, n = %d", (long long)N, D, n);
+  SLM_CHECK(crit >= 0 && crit <= 2, SLM_E_INVALID, "slm_dft_select: bad criterion %d", crit);
+  SLM_CHECK(bins == 0 || (bins >= 2 && bins <= 256), SLM_E_SHAPE,
+            "slm_dft_select: bins = %d (0 or 2..256)", bins);
+  const bool mse = crit == SLM_MSE;
+  if (mse)
+    SLM_CHECK(t_dtype == SLM_F64 && K == 0, SLM_E_DTYPE, "slm_dft_select: MSE needs F64 y, K = 0");
+  else
+    SLM_CHECK(t_dtype == SLM_I32 && K >= 2 && K <= 16, SLM_E_DTYPE,
+              "slm_dft_select: classification needs I32 labels and 2 <= K <= 16");
+  if (n_nodes == 0 || N == 0) return SLM_OK;
+  SLM_CHECK(X && row_off && target && dft_loss && sel && workspace, SLM_E_INVALID,
+            "slm_dft_select: NULL pointer");
+  slm_status pst = prepare_kernels();
+  if (pst) return pst;
+  DftArgs da{};
+  da.X = X; da.N = N; da.D = D; da.beg = row_off; da.end = row_off + 1; da.n_nodes = n_nodes;
+  da.labels = mse ? nullptr : static_cast<const int32_t *>(target);
+  da.y = mse ? static_cast<const double *>(target) : nullptr;
+  da.K = K; da.bins = bins; da.crit = crit; da.n = n; da.loss = dft_loss; da.sel = sel;
+  da.ws = workspace; da.ws_bytes = ws_bytes;
+  return launch_dft_select(da, S(stream));
 }
 
 slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,
@@ -862,6 +958,7 @@ slm_status slm_search_nodes(const void *X, int32_t x_dtype, int64_t N, int32_t D
   hipStream_t s = S(stream);
   const int Kc = mse ? 1 : p.K;
   SLM_HIP(hipMemsetAsync(w.scan_ws, 0, w.scan_ws_bytes, s));
+  if (w.dft_ws) SLM_HIP(hipMemsetAsync(w.dft_ws, 0, w.dft_ws_bytes, s));
   if (w.stat_sums)
     SLM_HIP(hipMemsetAsync(w.stat_sums, 0, stats_workspace_bytes(n_nodes, D, Kc), s));
   const uint64_t seed_tree[2] = {p.seed, (uint64_t)p.tree};
@@ -1065,6 +1162,7 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
   // scan accumulators start (and stay) zero; RNG key and tree id on the
   // device; root statistics
   SLM_HIP(hipMemsetAsync(w.scan_ws, 0, w.scan_ws_bytes, s));
+  if (w.dft_ws) SLM_HIP(hipMemsetAsync(w.dft_ws, 0, w.dft_ws_bytes, s));
   if (w.stat_sums)
     SLM_HIP(hipMemsetAsync(w.stat_sums, 0, stats_workspace_bytes((int)F, D, Kc), s));
   const uint64_t seed_tree[2] = {p.seed, (uint64_t)p.tree};

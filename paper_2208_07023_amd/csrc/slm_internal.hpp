@@ -224,10 +224,34 @@ struct PsoArgs {
   // internal: only the global best (a final evaluation whose personal bests
   // are never read again)
   int bests_only;
+  // optional [n_nodes, n_sel]: the start draws only these dimensions of each
+  // node (the others are zero; the top-n DFT channels)
+  const int32_t *dim_sel;
+  int n_sel;
 };
 slm_status launch_pso_init(const PsoArgs &a, hipStream_t s);
 void prepare_pso_kernels(int lds_max);
 slm_status launch_pso_step(const PsoArgs &a, hipStream_t s);
+
+// discriminant feature test of every node and its top n channels
+constexpr int DFT_DMAX = 4096;
+struct DftArgs {
+  const float *X;            // [N, D] float32, node rows contiguous
+  int64_t N;
+  int D;
+  const int64_t *beg, *end;  // node row ranges
+  int n_nodes;
+  const int32_t *labels;     // classification
+  const double *y;           // regression
+  int K, bins, crit;
+  int n;                     // channels kept per node
+  double *loss;              // [n_nodes, D] DFT losses
+  int32_t *sel;              // [n_nodes, n]
+  void *ws;                  // dft_workspace_bytes, zero-filled, left zero-filled
+  size_t ws_bytes;
+};
+size_t dft_workspace_bytes(int64_t N, int n_nodes, int D, int bins, int K, int crit);
+slm_status launch_dft_select(const DftArgs &d, hipStream_t s);
 
 // mixed-precision screening (bfloat16 screen, float32 re-score)
 slm_status launch_screen_select(const double *loss, int n_nodes, int P, int k, int32_t *sel,

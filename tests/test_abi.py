@@ -176,3 +176,39 @@ def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises(TypeError):
         api.project(torch.zeros(4, 2), torch.zeros(1, 2), torch.tensor([0, 4]), 1)
+
+
+def test_dft_validation():
+    lib = api.load()
+    args = lambda D=8, n=3, K=3, bins=64, crit=api.GINI, tt=api.I32: (
+        FAKE, 100, D, FAKE, 2, FAKE, tt, K, bins, crit, n, FAKE, FAKE, FAKE, 1 << 30, None)
+    assert lib.slm_dft_select(*args(n=0)) == 2
+    assert lib.slm_dft_select(*args(n=9)) == 2
+    assert lib.slm_dft_select(*args(D=5000, n=3)) == 2
+    assert lib.slm_dft_select(*args(crit=3)) == 1
+    assert lib.slm_dft_select(*args(bins=1)) == 2
+    assert lib.slm_dft_select(*args(K=1)) == 3
+    assert lib.slm_dft_select(*args(crit=api.MSE, K=0, tt=api.I32)) == 3
+    assert lib.slm_dft_select_workspace(100, 8, 2, 64, 3, api.GINI) > 256
+    sub = lambda sel, n_sel: lib.slm_pso_init_subspace(*([FAKE] * 8), 2, 8, 6, 0, 0, FAKE, api.F32,
+                                                       sel, n_sel, None)
+    assert sub(None, 3) == 1
+    assert sub(FAKE, 0) == 2
+    assert sub(FAKE, 7) == 2
+
+
+def test_grow_tree_dft_validation():
+    lib = api.load()
+    out = api.TreeOut()
+    for kw, want in ((dict(dft_top_n=9), 2), (dict(dft_top_n=-1), 2),
+                     (dict(dft_top_n=3, precision=1, rescore_k=4), 6)):
+        cfg = api.TreeConfig(crit=api.GINI, K=2, P=8, T=2, bins=16, **kw)
+        prm = cfg.c_params()
+        assert lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) == 0
+        xt = api.BF16 if kw.get("precision") == 1 else api.F32
+        st = lib.slm_grow_tree(FAKE, xt, 1000, 8, FAKE, api.I32, ctypes.byref(prm), FAKE,
+                               1 << 30, ctypes.byref(out), None)
+        assert st == want, kw
+    for n in (0, 3, 8):   # accepted: off, a subspace, all dimensions
+        prm = api.TreeConfig(crit=api.GINI, K=2, P=8, T=2, bins=16, dft_top_n=n).c_params()
+        assert lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) > 0
