@@ -124,6 +124,41 @@ def learned_vs_plain():
             "speedup_evals": r["evals"] / max(1, l["evals"])}
 
 
+def dft_vs_plain(Xd, yd, y, K, reps=3):
+    """Swarm in each node's top n DFT channels (Alg. 2) against the swarm in
+    all D dimensions, on the benchmark's data: for T = 5, 20, 50 moves, the
+    root's split loss, the tree's training accuracy and the time per tree
+    (mean of `reps` trees after one warm-up; each depth replayed as a HIP
+    graph; the DFT step is inside the timed tree)."""
+    import torch
+
+    from paper_2208_07023_amd import api
+    D = Xd.shape[1]
+    res = {}
+    for n in (0, 16):
+        arm = {}
+        for T in (5, 20, 50):
+            cfg = api.TreeConfig(crit=api.ENTROPY, K=K, max_depth=8, min_node=32, P=256, T=T,
+                                 bins=256, seed=0, use_graph=True, dft_top_n=n)
+            api.grow_tree(Xd, yd, cfg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            trees = []
+            for r in range(reps):
+                cfg.tree = r
+                trees.append(api.grow_tree(Xd, yd, cfg))
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            arm[f"T{T}"] = {"ms_per_tree": ms,
+                            "root_loss": float(np.mean([t["split_loss"][0] for t in trees])),
+                            "train_accuracy": float(np.mean([(api.predict(t, Xd) == y).mean()
+                                                             for t in trees])),
+                            "nodes": float(np.mean([t["n_nodes"] for t in trees]))}
+        res["plain" if n == 0 else f"top{n}_of_{D}"] = arm
+    log(f"dft vs plain: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +168,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain start comparison")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-dft", action="store_true",
+                    help="skip the top-n DFT channel comparison")
     ap.add_argument("--N", type=int, default=100_000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
@@ -248,6 +285,8 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if not args.no_dft:
+        out["dft_vs_plain"] = dft_vs_plain(Xd, yd, y, K)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_vs_plain()
     if not args.no_cpu_baseline:
