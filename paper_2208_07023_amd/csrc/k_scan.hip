@@ -293,6 +293,20 @@ Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
       if (num_items(n_nodes, N, c) * n_pt >= slots * m) break;
     }
     pl.CH = std::min<int64_t>(CH_MAX, (CH + 63) / 64 * 64);
+    // Few large nodes in one round of work-groups: 8-particle tiles with
+    // chunks long enough for about one work-group per CU.  The atomic merges
+    // of multi-chunk nodes scale with (work-groups x tile words), so narrower
+    // tiles over more rows merge less for the same parallelism (measured,
+    // N = 1e5, P = 256 root: 52 -> 39-44 us; tiles of 4 lose to the extra
+    // loads of narrow row segments).
+    if (N * n_pt <= slots * 4096 && N / std::max(1, n_nodes) >= 16384 && P >= 8) {
+      const int64_t n_pt8 = (P + 7) / 8;
+      const int64_t chunks = std::max<int64_t>(1, (int64_t)num_cus() / n_pt8 - n_nodes);
+      int64_t ch = ((N + chunks - 1) / chunks + 1023) / 1024 * 1024;
+      ch = std::max<int64_t>(std::max<int64_t>(4096, chunk_min(N)), std::min<int64_t>(CH_MAX, ch));
+      pl.PT = 8;
+      pl.CH = ch;
+    }
   }
   pl.G = std::max(1, 32 / pl.PT);
   return pl;
