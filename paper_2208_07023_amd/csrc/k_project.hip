@@ -168,8 +168,6 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
 // alone, so every output element is the same MFMA sequence whatever FN,
 // WAVES and the split of the rows.
 constexpr int SR = 32;             // rows per sub-tile
-// Word 3 of a gfx9 raw buffer resource (32-bit data format, no swizzle).
-constexpr int BUF_DW3 = 0x00020000;
 
 struct SubTile {
   int j;                           // node (-1: none left)

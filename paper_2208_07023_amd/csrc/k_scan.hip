@@ -633,7 +633,7 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   const Item it = find_item(a.beg, a.end, a.n_nodes, a.N, CH, v);
   if (it.node < 0) return;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int i = tid; i < hl.nwords; i += WGS) hc[i] = 0u;
   if constexpr (MSE) {
     for (int i = tid; i < B * SD; i += WGS) {
@@ -700,15 +700,30 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
       const float e1 = __fadd_rn(zmin, __fmul_rn((float)(g0 + 1), delta));
       return min((unsigned)(g0 + (e1 <= zu ? 1 : 0)), bmax);
     };
+    // Z and labels through buffer loads: each lane's offset is fixed and the
+    // offset of step (i + u) is a uniform scalar, so the loads need no
+    // vector address arithmetic.  Ranges: rows below it.hi, at most CH_MAX
+    // rows of at most 4096 floats from the base (< 2^31 bytes).
+    const int64_t rbase = it.lo + (int64_t)wave * RPW;     // this wave's first row
+    const int rs = (int)a.zl.rs;
+    const int64_t zspan = (it.hi - rbase) * rs * 4 + 128;
+    const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(a.Z + z_col(a.zl, (pt * PT) & ~31) + rbase * rs), 0,
+        (int)(zspan < 0x7FFFFFFF ? zspan : 0x7FFFFFFF), BUF_DW3);
+    const int zvo = ((pcl & 31) + rsub * rs) * 4, zso = (int)(step * rs * 4);
+    const __amdgpu_buffer_rsrc_t lr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t *>(a.labels ? a.labels + rbase : nullptr), 0,
+        MSE ? 0 : (int)((it.hi - rbase) * 4), BUF_DW3);
+    const int lvo = rsub * 4, lso = (int)(step * 4);
     for (; i + U <= nrows; i += U) {
       float z[U];
       int lab[U];
       double yv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        z[u] = zp[(int64_t)(i + u) * zstep];
+        z[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(zr, zvo, (i + u) * zso, 0));
         if constexpr (MSE) yv[u] = a.y[row0 + (int64_t)(i + u) * step];
-        else lab[u] = a.labels[row0 + (int64_t)(i + u) * step];
+        else lab[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, (i + u) * lso, 0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -1051,7 +1066,7 @@ void k_fused_hist(ScanArgs a, const float *X, const float *W, int D, int64_t CH,
   const Item it = find_item(a.beg, a.end, a.n_nodes, a.N, CH, v);
   if (it.node < 0) return;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int i = tid; i < hl.nwords; i += WGS) hc[i] = 0u;
   if (use_tbl) fill_log_table(lg, rc, tid);
   const int li = lane & 31, kh = lane >> 5;

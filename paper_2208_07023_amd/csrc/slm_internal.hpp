@@ -144,6 +144,9 @@ __device__ __forceinline__ uint16_t f64_to_bf16(double d) {
 // Placement of Z[i, p] (row i, particle p): (p / 32) * ts + i * rs + p % 32.
 // Row-major [N, P]: ts = 32, rs = P.  Particle-tiled [ceil(P/32), N, 32]:
 // ts = 32 N, rs = 32 (each 32-particle tile is a contiguous [N, 32] block).
+// Word 3 of a gfx9 raw buffer resource (32-bit data format, no swizzle).
+constexpr int BUF_DW3 = 0x00020000;
+
 struct ZLayout {
   int64_t ts, rs;
 };
