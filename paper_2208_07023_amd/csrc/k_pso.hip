@@ -50,6 +50,23 @@ __device__ __forceinline__ void store_w(void *W, int bf16, int64_t i, double x) 
 // happens in the same order as the sequential definition.
 constexpr int MOVE_WG = 256;
 
+// Squared norm of row r[0..D) summed in dimension order (s + r_d * r_d, each
+// operation rounded, as the sequential definition); the loads of eight
+// dimensions are issued before their adds so their latencies overlap.
+__device__ __forceinline__ double sq_norm_ordered(const double *r, int D) {
+  double s = 0.0;
+  int d = 0;
+  for (; d + 8 <= D; d += 8) {
+    double t[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = r[d + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s = s + t[k] * t[k];
+  }
+  for (; d < D; ++d) s = s + r[d] * r[d];
+  return s;
+}
+
 struct MoveGeom {
   int Dp, PPB;
 };
@@ -99,11 +116,7 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_init(PsoArgs a) {
     }
   }
   __syncthreads();
-  if (pv && dl == 0) {
-    double s = 0.0;
-    for (int d = 0; d < D; ++d) s = s + buf[pl * D + d] * buf[pl * D + d];
-    nrm_s[pl] = sqrt(s);
-  }
+  if (pv && dl == 0) nrm_s[pl] = sqrt(sq_norm_ordered(buf + pl * D, D));
   __syncthreads();
   if (!pv) return;
   const double nrm = nrm_s[pl];
@@ -148,6 +161,7 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
   double bl = __builtin_huge_val();
   int bp = 0x7fffffff;
   const double *gl = a.gloss ? a.gloss : a.loss;
+  const double gold = tid == 0 ? a.gbest_loss[j] : 0.0;   // prefetched with the losses
   for (int p = tid; p < P; p += BEST_WG) {
     const double l = gl[base + p];
     if (l < bl) {
@@ -155,23 +169,30 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
       bp = p;
     }
   }
-  red_l[tid] = bl;
-  red_p[tid] = bp;
-  __syncthreads();
-  for (int o = BEST_WG / 2; o > 0; o >>= 1) {
-    if (tid < o) {
-      const double l2 = red_l[tid + o];
-      const int p2 = red_p[tid + o];
-      if (l2 < red_l[tid] || (l2 == red_l[tid] && p2 < red_p[tid])) {
-        red_l[tid] = l2;
-        red_p[tid] = p2;
-      }
+  // smallest loss, ties to the lower p: over the wave by shuffles, then over
+  // the waves
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double l2 = __shfl_xor(bl, o);
+    const int p2 = __shfl_xor(bp, o);
+    if (l2 < bl || (l2 == bl && p2 < bp)) {
+      bl = l2;
+      bp = p2;
     }
-    __syncthreads();
   }
+  if ((tid & 63) == 0) {
+    red_l[tid >> 6] = bl;
+    red_p[tid >> 6] = bp;
+  }
+  __syncthreads();
   if (tid == 0) {
+    for (int w = 1; w < BEST_WG / 64; ++w)
+      if (red_l[w] < red_l[0] || (red_l[w] == red_l[0] && red_p[w] < red_p[0])) {
+        red_l[0] = red_l[w];
+        red_p[0] = red_p[w];
+      }
     const int ps = red_p[0];
-    const bool g = ps != 0x7fffffff && red_l[0] < a.gbest_loss[j];
+    const bool g = ps != 0x7fffffff && red_l[0] < gold;
     s_pstar = ps;
     s_improved = g;
     if (g) {
@@ -197,7 +218,7 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
 // (2) of the step: personal bests (strict <), then with move != 0 Eq. (11),
 // Eq. (12) and the unit-norm rescale.
 __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
-  extern __shared__ double buf[];          // [PPB][D] then gbest [D]
+  extern __shared__ double buf[];          // [PPB][D]
   __shared__ double nrm_s[MOVE_WG];
   const MoveGeom g = move_geom(a.D);
   const int bpn = (a.P + g.PPB - 1) / g.PPB;
@@ -207,9 +228,9 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   const bool pv = p < a.P;
   const int D = a.D, dh = (D + 1) / 2;
   const bool move = a.move != 0;
-  double *gb = buf + (size_t)g.PPB * D;
-  if (move)
-    for (int d = threadIdx.x; d < D; d += MOVE_WG) gb[d] = a.gbest[(int64_t)j * D + d];
+  // each thread reads the global-best coordinates of its own dimensions, so
+  // every load of the step is independent of the others
+  const double *gb = a.gbest + (int64_t)j * D;
   uint2 key;
   uint32_t tree;
   rng_key(a, &key, &tree);
@@ -217,17 +238,17 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   const int64_t gid = (int64_t)j * a.P + p;
   const double lp = pv ? a.loss[gid] : 0.0;
   const bool imp = pv && lp < a.pbest_loss[gid];
-  lds_barrier();
   if (pv) {
     for (int d = dl; d < D; d += g.Dp) {
       const int64_t e = gid * D + d;
       const double xv = a.x[e];
+      const double pold = a.pbest[e];   // loaded with x, before imp is known
       double pb;
       if (imp) {
         a.pbest[e] = xv;
         pb = xv;
       } else {
-        pb = a.pbest[e];
+        pb = pold;
       }
       if (!move) continue;
       const int m = d >> 1, h = d & 1;
@@ -245,11 +266,7 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   lds_barrier();   // every thread of the particle has read pbest_loss
   if (imp && dl == 0) a.pbest_loss[gid] = lp;
   if (!move) return;
-  if (pv && dl == 0) {
-    double s = 0.0;
-    for (int d = 0; d < D; ++d) s = s + buf[pl * D + d] * buf[pl * D + d];
-    nrm_s[pl] = sqrt(s);
-  }
+  if (pv && dl == 0) nrm_s[pl] = sqrt(sq_norm_ordered(buf + pl * D, D));
   lds_barrier();
   if (!pv) return;
   const double nrm = nrm_s[pl];
@@ -312,7 +329,7 @@ slm_status launch_pso_step(const PsoArgs &a, hipStream_t s) {
   if (a.bests_only) return SLM_OK;
   const MoveGeom g = move_geom(a.D);
   const int64_t grid = (int64_t)a.n_nodes * ((a.P + g.PPB - 1) / g.PPB);
-  const size_t lds = ((size_t)g.PPB * a.D + a.D) * sizeof(double);
+  const size_t lds = (size_t)g.PPB * a.D * sizeof(double);
   hipLaunchKernelGGL(k_pso_move, dim3((unsigned)grid), dim3(MOVE_WG), lds, s, a);
   SLM_LAUNCHED();
   return SLM_OK;

@@ -1369,14 +1369,14 @@ __global__ __launch_bounds__(WG) void k_scan_exact(ScanArgs a) {
 }
 
 // Finish of multi-chunk classification nodes: one work-group per particle
-// and bin-parallel (k_scan_finish_bins) when the nodes average at least four
-// chunks (few large nodes: root-like levels), else groups of particles per
+// and bin-parallel (k_scan_finish_bins) when the nodes average at least 16384
+// rows (few large nodes: root-like levels), else groups of particles per
 // work-group (k_scan_finish), whose fewer work-groups suit many small nodes
-// that merely straddle a chunk boundary.  Measured (N = 1e5, P = 256, 4096-row
-// chunks): root 58.8 -> 51.9 us by bins; 128 nodes of 781 rows 128 us by
-// groups, 154 us by bins.
-bool finish_by_bins(const ScanArgs &a, int64_t CH) {
-  return a.N / std::max(1, a.n_nodes) >= 4 * CH;
+// that merely straddle a chunk boundary.  Measured (N = 1e5, P = 256): root
+// 58.8 -> 51.9 us by bins; two nodes of 50000 rows 15.6 -> 8.6 us by bins;
+// 128 nodes of 781 rows 128 us by groups, 154 us by bins.
+bool finish_by_bins(const ScanArgs &a, int64_t) {
+  return a.N / std::max(1, a.n_nodes) >= 16384;
 }
 
 template <int PT, int KT, bool MSE>
