@@ -40,14 +40,14 @@ FP32_PEAK_TFLOPS = 157.3
 # Summary and commands: profiles/traffic_plain_tree_N100k_D64_P256.md
 TRAFFIC = {
     "k_scan_hist": {"source": "paper_2208_07023_amd/csrc/k_scan.hip",
-                    "sha256": "a8c3263a276ed1700f91621f6d476ac002a5e41fa9f49312d589aee2f0991501",
-                    "fetch_kib": 43121.9, "write_kib": 12024.0},
+                    "sha256": "93773a45e8b84ecad8f207809ede5e131f06e95342a292b9c9e02cea214df180",
+                    "fetch_kib": 43091.0, "write_kib": 3688.6},
     "k_scan_finish_bins": {"source": "paper_2208_07023_amd/csrc/k_scan.hip",
-                           "sha256": "a8c3263a276ed1700f91621f6d476ac002a5e41fa9f49312d589aee2f0991501",
-                           "fetch_kib": 3180.0, "write_kib": 3096.0},
+                           "sha256": "93773a45e8b84ecad8f207809ede5e131f06e95342a292b9c9e02cea214df180",
+                           "fetch_kib": 3178.0, "write_kib": 3096.0},
     "k_project": {"source": "paper_2208_07023_amd/csrc/k_project.hip",
-                  "sha256": "7f66646c62f54173b049899dd93751601527a6123bfb5482ba9c98da6e7f0d64",
-                  "fetch_kib": 10790.8, "write_kib": 83735.5},
+                  "sha256": "68cec81140aed47e95bdfa16a703de7eb364b5966d62f79f660c55f1b855b537",
+                  "fetch_kib": 10790.6, "write_kib": 83735.5},
 }
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.3, 1.0
 
