@@ -190,12 +190,6 @@ __device__ __forceinline__ SubTile next_subtile(const ProjectArgs &a, int j, int
   return {-1, 0, 0, 0};
 }
 
-// The sub-tile after c: the next rows of the same node without touching
-// memory, else the first sub-tile of a later node.
-__device__ __forceinline__ SubTile advance(const ProjectArgs &a, const SubTile &c, int64_t r_end) {
-  if (c.hi < c.end) return {c.j, c.hi, c.hi + SR < c.end ? c.hi + SR : c.end, c.end};
-  return next_subtile(a, c.j + 1, c.hi, r_end);
-}
 
 // MASK = false leaves rows and dimensions outside the data as loaded (from a
 // clamped address) instead of zeroing them, so nothing consumes the loads
@@ -320,8 +314,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
     const bool ok = c.lo + li < c.hi;
     load_run<KSP, XB, VEC, false>(a.X, ok ? c.lo + li : c.hi - 1, D, k0, ok, A);
   };
-  auto compute = [&](const SubTile &c, const float (&A)[KSP]) {
-    f32x16 acc[FN];
+  auto mma = [&](const float (&A)[KSP], f32x16 (&acc)[FN]) {
 #pragma unroll
     for (int f = 0; f < FN; ++f) acc[f] = f32x16{};
 #pragma unroll
@@ -329,79 +322,104 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
 #pragma unroll
       for (int f = 0; f < FN; ++f)
         acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[ks], bfrag[f][ks], acc[f], 0, 0, 0);
-    // Lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4 of the sub-tile
-    // and particle column l%32 of block f.
-    if (wave_full && c.hi - c.lo == SR) {
+  };
+  // Lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4 of the sub-tile and
+  // particle column l%32 of block f.
+  // Full sub-tile (32 rows, every column of the wave real): 16 stores per
+  // block from one address with immediate offsets.
+  auto compute_full = [&](int64_t lo, const float (&A)[KSP]) {
+    f32x16 acc[FN];
+    mma(A, acc);
 #pragma unroll
-      for (int f = 0; f < FN; ++f) {
-        if constexpr (STORE) {
-          float *zc = a.Z + z_col(a.zl, pw + f * 32 + li) + (c.lo + 4 * kh) * rs;
+    for (int f = 0; f < FN; ++f) {
+      if constexpr (STORE) {
+        float *zc = a.Z + z_col(a.zl, pw + f * 32 + li) + (lo + 4 * kh) * rs;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = acc[f][r];
-        }
-        float lo = acc[f][0], hi = acc[f][0];
-#pragma unroll
-        for (int r = 1; r < 16; ++r) {
-          lo = fminf(lo, acc[f][r]);
-          hi = fmaxf(hi, acc[f][r]);
-        }
-        mn[f] = fminf(mn[f], lo);
-        mx[f] = fmaxf(mx[f], hi);
+        for (int r = 0; r < 16; ++r) zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = acc[f][r];
       }
-    } else {
-      // Buffer stores whose offset is out of range (rows past the sub-tile,
-      // columns past P) are dropped by the hardware: the same 16 stores per
-      // block as above, with no branches, so the store count between the
-      // loads and their waits is the same on both paths.
-      const int nrow = (int)(c.hi - c.lo);
-      const uint32_t nb = (uint32_t)(nrow * rs * 4);
+      float l = acc[f][0], h = acc[f][0];
 #pragma unroll
-      for (int f = 0; f < FN; ++f) {
-        const bool pin = pw + f * 32 + li < P;
-        if constexpr (STORE) {
-          const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-              a.Z + (int64_t)((pw >> 5) + f) * a.zl.ts + c.lo * rs, 0, nb, BUF_DW3);
+      for (int r = 1; r < 16; ++r) {
+        l = fminf(l, acc[f][r]);
+        h = fmaxf(h, acc[f][r]);
+      }
+      mn[f] = fminf(mn[f], l);
+      mx[f] = fmaxf(mx[f], h);
+    }
+  };
+  // Sub-tile cut by the node's end, or a wave with columns past P: buffer
+  // stores whose offset is set out of range (rows past the sub-tile, columns
+  // past P) are dropped by the hardware.
+  auto compute_masked = [&](const SubTile &c, const float (&A)[KSP]) {
+    f32x16 acc[FN];
+    mma(A, acc);
+    const int nrow = (int)(c.hi - c.lo);
+    const uint32_t nb = (uint32_t)(nrow * rs * 4);
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
-            const uint32_t off =
-                pin && row < nrow ? (uint32_t)((row * rs + li) * 4) : 0x80000000u;
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(acc[f][r]), zr, (int)off, 0, 0);
-          }
-        }
-        float lo = __builtin_nanf(""), hi = __builtin_nanf("");
+    for (int f = 0; f < FN; ++f) {
+      const bool pin = pw + f * 32 + li < P;
+      if constexpr (STORE) {
+        const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
+            a.Z + (int64_t)((pw >> 5) + f) * a.zl.ts + c.lo * rs, 0, nb, BUF_DW3);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
-          const float z = pin && row < nrow ? acc[f][r] : __builtin_nanf("");
-          lo = fminf(lo, z);
-          hi = fmaxf(hi, z);
+          const uint32_t off = pin && row < nrow ? (uint32_t)((row * rs + li) * 4) : 0x80000000u;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(acc[f][r]), zr, (int)off, 0, 0);
         }
-        mn[f] = fminf(mn[f], lo);
-        mx[f] = fmaxf(mx[f], hi);
       }
+      float l = __builtin_nanf(""), h = __builtin_nanf("");
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
+        const float z = pin && row < nrow ? acc[f][r] : __builtin_nanf("");
+        l = fminf(l, z);
+        h = fmaxf(h, z);
+      }
+      mn[f] = fminf(mn[f], l);
+      mx[f] = fmaxf(mx[f], h);
     }
   };
+  auto load_full = [&](int64_t lo, float (&A)[KSP]) {
+    load_run<KSP, XB, VEC, false>(a.X, lo + li, D, k0, true, A);
+  };
 
+  // Node by node: the node's directions (prep), its full sub-tiles in a
+  // ping-pong loop whose only branches are its exits -- so the waits before
+  // each MFMA chain are for that chain's A operand alone, never for the
+  // previous sub-tile's stores (the vector memory counter counts both, in
+  // order) -- then its ragged last sub-tile.
   float A0[KSP], A1[KSP];
-  load_a(cur, A0);
-  // Wait for the first tile before the loop, so that on entering the loop no
-  // load is newer than the stores the steady state has in flight.
+  for (SubTile c = cur; c.j >= 0; c = next_subtile(a, c.j + 1, c.end, r_end)) {
+    const int64_t end = c.end;
+    const int64_t nfull = wave_full ? (end - c.lo) / SR : 0;
+    int64_t r = c.lo;
+    // the first A tile is loaded together with the node's B fragments
+    // (prep waits for both)
+    if (nfull > 0) load_full(r, A0);
+    prep(c);
+    if (nfull > 0) {
 #pragma unroll
-  for (int k = 0; k < KSP; ++k) asm volatile("" ::"v"(A0[k]));
-  while (true) {
-    prep(cur);
-    SubTile nxt = advance(a, cur, r_end);
-    load_a(nxt.j >= 0 ? nxt : cur, A1);
-    compute(cur, A0);
-    if (nxt.j < 0) break;
-    cur = nxt;
-    prep(cur);
-    nxt = advance(a, cur, r_end);
-    load_a(nxt.j >= 0 ? nxt : cur, A0);
-    compute(cur, A1);
-    if (nxt.j < 0) break;
-    cur = nxt;
+      for (int k = 0; k < KSP; ++k) asm volatile("" ::"v"(A0[k]));
+      int64_t s = 0;
+      while (true) {
+        load_full(s + 1 < nfull ? r + SR : r, A1);
+        compute_full(r, A0);
+        if (++s == nfull) break;
+        r += SR;
+        load_full(s + 1 < nfull ? r + SR : r, A0);
+        compute_full(r, A1);
+        if (++s == nfull) break;
+        r += SR;
+      }
+      r += SR;
+    }
+    while (r < end) {   // rows not in a full sub-tile of a full wave
+      const SubTile t{c.j, r, r + SR < end ? r + SR : end, end};
+      load_a(t, A0);
+      compute_masked(t, A0);
+      r = t.hi;
+    }
   }
   flush();
 }
