@@ -213,6 +213,27 @@ slm_status slm_dft_select(const float *X, int64_t N, int32_t D, const int64_t *r
                           void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * slm_ps_candidates -- candidate directions of the probabilistic search
+ * (Sec. II-B, Eqs. (5)-(8)), iteration t, for every node.
+ *
+ * Particle p of node j combines the R features ranks[j R .. j R + R) (most
+ * discriminant first, e.g. sel of slm_dft_select) with integer
+ * coefficients.  One Philox4x32-10 call per (p, rank d), key = seed,
+ * counter = (p R + d, 0x40000000 + t, node_id[j], tree); u24(w) = (w >> 8)
+ * 2^-24.  Rank d is used iff u24(w0) < pd[d]; its coefficient is k + 1 if
+ * k < m, else -(k - m + 1), with k = floor(u24(w1) 2m), m = amax[d] >= 1.  A
+ * particle that uses no rank takes +1 on rank 1.  x[j P + p] = c / ||c||
+ * (FP64, every coordinate written, zeros outside the used ranks) and W_out =
+ * x rounded to w_dtype (F32 or BF16).  ranks [n_nodes, R] int32, pd [R]
+ * float64, amax [R] int32, node_id [n_nodes], x [n_nodes P, D]: all
+ * [device].  1 <= R <= min(D, 64).  Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_ps_candidates(double *x, void *W_out, int32_t w_dtype, const int32_t *node_id,
+                             int32_t n_nodes, int32_t P, int32_t D, const int32_t *ranks,
+                             int32_t R, const double *pd, const int32_t *amax, uint64_t seed,
+                             uint32_t tree, uint32_t t, void *stream);
+
+/* ------------------------------------------------------------------------
  * slm_pso_step -- one synchronous swarm step for every node (Sec. III-A,
  * Eqs. (11)-(12), Alg. 1).
  *
@@ -318,7 +339,13 @@ typedef struct {
                           the first min(n_seeds, P) particles of every node
                           start at the network's seeds (slm_node_stats,
                           slm_mlp_forward with BF16 inference,
-                          slm_proposal_seeds); classification only        */
+                          slm_proposal_seeds); classification only;
+                          2 = probabilistic search instead of the swarm
+                          (Sec. II-B): every searched node ranks its
+                          features by DFT loss (slm_dft_select), and each of
+                          the T + 1 iterations evaluates P new candidates
+                          (slm_ps_candidates) and keeps the best; float32
+                          data only                                        */
   int32_t n_seeds;     /* M seeds per node (network output M * D)        */
   int32_t mlp_hidden;  /* hidden width H (network input (K + 1) * D)     */
   const float *mlp;    /* [device] packed parameters, slm_mlp_param_count */
@@ -327,6 +354,10 @@ typedef struct {
                           (slm_dft_select) and its swarm starts in the span
                           of its top dft_top_n channels (Alg. 2);
                           float32 data (precision 0) only                  */
+  const double *ps_pd;     /* proposal 2: [device] selection probability per
+                              rank (slm_ps_candidates)                      */
+  const int32_t *ps_amax;  /* proposal 2: [device] coefficient range per rank */
+  int32_t ps_R;            /* proposal 2: ranks combined, 1..min(D, 64)     */
 } slm_tree_params;
 
 typedef struct {

@@ -8,6 +8,7 @@ GPU is visible the calls raise; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 
@@ -39,7 +40,8 @@ class TreeParams(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("tree", ctypes.c_uint32), ("use_graph", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("proposal", ctypes.c_int32),
                 ("n_seeds", ctypes.c_int32), ("mlp_hidden", ctypes.c_int32),
-                ("mlp", ctypes.c_void_p), ("dft_top_n", ctypes.c_int32)]
+                ("mlp", ctypes.c_void_p), ("dft_top_n", ctypes.c_int32),
+                ("ps_pd", ctypes.c_void_p), ("ps_amax", ctypes.c_void_p), ("ps_R", ctypes.c_int32)]
 
 
 class TreeOut(ctypes.Structure):
@@ -69,6 +71,8 @@ _SIGS = {
     "slm_pso_init_subspace": ([_VP] * 7 + [_VP, _I32, _I32, _I32, _U64, _U32, _VP, _I32, _VP,
                                            _I32, _VP], _I32),
     "slm_dft_select_workspace": ([_I64, _I32, _I32, _I32, _I32, _I32], _SZ),
+    "slm_ps_candidates": ([_VP, _VP, _I32, _VP, _I32, _I32, _I32, _VP, _I32, _VP, _VP, _U64, _U32,
+                           _U32, _VP], _I32),
     "slm_dft_select": ([_VP, _I64, _I32, _VP, _I32, _VP, _I32, _I32, _I32, _I32, _I32, _VP, _VP,
                         _VP, _SZ, _VP], _I32),
     "slm_pso_step": ([_VP] * 7 + [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _I32, _D, _D,
@@ -321,6 +325,33 @@ def pso_init(sw: Swarm, seed: int, tree: int, sel=None):
                                       _p(sel), sel.shape[1], _stream()), "slm_pso_init_subspace")
 
 
+def ps_tables(R: int, alpha0: float, device="cuda"):
+    """Probabilistic-search tables over R ranks: coefficient range
+    A_d = alpha0 exp(-alpha (d - 1)) with alpha = ln(alpha0) / (R - 1) (from
+    alpha0 at rank 1 to 1 at rank R) and selection probability
+    P_d = A_d / alpha0.  Returns device (pd float64 [R], amax int32 [R])."""
+    d = np.arange(R, dtype=np.float64)
+    alpha = math.log(alpha0) / (R - 1) if R > 1 else 0.0
+    A = alpha0 * np.exp(-alpha * d)
+    pd = A / alpha0
+    amax = np.maximum(1, np.floor(A + 1e-9)).astype(np.int32)
+    return (torch.from_numpy(pd).to(device), torch.from_numpy(amax).to(device))
+
+
+def ps_candidates(sw: "Swarm", ranks, pd, amax, seed: int, tree: int, t: int):
+    """Candidates of the probabilistic search, iteration t, into sw.x / sw.W
+    (slm_ps_candidates); ranks: device int32 [n_nodes, R]."""
+    load()
+    _dev(ranks, torch.int32, "ranks")
+    _dev(pd, torch.float64, "pd")
+    _dev(amax, torch.int32, "amax")
+    nn = sw.node_id.numel()
+    wt = BF16 if sw.W.dtype == torch.bfloat16 else F32
+    _check(_lib.slm_ps_candidates(_p(sw.x), _p(sw.W), wt, _p(sw.node_id), nn, sw.P, sw.D,
+                                  _p(ranks), ranks.shape[1], _p(pd), _p(amax), seed, tree, t,
+                                  _stream()), "slm_ps_candidates")
+
+
 def dft_select(X, target, K: int, row_off, bins: int, crit: int, n: int):
     """Discriminant feature test of every node and its top n channels
     (slm_dft_select): (dft_loss float64 [n_nodes, D], sel int32 [n_nodes, n])."""
@@ -425,17 +456,26 @@ class TreeConfig:
     mlp_hidden: int = 256
     mlp: object = None
     dft_top_n: int = 0          # 1..D-1: swarm in each node's top n DFT channels
+    ps_R: int = 8               # proposal 2: ranks combined by the probabilistic search
+    ps_alpha0: float = 10.0     # proposal 2: coefficient range of rank 1
 
     def c_params(self) -> TreeParams:
         mlp = None
         if self.proposal == 1:
             _dev(self.mlp, torch.float32, "mlp")
             mlp = self.mlp.data_ptr()
+        pd = amax = None
+        if self.proposal == 2:
+            key = (self.ps_R, self.ps_alpha0)
+            if getattr(self, "_ps_key", None) != key:
+                self._ps_tables = ps_tables(self.ps_R, self.ps_alpha0)   # kept alive here
+                self._ps_key = key
+            pd, amax = (t.data_ptr() for t in self._ps_tables)
         return TreeParams(self.crit, self.K, self.max_depth, self.min_node, self.P, self.T,
                           self.bins, self.precision, self.rescore_k, self.omega, self.c1,
                           self.c2, self.seed, self.tree, int(self.use_graph), int(self.profile),
                           int(self.proposal), self.n_seeds, self.mlp_hidden, mlp,
-                          int(self.dft_top_n))
+                          int(self.dft_top_n), pd, amax, int(self.ps_R))
 
 
 _tree_ws: dict = {}

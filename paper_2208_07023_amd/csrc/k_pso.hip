@@ -279,6 +279,57 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   }
 }
 
+// Candidates of the probabilistic search (Sec. II-B, Eqs. (5)-(8)): particle
+// p of node j combines the node's R first-ranked features (ranks[j R + d],
+// most discriminant first) with integer coefficients.  One Philox4x32-10 call
+// per (p, rank d), counter (p R + d, 0x40000000 + t, node id, tree): rank d is
+// used iff u24(w0) < pd[d], with coefficient k + 1 (k < m) or -(k - m + 1),
+// k = floor(u24(w1) 2m), m = amax[d]; a draw that uses no rank takes +1 on
+// rank 1.  x = c / sqrt(sum c^2): the squared norm of the integers is exact,
+// so every coordinate is one correctly rounded division.  One thread per
+// (node, particle); x and its image W_out are written in full (zeros
+// elsewhere).
+constexpr uint32_t PS_STREAM = 0x40000000u;
+
+__global__ void k_ps_candidates(PsoArgs a, const int32_t *ranks, int R, const double *pd,
+                                const int32_t *amax, uint32_t t) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)a.n_nodes * a.P) return;
+  const int j = (int)(gid / a.P), p = (int)(gid % a.P);
+  const int D = a.D;
+  uint2 key;
+  uint32_t tree;
+  rng_key(a, &key, &tree);
+  const uint32_t node = (uint32_t)a.node_id[j];
+  // coefficient of rank d (recomputed in the second pass: no private array)
+  auto coef = [&](int d) {
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)(p * R + d), PS_STREAM + t, node, tree), key);
+    const int m = amax[d];
+    const int k = (int)floor(u24(w.y) * (2.0 * m));
+    return u24(w.x) < pd[d] ? (k < m ? k + 1 : -(k - m + 1)) : 0;
+  };
+  int64_t s = 0;
+  for (int d = 0; d < R; ++d) {
+    const int64_t v = coef(d);
+    s += v * v;
+  }
+  const bool none = s == 0;   // no rank used: +1 on rank 1
+  const double nrm = none ? 1.0 : sqrt((double)s);
+  double *xr = a.x + gid * D;
+  for (int dd = 0; dd < D; ++dd) {
+    xr[dd] = 0.0;
+    store_w(a.W_out, a.w_bf16, gid * D + dd, 0.0);
+  }
+  for (int d = 0; d < R; ++d) {
+    const int col = ranks[(int64_t)j * R + d];
+    const int v = none ? (d == 0 ? 1 : 0) : coef(d);
+    if (col < 0 || col >= D || v == 0) continue;
+    const double xv = (double)v / nrm;
+    xr[col] = xv;
+    store_w(a.W_out, a.w_bf16, gid * D + col, xv);
+  }
+}
+
 __global__ void k_predict(const float *w, const float *thr, const int32_t *left,
                           const int32_t *right, int n_tree, int D, const float *X, int64_t N,
                           int32_t *leaf_out) {
@@ -331,6 +382,18 @@ slm_status launch_pso_step(const PsoArgs &a, hipStream_t s) {
   const int64_t grid = (int64_t)a.n_nodes * ((a.P + g.PPB - 1) / g.PPB);
   const size_t lds = (size_t)g.PPB * a.D * sizeof(double);
   hipLaunchKernelGGL(k_pso_move, dim3((unsigned)grid), dim3(MOVE_WG), lds, s, a);
+  SLM_LAUNCHED();
+  return SLM_OK;
+}
+
+slm_status launch_ps_candidates(const PsoArgs &a, const int32_t *ranks, int R, const double *pd,
+                                const int32_t *amax, uint32_t t, hipStream_t s) {
+  SLM_CHECK(R >= 1 && R <= PS_RMAX && R <= a.D, SLM_E_SHAPE,
+            "probabilistic search: R = %d not in [1, min(D, %d)]", R, PS_RMAX);
+  const int64_t n = (int64_t)a.n_nodes * a.P;
+  if (n == 0) return SLM_OK;
+  hipLaunchKernelGGL(k_ps_candidates, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, a,
+                     ranks, R, pd, amax, t);
   SLM_LAUNCHED();
   return SLM_OK;
 }

@@ -166,9 +166,10 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base, int sea
     w.thr_r = c.take<float>((size_t)F * k);
     w.gloss = c.take<double>((size_t)F * p.P);
   }
-  if (p.dft_top_n > 0 && p.dft_top_n < D) {
+  const int n_sel = p.proposal == 2 ? p.ps_R : (p.dft_top_n > 0 && p.dft_top_n < D ? p.dft_top_n : 0);
+  if (n_sel > 0) {
     w.dft_loss = c.take<double>((size_t)F * D);
-    w.dft_sel = c.take<int32_t>((size_t)F * p.dft_top_n);
+    w.dft_sel = c.take<int32_t>((size_t)F * n_sel);
     w.dft_ws_bytes = dft_workspace_bytes(N, (int)F, D, p.bins, p.K, p.crit);
     w.dft_ws = c.take<char>(w.dft_ws_bytes);
   }
@@ -215,8 +216,17 @@ slm_status check_tree_params(const slm_tree_params *p, int64_t N, int32_t D) {
   if (p->dft_top_n > 0 && p->dft_top_n < D)
     SLM_CHECK(p->precision == 0, SLM_E_UNSUPPORTED,
               "slm_grow_tree: dft_top_n needs float32 data (precision 0)");
-  SLM_CHECK(p->proposal == 0 || p->proposal == 1, SLM_E_INVALID,
-            "slm_grow_tree: proposal %d (0 = random, 1 = learned)", p->proposal);
+  SLM_CHECK(p->proposal >= 0 && p->proposal <= 2, SLM_E_INVALID,
+            "slm_grow_tree: proposal %d (0 = random, 1 = learned, 2 = probabilistic search)",
+            p->proposal);
+  if (p->proposal == 2) {
+    SLM_CHECK(p->ps_R >= 1 && p->ps_R <= std::min(D, PS_RMAX), SLM_E_SHAPE,
+              "slm_grow_tree: ps_R = %d not in [1, min(D, %d)]", p->ps_R, PS_RMAX);
+    SLM_CHECK(p->ps_pd != nullptr && p->ps_amax != nullptr, SLM_E_INVALID,
+              "slm_grow_tree: proposal 2 needs ps_pd and ps_amax");
+    SLM_CHECK(p->precision == 0 && (p->dft_top_n == 0 || p->dft_top_n == D), SLM_E_UNSUPPORTED,
+              "slm_grow_tree: proposal 2 needs float32 data and no dft_top_n");
+  }
   if (p->proposal == 1) {
     SLM_CHECK(p->crit != SLM_MSE, SLM_E_UNSUPPORTED,
               "slm_grow_tree: the learned proposal needs class labels");
@@ -458,19 +468,23 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pa.zmin_reset = w.zmin; pa.zmax_reset = w.zmax;
   pa.seed_tree_dev = w.seed_tree;
   slm_status st;
-  if (p.dft_top_n > 0 && p.dft_top_n < D) {
+  const bool psearch = p.proposal == 2;
+  if (psearch || (p.dft_top_n > 0 && p.dft_top_n < D)) {
     // Alg. 2: the DFT of every node, then the swarm starts in the span of
-    // its top dft_top_n channels
+    // its top dft_top_n channels; the probabilistic search (proposal 2)
+    // combines the node's ps_R best-ranked features instead
     DftArgs da{};
     da.X = static_cast<const float *>(Xc); da.N = N; da.D = D; da.beg = w.beg;
     da.end = sc ? w.end_act : w.end; da.n_nodes = na;
     da.labels = mse ? nullptr : static_cast<const int32_t *>(tc);
     da.y = mse ? static_cast<const double *>(tc) : nullptr;
-    da.K = p.K; da.bins = p.bins; da.crit = p.crit; da.n = p.dft_top_n;
+    da.K = p.K; da.bins = p.bins; da.crit = p.crit; da.n = psearch ? p.ps_R : p.dft_top_n;
     da.loss = w.dft_loss; da.sel = w.dft_sel; da.ws = w.dft_ws; da.ws_bytes = w.dft_ws_bytes;
     if ((st = launch_dft_select(da, s))) return st;
-    pa.dim_sel = w.dft_sel;
-    pa.n_sel = p.dft_top_n;
+    if (!psearch) {
+      pa.dim_sel = w.dft_sel;
+      pa.n_sel = p.dft_top_n;
+    }
   }
   st = launch_pso_init(pa, s);
   if (st) return st;
@@ -516,6 +530,9 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   ProjectArgs pmm = pr;
   pmm.Z = nullptr;
   for (int t = 0; t <= p.T; ++t) {
+    if (psearch &&
+        (st = launch_ps_candidates(pa, w.dft_sel, p.ps_R, p.ps_pd, p.ps_amax, (uint32_t)t, s)))
+      return st;
     if (lt && (st = lt->begin(0, s))) return st;
     if ((st = launch_project(fused ? pmm : pr, s))) return st;
     if (lt && (st = lt->end(s))) return st;
@@ -542,7 +559,9 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
         return st;
     }
     pa.move = t < p.T;
-    pa.bests_only = t == p.T;   // the swarm ends: only the global best is read
+    // the swarm ends (or the search draws new candidates): only the global
+    // best is kept
+    pa.bests_only = t == p.T || psearch;
     pa.iter = (uint32_t)(t + 1);
     if (lt && (st = lt->begin(2, s))) return st;
     if ((st = launch_pso_step(pa, s))) return st;
@@ -573,7 +592,10 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)(p.proposal == 1 ? p.n_seeds : 0),
            (uint64_t)(p.proposal == 1 ? p.mlp_hidden : 0),
            (uint64_t)(getenv("SLM_FUSED") && getenv("SLM_FUSED")[0] == '1'),
-           (uint64_t)p.dft_top_n, (uint64_t)(uintptr_t)w.dft_ws};
+           (uint64_t)p.dft_top_n, (uint64_t)(uintptr_t)w.dft_ws,
+           (uint64_t)(p.proposal == 2 ? p.ps_R : 0),
+           (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_pd : nullptr),
+           (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_amax : nullptr)};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -808,6 +830,28 @@ slm_status slm_dft_select(const float *X, int64_t N, int32_t D, const int64_t *r
   da.K = K; da.bins = bins; da.crit = crit; da.n = n; da.loss = dft_loss; da.sel = sel;
   da.ws = workspace; da.ws_bytes = ws_bytes;
   return launch_dft_select(da, S(stream));
+}
+
+slm_status slm_ps_candidates(double *x, void *W_out, int32_t w_dtype, const int32_t *node_id,
+                             int32_t n_nodes, int32_t P, int32_t D, const int32_t *ranks,
+                             int32_t R, const double *pd, const int32_t *amax, uint64_t seed,
+                             uint32_t tree, uint32_t t, void *stream) {
+  clear_error();
+  SLM_CHECK(n_nodes >= 0 && P >= 1 && P <= PMAX && D >= 1 && D <= DMAX, SLM_E_SHAPE,
+            "slm_ps_candidates: bad sizes");
+  SLM_CHECK(R >= 1 && R <= std::min(D, PS_RMAX), SLM_E_SHAPE,
+            "slm_ps_candidates: R = %d not in [1, min(D, %d)]", R, PS_RMAX);
+  SLM_CHECK(w_dtype == SLM_F32 || w_dtype == SLM_BF16, SLM_E_DTYPE,
+            "slm_ps_candidates: W_out must be F32 or BF16");
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(x && W_out && node_id && ranks && pd && amax, SLM_E_INVALID,
+            "slm_ps_candidates: NULL pointer");
+  slm_status pst = prepare_kernels();
+  if (pst) return pst;
+  PsoArgs a{};
+  a.x = x; a.node_id = node_id; a.n_nodes = n_nodes; a.P = P; a.D = D; a.seed = seed;
+  a.tree = tree; a.W_out = W_out; a.w_bf16 = w_dtype == SLM_BF16;
+  return launch_ps_candidates(a, ranks, R, pd, amax, t, S(stream));
 }
 
 slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,

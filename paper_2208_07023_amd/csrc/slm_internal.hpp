@@ -235,6 +235,10 @@ struct PsoArgs {
 slm_status launch_pso_init(const PsoArgs &a, hipStream_t s);
 void prepare_pso_kernels(int lds_max);
 slm_status launch_pso_step(const PsoArgs &a, hipStream_t s);
+// probabilistic search candidates (ranks [n_nodes, R], pd / amax [R], device)
+constexpr int PS_RMAX = 64;
+slm_status launch_ps_candidates(const PsoArgs &a, const int32_t *ranks, int R, const double *pd,
+                                const int32_t *amax, uint32_t t, hipStream_t s);
 
 // discriminant feature test of every node and its top n channels
 constexpr int DFT_DMAX = 4096;

@@ -212,3 +212,18 @@ def test_grow_tree_dft_validation():
     for n in (0, 3, 8):   # accepted: off, a subspace, all dimensions
         prm = api.TreeConfig(crit=api.GINI, K=2, P=8, T=2, bins=16, dft_top_n=n).c_params()
         assert lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) > 0
+
+
+def test_probabilistic_search_validation():
+    lib = api.load()
+    cand = lambda R, ranks=FAKE: lib.slm_ps_candidates(FAKE, FAKE, api.F32, FAKE, 2, 8, 6, ranks,
+                                                       R, FAKE, FAKE, 0, 0, 0, None)
+    assert cand(0) == 2 and cand(7) == 2 and cand(65) == 2
+    assert cand(3, ranks=None) == 1
+    prm = api.TreeConfig(crit=api.GINI, K=2, P=8, T=2, bins=16).c_params()
+    prm.proposal = 2
+    for R, pd, want_ok in ((0, FAKE, False), (9, FAKE, False), (3, None, False), (3, FAKE, True)):
+        prm.ps_R, prm.ps_pd, prm.ps_amax = R, pd, FAKE
+        assert (lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) > 0) == want_ok, R
+    prm.ps_R, prm.ps_pd, prm.dft_top_n = 3, FAKE, 4
+    assert lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) == 0

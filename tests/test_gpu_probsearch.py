@@ -1,0 +1,65 @@
+"""GPU parity of the probabilistic search (Sec. II-B) against the oracle
+(oracle.probsearch): the candidates bit for bit (integer coefficients, exact
+squared norms, one correctly rounded division per coordinate), and a tree
+grown with proposal 2: its root direction lies in the span of the root's top
+R DFT channels, every split is consistent, and graph replay reproduces it."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dft as OD
+from oracle import probsearch as PS
+from oracle import split as OS
+from paper_2208_07023_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("R,alpha0,D", [(8, 10.0, 24), (1, 3.0, 5), (20, 6.0, 20)])
+def test_candidates_match_oracle(gpu_lib, R, alpha0, D):
+    api = gpu_lib
+    nodes = [0, 4, 17]
+    P = 40
+    rng = np.random.default_rng(R + D)
+    ranks = np.stack([rng.permutation(D)[:R] for _ in nodes]).astype(np.int32)
+    pd, amax = api.ps_tables(R, alpha0)
+    pd_ref, am_ref = PS.tables(R, alpha0)
+    assert np.array_equal(pd.cpu().numpy(), pd_ref) and np.array_equal(amax.cpu().numpy(), am_ref)
+    sw = api.pso_alloc(len(nodes), P, D, nodes)
+    for t in (0, 3):
+        api.ps_candidates(sw, _t(ranks), pd, amax, seed=7, tree=2, t=t)
+        x = sw.x.cpu().numpy()
+        for j, nid in enumerate(nodes):
+            ref = PS.candidates(7, 2, nid, t, P, D, ranks[j], pd_ref, am_ref)
+            assert np.array_equal(x[j * P:(j + 1) * P], ref), (t, j)
+        assert np.array_equal(sw.W.cpu().numpy(), x.astype(np.float32))
+
+
+def test_tree_with_probabilistic_search(gpu_lib):
+    api = gpu_lib
+    D, K, R = 16, 3, 5
+    X, y = inputs.cluster_mixture(12000, D, K, clusters_per_class=2, mean_std=1.0, seed=31)
+    cfg = api.TreeConfig(crit=api.GINI, K=K, max_depth=4, min_node=32, P=64, T=10, bins=64,
+                         seed=4, proposal=2, ps_R=R, ps_alpha0=6.0)
+    Xd, yd = _t(X), _t(y)
+    tr = api.grow_tree(Xd, yd, cfg)
+    top = OD.top_n(OD.dft_losses(X, y, OS.GINI, K, 64), R)
+    assert set(np.nonzero(tr["w"][0])[0].tolist()) <= set(top.tolist())
+    split = 0
+    for i in range(tr["n_nodes"]):
+        if tr["left"][i] < 0:
+            continue
+        split += 1
+        assert 1 <= np.count_nonzero(tr["w"][i]) <= R
+        nl, nr = tr["n"][tr["left"][i]], tr["n"][tr["right"][i]]
+        assert nl + nr == tr["n"][i] and nl > 0 and nr > 0
+        assert tr["split_loss"][i] < tr["impurity"][i]
+    assert split >= 3
+    cfg.use_graph = True
+    tg = api.grow_tree(Xd, yd, cfg)
+    for k in ("w", "thr", "left", "right", "split_loss"):
+        assert np.array_equal(tr[k], tg[k]), k
