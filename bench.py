@@ -159,6 +159,37 @@ def dft_vs_plain(Xd, yd, y, K, reps=3):
     return res
 
 
+def probsearch_vs_pso(Xd, yd, K):
+    """The paper's comparison of the swarm with the original SLM's
+    probabilistic search (Sec. II-B), on the benchmark's data: the root's
+    split loss and search time after T + 1 evaluations of P = 256 candidates
+    (trees of depth 1; mean of 2 trees after one warm-up; the probabilistic
+    search combines the root's 16 best DFT-ranked features, alpha0 = 10)."""
+    import torch
+
+    from paper_2208_07023_amd import api
+    res = {}
+    for name, prop, Ts in (("pso", 0, (10, 50)), ("probabilistic_R16", 2, (10, 50, 200, 1000))):
+        arm = {}
+        for T in Ts:
+            cfg = api.TreeConfig(crit=api.ENTROPY, K=K, max_depth=1, min_node=32, P=256, T=T,
+                                 bins=256, seed=0, use_graph=True, proposal=prop, ps_R=16,
+                                 ps_alpha0=10.0)
+            api.grow_tree(Xd, yd, cfg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            losses = []
+            for r in range(2):
+                cfg.tree = r
+                losses.append(api.grow_tree(Xd, yd, cfg)["split_loss"][0])
+            torch.cuda.synchronize()
+            arm[f"T{T}"] = {"evaluations": T + 1, "root_loss": float(np.mean(losses)),
+                            "ms": 1e3 * (time.perf_counter() - t0) / 2}
+        res[name] = arm
+    log(f"probabilistic search vs pso: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,7 +200,7 @@ def main():
                     help="skip the learned-vs-plain start comparison")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-dft", action="store_true",
-                    help="skip the top-n DFT channel comparison")
+                    help="skip the top-n DFT channel and probabilistic-search comparisons")
     ap.add_argument("--N", type=int, default=100_000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
@@ -287,6 +318,7 @@ def main():
     }
     if not args.no_dft:
         out["dft_vs_plain"] = dft_vs_plain(Xd, yd, y, K)
+        out["probsearch_vs_pso"] = probsearch_vs_pso(Xd, yd, K)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_vs_plain()
     if not args.no_cpu_baseline:
