@@ -15,10 +15,11 @@ Particle Swarm Optimization and Parallel Processing", arXiv 2208.07023):
 * the discriminant feature test of a node and the swarm start in its top n
   channels (oracle.dft; Alg. 2);
 * the original SLM's probabilistic search over the DFT-ranked channels
-  (oracle.probsearch; Sec. II-B).
+  (oracle.probsearch; Sec. II-B);
+* bagged (forest) and boosted ensembles of SLM trees (oracle.ensemble; Sec. V).
 
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It shares no code with the GPU path and imports nothing
 from it; both sides take inputs from the seeded generators only.
 """
-from . import philox, split, pso, screen, dft, probsearch, tree, brute  # noqa: F401
+from . import philox, split, pso, screen, dft, probsearch, tree, brute, ensemble  # noqa: F401

@@ -124,6 +124,21 @@ def abs_direction_regression(n: int, d: int = 128, n_dirs: int = 8, noise: float
     return X, y
 
 
+def friedman1(n: int, d: int = 10, noise: float = 1.0, seed: int = 0):
+    """Friedman's first regression function (Friedman, Ann. Statist. 1991):
+    x ~U[0, 1]^d (d >= 5, only the first five inputs matter),
+    y = 10 sin(pi x1 x2) + 20 (x3 - 1/2)^2 + 10 x4 + 5 x5 + N(0, noise^2).
+    y is computed from the float32 X.  Returns (X f32 [n,d], y f64 [n])."""
+    if d < 5:
+        raise ValueError("friedman1 needs d >= 5")
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0.0, 1.0, size=(n, d)).astype(np.float32)
+    x = X.astype(np.float64)
+    y = (10.0 * np.sin(np.pi * x[:, 0] * x[:, 1]) + 20.0 * (x[:, 2] - 0.5) ** 2
+         + 10.0 * x[:, 3] + 5.0 * x[:, 4] + noise * rng.standard_normal(n))
+    return X, y
+
+
 # --------------------------------------------------------------------------
 # small fixtures for parity tests
 # --------------------------------------------------------------------------
