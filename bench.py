@@ -46,8 +46,8 @@ TRAFFIC = {
                            "sha256": "93773a45e8b84ecad8f207809ede5e131f06e95342a292b9c9e02cea214df180",
                            "fetch_kib": 3178.0, "write_kib": 3096.0},
     "k_project": {"source": "paper_2208_07023_amd/csrc/k_project.hip",
-                  "sha256": "68cec81140aed47e95bdfa16a703de7eb364b5966d62f79f660c55f1b855b537",
-                  "fetch_kib": 10790.6, "write_kib": 83735.5},
+                  "sha256": "d7ce5b1df898b676221c8248f9417a4736e5f4fbf0e89cc6f5a2f29ab775a325",
+                  "fetch_kib": 10777.5, "write_kib": 83735.5},
 }
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.3, 1.0
 
