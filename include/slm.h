@@ -402,6 +402,81 @@ slm_status slm_predict(const float *w, const float *thr, const int32_t *left,
                        const float *X, int64_t N, int32_t *leaf_out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * slm_grow_forest -- SLM/SLR Forest (Sec. V; bagging after random forests):
+ * n_trees trees, tree b grown as slm_grow_tree grows one, with tree id
+ * prm->tree + b, on a bootstrap sample of the N rows (bootstrap = 1) or on all
+ * N rows (bootstrap = 0).
+ *
+ * Bootstrap draw i of tree b (i = 0 .. N-1) is word (i mod 4) of Philox4x32-10
+ * with counter (i div 4, 0x80000000, 0xFFFFFFFF, prm->tree + b) and the seed
+ * as key, mapped to row floor(w * N / 2^32); the sample keeps draw order.
+ * All trees grow together: each depth's frontier nodes of every tree are
+ * searched in one swarm loop (rows of tree b sit at b*N .. (b+1)*N - 1 of a
+ * gathered copy of X in the workspace).
+ *
+ * X, target, prm: as slm_grow_tree.  n_trees in 1..65535, n_trees * N < 2^31.
+ * out ([host], max_nodes for the whole forest): nodes of all trees, numbered
+ * breadth first over the forest (roots are nodes 0 .. n_trees-1; each depth's
+ * nodes follow tree order); child indices are global.  tree_of ([host]
+ * [max_nodes] or NULL) receives every node's tree b.  sample_idx ([device]
+ * int32 [n_trees, N] or NULL) receives the drawn rows (bootstrap = 1).
+ * workspace: device scratch >= slm_grow_forest_workspace(prm, N, D, n_trees)
+ * bytes (about n_trees times a tree's).  Synchronous.
+ * ------------------------------------------------------------------------ */
+size_t slm_grow_forest_workspace(const slm_tree_params *prm, int64_t N, int32_t D,
+                                 int32_t n_trees);
+slm_status slm_grow_forest(const void *X, int32_t x_dtype, int64_t N, int32_t D,
+                           const void *target, int32_t t_dtype, const slm_tree_params *prm,
+                           int32_t n_trees, int32_t bootstrap, void *workspace, size_t ws_bytes,
+                           int32_t *sample_idx, slm_tree_out *out, int32_t *tree_of,
+                           void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_forest_predict -- the forest's output for rows X [device, N, D] F32
+ * (Sec. V): every tree routes each row from its root as slm_predict does
+ * (right iff float32(w . x) >= thr, FP32 accumulation in dimension order).
+ * Classification (K in 2..16): each tree votes for its leaf's majority class
+ * (first maximum of the leaf's class counts) and out (int32 [N]) receives the
+ * class with most votes, the smallest on ties.  Regression (K = 0): out (f64
+ * [N]) receives the mean of the trees' leaf values, summed in tree order.
+ * Tree arrays are device copies of a forest's w [n_nodes, D], thr, left,
+ * right, leaf [n_nodes, max(K, 1)]; roots [device, n_trees] index the roots
+ * (a root outside 0 .. n_nodes-1 gives leaf -1: no vote, or a NaN mean).
+ * leaf_ids [device] int32 [n_trees, N] receives the leaf of every (tree, row).
+ * Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_forest_predict(const float *w, const float *thr, const int32_t *left,
+                              const int32_t *right, const double *leaf, int32_t n_nodes,
+                              const int32_t *roots, int32_t n_trees, int32_t D, int32_t K,
+                              const float *X, int64_t N, int32_t *leaf_ids, void *out,
+                              void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_boost -- SLM/SLR Boost (Sec. V; gradient boosting after XGBoost):
+ * n_rounds rounds of SLR trees (prm: crit SLM_MSE, K 0, precision 0) fitted
+ * to negative gradients, each added with shrinkage lr.
+ *   regression (n_classes = 0, target F64 [N]): F0 = mean(y); round m grows
+ *     one tree (tree id prm->tree + m) on r = y - F and sets F += lr * h(x);
+ *   classification (n_classes = K in 2..16, target I32 labels): F0 = 0;
+ *     round m computes p = softmax(F) (FP64, maximum subtracted) and grows K
+ *     trees together (tree k: id prm->tree + m*K + k, on the K-fold copy of
+ *     X with targets 1{y = k} - p_k), then F_k += lr * h_k(x).
+ * h(x) is the leaf mean each training row reaches under the prediction rule
+ * (right iff float32(w . x) >= thr, FP32 accumulation in dimension order).
+ * X [device, N, D] F32.  F [device] f64 [N, max(K, 1)] receives the final
+ * training scores; F0 [host] f64 [max(K, 1)] the initial ones.  out ([host],
+ * max_nodes for all rounds): the trees in round order (round m's K trees
+ * together, roots first), child indices global; tree_of ([host] or NULL)
+ * receives m * max(K, 1) + k per node.  workspace: device scratch >=
+ * slm_boost_workspace(prm, N, D, n_classes) bytes.  Synchronous.
+ * ------------------------------------------------------------------------ */
+size_t slm_boost_workspace(const slm_tree_params *prm, int64_t N, int32_t D, int32_t n_classes);
+slm_status slm_boost(const float *X, int64_t N, int32_t D, const void *target, int32_t t_dtype,
+                     int32_t n_classes, const slm_tree_params *prm, int32_t n_rounds, double lr,
+                     void *workspace, size_t ws_bytes, double *F, double *F0, slm_tree_out *out,
+                     int32_t *tree_of, void *stream);
+
+/* ------------------------------------------------------------------------
  * slm_search_nodes -- the swarm search of a batch of nodes (Alg. 1 for every
  * node, all evaluated together), without partitioning: the per-depth step of
  * slm_grow_tree on caller-given node row sets.

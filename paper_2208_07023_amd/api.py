@@ -84,6 +84,14 @@ _SIGS = {
     "slm_grow_tree": ([_VP, _I32, _I64, _I32, _VP, _I32, ctypes.POINTER(TreeParams), _VP, _SZ,
                        ctypes.POINTER(TreeOut), _VP], _I32),
     "slm_predict": ([_VP, _VP, _VP, _VP, _I32, _I32, _VP, _I64, _VP, _VP], _I32),
+    "slm_grow_forest_workspace": ([ctypes.POINTER(TreeParams), _I64, _I32, _I32], _SZ),
+    "slm_grow_forest": ([_VP, _I32, _I64, _I32, _VP, _I32, ctypes.POINTER(TreeParams), _I32, _I32,
+                         _VP, _SZ, _VP, ctypes.POINTER(TreeOut), _VP, _VP], _I32),
+    "slm_forest_predict": ([_VP, _VP, _VP, _VP, _VP, _I32, _VP, _I32, _I32, _I32, _VP, _I64, _VP,
+                            _VP, _VP], _I32),
+    "slm_boost_workspace": ([ctypes.POINTER(TreeParams), _I64, _I32, _I32], _SZ),
+    "slm_boost": ([_VP, _I64, _I32, _VP, _I32, _I32, ctypes.POINTER(TreeParams), _I32, _D, _VP,
+                   _SZ, _VP, _VP, ctypes.POINTER(TreeOut), _VP, _VP], _I32),
     "slm_evaluate": ([_VP, _I64, _I32, _VP, _VP, _I32, _I32, _VP, _I32, _I32, _I32, _VP, _VP, _VP,
                       _VP, _VP, _VP, _SZ, _VP], _I32),
     "slm_search_nodes_workspace": ([ctypes.POINTER(TreeParams), _I64, _I32, _I32], _SZ),
@@ -510,9 +518,21 @@ def grow_tree(X, target, cfg: TreeConfig, workspace=None, stats: bool = False):
         _dev(target, torch.int32, "target")
         tt = I32
     ws = workspace if workspace is not None else tree_workspace(cfg, N, D, X.device)
-    maxn = 2 ** (cfg.max_depth + 1) - 1
-    maxn = int(min(maxn, 2 * max(1, N) + 1))
-    kk = max(cfg.K, 1)
+    arr, out = _tree_arrays(_max_nodes(cfg, N), D, cfg.K, stats)
+    prm = cfg.c_params()
+    _check(_lib.slm_grow_tree(_p(X), _xdtype(X), N, D, _p(target), tt, ctypes.byref(prm), _p(ws),
+                              ws.numel(), ctypes.byref(out), _stream()), "slm_grow_tree")
+    return _tree_result(arr, out, cfg.K)
+
+
+def _max_nodes(cfg, N: int) -> int:
+    """Node capacity of one tree: 2^(max_depth+1) - 1, at most 2N + 1."""
+    return int(min(2 ** (cfg.max_depth + 1) - 1, 2 * max(1, N) + 1))
+
+
+def _tree_arrays(maxn: int, D: int, K: int, stats: bool = False):
+    """Host output arrays of maxn nodes and the slm_tree_out that points at them."""
+    kk = max(K, 1)
     arr = dict(w=np.zeros((maxn, D), np.float32), thr=np.zeros(maxn, np.float32),
                left=np.zeros(maxn, np.int32), right=np.zeros(maxn, np.int32),
                leaf=np.zeros((maxn, kk), np.float64), n=np.zeros(maxn, np.int64),
@@ -520,21 +540,173 @@ def grow_tree(X, target, cfg: TreeConfig, workspace=None, stats: bool = False):
                depth=np.zeros(maxn, np.int32), heap=np.zeros(maxn, np.int32),
                timing=np.zeros(8), sample_splits=np.zeros(2, np.int64))
     if stats:
-        arr["stats"] = np.zeros((maxn, (cfg.K + 1) * D), np.float32)
+        arr["stats"] = np.zeros((maxn, (K + 1) * D), np.float32)
         arr["sigma"] = np.zeros((maxn, D), np.float32)
     out = TreeOut(maxn, 0, *[arr[k].ctypes.data for k in
                              ("w", "thr", "left", "right", "leaf", "n", "impurity", "split_loss",
                               "depth", "heap", "timing", "sample_splits")],
                   arr["stats"].ctypes.data if stats else None,
                   arr["sigma"].ctypes.data if stats else None)
-    prm = cfg.c_params()
-    _check(_lib.slm_grow_tree(_p(X), _xdtype(X), N, D, _p(target), tt, ctypes.byref(prm), _p(ws),
-                              ws.numel(), ctypes.byref(out), _stream()), "slm_grow_tree")
+    return arr, out
+
+
+_NODE_FIELDS = ("w", "thr", "left", "right", "leaf", "n", "impurity", "split_loss", "depth",
+                "heap", "stats", "sigma")
+
+
+def _tree_result(arr, out, K):
     n = out.n_nodes
     res = {k: (v[:n] if k not in ("timing", "sample_splits") else v) for k, v in arr.items()}
     res["n_nodes"] = n
-    res["K"] = cfg.K
+    res["K"] = K
     return res
+
+
+# ------------------------------------------------------------------ ensembles
+_forest_ws: dict = {}
+
+
+def _cached_ws(cache: dict, need: int, device) -> torch.Tensor:
+    key = str(device)
+    buf = cache.get(key)
+    if buf is None or buf.numel() < need:
+        cache.pop(key, None)
+        buf = torch.empty(need, dtype=torch.uint8, device=device)
+        cache[key] = buf
+    return buf
+
+
+def grow_forest(X, target, cfg: TreeConfig, n_trees: int, bootstrap: bool = True,
+                return_samples: bool = False):
+    """SLM/SLR Forest: n_trees trees grown together, tree b on bootstrap sample
+    b (tree id cfg.tree + b).  Returns the forest's host arrays (nodes of all
+    trees, breadth first over the forest, roots 0 .. n_trees-1) with "tree_of"
+    and "roots"; with return_samples also the drawn rows [n_trees, N]."""
+    load()
+    _dev(X, torch.bfloat16 if cfg.precision == 1 else torch.float32, "X")
+    N, D = X.shape
+    if cfg.crit == MSE:
+        _dev(target, torch.float64, "target")
+        tt = F64
+    else:
+        _dev(target, torch.int32, "target")
+        tt = I32
+    prm = cfg.c_params()
+    need = _lib.slm_grow_forest_workspace(ctypes.byref(prm), N, D, n_trees)
+    if need == 0:
+        raise SlmError(1, "slm_grow_forest_workspace", _lib.slm_last_error().decode())
+    ws = _cached_ws(_forest_ws, need, X.device)
+    maxn = n_trees * _max_nodes(cfg, N)
+    arr, out = _tree_arrays(maxn, D, cfg.K)
+    tree_of = np.zeros(maxn, np.int32)
+    samples = (torch.empty((n_trees, N), dtype=torch.int32, device=X.device)
+               if return_samples and bootstrap else None)
+    _check(_lib.slm_grow_forest(_p(X), _xdtype(X), N, D, _p(target), tt, ctypes.byref(prm),
+                                n_trees, int(bootstrap), _p(ws), ws.numel(), _p(samples),
+                                ctypes.byref(out), tree_of.ctypes.data, _stream()),
+           "slm_grow_forest")
+    res = _tree_result(arr, out, cfg.K)
+    res["tree_of"] = tree_of[:out.n_nodes]
+    res["roots"] = np.arange(n_trees, dtype=np.int32)
+    res["n_trees"] = n_trees
+    if return_samples:
+        res["samples"] = samples
+    return res
+
+
+def forest_tree(forest: dict, b: int) -> dict:
+    """Tree b of a forest as a stand-alone tree dict (nodes renumbered from 0 in
+    forest order, which is the tree's own breadth-first order)."""
+    idx = np.nonzero(forest["tree_of"] == b)[0]
+    remap = np.full(forest["n_nodes"], -1, np.int64)
+    remap[idx] = np.arange(idx.size)
+    res = {k: forest[k][idx].copy() for k in _NODE_FIELDS if k in forest}
+    for k in ("left", "right"):
+        c = res[k]
+        res[k] = np.where(c >= 0, remap[np.maximum(c, 0)], -1).astype(np.int32)
+    res["n_nodes"] = idx.size
+    res["K"] = forest["K"]
+    return res
+
+
+def forest_predict(forest: dict, X, return_leaves: bool = False):
+    """Forest output for the rows X (device float32): majority class (int32)
+    or mean (float64); return_leaves also gives the leaf ids [n_trees, N]."""
+    load()
+    _dev(X, torch.float32, "X")
+    dev = X.device
+    t = {k: torch.from_numpy(np.ascontiguousarray(forest[k])).to(dev)
+         for k in ("w", "thr", "left", "right", "leaf", "roots")}
+    nt = int(forest["roots"].size)
+    N, D = X.shape
+    leaves = torch.empty((nt, N), dtype=torch.int32, device=dev)
+    K = forest["K"] if forest["K"] > 1 else 0
+    out = torch.empty(N, dtype=torch.int32 if K else torch.float64, device=dev)
+    _check(_lib.slm_forest_predict(_p(t["w"]), _p(t["thr"]), _p(t["left"]), _p(t["right"]),
+                                   _p(t["leaf"]), int(forest["n_nodes"]), _p(t["roots"]), nt, D, K,
+                                   _p(X), N, _p(leaves), _p(out), _stream()), "slm_forest_predict")
+    return (out, leaves) if return_leaves else out
+
+
+_boost_ws: dict = {}
+
+
+def boost(X, target, cfg: TreeConfig, n_rounds: int, lr: float, n_classes: int = 0):
+    """SLM/SLR Boost: n_rounds rounds of SLR trees (cfg must be an MSE config)
+    on negative gradients; n_classes = 0 for regression (target float64),
+    else K-class softmax (target int32 labels).  Returns host arrays of all
+    trees (round order) with "tree_of", "F0", the learning rate and the final
+    training scores F (device [N, max(K, 1)])."""
+    load()
+    _dev(X, torch.float32, "X")
+    N, D = X.shape
+    if n_classes:
+        _dev(target, torch.int32, "target")
+        tt = I32
+    else:
+        _dev(target, torch.float64, "target")
+        tt = F64
+    prm = cfg.c_params()
+    need = _lib.slm_boost_workspace(ctypes.byref(prm), N, D, n_classes)
+    if need == 0:
+        raise SlmError(1, "slm_boost_workspace", _lib.slm_last_error().decode())
+    ws = _cached_ws(_boost_ws, need, X.device)
+    Kc = max(1, n_classes)
+    maxn = max(1, n_rounds * Kc * _max_nodes(cfg, N))
+    arr, out = _tree_arrays(maxn, D, 0)
+    tree_of = np.zeros(maxn, np.int32)
+    F = torch.empty((N, Kc), dtype=torch.float64, device=X.device)
+    F0 = np.zeros(Kc)
+    _check(_lib.slm_boost(_p(X), N, D, _p(target), tt, n_classes, ctypes.byref(prm), n_rounds,
+                          float(lr), _p(ws), ws.numel(), _p(F), F0.ctypes.data,
+                          ctypes.byref(out), tree_of.ctypes.data, _stream()), "slm_boost")
+    res = _tree_result(arr, out, 0)
+    res["tree_of"] = tree_of[:out.n_nodes]
+    res.update(F0=F0, lr=float(lr), n_classes=n_classes, n_rounds=n_rounds, F=F)
+    return res
+
+
+def boost_scores(model: dict, X, rounds=None):
+    """F(x) of a boosted model on the device: F0 + lr * the trees' leaf values,
+    added round by round ([N, max(K, 1)] float64); rounds limits the sum to
+    the first rounds."""
+    load()
+    _dev(X, torch.float32, "X")
+    Kc = max(1, model["n_classes"])
+    N = X.shape[0]
+    F = torch.from_numpy(np.tile(model["F0"], (N, 1))).to(X.device)
+    nt = (model["n_rounds"] if rounds is None else rounds) * Kc
+    tree = {k: model[k] for k in ("w", "thr", "left", "right", "leaf", "n_nodes")}
+    tree["K"] = 0
+    tree["roots"] = np.array([np.nonzero(model["tree_of"] == t)[0][0] for t in range(nt)],
+                             dtype=np.int32)
+    if nt == 0:
+        return F
+    _, leaves = forest_predict(tree, X, return_leaves=True)
+    h = torch.from_numpy(model["leaf"][:, 0]).to(X.device)[leaves.long()]   # [nt, N]
+    for t in range(nt):
+        F[:, t % Kc] += model["lr"] * h[t]
+    return F
 
 
 # ------------------------------------------------------------------ node-batch search

@@ -19,8 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libslm.so")
 
 SOURCES = ["k_project.hip", "k_scan.hip", "k_pso.hip", "k_screen.hip", "k_mlp.hip", "k_tree.hip", "k_dft.hip",
-           "slm_api.cpp"]
-HEADERS = ["slm_internal.hpp"]
+           "k_forest.hip", "slm_api.cpp"]
+HEADERS = ["slm_internal.hpp", "philox.hpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

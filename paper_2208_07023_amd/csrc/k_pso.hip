@@ -7,34 +7,19 @@
 // 64-bit seed as key, so any (tree, node, iteration, particle, dimension)
 // draw can be reproduced independently.
 #include "slm_internal.hpp"
+#include "philox.hpp"
 
 namespace slm {
 namespace {
 
-constexpr uint32_t PH_M0 = 0xD2511F53u, PH_M1 = 0xCD9E8D57u;
-constexpr uint32_t PH_W0 = 0x9E3779B9u, PH_W1 = 0xBB67AE85u;
-constexpr uint32_t INIT_STREAM = 0xFFFFFFFFu;
 constexpr int DMAX = 4096;
 
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k.x += PH_W0;
-      k.y += PH_W1;
-    }
-    const uint32_t lo0 = PH_M0 * c.x, hi0 = __umulhi(PH_M0, c.x);
-    const uint32_t lo1 = PH_M1 * c.z, hi1 = __umulhi(PH_M1, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-  }
-  return c;
-}
-
-__device__ __forceinline__ double u24(uint32_t w) { return (double)(w >> 8) * 0x1p-24; }
-
-__device__ __forceinline__ void rng_key(const PsoArgs &a, uint2 *key, uint32_t *tree) {
+// key and tree word of node j's draws (trees of a forest add their index to
+// the base tree id)
+__device__ __forceinline__ void rng_key(const PsoArgs &a, int j, uint2 *key, uint32_t *tree) {
   const uint64_t seed = a.seed_tree_dev ? a.seed_tree_dev[0] : a.seed;
-  *tree = a.seed_tree_dev ? (uint32_t)a.seed_tree_dev[1] : a.tree;
+  *tree = (a.seed_tree_dev ? (uint32_t)a.seed_tree_dev[1] : a.tree) +
+          (a.tree_off ? a.tree_off[j] : 0u);
   *key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
@@ -89,7 +74,7 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_init(PsoArgs a) {
   const int D = a.D, dh = (D + 1) / 2;
   uint2 key;
   uint32_t tree;
-  rng_key(a, &key, &tree);
+  rng_key(a, j, &key, &tree);
   const uint32_t node = (uint32_t)a.node_id[j];
   const int64_t gid = (int64_t)j * a.P + p;
   const bool masked = a.dim_sel != nullptr;
@@ -233,7 +218,7 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   const double *gb = a.gbest + (int64_t)j * D;
   uint2 key;
   uint32_t tree;
-  rng_key(a, &key, &tree);
+  rng_key(a, j, &key, &tree);
   const uint32_t node = (uint32_t)a.node_id[j];
   const int64_t gid = (int64_t)j * a.P + p;
   const double lp = pv ? a.loss[gid] : 0.0;
@@ -289,7 +274,6 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
 // so every coordinate is one correctly rounded division.  One thread per
 // (node, particle); x and its image W_out are written in full (zeros
 // elsewhere).
-constexpr uint32_t PS_STREAM = 0x40000000u;
 
 __global__ void k_ps_candidates(PsoArgs a, const int32_t *ranks, int R, const double *pd,
                                 const int32_t *amax, uint32_t t) {
@@ -299,7 +283,7 @@ __global__ void k_ps_candidates(PsoArgs a, const int32_t *ranks, int R, const do
   const int D = a.D;
   uint2 key;
   uint32_t tree;
-  rng_key(a, &key, &tree);
+  rng_key(a, j, &key, &tree);
   const uint32_t node = (uint32_t)a.node_id[j];
   // coefficient of rank d (recomputed in the second pass: no private array)
   auto coef = [&](int d) {

@@ -49,11 +49,14 @@ struct Carver {
   }
 };
 
-int64_t max_active(const slm_tree_params &p, int64_t N) {
-  if (p.max_depth <= 0) return 0;
+// Most nodes one depth searches: per tree 2^(max_depth - 1), and at most
+// N / min_node over all trees (their row sets are disjoint).  At least one
+// slot per root (the roots' statistics).
+int64_t max_active(const slm_tree_params &p, int64_t N, int64_t n_roots = 1) {
+  if (p.max_depth <= 0) return n_roots;
   const int64_t by_depth = p.max_depth - 1 >= 30 ? (1ll << 30) : (1ll << (p.max_depth - 1));
   const int64_t by_size = std::max<int64_t>(1, N / std::max(1, p.min_node));
-  return std::max<int64_t>(1, std::min(by_depth, by_size));
+  return std::max<int64_t>(n_roots, std::min(by_depth * n_roots, by_size));
 }
 
 struct TreeWS {
@@ -63,6 +66,7 @@ struct TreeWS {
   double *x, *v, *pbest, *pbest_loss, *loss, *gbest, *gbest_loss;
   void *W, *gW;
   int32_t *split, *gbest_p, *gbest_split, *node_id, *do_split;
+  uint32_t *tree_off;   // tree of every searched node (several roots)
   float *thr, *gbest_thr;
   int64_t *beg, *end, *n_left, *off_left, *off_right;
   uint64_t *seed_tree;
@@ -93,11 +97,11 @@ struct TreeWS {
 // Workspace of a tree build (search_nodes = 0) or of one node-batch search of
 // search_nodes nodes (no partition buffers).  stats: node statistics wanted.
 TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base, int search_nodes = 0,
-             bool stats = false) {
+             bool stats = false, int64_t n_roots = 1) {
   Carver c{static_cast<char *>(base)};
   TreeWS w{};
   const bool search = search_nodes > 0;
-  const int64_t F = search ? search_nodes : max_active(p, N);
+  const int64_t F = search ? search_nodes : max_active(p, N, n_roots);
   const bool mse = p.crit == SLM_MSE;
   const size_t xb = p.precision == 1 ? 2 : 4;
   const int Kc = mse ? 1 : p.K;
@@ -128,6 +132,7 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base, int sea
   w.beg = c.take<int64_t>((size_t)F);
   w.end = c.take<int64_t>((size_t)F);
   w.node_id = c.take<int32_t>((size_t)F);
+  if (n_roots > 1) w.tree_off = c.take<uint32_t>((size_t)F);
   w.do_split = c.take<int32_t>((size_t)F);
   w.n_left = c.take<int64_t>((size_t)F);
   w.seed_tree = c.take<uint64_t>(2);
@@ -250,6 +255,7 @@ struct HNode {
   int depth, heap;
   double impurity;
   bool impure;
+  uint32_t tree;   // root index (trees grown together)
 };
 
 struct StatsHost {
@@ -467,6 +473,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pa.gloss = scr ? w.gloss : nullptr;
   pa.zmin_reset = w.zmin; pa.zmax_reset = w.zmax;
   pa.seed_tree_dev = w.seed_tree;
+  pa.tree_off = w.tree_off;
   slm_status st;
   const bool psearch = p.proposal == 2;
   if (psearch || (p.dft_top_n > 0 && p.dft_top_n < D)) {
@@ -595,7 +602,8 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)p.dft_top_n, (uint64_t)(uintptr_t)w.dft_ws,
            (uint64_t)(p.proposal == 2 ? p.ps_R : 0),
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_pd : nullptr),
-           (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_amax : nullptr)};
+           (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_amax : nullptr),
+           (uint64_t)(uintptr_t)w.tree_off};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -1159,49 +1167,28 @@ static bool tree_stats(const slm_tree_params &p, int32_t D) {
   return p.crit != SLM_MSE && p.K * D <= 4096;
 }
 
-size_t slm_grow_tree_workspace(const slm_tree_params *prm, int64_t N, int32_t D) {
-  if (check_tree_params(prm, N, D) != SLM_OK) return 0;
-  return carve(*prm, N, D, nullptr, 0, tree_stats(*prm, D)).total;
-}
-
-slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, const void *target,
-                         int32_t t_dtype, const slm_tree_params *prm, void *workspace,
-                         size_t ws_bytes, slm_tree_out *out, void *stream) {
-  clear_error();
-  slm_status st = check_tree_params(prm, N, D);
-  if (st) return st;
-  const slm_tree_params &p = *prm;
+// Breadth-first growth of one tree per root: root r owns rows
+// roots[r].first .. roots[r].second - 1 of X / target and its draws use tree
+// id p.tree + r.  Every depth searches the frontier nodes of all trees in one
+// swarm loop.  Nodes are written to out from index base on (children indices
+// are global); tree_of (optional) receives each node's root index.  ss[0..1]
+// accumulate the sample-split counts.
+static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *target,
+                            const slm_tree_params &p, const TreeWS &w,
+                            const std::vector<std::pair<int64_t, int64_t>> &roots, int base,
+                            slm_tree_out *out, int32_t *tree_of, int64_t *ss, hipStream_t s) {
+  slm_status st;
   const bool mse = p.crit == SLM_MSE;
-  SLM_CHECK(x_dtype == (p.precision == 1 ? SLM_BF16 : SLM_F32), SLM_E_DTYPE,
-            "slm_grow_tree: X must be F32 (precision 0) or BF16 (precision 1)");
-  SLM_CHECK(t_dtype == (mse ? SLM_F64 : SLM_I32), SLM_E_DTYPE,
-            "slm_grow_tree: target dtype does not match the criterion");
-  SLM_CHECK(X && target && workspace && out, SLM_E_INVALID, "slm_grow_tree: NULL pointer");
-  SLM_CHECK(out->w && out->thr && out->left && out->right && out->leaf && out->n &&
-                out->impurity && out->split_loss && out->depth && out->heap,
-            SLM_E_INVALID, "slm_grow_tree: NULL output array");
-  SLM_CHECK(out->max_nodes >= 1, SLM_E_SHAPE, "slm_grow_tree: max_nodes < 1");
-  const TreeWS w = carve(p, N, D, workspace, 0, tree_stats(p, D));
-  SLM_CHECK(ws_bytes >= w.total, SLM_E_NOMEM, "slm_grow_tree: workspace of %zu bytes, %zu needed",
-            ws_bytes, w.total);
-  SLM_CHECK(!out->stats || tree_stats(p, D), SLM_E_UNSUPPORTED,
-            "slm_grow_tree: node statistics need class labels and K * D <= 4096");
   const bool want_stats = out->stats != nullptr;
   const int KD1 = (p.K + 1) * D;
+  const int n_roots = (int)roots.size();
   std::vector<float> hst, hsg;
-  if ((st = prepare_kernels())) return st;
-  hipStream_t s = S(stream);
-  const int K = mse ? 0 : p.K;
   const int Kc = mse ? 1 : p.K;
-  const size_t tb = mse ? 8 : 4;
-  const int64_t F = max_active(p, N);
+  const int64_t F = max_active(p, N, n_roots);
   double *timing = out->timing;
-  if (timing) std::fill(timing, timing + 8, 0.0);
-  Timer tm_all, tm_swarm, tm_part;
+  Timer tm_swarm, tm_part;
   const bool prof = p.profile && timing;
   LaunchTimes lt;
-  if ((st = tm_all.start(timing ? &timing[0] : nullptr, s))) return st;
-  int64_t ss = 0, ss_r = 0;
 
   // scan accumulators start (and stay) zero; RNG key and tree id on the
   // device; root statistics
@@ -1213,20 +1200,24 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
   SLM_HIP(hipMemcpyAsync(w.seed_tree, seed_tree, 16, hipMemcpyHostToDevice, s));
   std::vector<int64_t> hb(F), he(F), hnl(F);
   std::vector<int32_t> hid(F), hsplit(F);
-  hb[0] = 0;
-  he[0] = N;
-  SLM_HIP(hipMemcpyAsync(w.beg, hb.data(), 8, hipMemcpyHostToDevice, s));
-  SLM_HIP(hipMemcpyAsync(w.end, he.data(), 8, hipMemcpyHostToDevice, s));
-  if ((st = clear_stats(w, 1, p.crit, Kc, s))) return st;
-  if ((st = launch_node_stats(w.beg, w.end, 1, N, mse ? nullptr : (const int32_t *)target,
+  std::vector<uint32_t> htr(F);
+  for (int r = 0; r < n_roots; ++r) {
+    hb[r] = roots[r].first;
+    he[r] = roots[r].second;
+  }
+  SLM_HIP(hipMemcpyAsync(w.beg, hb.data(), n_roots * 8, hipMemcpyHostToDevice, s));
+  SLM_HIP(hipMemcpyAsync(w.end, he.data(), n_roots * 8, hipMemcpyHostToDevice, s));
+  if ((st = clear_stats(w, n_roots, p.crit, Kc, s))) return st;
+  if ((st = launch_node_stats(w.beg, w.end, n_roots, N, mse ? nullptr : (const int32_t *)target,
                               mse ? (const double *)target : nullptr, Kc, w.st, s)))
     return st;
   StatsHost sh;
-  if ((st = read_stats(w, 1, p.crit, Kc, sh, s))) return st;
+  if ((st = read_stats(w, n_roots, p.crit, Kc, sh, s))) return st;
   SLM_HIP(hipStreamSynchronize(s));
 
-  int nn = 0;
-  auto new_node = [&](int depth, int heap, int stat_i, int64_t b, int64_t e, HNode *hn) -> bool {
+  int nn = base;
+  auto new_node = [&](int depth, int heap, int stat_i, int64_t b, int64_t e, uint32_t tree,
+                      HNode *hn) -> bool {
     if (nn >= out->max_nodes) return false;
     const int i = nn++;
     double imp;
@@ -1241,16 +1232,20 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
     out->right[i] = -1;
     out->depth[i] = depth;
     out->heap[i] = heap;
+    if (tree_of) tree_of[i] = (int32_t)tree;
     std::fill(out->w + (size_t)i * D, out->w + (size_t)(i + 1) * D, 0.0f);
     if (out->stats)
       std::fill(out->stats + (size_t)i * KD1, out->stats + (size_t)(i + 1) * KD1, 0.0f);
     if (out->stats && out->sigma)
       std::fill(out->sigma + (size_t)i * D, out->sigma + (size_t)(i + 1) * D, 0.0f);
-    *hn = HNode{i, b, e, depth, heap, imp, impure};
+    *hn = HNode{i, b, e, depth, heap, imp, impure, tree};
     return true;
   };
-  std::vector<HNode> frontier(1);
-  SLM_CHECK(new_node(0, 0, 0, 0, N, &frontier[0]), SLM_E_SHAPE, "slm_grow_tree: max_nodes = 0");
+  std::vector<HNode> frontier(n_roots);
+  for (int r = 0; r < n_roots; ++r)
+    SLM_CHECK(new_node(0, 0, r, roots[r].first, roots[r].second, (uint32_t)r, &frontier[r]),
+              SLM_E_SHAPE, "grow: max_nodes = %d holds fewer than the %d roots", out->max_nodes,
+              n_roots);
 
   const void *Xc = X;
   const void *tc = target;
@@ -1266,18 +1261,22 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
       if (f.depth < p.max_depth && f.end - f.beg >= p.min_node && f.impure) active.push_back(f);
     if (active.empty()) break;
     const int na = (int)active.size();
-    SLM_CHECK(na <= F, SLM_E_SHAPE, "slm_grow_tree: frontier of %d nodes exceeds %lld", na,
+    SLM_CHECK(na <= F, SLM_E_SHAPE, "grow: frontier of %d nodes exceeds %lld", na,
               (long long)F);
     for (int j = 0; j < na; ++j) {
       hb[j] = active[j].beg;
       he[j] = active[j].end;
       hid[j] = active[j].heap;
-      ss += (active[j].end - active[j].beg) * (int64_t)p.P * (p.T + 1);
-      if (p.precision == 1) ss_r += (active[j].end - active[j].beg) * (int64_t)p.rescore_k * (p.T + 1);
+      htr[j] = active[j].tree;
+      ss[0] += (active[j].end - active[j].beg) * (int64_t)p.P * (p.T + 1);
+      if (p.precision == 1)
+        ss[1] += (active[j].end - active[j].beg) * (int64_t)p.rescore_k * (p.T + 1);
     }
     SLM_HIP(hipMemcpyAsync(w.beg, hb.data(), na * 8, hipMemcpyHostToDevice, s));
     SLM_HIP(hipMemcpyAsync(w.end, he.data(), na * 8, hipMemcpyHostToDevice, s));
     SLM_HIP(hipMemcpyAsync(w.node_id, hid.data(), na * 4, hipMemcpyHostToDevice, s));
+    if (w.tree_off)
+      SLM_HIP(hipMemcpyAsync(w.tree_off, htr.data(), na * 4, hipMemcpyHostToDevice, s));
     if (want_stats && p.proposal != 1) {
       StatsArgs sa{};
       sa.X = Xc; sa.x_bf16 = p.precision == 1; sa.N = N; sa.D = D;
@@ -1364,10 +1363,10 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
       out->thr[i] = hgt[j];
       HNode l, r;
       const int64_t mid = a.beg + hnl[j];
-      SLM_CHECK(new_node(a.depth + 1, 2 * a.heap + 1, 2 * j, a.beg, mid, &l), SLM_E_SHAPE,
-                "slm_grow_tree: more than max_nodes = %d nodes", out->max_nodes);
-      SLM_CHECK(new_node(a.depth + 1, 2 * a.heap + 2, 2 * j + 1, mid, a.end, &r), SLM_E_SHAPE,
-                "slm_grow_tree: more than max_nodes = %d nodes", out->max_nodes);
+      SLM_CHECK(new_node(a.depth + 1, 2 * a.heap + 1, 2 * j, a.beg, mid, a.tree, &l),
+                SLM_E_SHAPE, "grow: more than max_nodes = %d nodes", out->max_nodes);
+      SLM_CHECK(new_node(a.depth + 1, 2 * a.heap + 2, 2 * j + 1, mid, a.end, a.tree, &r),
+                SLM_E_SHAPE, "grow: more than max_nodes = %d nodes", out->max_nodes);
       out->left[i] = l.idx;
       out->right[i] = r.idx;
       next.push_back(l);
@@ -1378,14 +1377,332 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
     nb ^= 1;
     frontier.swap(next);
   }
-  (void)K;
-  (void)tb;
+  out->n_nodes = nn;
+  return SLM_OK;
+}
+
+// common argument checks of the tree, forest and boosting entry points
+static slm_status check_grow_args(const char *who, const void *X, int32_t x_dtype,
+                                  const void *target, int32_t t_dtype, const slm_tree_params &p,
+                                  int32_t D, const slm_tree_out *out) {
+  const bool mse = p.crit == SLM_MSE;
+  SLM_CHECK(x_dtype == (p.precision == 1 ? SLM_BF16 : SLM_F32), SLM_E_DTYPE,
+            "%s: X must be F32 (precision 0) or BF16 (precision 1)", who);
+  SLM_CHECK(t_dtype == (mse ? SLM_F64 : SLM_I32), SLM_E_DTYPE,
+            "%s: target dtype does not match the criterion", who);
+  SLM_CHECK(X && target && out, SLM_E_INVALID, "%s: NULL pointer", who);
+  SLM_CHECK(out->w && out->thr && out->left && out->right && out->leaf && out->n &&
+                out->impurity && out->split_loss && out->depth && out->heap,
+            SLM_E_INVALID, "%s: NULL output array", who);
+  SLM_CHECK(out->max_nodes >= 1, SLM_E_SHAPE, "%s: max_nodes < 1", who);
+  SLM_CHECK(!out->stats || tree_stats(p, D), SLM_E_UNSUPPORTED,
+            "%s: node statistics need class labels and K * D <= 4096", who);
+  return SLM_OK;
+}
+
+size_t slm_grow_tree_workspace(const slm_tree_params *prm, int64_t N, int32_t D) {
+  if (check_tree_params(prm, N, D) != SLM_OK) return 0;
+  return carve(*prm, N, D, nullptr, 0, tree_stats(*prm, D)).total;
+}
+
+slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, const void *target,
+                         int32_t t_dtype, const slm_tree_params *prm, void *workspace,
+                         size_t ws_bytes, slm_tree_out *out, void *stream) {
+  clear_error();
+  slm_status st = check_tree_params(prm, N, D);
+  if (st) return st;
+  const slm_tree_params &p = *prm;
+  if ((st = check_grow_args("slm_grow_tree", X, x_dtype, target, t_dtype, p, D, out))) return st;
+  SLM_CHECK(workspace, SLM_E_INVALID, "slm_grow_tree: NULL workspace");
+  const TreeWS w = carve(p, N, D, workspace, 0, tree_stats(p, D));
+  SLM_CHECK(ws_bytes >= w.total, SLM_E_NOMEM, "slm_grow_tree: workspace of %zu bytes, %zu needed",
+            ws_bytes, w.total);
+  if ((st = prepare_kernels())) return st;
+  hipStream_t s = S(stream);
+  if (out->timing) std::fill(out->timing, out->timing + 8, 0.0);
+  Timer tm_all;
+  if ((st = tm_all.start(out->timing ? &out->timing[0] : nullptr, s))) return st;
+  int64_t ss[2] = {0, 0};
+  if ((st = grow_impl(X, N, D, target, p, w, {{0, N}}, 0, out, nullptr, ss, s))) return st;
   SLM_HIP(hipStreamSynchronize(s));
   if ((st = tm_all.stop(s))) return st;
-  out->n_nodes = nn;
   if (out->sample_splits) {
-    out->sample_splits[0] = ss;
-    out->sample_splits[1] = ss_r;
+    out->sample_splits[0] = ss[0];
+    out->sample_splits[1] = ss[1];
+  }
+  return SLM_OK;
+}
+
+// ---------------------------------------------------------------- forest
+// Workspace of a forest: the gathered rows of every tree (X, targets, draws)
+// ahead of the tree workspace of n_trees * N rows.
+struct ForestWS {
+  void *X, *t;
+  int32_t *idx;
+  TreeWS tree;
+  size_t total;
+};
+
+static ForestWS carve_forest(const slm_tree_params &p, int64_t N, int32_t D, int32_t n_trees,
+                             void *base) {
+  Carver c{static_cast<char *>(base)};
+  ForestWS f{};
+  const int64_t NT = N * n_trees;
+  const size_t xb = p.precision == 1 ? 2 : 4;
+  f.X = c.take<char>((size_t)NT * D * xb);
+  f.t = c.take<char>((size_t)NT * (p.crit == SLM_MSE ? 8 : 4));
+  f.idx = c.take<int32_t>((size_t)NT);
+  c.off = (c.off + 255) / 256 * 256;
+  f.tree = carve(p, NT, D, base ? static_cast<char *>(base) + c.off : nullptr, 0, tree_stats(p, D),
+                 n_trees);
+  f.total = c.off + f.tree.total;
+  return f;
+}
+
+static slm_status check_forest(const slm_tree_params *prm, int64_t N, int32_t D, int32_t n_trees) {
+  slm_status st = check_tree_params(prm, N, D);
+  if (st) return st;
+  SLM_CHECK(n_trees >= 1 && n_trees <= 65535 && N * n_trees < (1ll << 31), SLM_E_SHAPE,
+            "slm_grow_forest: n_trees = %d (1..65535, n_trees * N < 2^31)", n_trees);
+  return SLM_OK;
+}
+
+size_t slm_grow_forest_workspace(const slm_tree_params *prm, int64_t N, int32_t D,
+                                 int32_t n_trees) {
+  if (check_forest(prm, N, D, n_trees) != SLM_OK) return 0;
+  return carve_forest(*prm, N, D, n_trees, nullptr).total;
+}
+
+slm_status slm_grow_forest(const void *X, int32_t x_dtype, int64_t N, int32_t D,
+                           const void *target, int32_t t_dtype, const slm_tree_params *prm,
+                           int32_t n_trees, int32_t bootstrap, void *workspace, size_t ws_bytes,
+                           int32_t *sample_idx, slm_tree_out *out, int32_t *tree_of,
+                           void *stream) {
+  clear_error();
+  slm_status st = check_forest(prm, N, D, n_trees);
+  if (st) return st;
+  const slm_tree_params &p = *prm;
+  if ((st = check_grow_args("slm_grow_forest", X, x_dtype, target, t_dtype, p, D, out))) return st;
+  SLM_CHECK(bootstrap == 0 || bootstrap == 1, SLM_E_INVALID, "slm_grow_forest: bootstrap %d",
+            bootstrap);
+  SLM_CHECK(workspace, SLM_E_INVALID, "slm_grow_forest: NULL workspace");
+  const ForestWS f = carve_forest(p, N, D, n_trees, workspace);
+  SLM_CHECK(ws_bytes >= f.total, SLM_E_NOMEM,
+            "slm_grow_forest: workspace of %zu bytes, %zu needed", ws_bytes, f.total);
+  if ((st = prepare_kernels())) return st;
+  hipStream_t s = S(stream);
+  if (out->timing) std::fill(out->timing, out->timing + 8, 0.0);
+  Timer tm_all;
+  if ((st = tm_all.start(out->timing ? &out->timing[0] : nullptr, s))) return st;
+  const int64_t NT = N * n_trees;
+  const size_t xb = p.precision == 1 ? 2 : 4;
+  const int tb = p.crit == SLM_MSE ? 8 : 4;
+  if (bootstrap && (st = launch_boot_draw(p.seed, p.tree, n_trees, N, f.idx, s))) return st;
+  if ((st = launch_gather_rows(X, (size_t)D * xb, N, NT, bootstrap ? f.idx : nullptr, f.X, target,
+                               tb, f.t, s)))
+    return st;
+  if (sample_idx && bootstrap)
+    SLM_HIP(hipMemcpyAsync(sample_idx, f.idx, (size_t)NT * 4, hipMemcpyDeviceToDevice, s));
+  std::vector<std::pair<int64_t, int64_t>> roots(n_trees);
+  for (int b = 0; b < n_trees; ++b) roots[b] = {(int64_t)b * N, (int64_t)(b + 1) * N};
+  int64_t ss[2] = {0, 0};
+  if ((st = grow_impl(f.X, NT, D, f.t, p, f.tree, roots, 0, out, tree_of, ss, s))) return st;
+  SLM_HIP(hipStreamSynchronize(s));
+  if ((st = tm_all.stop(s))) return st;
+  if (out->sample_splits) {
+    out->sample_splits[0] = ss[0];
+    out->sample_splits[1] = ss[1];
+  }
+  return SLM_OK;
+}
+
+slm_status slm_forest_predict(const float *w, const float *thr, const int32_t *left,
+                              const int32_t *right, const double *leaf, int32_t n_nodes,
+                              const int32_t *roots, int32_t n_trees, int32_t D, int32_t K,
+                              const float *X, int64_t N, int32_t *leaf_ids, void *out,
+                              void *stream) {
+  clear_error();
+  SLM_CHECK(n_nodes >= 1 && n_trees >= 1 && n_trees <= 65535 && D >= 1 && D <= DMAX && N >= 0 &&
+                N < (1ll << 31) && N * n_trees < (1ll << 31),
+            SLM_E_SHAPE, "slm_forest_predict: bad sizes");
+  SLM_CHECK(K == 0 || (K >= 2 && K <= 16), SLM_E_SHAPE, "slm_forest_predict: K = %d (0 or 2..16)",
+            K);
+  if (N == 0) return SLM_OK;
+  SLM_CHECK(w && thr && left && right && leaf && roots && X && leaf_ids && out, SLM_E_INVALID,
+            "slm_forest_predict: NULL pointer");
+  hipStream_t s = S(stream);
+  slm_status st = launch_forest_leaves(w, thr, left, right, n_nodes, roots, n_trees, D, X, N,
+                                       leaf_ids, s);
+  if (st) return st;
+  return launch_forest_combine(leaf_ids, leaf, n_nodes, n_trees, K, N, out, s);
+}
+
+// ---------------------------------------------------------------- boosting
+// Workspace of boosting: the per-class copies of X (n_classes > 1), the
+// residual targets, leaf ids, one round's tree arrays and the tree workspace
+// of Kc * N rows.
+struct BoostWS {
+  float *Xrep;
+  double *r;
+  int32_t *leaf_ids, *roots;
+  float *dw, *dthr;
+  int32_t *dl, *dr;
+  double *dleaf;
+  int64_t round_nodes;
+  TreeWS tree;
+  size_t total;
+};
+
+static int64_t boost_round_nodes(const slm_tree_params &p, int64_t N, int Kc) {
+  const int64_t by_depth = p.max_depth >= 29 ? (1ll << 30) : (2ll << p.max_depth) - 1;
+  return Kc * std::min(by_depth, 2 * N - 1);
+}
+
+static BoostWS carve_boost(const slm_tree_params &p, int64_t N, int32_t D, int32_t n_classes,
+                           void *base) {
+  Carver c{static_cast<char *>(base)};
+  BoostWS b{};
+  const int Kc = std::max(1, (int)n_classes);
+  if (Kc > 1) b.Xrep = c.take<float>((size_t)Kc * N * D);
+  b.r = c.take<double>((size_t)Kc * N);
+  b.leaf_ids = c.take<int32_t>((size_t)Kc * N);
+  b.roots = c.take<int32_t>((size_t)Kc);
+  b.round_nodes = boost_round_nodes(p, N, Kc);
+  b.dw = c.take<float>((size_t)b.round_nodes * D);
+  b.dthr = c.take<float>((size_t)b.round_nodes);
+  b.dl = c.take<int32_t>((size_t)b.round_nodes);
+  b.dr = c.take<int32_t>((size_t)b.round_nodes);
+  b.dleaf = c.take<double>((size_t)b.round_nodes);
+  c.off = (c.off + 255) / 256 * 256;
+  b.tree = carve(p, (int64_t)Kc * N, D, base ? static_cast<char *>(base) + c.off : nullptr, 0,
+                 false, Kc);
+  b.total = c.off + b.tree.total;
+  return b;
+}
+
+static slm_status check_boost(const slm_tree_params *prm, int64_t N, int32_t D, int32_t n_classes,
+                              int32_t n_rounds) {
+  slm_status st = check_tree_params(prm, N, D);
+  if (st) return st;
+  SLM_CHECK(prm->crit == SLM_MSE && prm->precision == 0, SLM_E_INVALID,
+            "slm_boost: the trees are SLR trees (crit SLM_MSE, precision 0)");
+  SLM_CHECK(prm->proposal != 1, SLM_E_UNSUPPORTED, "slm_boost: no learned proposal");
+  SLM_CHECK(n_classes == 0 || (n_classes >= 2 && n_classes <= 16), SLM_E_SHAPE,
+            "slm_boost: n_classes = %d (0 = regression, 2..16)", n_classes);
+  SLM_CHECK(n_rounds >= 0 && N * std::max(1, (int)n_classes) < (1ll << 31), SLM_E_SHAPE,
+            "slm_boost: n_rounds = %d, N = %lld out of range", n_rounds, (long long)N);
+  SLM_CHECK(boost_round_nodes(*prm, N, std::max(1, (int)n_classes)) < (1ll << 31), SLM_E_SHAPE,
+            "slm_boost: too many nodes per round");
+  return SLM_OK;
+}
+
+size_t slm_boost_workspace(const slm_tree_params *prm, int64_t N, int32_t D, int32_t n_classes) {
+  if (check_boost(prm, N, D, n_classes, 0) != SLM_OK) return 0;
+  return carve_boost(*prm, N, D, n_classes, nullptr).total;
+}
+
+slm_status slm_boost(const float *X, int64_t N, int32_t D, const void *target, int32_t t_dtype,
+                     int32_t n_classes, const slm_tree_params *prm, int32_t n_rounds, double lr,
+                     void *workspace, size_t ws_bytes, double *F, double *F0, slm_tree_out *out,
+                     int32_t *tree_of, void *stream) {
+  clear_error();
+  slm_status st = check_boost(prm, N, D, n_classes, n_rounds);
+  if (st) return st;
+  const slm_tree_params &p = *prm;
+  const int Kc = std::max(1, (int)n_classes);
+  SLM_CHECK(t_dtype == (n_classes ? SLM_I32 : SLM_F64), SLM_E_DTYPE,
+            "slm_boost: target must be I32 labels (n_classes > 0) or F64 (regression)");
+  SLM_CHECK(std::isfinite(lr), SLM_E_INVALID, "slm_boost: lr must be finite");
+  SLM_CHECK(X && target && F && F0 && out && workspace, SLM_E_INVALID, "slm_boost: NULL pointer");
+  SLM_CHECK(!out->stats, SLM_E_UNSUPPORTED, "slm_boost: no node statistics output");
+  slm_tree_params q = p;
+  if ((st = check_grow_args("slm_boost", X, SLM_F32, F, SLM_F64, q, D, out))) return st;
+  const BoostWS b = carve_boost(p, N, D, n_classes, workspace);
+  SLM_CHECK(ws_bytes >= b.total, SLM_E_NOMEM, "slm_boost: workspace of %zu bytes, %zu needed",
+            ws_bytes, b.total);
+  if ((st = prepare_kernels())) return st;
+  hipStream_t s = S(stream);
+  if (out->timing) std::fill(out->timing, out->timing + 8, 0.0);
+  Timer tm_all;
+  if ((st = tm_all.start(out->timing ? &out->timing[0] : nullptr, s))) return st;
+  const int64_t NT = (int64_t)Kc * N;
+  const int32_t *labels = n_classes ? static_cast<const int32_t *>(target) : nullptr;
+  const double *y = n_classes ? nullptr : static_cast<const double *>(target);
+  // initial scores: the mean target (regression, from the root statistics
+  // kernel) or zero; every row starts at F0
+  std::vector<double> f0(Kc, 0.0);
+  if (!n_classes) {
+    const TreeWS &w = b.tree;
+    const int64_t be[2] = {0, N};
+    SLM_HIP(hipMemcpyAsync(w.beg, &be[0], 8, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(w.end, &be[1], 8, hipMemcpyHostToDevice, s));
+    if ((st = clear_stats(w, 1, SLM_MSE, 1, s))) return st;
+    if ((st = launch_node_stats(w.beg, w.end, 1, N, nullptr, y, 1, w.st, s))) return st;
+    double s1 = 0;
+    uint32_t cnt = 0;
+    SLM_HIP(hipMemcpyAsync(&s1, w.st.s1, 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(&cnt, w.st.cnt, 4, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipStreamSynchronize(s));
+    f0[0] = s1 / (double)cnt;
+  }
+  for (int k = 0; k < Kc; ++k) F0[k] = f0[k];
+  // F [N, Kc] = F0 in every row: the one row replicated by a gather
+  SLM_HIP(hipMemcpyAsync(b.r, f0.data(), Kc * 8, hipMemcpyHostToDevice, s));
+  if ((st = launch_gather_rows(b.r, (size_t)Kc * 8, 1, N, nullptr, F, nullptr, 0, nullptr, s)))
+    return st;
+  if (Kc > 1 &&
+      (st = launch_gather_rows(X, (size_t)D * 4, N, NT, nullptr, b.Xrep, nullptr, 0, nullptr, s)))
+    return st;
+  const float *Xg = Kc > 1 ? b.Xrep : X;
+  std::vector<std::pair<int64_t, int64_t>> roots(Kc);
+  for (int k = 0; k < Kc; ++k) roots[k] = {(int64_t)k * N, (int64_t)(k + 1) * N};
+  int64_t ss[2] = {0, 0};
+  int base = 0;
+  std::vector<int32_t> hl, hr, rts(Kc), rtree;
+  std::vector<double> hlv;
+  for (int m = 0; m < n_rounds; ++m) {
+    if ((st = launch_boost_residual(labels, y, F, N, n_classes, b.r, s))) return st;
+    q.tree = p.tree + (uint32_t)(m * Kc);
+    rtree.assign(out->max_nodes, 0);
+    if ((st = grow_impl(Xg, NT, D, b.r, q, b.tree, roots, base, out,
+                        tree_of ? rtree.data() : nullptr, ss, s)))
+      return st;
+    const int cnt = out->n_nodes - base;
+    SLM_CHECK(cnt <= b.round_nodes, SLM_E_SHAPE, "slm_boost: round of %d nodes", cnt);
+    if (tree_of)
+      for (int i = base; i < out->n_nodes; ++i) tree_of[i] = m * Kc + rtree[i];
+    // this round's trees on the device, indices relative to the round
+    hl.resize(cnt);
+    hr.resize(cnt);
+    hlv.resize(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      const int l = out->left[base + i], r = out->right[base + i];
+      hl[i] = l < 0 ? -1 : l - base;
+      hr[i] = r < 0 ? -1 : r - base;
+      hlv[i] = out->leaf[base + i];
+    }
+    for (int k = 0; k < Kc; ++k) rts[k] = k;   // the roots come first
+    SLM_HIP(hipMemcpyAsync(b.dw, out->w + (size_t)base * D, (size_t)cnt * D * 4,
+                           hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(b.dthr, out->thr + base, (size_t)cnt * 4, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(b.dl, hl.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(b.dr, hr.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(b.dleaf, hlv.data(), (size_t)cnt * 8, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(b.roots, rts.data(), (size_t)Kc * 4, hipMemcpyHostToDevice, s));
+    if ((st = launch_forest_leaves(b.dw, b.dthr, b.dl, b.dr, cnt, b.roots, Kc, D, X, N,
+                                   b.leaf_ids, s)))
+      return st;
+    if ((st = launch_boost_update(F, b.leaf_ids, b.dleaf, cnt, N, Kc, lr, s))) return st;
+    // the host arrays above are reused next round
+    SLM_HIP(hipStreamSynchronize(s));
+    base = out->n_nodes;
+  }
+  out->n_nodes = base;
+  SLM_HIP(hipStreamSynchronize(s));
+  if ((st = tm_all.stop(s))) return st;
+  if (out->sample_splits) {
+    out->sample_splits[0] = ss[0];
+    out->sample_splits[1] = ss[1];
   }
   return SLM_OK;
 }

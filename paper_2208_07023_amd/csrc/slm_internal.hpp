@@ -231,6 +231,9 @@ struct PsoArgs {
   // node (the others are zero; the top-n DFT channels)
   const int32_t *dim_sel;
   int n_sel;
+  // optional [n_nodes]: added to the tree id of node j's draws (the trees of
+  // a forest grown together)
+  const uint32_t *tree_off;
 };
 slm_status launch_pso_init(const PsoArgs &a, hipStream_t s);
 void prepare_pso_kernels(int lds_max);
@@ -304,6 +307,23 @@ slm_status launch_seeds(const float *o, const float *sigma, int n_nodes, int M, 
 slm_status launch_predict(const float *w, const float *thr, const int32_t *left,
                           const int32_t *right, int n_tree, int D, const float *X, int64_t N,
                           int32_t *leaf_out, hipStream_t s);
+
+// ensembles (k_forest.hip)
+slm_status launch_boot_draw(uint64_t seed, uint32_t tree0, int n_trees, int64_t N, int32_t *idx,
+                            hipStream_t s);
+slm_status launch_gather_rows(const void *src, size_t row_bytes, int64_t N, int64_t n_out,
+                              const int32_t *idx, void *dst, const void *tsrc, int tb, void *tdst,
+                              hipStream_t s);
+slm_status launch_forest_leaves(const float *w, const float *thr, const int32_t *left,
+                                const int32_t *right, int n_nodes, const int32_t *roots,
+                                int n_trees, int D, const float *X, int64_t N, int32_t *leaf_out,
+                                hipStream_t s);
+slm_status launch_forest_combine(const int32_t *leaf_ids, const double *leaf, int n_nodes,
+                                 int n_trees, int K, int64_t N, void *out, hipStream_t s);
+slm_status launch_boost_residual(const int32_t *labels, const double *y, const double *F,
+                                 int64_t N, int K, double *r, hipStream_t s);
+slm_status launch_boost_update(double *F, const int32_t *leaf_ids, const double *leaf,
+                               int n_nodes, int64_t N, int Kc, double lr, hipStream_t s);
 
 struct TreeStats {
   uint32_t *counts;   // [n * K] classification

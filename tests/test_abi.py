@@ -227,3 +227,41 @@ def test_probabilistic_search_validation():
         assert (lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) > 0) == want_ok, R
     prm.ps_R, prm.ps_pd, prm.dft_top_n = 3, FAKE, 4
     assert lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8) == 0
+
+
+def test_forest_and_boost_validation():
+    lib = api.load()
+    out = api.TreeOut()
+    prm = api.TreeConfig(crit=api.GINI, K=3, max_depth=4, P=8, T=2, bins=16).c_params()
+    one = lib.slm_grow_tree_workspace(ctypes.byref(prm), 1000, 8)
+    four = lib.slm_grow_forest_workspace(ctypes.byref(prm), 1000, 8, 4)
+    # four trees: four gathered copies of the rows ahead of a 4000-row tree workspace
+    assert four > 4 * 1000 * 8 * 4 + lib.slm_grow_tree_workspace(ctypes.byref(prm), 4000, 8) - 4096
+    assert four > 3 * one
+    for nt in (0, 70000):
+        assert lib.slm_grow_forest_workspace(ctypes.byref(prm), 1000, 8, nt) == 0
+        st = lib.slm_grow_forest(FAKE, api.F32, 1000, 8, FAKE, api.I32, ctypes.byref(prm), nt, 1,
+                                 FAKE, 1 << 40, None, ctypes.byref(out), None, None)
+        assert st == 2 and "n_trees" in _err(lib)
+    # n_trees * N must stay below 2^31
+    assert lib.slm_grow_forest_workspace(ctypes.byref(prm), 1 << 20, 8, 4096) == 0
+    st = lib.slm_grow_forest(FAKE, api.F32, 1000, 8, FAKE, api.I32, ctypes.byref(prm), 2, 2, FAKE,
+                             1 << 40, None, ctypes.byref(out), None, None)
+    assert st == 1   # NULL output arrays are found before the bootstrap flag
+    pred = lambda K, nt=2: lib.slm_forest_predict(FAKE, FAKE, FAKE, FAKE, FAKE, 5, FAKE, nt, 8, K,
+                                                  FAKE, 10, FAKE, FAKE, None)
+    assert pred(1) == 2 and pred(17) == 2 and pred(3, nt=0) == 2
+    # boosting grows SLR trees: an MSE parameter set with K = 0
+    mse = api.TreeConfig(crit=api.MSE, K=0, max_depth=3, P=8, T=2, bins=16).c_params()
+    assert lib.slm_boost_workspace(ctypes.byref(mse), 1000, 8, 0) > 0
+    assert lib.slm_boost_workspace(ctypes.byref(mse), 1000, 8, 3) > \
+        lib.slm_boost_workspace(ctypes.byref(mse), 1000, 8, 0)
+    assert lib.slm_boost_workspace(ctypes.byref(prm), 1000, 8, 3) == 0
+    assert lib.slm_boost_workspace(ctypes.byref(mse), 1000, 8, 1) == 0
+    assert lib.slm_boost_workspace(ctypes.byref(mse), 1000, 8, 17) == 0
+    st = lib.slm_boost(FAKE, 1000, 8, FAKE, api.F64, 3, ctypes.byref(mse), 2, 0.1, FAKE, 1 << 40,
+                       FAKE, FAKE, ctypes.byref(out), None, None)
+    assert st == 3 and "labels" in _err(lib)
+    st = lib.slm_boost(FAKE, 1000, 8, FAKE, api.F64, 0, ctypes.byref(mse), 2, float("nan"), FAKE,
+                       1 << 40, FAKE, FAKE, ctypes.byref(out), None, None)
+    assert st == 1 and "lr" in _err(lib)
