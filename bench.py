@@ -190,6 +190,91 @@ def probsearch_vs_pso(Xd, yd, K):
     return res
 
 
+def forest_vs_trees(Xd, yd, K, n_trees=30):
+    """SLM Forest of n_trees trees (Sec. V: 30 per ensemble) on the benchmark's
+    data and tree settings: the forest grown together (one breadth-first pass,
+    every depth's nodes of all trees in one swarm loop) against the same trees
+    grown one after another (slm_grow_forest with one tree per call and the
+    same tree ids, so both arms draw the same bootstrap samples and give the
+    same trees).  One warm-up of each arm, then one timed run."""
+    import torch
+
+    from paper_2208_07023_amd import api
+    cfg = api.TreeConfig(crit=api.ENTROPY, K=K, max_depth=8, min_node=32, P=256, T=50, bins=256,
+                         seed=0, use_graph=True)
+
+    def together():
+        cfg.tree = 0
+        return api.grow_forest(Xd, yd, cfg, n_trees)
+
+    def one_by_one():
+        out = []
+        for b in range(n_trees):
+            cfg.tree = b
+            out.append(api.grow_forest(Xd, yd, cfg, 1))
+        return out
+
+    res = {}
+    for name, fn in (("together", together), ("one_by_one", one_by_one)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ss = (int(r["sample_splits"][0]) if isinstance(r, dict)
+              else sum(int(t["sample_splits"][0]) for t in r))
+        res[name] = {"ms": 1e3 * dt, "trees_per_s": n_trees / dt, "sample_splits_per_s": ss / dt,
+                     "nodes": int(r["n_nodes"]) if isinstance(r, dict)
+                     else sum(int(t["n_nodes"]) for t in r)}
+        if name == "together":
+            forest = r
+        else:
+            same = all(np.array_equal(api.forest_tree(forest, b)[k], api.forest_tree(t, 0)[k])
+                       for b, t in enumerate(r) for k in ("w", "thr", "left", "right"))
+    res["same_trees"] = bool(same)
+    res["speedup"] = res["one_by_one"]["ms"] / res["together"]["ms"]
+    res["n_trees"] = n_trees
+    log(f"forest vs trees: {res}")
+    return res
+
+
+def boost_rounds(Xd, yd, K, rounds=10, lr=0.3):
+    """SLR Boost (squared loss, Friedman's first function with D = 64 inputs,
+    N = 100000) and SLM Boost (K-class softmax on the benchmark's data): SLR
+    trees of depth 4, P = 64, T = 20, 256 bins; time per round and the
+    training loss after the last round."""
+    import torch
+
+    from paper_2208_07023_amd import api, inputs
+    N, D = Xd.shape
+    Xr, yr = inputs.friedman1(N, D, noise=1.0, seed=1)
+    Xrd, yrd = torch.from_numpy(Xr).cuda(), torch.from_numpy(yr).cuda()
+    cfg = api.TreeConfig(crit=api.MSE, K=0, max_depth=4, min_node=32, P=64, T=20, bins=256,
+                         seed=0, use_graph=True)
+    res = {}
+    for name, X, y, nc in (("slr_boost", Xrd, yrd, 0), ("slm_boost", Xd, yd, K)):
+        api.boost(X, y, cfg, 1, lr, n_classes=nc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m = api.boost(X, y, cfg, rounds, lr, n_classes=nc)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        F = m["F"]
+        if nc:
+            loss = float(-torch.log_softmax(F, dim=1)[torch.arange(N, device=F.device),
+                                                       y.long()].mean())
+            base = float(np.log(nc))
+        else:
+            loss = float(((y - F[:, 0]) ** 2).mean())
+            base = float(((y - y.mean()) ** 2).mean())
+        res[name] = {"rounds": rounds, "trees": rounds * max(1, nc), "ms_per_round": 1e3 * dt / rounds,
+                     "sample_splits_per_s": int(m["sample_splits"][0]) / dt,
+                     "train_loss_start": base, "train_loss_end": loss, "lr": lr}
+    log(f"boost: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +286,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-dft", action="store_true",
                     help="skip the top-n DFT channel and probabilistic-search comparisons")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the forest and boosting legs")
     ap.add_argument("--N", type=int, default=100_000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
@@ -319,6 +406,9 @@ def main():
     if not args.no_dft:
         out["dft_vs_plain"] = dft_vs_plain(Xd, yd, y, K)
         out["probsearch_vs_pso"] = probsearch_vs_pso(Xd, yd, K)
+    if not args.no_ensemble:
+        out["forest_vs_trees"] = forest_vs_trees(Xd, yd, K)
+        out["boost"] = boost_rounds(Xd, yd, K)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_vs_plain()
     if not args.no_cpu_baseline:
