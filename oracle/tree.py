@@ -7,7 +7,8 @@ Readings of the paper used here:
   regression: not all targets equal) -- the paper's "pure enough" and "small
   enough" stopping rule (Sec. II-A);
 * search = 2 replaces the swarm by the probabilistic search over the node's
-  top ps_R DFT channels (oracle.probsearch);
+  top ps_R DFT channels (oracle.probsearch); search = 1 runs the adaptive
+  swarm (oracle.apso) instead of the plain one;
 * the swarm runs in all D input dimensions unless dft_top_n = n with
   0 < n < D: then every searched node first runs the DFT and the swarm
   starts in the span of its top n channels (oracle.dft; Alg. 2);
@@ -25,6 +26,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import apso
 from . import dft
 from . import probsearch
 from . import screen
@@ -49,7 +51,8 @@ class TreeParams:
     precision: int = 0         # 1 = bfloat16 screening, float32 re-scoring
     rescore_k: int = 32
     dft_top_n: int = 0         # 0 < n < D: swarm in the node's top n DFT channels
-    search: int = 0            # 0 = swarm (Alg. 1); 2 = probabilistic search (Sec. II-B)
+    search: int = 0            # 0 = swarm (Alg. 1); 1 = APSO (Sec. III-B); 2 = probabilistic
+                               # search (Sec. II-B)
     ps_R: int = 8              # probabilistic search: ranks combined
     ps_alpha0: float = 10.0    # probabilistic search: coefficient range of rank 1
 
@@ -157,7 +160,10 @@ def grow_tree(X, target, prm: TreeParams, rows=None, keep_rows=False):
             elif 0 < prm.dft_top_n < D:
                 sel = dft.top_n(dft.dft_losses(Xn, tn, prm.crit, prm.K, prm.bins), prm.dft_top_n)
                 x0 = dft.subspace_start(prm.seed, prm.tree, hid, prm.P, D, sel)
-            if prm.search != 2:
+            if prm.search == 1:
+                res = apso.run_apso(evaluate_node(Xn, tn, prm), prm.P, D, prm.T, prm.seed,
+                                    prm.tree, hid, x0=x0)
+            elif prm.search != 2:
                 res = run_pso(evaluate_node(Xn, tn, prm), prm.P, D, prm.T, prm.omega,
                               prm.c1, prm.c2, prm.seed, prm.tree, hid, x0=x0)
             tr.split_loss[idx] = res["loss"]
