@@ -267,6 +267,43 @@ slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss,
                         void *stream);
 
 /* ------------------------------------------------------------------------
+ * slm_apso_step -- one step of the adaptive swarm (APSO, Sec. III-B) for a
+ * batch of nodes: the bests exactly as slm_pso_step, then per node the
+ * evolutionary state estimation and parameter change, then the move of
+ * Eqs. (11)-(12) with the node's own omega, c1, c2.
+ *   dist [n_nodes * P] (out): d_i, the mean distance of particle i to the
+ *     other particles of its node;
+ *   f [n_nodes] (out): (d_g - d_min) / (d_max - d_min), g = gbest_p (0 if
+ *     negative); 0 when d_max = d_min;
+ *   state [n_nodes] (in/out): 1 exploration, 2 exploitation, 3 convergence,
+ *     4 jumping-out (1 before the first move); the previous state is kept
+ *     while its fuzzy membership of f stays positive, else the state of
+ *     largest membership (lower state on ties);
+ *   par [n_nodes * 3] (in/out): omega, c1, c2 (c1 = c2 = 2 before the first
+ *     move); omega = 1 / (1 + 1.5 exp(-2.6 f)); c1, c2 move by delta ~
+ *     U[0.05, 0.1] (half of it in states 2 and 3) in the state's directions,
+ *     are clamped to [1.5, 2.5] and scaled to sum 4 when above it;
+ *   worst [n_nodes] (out): the particle of highest loss (NaN as +inf, lowest
+ *     index on ties);
+ *   elite [n_nodes * D] (out, state 3 only): one coordinate (uniform) of the
+ *     global best moved by 2 sigma N(0, 1), sigma = 1 - 0.9 iter / T, scaled
+ *     to unit norm; it replaces the worst particle after the move, with zero
+ *     velocity.
+ * The draws of move iter use Philox counters (0 | 1, 0x20000000 + iter, node
+ * id, tree).  P in 2..4096.  workspace [device] >= slm_apso_workspace(n_nodes,
+ * P) bytes (partial distance sums).  Other arguments as slm_pso_step (with
+ * move = 1 and no screening).  Asynchronous.
+ * ------------------------------------------------------------------------ */
+size_t slm_apso_workspace(int32_t n_nodes, int32_t P);
+slm_status slm_apso_step(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,
+                         double *gbest_loss, int32_t *gbest_p, const double *loss,
+                         const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
+                         uint64_t seed, uint32_t tree, uint32_t iter, uint32_t T, int32_t *state,
+                         double *par, double *dist, double *f, int32_t *worst, double *elite,
+                         void *workspace, size_t ws_bytes, void *W_out, int32_t w_dtype,
+                         void *stream);
+
+/* ------------------------------------------------------------------------
  * Mixed-precision screening of one swarm evaluation.  The paper scores a
  * direction by the loss of its best threshold (Sec. III-B) and names faster
  * projection search on high-dimensional data as open (Sec. VI); screening
@@ -358,6 +395,9 @@ typedef struct {
                               rank (slm_ps_candidates)                      */
   const int32_t *ps_amax;  /* proposal 2: [device] coefficient range per rank */
   int32_t ps_R;            /* proposal 2: ranks combined, 1..min(D, 64)     */
+  int32_t apso;            /* 1 = adaptive swarm (slm_apso_step) in place of
+                              the plain one (Sec. III-B); P >= 2, not with
+                              proposal 2                                    */
 } slm_tree_params;
 
 typedef struct {

@@ -41,7 +41,8 @@ class TreeParams(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("proposal", ctypes.c_int32),
                 ("n_seeds", ctypes.c_int32), ("mlp_hidden", ctypes.c_int32),
                 ("mlp", ctypes.c_void_p), ("dft_top_n", ctypes.c_int32),
-                ("ps_pd", ctypes.c_void_p), ("ps_amax", ctypes.c_void_p), ("ps_R", ctypes.c_int32)]
+                ("ps_pd", ctypes.c_void_p), ("ps_amax", ctypes.c_void_p), ("ps_R", ctypes.c_int32),
+                ("apso", ctypes.c_int32)]
 
 
 class TreeOut(ctypes.Structure):
@@ -77,6 +78,9 @@ _SIGS = {
                         _VP, _SZ, _VP], _I32),
     "slm_pso_step": ([_VP] * 7 + [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _I32, _D, _D,
                                   _D, _U64, _U32, _U32, _I32, _VP, _I32, _VP], _I32),
+    "slm_apso_workspace": ([_I32, _I32], _SZ),
+    "slm_apso_step": ([_VP] * 8 + [_VP, _I32, _I32, _I32, _U64, _U32, _U32, _U32, _VP, _VP, _VP,
+                                   _VP, _VP, _VP, _VP, _SZ, _VP, _I32, _VP], _I32),
     "slm_screen_select": ([_VP, _I32, _I32, _I32, _VP, _VP], _I32),
     "slm_screen_gather": ([_VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP], _I32),
     "slm_screen_merge": ([_VP, _VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP], _I32),
@@ -400,6 +404,44 @@ def pso_step(sw: Swarm, loss, omega, c1, c2, seed, tree, it, move, split=None, t
                              int(bool(move)), _p(sw.W), wt, _stream()), "slm_pso_step")
 
 
+@dataclass
+class ApsoState:
+    state: torch.Tensor     # [n] int32, 1..4
+    par: torch.Tensor       # [n, 3] f64: omega, c1, c2
+    dist: torch.Tensor      # [n * P] f64
+    f: torch.Tensor         # [n] f64
+    worst: torch.Tensor     # [n] int32
+    elite: torch.Tensor     # [n, D] f64
+    ws: torch.Tensor
+
+
+def apso_alloc(sw: Swarm) -> ApsoState:
+    """Adaptive-swarm state of every node of sw, at its start (exploration,
+    omega 0.9, c1 = c2 = 2)."""
+    load()
+    n, dev = sw.node_id.numel(), sw.x.device
+    par = torch.tensor([[0.9, 2.0, 2.0]], dtype=torch.float64, device=dev).repeat(n, 1)
+    ws = torch.empty(_lib.slm_apso_workspace(n, sw.P), dtype=torch.uint8, device=dev)
+    return ApsoState(state=torch.ones(n, dtype=torch.int32, device=dev), par=par,
+                     dist=torch.zeros(n * sw.P, dtype=torch.float64, device=dev),
+                     f=torch.zeros(n, dtype=torch.float64, device=dev),
+                     worst=torch.zeros(n, dtype=torch.int32, device=dev),
+                     elite=torch.zeros(n, sw.D, dtype=torch.float64, device=dev), ws=ws)
+
+
+def apso_step(sw: Swarm, ap: ApsoState, loss, seed: int, tree: int, it: int, T: int):
+    """One adaptive-swarm step (bests, state estimation, move) of every node."""
+    load()
+    nn = sw.node_id.numel()
+    wt = BF16 if sw.W.dtype == torch.bfloat16 else F32
+    _dev(loss, torch.float64, "loss")
+    _check(_lib.slm_apso_step(_p(sw.x), _p(sw.v), _p(sw.pbest), _p(sw.pbest_loss), _p(sw.gbest),
+                              _p(sw.gbest_loss), _p(sw.gbest_p), _p(loss), _p(sw.node_id), nn,
+                              sw.P, sw.D, seed, tree, it, T, _p(ap.state), _p(ap.par),
+                              _p(ap.dist), _p(ap.f), _p(ap.worst), _p(ap.elite), _p(ap.ws),
+                              ap.ws.numel(), _p(sw.W), wt, _stream()), "slm_apso_step")
+
+
 # ------------------------------------------------------------------ screening
 def screen_select(loss, n_nodes: int, P: int, k: int):
     """Per node the k particles with the smallest losses, ascending by
@@ -466,6 +508,7 @@ class TreeConfig:
     dft_top_n: int = 0          # 1..D-1: swarm in each node's top n DFT channels
     ps_R: int = 8               # proposal 2: ranks combined by the probabilistic search
     ps_alpha0: float = 10.0     # proposal 2: coefficient range of rank 1
+    apso: bool = False          # adaptive swarm (APSO) in place of the plain one
 
     def c_params(self) -> TreeParams:
         mlp = None
@@ -483,7 +526,7 @@ class TreeConfig:
                           self.bins, self.precision, self.rescore_k, self.omega, self.c1,
                           self.c2, self.seed, self.tree, int(self.use_graph), int(self.profile),
                           int(self.proposal), self.n_seeds, self.mlp_hidden, mlp,
-                          int(self.dft_top_n), pd, amax, int(self.ps_R))
+                          int(self.dft_top_n), pd, amax, int(self.ps_R), int(self.apso))
 
 
 _tree_ws: dict = {}

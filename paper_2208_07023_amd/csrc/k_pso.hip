@@ -9,6 +9,8 @@
 #include "slm_internal.hpp"
 #include "philox.hpp"
 
+#include <algorithm>
+
 namespace slm {
 namespace {
 
@@ -124,6 +126,12 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_init(PsoArgs a) {
       a.gbest_p[j] = -1;
       if (a.gbest_split) a.gbest_split[j] = -1;
       if (a.gbest_thr) a.gbest_thr[j] = __builtin_huge_valf();
+      if (a.apso_state) {   // the adaptive swarm starts exploring with c1 = c2 = 2
+        a.apso_state[j] = 1;
+        a.apso_par[(int64_t)j * 3 + 0] = 0.9;
+        a.apso_par[(int64_t)j * 3 + 1] = 2.0;
+        a.apso_par[(int64_t)j * 3 + 2] = 2.0;
+      }
     }
   }
 }
@@ -200,6 +208,219 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- adaptive swarm
+// APSO (Sec. III-B; the state estimation and the changes as in the APSO
+// reference): between the bests and the move, every node estimates its
+// evolutionary state from the particles' mean distances, changes c1, c2 and
+// the inertia weight with the state, and in the convergence state prepares an
+// elitist-learning candidate that replaces its worst particle after the move.
+constexpr int AD_T = 64;          // particle tile of the distance kernel
+constexpr int AD_KC = 16;         // dimensions per LDS chunk
+constexpr uint32_t APSO_STREAM = 0x20000000u;
+
+// Partial sums of ||x_i - x_j|| over the j of one 64-particle tile, for the
+// i of another: work-group (node, i tile, j tile), 256 threads, each a 4 x 4
+// block of pairs; dimensions staged through LDS 16 at a time.  part[(node P +
+// i) nb + j tile] (nb tiles per node).
+__global__ __launch_bounds__(256) void k_apso_dist(PsoArgs a) {
+  __shared__ double xi[AD_T][AD_KC + 1], xj[AD_T][AD_KC + 1];
+  const int P = a.P, D = a.D, nb = (P + AD_T - 1) / AD_T;
+  const int blk = blockIdx.x;
+  const int j = blk / (nb * nb), bi = (blk / nb) % nb, bj = blk % nb;
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  const int64_t base = (int64_t)j * P;
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+  for (int d0 = 0; d0 < D; d0 += AD_KC) {
+#pragma unroll
+    for (int k = 0; k < AD_T * AD_KC / 256; ++k) {
+      const int e = tid + 256 * k, row = e / AD_KC, col = e % AD_KC;
+      const int i = bi * AD_T + row, jj = bj * AD_T + row, d = d0 + col;
+      xi[row][col] = i < P && d < D ? a.x[(base + i) * D + d] : 0.0;
+      xj[row][col] = jj < P && d < D ? a.x[(base + jj) * D + d] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < AD_KC; ++k) {
+      double u[4], w[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) u[r] = xi[ti * 4 + r][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) w[c] = xj[tj * 4 + c][k];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double df = u[r] - w[c];
+          acc[r][c] = acc[r][c] + df * df;
+        }
+    }
+    __syncthreads();
+  }
+  // row sums over this thread's 4 columns, then over the 16 column groups in
+  // a fixed order (the LDS of the staging is reused)
+  double *red = &xi[0][0];   // [64 rows][16 groups] fits in xi
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (bj * AD_T + tj * 4 + c < P) s = s + sqrt(acc[r][c]);
+    red[(ti * 4 + r) * 16 + tj] = s;
+  }
+  __syncthreads();
+  if (tid < AD_T) {
+    const int i = bi * AD_T + tid;
+    if (i < P) {
+      double s = 0.0;
+      for (int g = 0; g < 16; ++g) s = s + red[tid * 16 + g];
+      a.apso_part[(base + i) * nb + bj] = s;
+    }
+  }
+}
+
+__device__ __forceinline__ double apso_mu(int s, double f) {
+  switch (s) {
+    case 1:   // exploration
+      return f <= 0.4 ? 0.0 : f <= 0.6 ? 5.0 * f - 2.0 : f <= 0.7 ? 1.0 : f <= 0.8 ? -10.0 * f + 8.0 : 0.0;
+    case 2:   // exploitation
+      return f <= 0.2 ? 0.0 : f <= 0.3 ? 10.0 * f - 2.0 : f <= 0.4 ? 1.0 : f <= 0.6 ? -5.0 * f + 3.0 : 0.0;
+    case 3:   // convergence
+      return f <= 0.1 ? 1.0 : f <= 0.3 ? -5.0 * f + 1.5 : 0.0;
+    default:  // jumping-out
+      return f <= 0.7 ? 0.0 : f <= 0.9 ? 5.0 * f - 3.5 : 1.0;
+  }
+}
+
+// One work-group per node: mean distances d_i, f = (d_g - d_min) / (d_max -
+// d_min) (g = the global best's particle; f = 0 if d_max = d_min), the state
+// (kept while its membership is positive, else the largest membership, lower
+// state on ties), inertia 1 / (1 + 1.5 exp(-2.6 f)), c1 / c2 changed by
+// delta ~ U[0.05, 0.1] (half in exploitation and convergence), clamped to
+// [1.5, 2.5] and scaled to sum 4; the worst particle (highest loss, NaN as
+// +inf, lowest index on ties); in convergence the elite candidate: one
+// coordinate of the global best moved by 2 sigma N(0, 1), sigma = 1 - 0.9 t/T,
+// scaled to unit norm.  Draws: Philox counters (0 | 1, APSO_STREAM + t, node,
+// tree).
+__global__ __launch_bounds__(256) void k_apso_adapt(PsoArgs a) {
+  __shared__ double s_mn[4], s_mx[4], s_wl[4], s_dg, s_nrm;
+  __shared__ int s_wp[4], s_dim, s_state;
+  __shared__ double e[DMAX];
+  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int P = a.P, D = a.D, nb = (P + AD_T - 1) / AD_T;
+  const int64_t base = (int64_t)j * P;
+  const int g = max(0, a.gbest_p[j]);
+  double mn = __builtin_huge_val(), mx = -__builtin_huge_val(), wl = -__builtin_huge_val();
+  int wp = 0x7fffffff;
+  for (int i = tid; i < P; i += 256) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s = s + a.apso_part[(base + i) * nb + b];
+    const double di = s / (double)(P - 1);
+    a.apso_dist[base + i] = di;
+    mn = fmin(mn, di);
+    mx = fmax(mx, di);
+    if (i == g) s_dg = di;
+    double l = a.loss[base + i];
+    if (l != l) l = __builtin_huge_val();
+    if (l > wl || (l == wl && i < wp)) {
+      wl = l;
+      wp = i;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, o));
+    mx = fmax(mx, __shfl_xor(mx, o));
+    const double l2 = __shfl_xor(wl, o);
+    const int p2 = __shfl_xor(wp, o);
+    if (l2 > wl || (l2 == wl && p2 < wp)) {
+      wl = l2;
+      wp = p2;
+    }
+  }
+  if (lane == 0) {
+    s_mn[wv] = mn;
+    s_mx[wv] = mx;
+    s_wl[wv] = wl;
+    s_wp[wv] = wp;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w) {
+      mn = fmin(mn, s_mn[w]);
+      mx = fmax(mx, s_mx[w]);
+      if (s_wl[w] > wl || (s_wl[w] == wl && s_wp[w] < wp)) {
+        wl = s_wl[w];
+        wp = s_wp[w];
+      }
+    }
+    const double f = mx > mn ? (s_dg - mn) / (mx - mn) : 0.0;
+    const int prev = a.apso_state[j];
+    int st = prev;
+    if (!(prev >= 1 && prev <= 4 && apso_mu(prev, f) > 0.0)) {
+      st = 1;
+      for (int q = 2; q <= 4; ++q)
+        if (apso_mu(q, f) > apso_mu(st, f)) st = q;
+    }
+    uint2 key;
+    uint32_t tree;
+    rng_key(a, j, &key, &tree);
+    const uint32_t node = (uint32_t)a.node_id[j];
+    const uint4 w0 = philox4x32_10(make_uint4(0u, APSO_STREAM + a.iter, node, tree), key);
+    const double d1 = 0.05 + 0.05 * u24(w0.x), d2 = 0.05 + 0.05 * u24(w0.y);
+    double c1 = a.apso_par[(int64_t)j * 3 + 1], c2 = a.apso_par[(int64_t)j * 3 + 2];
+    if (st == 1) {
+      c1 = c1 + d1;
+      c2 = c2 - d2;
+    } else if (st == 2) {
+      c1 = c1 + 0.5 * d1;
+      c2 = c2 - 0.5 * d2;
+    } else if (st == 3) {
+      c1 = c1 + 0.5 * d1;
+      c2 = c2 + 0.5 * d2;
+    } else {
+      c1 = c1 - d1;
+      c2 = c2 + d2;
+    }
+    c1 = fmin(fmax(c1, 1.5), 2.5);
+    c2 = fmin(fmax(c2, 1.5), 2.5);
+    if (c1 + c2 > 4.0) {
+      const double sc = 4.0 / (c1 + c2);
+      c1 = c1 * sc;
+      c2 = c2 * sc;
+    }
+    a.apso_par[(int64_t)j * 3 + 0] = 1.0 / (1.0 + 1.5 * exp(-2.6 * f));
+    a.apso_par[(int64_t)j * 3 + 1] = c1;
+    a.apso_par[(int64_t)j * 3 + 2] = c2;
+    a.apso_state[j] = st;
+    a.apso_f[j] = f;
+    a.apso_worst[j] = wp == 0x7fffffff ? 0 : wp;
+    s_state = st;
+    s_dim = (int)(((uint64_t)w0.z * (uint64_t)D) >> 32);
+    if (st == 3) {
+      const uint4 w1 = philox4x32_10(make_uint4(1u, APSO_STREAM + a.iter, node, tree), key);
+      const double u1 = ((double)w1.x + 0.5) * 0x1p-32;
+      const double u2 = (double)w1.y * 0x1p-32;
+      const double gv = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+      const double sig = 1.0 - (1.0 - 0.1) * ((double)a.iter / (double)max(1u, a.apso_T));
+      s_nrm = (2.0 * sig) * gv;   // the step, until the norm is known
+    }
+  }
+  __syncthreads();
+  if (s_state != 3) return;
+  const double *gb = a.gbest + (int64_t)j * D;
+  for (int d = tid; d < D; d += 256) e[d] = d == s_dim ? gb[d] + s_nrm : gb[d];
+  __syncthreads();
+  if (tid == 0) s_nrm = sqrt(sq_norm_ordered(e, D));
+  __syncthreads();
+  const double nrm = s_nrm;
+  for (int d = tid; d < D; d += 256)
+    a.apso_elite[(int64_t)j * D + d] = nrm > 0.0 ? e[d] / nrm : gb[d];
+}
+
 // (2) of the step: personal bests (strict <), then with move != 0 Eq. (11),
 // Eq. (12) and the unit-norm rescale.
 __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
@@ -223,6 +444,13 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   const int64_t gid = (int64_t)j * a.P + p;
   const double lp = pv ? a.loss[gid] : 0.0;
   const bool imp = pv && lp < a.pbest_loss[gid];
+  // the adaptive swarm's parameters of this node, and the particle its elite
+  // candidate replaces (convergence state)
+  const bool ap = a.apso_state != nullptr;
+  const double omega = ap ? a.apso_par[(int64_t)j * 3 + 0] : a.omega;
+  const double c1 = ap ? a.apso_par[(int64_t)j * 3 + 1] : a.c1;
+  const double c2 = ap ? a.apso_par[(int64_t)j * 3 + 2] : a.c2;
+  const bool el = ap && a.apso_state[j] == 3 && p == a.apso_worst[j];
   if (pv) {
     for (int d = dl; d < D; d += g.Dp) {
       const int64_t e = gid * D + d;
@@ -240,11 +468,11 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
       const uint4 w = philox4x32_10(make_uint4((uint32_t)(p * dh + m), a.iter, node, tree), key);
       const double r1 = u24(h ? w.z : w.x);
       const double r2 = u24(h ? w.w : w.y);
-      const double t0 = a.omega * a.v[e];
-      const double t1 = (a.c1 * r1) * (pb - xv);
-      const double t2 = (a.c2 * r2) * (gb[d] - xv);
+      const double t0 = omega * a.v[e];
+      const double t1 = (c1 * r1) * (pb - xv);
+      const double t2 = (c2 * r2) * (gb[d] - xv);
       const double vn = (t0 + t1) + t2;
-      a.v[e] = vn;
+      a.v[e] = el ? 0.0 : vn;
       buf[pl * D + d] = xv + vn;
     }
   }
@@ -258,7 +486,8 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   for (int d = dl; d < D; d += g.Dp) {
     const int64_t e = gid * D + d;
     // x + v == 0 exactly means x == -v: keep the previous position
-    const double xv = nrm > 0.0 ? buf[pl * D + d] / nrm : -a.v[e];
+    const double xv = el ? a.apso_elite[(int64_t)j * D + d]
+                         : (nrm > 0.0 ? buf[pl * D + d] / nrm : -a.v[e]);
     a.x[e] = xv;
     store_w(a.W_out, a.w_bf16, e, xv);
   }
@@ -344,6 +573,11 @@ void prepare_pso_kernels(int lds_max) {
     (void)hipGetLastError();
 }
 
+size_t apso_part_bytes(int n_nodes, int P) {
+  return (size_t)std::max(0, n_nodes) * std::max(0, P) * ((std::max(0, P) + AD_T - 1) / AD_T) *
+         sizeof(double);
+}
+
 slm_status launch_pso_init(const PsoArgs &a, hipStream_t s) {
   SLM_CHECK(a.D <= DMAX, SLM_E_SHAPE, "slm_pso_init: D = %d exceeds %d", a.D, DMAX);
   if ((int64_t)a.n_nodes * a.P == 0) return SLM_OK;
@@ -362,6 +596,15 @@ slm_status launch_pso_step(const PsoArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_pso_bests, dim3((unsigned)a.n_nodes), dim3(BEST_WG), 0, s, a);
   SLM_LAUNCHED();
   if (a.bests_only) return SLM_OK;
+  if (a.apso_state && a.move) {
+    SLM_CHECK(a.P >= 2, SLM_E_SHAPE, "apso: P = %d (at least 2 particles)", a.P);
+    const int nb = (a.P + AD_T - 1) / AD_T;
+    hipLaunchKernelGGL(k_apso_dist, dim3((unsigned)((int64_t)a.n_nodes * nb * nb)), dim3(256), 0,
+                       s, a);
+    SLM_LAUNCHED();
+    hipLaunchKernelGGL(k_apso_adapt, dim3((unsigned)a.n_nodes), dim3(256), 0, s, a);
+    SLM_LAUNCHED();
+  }
   const MoveGeom g = move_geom(a.D);
   const int64_t grid = (int64_t)a.n_nodes * ((a.P + g.PPB - 1) / g.PPB);
   const size_t lds = (size_t)g.PPB * a.D * sizeof(double);

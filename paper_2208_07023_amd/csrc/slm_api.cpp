@@ -67,6 +67,10 @@ struct TreeWS {
   void *W, *gW;
   int32_t *split, *gbest_p, *gbest_split, *node_id, *do_split;
   uint32_t *tree_off;   // tree of every searched node (several roots)
+  // adaptive swarm: per-node state, parameters, distances, worst particle,
+  // elite candidate, partial distance sums
+  int32_t *ap_state, *ap_worst;
+  double *ap_par, *ap_dist, *ap_f, *ap_elite, *ap_part;
   float *thr, *gbest_thr;
   int64_t *beg, *end, *n_left, *off_left, *off_right;
   uint64_t *seed_tree;
@@ -133,6 +137,15 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base, int sea
   w.end = c.take<int64_t>((size_t)F);
   w.node_id = c.take<int32_t>((size_t)F);
   if (n_roots > 1) w.tree_off = c.take<uint32_t>((size_t)F);
+  if (p.apso) {
+    w.ap_state = c.take<int32_t>((size_t)F);
+    w.ap_worst = c.take<int32_t>((size_t)F);
+    w.ap_par = c.take<double>((size_t)F * 3);
+    w.ap_dist = c.take<double>((size_t)F * p.P);
+    w.ap_f = c.take<double>((size_t)F);
+    w.ap_elite = c.take<double>((size_t)F * D);
+    w.ap_part = reinterpret_cast<double *>(c.take<char>(apso_part_bytes((int)F, p.P)));
+  }
   w.do_split = c.take<int32_t>((size_t)F);
   w.n_left = c.take<int64_t>((size_t)F);
   w.seed_tree = c.take<uint64_t>(2);
@@ -232,6 +245,11 @@ slm_status check_tree_params(const slm_tree_params *p, int64_t N, int32_t D) {
     SLM_CHECK(p->precision == 0 && (p->dft_top_n == 0 || p->dft_top_n == D), SLM_E_UNSUPPORTED,
               "slm_grow_tree: proposal 2 needs float32 data and no dft_top_n");
   }
+  SLM_CHECK(p->apso == 0 || p->apso == 1, SLM_E_INVALID, "slm_grow_tree: apso %d (0 or 1)",
+            p->apso);
+  if (p->apso)
+    SLM_CHECK(p->P >= 2 && p->proposal != 2, SLM_E_UNSUPPORTED,
+              "slm_grow_tree: the adaptive swarm needs P >= 2 and a swarm (not proposal 2)");
   if (p->proposal == 1) {
     SLM_CHECK(p->crit != SLM_MSE, SLM_E_UNSUPPORTED,
               "slm_grow_tree: the learned proposal needs class labels");
@@ -474,6 +492,11 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pa.zmin_reset = w.zmin; pa.zmax_reset = w.zmax;
   pa.seed_tree_dev = w.seed_tree;
   pa.tree_off = w.tree_off;
+  if (p.apso) {
+    pa.apso_state = w.ap_state; pa.apso_par = w.ap_par; pa.apso_dist = w.ap_dist;
+    pa.apso_f = w.ap_f; pa.apso_worst = w.ap_worst; pa.apso_elite = w.ap_elite;
+    pa.apso_part = w.ap_part; pa.apso_T = (uint32_t)std::max(1, p.T);
+  }
   slm_status st;
   const bool psearch = p.proposal == 2;
   if (psearch || (p.dft_top_n > 0 && p.dft_top_n < D)) {
@@ -603,7 +626,7 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)(p.proposal == 2 ? p.ps_R : 0),
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_pd : nullptr),
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_amax : nullptr),
-           (uint64_t)(uintptr_t)w.tree_off};
+           (uint64_t)(uintptr_t)w.tree_off, (uint64_t)p.apso};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -893,6 +916,42 @@ slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss,
   a.n_nodes = n_nodes; a.P = P; a.D = D; a.omega = omega; a.c1 = c1; a.c2 = c2;
   a.seed = seed; a.tree = tree; a.iter = iter; a.move = move;
   a.W_out = W_out; a.w_bf16 = w_dtype == SLM_BF16;
+  return launch_pso_step(a, S(stream));
+}
+
+size_t slm_apso_workspace(int32_t n_nodes, int32_t P) {
+  return std::max<size_t>(256, apso_part_bytes(n_nodes, P));
+}
+
+slm_status slm_apso_step(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,
+                         double *gbest_loss, int32_t *gbest_p, const double *loss,
+                         const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
+                         uint64_t seed, uint32_t tree, uint32_t iter, uint32_t T, int32_t *state,
+                         double *par, double *dist, double *f, int32_t *worst, double *elite,
+                         void *workspace, size_t ws_bytes, void *W_out, int32_t w_dtype,
+                         void *stream) {
+  clear_error();
+  SLM_CHECK(n_nodes >= 0 && P >= 2 && P <= PMAX && D >= 1 && D <= DMAX, SLM_E_SHAPE,
+            "slm_apso_step: bad sizes (2 <= P <= %d, 1 <= D <= %d)", PMAX, DMAX);
+  SLM_CHECK(w_dtype == SLM_F32 || w_dtype == SLM_BF16, SLM_E_DTYPE,
+            "slm_apso_step: W_out must be F32 or BF16");
+  SLM_CHECK(iter >= 1 && T >= 1, SLM_E_INVALID, "slm_apso_step: iter and T must be >= 1");
+  if (n_nodes == 0) return SLM_OK;
+  SLM_CHECK(x && v && pbest && pbest_loss && gbest && gbest_loss && gbest_p && loss && node_id &&
+                state && par && dist && f && worst && elite && workspace && W_out,
+            SLM_E_INVALID, "slm_apso_step: NULL pointer");
+  SLM_CHECK(ws_bytes >= apso_part_bytes(n_nodes, P), SLM_E_NOMEM,
+            "slm_apso_step: workspace of %zu bytes too small", ws_bytes);
+  slm_status pst = prepare_kernels();
+  if (pst) return pst;
+  PsoArgs a{};
+  a.x = x; a.v = v; a.pbest = pbest; a.pbest_loss = pbest_loss; a.gbest = gbest;
+  a.gbest_loss = gbest_loss; a.gbest_p = gbest_p; a.loss = loss; a.node_id = node_id;
+  a.n_nodes = n_nodes; a.P = P; a.D = D; a.seed = seed; a.tree = tree; a.iter = iter;
+  a.move = 1; a.W_out = W_out; a.w_bf16 = w_dtype == SLM_BF16;
+  a.apso_state = state; a.apso_par = par; a.apso_dist = dist; a.apso_f = f;
+  a.apso_worst = worst; a.apso_elite = elite;
+  a.apso_part = static_cast<double *>(workspace); a.apso_T = T;
   return launch_pso_step(a, S(stream));
 }
 

@@ -234,7 +234,19 @@ struct PsoArgs {
   // optional [n_nodes]: added to the tree id of node j's draws (the trees of
   // a forest grown together)
   const uint32_t *tree_off;
+  // adaptive swarm (APSO): state estimation and parameter change between the
+  // bests and the move; apso_state null = plain swarm
+  int32_t *apso_state;   // [n_nodes] 1 exploration .. 4 jumping-out
+  double *apso_par;      // [n_nodes * 3] omega, c1, c2
+  double *apso_dist;     // [n_nodes * P] mean distances
+  double *apso_f;        // [n_nodes] evolutionary factor
+  int32_t *apso_worst;   // [n_nodes] particle replaced by the elite candidate
+  double *apso_elite;    // [n_nodes * D] elite candidate (convergence)
+  double *apso_part;     // [n_nodes * P * ceil(P / 64)] partial distance sums
+  uint32_t apso_T;       // moves of the run (the elite step's sigma schedule)
 };
+// bytes of apso_part for n_nodes swarms of P particles
+size_t apso_part_bytes(int n_nodes, int P);
 slm_status launch_pso_init(const PsoArgs &a, hipStream_t s);
 void prepare_pso_kernels(int lds_max);
 slm_status launch_pso_step(const PsoArgs &a, hipStream_t s);

@@ -1,0 +1,151 @@
+"""GPU adaptive swarm (slm_apso_step; slm_grow_tree with apso = 1) against the
+oracle (oracle.apso):
+
+* one step on swarms spread, gathered around their global best (convergence,
+  elitist learning) and with the best far outside (jumping-out), P across a
+  64-particle tile boundary: mean distances, the evolutionary factor, the
+  state, omega / c1 / c2, the worst particle, the elite candidate and the
+  moved swarm, each against the oracle;
+* a whole APSO search of one node and an APSO tree: split losses and accuracy
+  close to the oracle's, graph replay identical.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import apso as A
+from oracle import pso as OP
+from oracle import split as OS
+from oracle import tree as OT
+from paper_2208_07023_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _unit(a):
+    return a / np.linalg.norm(a, axis=-1, keepdims=True)
+
+
+def _swarms(P, D, seed):
+    """Three nodes: spread; gathered around particle 5 (the best); particle 5
+    far from the others."""
+    st = inputs.random_pso_state(3, P, D, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    x = st.x.reshape(3, P, D).copy()
+    loss = st.loss.reshape(3, P).copy()
+    c = _unit(rng.standard_normal(D))
+    x[1] = _unit(c + 0.02 * rng.standard_normal((P, D)))
+    x[1, 5] = c
+    loss[1, 5] = -1.0
+    far = _unit(rng.standard_normal(D))
+    x[2] = _unit(-far + 0.05 * rng.standard_normal((P, D)))
+    x[2, 5] = far
+    loss[2, 5] = -1.0
+    st.x[:] = x.reshape(-1, D)
+    st.loss[:] = loss.reshape(-1)
+    return st
+
+
+@pytest.mark.parametrize("P,D", [(24, 13), (70, 9), (130, 40)])
+def test_apso_step_matches_oracle(gpu_lib, P, D):
+    api = gpu_lib
+    nn, seed, tree, it, T = 3, 21, 2, 4, 10
+    st = _swarms(P, D, seed=P + D)
+    node_id = np.array([3, 8, 11], dtype=np.int32)
+    state0 = np.array([1, 2, 3], dtype=np.int32)
+    par0 = np.array([[0.9, 2.0, 2.0], [0.7, 2.3, 1.6], [0.5, 1.7, 2.2]])
+    sw = api.pso_alloc(nn, P, D, node_id)
+    for name in ("x", "v", "pbest", "pbest_loss", "gbest", "gbest_loss"):
+        getattr(sw, name).copy_(_t(getattr(st, name)).view_as(getattr(sw, name)))
+    sw.gbest_p.copy_(_t(st.gbest_p))
+    ap = api.apso_alloc(sw)
+    ap.state.copy_(_t(state0))
+    ap.par.copy_(_t(par0))
+    api.apso_step(sw, ap, _t(st.loss), seed, tree, it, T)
+    torch.cuda.synchronize()
+    g = {k: getattr(ap, k).cpu().numpy() for k in ("state", "par", "dist", "f", "worst", "elite")}
+    gx, gv = sw.x.cpu().numpy().reshape(nn, P, D), sw.v.cpu().numpy().reshape(nn, P, D)
+    states = []
+    for j in range(nn):
+        s = slice(j * P, (j + 1) * P)
+        x, v = st.x[s].copy(), st.v[s].copy()
+        pb, pbl = st.pbest[s].copy(), st.pbest_loss[s].copy()
+        gb, gbl, gp = st.gbest[j].copy(), st.gbest_loss[j:j + 1].copy(), st.gbest_p[j:j + 1].copy()
+        OP.update_bests(x, st.loss[s], pb, pbl, gb, gbl, gp)
+        a = A.apso_adapt(x, gb, gp[0], st.loss[s], int(state0[j]), par0[j, 1], par0[j, 2], seed,
+                         tree, int(node_id[j]), it, T)
+        assert np.allclose(g["dist"][s], a["d"], rtol=1e-13, atol=0), j
+        assert g["f"][j] == pytest.approx(a["f"], abs=1e-12), j
+        assert g["state"][j] == a["state"], j
+        assert g["par"][j, 0] == pytest.approx(a["omega"], rel=1e-15), j
+        assert g["par"][j, 1] == pytest.approx(a["c1"], rel=1e-15) and \
+            g["par"][j, 2] == pytest.approx(a["c2"], rel=1e-15), j
+        assert g["worst"][j] == a["worst"], j
+        r1, r2 = OP.uniforms(seed, tree, int(node_id[j]), it, P, D)
+        xn, vn = OP.move(x, v, pb, gb, r1, r2, a["omega"], a["c1"], a["c2"])
+        if a["elite"] is not None:
+            assert np.allclose(g["elite"][j], a["elite"], rtol=0, atol=1e-14), j
+            xn[a["worst"]] = a["elite"]
+            vn[a["worst"]] = 0.0
+        assert np.allclose(gx[j], xn, rtol=0, atol=1e-12), j
+        assert np.allclose(gv[j], vn, rtol=0, atol=1e-12), j
+        states.append(a["state"])
+    # the three swarms read as intended: gathered around the best -> convergence,
+    # best far outside -> jumping-out
+    assert states[1] == A.CONVERGENCE and states[2] == A.JUMPING_OUT
+    assert np.array_equal(sw.W.cpu().numpy(), sw.x.cpu().numpy().astype(np.float32))
+
+
+def _oracle_params(cfg, search):
+    return OT.TreeParams(crit=cfg.crit, K=cfg.K, max_depth=cfg.max_depth, min_node=cfg.min_node,
+                         P=cfg.P, T=cfg.T, bins=cfg.bins, seed=cfg.seed, tree=cfg.tree,
+                         search=search)
+
+
+def test_apso_single_node_close_to_oracle(gpu_lib):
+    api = gpu_lib
+    X, y, _ = inputs.two_class_gaussian(1000, 8, seed=3)
+    cfg = api.TreeConfig(crit=api.GINI, K=2, max_depth=1, min_node=2, P=32, T=20, bins=0, seed=4,
+                         apso=True)
+    g = api.grow_tree(_t(X), _t(y), cfg)
+    o = OT.grow_tree(X, y, _oracle_params(cfg, 1))
+    print(f"APSO root loss gpu {g['split_loss'][0]:.6f} oracle {o.split_loss[0]:.6f}")
+    assert abs(g["split_loss"][0] - o.split_loss[0]) <= 0.01
+    assert g["split_loss"][0] < g["impurity"][0]
+
+
+def test_apso_tree_close_to_oracle_and_replays(gpu_lib):
+    api = gpu_lib
+    Xa, ya = inputs.cluster_mixture(3000, 10, 3, mean_std=1.0, seed=5)
+    X, y, Xt, yt = Xa[:2000], ya[:2000], Xa[2000:], ya[2000:]
+    cfg = api.TreeConfig(crit=api.ENTROPY, K=3, max_depth=3, min_node=16, P=32, T=10, bins=64,
+                         seed=6, apso=True)
+    Xd, yd = _t(X), _t(y)
+    g = api.grow_tree(Xd, yd, cfg)
+    o = OT.grow_tree(X, y, _oracle_params(cfg, 1))
+    acc_g = float((api.predict(g, _t(Xt)) == yt).mean())
+    acc_o = float((OT.predict(o, Xt) == yt).mean())
+    print(f"APSO tree held-out accuracy gpu {acc_g:.4f} oracle {acc_o:.4f}; "
+          f"root loss gpu {g['split_loss'][0]:.5f} oracle {o.split_loss[0]:.5f}")
+    assert abs(acc_g - acc_o) <= 0.05
+    assert g["split_loss"][0] == pytest.approx(o.split_loss[0], rel=0.02)
+    for i in range(g["n_nodes"]):
+        if g["left"][i] >= 0:
+            assert g["split_loss"][i] < g["impurity"][i]
+            assert g["n"][g["left"][i]] + g["n"][g["right"][i]] == g["n"][i]
+    cfg.use_graph = True
+    r = api.grow_tree(Xd, yd, cfg)
+    for k in ("w", "thr", "left", "right", "split_loss"):
+        assert np.array_equal(g[k], r[k]), k
+    # a forest of APSO trees grown together equals its trees grown alone
+    f = api.grow_forest(Xd, yd, cfg, 2, bootstrap=False)
+    for b in range(2):
+        cfg.tree = b
+        alone = api.grow_tree(Xd, yd, cfg)
+        mine = api.forest_tree(f, b)
+        for k in ("w", "thr", "left", "right"):
+            assert np.array_equal(mine[k], alone[k]), (b, k)
