@@ -160,21 +160,22 @@ def dft_vs_plain(Xd, yd, y, K, reps=3):
 
 
 def probsearch_vs_pso(Xd, yd, K):
-    """The paper's comparison of the swarm with the original SLM's
-    probabilistic search (Sec. II-B), on the benchmark's data: the root's
-    split loss and search time after T + 1 evaluations of P = 256 candidates
+    """The paper's comparison of the swarm (plain and adaptive, APSO) with the
+    original SLM's probabilistic search (Sec. II-B), on the benchmark's data:
+    the root's split loss and search time after T + 1 evaluations of P = 256 candidates
     (trees of depth 1; mean of 2 trees after one warm-up; the probabilistic
     search combines the root's 16 best DFT-ranked features, alpha0 = 10)."""
     import torch
 
     from paper_2208_07023_amd import api
     res = {}
-    for name, prop, Ts in (("pso", 0, (10, 50)), ("probabilistic_R16", 2, (10, 50, 200, 1000))):
+    for name, prop, apso, Ts in (("pso", 0, False, (10, 50)), ("apso", 0, True, (10, 50)),
+                                 ("probabilistic_R16", 2, False, (10, 50, 200, 1000))):
         arm = {}
         for T in Ts:
             cfg = api.TreeConfig(crit=api.ENTROPY, K=K, max_depth=1, min_node=32, P=256, T=T,
                                  bins=256, seed=0, use_graph=True, proposal=prop, ps_R=16,
-                                 ps_alpha0=10.0)
+                                 ps_alpha0=10.0, apso=apso)
             api.grow_tree(Xd, yd, cfg)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

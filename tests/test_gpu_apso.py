@@ -108,7 +108,7 @@ def _oracle_params(cfg, search):
 
 def test_apso_single_node_close_to_oracle(gpu_lib):
     api = gpu_lib
-    X, y, _ = inputs.two_class_gaussian(1000, 8, seed=3)
+    X, y = inputs.cluster_mixture(1000, 8, 2, mean_std=0.7, seed=3)
     cfg = api.TreeConfig(crit=api.GINI, K=2, max_depth=1, min_node=2, P=32, T=20, bins=0, seed=4,
                          apso=True)
     g = api.grow_tree(_t(X), _t(y), cfg)
