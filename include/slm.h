@@ -288,7 +288,11 @@ slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss,
  *   elite [n_nodes * D] (out, state 3 only): one coordinate (uniform) of the
  *     global best moved by 2 sigma N(0, 1), sigma = 1 - 0.9 iter / T, scaled
  *     to unit norm; it replaces the worst particle after the move, with zero
- *     velocity.
+ *     velocity;
+ *   sel [device, n_nodes * n_sel] or NULL (n_sel 0): the coordinates each
+ *     node's swarm lives in (its top DFT channels, Alg. 2); the elite step
+ *     then perturbs sel[j n_sel + floor(w n_sel / 2^32)] instead of
+ *     coordinate floor(w D / 2^32).
  * The draws of move iter use Philox counters (0 | 1, 0x20000000 + iter, node
  * id, tree).  P in 2..4096.  workspace [device] >= slm_apso_workspace(n_nodes,
  * P) bytes (partial distance sums).  Other arguments as slm_pso_step (with
@@ -300,8 +304,8 @@ slm_status slm_apso_step(double *x, double *v, double *pbest, double *pbest_loss
                          const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
                          uint64_t seed, uint32_t tree, uint32_t iter, uint32_t T, int32_t *state,
                          double *par, double *dist, double *f, int32_t *worst, double *elite,
-                         void *workspace, size_t ws_bytes, void *W_out, int32_t w_dtype,
-                         void *stream);
+                         const int32_t *sel, int32_t n_sel, void *workspace, size_t ws_bytes,
+                         void *W_out, int32_t w_dtype, void *stream);
 
 /* ------------------------------------------------------------------------
  * Mixed-precision screening of one swarm evaluation.  The paper scores a

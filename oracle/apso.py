@@ -32,7 +32,9 @@ this build, from that method as published:
   same r1, r2 draws as the plain swarm (oracle.pso);
 * the extra draws of move t come from Philox4x32-10 counters
   (0, APSO_STREAM + t, node, tree): delta1 = 0.05 + 0.05 u24(w0),
-  delta2 = 0.05 + 0.05 u24(w1), d = floor(w2 D / 2^32); and
+  delta2 = 0.05 + 0.05 u24(w1), d = floor(w2 D / 2^32) (with the swarm in
+  the span of a node's top n DFT channels, Alg. 2: the floor(w2 n / 2^32)-th
+  of those channels, so the step stays in the subspace); and
   (1, APSO_STREAM + t, node, tree): the normal draw from words 0 and 1 as in
   the swarm's start (Box-Muller, cosine branch).
 """
@@ -139,14 +141,19 @@ def adapt(state: int, c1: float, c2: float, d1: float, d2: float):
     return c1, c2
 
 
-def draws(seed: int, tree: int, node: int, t: int, D: int):
-    """(delta1, delta2, elite dimension, normal draw) of move t."""
+def draws(seed: int, tree: int, node: int, t: int, D: int, dims=None):
+    """(delta1, delta2, elite dimension, normal draw) of move t; with dims
+    (the swarm's coordinates, e.g. a node's top DFT channels) the dimension is
+    dims[floor(w2 len(dims) / 2^32)]."""
     ctr = np.array([[0, APSO_STREAM + t, node, tree], [1, APSO_STREAM + t, node, tree]],
                    dtype=np.uint64)
     w = philox4x32_10(ctr, seed_key(seed))
     d1 = 0.05 + 0.05 * float(u24(w[0, 0]))
     d2 = 0.05 + 0.05 * float(u24(w[0, 1]))
-    dim = int((int(w[0, 2]) * D) >> 32)
+    if dims is None:
+        dim = int((int(w[0, 2]) * D) >> 32)
+    else:
+        dim = int(dims[(int(w[0, 2]) * len(dims)) >> 32])
     u1 = (float(w[1, 0]) + 0.5) * (2.0 ** -32)
     u2 = float(w[1, 1]) * (2.0 ** -32)
     g = math.sqrt(-2.0 * math.log(u1)) * math.cos(TWO_PI * u2)
@@ -170,13 +177,14 @@ def worst_particle(loss) -> int:
 
 
 def apso_adapt(x, gbest, gbest_p: int, loss, state: int, c1: float, c2: float,
-               seed: int, tree: int, node: int, t: int, T: int):
-    """One state estimation and parameter change before move t (1..T).
+               seed: int, tree: int, node: int, t: int, T: int, dims=None):
+    """One state estimation and parameter change before move t (1..T); dims:
+    the coordinates the swarm lives in (None: all).
     Returns dict(d, f, state, omega, c1, c2, worst, elite or None)."""
     d = mean_distances(x)
     f = evolutionary_factor(d, max(0, int(gbest_p)))
     st = classify(f, state)
-    d1, d2, dim, g = draws(seed, tree, node, t, x.shape[1])
+    d1, d2, dim, g = draws(seed, tree, node, t, x.shape[1], dims)
     c1n, c2n = adapt(st, c1, c2, d1, d2)
     out = dict(d=d, f=f, state=st, omega=inertia(f), c1=c1n, c2=c2n, worst=worst_particle(loss),
                elite=None)
@@ -185,8 +193,10 @@ def apso_adapt(x, gbest, gbest_p: int, loss, state: int, c1: float, c2: float,
     return out
 
 
-def run_apso(evaluate, P, D, T, seed, tree, node, x0=None, log=None):
-    """APSO for one node; evaluate as in oracle.pso.run_pso.
+def run_apso(evaluate, P, D, T, seed, tree, node, x0=None, log=None, dims=None):
+    """APSO for one node; evaluate as in oracle.pso.run_pso.  dims: the
+    coordinates the swarm lives in (a start in their span, x0, keeps the others
+    at zero; the elitist step perturbs one of them).
     Returns dict(gbest, loss, split, thr, p, evals, history, states)."""
     x = init_positions(seed, tree, node, P, D) if x0 is None else np.array(x0, dtype=np.float64)
     v = np.zeros_like(x)
@@ -206,7 +216,8 @@ def run_apso(evaluate, P, D, T, seed, tree, node, x0=None, log=None):
         history.append(float(gbest_loss[0]))
         if t == T:
             break
-        a = apso_adapt(x, gbest, gbest_p[0], loss, state, c1, c2, seed, tree, node, t + 1, T)
+        a = apso_adapt(x, gbest, gbest_p[0], loss, state, c1, c2, seed, tree, node, t + 1, T,
+                       dims)
         if log is not None:
             log.append(a)
         state, c1, c2 = a["state"], a["c1"], a["c2"]

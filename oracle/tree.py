@@ -157,12 +157,13 @@ def grow_tree(X, target, prm: TreeParams, rows=None, keep_rows=False):
                 pd, am = probsearch.tables(R, prm.ps_alpha0)
                 res = probsearch.run_search(evaluate_node(Xn, tn, prm), prm.P, D, prm.T, prm.seed,
                                             prm.tree, hid, ranks, pd, am)
-            elif 0 < prm.dft_top_n < D:
+            sel = None
+            if prm.search != 2 and 0 < prm.dft_top_n < D:
                 sel = dft.top_n(dft.dft_losses(Xn, tn, prm.crit, prm.K, prm.bins), prm.dft_top_n)
                 x0 = dft.subspace_start(prm.seed, prm.tree, hid, prm.P, D, sel)
             if prm.search == 1:
                 res = apso.run_apso(evaluate_node(Xn, tn, prm), prm.P, D, prm.T, prm.seed,
-                                    prm.tree, hid, x0=x0)
+                                    prm.tree, hid, x0=x0, dims=sel)
             elif prm.search != 2:
                 res = run_pso(evaluate_node(Xn, tn, prm), prm.P, D, prm.T, prm.omega,
                               prm.c1, prm.c2, prm.seed, prm.tree, hid, x0=x0)

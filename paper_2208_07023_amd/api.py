@@ -80,7 +80,7 @@ _SIGS = {
                                   _D, _U64, _U32, _U32, _I32, _VP, _I32, _VP], _I32),
     "slm_apso_workspace": ([_I32, _I32], _SZ),
     "slm_apso_step": ([_VP] * 8 + [_VP, _I32, _I32, _I32, _U64, _U32, _U32, _U32, _VP, _VP, _VP,
-                                   _VP, _VP, _VP, _VP, _SZ, _VP, _I32, _VP], _I32),
+                                   _VP, _VP, _VP, _VP, _I32, _VP, _SZ, _VP, _I32, _VP], _I32),
     "slm_screen_select": ([_VP, _I32, _I32, _I32, _VP, _VP], _I32),
     "slm_screen_gather": ([_VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP], _I32),
     "slm_screen_merge": ([_VP, _VP, _VP, _VP, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP], _I32),
@@ -429,17 +429,22 @@ def apso_alloc(sw: Swarm) -> ApsoState:
                      elite=torch.zeros(n, sw.D, dtype=torch.float64, device=dev), ws=ws)
 
 
-def apso_step(sw: Swarm, ap: ApsoState, loss, seed: int, tree: int, it: int, T: int):
-    """One adaptive-swarm step (bests, state estimation, move) of every node."""
+def apso_step(sw: Swarm, ap: ApsoState, loss, seed: int, tree: int, it: int, T: int, sel=None):
+    """One adaptive-swarm step (bests, state estimation, move) of every node;
+    sel (device int32 [n_nodes, n]): the channels each swarm lives in."""
     load()
     nn = sw.node_id.numel()
     wt = BF16 if sw.W.dtype == torch.bfloat16 else F32
     _dev(loss, torch.float64, "loss")
+    n_sel = 0
+    if sel is not None:
+        _dev(sel, torch.int32, "sel")
+        n_sel = sel.shape[-1]
     _check(_lib.slm_apso_step(_p(sw.x), _p(sw.v), _p(sw.pbest), _p(sw.pbest_loss), _p(sw.gbest),
                               _p(sw.gbest_loss), _p(sw.gbest_p), _p(loss), _p(sw.node_id), nn,
                               sw.P, sw.D, seed, tree, it, T, _p(ap.state), _p(ap.par),
-                              _p(ap.dist), _p(ap.f), _p(ap.worst), _p(ap.elite), _p(ap.ws),
-                              ap.ws.numel(), _p(sw.W), wt, _stream()), "slm_apso_step")
+                              _p(ap.dist), _p(ap.f), _p(ap.worst), _p(ap.elite), _p(sel), n_sel,
+                              _p(ap.ws), ap.ws.numel(), _p(sw.W), wt, _stream()), "slm_apso_step")
 
 
 # ------------------------------------------------------------------ screening

@@ -303,7 +303,8 @@ __device__ __forceinline__ double apso_mu(int s, double f) {
 // [1.5, 2.5] and scaled to sum 4; the worst particle (highest loss, NaN as
 // +inf, lowest index on ties); in convergence the elite candidate: one
 // coordinate of the global best moved by 2 sigma N(0, 1), sigma = 1 - 0.9 t/T,
-// scaled to unit norm.  Draws: Philox counters (0 | 1, APSO_STREAM + t, node,
+// scaled to unit norm (with apso_sel, the coordinate is one of the node's
+// listed channels).  Draws: Philox counters (0 | 1, APSO_STREAM + t, node,
 // tree).
 __global__ __launch_bounds__(256) void k_apso_adapt(PsoArgs a) {
   __shared__ double s_mn[4], s_mx[4], s_wl[4], s_dg, s_nrm;
@@ -399,7 +400,13 @@ __global__ __launch_bounds__(256) void k_apso_adapt(PsoArgs a) {
     a.apso_f[j] = f;
     a.apso_worst[j] = wp == 0x7fffffff ? 0 : wp;
     s_state = st;
-    s_dim = (int)(((uint64_t)w0.z * (uint64_t)D) >> 32);
+    if (a.apso_sel && a.apso_n_sel > 0) {
+      const int k = (int)(((uint64_t)w0.z * (uint64_t)a.apso_n_sel) >> 32);
+      const int dsel = a.apso_sel[(int64_t)j * a.apso_n_sel + k];
+      s_dim = dsel >= 0 && dsel < D ? dsel : 0;
+    } else {
+      s_dim = (int)(((uint64_t)w0.z * (uint64_t)D) >> 32);
+    }
     if (st == 3) {
       const uint4 w1 = philox4x32_10(make_uint4(1u, APSO_STREAM + a.iter, node, tree), key);
       const double u1 = ((double)w1.x + 0.5) * 0x1p-32;

@@ -514,6 +514,10 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
     if (!psearch) {
       pa.dim_sel = w.dft_sel;
       pa.n_sel = p.dft_top_n;
+      if (p.apso) {   // the elitist step stays in the node's channels
+        pa.apso_sel = w.dft_sel;
+        pa.apso_n_sel = p.dft_top_n;
+      }
     }
   }
   st = launch_pso_init(pa, s);
@@ -928,9 +932,11 @@ slm_status slm_apso_step(double *x, double *v, double *pbest, double *pbest_loss
                          const int32_t *node_id, int32_t n_nodes, int32_t P, int32_t D,
                          uint64_t seed, uint32_t tree, uint32_t iter, uint32_t T, int32_t *state,
                          double *par, double *dist, double *f, int32_t *worst, double *elite,
-                         void *workspace, size_t ws_bytes, void *W_out, int32_t w_dtype,
-                         void *stream) {
+                         const int32_t *sel, int32_t n_sel, void *workspace, size_t ws_bytes,
+                         void *W_out, int32_t w_dtype, void *stream) {
   clear_error();
+  SLM_CHECK((sel == nullptr) == (n_sel == 0) && n_sel >= 0 && n_sel <= D, SLM_E_INVALID,
+            "slm_apso_step: sel and n_sel (1..D) go together");
   SLM_CHECK(n_nodes >= 0 && P >= 2 && P <= PMAX && D >= 1 && D <= DMAX, SLM_E_SHAPE,
             "slm_apso_step: bad sizes (2 <= P <= %d, 1 <= D <= %d)", PMAX, DMAX);
   SLM_CHECK(w_dtype == SLM_F32 || w_dtype == SLM_BF16, SLM_E_DTYPE,
@@ -952,6 +958,7 @@ slm_status slm_apso_step(double *x, double *v, double *pbest, double *pbest_loss
   a.apso_state = state; a.apso_par = par; a.apso_dist = dist; a.apso_f = f;
   a.apso_worst = worst; a.apso_elite = elite;
   a.apso_part = static_cast<double *>(workspace); a.apso_T = T;
+  a.apso_sel = sel; a.apso_n_sel = n_sel;
   return launch_pso_step(a, S(stream));
 }
 

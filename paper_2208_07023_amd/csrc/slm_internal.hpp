@@ -244,6 +244,10 @@ struct PsoArgs {
   double *apso_elite;    // [n_nodes * D] elite candidate (convergence)
   double *apso_part;     // [n_nodes * P * ceil(P / 64)] partial distance sums
   uint32_t apso_T;       // moves of the run (the elite step's sigma schedule)
+  // optional [n_nodes, apso_n_sel]: the coordinates the swarm lives in (the
+  // top DFT channels); the elite step perturbs one of them
+  const int32_t *apso_sel;
+  int apso_n_sel;
 };
 // bytes of apso_part for n_nodes swarms of P particles
 size_t apso_part_bytes(int n_nodes, int P);

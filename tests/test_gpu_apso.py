@@ -50,11 +50,14 @@ def _swarms(P, D, seed):
     return st
 
 
-@pytest.mark.parametrize("P,D", [(24, 13), (70, 9), (130, 40)])
-def test_apso_step_matches_oracle(gpu_lib, P, D):
+@pytest.mark.parametrize("P,D,n_sel", [(24, 13, 0), (70, 9, 0), (130, 40, 0), (70, 12, 4)])
+def test_apso_step_matches_oracle(gpu_lib, P, D, n_sel):
     api = gpu_lib
     nn, seed, tree, it, T = 3, 21, 2, 4, 10
     st = _swarms(P, D, seed=P + D)
+    rng = np.random.default_rng(P)
+    sel = (np.stack([rng.choice(D, n_sel, replace=False) for _ in range(nn)]).astype(np.int32)
+           if n_sel else None)
     node_id = np.array([3, 8, 11], dtype=np.int32)
     state0 = np.array([1, 2, 3], dtype=np.int32)
     par0 = np.array([[0.9, 2.0, 2.0], [0.7, 2.3, 1.6], [0.5, 1.7, 2.2]])
@@ -65,7 +68,7 @@ def test_apso_step_matches_oracle(gpu_lib, P, D):
     ap = api.apso_alloc(sw)
     ap.state.copy_(_t(state0))
     ap.par.copy_(_t(par0))
-    api.apso_step(sw, ap, _t(st.loss), seed, tree, it, T)
+    api.apso_step(sw, ap, _t(st.loss), seed, tree, it, T, sel=None if sel is None else _t(sel))
     torch.cuda.synchronize()
     g = {k: getattr(ap, k).cpu().numpy() for k in ("state", "par", "dist", "f", "worst", "elite")}
     gx, gv = sw.x.cpu().numpy().reshape(nn, P, D), sw.v.cpu().numpy().reshape(nn, P, D)
@@ -77,7 +80,7 @@ def test_apso_step_matches_oracle(gpu_lib, P, D):
         gb, gbl, gp = st.gbest[j].copy(), st.gbest_loss[j:j + 1].copy(), st.gbest_p[j:j + 1].copy()
         OP.update_bests(x, st.loss[s], pb, pbl, gb, gbl, gp)
         a = A.apso_adapt(x, gb, gp[0], st.loss[s], int(state0[j]), par0[j, 1], par0[j, 2], seed,
-                         tree, int(node_id[j]), it, T)
+                         tree, int(node_id[j]), it, T, None if sel is None else sel[j])
         assert np.allclose(g["dist"][s], a["d"], rtol=1e-13, atol=0), j
         assert g["f"][j] == pytest.approx(a["f"], abs=1e-12), j
         assert g["state"][j] == a["state"], j
@@ -149,3 +152,26 @@ def test_apso_tree_close_to_oracle_and_replays(gpu_lib):
         mine = api.forest_tree(f, b)
         for k in ("w", "thr", "left", "right"):
             assert np.array_equal(mine[k], alone[k]), (b, k)
+
+
+def test_apso_in_top_dft_channels(gpu_lib):
+    """APSO over each node's top n DFT channels (Alg. 2 with the adaptive
+    swarm): every split direction lies in its node's channels (checked against
+    the oracle's DFT where the node's rows are known exactly)."""
+    from oracle import dft as OD
+    api = gpu_lib
+    D, K, n = 16, 3, 3
+    X, y = inputs.cluster_mixture(8000, D, K, clusters_per_class=2, mean_std=1.0, seed=23)
+    cfg = api.TreeConfig(crit=api.ENTROPY, K=K, max_depth=3, min_node=32, P=32, T=12, bins=64,
+                         seed=5, dft_top_n=n, apso=True)
+    tr = api.grow_tree(_t(X), _t(y), cfg)
+    split = 0
+    for i in range(tr["n_nodes"]):
+        if tr["left"][i] < 0:
+            continue
+        split += 1
+        support = np.nonzero(tr["w"][i])[0]
+        assert 1 <= len(support) <= n, i
+    top = OD.top_n(OD.dft_losses(X, y, api.ENTROPY, K, 64), n)
+    assert set(np.nonzero(tr["w"][0])[0].tolist()) <= set(top.tolist())
+    assert split >= 2

@@ -154,3 +154,21 @@ def test_apso_tree_root_is_the_apso_run():
     assert np.array_equal(tr["w"][0], r["gbest"].astype(np.float32))
     assert tr["split_loss"][0] == r["loss"] < tr["impurity"][0]
     assert tr["n"][1] + tr["n"][2] == 400
+
+
+def test_run_in_a_subspace_stays_there():
+    from oracle import dft as OD
+    rng = np.random.default_rng(6)
+    D, dims = 9, np.array([7, 2, 4])
+    target = np.zeros(D)
+    target[dims] = rng.standard_normal(3)
+    x0 = OD.subspace_start(3, 0, 1, 16, D, dims)
+    log = []
+    r = A.run_apso(_angle_loss(target), 16, D, 30, 3, 0, 1, x0=x0, log=log, dims=dims)
+    out = np.setdiff1d(np.arange(D), dims)
+    assert np.all(r["gbest"][out] == 0.0)
+    assert any(a["elite"] is not None for a in log)
+    for a in log:
+        if a["elite"] is not None:
+            assert np.all(a["elite"][out] == 0.0)
+    assert r["loss"] < 1e-3
