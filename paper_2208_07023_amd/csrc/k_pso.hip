@@ -214,72 +214,85 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
 // evolutionary state from the particles' mean distances, changes c1, c2 and
 // the inertia weight with the state, and in the convergence state prepares an
 // elitist-learning candidate that replaces its worst particle after the move.
-constexpr int AD_T = 64;          // particle tile of the distance kernel
 constexpr int AD_KC = 16;         // dimensions per LDS chunk
 constexpr uint32_t APSO_STREAM = 0x20000000u;
 
-// Partial sums of ||x_i - x_j|| over the j of one 64-particle tile, for the
-// i of another: work-group (node, i tile, j tile), 256 threads, each a 4 x 4
-// block of pairs; dimensions staged through LDS 16 at a time.  part[(node P +
-// i) nb + j tile] (nb tiles per node).
+// Partial sums of ||x_i - x_j|| over the j of one particle tile, for the i of
+// another: work-group (node, i tile, j tile) of 256 threads (16 x 16), each an
+// MT x MT block of pairs (tiles of 16 MT particles); dimensions staged through
+// LDS 16 at a time.  part[(node P + i) * ceil(P / 16) + j tile].  Few nodes
+// take small tiles (enough work-groups to fill the chip), many nodes large
+// ones (fewer LDS reads per pair).
+template <int MT>
 __global__ __launch_bounds__(256) void k_apso_dist(PsoArgs a) {
-  __shared__ double xi[AD_T][AD_KC + 1], xj[AD_T][AD_KC + 1];
-  const int P = a.P, D = a.D, nb = (P + AD_T - 1) / AD_T;
+  constexpr int TL = 16 * MT;
+  __shared__ double xi[TL][AD_KC + 1], xj[TL][AD_KC + 1];
+  const int P = a.P, D = a.D, nb = (P + TL - 1) / TL, stride = (P + 15) / 16;
   const int blk = blockIdx.x;
   const int j = blk / (nb * nb), bi = (blk / nb) % nb, bj = blk % nb;
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
   const int64_t base = (int64_t)j * P;
-  double acc[4][4];
+  double acc[MT][MT];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int r = 0; r < MT; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int c = 0; c < MT; ++c) acc[r][c] = 0.0;
   for (int d0 = 0; d0 < D; d0 += AD_KC) {
 #pragma unroll
-    for (int k = 0; k < AD_T * AD_KC / 256; ++k) {
+    for (int k = 0; k < MT; ++k) {
       const int e = tid + 256 * k, row = e / AD_KC, col = e % AD_KC;
-      const int i = bi * AD_T + row, jj = bj * AD_T + row, d = d0 + col;
+      const int i = bi * TL + row, jj = bj * TL + row, d = d0 + col;
       xi[row][col] = i < P && d < D ? a.x[(base + i) * D + d] : 0.0;
       xj[row][col] = jj < P && d < D ? a.x[(base + jj) * D + d] : 0.0;
     }
     __syncthreads();
 #pragma unroll 4
     for (int k = 0; k < AD_KC; ++k) {
-      double u[4], w[4];
+      double u[MT], w[MT];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) u[r] = xi[ti * 4 + r][k];
+      for (int r = 0; r < MT; ++r) u[r] = xi[ti * MT + r][k];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) w[c] = xj[tj * 4 + c][k];
+      for (int c = 0; c < MT; ++c) w[c] = xj[tj * MT + c][k];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < MT; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < MT; ++c) {
           const double df = u[r] - w[c];
           acc[r][c] = acc[r][c] + df * df;
         }
     }
     __syncthreads();
   }
-  // row sums over this thread's 4 columns, then over the 16 column groups in
+  // row sums over this thread's MT columns, then over the 16 column groups in
   // a fixed order (the LDS of the staging is reused)
-  double *red = &xi[0][0];   // [64 rows][16 groups] fits in xi
+  double *red = &xi[0][0];   // [TL rows][16 groups] fits in xi
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < MT; ++r) {
     double s = 0.0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (bj * AD_T + tj * 4 + c < P) s = s + sqrt(acc[r][c]);
-    red[(ti * 4 + r) * 16 + tj] = s;
+    for (int c = 0; c < MT; ++c)
+      if (bj * TL + tj * MT + c < P) s = s + sqrt(acc[r][c]);
+    red[(ti * MT + r) * 16 + tj] = s;
   }
   __syncthreads();
-  if (tid < AD_T) {
-    const int i = bi * AD_T + tid;
+  if (tid < TL) {
+    const int i = bi * TL + tid;
     if (i < P) {
       double s = 0.0;
       for (int g = 0; g < 16; ++g) s = s + red[tid * 16 + g];
-      a.apso_part[(base + i) * nb + bj] = s;
+      a.apso_part[(base + i) * stride + bj] = s;
     }
   }
+}
+
+// micro-tile of the distance kernel: the largest whose grid still has 512
+// work-groups (1 when none has)
+__host__ __device__ __forceinline__ int apso_mt(int n_nodes, int P) {
+  for (int mt = 4; mt > 1; mt >>= 1) {
+    const int64_t nb = (P + 16 * mt - 1) / (16 * mt);
+    if ((int64_t)n_nodes * nb * nb >= 512) return mt;
+  }
+  return 1;
 }
 
 __device__ __forceinline__ double apso_mu(int s, double f) {
@@ -311,14 +324,15 @@ __global__ __launch_bounds__(256) void k_apso_adapt(PsoArgs a) {
   __shared__ int s_wp[4], s_dim, s_state;
   __shared__ double e[DMAX];
   const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int P = a.P, D = a.D, nb = (P + AD_T - 1) / AD_T;
+  const int P = a.P, D = a.D, stride = (P + 15) / 16;
+  const int nb = (P + 16 * apso_mt(a.n_nodes, P) - 1) / (16 * apso_mt(a.n_nodes, P));
   const int64_t base = (int64_t)j * P;
   const int g = max(0, a.gbest_p[j]);
   double mn = __builtin_huge_val(), mx = -__builtin_huge_val(), wl = -__builtin_huge_val();
   int wp = 0x7fffffff;
   for (int i = tid; i < P; i += 256) {
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s = s + a.apso_part[(base + i) * nb + b];
+    for (int b = 0; b < nb; ++b) s = s + a.apso_part[(base + i) * stride + b];
     const double di = s / (double)(P - 1);
     a.apso_dist[base + i] = di;
     mn = fmin(mn, di);
@@ -581,7 +595,7 @@ void prepare_pso_kernels(int lds_max) {
 }
 
 size_t apso_part_bytes(int n_nodes, int P) {
-  return (size_t)std::max(0, n_nodes) * std::max(0, P) * ((std::max(0, P) + AD_T - 1) / AD_T) *
+  return (size_t)std::max(0, n_nodes) * std::max(0, P) * ((std::max(0, P) + 15) / 16) *
          sizeof(double);
 }
 
@@ -605,9 +619,11 @@ slm_status launch_pso_step(const PsoArgs &a, hipStream_t s) {
   if (a.bests_only) return SLM_OK;
   if (a.apso_state && a.move) {
     SLM_CHECK(a.P >= 2, SLM_E_SHAPE, "apso: P = %d (at least 2 particles)", a.P);
-    const int nb = (a.P + AD_T - 1) / AD_T;
-    hipLaunchKernelGGL(k_apso_dist, dim3((unsigned)((int64_t)a.n_nodes * nb * nb)), dim3(256), 0,
-                       s, a);
+    const int mt = apso_mt(a.n_nodes, a.P), nb = (a.P + 16 * mt - 1) / (16 * mt);
+    const dim3 grid((unsigned)((int64_t)a.n_nodes * nb * nb));
+    if (mt == 4) hipLaunchKernelGGL(k_apso_dist<4>, grid, dim3(256), 0, s, a);
+    else if (mt == 2) hipLaunchKernelGGL(k_apso_dist<2>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_apso_dist<1>, grid, dim3(256), 0, s, a);
     SLM_LAUNCHED();
     hipLaunchKernelGGL(k_apso_adapt, dim3((unsigned)a.n_nodes), dim3(256), 0, s, a);
     SLM_LAUNCHED();

@@ -175,3 +175,26 @@ def test_apso_in_top_dft_channels(gpu_lib):
     top = OD.top_n(OD.dft_losses(X, y, api.ENTROPY, K, 64), n)
     assert set(np.nonzero(tr["w"][0])[0].tolist()) <= set(top.tolist())
     assert split >= 2
+
+
+@pytest.mark.parametrize("nn,P,D", [(3, 70, 9), (40, 130, 7), (40, 256, 20)])
+def test_apso_distances_every_tile_size(gpu_lib, nn, P, D):
+    """Mean distances and evolutionary factors of node batches that take the
+    distance kernel's 16-, 32- and 64-particle tiles."""
+    api = gpu_lib
+    st = inputs.random_pso_state(nn, P, D, seed=nn + P)
+    node_id = np.arange(nn, dtype=np.int32)
+    sw = api.pso_alloc(nn, P, D, node_id)
+    for name in ("x", "v", "pbest", "pbest_loss", "gbest", "gbest_loss"):
+        getattr(sw, name).copy_(_t(getattr(st, name)).view_as(getattr(sw, name)))
+    sw.gbest_p.copy_(_t(st.gbest_p))
+    ap = api.apso_alloc(sw)
+    api.apso_step(sw, ap, _t(st.loss), 1, 0, 2, 10)
+    torch.cuda.synchronize()
+    dist, f = ap.dist.cpu().numpy(), ap.f.cpu().numpy()
+    gp = sw.gbest_p.cpu().numpy()
+    for j in range(nn):
+        s = slice(j * P, (j + 1) * P)
+        d = A.mean_distances(st.x[s])
+        assert np.allclose(dist[s], d, rtol=1e-13, atol=0), j
+        assert f[j] == pytest.approx(A.evolutionary_factor(d, gp[j]), abs=1e-12), j
