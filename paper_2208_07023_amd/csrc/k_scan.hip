@@ -299,13 +299,57 @@ Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
     // tiles over more rows merge less for the same parallelism (measured,
     // N = 1e5, P = 256 root: 52 -> 39-44 us; tiles of 4 lose to the extra
     // loads of narrow row segments).
+    //
+    // The chunk length is the one with the fewest rows on the busiest CU.
+    // Items (chunk pieces of n_nodes equal nodes, a chunk cut by a node
+    // boundary being two) go out in order, CUs / ceil(P / 8) per round of
+    // work-groups: each round costs its longest item, and every extra round
+    // a fixed 3072 rows (its start latency).  Chunks are whole multiples of
+    // 1024 rows, so every wave's rows of a full chunk go through the
+    // 16-row unrolled loop (12544-row chunks: 42.2 us, 13312: 35.5 us, both 8
+    // items).  Measured on MI355X (N = 1e5,
+    // P = 256, standalone scan), the time follows this cost: one node 35.6 us
+    // at 8 items of 13312 rows against 46.9 us at 10 items of 10240 (a
+    // second round of 10240 rows); four nodes of 25 000 rows 50.7 us at 16
+    // items of 8192 against 68.1 us at one item per node (25 000 rows).
     if (N * n_pt <= slots * 4096 && N / std::max(1, n_nodes) >= 16384 && P >= 8) {
       const int64_t n_pt8 = (P + 7) / 8;
-      const int64_t chunks = std::max<int64_t>(1, (int64_t)num_cus() / n_pt8 - n_nodes);
-      int64_t ch = ((N + chunks - 1) / chunks + 1023) / 1024 * 1024;
-      ch = std::max<int64_t>(std::max<int64_t>(4096, chunk_min(N)), std::min<int64_t>(CH_MAX, ch));
+      const int64_t per = std::max<int64_t>(1, (int64_t)num_cus() / n_pt8);
+      const int nn = std::max(1, n_nodes);
+      // the last answer is kept: one search per shape, not per launch
+      static thread_local int64_t memo[4] = {-1, -1, -1, -1};
+      if (memo[0] == N && memo[1] == nn && memo[2] == per) {
+        pl.PT = 8;
+        pl.CH = memo[3];
+        pl.G = std::max(1, 32 / pl.PT);
+        return pl;
+      }
+      int64_t best = -1, best_cost = 0;
+      for (int64_t c = std::max<int64_t>(4096, (chunk_min(N) + 1023) / 1024 * 1024); c <= CH_MAX;
+           c += 1024) {
+        int64_t cost = 0, rmax = 0, idx = 0;
+        for (int j = 0; j < nn; ++j) {
+          const int64_t b = N * j / nn, e = N * (j + 1) / nn;
+          for (int64_t k = b / c; k * c < e; ++k) {
+            rmax = std::max(rmax, std::min(e, (k + 1) * c) - std::max(b, k * c));
+            if (++idx % per == 0) {
+              cost += rmax;
+              rmax = 0;
+            }
+          }
+        }
+        cost += rmax + 3072 * ((idx + per - 1) / per - 1);
+        if (best < 0 || cost < best_cost) {
+          best = c;
+          best_cost = cost;
+        }
+      }
+      memo[0] = N;
+      memo[1] = nn;
+      memo[2] = per;
+      memo[3] = best;
       pl.PT = 8;
-      pl.CH = ch;
+      pl.CH = best;
     }
   }
   pl.G = std::max(1, 32 / pl.PT);
