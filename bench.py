@@ -40,10 +40,10 @@ FP32_PEAK_TFLOPS = 157.3
 # Summary and commands: profiles/traffic_plain_tree_N100k_D64_P256.md
 TRAFFIC = {
     "k_scan_hist": {"source": "paper_2208_07023_amd/csrc/k_scan.hip",
-                    "sha256": "93773a45e8b84ecad8f207809ede5e131f06e95342a292b9c9e02cea214df180",
-                    "fetch_kib": 43091.0, "write_kib": 3688.6},
+                    "sha256": "1b66fdfd18c96549233842d08856923bcf5bf75ef27492a5cc3618364facb26a",
+                    "fetch_kib": 43097.7, "write_kib": 4152.8},
     "k_scan_finish_bins": {"source": "paper_2208_07023_amd/csrc/k_scan.hip",
-                           "sha256": "93773a45e8b84ecad8f207809ede5e131f06e95342a292b9c9e02cea214df180",
+                           "sha256": "1b66fdfd18c96549233842d08856923bcf5bf75ef27492a5cc3618364facb26a",
                            "fetch_kib": 3178.0, "write_kib": 3096.0},
     "k_project": {"source": "paper_2208_07023_amd/csrc/k_project.hip",
                   "sha256": "d7ce5b1df898b676221c8248f9417a4736e5f4fbf0e89cc6f5a2f29ab775a325",
