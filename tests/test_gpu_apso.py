@@ -198,3 +198,36 @@ def test_apso_distances_every_tile_size(gpu_lib, nn, P, D):
         d = A.mean_distances(st.x[s])
         assert np.allclose(dist[s], d, rtol=1e-13, atol=0), j
         assert f[j] == pytest.approx(A.evolutionary_factor(d, gp[j]), abs=1e-12), j
+
+
+@pytest.mark.parametrize("kind", ["regression", "screened"])
+def test_apso_tree_other_modes(gpu_lib, kind):
+    """APSO with the MSE criterion, and with bfloat16 screening: valid splits,
+    and the same tree on a graph replay."""
+    api = gpu_lib
+    if kind == "regression":
+        X, y = inputs.friedman1(6000, 8, seed=3)
+        Xd, yd = _t(X), _t(y)
+        cfg = api.TreeConfig(crit=api.MSE, K=0, max_depth=3, min_node=16, P=32, T=8, bins=64,
+                             seed=2, apso=True)
+    else:
+        from oracle import screen as SC
+        X, y = inputs.cluster_mixture(6000, 16, 3, seed=3)
+        Xd = torch.from_numpy(SC.bf16_round(X)).cuda().to(torch.bfloat16)
+        yd = _t(y)
+        cfg = api.TreeConfig(crit=api.GINI, K=3, max_depth=3, min_node=16, P=32, T=8, bins=64,
+                             seed=2, apso=True, precision=1, rescore_k=8)
+    g = api.grow_tree(Xd, yd, cfg)
+    split = 0
+    for i in range(g["n_nodes"]):
+        l, r = g["left"][i], g["right"][i]
+        if l >= 0:
+            split += 1
+            assert g["split_loss"][i] < g["impurity"][i]
+            assert g["n"][l] + g["n"][r] == g["n"][i] and g["n"][l] > 0 and g["n"][r] > 0
+    assert split >= 2
+    if kind == "screened":   # deterministic (the regression sums use atomics)
+        cfg.use_graph = True
+        r2 = api.grow_tree(Xd, yd, cfg)
+        for k in ("w", "thr", "left", "right"):
+            assert np.array_equal(g[k], r2[k]), k

@@ -230,3 +230,26 @@ def test_boost_training_loss_close_to_oracle(gpu_lib, n_classes):
         lo = np.mean((y - Fo[-1]) ** 2)
     print(f"boost training loss gpu {lg:.5f} oracle {lo:.5f}")
     assert lg <= 1.05 * lo
+
+
+def test_bf16_forest_with_odd_rows_equals_trees_alone(gpu_lib):
+    """Screened (bfloat16 X) forest with D odd: 26-byte rows take the gather's
+    2-byte path; every tree still equals the tree grown alone."""
+    from oracle import screen as SC
+    api = gpu_lib
+    N, D, K, nt = 5000, 13, 3, 2
+    X, y = inputs.cluster_mixture(N, D, K, seed=31)
+    X = SC.bf16_round(X)
+    Xb = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    cfg = api.TreeConfig(crit=api.GINI, K=K, max_depth=3, min_node=16, P=32, T=4, bins=64, seed=9,
+                         precision=1, rescore_k=8, tree=4)
+    f = api.grow_forest(Xb, _t(y), cfg, nt, return_samples=True)
+    for b in range(nt):
+        idx = E.bootstrap_indices(9, 4 + b, N)
+        assert np.array_equal(f["samples"][b].cpu().numpy(), idx)
+        cfg.tree = 4 + b
+        alone = api.grow_tree(Xb[torch.from_numpy(idx).cuda()].contiguous(), _t(y[idx]), cfg)
+        cfg.tree = 4
+        mine = api.forest_tree(f, b)
+        for k in ("w", "thr", "left", "right", "n", "split_loss"):
+            assert np.array_equal(mine[k], alone[k]), (b, k)
