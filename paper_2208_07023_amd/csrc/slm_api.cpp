@@ -276,10 +276,43 @@ struct HNode {
   uint32_t tree;   // root index (trees grown together)
 };
 
+// ---------------------------------------------------------------- pinned staging
+// The tree driver's per-depth host <-> device transfers go through
+// page-locked host memory: one arena per thread, grown at the start of a
+// build (when no transfer of an earlier build is in flight) and then reused,
+// so every transfer is a direct DMA copy instead of a staged pageable one.
+struct PinnedArena {
+  char *base = nullptr;
+  size_t cap = 0, off = 0;
+};
+thread_local PinnedArena g_pin;
+
+slm_status pinned_begin(size_t bytes) {
+  if (g_pin.cap < bytes) {
+    if (g_pin.base) (void)hipHostFree(g_pin.base);
+    g_pin.base = nullptr;
+    g_pin.cap = 0;
+    SLM_HIP(hipHostMalloc(reinterpret_cast<void **>(&g_pin.base), bytes, hipHostMallocDefault));
+    g_pin.cap = bytes;
+  }
+  g_pin.off = 0;
+  return SLM_OK;
+}
+
+template <typename T>
+T *pinned_take(size_t n) {
+  const size_t o = (g_pin.off + 63) / 64 * 64;
+  g_pin.off = o + n * sizeof(T);
+  return reinterpret_cast<T *>(g_pin.base + o);
+}
+
+size_t pinned_bytes(size_t n, size_t elem) { return (n * elem + 63) / 64 * 64; }
+
+// host copies of the node statistics (capacity 2F entries, pinned)
 struct StatsHost {
-  std::vector<uint32_t> counts, cnt;
-  std::vector<double> s1, s2;
-  std::vector<unsigned long long> ymin, ymax;
+  uint32_t *counts, *cnt;
+  double *s1, *s2;
+  unsigned long long *ymin, *ymax;
 };
 
 double dec_f64(unsigned long long e) {
@@ -331,20 +364,13 @@ void summarize(const StatsHost &h, int i, int crit, int K, double *imp, bool *im
 
 slm_status read_stats(const TreeWS &w, int n, int crit, int K, StatsHost &h, hipStream_t s) {
   if (crit == SLM_MSE) {
-    h.cnt.resize(n);
-    h.s1.resize(n);
-    h.s2.resize(n);
-    h.ymin.resize(n);
-    h.ymax.resize(n);
-    SLM_HIP(hipMemcpyAsync(h.cnt.data(), w.st.cnt, n * 4, hipMemcpyDeviceToHost, s));
-    SLM_HIP(hipMemcpyAsync(h.s1.data(), w.st.s1, n * 8, hipMemcpyDeviceToHost, s));
-    SLM_HIP(hipMemcpyAsync(h.s2.data(), w.st.s2, n * 8, hipMemcpyDeviceToHost, s));
-    SLM_HIP(hipMemcpyAsync(h.ymin.data(), w.st.ymin, n * 8, hipMemcpyDeviceToHost, s));
-    SLM_HIP(hipMemcpyAsync(h.ymax.data(), w.st.ymax, n * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.cnt, w.st.cnt, n * 4, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.s1, w.st.s1, n * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.s2, w.st.s2, n * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.ymin, w.st.ymin, n * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.ymax, w.st.ymax, n * 8, hipMemcpyDeviceToHost, s));
   } else {
-    h.counts.resize((size_t)n * K);
-    SLM_HIP(hipMemcpyAsync(h.counts.data(), w.st.counts, (size_t)n * K * 4,
-                           hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(h.counts, w.st.counts, (size_t)n * K * 4, hipMemcpyDeviceToHost, s));
   }
   return SLM_OK;
 }
@@ -1264,20 +1290,39 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
     SLM_HIP(hipMemsetAsync(w.stat_sums, 0, stats_workspace_bytes((int)F, D, Kc), s));
   const uint64_t seed_tree[2] = {p.seed, (uint64_t)p.tree};
   SLM_HIP(hipMemcpyAsync(w.seed_tree, seed_tree, 16, hipMemcpyHostToDevice, s));
-  std::vector<int64_t> hb(F), he(F), hnl(F);
-  std::vector<int32_t> hid(F), hsplit(F);
-  std::vector<uint32_t> htr(F);
+  // pinned host arrays of the per-depth transfers (the previous build's
+  // transfers have completed: every build ends with a synchronisation)
+  {
+    const size_t F2 = (size_t)2 * F;
+    const size_t need = 3 * pinned_bytes(F, 8) + 3 * pinned_bytes(F, 4) + pinned_bytes(F, 8) +
+                        pinned_bytes(F, 4) + pinned_bytes((size_t)F * D, 8) +
+                        pinned_bytes((size_t)F * D, 4) + pinned_bytes(F2 * Kc, 4) +
+                        pinned_bytes(F2, 4) + 4 * pinned_bytes(F2, 8) + 64;
+    if ((st = pinned_begin(need))) return st;
+  }
+  int64_t *hb = pinned_take<int64_t>(F), *he = pinned_take<int64_t>(F),
+          *hnl = pinned_take<int64_t>(F);
+  int32_t *hid = pinned_take<int32_t>(F), *hsplit = pinned_take<int32_t>(F);
+  uint32_t *htr = pinned_take<uint32_t>(F);
+  double *hgl = pinned_take<double>(F), *hgb = pinned_take<double>((size_t)F * D);
+  float *hgt = pinned_take<float>(F), *hgw = pinned_take<float>((size_t)F * D);
+  StatsHost sh;
+  sh.counts = pinned_take<uint32_t>((size_t)2 * F * Kc);
+  sh.cnt = pinned_take<uint32_t>((size_t)2 * F);
+  sh.s1 = pinned_take<double>((size_t)2 * F);
+  sh.s2 = pinned_take<double>((size_t)2 * F);
+  sh.ymin = pinned_take<unsigned long long>((size_t)2 * F);
+  sh.ymax = pinned_take<unsigned long long>((size_t)2 * F);
   for (int r = 0; r < n_roots; ++r) {
     hb[r] = roots[r].first;
     he[r] = roots[r].second;
   }
-  SLM_HIP(hipMemcpyAsync(w.beg, hb.data(), n_roots * 8, hipMemcpyHostToDevice, s));
-  SLM_HIP(hipMemcpyAsync(w.end, he.data(), n_roots * 8, hipMemcpyHostToDevice, s));
+  SLM_HIP(hipMemcpyAsync(w.beg, hb, n_roots * 8, hipMemcpyHostToDevice, s));
+  SLM_HIP(hipMemcpyAsync(w.end, he, n_roots * 8, hipMemcpyHostToDevice, s));
   if ((st = clear_stats(w, n_roots, p.crit, Kc, s))) return st;
   if ((st = launch_node_stats(w.beg, w.end, n_roots, N, mse ? nullptr : (const int32_t *)target,
                               mse ? (const double *)target : nullptr, Kc, w.st, s)))
     return st;
-  StatsHost sh;
   if ((st = read_stats(w, n_roots, p.crit, Kc, sh, s))) return st;
   SLM_HIP(hipStreamSynchronize(s));
 
@@ -1318,8 +1363,6 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
   void *Xbuf[2] = {w.Xa, w.Xb};
   void *tbuf[2] = {w.ta, w.tb};
   int nb = 0;
-  std::vector<double> hgl(F), hgb((size_t)F * D);
-  std::vector<float> hgt(F), hgw((size_t)F * D);
 
   while (!frontier.empty()) {
     std::vector<HNode> active;
@@ -1338,11 +1381,11 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
       if (p.precision == 1)
         ss[1] += (active[j].end - active[j].beg) * (int64_t)p.rescore_k * (p.T + 1);
     }
-    SLM_HIP(hipMemcpyAsync(w.beg, hb.data(), na * 8, hipMemcpyHostToDevice, s));
-    SLM_HIP(hipMemcpyAsync(w.end, he.data(), na * 8, hipMemcpyHostToDevice, s));
-    SLM_HIP(hipMemcpyAsync(w.node_id, hid.data(), na * 4, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(w.beg, hb, na * 8, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(w.end, he, na * 8, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(w.node_id, hid, na * 4, hipMemcpyHostToDevice, s));
     if (w.tree_off)
-      SLM_HIP(hipMemcpyAsync(w.tree_off, htr.data(), na * 4, hipMemcpyHostToDevice, s));
+      SLM_HIP(hipMemcpyAsync(w.tree_off, htr, na * 4, hipMemcpyHostToDevice, s));
     if (want_stats && p.proposal != 1) {
       StatsArgs sa{};
       sa.X = Xc; sa.x_bf16 = p.precision == 1; sa.N = N; sa.D = D;
@@ -1366,9 +1409,9 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
       timing[6] += cnt[0];
       timing[7] += cnt[1];
     }
-    SLM_HIP(hipMemcpyAsync(hgl.data(), w.gbest_loss, na * 8, hipMemcpyDeviceToHost, s));
-    SLM_HIP(hipMemcpyAsync(hgt.data(), w.gbest_thr, na * 4, hipMemcpyDeviceToHost, s));
-    SLM_HIP(hipMemcpyAsync(hgb.data(), w.gbest, (size_t)na * D * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(hgl, w.gbest_loss, na * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(hgt, w.gbest_thr, na * 4, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(hgb, w.gbest, (size_t)na * D * 8, hipMemcpyDeviceToHost, s));
     if (want_stats) {
       hst.resize((size_t)na * KD1);
       hsg.resize((size_t)na * D);
@@ -1395,8 +1438,8 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
     }
     if (nsplit == 0) break;
     if ((st = tm_part.start(timing ? &timing[2] : nullptr, s))) return st;
-    SLM_HIP(hipMemcpyAsync(w.do_split, hsplit.data(), na * 4, hipMemcpyHostToDevice, s));
-    SLM_HIP(hipMemcpyAsync(w.gW, hgw.data(), (size_t)na * D * 4, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(w.do_split, hsplit, na * 4, hipMemcpyHostToDevice, s));
+    SLM_HIP(hipMemcpyAsync(w.gW, hgw, (size_t)na * D * 4, hipMemcpyHostToDevice, s));
     ProjectArgs pr{};
     pr.X = Xc; pr.x_bf16 = p.precision == 1; pr.w_bf16 = 0; pr.N = N; pr.D = D; pr.W = w.gW;
     pr.beg = w.beg; pr.end = w.end;
@@ -1415,7 +1458,7 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
     pa.cnt_left = w.cnt_left; pa.off_left = w.off_left; pa.off_right = w.off_right;
     pa.n_left = w.n_left; pa.child = w.st;
     if ((st = launch_partition(pa, s))) return st;
-    SLM_HIP(hipMemcpyAsync(hnl.data(), w.n_left, na * 8, hipMemcpyDeviceToHost, s));
+    SLM_HIP(hipMemcpyAsync(hnl, w.n_left, na * 8, hipMemcpyDeviceToHost, s));
     if ((st = read_stats(w, 2 * na, p.crit, Kc, sh, s))) return st;
     SLM_HIP(hipStreamSynchronize(s));
     if ((st = tm_part.stop(s))) return st;
@@ -1424,7 +1467,7 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
       if (!hsplit[j]) continue;
       const HNode &a = active[j];
       const int i = a.idx;
-      std::copy(hgw.begin() + (size_t)j * D, hgw.begin() + (size_t)(j + 1) * D,
+      std::copy(hgw + (size_t)j * D, hgw + (size_t)(j + 1) * D,
                 out->w + (size_t)i * D);
       out->thr[i] = hgt[j];
       HNode l, r;
