@@ -1292,20 +1292,37 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
   SLM_HIP(hipMemcpyAsync(w.seed_tree, seed_tree, 16, hipMemcpyHostToDevice, s));
   // pinned host arrays of the per-depth transfers (the previous build's
   // transfers have completed: every build ends with a synchronisation)
+  // The depth's upload (row ranges, heap ids, tree indices) and the swarm's
+  // results (global bests, losses, thresholds) are each one contiguous span
+  // of the workspace; their host images mirror the spans, so each moves in
+  // one copy (the results span only while it is small).
+  char *const up0 = reinterpret_cast<char *>(w.beg);
+  const size_t up_span =
+      (w.tree_off ? reinterpret_cast<char *>(w.tree_off + F) : reinterpret_cast<char *>(w.node_id + F)) -
+      up0;
+  char *const dn0 = reinterpret_cast<char *>(w.gbest);
+  const size_t dn_span = reinterpret_cast<char *>(w.gbest_thr + F) - dn0;
   {
     const size_t F2 = (size_t)2 * F;
-    const size_t need = 3 * pinned_bytes(F, 8) + 3 * pinned_bytes(F, 4) + pinned_bytes(F, 8) +
-                        pinned_bytes(F, 4) + pinned_bytes((size_t)F * D, 8) +
-                        pinned_bytes((size_t)F * D, 4) + pinned_bytes(F2 * Kc, 4) +
-                        pinned_bytes(F2, 4) + 4 * pinned_bytes(F2, 8) + 64;
+    const size_t need = pinned_bytes(up_span, 1) + pinned_bytes(dn_span, 1) + pinned_bytes(F, 8) +
+                        pinned_bytes(F, 4) + pinned_bytes((size_t)F * D, 4) +
+                        pinned_bytes(F2 * Kc, 4) + pinned_bytes(F2, 4) + 4 * pinned_bytes(F2, 8) +
+                        64;
     if ((st = pinned_begin(need))) return st;
   }
-  int64_t *hb = pinned_take<int64_t>(F), *he = pinned_take<int64_t>(F),
-          *hnl = pinned_take<int64_t>(F);
-  int32_t *hid = pinned_take<int32_t>(F), *hsplit = pinned_take<int32_t>(F);
-  uint32_t *htr = pinned_take<uint32_t>(F);
-  double *hgl = pinned_take<double>(F), *hgb = pinned_take<double>((size_t)F * D);
-  float *hgt = pinned_take<float>(F), *hgw = pinned_take<float>((size_t)F * D);
+  char *const hup = pinned_take<char>(up_span), *const hdn = pinned_take<char>(dn_span);
+  int64_t *hb = reinterpret_cast<int64_t *>(hup);
+  int64_t *he = reinterpret_cast<int64_t *>(hup + (reinterpret_cast<char *>(w.end) - up0));
+  int32_t *hid = reinterpret_cast<int32_t *>(hup + (reinterpret_cast<char *>(w.node_id) - up0));
+  uint32_t *htr =
+      w.tree_off ? reinterpret_cast<uint32_t *>(hup + (reinterpret_cast<char *>(w.tree_off) - up0))
+                 : nullptr;
+  double *hgb = reinterpret_cast<double *>(hdn);
+  double *hgl = reinterpret_cast<double *>(hdn + (reinterpret_cast<char *>(w.gbest_loss) - dn0));
+  float *hgt = reinterpret_cast<float *>(hdn + (reinterpret_cast<char *>(w.gbest_thr) - dn0));
+  int64_t *hnl = pinned_take<int64_t>(F);
+  int32_t *hsplit = pinned_take<int32_t>(F);
+  float *hgw = pinned_take<float>((size_t)F * D);
   StatsHost sh;
   sh.counts = pinned_take<uint32_t>((size_t)2 * F * Kc);
   sh.cnt = pinned_take<uint32_t>((size_t)2 * F);
@@ -1376,16 +1393,17 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
       hb[j] = active[j].beg;
       he[j] = active[j].end;
       hid[j] = active[j].heap;
-      htr[j] = active[j].tree;
+      if (htr) htr[j] = active[j].tree;
       ss[0] += (active[j].end - active[j].beg) * (int64_t)p.P * (p.T + 1);
       if (p.precision == 1)
         ss[1] += (active[j].end - active[j].beg) * (int64_t)p.rescore_k * (p.T + 1);
     }
-    SLM_HIP(hipMemcpyAsync(w.beg, hb, na * 8, hipMemcpyHostToDevice, s));
-    SLM_HIP(hipMemcpyAsync(w.end, he, na * 8, hipMemcpyHostToDevice, s));
-    SLM_HIP(hipMemcpyAsync(w.node_id, hid, na * 4, hipMemcpyHostToDevice, s));
-    if (w.tree_off)
-      SLM_HIP(hipMemcpyAsync(w.tree_off, htr, na * 4, hipMemcpyHostToDevice, s));
+    {
+      // one copy: beg, end and node_id (and tree_off) up to entry na
+      char *last = w.tree_off ? reinterpret_cast<char *>(w.tree_off + na)
+                              : reinterpret_cast<char *>(w.node_id + na);
+      SLM_HIP(hipMemcpyAsync(up0, hup, (size_t)(last - up0), hipMemcpyHostToDevice, s));
+    }
     if (want_stats && p.proposal != 1) {
       StatsArgs sa{};
       sa.X = Xc; sa.x_bf16 = p.precision == 1; sa.N = N; sa.D = D;
@@ -1409,9 +1427,14 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
       timing[6] += cnt[0];
       timing[7] += cnt[1];
     }
-    SLM_HIP(hipMemcpyAsync(hgl, w.gbest_loss, na * 8, hipMemcpyDeviceToHost, s));
-    SLM_HIP(hipMemcpyAsync(hgt, w.gbest_thr, na * 4, hipMemcpyDeviceToHost, s));
-    SLM_HIP(hipMemcpyAsync(hgb, w.gbest, (size_t)na * D * 8, hipMemcpyDeviceToHost, s));
+    if (dn_span <= ((size_t)512 << 10)) {
+      const size_t n_dn = reinterpret_cast<char *>(w.gbest_thr + na) - dn0;
+      SLM_HIP(hipMemcpyAsync(hdn, dn0, n_dn, hipMemcpyDeviceToHost, s));
+    } else {
+      SLM_HIP(hipMemcpyAsync(hgl, w.gbest_loss, na * 8, hipMemcpyDeviceToHost, s));
+      SLM_HIP(hipMemcpyAsync(hgt, w.gbest_thr, na * 4, hipMemcpyDeviceToHost, s));
+      SLM_HIP(hipMemcpyAsync(hgb, w.gbest, (size_t)na * D * 8, hipMemcpyDeviceToHost, s));
+    }
     if (want_stats) {
       hst.resize((size_t)na * KD1);
       hsg.resize((size_t)na * D);
