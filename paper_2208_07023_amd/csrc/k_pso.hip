@@ -154,7 +154,8 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
   double bl = __builtin_huge_val();
   int bp = 0x7fffffff;
   const double *gl = a.gloss ? a.gloss : a.loss;
-  const double gold = tid == 0 ? a.gbest_loss[j] : 0.0;   // prefetched with the losses
+  const double *gl_in = a.gbest_loss_in ? a.gbest_loss_in : a.gbest_loss;
+  const double gold = tid == 0 ? gl_in[j] : 0.0;   // prefetched with the losses
   for (int p = tid; p < P; p += BEST_WG) {
     const double l = gl[base + p];
     if (l < bl) {
@@ -193,12 +194,17 @@ __global__ __launch_bounds__(BEST_WG) void k_pso_bests(PsoArgs a) {
       a.gbest_p[j] = ps;
       if (a.gbest_split && a.split) a.gbest_split[j] = a.split[base + ps];
       if (a.gbest_thr && a.thr) a.gbest_thr[j] = a.thr[base + ps];
+    } else if (a.gbest_loss_in) {
+      a.gbest_loss[j] = gold;   // carried over from the input record
     }
   }
   __syncthreads();
   if (s_improved) {
     const int ps = s_pstar;
     for (int d = tid; d < D; d += BEST_WG) a.gbest[(int64_t)j * D + d] = a.x[(base + ps) * D + d];
+  } else if (a.gbest_in) {
+    for (int d = tid; d < D; d += BEST_WG)
+      a.gbest[(int64_t)j * D + d] = a.gbest_in[(int64_t)j * D + d];
   }
   if (a.zmin_reset) {
     for (int p = tid; p < P; p += BEST_WG) {
@@ -514,6 +520,122 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_move(PsoArgs a) {
   }
 }
 
+// Bests and move in one launch (the plain swarm): every work-group of node j
+// finds the node's argmin over the P losses itself (lowest p on ties), so the
+// global best it moves towards is x_in[p*] when that improves on the input
+// record, else the input record; work-group 0 of the node writes the new
+// record to gbest / gbest_loss (other buffers than the ones read), the
+// positions move from x_in to x.  Same arithmetic as k_pso_bests followed by
+// k_pso_move.
+__global__ __launch_bounds__(MOVE_WG) void k_pso_fused(PsoArgs a) {
+  extern __shared__ double buf[];          // [PPB][D]
+  __shared__ double nrm_s[MOVE_WG];
+  __shared__ double red_l[MOVE_WG / 64];
+  __shared__ int red_p[MOVE_WG / 64];
+  const MoveGeom g = move_geom(a.D);
+  const int bpn = (a.P + g.PPB - 1) / g.PPB;
+  const int j = blockIdx.x / bpn, blk = blockIdx.x % bpn;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int pl = tid / g.Dp, dl = tid % g.Dp;
+  const int p = blk * g.PPB + pl;
+  const bool pv = p < a.P;
+  const int D = a.D, dh = (D + 1) / 2, P = a.P;
+  const int64_t base = (int64_t)j * P;
+  // the node's argmin
+  double bl = __builtin_huge_val();
+  int bp = 0x7fffffff;
+  for (int q = tid; q < P; q += MOVE_WG) {
+    const double l = a.loss[base + q];
+    if (l < bl) {
+      bl = l;
+      bp = q;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double l2 = __shfl_xor(bl, o);
+    const int p2 = __shfl_xor(bp, o);
+    if (l2 < bl || (l2 == bl && p2 < bp)) {
+      bl = l2;
+      bp = p2;
+    }
+  }
+  if (lane == 0) {
+    red_l[wv] = bl;
+    red_p[wv] = bp;
+  }
+  const double gold = a.gbest_loss_in[j];
+  lds_barrier();
+  bl = red_l[0];
+  bp = red_p[0];
+#pragma unroll
+  for (int w = 1; w < MOVE_WG / 64; ++w)
+    if (red_l[w] < bl || (red_l[w] == bl && red_p[w] < bp)) {
+      bl = red_l[w];
+      bp = red_p[w];
+    }
+  const bool improved = bp != 0x7fffffff && bl < gold;
+  const double *gsrc = improved ? a.x_in + (base + bp) * D : a.gbest_in + (int64_t)j * D;
+  if (blk == 0) {
+    for (int d = tid; d < D; d += MOVE_WG) a.gbest[(int64_t)j * D + d] = gsrc[d];
+    if (tid == 0) {
+      a.gbest_loss[j] = improved ? bl : gold;
+      if (improved) {
+        a.gbest_p[j] = bp;
+        if (a.gbest_split && a.split) a.gbest_split[j] = a.split[base + bp];
+        if (a.gbest_thr && a.thr) a.gbest_thr[j] = a.thr[base + bp];
+      }
+    }
+  }
+  if (a.zmin_reset && pv && dl == 0) {
+    a.zmin_reset[base + p] = __builtin_huge_valf();
+    a.zmax_reset[base + p] = -__builtin_huge_valf();
+  }
+  uint2 key;
+  uint32_t tree;
+  rng_key(a, j, &key, &tree);
+  const uint32_t node = (uint32_t)a.node_id[j];
+  const int64_t gid = base + p;
+  const double lp = pv ? a.loss[gid] : 0.0;
+  const bool imp = pv && lp < a.pbest_loss[gid];
+  if (pv) {
+    for (int d = dl; d < D; d += g.Dp) {
+      const int64_t e = gid * D + d;
+      const double xv = a.x_in[e];
+      const double pold = a.pbest[e];
+      double pb;
+      if (imp) {
+        a.pbest[e] = xv;
+        pb = xv;
+      } else {
+        pb = pold;
+      }
+      const int m = d >> 1, h = d & 1;
+      const uint4 w = philox4x32_10(make_uint4((uint32_t)(p * dh + m), a.iter, node, tree), key);
+      const double r1 = u24(h ? w.z : w.x);
+      const double r2 = u24(h ? w.w : w.y);
+      const double t0 = a.omega * a.v[e];
+      const double t1 = (a.c1 * r1) * (pb - xv);
+      const double t2 = (a.c2 * r2) * (gsrc[d] - xv);
+      const double vn = (t0 + t1) + t2;
+      a.v[e] = vn;
+      buf[pl * D + d] = xv + vn;
+    }
+  }
+  lds_barrier();
+  if (imp && dl == 0) a.pbest_loss[gid] = lp;
+  if (pv && dl == 0) nrm_s[pl] = sqrt(sq_norm_ordered(buf + pl * D, D));
+  lds_barrier();
+  if (!pv) return;
+  const double nrm = nrm_s[pl];
+  for (int d = dl; d < D; d += g.Dp) {
+    const int64_t e = gid * D + d;
+    const double xv = nrm > 0.0 ? buf[pl * D + d] / nrm : -a.v[e];
+    a.x[e] = xv;
+    store_w(a.W_out, a.w_bf16, e, xv);
+  }
+}
+
 // Candidates of the probabilistic search (Sec. II-B, Eqs. (5)-(8)): particle
 // p of node j combines the node's R first-ranked features (ranks[j R + d],
 // most discriminant first) with integer coefficients.  One Philox4x32-10 call
@@ -586,12 +708,28 @@ __global__ void k_predict(const float *w, const float *thr, const int32_t *left,
 
 void prepare_pso_kernels(int lds_max) {
   const int dyn = lds_max - 4096;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_pso_fused),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess)
+    (void)hipGetLastError();
   if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_pso_move),
                           hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess)
     (void)hipGetLastError();
   if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_pso_init),
                           hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess)
     (void)hipGetLastError();
+}
+
+slm_status launch_pso_fused(const PsoArgs &a, hipStream_t s) {
+  SLM_CHECK(a.D <= DMAX, SLM_E_SHAPE, "pso step: D = %d exceeds %d", a.D, DMAX);
+  SLM_CHECK(a.x_in && a.gbest_in && a.gbest_loss_in && !a.gloss && !a.apso_state && a.move,
+            SLM_E_INVALID, "pso step: fused step needs its input buffers");
+  if (a.n_nodes == 0) return SLM_OK;
+  const MoveGeom g = move_geom(a.D);
+  const int64_t grid = (int64_t)a.n_nodes * ((a.P + g.PPB - 1) / g.PPB);
+  const size_t lds = (size_t)g.PPB * a.D * sizeof(double);
+  hipLaunchKernelGGL(k_pso_fused, dim3((unsigned)grid), dim3(MOVE_WG), lds, s, a);
+  SLM_LAUNCHED();
+  return SLM_OK;
 }
 
 size_t apso_part_bytes(int n_nodes, int P) {

@@ -71,6 +71,8 @@ struct TreeWS {
   // elite candidate, partial distance sums
   int32_t *ap_state, *ap_worst;
   double *ap_par, *ap_dist, *ap_f, *ap_elite, *ap_part;
+  // fused swarm steps: the second position buffer and global-best record
+  double *x2, *gbest2, *gbest_loss2;
   float *thr, *gbest_thr;
   int64_t *beg, *end, *n_left, *off_left, *off_right;
   uint64_t *seed_tree;
@@ -97,6 +99,19 @@ struct TreeWS {
   size_t scan_ws_bytes;
   size_t total;
 };
+
+// The plain swarm's bests and move run as one launch (k_pso_fused) in tree
+// builds; SLM_PSO_FUSED=0 keeps the two launches (timing comparisons).
+bool fused_step_enabled() {
+  static const int on = [] {
+    const char *e = getenv("SLM_PSO_FUSED");
+    return e && e[0] == '0' ? 0 : 1;
+  }();
+  return on != 0;
+}
+bool fused_step_possible(const slm_tree_params &p) {
+  return fused_step_enabled() && p.apso == 0 && p.precision == 0 && p.proposal != 2;
+}
 
 // Workspace of a tree build (search_nodes = 0) or of one node-batch search of
 // search_nodes nodes (no partition buffers).  stats: node statistics wanted.
@@ -137,6 +152,11 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base, int sea
   w.end = c.take<int64_t>((size_t)F);
   w.node_id = c.take<int32_t>((size_t)F);
   if (n_roots > 1) w.tree_off = c.take<uint32_t>((size_t)F);
+  if (!search && fused_step_possible(p)) {
+    w.x2 = c.take<double>((size_t)F * p.P * D);
+    w.gbest2 = c.take<double>((size_t)F * D);
+    w.gbest_loss2 = c.take<double>((size_t)F);
+  }
   if (p.apso) {
     w.ap_state = c.take<int32_t>((size_t)F);
     w.ap_worst = c.take<int32_t>((size_t)F);
@@ -589,6 +609,8 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   const bool fused = !scr && fz && fz[0] == '1' && fused_eligible(sa, D, false, false);
   ProjectArgs pmm = pr;
   pmm.Z = nullptr;
+  // bests and move in one launch (plain swarm in a tree build)
+  const bool fused_steps = w.x2 != nullptr && !sc && !psearch && !scr && !p.apso;
   for (int t = 0; t <= p.T; ++t) {
     if (psearch &&
         (st = launch_ps_candidates(pa, w.dft_sel, p.ps_R, p.ps_pd, p.ps_amax, (uint32_t)t, s)))
@@ -624,7 +646,34 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
     pa.bests_only = t == p.T || psearch;
     pa.iter = (uint32_t)(t + 1);
     if (lt && (st = lt->begin(2, s))) return st;
-    if ((st = launch_pso_step(pa, s))) return st;
+    if (fused_steps) {
+      // ping-pong: step t reads buffer t % 2 and writes the other; the last
+      // (bests-only) step writes the primary record
+      double *X[2] = {w.x, w.x2}, *G[2] = {w.gbest, w.gbest2}, *L[2] = {w.gbest_loss, w.gbest_loss2};
+      const int cur = t & 1;
+      PsoArgs pf = pa;
+      pf.x_in = X[cur];
+      pf.gbest_in = G[cur];
+      pf.gbest_loss_in = L[cur];
+      if (t < p.T) {
+        pf.x = X[cur ^ 1];
+        pf.gbest = G[cur ^ 1];
+        pf.gbest_loss = L[cur ^ 1];
+        st = launch_pso_fused(pf, s);
+      } else {
+        pf.x = X[cur];
+        pf.gbest = w.gbest;
+        pf.gbest_loss = w.gbest_loss;
+        if (cur == 0) {
+          pf.gbest_in = nullptr;
+          pf.gbest_loss_in = nullptr;
+        }
+        st = launch_pso_step(pf, s);
+      }
+      if (st) return st;
+    } else if ((st = launch_pso_step(pa, s))) {
+      return st;
+    }
     if (lt && (st = lt->end(s))) return st;
     if (sc) {
       if ((st = launch_search_stop(w.gbest_loss, sc->target, w.beg, w.end_act, w.done, sc->evals,
@@ -656,7 +705,7 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)(p.proposal == 2 ? p.ps_R : 0),
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_pd : nullptr),
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_amax : nullptr),
-           (uint64_t)(uintptr_t)w.tree_off, (uint64_t)p.apso};
+           (uint64_t)(uintptr_t)w.tree_off, (uint64_t)p.apso, (uint64_t)(uintptr_t)w.x2};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);

@@ -248,7 +248,16 @@ struct PsoArgs {
   // top DFT channels); the elite step perturbs one of them
   const int32_t *apso_sel;
   int apso_n_sel;
+  // fused step (bests and move in one launch): positions and the global-best
+  // record are read from these buffers and written to x / gbest / gbest_loss
+  // (ping-pong; the other work-groups of a node still read the old record).
+  // Also, for a bests-only step, the record to compare with and to carry
+  // over when not improved.
+  const double *x_in, *gbest_in, *gbest_loss_in;
 };
+// bests and move in one launch (plain swarm, no screening): every work-group
+// finds its node's argmin itself; the record and positions ping-pong
+slm_status launch_pso_fused(const PsoArgs &a, hipStream_t s);
 // bytes of apso_part for n_nodes swarms of P particles
 size_t apso_part_bytes(int n_nodes, int P);
 slm_status launch_pso_init(const PsoArgs &a, hipStream_t s);

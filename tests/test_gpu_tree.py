@@ -129,3 +129,34 @@ def test_predict_routes_like_the_float32_rule(gpu_lib):
         nxt = np.where(z >= g["thr"][node], g["right"][node], g["left"][node])
         node = np.where(internal, nxt, node)
     assert np.array_equal(leaves, node)
+
+
+def test_fused_swarm_steps_build_the_same_tree(gpu_lib, tmp_path):
+    """The one-launch swarm step (bests and move fused, positions and global
+    best ping-ponged) builds exactly the tree of the two-launch step, for an
+    odd and an even number of moves."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np, torch, sys\n"
+        "from paper_2208_07023_amd import api, inputs\n"
+        "X, y = inputs.cluster_mixture(6000, 12, 3, seed=4)\n"
+        "out = []\n"
+        "for T in (5, 6):\n"
+        "    cfg = api.TreeConfig(crit=api.ENTROPY, K=3, max_depth=4, min_node=16, P=64, T=T, bins=64, seed=1)\n"
+        "    tr = api.grow_tree(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), cfg)\n"
+        "    out += [tr[k] for k in ('w', 'thr', 'left', 'right', 'split_loss')]\n"
+        "np.savez(sys.argv[1], *out)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = []
+    for flag in ("1", "0"):
+        path = str(tmp_path / f"fused_steps_{flag}.npz")
+        env = dict(os.environ, SLM_PSO_FUSED=flag)
+        subprocess.run([sys.executable, "-c", code, path], env=env, cwd=root, check=True,
+                       timeout=240)
+        res.append(np.load(path))
+    a, b = res
+    assert len(a.files) == len(b.files) == 10
+    for k in a.files:
+        assert np.array_equal(a[k], b[k]), k
