@@ -463,9 +463,16 @@ slm_status launch_short(const ProjectArgs &a, hipStream_t s) {
   // wave keeps its SIMD's matrix core busy on its own, and longer runs
   // amortise its prologue); each work-group takes a contiguous run of whole
   // 32-row sub-tiles (SLM_PROJ_RT overrides the run length).
+  //
+  // The run length comes from the rows inside the nodes (a.rows, when known):
+  // work-groups still cover [0, N) in runs of RB rows, and those whose run
+  // holds no node row return at once, so a depth whose nodes hold a small
+  // part of the rows (the last levels of trees grown together) spreads those
+  // rows over the whole chip instead of over the few runs they fall in.
+  const int64_t NA = a.rows > 0 && a.rows < a.N ? a.rows : a.N;
   const int64_t cap = std::max<int64_t>(1, (int64_t)num_cus_proj() * 4 / WAVES);
-  int64_t bpp = std::max<int64_t>(1, std::min<int64_t>((a.N + SR - 1) / SR, cap / n_pt));
-  int64_t RB = ((a.N + bpp - 1) / bpp + SR - 1) / SR * SR;
+  int64_t bpp = std::max<int64_t>(1, std::min<int64_t>((NA + SR - 1) / SR, cap / n_pt));
+  int64_t RB = ((NA + bpp - 1) / bpp + SR - 1) / SR * SR;
   bpp = (a.N + RB - 1) / RB;
   if (const char *env = getenv("SLM_PROJ_RT")) {
     const long long v = atoll(env);

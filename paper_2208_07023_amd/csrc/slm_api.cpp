@@ -522,7 +522,8 @@ static slm_status learned_start(const slm_tree_params &p, const TreeWS &w, const
 
 // swarm loop of one depth: T+1 evaluations (project, scan, step)
 static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const void *Xc,
-                             const void *tc, int64_t N, int32_t D, int na, hipStream_t s,
+                             const void *tc, int64_t N, int32_t D, int na, int64_t rows,
+                             hipStream_t s,
                              LaunchTimes *lt = nullptr, const SearchCtl *sc = nullptr) {
   const bool mse = p.crit == SLM_MSE;
   PsoArgs pa{};
@@ -579,6 +580,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pr.end = ends;
   pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
   pr.zl = zlayout_of(1, N, p.P);
+  pr.rows = rows;
   ScanArgs sa{};
   sa.Z = w.Z; sa.zl = pr.zl; sa.zmin = w.zmin; sa.zmax = w.zmax;
   sa.labels = mse ? nullptr : static_cast<const int32_t *>(tc);
@@ -690,7 +692,8 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
 }
 
 static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, const void *Xc,
-                                   const void *tc, int64_t N, int32_t D, int na, hipStream_t s) {
+                                   const void *tc, int64_t N, int32_t D, int na, int64_t rows,
+                                   hipStream_t s) {
   GraphKey key;
   key.k = {(uint64_t)(uintptr_t)Xc, (uint64_t)(uintptr_t)tc, (uint64_t)(uintptr_t)w.Z,
            (uint64_t)N, (uint64_t)D, (uint64_t)na, (uint64_t)p.P, (uint64_t)p.T,
@@ -705,7 +708,8 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)(p.proposal == 2 ? p.ps_R : 0),
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_pd : nullptr),
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_amax : nullptr),
-           (uint64_t)(uintptr_t)w.tree_off, (uint64_t)p.apso, (uint64_t)(uintptr_t)w.x2};
+           (uint64_t)(uintptr_t)w.tree_off, (uint64_t)p.apso, (uint64_t)(uintptr_t)w.x2,
+           (uint64_t)rows};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -726,7 +730,7 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
     if (!cs) SLM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     SLM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     set_capturing(true);
-    slm_status st = swarm_loop(p, w, Xc, tc, N, D, na, cs);
+    slm_status st = swarm_loop(p, w, Xc, tc, N, D, na, rows, cs);
     set_capturing(false);
     hipGraph_t gcap = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &gcap);
@@ -1163,7 +1167,7 @@ slm_status slm_search_nodes(const void *X, int32_t x_dtype, int64_t N, int32_t D
   SLM_HIP(hipMemsetAsync(w.done, 0, (size_t)n_nodes * 4, s));
   uint32_t h_remaining = 0;
   const SearchCtl sc{target_loss, evals, &h_remaining};
-  if ((st = swarm_loop(p, w, X, target, N, D, n_nodes, s, nullptr, &sc))) return st;
+  if ((st = swarm_loop(p, w, X, target, N, D, n_nodes, 0, s, nullptr, &sc))) return st;
   SLM_HIP(hipMemcpyAsync(gbest, w.gbest, (size_t)n_nodes * D * 8, hipMemcpyDeviceToDevice, s));
   SLM_HIP(hipMemcpyAsync(gbest_loss, w.gbest_loss, (size_t)n_nodes * 8, hipMemcpyDeviceToDevice, s));
   SLM_HIP(hipMemcpyAsync(gbest_split, w.gbest_split, (size_t)n_nodes * 4, hipMemcpyDeviceToDevice,
@@ -1438,7 +1442,9 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
     const int na = (int)active.size();
     SLM_CHECK(na <= F, SLM_E_SHAPE, "grow: frontier of %d nodes exceeds %lld", na,
               (long long)F);
+    int64_t rows = 0;   // rows inside the depth's nodes
     for (int j = 0; j < na; ++j) {
+      rows += active[j].end - active[j].beg;
       hb[j] = active[j].beg;
       he[j] = active[j].end;
       hid[j] = active[j].heap;
@@ -1446,6 +1452,14 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
       ss[0] += (active[j].end - active[j].beg) * (int64_t)p.P * (p.T + 1);
       if (p.precision == 1)
         ss[1] += (active[j].end - active[j].beg) * (int64_t)p.rescore_k * (p.T + 1);
+    }
+    // The projection's launch is sized by the depth's rows, rounded up to
+    // N / 2^k: captured swarm loops are keyed by it, and the rounding keeps
+    // trees of one shape on the same few graphs.
+    {
+      int k = 0;
+      while (k < 20 && (N >> (k + 1)) >= rows) ++k;
+      rows = N >> k;
     }
     {
       // one copy: beg, end and node_id (and tree_off) up to entry na
@@ -1463,10 +1477,10 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
     }
     if ((st = tm_swarm.start(timing ? &timing[1] : nullptr, s))) return st;
     if (prof)
-      st = swarm_loop(p, w, Xc, tc, N, D, na, s, &lt);
+      st = swarm_loop(p, w, Xc, tc, N, D, na, rows, s, &lt);
     else
-      st = p.use_graph ? swarm_loop_graph(p, w, Xc, tc, N, D, na, s)
-                       : swarm_loop(p, w, Xc, tc, N, D, na, s);
+      st = p.use_graph ? swarm_loop_graph(p, w, Xc, tc, N, D, na, rows, s)
+                       : swarm_loop(p, w, Xc, tc, N, D, na, rows, s);
     if (st) return st;
     if ((st = tm_swarm.stop(s))) return st;
     if (prof) {

@@ -170,6 +170,8 @@ struct ProjectArgs {
   float *Z;
   float *zmin, *zmax;
   ZLayout zl;
+  int64_t rows;      // rows inside the nodes' ranges when the caller knows it
+                     // (sizes the launch; 0: N)
 };
 slm_status launch_project(const ProjectArgs &a, hipStream_t s);
 slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s);
