@@ -176,8 +176,26 @@ struct SubTile {
 };
 
 // First sub-tile of rows >= r inside [.., r_end), starting the search at node j.
+// With a.vpre, r and r_end count the nodes' rows alone (node j's rows are
+// vpre[j] .. vpre[j+1]-1 of that count) and the sub-tile is in data rows.
 __device__ __forceinline__ SubTile next_subtile(const ProjectArgs &a, int j, int64_t r,
                                                 int64_t r_end) {
+  if (a.vpre) {
+    for (; j < a.n_nodes; ++j) {
+      const int64_t v0 = a.vpre[j], v1 = a.vpre[j + 1];
+      if (v0 >= r_end) break;
+      const int64_t vl = r > v0 ? r : v0;
+      if (vl < v1) {
+        const Range nr = load_range(a.beg, a.end, j, a.N);
+        const int64_t lo = nr.lo + (vl - v0);
+        int64_t hi = nr.lo + ((v1 < r_end ? v1 : r_end) - v0);
+        hi = hi < nr.hi ? hi : nr.hi;
+        if (lo >= hi) continue;
+        return {j, lo, hi < lo + SR ? hi : lo + SR, hi};
+      }
+    }
+    return {-1, 0, 0, 0};
+  }
   for (; j < a.n_nodes; ++j) {
     const Range nr = load_range(a.beg, a.end, j, a.N);
     const int64_t lo = r > nr.lo ? r : nr.lo;
@@ -247,9 +265,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
                                                               int blocks_per_pt) {
   constexpr int PTILE = 32 * FN * WAVES;
   const int pt = blockIdx.x / blocks_per_pt;
+  if (a.n_nodes <= 0) return;
+  // rows of the run: data rows, or (a.vpre) rows of the nodes alone, whose
+  // count is read here so that a captured launch serves any node sizes
+  const int64_t n_rows = a.vpre ? a.vpre[a.n_nodes] : a.N;
+  if (a.vpre) RB = ((n_rows + blocks_per_pt - 1) / blocks_per_pt + SR - 1) / SR * SR;
   const int64_t r_begin = (int64_t)(blockIdx.x % blocks_per_pt) * RB;
-  const int64_t r_end = r_begin + RB < a.N ? r_begin + RB : a.N;
-  if (r_begin >= r_end || a.n_nodes <= 0) return;
+  const int64_t r_end = r_begin + RB < n_rows ? r_begin + RB : n_rows;
+  if (r_begin >= r_end) return;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int D = a.D, P = a.P;
   const int li = lane & 31, kh = lane >> 5, k0 = kh * KSP;
@@ -264,7 +287,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
     int lo = 0, hi = a.n_nodes;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (load_range(a.beg, a.end, mid, a.N).hi <= r_begin) lo = mid + 1; else hi = mid;
+      const int64_t e = a.vpre ? a.vpre[mid + 1] : load_range(a.beg, a.end, mid, a.N).hi;
+      if (e <= r_begin) lo = mid + 1; else hi = mid;
     }
     j0 = lo;
   }
@@ -390,7 +414,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
   // previous sub-tile's stores (the vector memory counter counts both, in
   // order) -- then its ragged last sub-tile.
   float A0[KSP], A1[KSP];
-  for (SubTile c = cur; c.j >= 0; c = next_subtile(a, c.j + 1, c.end, r_end)) {
+  // (the next node's rows all lie past r_begin, in either count)
+  for (SubTile c = cur; c.j >= 0; c = next_subtile(a, c.j + 1, r_begin, r_end)) {
     const int64_t end = c.end;
     const int64_t nfull = wave_full ? (end - c.lo) / SR : 0;
     int64_t r = c.lo;
@@ -464,17 +489,14 @@ slm_status launch_short(const ProjectArgs &a, hipStream_t s) {
   // amortise its prologue); each work-group takes a contiguous run of whole
   // 32-row sub-tiles (SLM_PROJ_RT overrides the run length).
   //
-  // The run length comes from the rows inside the nodes (a.rows, when known):
-  // work-groups still cover [0, N) in runs of RB rows, and those whose run
-  // holds no node row return at once, so a depth whose nodes hold a small
-  // part of the rows (the last levels of trees grown together) spreads those
-  // rows over the whole chip instead of over the few runs they fall in.
-  const int64_t NA = a.rows > 0 && a.rows < a.N ? a.rows : a.N;
+  // With a.vpre the runs split the nodes' rows alone (the kernel reads their
+  // count), so a depth whose nodes hold a small part of the data (the last
+  // levels of trees grown together) still spreads over the whole chip.
   const int64_t cap = std::max<int64_t>(1, (int64_t)num_cus_proj() * 4 / WAVES);
-  int64_t bpp = std::max<int64_t>(1, std::min<int64_t>((NA + SR - 1) / SR, cap / n_pt));
-  int64_t RB = ((NA + bpp - 1) / bpp + SR - 1) / SR * SR;
-  bpp = (a.N + RB - 1) / RB;
-  if (const char *env = getenv("SLM_PROJ_RT")) {
+  int64_t bpp = std::max<int64_t>(1, std::min<int64_t>((a.N + SR - 1) / SR, cap / n_pt));
+  int64_t RB = ((a.N + bpp - 1) / bpp + SR - 1) / SR * SR;
+  if (!a.vpre) bpp = (a.N + RB - 1) / RB;
+  if (const char *env = a.vpre ? nullptr : getenv("SLM_PROJ_RT")) {
     const long long v = atoll(env);
     if (v >= 1 && v <= (1 << 24)) {
       RB = v;

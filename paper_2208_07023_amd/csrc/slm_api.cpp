@@ -67,6 +67,7 @@ struct TreeWS {
   void *W, *gW;
   int32_t *split, *gbest_p, *gbest_split, *node_id, *do_split;
   uint32_t *tree_off;   // tree of every searched node (several roots)
+  int64_t *vpre;        // rows of the searched nodes before each one (F + 1)
   // adaptive swarm: per-node state, parameters, distances, worst particle,
   // elite candidate, partial distance sums
   int32_t *ap_state, *ap_worst;
@@ -152,6 +153,7 @@ TreeWS carve(const slm_tree_params &p, int64_t N, int32_t D, void *base, int sea
   w.end = c.take<int64_t>((size_t)F);
   w.node_id = c.take<int32_t>((size_t)F);
   if (n_roots > 1) w.tree_off = c.take<uint32_t>((size_t)F);
+  w.vpre = c.take<int64_t>((size_t)F + 1);
   if (!search && fused_step_possible(p)) {
     w.x2 = c.take<double>((size_t)F * p.P * D);
     w.gbest2 = c.take<double>((size_t)F * D);
@@ -522,7 +524,7 @@ static slm_status learned_start(const slm_tree_params &p, const TreeWS &w, const
 
 // swarm loop of one depth: T+1 evaluations (project, scan, step)
 static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const void *Xc,
-                             const void *tc, int64_t N, int32_t D, int na, int64_t rows,
+                             const void *tc, int64_t N, int32_t D, int na, bool vrows,
                              hipStream_t s,
                              LaunchTimes *lt = nullptr, const SearchCtl *sc = nullptr) {
   const bool mse = p.crit == SLM_MSE;
@@ -580,7 +582,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pr.end = ends;
   pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
   pr.zl = zlayout_of(1, N, p.P);
-  pr.rows = rows;
+  pr.vpre = vrows ? w.vpre : nullptr;
   ScanArgs sa{};
   sa.Z = w.Z; sa.zl = pr.zl; sa.zmin = w.zmin; sa.zmax = w.zmax;
   sa.labels = mse ? nullptr : static_cast<const int32_t *>(tc);
@@ -692,7 +694,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
 }
 
 static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, const void *Xc,
-                                   const void *tc, int64_t N, int32_t D, int na, int64_t rows,
+                                   const void *tc, int64_t N, int32_t D, int na, bool vrows,
                                    hipStream_t s) {
   GraphKey key;
   key.k = {(uint64_t)(uintptr_t)Xc, (uint64_t)(uintptr_t)tc, (uint64_t)(uintptr_t)w.Z,
@@ -709,7 +711,7 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_pd : nullptr),
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_amax : nullptr),
            (uint64_t)(uintptr_t)w.tree_off, (uint64_t)p.apso, (uint64_t)(uintptr_t)w.x2,
-           (uint64_t)rows};
+           (uint64_t)vrows};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -730,7 +732,7 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
     if (!cs) SLM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     SLM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     set_capturing(true);
-    slm_status st = swarm_loop(p, w, Xc, tc, N, D, na, rows, cs);
+    slm_status st = swarm_loop(p, w, Xc, tc, N, D, na, vrows, cs);
     set_capturing(false);
     hipGraph_t gcap = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &gcap);
@@ -1167,7 +1169,7 @@ slm_status slm_search_nodes(const void *X, int32_t x_dtype, int64_t N, int32_t D
   SLM_HIP(hipMemsetAsync(w.done, 0, (size_t)n_nodes * 4, s));
   uint32_t h_remaining = 0;
   const SearchCtl sc{target_loss, evals, &h_remaining};
-  if ((st = swarm_loop(p, w, X, target, N, D, n_nodes, 0, s, nullptr, &sc))) return st;
+  if ((st = swarm_loop(p, w, X, target, N, D, n_nodes, false, s, nullptr, &sc))) return st;
   SLM_HIP(hipMemcpyAsync(gbest, w.gbest, (size_t)n_nodes * D * 8, hipMemcpyDeviceToDevice, s));
   SLM_HIP(hipMemcpyAsync(gbest_loss, w.gbest_loss, (size_t)n_nodes * 8, hipMemcpyDeviceToDevice, s));
   SLM_HIP(hipMemcpyAsync(gbest_split, w.gbest_split, (size_t)n_nodes * 4, hipMemcpyDeviceToDevice,
@@ -1350,9 +1352,7 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
   // of the workspace; their host images mirror the spans, so each moves in
   // one copy (the results span only while it is small).
   char *const up0 = reinterpret_cast<char *>(w.beg);
-  const size_t up_span =
-      (w.tree_off ? reinterpret_cast<char *>(w.tree_off + F) : reinterpret_cast<char *>(w.node_id + F)) -
-      up0;
+  const size_t up_span = reinterpret_cast<char *>(w.vpre + F + 1) - up0;
   char *const dn0 = reinterpret_cast<char *>(w.gbest);
   const size_t dn_span = reinterpret_cast<char *>(w.gbest_thr + F) - dn0;
   {
@@ -1370,6 +1370,7 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
   uint32_t *htr =
       w.tree_off ? reinterpret_cast<uint32_t *>(hup + (reinterpret_cast<char *>(w.tree_off) - up0))
                  : nullptr;
+  int64_t *hvp = reinterpret_cast<int64_t *>(hup + (reinterpret_cast<char *>(w.vpre) - up0));
   double *hgb = reinterpret_cast<double *>(hdn);
   double *hgl = reinterpret_cast<double *>(hdn + (reinterpret_cast<char *>(w.gbest_loss) - dn0));
   float *hgt = reinterpret_cast<float *>(hdn + (reinterpret_cast<char *>(w.gbest_thr) - dn0));
@@ -1442,9 +1443,9 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
     const int na = (int)active.size();
     SLM_CHECK(na <= F, SLM_E_SHAPE, "grow: frontier of %d nodes exceeds %lld", na,
               (long long)F);
-    int64_t rows = 0;   // rows inside the depth's nodes
+    hvp[0] = 0;
     for (int j = 0; j < na; ++j) {
-      rows += active[j].end - active[j].beg;
+      hvp[j + 1] = hvp[j] + (active[j].end - active[j].beg);
       hb[j] = active[j].beg;
       he[j] = active[j].end;
       hid[j] = active[j].heap;
@@ -1453,18 +1454,10 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
       if (p.precision == 1)
         ss[1] += (active[j].end - active[j].beg) * (int64_t)p.rescore_k * (p.T + 1);
     }
-    // The projection's launch is sized by the depth's rows, rounded up to
-    // N / 2^k: captured swarm loops are keyed by it, and the rounding keeps
-    // trees of one shape on the same few graphs.
     {
-      int k = 0;
-      while (k < 20 && (N >> (k + 1)) >= rows) ++k;
-      rows = N >> k;
-    }
-    {
-      // one copy: beg, end and node_id (and tree_off) up to entry na
-      char *last = w.tree_off ? reinterpret_cast<char *>(w.tree_off + na)
-                              : reinterpret_cast<char *>(w.node_id + na);
+      // one copy: beg, end, node_id (and tree_off) up to entry na, and the
+      // row prefix up to entry na + 1
+      char *last = reinterpret_cast<char *>(w.vpre + na + 1);
       SLM_HIP(hipMemcpyAsync(up0, hup, (size_t)(last - up0), hipMemcpyHostToDevice, s));
     }
     if (want_stats && p.proposal != 1) {
@@ -1477,10 +1470,10 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
     }
     if ((st = tm_swarm.start(timing ? &timing[1] : nullptr, s))) return st;
     if (prof)
-      st = swarm_loop(p, w, Xc, tc, N, D, na, rows, s, &lt);
+      st = swarm_loop(p, w, Xc, tc, N, D, na, true, s, &lt);
     else
-      st = p.use_graph ? swarm_loop_graph(p, w, Xc, tc, N, D, na, rows, s)
-                       : swarm_loop(p, w, Xc, tc, N, D, na, rows, s);
+      st = p.use_graph ? swarm_loop_graph(p, w, Xc, tc, N, D, na, true, s)
+                       : swarm_loop(p, w, Xc, tc, N, D, na, true, s);
     if (st) return st;
     if ((st = tm_swarm.stop(s))) return st;
     if (prof) {

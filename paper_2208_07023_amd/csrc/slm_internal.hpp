@@ -170,8 +170,10 @@ struct ProjectArgs {
   float *Z;
   float *zmin, *zmax;
   ZLayout zl;
-  int64_t rows;      // rows inside the nodes' ranges when the caller knows it
-                     // (sizes the launch; 0: N)
+  // Optional: vpre[j] = rows of nodes 0 .. j-1 (n_nodes + 1 entries, on the
+  // device).  Work is then split over the nodes' rows alone, as if they
+  // were contiguous, instead of over [0, N).
+  const int64_t *vpre;
 };
 slm_status launch_project(const ProjectArgs &a, hipStream_t s);
 slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s);
