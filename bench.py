@@ -46,8 +46,8 @@ TRAFFIC = {
                            "sha256": "1b66fdfd18c96549233842d08856923bcf5bf75ef27492a5cc3618364facb26a",
                            "fetch_kib": 3178.0, "write_kib": 3096.0},
     "k_project": {"source": "paper_2208_07023_amd/csrc/k_project.hip",
-                  "sha256": "d7ce5b1df898b676221c8248f9417a4736e5f4fbf0e89cc6f5a2f29ab775a325",
-                  "fetch_kib": 10777.5, "write_kib": 83735.5},
+                  "sha256": "e27b8abdd5cb1cd0f31e799308bbb86a24ab450dfe1c5fcaa61baee64f9fe512",
+                  "fetch_kib": 10796.9, "write_kib": 83806.5},
 }
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.3, 1.0
 
