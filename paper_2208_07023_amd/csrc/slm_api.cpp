@@ -452,7 +452,11 @@ std::map<GraphKey, hipGraphExec_t> g_graphs;
 }  // namespace
 
 // Optional per-launch timing: event pairs recorded around launches on the
-// launch stream, read after the depth's synchronisation.
+// launch stream, read after the depth's synchronisation.  The events skip the
+// system-scope fence a recorded event otherwise issues (a write-back of the
+// dirty L2 lines, e.g. of the Z a projection has just written): they order
+// nothing, the stream synchronisation does, and the fence would add several
+// microseconds to every measured span.
 struct LaunchTimes {
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, size_t>> marks;   // (kind, index of the start event)
@@ -460,7 +464,7 @@ struct LaunchTimes {
   hipEvent_t next() {
     if (used == pool.size()) {
       hipEvent_t e = nullptr;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
       pool.push_back(e);
     }
     return pool[used++];
