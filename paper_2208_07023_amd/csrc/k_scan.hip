@@ -649,6 +649,17 @@ __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &
 
 // ---------------------------------------------------------------- histogram kernel
 // Two 512-thread work-groups per CU: at most 128 VGPRs per thread.
+// Row coordinates of the histogram's work items and slots: data rows, or
+// (a.vpre) the rows of the nodes alone, node j holding vpre[j] .. vpre[j+1]-1.
+struct Coords {
+  const int64_t *beg, *end;
+  int64_t N;
+};
+__device__ __forceinline__ Coords coords_of(const ScanArgs &a) {
+  if (a.vpre) return {a.vpre, a.vpre + 1, a.vpre[a.n_nodes]};
+  return {a.beg, a.end, a.N};
+}
+
 template <int PT, int KT, bool MSE>
 __global__ __launch_bounds__(HIST_WG) __attribute__((amdgpu_waves_per_eu(4)))
 void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, size_t slot_sz,
@@ -674,8 +685,17 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   if (L >= total_blocks) return;
   const int64_t v = L / n_pt;
   const int pt = (int)(L % n_pt);
-  const Item it = find_item(a.beg, a.end, a.n_nodes, a.N, CH, v);
+  const Coords co = coords_of(a);
+  Item it = find_item(co.beg, co.end, a.n_nodes, co.N, CH, v);
   if (it.node < 0) return;
+  if (a.vpre) {   // back to data rows
+    const Range nr = load_range(a.beg, a.end, it.node, a.N);
+    const int64_t off = nr.lo - co.beg[it.node];
+    it.lo += off;
+    it.hi += off;
+    if (it.hi > nr.hi) it.hi = nr.hi;
+    if (it.lo >= it.hi) return;   // cannot happen with vpre matching the ranges
+  }
 
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int i = tid; i < hl.nwords; i += WGS) hc[i] = 0u;
@@ -794,7 +814,7 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   // ---- a node spanning several chunks: add into its accumulator slot (the
   // node's first chunk index); k_scan_finish completes it
   if (it.nchunks > 1) {
-    const Range nr = load_range(a.beg, a.end, it.node, a.N);
+    const Range nr = load_range(co.beg, co.end, it.node, co.N);
     const int64_t slot = nr.lo / CH;
     if (slot >= n_slots) return;   // cannot happen with a workspace sized by the plan
     // replica it.chunk % R of the slot: fewer atomics on each address
@@ -847,17 +867,19 @@ __global__ __launch_bounds__(256) void k_scan_finish(ScanArgs a, int64_t CH, int
   if (slot >= n_slots) return;
   // the node whose rows start in chunk `slot` and continue past it
   const int64_t lim = (slot + 1) * CH;
+  if (a.n_nodes <= 0) return;
+  const Coords co = coords_of(a);
   auto beg_of = [&](int j) {
-    const int64_t x = a.beg[j];
-    return x < 0 ? (int64_t)0 : (x > a.N ? a.N : x);
+    const int64_t x = co.beg[j];
+    return x < 0 ? (int64_t)0 : (x > co.N ? co.N : x);
   };
-  if (a.n_nodes <= 0 || beg_of(0) >= lim) return;
+  if (beg_of(0) >= lim) return;
   int lo = 0, hi = a.n_nodes - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (beg_of(mid) < lim) lo = mid; else hi = mid - 1;
   }
-  const Range r = load_range(a.beg, a.end, lo, a.N);
+  const Range r = load_range(co.beg, co.end, lo, co.N);
   if (r.hi <= r.lo || r.lo / CH != slot || (r.hi - 1) / CH == slot) return;
   const int B = a.bins;
   const int K = MSE ? 1 : a.K;
@@ -900,17 +922,19 @@ __global__ __launch_bounds__(256) void k_scan_finish_bins(ScanArgs a, int PT, in
   if (slot >= n_slots || pt * PT + qt >= a.P) return;
   // the node whose rows start in chunk `slot` and continue past it
   const int64_t lim = (slot + 1) * CH;
+  if (a.n_nodes <= 0) return;
+  const Coords co = coords_of(a);
   auto beg_of = [&](int j) {
-    const int64_t x = a.beg[j];
-    return x < 0 ? (int64_t)0 : (x > a.N ? a.N : x);
+    const int64_t x = co.beg[j];
+    return x < 0 ? (int64_t)0 : (x > co.N ? co.N : x);
   };
-  if (a.n_nodes <= 0 || beg_of(0) >= lim) return;
+  if (beg_of(0) >= lim) return;
   int lo = 0, hi = a.n_nodes - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (beg_of(mid) < lim) lo = mid; else hi = mid - 1;
   }
-  const Range r = load_range(a.beg, a.end, lo, a.N);
+  const Range r = load_range(co.beg, co.end, lo, co.N);
   if (r.hi <= r.lo || r.lo / CH != slot || (r.hi - 1) / CH == slot) return;
   const int B = a.bins, K = a.K, SB = K * PT;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1107,8 +1131,17 @@ void k_fused_hist(ScanArgs a, const float *X, const float *W, int D, int64_t CH,
   const int64_t v = (local / n_pt) * 8 + (bid & 7);
   const int pt = (int)(local % n_pt);
   if (v >= n_items) return;
-  const Item it = find_item(a.beg, a.end, a.n_nodes, a.N, CH, v);
+  const Coords co = coords_of(a);
+  Item it = find_item(co.beg, co.end, a.n_nodes, co.N, CH, v);
   if (it.node < 0) return;
+  if (a.vpre) {   // back to data rows
+    const Range nr = load_range(a.beg, a.end, it.node, a.N);
+    const int64_t off = nr.lo - co.beg[it.node];
+    it.lo += off;
+    it.hi += off;
+    if (it.hi > nr.hi) it.hi = nr.hi;
+    if (it.lo >= it.hi) return;   // cannot happen with vpre matching the ranges
+  }
 
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int i = tid; i < hl.nwords; i += WGS) hc[i] = 0u;
@@ -1169,7 +1202,7 @@ void k_fused_hist(ScanArgs a, const float *X, const float *W, int D, int64_t CH,
 
   // ---- a node spanning several chunks: add into its accumulator slot
   if (it.nchunks > 1) {
-    const Range nr = load_range(a.beg, a.end, it.node, a.N);
+    const Range nr = load_range(co.beg, co.end, it.node, co.N);
     const int64_t slot = nr.lo / CH;
     if (slot >= n_slots) return;   // cannot happen with a workspace sized by the plan
     unsigned long long *gc = reinterpret_cast<unsigned long long *>(
@@ -1426,7 +1459,8 @@ bool finish_by_bins(const ScanArgs &a, int64_t) {
 template <int PT, int KT, bool MSE>
 slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
   const int n_pt = (a.P + PT - 1) / PT;
-  const int64_t items = num_items(a.n_nodes, a.N, pl.CH);
+  const int64_t NW = a.vpre ? a.rows : a.N;   // extent of the item coordinates
+  const int64_t items = num_items(a.n_nodes, NW, pl.CH);
   const int64_t total = items * n_pt;
   if (total == 0) return SLM_OK;
   const int64_t grid = (total + 8 * pl.G - 1) / (8 * pl.G) * (8 * pl.G);
@@ -1442,8 +1476,8 @@ slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
   hipLaunchKernelGGL((k_scan_hist<PT, KT, MSE>), dim3((unsigned)grid), dim3(HIST_WG), lds, s, a, pl.CH,
                      n_pt, pl.G, total, slot, n_slots, R);
   SLM_LAUNCHED();
-  if (a.N > pl.CH) {   // some node may span several chunks
-    const int64_t used = (a.N - 1) / pl.CH + 1;
+  if (NW > pl.CH) {   // some node may span several chunks
+    const int64_t used = (NW - 1) / pl.CH + 1;
     if (MSE || !finish_by_bins(a, pl.CH)) {
       constexpr int NQ = fin_nq(PT, KT);
       const int64_t grid_f = used * n_pt * (PT / NQ);
@@ -1551,7 +1585,13 @@ slm_status launch_scan_empty_nodes(const ScanArgs &a, hipStream_t s) {
 
 slm_status launch_scan_hist(const ScanArgs &a, hipStream_t s) {
   if (a.N <= 0 || a.n_nodes <= 0) return SLM_OK;
-  const Plan pl = make_plan(a.N, a.n_nodes, a.P, a.bins, a.crit == SLM_MSE ? 1 : a.K, a.crit);
+  SLM_CHECK(!a.vpre || (a.rows >= 1 && a.rows <= a.N), SLM_E_INVALID,
+            "slm_split_scan: row-prefix bound %lld outside [1, N]", (long long)a.rows);
+  // With a row prefix the plan is made for the nodes' rows; its chunks stay
+  // at least chunk_min(rows) long, so the slots, counted for N, still cover
+  // every first chunk.
+  const int64_t NW = a.vpre ? a.rows : a.N;
+  const Plan pl = make_plan(NW, a.n_nodes, a.P, a.bins, a.crit == SLM_MSE ? 1 : a.K, a.crit);
   return launch_hist(a, pl, s);
 }
 

@@ -528,7 +528,7 @@ static slm_status learned_start(const slm_tree_params &p, const TreeWS &w, const
 
 // swarm loop of one depth: T+1 evaluations (project, scan, step)
 static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const void *Xc,
-                             const void *tc, int64_t N, int32_t D, int na, bool vrows,
+                             const void *tc, int64_t N, int32_t D, int na, int64_t vrows,
                              hipStream_t s,
                              LaunchTimes *lt = nullptr, const SearchCtl *sc = nullptr) {
   const bool mse = p.crit == SLM_MSE;
@@ -586,7 +586,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pr.end = ends;
   pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
   pr.zl = zlayout_of(1, N, p.P);
-  pr.vpre = vrows ? w.vpre : nullptr;
+  pr.vpre = vrows > 0 ? w.vpre : nullptr;
   ScanArgs sa{};
   sa.Z = w.Z; sa.zl = pr.zl; sa.zmin = w.zmin; sa.zmax = w.zmax;
   sa.labels = mse ? nullptr : static_cast<const int32_t *>(tc);
@@ -594,6 +594,9 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   sa.K = p.K; sa.N = N; sa.beg = w.beg; sa.end = ends; sa.n_nodes = na; sa.P = p.P;
   sa.bins = p.bins; sa.crit = p.crit; sa.best_split = w.split; sa.best_loss = w.loss;
   sa.threshold = w.thr; sa.ws = w.scan_ws; sa.ws_bytes = w.scan_ws_bytes;
+  // row prefix for the histogram scan (vrows: a bound on the nodes' rows)
+  sa.vpre = vrows > 0 && p.bins ? w.vpre : nullptr;
+  sa.rows = vrows;
   // float32 re-scoring of the screened evaluation's best rescore_k particles
   const int k = p.rescore_k;
   ProjectArgs prr = pr;
@@ -615,6 +618,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   // vs 135 us per evaluation).
   const char *fz = getenv("SLM_FUSED");
   const bool fused = !scr && fz && fz[0] == '1' && fused_eligible(sa, D, false, false);
+  if (fused) sa.vpre = nullptr;   // the fused kernels count data rows
   ProjectArgs pmm = pr;
   pmm.Z = nullptr;
   // bests and move in one launch (plain swarm in a tree build)
@@ -698,7 +702,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
 }
 
 static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, const void *Xc,
-                                   const void *tc, int64_t N, int32_t D, int na, bool vrows,
+                                   const void *tc, int64_t N, int32_t D, int na, int64_t vrows,
                                    hipStream_t s) {
   GraphKey key;
   key.k = {(uint64_t)(uintptr_t)Xc, (uint64_t)(uintptr_t)tc, (uint64_t)(uintptr_t)w.Z,
@@ -1173,7 +1177,7 @@ slm_status slm_search_nodes(const void *X, int32_t x_dtype, int64_t N, int32_t D
   SLM_HIP(hipMemsetAsync(w.done, 0, (size_t)n_nodes * 4, s));
   uint32_t h_remaining = 0;
   const SearchCtl sc{target_loss, evals, &h_remaining};
-  if ((st = swarm_loop(p, w, X, target, N, D, n_nodes, false, s, nullptr, &sc))) return st;
+  if ((st = swarm_loop(p, w, X, target, N, D, n_nodes, 0, s, nullptr, &sc))) return st;
   SLM_HIP(hipMemcpyAsync(gbest, w.gbest, (size_t)n_nodes * D * 8, hipMemcpyDeviceToDevice, s));
   SLM_HIP(hipMemcpyAsync(gbest_loss, w.gbest_loss, (size_t)n_nodes * 8, hipMemcpyDeviceToDevice, s));
   SLM_HIP(hipMemcpyAsync(gbest_split, w.gbest_split, (size_t)n_nodes * 4, hipMemcpyDeviceToDevice,
@@ -1458,6 +1462,11 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
       if (p.precision == 1)
         ss[1] += (active[j].end - active[j].beg) * (int64_t)p.rescore_k * (p.T + 1);
     }
+    // The histogram's chunk plan is made for the depth's rows rounded up to
+    // N / 2^k: captured swarm loops are keyed by it, and the rounding keeps
+    // trees of one shape on the same few graphs.
+    int64_t rows_q = N;
+    while (rows_q > 1 && (rows_q >> 1) >= hvp[na]) rows_q >>= 1;
     {
       // one copy: beg, end, node_id (and tree_off) up to entry na, and the
       // row prefix up to entry na + 1
@@ -1474,10 +1483,10 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
     }
     if ((st = tm_swarm.start(timing ? &timing[1] : nullptr, s))) return st;
     if (prof)
-      st = swarm_loop(p, w, Xc, tc, N, D, na, true, s, &lt);
+      st = swarm_loop(p, w, Xc, tc, N, D, na, rows_q, s, &lt);
     else
-      st = p.use_graph ? swarm_loop_graph(p, w, Xc, tc, N, D, na, true, s)
-                       : swarm_loop(p, w, Xc, tc, N, D, na, true, s);
+      st = p.use_graph ? swarm_loop_graph(p, w, Xc, tc, N, D, na, rows_q, s)
+                       : swarm_loop(p, w, Xc, tc, N, D, na, rows_q, s);
     if (st) return st;
     if ((st = tm_swarm.stop(s))) return st;
     if (prof) {

@@ -195,6 +195,12 @@ struct ScanArgs {
   double *sums_out;
   void *ws;
   size_t ws_bytes;
+  // Optional (histogram scan only): vpre[j] = rows of nodes 0 .. j-1
+  // (n_nodes + 1 entries, on the device) and rows >= vpre[n_nodes], rows <=
+  // N.  Work items and accumulator slots then follow the nodes' rows alone,
+  // as if the nodes were contiguous, and the chunk plan is made for rows.
+  const int64_t *vpre;
+  int64_t rows;
 };
 size_t scan_workspace_bytes(int64_t N, int n_nodes, int P, int bins, int K, int crit);
 slm_status launch_scan_hist(const ScanArgs &a, hipStream_t s);
