@@ -40,14 +40,14 @@ FP32_PEAK_TFLOPS = 157.3
 # Summary and commands: profiles/traffic_plain_tree_N100k_D64_P256.md
 TRAFFIC = {
     "k_scan_hist": {"source": "paper_2208_07023_amd/csrc/k_scan.hip",
-                    "sha256": "1b66fdfd18c96549233842d08856923bcf5bf75ef27492a5cc3618364facb26a",
-                    "fetch_kib": 43097.7, "write_kib": 4152.8},
+                    "sha256": "ff9dfdac653262ac9b4ffe12fee175c2807725ac5b8b158f0422af213006f907",
+                    "fetch_kib": 43088.5, "write_kib": 4152.8},
     "k_scan_finish_bins": {"source": "paper_2208_07023_amd/csrc/k_scan.hip",
-                           "sha256": "1b66fdfd18c96549233842d08856923bcf5bf75ef27492a5cc3618364facb26a",
-                           "fetch_kib": 3178.0, "write_kib": 3096.0},
+                           "sha256": "ff9dfdac653262ac9b4ffe12fee175c2807725ac5b8b158f0422af213006f907",
+                           "fetch_kib": 3174.0, "write_kib": 3096.0},
     "k_project": {"source": "paper_2208_07023_amd/csrc/k_project.hip",
                   "sha256": "e27b8abdd5cb1cd0f31e799308bbb86a24ab450dfe1c5fcaa61baee64f9fe512",
-                  "fetch_kib": 10796.9, "write_kib": 83806.5},
+                  "fetch_kib": 10796.4, "write_kib": 83806.5},
 }
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.3, 1.0
 
