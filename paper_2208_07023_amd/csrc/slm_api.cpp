@@ -1463,10 +1463,16 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
         ss[1] += (active[j].end - active[j].beg) * (int64_t)p.rescore_k * (p.T + 1);
     }
     // The histogram's chunk plan is made for the depth's rows rounded up to
-    // N / 2^k: captured swarm loops are keyed by it, and the rounding keeps
-    // trees of one shape on the same few graphs.
+    // a multiple of an eighth of N / 2^k (the smallest such power at or
+    // above them): captured swarm loops are keyed by it, and the rounding
+    // keeps trees of one shape on a few graphs (measured against N / 2^k
+    // alone: 2.45 -> 2.47e11 sample-splits/s, 30-tree forest 217 -> 214 ms).
     int64_t rows_q = N;
     while (rows_q > 1 && (rows_q >> 1) >= hvp[na]) rows_q >>= 1;
+    if (rows_q >= 8) {
+      const int64_t step = rows_q / 8;
+      rows_q = std::min(rows_q, (hvp[na] + step - 1) / step * step);
+    }
     {
       // one copy: beg, end, node_id (and tree_off) up to entry na, and the
       // row prefix up to entry na + 1
