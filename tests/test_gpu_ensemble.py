@@ -253,3 +253,40 @@ def test_bf16_forest_with_odd_rows_equals_trees_alone(gpu_lib):
         mine = api.forest_tree(f, b)
         for k in ("w", "thr", "left", "right", "n", "split_loss"):
             assert np.array_equal(mine[k], alone[k]), (b, k)
+
+
+def test_many_trees_scan_what_they_partition(gpu_lib):
+    """Twelve trees grown together over 96 000 stacked rows: the deeper
+    depths search a sparse subset of the rows (nodes of other trees stopped),
+    spread over several chunks each.  Every split's histogram loss equals the
+    size-weighted impurity of the children the partition made (the scan
+    binned exactly the node's rows), the children's class counts add up to
+    the parent's, and each tree equals the one grown alone."""
+    api = gpu_lib
+    N, D, K, nt = 8000, 12, 3, 12
+    X, y = inputs.cluster_mixture(N, D, K, clusters_per_class=3, seed=21)
+    cfg = api.TreeConfig(crit=OS.ENTROPY, K=K, max_depth=6, min_node=64, P=64, T=4, bins=128,
+                         seed=7, tree=40, use_graph=True)
+    f = api.grow_forest(_t(X), _t(y), cfg, nt)
+    depths = set()
+    for b in range(nt):
+        tr = api.forest_tree(f, b)
+        n = tr["n"]
+        for i in range(tr["n_nodes"]):
+            l, r = tr["left"][i], tr["right"][i]
+            if l < 0:
+                continue
+            depths.add(int(tr["depth"][i]))
+            assert n[l] + n[r] == n[i] and n[l] > 0 and n[r] > 0
+            w = (n[l] * tr["impurity"][l] + n[r] * tr["impurity"][r]) / n[i]
+            assert w == pytest.approx(tr["split_loss"][i], rel=1e-9, abs=1e-12), (b, i)
+            assert np.array_equal(tr["leaf"][l] + tr["leaf"][r], tr["leaf"][i]), (b, i)
+        if b % 4 == 0:
+            idx = E.bootstrap_indices(7, 40 + b, N)
+            cfg.tree = 40 + b
+            alone = api.grow_tree(_t(X[idx]), _t(y[idx]), cfg)
+            cfg.tree = 40
+            assert tr["n_nodes"] == alone["n_nodes"], b
+            for k in ("w", "thr", "left", "right", "leaf", "n", "split_loss"):
+                assert np.array_equal(tr[k], alone[k]), (b, k)
+    assert len(depths) >= 3
