@@ -366,7 +366,11 @@ typedef struct {
   int32_t min_node;
   int32_t P;           /* particles per node                            */
   int32_t T;           /* moves (T+1 evaluations)                       */
-  int32_t bins;        /* 2..256 (histogram scan); 0 = exact scan       */
+  int32_t bins;        /* 2..256 (histogram scan); 0 = exact scan, which
+                          takes nodes of at most 8192 rows: slm_grow_tree,
+                          slm_grow_forest and slm_boost with N > 8192
+                          return SLM_E_UNSUPPORTED (their workspace
+                          queries 0) before any launch                  */
   int32_t precision;   /* 0 = FP32 projection; 1 = BF16 screen + FP32
                           re-scoring of the best rescore_k per node      */
   int32_t rescore_k;   /* 1..P, used with precision = 1                 */

@@ -37,6 +37,16 @@ this build, from that method as published:
   of those channels, so the step stays in the subspace); and
   (1, APSO_STREAM + t, node, tree): the normal draw from words 0 and 1 as in
   the swarm's start (Box-Muller, cosine branch).
+
+Parity unpinned: the membership breakpoints of `memberships`, the hysteresis
+rule of `classify`, the inertia law of `inertia`, the delta range of the c1/c2
+changes, the clamp and sum limits, and the elitist step's sigma schedule are
+readings of the APSO reference, which is not at hand, recalled rather than
+checked against it.  The tests pin only what the paper itself fixes (the four
+states and the directions in which c1 and c2 move in each) and what holds
+mathematically (distances, the evolutionary factor's range and extremes, the
+unit norm of the elitist candidate); a shifted breakpoint or inertia constant
+would pass them.  The GPU follows these readings and is compared with them.
 """
 from __future__ import annotations
 

@@ -123,7 +123,7 @@ slm_status launch_dft_select(const DftArgs &d, hipStream_t s) {
   sa.threshold = thr;
   sa.ws = scan_ws;
   sa.ws_bytes = scan_b;
-  if ((st = d.bins ? launch_scan_hist(sa, s) : launch_scan_exact(sa, 8192, s))) return st;
+  if ((st = d.bins ? launch_scan_hist(sa, s) : launch_scan_exact(sa, EXACT_ROWS, s))) return st;
   if ((st = launch_scan_empty_nodes(sa, s))) return st;
   if ((st = launch_screen_select(d.loss, d.n_nodes, d.D, d.n, d.sel, s))) return st;
   // leave the whole workspace zero-filled (the scan part already is)

@@ -1236,7 +1236,7 @@ __global__ void k_scan_empty_nodes(ScanArgs a, int Kc) {
 }
 
 // ---------------------------------------------------------------- exact kernel
-constexpr int EXACT_MAX = 8192;
+constexpr int EXACT_MAX = EXACT_ROWS;
 constexpr int EXACT_KMAX = 16;
 
 template <bool MSE>
@@ -1452,8 +1452,9 @@ __global__ __launch_bounds__(WG) void k_scan_exact(ScanArgs a) {
 // that merely straddle a chunk boundary.  Measured (N = 1e5, P = 256): root
 // 58.8 -> 51.9 us by bins; two nodes of 50000 rows 15.6 -> 8.6 us by bins;
 // 128 nodes of 781 rows 128 us by groups, 154 us by bins.
+// With a row prefix the nodes hold a.rows rows between them, not a.N.
 bool finish_by_bins(const ScanArgs &a, int64_t) {
-  return a.N / std::max(1, a.n_nodes) >= 16384;
+  return (a.vpre ? a.rows : a.N) / std::max(1, a.n_nodes) >= 16384;
 }
 
 template <int PT, int KT, bool MSE>

@@ -608,7 +608,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
     sar.best_split = w.split_r; sar.best_loss = w.loss_r; sar.threshold = w.thr_r;
   }
   auto scan = [&](const ScanArgs &x) {
-    slm_status r = p.bins ? launch_scan_hist(x, s) : launch_scan_exact(x, 8192, s);
+    slm_status r = p.bins ? launch_scan_hist(x, s) : launch_scan_exact(x, EXACT_ROWS, s);
     if (!r && sc && p.bins) r = launch_scan_empty_nodes(x, s);
     return r;
   };
@@ -1158,8 +1158,8 @@ slm_status slm_search_nodes(const void *X, int32_t x_dtype, int64_t N, int32_t D
     std::vector<int64_t> ho((size_t)n_nodes + 1);
     SLM_HIP(hipMemcpy(ho.data(), row_off, ho.size() * 8, hipMemcpyDeviceToHost));
     for (int j = 0; j < n_nodes; ++j)
-      SLM_CHECK(ho[j + 1] - ho[j] <= 8192, SLM_E_UNSUPPORTED,
-                "slm_search_nodes: the exact scan takes nodes of at most 8192 rows");
+      SLM_CHECK(ho[j + 1] - ho[j] <= EXACT_ROWS, SLM_E_UNSUPPORTED,
+                "slm_search_nodes: the exact scan takes nodes of at most %d rows", EXACT_ROWS);
   }
   if ((st = prepare_kernels())) return st;
   hipStream_t s = S(stream);
@@ -1607,8 +1607,19 @@ static slm_status check_grow_args(const char *who, const void *X, int32_t x_dtyp
   return SLM_OK;
 }
 
+// A grown tree's root holds all of its N rows, and the exact scan (bins = 0)
+// takes nodes of at most EXACT_ROWS rows: larger trees are refused before any
+// launch rather than left unsplit.
+static slm_status check_exact_rows(const char *who, const slm_tree_params *p, int64_t N) {
+  SLM_CHECK(p->bins != 0 || N <= EXACT_ROWS, SLM_E_UNSUPPORTED,
+            "%s: the exact scan (bins = 0) takes nodes of at most %d rows; the root holds %lld",
+            who, EXACT_ROWS, (long long)N);
+  return SLM_OK;
+}
+
 size_t slm_grow_tree_workspace(const slm_tree_params *prm, int64_t N, int32_t D) {
   if (check_tree_params(prm, N, D) != SLM_OK) return 0;
+  if (check_exact_rows("slm_grow_tree_workspace", prm, N) != SLM_OK) return 0;
   return carve(*prm, N, D, nullptr, 0, tree_stats(*prm, D)).total;
 }
 
@@ -1618,6 +1629,7 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
   clear_error();
   slm_status st = check_tree_params(prm, N, D);
   if (st) return st;
+  if ((st = check_exact_rows("slm_grow_tree", prm, N))) return st;
   const slm_tree_params &p = *prm;
   if ((st = check_grow_args("slm_grow_tree", X, x_dtype, target, t_dtype, p, D, out))) return st;
   SLM_CHECK(workspace, SLM_E_INVALID, "slm_grow_tree: NULL workspace");
@@ -1671,7 +1683,7 @@ static slm_status check_forest(const slm_tree_params *prm, int64_t N, int32_t D,
   if (st) return st;
   SLM_CHECK(n_trees >= 1 && n_trees <= 65535 && N * n_trees < (1ll << 31), SLM_E_SHAPE,
             "slm_grow_forest: n_trees = %d (1..65535, n_trees * N < 2^31)", n_trees);
-  return SLM_OK;
+  return check_exact_rows("slm_grow_forest", prm, N);
 }
 
 size_t slm_grow_forest_workspace(const slm_tree_params *prm, int64_t N, int32_t D,
@@ -1791,6 +1803,7 @@ static slm_status check_boost(const slm_tree_params *prm, int64_t N, int32_t D, 
                               int32_t n_rounds) {
   slm_status st = check_tree_params(prm, N, D);
   if (st) return st;
+  if ((st = check_exact_rows("slm_boost", prm, N))) return st;
   SLM_CHECK(prm->crit == SLM_MSE && prm->precision == 0, SLM_E_INVALID,
             "slm_boost: the trees are SLR trees (crit SLM_MSE, precision 0)");
   SLM_CHECK(prm->proposal != 1, SLM_E_UNSUPPORTED, "slm_boost: no learned proposal");

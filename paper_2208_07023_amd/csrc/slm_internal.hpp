@@ -206,6 +206,9 @@ size_t scan_workspace_bytes(int64_t N, int n_nodes, int P, int bins, int K, int 
 slm_status launch_scan_hist(const ScanArgs &a, hipStream_t s);
 // "no split" outputs for nodes without rows (the histogram scan skips them)
 slm_status launch_scan_empty_nodes(const ScanArgs &a, hipStream_t s);
+// The exact scan sorts one node's rows in one work-group's LDS: nodes of at
+// most EXACT_ROWS rows.
+constexpr int EXACT_ROWS = 8192;
 slm_status launch_scan_exact(const ScanArgs &a, int max_rows, hipStream_t s);
 // fused projection + histogram scan (float32, D <= 64, 2 <= K <= 4, Gini /
 // entropy, particle-tiled layout of the scan arguments)

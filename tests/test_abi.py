@@ -265,3 +265,32 @@ def test_forest_and_boost_validation():
     st = lib.slm_boost(FAKE, 1000, 8, FAKE, api.F64, 0, ctypes.byref(mse), 2, float("nan"), FAKE,
                        1 << 40, FAKE, FAKE, ctypes.byref(out), None, None)
     assert st == 1 and "lr" in _err(lib)
+
+
+def test_exact_scan_tree_refuses_large_roots():
+    """The exact scan (bins = 0) sorts a node in one work-group's LDS, at most
+    8192 rows; a tree, forest or boosting round whose root holds more rows is
+    refused before any launch (Sec. II-A, Eqs. (3)-(4) are not silently
+    replaced by a leaf)."""
+    lib = api.load()
+    out = api.TreeOut()
+    cls = api.TreeConfig(crit=api.GINI, K=2, max_depth=3, P=8, T=2, bins=0).c_params()
+    assert lib.slm_grow_tree_workspace(ctypes.byref(cls), 8192, 8) > 0
+    assert lib.slm_grow_tree_workspace(ctypes.byref(cls), 8193, 8) == 0
+    st = lib.slm_grow_tree(FAKE, api.F32, 8193, 8, FAKE, api.I32, ctypes.byref(cls), FAKE,
+                           1 << 40, ctypes.byref(out), None)
+    assert st == 6 and "8192" in _err(lib)
+    assert lib.slm_grow_forest_workspace(ctypes.byref(cls), 8192, 8, 3) > 0
+    assert lib.slm_grow_forest_workspace(ctypes.byref(cls), 10_000, 8, 3) == 0
+    st = lib.slm_grow_forest(FAKE, api.F32, 10_000, 8, FAKE, api.I32, ctypes.byref(cls), 3, 1,
+                             FAKE, 1 << 40, None, ctypes.byref(out), None, None)
+    assert st == 6 and "8192" in _err(lib)
+    mse = api.TreeConfig(crit=api.MSE, K=0, max_depth=3, P=8, T=2, bins=0).c_params()
+    assert lib.slm_boost_workspace(ctypes.byref(mse), 8192, 8, 0) > 0
+    assert lib.slm_boost_workspace(ctypes.byref(mse), 8193, 8, 0) == 0
+    st = lib.slm_boost(FAKE, 8193, 8, FAKE, api.F64, 0, ctypes.byref(mse), 2, 0.1, FAKE, 1 << 40,
+                       FAKE, FAKE, ctypes.byref(out), None, None)
+    assert st == 6 and "8192" in _err(lib)
+    # the histogram scan has no such limit
+    hist = api.TreeConfig(crit=api.GINI, K=2, max_depth=3, P=8, T=2, bins=16).c_params()
+    assert lib.slm_grow_tree_workspace(ctypes.byref(hist), 1 << 20, 8) > 0

@@ -13,6 +13,13 @@
   falls linearly from 1 to 0.1;
 * a run never loses its global best, T = 0 is the plain swarm's single
   evaluation, and on a smooth landscape the adaptive swarm converges.
+
+Parity unpinned: the membership breakpoints, the hysteresis of `classify`, the
+inertia law, the delta range and the sigma schedule are readings of the APSO
+reference, which is not at hand.  `test_inertia_and_memberships` checks the
+inertia end points against the oracle's own formula and the core intervals'
+order only, so a shifted breakpoint or constant would still pass; what these
+tests do pin is what the paper fixes and what holds mathematically.
 """
 import math
 
