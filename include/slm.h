@@ -234,6 +234,18 @@ slm_status slm_ps_candidates(double *x, void *W_out, int32_t w_dtype, const int3
                              uint32_t tree, uint32_t t, void *stream);
 
 /* ------------------------------------------------------------------------
+ * slm_ps_tables -- the tables slm_ps_candidates draws from (Sec. II-B,
+ * Eq. (8): the coefficient range falls exponentially with the rank):
+ *   A_d = alpha0 exp(-alpha d), alpha = ln(alpha0) / (R - 1)  (0 if R = 1),
+ * for ranks d = 0 .. R-1, so A falls from alpha0 at the first rank to 1 at
+ * the last; pd[d] = A_d / alpha0 (selection probability), amax[d] =
+ * max(1, floor(A_d + 1e-9)) (coefficient range).  FP64 on the device.
+ * pd [device] f64 [R], amax [device] int32 [R]; 1 <= R <= 64; alpha0
+ * finite, >= 1.  Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_ps_tables(int32_t R, double alpha0, double *pd, int32_t *amax, void *stream);
+
+/* ------------------------------------------------------------------------
  * slm_pso_step -- one synchronous swarm step for every node (Sec. III-A,
  * Eqs. (11)-(12), Alg. 1).
  *
@@ -408,6 +420,8 @@ typedef struct {
                               proposal 2                                    */
 } slm_tree_params;
 
+#define SLM_TIMING_SLOTS 12
+
 typedef struct {
   int32_t max_nodes;   /* capacity of every array below                 */
   int32_t n_nodes;     /* [out] nodes written                           */
@@ -419,11 +433,15 @@ typedef struct {
   double *impurity;    /* node impurity                                 */
   double *split_loss;  /* global-best loss (+inf if not searched)       */
   int32_t *depth, *heap;
-  double *timing;      /* optional [8]: [0] whole call, [1] swarm loops,
-                          [2] partitions (ms); with profile = 1 also the
-                          summed kernel times of [3] projections, [4] scans,
-                          [5] swarm steps (ms), [6] projection launches,
-                          [7] scan launches                                */
+  double *timing;      /* optional [SLM_TIMING_SLOTS = 12]: [0] whole
+                          call, [1] swarm loops, [2] partitions (ms); with
+                          profile = 1 also the summed kernel times of
+                          [3] projections, [4] scans, [5] swarm steps (ms),
+                          [6] projection launches, [7] scan launches, and
+                          for screened evaluations (precision = 1) of the
+                          FP32 re-scoring: [8] projections, [9] scans (ms),
+                          [10] / [11] their launches ([3] / [4] then hold
+                          the screening launches only)                   */
   int64_t *sample_splits;    /* optional [2]: [0] sum over evaluations of
                                 n_j * P (screened ones with precision = 1),
                                 [1] re-scored n_j * rescore_k (else 0)      */
@@ -523,6 +541,27 @@ slm_status slm_boost(const float *X, int64_t N, int32_t D, const void *target, i
                      int32_t n_classes, const slm_tree_params *prm, int32_t n_rounds, double lr,
                      void *workspace, size_t ws_bytes, double *F, double *F0, slm_tree_out *out,
                      int32_t *tree_of, void *stream);
+
+/* ------------------------------------------------------------------------
+ * slm_boost_scores -- the scores of a boosted model for rows X (Sec. V):
+ * F(x) = F0 + lr * sum over rounds m of h_m(x), added round by round in the
+ * order slm_boost accumulated its training scores (so the training rows get
+ * slm_boost's F bit for bit).  h_m,k(x) is the leaf mean that row x reaches
+ * in tree m * max(K, 1) + k (right iff float32(w . x) >= thr, FP32
+ * accumulation in dimension order).
+ * Tree arrays: device copies of slm_boost's output (w [n_nodes, D], thr,
+ * left, right, leaf [n_nodes]); roots [device, n_rounds * max(K, 1)] the
+ * root of every tree in tree order.  F0 [host] f64 [max(K, 1)]; X [device]
+ * F32 [N, D]; leaf_ids [device] int32 [n_rounds * max(K, 1), N] scratch
+ * (receives every tree's leaf); F [device] f64 [N, max(K, 1)] receives the
+ * scores.  n_classes: 0 (regression) or K in 2..16.  n_rounds = 0 gives F0.
+ * Asynchronous.
+ * ------------------------------------------------------------------------ */
+slm_status slm_boost_scores(const float *w, const float *thr, const int32_t *left,
+                            const int32_t *right, const double *leaf, int32_t n_nodes,
+                            const int32_t *roots, int32_t n_rounds, int32_t n_classes, int32_t D,
+                            const double *F0, double lr, const float *X, int64_t N,
+                            int32_t *leaf_ids, double *F, void *stream);
 
 /* ------------------------------------------------------------------------
  * slm_search_nodes -- the swarm search of a batch of nodes (Alg. 1 for every

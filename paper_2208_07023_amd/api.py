@@ -8,7 +8,6 @@ GPU is visible the calls raise; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from dataclasses import dataclass
 
@@ -21,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libslm.so")
 F32, BF16, F64, I32 = 0, 1, 2, 3
 GINI, ENTROPY, MSE = 0, 1, 2
 Z_ROWS, Z_TILED = 0, 1
+TIMING_SLOTS = 12   # slm_tree_out.timing entries (SLM_TIMING_SLOTS)
 STATUS = {0: "SLM_OK", 1: "SLM_E_INVALID", 2: "SLM_E_SHAPE", 3: "SLM_E_DTYPE",
           4: "SLM_E_NOMEM", 5: "SLM_E_HIP", 6: "SLM_E_UNSUPPORTED"}
 
@@ -72,6 +72,9 @@ _SIGS = {
     "slm_pso_init_subspace": ([_VP] * 7 + [_VP, _I32, _I32, _I32, _U64, _U32, _VP, _I32, _VP,
                                            _I32, _VP], _I32),
     "slm_dft_select_workspace": ([_I64, _I32, _I32, _I32, _I32, _I32], _SZ),
+    "slm_ps_tables": ([_I32, _D, _VP, _VP, _VP], _I32),
+    "slm_boost_scores": ([_VP, _VP, _VP, _VP, _VP, _I32, _VP, _I32, _I32, _I32, _VP, _D, _VP, _I64,
+                          _VP, _VP, _VP], _I32),
     "slm_ps_candidates": ([_VP, _VP, _I32, _VP, _I32, _I32, _I32, _VP, _I32, _VP, _VP, _U64, _U32,
                            _U32, _VP], _I32),
     "slm_dft_select": ([_VP, _I64, _I32, _VP, _I32, _VP, _I32, _I32, _I32, _I32, _I32, _VP, _VP,
@@ -338,16 +341,13 @@ def pso_init(sw: Swarm, seed: int, tree: int, sel=None):
 
 
 def ps_tables(R: int, alpha0: float, device="cuda"):
-    """Probabilistic-search tables over R ranks: coefficient range
-    A_d = alpha0 exp(-alpha (d - 1)) with alpha = ln(alpha0) / (R - 1) (from
-    alpha0 at rank 1 to 1 at rank R) and selection probability
-    P_d = A_d / alpha0.  Returns device (pd float64 [R], amax int32 [R])."""
-    d = np.arange(R, dtype=np.float64)
-    alpha = math.log(alpha0) / (R - 1) if R > 1 else 0.0
-    A = alpha0 * np.exp(-alpha * d)
-    pd = A / alpha0
-    amax = np.maximum(1, np.floor(A + 1e-9)).astype(np.int32)
-    return (torch.from_numpy(pd).to(device), torch.from_numpy(amax).to(device))
+    """Probabilistic-search tables over R ranks (slm_ps_tables): device
+    (pd float64 [R], amax int32 [R])."""
+    load()
+    pd = torch.empty(R, dtype=torch.float64, device=device)
+    amax = torch.empty(R, dtype=torch.int32, device=device)
+    _check(_lib.slm_ps_tables(int(R), float(alpha0), _p(pd), _p(amax), _stream()), "slm_ps_tables")
+    return pd, amax
 
 
 def ps_candidates(sw: "Swarm", ranks, pd, amax, seed: int, tree: int, t: int):
@@ -586,7 +586,7 @@ def _tree_arrays(maxn: int, D: int, K: int, stats: bool = False):
                leaf=np.zeros((maxn, kk), np.float64), n=np.zeros(maxn, np.int64),
                impurity=np.zeros(maxn), split_loss=np.zeros(maxn),
                depth=np.zeros(maxn, np.int32), heap=np.zeros(maxn, np.int32),
-               timing=np.zeros(8), sample_splits=np.zeros(2, np.int64))
+               timing=np.zeros(TIMING_SLOTS), sample_splits=np.zeros(2, np.int64))
     if stats:
         arr["stats"] = np.zeros((maxn, (K + 1) * D), np.float32)
         arr["sigma"] = np.zeros((maxn, D), np.float32)
@@ -735,25 +735,27 @@ def boost(X, target, cfg: TreeConfig, n_rounds: int, lr: float, n_classes: int =
 
 
 def boost_scores(model: dict, X, rounds=None):
-    """F(x) of a boosted model on the device: F0 + lr * the trees' leaf values,
-    added round by round ([N, max(K, 1)] float64); rounds limits the sum to
-    the first rounds."""
+    """F(x) of a boosted model on the device (slm_boost_scores): F0 + lr *
+    the trees' leaf values, added round by round ([N, max(K, 1)] float64);
+    rounds limits the sum to the first rounds."""
     load()
     _dev(X, torch.float32, "X")
     Kc = max(1, model["n_classes"])
-    N = X.shape[0]
-    F = torch.from_numpy(np.tile(model["F0"], (N, 1))).to(X.device)
-    nt = (model["n_rounds"] if rounds is None else rounds) * Kc
-    tree = {k: model[k] for k in ("w", "thr", "left", "right", "leaf", "n_nodes")}
-    tree["K"] = 0
-    tree["roots"] = np.array([np.nonzero(model["tree_of"] == t)[0][0] for t in range(nt)],
-                             dtype=np.int32)
-    if nt == 0:
-        return F
-    _, leaves = forest_predict(tree, X, return_leaves=True)
-    h = torch.from_numpy(model["leaf"][:, 0]).to(X.device)[leaves.long()]   # [nt, N]
-    for t in range(nt):
-        F[:, t % Kc] += model["lr"] * h[t]
+    N, D = X.shape
+    n_rounds = model["n_rounds"] if rounds is None else rounds
+    nt = n_rounds * Kc
+    dev = X.device
+    roots = np.array([np.nonzero(model["tree_of"] == t)[0][0] for t in range(nt)], dtype=np.int32)
+    t = {k: torch.from_numpy(np.ascontiguousarray(model[k])).to(dev)
+         for k in ("w", "thr", "left", "right", "leaf")}
+    r = torch.from_numpy(roots).to(dev)
+    leaves = torch.empty((max(1, nt), N), dtype=torch.int32, device=dev)
+    F = torch.empty((N, Kc), dtype=torch.float64, device=dev)
+    F0 = np.ascontiguousarray(model["F0"], dtype=np.float64)
+    _check(_lib.slm_boost_scores(_p(t["w"]), _p(t["thr"]), _p(t["left"]), _p(t["right"]),
+                                 _p(t["leaf"]), int(model["n_nodes"]), _p(r), int(n_rounds),
+                                 int(model["n_classes"]), D, F0.ctypes.data, float(model["lr"]),
+                                 _p(X), N, _p(leaves), _p(F), _stream()), "slm_boost_scores")
     return F
 
 
@@ -906,9 +908,9 @@ def predict_leaves(tree: dict, X):
 
 
 def predict(tree: dict, X):
-    """Class ids (argmax of the leaf counts) or regression means."""
-    leaves = predict_leaves(tree, X).cpu().numpy()
-    leaf = tree["leaf"][leaves]
-    if tree["K"] > 1:
-        return np.argmax(leaf, axis=1)
-    return leaf[:, 0]
+    """Class ids (the leaf's majority class, smallest on ties) or regression
+    means of the rows X, computed on the device as a one-tree forest
+    (slm_forest_predict); returned as a host array."""
+    one = {k: tree[k] for k in ("w", "thr", "left", "right", "leaf", "n_nodes", "K")}
+    one["roots"] = np.zeros(1, np.int32)
+    return forest_predict(one, X).cpu().numpy()

@@ -183,6 +183,16 @@ __global__ __launch_bounds__(FWG) void k_boost_update(double *F, const int32_t *
   }
 }
 
+// F[i * Kc + k] = F0[k] (the boosted model's initial scores)
+struct F0Vals {
+  double v[16];
+};
+__global__ __launch_bounds__(FWG) void k_boost_init(double *F, int64_t N, int Kc, F0Vals f0) {
+  const int64_t i = (int64_t)blockIdx.x * FWG + threadIdx.x;
+  if (i >= N) return;
+  for (int k = 0; k < Kc; ++k) F[i * Kc + k] = f0.v[k];
+}
+
 unsigned blocks_for(int64_t n) { return (unsigned)((n + FWG - 1) / FWG); }
 
 }  // namespace
@@ -271,6 +281,16 @@ slm_status launch_boost_update(double *F, const int32_t *leaf_ids, const double 
   if (N == 0) return SLM_OK;
   hipLaunchKernelGGL(k_boost_update, dim3(blocks_for(N)), dim3(FWG), 0, s, F, leaf_ids, leaf,
                      n_nodes, N, Kc, lr);
+  SLM_LAUNCHED();
+  return SLM_OK;
+}
+
+slm_status launch_boost_init(double *F, int64_t N, int Kc, const double *F0, hipStream_t s) {
+  SLM_CHECK(Kc >= 1 && Kc <= 16, SLM_E_SHAPE, "boost: %d score columns (1..16)", Kc);
+  if (N == 0) return SLM_OK;
+  F0Vals f0{};
+  for (int k = 0; k < Kc; ++k) f0.v[k] = F0[k];
+  hipLaunchKernelGGL(k_boost_init, dim3(blocks_for(N)), dim3(FWG), 0, s, F, N, Kc, f0);
   SLM_LAUNCHED();
   return SLM_OK;
 }

@@ -677,6 +677,418 @@ slm_status launch_bf16(const ProjectArgs &a, hipStream_t s) {
   return SLM_OK;
 }
 
+// ---------------------------------------------------------------- streaming projection
+// W-stationary projection for D > 64 (float32 data) and for bfloat16 data.
+// A work-group of SW = 4 waves owns PT = 32 FN particles of the current
+// node: their directions sit in LDS in MFMA fragment order (each lane's
+// operand of one step is one 16-byte LDS read, 64 lanes read 1 KB
+// contiguously, no bank conflicts), loaded once per node.  Each wave takes
+// its own 32-row sub-tiles (the work-group steps over the node's rows 128 at
+// a time) and reads its A operand straight from global memory into
+// registers, double-buffered across sub-tiles; every wave computes all PT
+// particles of its rows, so each X row is read once per particle tile.
+//
+// The dimensions are taken in chunks of KCH: in chunk c, lanes 0-31 supply
+// the first half of the chunk's dimensions and lanes 32-63 the second half,
+// so a lane's A operand for a chunk is one contiguous 256-byte run of its X
+// row.  Three operand kinds:
+//   MK_BB  X and W bfloat16: v_mfma_f32_32x32x16_bf16, KCH = 256 (16 steps
+//          of 8 dimensions per half);
+//   MK_XB  X bfloat16, W float32: v_mfma_f32_32x32x2f32, KCH = 256 (128
+//          steps of one dimension per half; X widened exactly);
+//   MK_FF  X and W float32: v_mfma_f32_32x32x2f32, KCH = 128 (64 steps).
+// Dimensions past D are zero in W (the A operand there holds whatever
+// finite X values the clamped loads read).  Each output element is the same
+// MFMA sequence whatever FN, the grid and the row split, so a column
+// recomputed alone (P = 1, the partition) is bit-identical to the column
+// computed among many particles.
+constexpr int MK_BB = 0, MK_XB = 1, MK_FF = 2;
+constexpr int SW = 4;   // waves per work-group, one per SIMD
+
+template <int MK>
+struct StreamOps {
+  static constexpr int KCH = MK == MK_FF ? 128 : 256;   // dimensions per chunk
+  static constexpr int XBYTES = MK == MK_FF ? 4 : 2;     // bytes per X element
+  static constexpr int WBYTES = MK == MK_BB ? 2 : 4;     // bytes per W element
+  // 16-byte W groups per lane and chunk: the lane's half-chunk of W
+  static constexpr int G = KCH / 2 * WBYTES / 16;
+};
+
+__host__ __device__ constexpr size_t stream_lds_bytes(int MK, int FN, int D) {
+  return (size_t)((D + (MK == MK_FF ? 127 : 255)) / (MK == MK_FF ? 128 : 256)) * FN *
+         ((MK == MK_FF ? 128 : 256) / 2 * (MK == MK_BB ? 2 : 4) / 16) * 1024;
+}
+
+// one 16-byte group of a row: elements e0 .. e0 + 16/EB - 1 (EB bytes each)
+// of row `row` of a [*, D] matrix; elements past D read as zero when MASK,
+// else from element 0 of the row (finite data, met by zeros in W).
+template <int EB, bool VEC, bool MASK>
+__device__ __forceinline__ uint4 load_group(const void *base, int64_t row, int D, int e0) {
+  constexpr int NE = 16 / EB;
+  if constexpr (VEC) {
+    const bool in = e0 < D;
+    const char *p = static_cast<const char *>(base) + (row * D + (in ? e0 : 0)) * EB;
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    if (MASK && !in) return make_uint4(0u, 0u, 0u, 0u);
+    return v;
+  } else {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if constexpr (EB == 4) {
+      const float *r = static_cast<const float *>(base) + row * D;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int k = e0 + e;
+        const float v = r[k < D ? k : 0];
+        w[e] = (!MASK || k < D) ? __float_as_uint(v) : 0u;
+      }
+    } else {
+      const uint16_t *r = static_cast<const uint16_t *>(base) + row * D;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int k = e0 + e;
+        const uint32_t v = r[k < D ? k : 0];
+        w[e >> 1] |= ((!MASK || k < D) ? v : 0u) << (16 * (e & 1));
+      }
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+template <int MK, int FN, bool VEC, bool TILED>
+__global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64_t RB,
+                                                            int blocks_per_pt, int n_pt,
+                                                            int xcd_map) {
+  using O = StreamOps<MK>;
+  constexpr int KCH = O::KCH, G = O::G;
+  constexpr int PT = 32 * FN;
+  extern __shared__ __align__(16) uint4 wl[];   // [chunk][f][g][lane]
+  if (a.n_nodes <= 0) return;
+  // work-group -> (particle tile, row run).  xcd_map: work-groups are dealt
+  // to the 8 XCDs round robin; the particle tiles of one row run are kept on
+  // one XCD so that its L2 serves the run's X rows to all of them.
+  int pt, run;
+  {
+    const int b = blockIdx.x;
+    if (xcd_map) {
+      const int x = b & 7, q = b >> 3;
+      pt = q % n_pt;
+      run = x * (blocks_per_pt >> 3) + q / n_pt;
+    } else {
+      pt = b / blocks_per_pt;
+      run = b % blocks_per_pt;
+    }
+  }
+  const int64_t n_rows = a.vpre ? a.vpre[a.n_nodes] : a.N;
+  if (a.vpre) RB = ((n_rows + blocks_per_pt - 1) / blocks_per_pt + SR - 1) / SR * SR;
+  const int64_t r_begin = (int64_t)run * RB;
+  const int64_t r_end = r_begin + RB < n_rows ? r_begin + RB : n_rows;
+  if (r_begin >= r_end) return;
+  const int D = a.D, P = a.P;
+  const int nch = (D + KCH - 1) / KCH;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 31, kh = lane >> 5;
+  const int p0 = pt * PT;
+  const bool tile_full = p0 + PT <= P;
+  const int64_t rs = TILED ? (int64_t)32 : a.zl.rs;
+  const bool do_mm = a.zmin != nullptr;
+
+  int j0 = 0;
+  {
+    int lo = 0, hi = a.n_nodes;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const int64_t e = a.vpre ? a.vpre[mid + 1] : load_range(a.beg, a.end, mid, a.N).hi;
+      if (e <= r_begin) lo = mid + 1; else hi = mid;
+    }
+    j0 = lo;
+  }
+
+  float mn[FN], mx[FN];
+  // the node's W tile into LDS, fragment order: group g of lane (li, h) in
+  // chunk c, block f holds W elements c KCH + h KCH/2 + g (16 / WBYTES) ...
+  auto fill_w = [&](int j) {
+    const int64_t wb = (int64_t)j * P;
+    const int units = nch * FN * G * 64;
+    constexpr int UB = 8;   // loads in flight per thread
+    for (int u0 = threadIdx.x; u0 < units; u0 += UB * 64 * SW) {
+      uint4 v[UB];
+#pragma unroll
+      for (int e = 0; e < UB; ++e) {
+        const int u = u0 + e * 64 * SW;
+        const int l = u & 63;
+        const int g = (u >> 6) % G;
+        const int f = (u / (64 * G)) % FN;
+        const int c = u / (64 * G * FN);
+        const int p = p0 + f * 32 + (l & 31);
+        const int e0 = c * KCH + (l >> 5) * (KCH / 2) + g * (16 / O::WBYTES);
+        v[e] = make_uint4(0u, 0u, 0u, 0u);
+        if (u < units && p < P) v[e] = load_group<O::WBYTES, VEC, true>(a.W, wb + p, D, e0);
+      }
+#pragma unroll
+      for (int e = 0; e < UB; ++e) {
+        const int u = u0 + e * 64 * SW;
+        if (u < units) wl[u] = v[e];
+      }
+    }
+  };
+  auto flush = [&](int j) {
+    if (!do_mm) return;
+    const int64_t wb = (int64_t)j * P;
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+      const int p = p0 + f * 32 + li;
+      const float m0 = fminf(mn[f], __shfl_xor(mn[f], 32));
+      const float m1 = fmaxf(mx[f], __shfl_xor(mx[f], 32));
+      if (lane < 32 && p < P && m0 <= m1) {
+        atomic_min_f32(&a.zmin[wb + p], m0);
+        atomic_max_f32(&a.zmax[wb + p], m1);
+      }
+    }
+  };
+  // A operand of one chunk: 16 groups of 16 bytes, the lane's contiguous
+  // half-chunk of row `row`
+  auto load_a = [&](int64_t row, int c, uint4 (&A)[16]) {
+    const int e0 = c * KCH + kh * (KCH / 2);
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      A[q] = load_group<O::XBYTES, VEC, false>(a.X, row, D, e0 + q * (16 / O::XBYTES));
+  };
+  auto mma_chunk = [&](int c, const uint4 (&A)[16], f32x16 (&acc)[FN]) {
+    const uint4 *wc = wl + (size_t)c * FN * G * 64 + lane;
+    if constexpr (MK == MK_BB) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+#pragma unroll
+        for (int f = 0; f < FN; ++f) {
+          const uint4 b = wc[(f * G + q) * 64];
+          acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A[q]),
+                                                           __builtin_bit_cast(bf16x8, b), acc[f],
+                                                           0, 0, 0);
+        }
+    } else if constexpr (MK == MK_XB) {
+      // A[q] holds 8 bfloat16 (steps 8q .. 8q+7), W groups 2q, 2q+1 the
+      // matching 8 floats
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const uint32_t w4[4] = {A[q].x, A[q].y, A[q].z, A[q].w};
+#pragma unroll
+        for (int f = 0; f < FN; ++f) {
+          const uint4 b0 = wc[(f * G + 2 * q) * 64], b1 = wc[(f * G + 2 * q + 1) * 64];
+          const uint32_t bw[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float xa = __uint_as_float((e & 1) ? (w4[e >> 1] & 0xFFFF0000u) : (w4[e >> 1] << 16));
+            acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, __uint_as_float(bw[e]), acc[f], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const uint32_t w4[4] = {A[q].x, A[q].y, A[q].z, A[q].w};
+#pragma unroll
+        for (int f = 0; f < FN; ++f) {
+          const uint4 b = wc[(f * G + q) * 64];
+          const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(w4[e]),
+                                                          __uint_as_float(bw[e]), acc[f], 0, 0, 0);
+        }
+      }
+    }
+  };
+  // Lane l, register r of block f holds row 8 (r/4) + 4 (l/32) + r%4 of the
+  // sub-tile and particle p0 + 32 f + l%32.
+  auto epilogue = [&](int64_t lo, int nrow, const f32x16 (&acc)[FN]) {
+    if (nrow == SR && tile_full) {
+#pragma unroll
+      for (int f = 0; f < FN; ++f) {
+        float *zc = a.Z + z_col(a.zl, p0 + f * 32 + li) + (lo + 4 * kh) * rs;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = acc[f][r];
+        float l = acc[f][0], h = acc[f][0];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) {
+          l = fminf(l, acc[f][r]);
+          h = fmaxf(h, acc[f][r]);
+        }
+        mn[f] = fminf(mn[f], l);
+        mx[f] = fmaxf(mx[f], h);
+      }
+      return;
+    }
+    // rows past the node's end or columns past P: buffer stores with an
+    // out-of-range offset are dropped by the hardware
+    const uint32_t nb = (uint32_t)(nrow * rs * 4);
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+      const bool pin = p0 + f * 32 + li < P;
+      const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
+          a.Z + (int64_t)((p0 >> 5) + f) * a.zl.ts + lo * rs, 0, nb, BUF_DW3);
+      float l = __builtin_nanf(""), h = __builtin_nanf("");
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
+        const bool ok = pin && row < nrow;
+        const uint32_t off = ok ? (uint32_t)((row * rs + li) * 4) : 0x80000000u;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(acc[f][r]), zr, (int)off, 0, 0);
+        const float z = ok ? acc[f][r] : __builtin_nanf("");
+        l = fminf(l, z);
+        h = fmaxf(h, z);
+      }
+      mn[f] = fminf(mn[f], l);
+      mx[f] = fmaxf(mx[f], h);
+    }
+  };
+  // one sub-tile: rows lo .. lo + nrow - 1, A of chunk 0 already in A0
+  auto subtile = [&](int64_t lo, int nrow, uint4 (&A0)[16], uint4 (&A1)[16]) {
+    f32x16 acc[FN];
+#pragma unroll
+    for (int f = 0; f < FN; ++f) acc[f] = f32x16{};
+    const int64_t row = lo + (li < nrow ? li : nrow - 1);
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) load_a(row, c + 1, A1);
+      mma_chunk(c, A0, acc);
+      if (c + 1 < nch) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) A0[q] = A1[q];
+      }
+    }
+    epilogue(lo, nrow, acc);
+  };
+
+  uint4 A0[16], A1[16];
+  bool first = true;
+  for (SubTile c = next_subtile(a, j0, r_begin, r_end); c.j >= 0;
+       c = next_subtile(a, c.j + 1, r_begin, r_end)) {
+    const int64_t end = c.end;
+    int64_t my = c.lo + SR * wave;   // this wave's first sub-tile
+    const auto row_of = [&](int64_t lo) {
+      const int64_t n = end - lo < SR ? end - lo : SR;
+      return lo + (li < n ? li : n - 1);
+    };
+    if (my < end) load_a(row_of(my), 0, A0);
+    // the previous node's LDS reads are done before its tile is replaced
+    // (an LDS-only barrier: the A loads just issued stay in flight)
+    if (!first) lds_barrier();
+    first = false;
+    fill_w(c.j);
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+      mn[f] = __builtin_huge_valf();
+      mx[f] = -__builtin_huge_valf();
+    }
+    lds_barrier();
+    // ping-pong over this wave's sub-tiles of the node, SW SR rows apart
+    while (my < end) {
+      const int64_t nx = my + SW * SR;
+      const int n0 = (int)(end - my < SR ? end - my : SR);
+      if (nch == 1) {
+        if (nx < end) load_a(row_of(nx), 0, A1);
+        subtile(my, n0, A0, A1);
+        if (nx >= end) break;
+        const int64_t nx2 = nx + SW * SR;
+        const int n1 = (int)(end - nx < SR ? end - nx : SR);
+        if (nx2 < end) load_a(row_of(nx2), 0, A0);
+        subtile(nx, n1, A1, A0);
+        my = nx2;
+      } else {
+        subtile(my, n0, A0, A1);
+        my = nx;
+        if (my < end) load_a(row_of(my), 0, A0);
+      }
+    }
+    flush(c.j);
+  }
+}
+
+template <int MK, int FN, bool VEC>
+slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s) {
+  constexpr int PT = 32 * FN;
+  const int n_pt = (a.P + PT - 1) / PT;
+  const int cus = num_cus_proj();
+  // one work-group per CU (LDS and registers allow one): the particle tiles
+  // share the CUs, each tile's rows split into runs of whole sub-tiles
+  int64_t bpp = std::max<int64_t>(1, std::min<int64_t>((a.N + SR - 1) / SR, cus / n_pt));
+  int xcd = 0;
+  if (bpp >= 8 && n_pt * bpp >= 64) {
+    bpp = bpp / 8 * 8;
+    xcd = 1;
+  }
+  int64_t RB = ((a.N + bpp - 1) / bpp + SR - 1) / SR * SR;
+  if (!a.vpre && !xcd) bpp = (a.N + RB - 1) / RB;
+  const int64_t grid = bpp * n_pt;
+  if (grid == 0) return SLM_OK;
+  SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_project: grid too large");
+  const size_t lds = stream_lds_bytes(MK, FN, a.D);
+  if (a.zl.rs == 32)
+    hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, true>), dim3((unsigned)grid), dim3(64 * SW),
+                       lds, s, a, RB, (int)bpp, n_pt, xcd);
+  else
+    hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, false>), dim3((unsigned)grid), dim3(64 * SW),
+                       lds, s, a, RB, (int)bpp, n_pt, xcd);
+  SLM_LAUNCHED();
+  return SLM_OK;
+}
+
+constexpr size_t STREAM_LDS_MAX = 128 * 1024;
+
+template <int MK>
+slm_status launch_stream(const ProjectArgs &a, hipStream_t s) {
+  const size_t xe = MK == MK_FF ? 4 : 2, we = MK == MK_BB ? 2 : 4;
+  // 16-byte groups need rows that are whole groups in both matrices
+  const bool vec = (a.D * xe) % 16 == 0 && (a.D * we) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(a.X) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(a.W) % 16 == 0;
+  const int blocks = (a.P + 31) / 32;
+  if (blocks >= 4 && stream_lds_bytes(MK, 4, a.D) <= STREAM_LDS_MAX)
+    return vec ? launch_stream_f<MK, 4, true>(a, s) : launch_stream_f<MK, 4, false>(a, s);
+  if (blocks >= 2 && stream_lds_bytes(MK, 2, a.D) <= STREAM_LDS_MAX)
+    return vec ? launch_stream_f<MK, 2, true>(a, s) : launch_stream_f<MK, 2, false>(a, s);
+  return vec ? launch_stream_f<MK, 1, true>(a, s) : launch_stream_f<MK, 1, false>(a, s);
+}
+
+// The streaming kernel serves every launch of a given (D, data types) or
+// none, so a column recomputed alone always runs the kernel the swarm ran.
+bool stream_eligible(const ProjectArgs &a) {
+  if (a.Z == nullptr) return false;
+  const int mk = a.x_bf16 && a.w_bf16 ? MK_BB : a.x_bf16 ? MK_XB : MK_FF;
+  if (mk == MK_FF && a.D <= 64) return false;      // k_project_short
+  if (a.w_bf16 && !a.x_bf16) return false;
+  return stream_lds_bytes(mk, 1, a.D) <= STREAM_LDS_MAX;
+}
+
+template <int MK, int FN, bool VEC, bool TILED>
+void set_stream_attr(int bytes) {
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_project_stream<MK, FN, VEC, TILED>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+    (void)hipGetLastError();
+}
+template <int MK, int FN>
+void set_stream_attr_fn(int bytes) {
+  set_stream_attr<MK, FN, true, true>(bytes);
+  set_stream_attr<MK, FN, true, false>(bytes);
+  set_stream_attr<MK, FN, false, true>(bytes);
+  set_stream_attr<MK, FN, false, false>(bytes);
+}
+template <int MK>
+void set_stream_attr_mk(int bytes) {
+  set_stream_attr_fn<MK, 1>(bytes);
+  set_stream_attr_fn<MK, 2>(bytes);
+  set_stream_attr_fn<MK, 4>(bytes);
+}
+
+// SLM_PROJ_STREAM=0 keeps the tile kernels for every shape (timing
+// comparisons; read once per process)
+bool stream_enabled() {
+  static const int on = [] {
+    const char *e = getenv("SLM_PROJ_STREAM");
+    return e && e[0] == '0' ? 0 : 1;
+  }();
+  return on != 0;
+}
+
 __global__ void k_fill_minmax(float *zmin, float *zmax, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -713,9 +1125,21 @@ slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s
   return SLM_OK;
 }
 
+void prepare_project_kernels(int lds_max) {
+  const int dyn = (int)std::min<size_t>((size_t)lds_max, STREAM_LDS_MAX);
+  set_stream_attr_mk<MK_BB>(dyn);
+  set_stream_attr_mk<MK_XB>(dyn);
+  set_stream_attr_mk<MK_FF>(dyn);
+}
+
 slm_status launch_project(const ProjectArgs &a, hipStream_t s) {
   SLM_CHECK(a.Z != nullptr || (a.D <= 64 && !a.x_bf16 && !a.w_bf16 && a.zmin), SLM_E_INVALID,
             "slm_project: a min/max-only pass needs float32 data, D <= 64 and zmin/zmax");
+  if (stream_enabled() && stream_eligible(a)) {
+    if (a.x_bf16 && a.w_bf16) return launch_stream<MK_BB>(a, s);
+    if (a.x_bf16) return launch_stream<MK_XB>(a, s);
+    return launch_stream<MK_FF>(a, s);
+  }
   // both bfloat16: bfloat16 matrix cores
   if (a.x_bf16 && a.w_bf16) {
     if (a.P > 64) return launch_bf16<128, 128>(a, s);

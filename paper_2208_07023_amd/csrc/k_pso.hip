@@ -647,6 +647,21 @@ __global__ __launch_bounds__(MOVE_WG) void k_pso_fused(PsoArgs a) {
 // (node, particle); x and its image W_out are written in full (zeros
 // elsewhere).
 
+// Tables of the probabilistic search over R ranks (Eq. (8), reading of this
+// build): A_d = alpha0 exp(-alpha d), alpha = ln(alpha0) / (R - 1), so A falls
+// from alpha0 at the first rank (d = 0) to 1 at the last; the selection
+// probability is A_d / alpha0 and the coefficient range floor(A_d) (at least 1;
+// the 1e-9 keeps a rounded A just below an integer on it).
+__global__ void k_ps_tables(int R, double alpha0, double *pd, int32_t *amax) {
+  const int d = threadIdx.x;
+  if (d >= R) return;
+  const double alpha = R > 1 ? log(alpha0) / (double)(R - 1) : 0.0;
+  const double A = alpha0 * exp(-(alpha * (double)d));
+  pd[d] = A / alpha0;
+  const double f = floor(A + 1e-9);
+  amax[d] = f < 1.0 ? 1 : (int32_t)f;
+}
+
 __global__ void k_ps_candidates(PsoArgs a, const int32_t *ranks, int R, const double *pd,
                                 const int32_t *amax, uint32_t t) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -782,6 +797,12 @@ slm_status launch_ps_candidates(const PsoArgs &a, const int32_t *ranks, int R, c
   if (n == 0) return SLM_OK;
   hipLaunchKernelGGL(k_ps_candidates, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, a,
                      ranks, R, pd, amax, t);
+  SLM_LAUNCHED();
+  return SLM_OK;
+}
+
+slm_status launch_ps_tables(int R, double alpha0, double *pd, int32_t *amax, hipStream_t s) {
+  hipLaunchKernelGGL(k_ps_tables, dim3(1), dim3(PS_RMAX), 0, s, R, alpha0, pd, amax);
   SLM_LAUNCHED();
   return SLM_OK;
 }

@@ -1563,6 +1563,7 @@ slm_status prepare_kernels() {
     set_lds_attr_pt<8>(dyn);
     set_lds_attr_pt<4>(dyn);
     prepare_pso_kernels(lds);
+    prepare_project_kernels(lds);
   });
   return SLM_OK;
 }

@@ -642,10 +642,10 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
       if ((st = launch_screen_select(w.loss, na, p.P, k, w.sel, s))) return st;
       if ((st = launch_screen_gather(w.x, w.sel, na, p.P, k, D, w.W32, s))) return st;
       if ((st = launch_fill_minmax(w.zmin_r, w.zmax_r, (int64_t)na * k, s))) return st;
-      if (lt && (st = lt->begin(0, s))) return st;
+      if (lt && (st = lt->begin(3, s))) return st;
       if ((st = launch_project(prr, s))) return st;
       if (lt && (st = lt->end(s))) return st;
-      if (lt && (st = lt->begin(1, s))) return st;
+      if (lt && (st = lt->begin(4, s))) return st;
       if ((st = scan(sar))) return st;
       if (lt && (st = lt->end(s))) return st;
       if ((st = launch_screen_merge(w.sel, w.loss_r, w.split_r, w.thr_r, na, p.P, k, w.loss,
@@ -791,8 +791,9 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, con
             "slm_project: bad Z layout %d", z_layout);
   if (N == 0 || n_nodes == 0) return SLM_OK;
   SLM_CHECK(X && W && row_off && Z && zmin && zmax, SLM_E_INVALID, "slm_project: NULL pointer");
-  slm_status st = launch_fill_minmax(zmin, zmax, (int64_t)n_nodes * P, S(stream));
+  slm_status st = prepare_kernels();
   if (st) return st;
+  if ((st = launch_fill_minmax(zmin, zmax, (int64_t)n_nodes * P, S(stream)))) return st;
   ProjectArgs a{};
   a.X = X; a.x_bf16 = x_dtype == SLM_BF16; a.w_bf16 = w_dtype == SLM_BF16; a.N = N; a.D = D;
   a.W = W;
@@ -976,6 +977,16 @@ slm_status slm_ps_candidates(double *x, void *W_out, int32_t w_dtype, const int3
   a.x = x; a.node_id = node_id; a.n_nodes = n_nodes; a.P = P; a.D = D; a.seed = seed;
   a.tree = tree; a.W_out = W_out; a.w_bf16 = w_dtype == SLM_BF16;
   return launch_ps_candidates(a, ranks, R, pd, amax, t, S(stream));
+}
+
+slm_status slm_ps_tables(int32_t R, double alpha0, double *pd, int32_t *amax, void *stream) {
+  clear_error();
+  SLM_CHECK(R >= 1 && R <= PS_RMAX, SLM_E_SHAPE, "slm_ps_tables: R = %d not in [1, %d]", R,
+            PS_RMAX);
+  SLM_CHECK(std::isfinite(alpha0) && alpha0 >= 1.0, SLM_E_INVALID,
+            "slm_ps_tables: alpha0 must be finite and >= 1");
+  SLM_CHECK(pd && amax, SLM_E_INVALID, "slm_ps_tables: NULL pointer");
+  return launch_ps_tables(R, alpha0, pd, amax, S(stream));
 }
 
 slm_status slm_pso_step(double *x, double *v, double *pbest, double *pbest_loss, double *gbest,
@@ -1497,10 +1508,19 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
     if ((st = tm_swarm.stop(s))) return st;
     if (prof) {
       SLM_HIP(hipStreamSynchronize(s));
-      double cnt[3] = {0, 0, 0};
-      if ((st = lt.collect(timing + 3, cnt))) return st;
+      // kinds: 0 projection, 1 scan, 2 swarm step, 3 re-scoring
+      // projection, 4 re-scoring scan (screened evaluations)
+      double acc[5] = {0, 0, 0, 0, 0}, cnt[5] = {0, 0, 0, 0, 0};
+      if ((st = lt.collect(acc, cnt))) return st;
+      timing[3] += acc[0];
+      timing[4] += acc[1];
+      timing[5] += acc[2];
       timing[6] += cnt[0];
       timing[7] += cnt[1];
+      timing[8] += acc[3];
+      timing[9] += acc[4];
+      timing[10] += cnt[3];
+      timing[11] += cnt[4];
     }
     if (dn_span <= ((size_t)512 << 10)) {
       const size_t n_dn = reinterpret_cast<char *>(w.gbest_thr + na) - dn0;
@@ -1638,7 +1658,7 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D, c
             ws_bytes, w.total);
   if ((st = prepare_kernels())) return st;
   hipStream_t s = S(stream);
-  if (out->timing) std::fill(out->timing, out->timing + 8, 0.0);
+  if (out->timing) std::fill(out->timing, out->timing + SLM_TIMING_SLOTS, 0.0);
   Timer tm_all;
   if ((st = tm_all.start(out->timing ? &out->timing[0] : nullptr, s))) return st;
   int64_t ss[2] = {0, 0};
@@ -1710,7 +1730,7 @@ slm_status slm_grow_forest(const void *X, int32_t x_dtype, int64_t N, int32_t D,
             "slm_grow_forest: workspace of %zu bytes, %zu needed", ws_bytes, f.total);
   if ((st = prepare_kernels())) return st;
   hipStream_t s = S(stream);
-  if (out->timing) std::fill(out->timing, out->timing + 8, 0.0);
+  if (out->timing) std::fill(out->timing, out->timing + SLM_TIMING_SLOTS, 0.0);
   Timer tm_all;
   if ((st = tm_all.start(out->timing ? &out->timing[0] : nullptr, s))) return st;
   const int64_t NT = N * n_trees;
@@ -1754,6 +1774,36 @@ slm_status slm_forest_predict(const float *w, const float *thr, const int32_t *l
                                        leaf_ids, s);
   if (st) return st;
   return launch_forest_combine(leaf_ids, leaf, n_nodes, n_trees, K, N, out, s);
+}
+
+slm_status slm_boost_scores(const float *w, const float *thr, const int32_t *left,
+                            const int32_t *right, const double *leaf, int32_t n_nodes,
+                            const int32_t *roots, int32_t n_rounds, int32_t n_classes, int32_t D,
+                            const double *F0, double lr, const float *X, int64_t N,
+                            int32_t *leaf_ids, double *F, void *stream) {
+  clear_error();
+  const int Kc = std::max(1, (int)n_classes);
+  SLM_CHECK(n_classes == 0 || (n_classes >= 2 && n_classes <= 16), SLM_E_SHAPE,
+            "slm_boost_scores: n_classes = %d (0 or 2..16)", n_classes);
+  SLM_CHECK(n_rounds >= 0 && n_nodes >= 0 && D >= 1 && D <= DMAX && N >= 0 && N < (1ll << 31) &&
+                (int64_t)n_rounds * Kc <= 65535 && N * n_rounds * Kc < (1ll << 31),
+            SLM_E_SHAPE, "slm_boost_scores: bad sizes");
+  SLM_CHECK(std::isfinite(lr), SLM_E_INVALID, "slm_boost_scores: lr must be finite");
+  SLM_CHECK(F0 && F, SLM_E_INVALID, "slm_boost_scores: NULL pointer");
+  if (N == 0) return SLM_OK;
+  hipStream_t s = S(stream);
+  slm_status st = launch_boost_init(F, N, Kc, F0, s);
+  if (st || n_rounds == 0) return st;
+  SLM_CHECK(n_nodes >= 1 && w && thr && left && right && leaf && roots && X && leaf_ids,
+            SLM_E_INVALID, "slm_boost_scores: NULL pointer");
+  const int nt = n_rounds * Kc;
+  if ((st = launch_forest_leaves(w, thr, left, right, n_nodes, roots, nt, D, X, N, leaf_ids, s)))
+    return st;
+  // round by round, as the training scores were accumulated
+  for (int m = 0; m < n_rounds; ++m)
+    if ((st = launch_boost_update(F, leaf_ids + (size_t)m * Kc * N, leaf, n_nodes, N, Kc, lr, s)))
+      return st;
+  return SLM_OK;
 }
 
 // ---------------------------------------------------------------- boosting
@@ -1842,7 +1892,7 @@ slm_status slm_boost(const float *X, int64_t N, int32_t D, const void *target, i
             ws_bytes, b.total);
   if ((st = prepare_kernels())) return st;
   hipStream_t s = S(stream);
-  if (out->timing) std::fill(out->timing, out->timing + 8, 0.0);
+  if (out->timing) std::fill(out->timing, out->timing + SLM_TIMING_SLOTS, 0.0);
   Timer tm_all;
   if ((st = tm_all.start(out->timing ? &out->timing[0] : nullptr, s))) return st;
   const int64_t NT = (int64_t)Kc * N;

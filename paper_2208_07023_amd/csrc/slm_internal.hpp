@@ -177,6 +177,8 @@ struct ProjectArgs {
 };
 slm_status launch_project(const ProjectArgs &a, hipStream_t s);
 slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s);
+// raises the dynamic-LDS limit of the streaming projection kernels
+void prepare_project_kernels(int lds_max);
 
 struct ScanArgs {
   const float *Z;
@@ -278,6 +280,7 @@ void prepare_pso_kernels(int lds_max);
 slm_status launch_pso_step(const PsoArgs &a, hipStream_t s);
 // probabilistic search candidates (ranks [n_nodes, R], pd / amax [R], device)
 constexpr int PS_RMAX = 64;
+slm_status launch_ps_tables(int R, double alpha0, double *pd, int32_t *amax, hipStream_t s);
 slm_status launch_ps_candidates(const PsoArgs &a, const int32_t *ranks, int R, const double *pd,
                                 const int32_t *amax, uint32_t t, hipStream_t s);
 
@@ -360,6 +363,7 @@ slm_status launch_forest_combine(const int32_t *leaf_ids, const double *leaf, in
                                  int n_trees, int K, int64_t N, void *out, hipStream_t s);
 slm_status launch_boost_residual(const int32_t *labels, const double *y, const double *F,
                                  int64_t N, int K, double *r, hipStream_t s);
+slm_status launch_boost_init(double *F, int64_t N, int Kc, const double *F0, hipStream_t s);
 slm_status launch_boost_update(double *F, const int32_t *leaf_ids, const double *leaf,
                                int n_nodes, int64_t N, int Kc, double lr, hipStream_t s);
 

@@ -138,72 +138,138 @@ def mean_best_cos2(net: Net, stats, targets, bf16: bool = True) -> float:
 
 
 # ------------------------------------------------------------------ comparison
-def _route_depths(tr, X):
-    """Rows of every searched node of a grown tree, by depth: list of
-    (node indices, row index arrays).  Routing follows the tree's stored
-    float32 rule (right iff float32(w.x) >= t) on the host."""
-    n_nodes = tr["n_nodes"]
-    rows = {0: np.arange(X.shape[0])}
+def _ancestors(tree: dict, leaves, device):
+    """For every row's leaf, the node it passed at each depth: [depth, rows]
+    (-1 below the row's leaf).  Index bookkeeping on the tree's child lists;
+    the routing itself (slm_predict) ran on the device."""
+    n = int(tree["n_nodes"])
+    parent = np.full(n, -1, np.int64)
+    for i in range(n):
+        for c in (tree["left"][i], tree["right"][i]):
+            if c >= 0:
+                parent[c] = i
+    depth = tree["depth"][:n].astype(np.int64)
+    max_d = int(depth.max()) if n else 0
+    par = torch.from_numpy(parent).to(device)
+    dep = torch.from_numpy(depth).to(device)
+    cur = leaves.to(torch.int64)
+    out = torch.full((max_d + 1, cur.numel()), -1, dtype=torch.int64, device=device)
+    for d in range(max_d, -1, -1):
+        # every row's node is at depth <= d + 1 here: one step up suffices
+        cur = torch.where(dep[cur] > d, par[cur], cur)
+        out[d] = torch.where(dep[cur] == d, cur, out[d])
+    return out
+
+
+def _node_sets(trees, row_sets, X, device):
+    """Rows of every searched node, by depth, over several trees: a list of
+    (row indices into X grouped by node, node sizes, (tree, node) pairs).
+    Rows are routed through each tree by slm_predict on the device."""
     by_depth = {}
-    for i in range(n_nodes):
-        r = rows.get(i)
-        if r is None:
-            continue
-        if np.isfinite(tr["split_loss"][i]):
-            by_depth.setdefault(int(tr["depth"][i]), []).append((i, r))
-        if tr["left"][i] >= 0:
-            z = (X[r].astype(np.float64) @ tr["w"][i].astype(np.float64)).astype(np.float32)
-            right = z >= tr["thr"][i]
-            rows[int(tr["left"][i])] = r[~right]
-            rows[int(tr["right"][i])] = r[right]
+    for b, (tr, rows) in enumerate(zip(trees, row_sets)):
+        leaves = api.predict_leaves(tr, X.index_select(0, rows).contiguous())
+        anc = _ancestors(tr, leaves, device)
+        searched = np.isfinite(tr["split_loss"][:tr["n_nodes"]])
+        for d in range(anc.shape[0]):
+            ids = anc[d]
+            keep = ids >= 0
+            if not bool(keep.any()):
+                continue
+            ids_k = ids[keep]
+            rows_k = rows[keep.nonzero().squeeze(1)]
+            order = torch.argsort(ids_k, stable=True)
+            ids_s, rows_s = ids_k[order], rows_k[order]
+            uniq, counts = torch.unique_consecutive(ids_s, return_counts=True)
+            uq, ct = uniq.cpu().numpy(), counts.cpu().numpy()
+            starts = np.concatenate([[0], np.cumsum(ct)])
+            for j, node in enumerate(uq):
+                if not searched[node]:
+                    continue
+                by_depth.setdefault(d, []).append((b, int(node), rows_s[starts[j]:starts[j + 1]]))
     return [by_depth[d] for d in sorted(by_depth)]
 
 
-def compare_starts(net: Net, X, y, K: int, ref_P: int = 256, ref_T: int = 200, P: int = 64,
-                   T_max: int = 50, tol: float = 0.01, max_depth: int = 8, seed: int = 0,
-                   tree: int = 0, device="cuda", log=None):
-    """Paired comparison of random and learned swarm starts on one tree.
+def compare_forest(nets: dict, N: int, D: int, K: int, n_trees: int, ref_P: int = 256,
+                   ref_T: int = 200, P: int = 64, T_max: int = 50, tol: float = 0.01,
+                   max_depth: int = 8, seed: int = 0, mean_std: float = 0.8, clusters: int = 4,
+                   device="cuda", log=None):
+    """Paired comparison of random and learned (hybrid) swarm starts on the
+    nodes of a bootstrap forest.
 
-    A reference tree grown with plain PSO at an extended budget (ref_P
-    particles, ref_T moves) fixes the node row sets and each node's reference
-    loss L_ref.  On exactly those nodes, batched per depth, each arm searches
-    with P particles until its global-best loss is <= (1 + tol) L_ref or after
-    T_max moves.  Returns per-arm totals: wall ms (including the learned arm's
+    A plain forest (n_trees bootstrap trees, P particles, T_max moves) fixes
+    the node row sets; a reference search of every node (ref_P particles,
+    ref_T moves) fixes each node's reference loss L_ref.  Then, on exactly
+    those nodes, batched per depth over all trees, each arm searches with P
+    particles until its global-best loss is <= (1 + tol) L_ref or after T_max
+    moves: "random" starts all P particles at random (Sec. III-A); "learned_M"
+    places the network's M seeds on the first M particles and keeps P - M
+    random ones.  Returns per arm: wall ms (including the learned arms'
     statistics and inference), evaluations, nodes that met the target."""
-    Xd = torch.from_numpy(X).to(device)
-    yd = torch.from_numpy(y).to(device)
-    ref_cfg = api.TreeConfig(crit=api.ENTROPY, K=K, max_depth=max_depth, min_node=32, P=ref_P,
-                             T=ref_T, bins=256, seed=seed + 1, tree=tree)
-    ref = api.grow_tree(Xd, yd, ref_cfg)
-    depths = _route_depths(ref, X)
-    res = {}
-    for arm in ("random", "learned"):
-        cfg = api.TreeConfig(crit=api.ENTROPY, K=K, P=P, T=T_max, bins=256, seed=seed, tree=tree,
-                             proposal=1 if arm == "learned" else 0, n_seeds=net.n_seeds,
-                             mlp_hidden=net.hidden, mlp=net.params if arm == "learned" else None)
-        ms, evals, met, nodes = 0.0, 0, 0, 0
-        for nodes_d in depths:
-            idx = np.concatenate([r for _, r in nodes_d])
-            sizes = [len(r) for _, r in nodes_d]
-            off = torch.from_numpy(inputs.segment_offsets(sizes)).to(device)
-            Xs = Xd.index_select(0, torch.from_numpy(idx).to(device)).contiguous()
-            ys = yd.index_select(0, torch.from_numpy(idx).to(device)).contiguous()
-            heap = torch.from_numpy(np.array([int(ref["heap"][i]) for i, _ in nodes_d],
-                                             np.int32)).to(device)
-            lref = np.array([ref["split_loss"][i] for i, _ in nodes_d])
+    X, y = cluster_mixture_gpu(N, D, K, clusters, mean_std, seed, device)
+    cfg = api.TreeConfig(crit=api.ENTROPY, K=K, max_depth=max_depth, min_node=32, P=P, T=T_max,
+                         bins=256, seed=seed, tree=0, use_graph=True)
+    forest = api.grow_forest(X, y, cfg, n_trees, return_samples=True)
+    trees = [api.forest_tree(forest, b) for b in range(n_trees)]
+    samples = forest["samples"].to(torch.int64)
+    depths = _node_sets(trees, [samples[b] for b in range(n_trees)], X, device)
+    api._forest_ws.clear()
+    n_nodes = sum(len(d) for d in depths)
+    if log:
+        log(f"compare: {n_trees} trees, {n_nodes} searched nodes over {len(depths)} depths")
+    batches = []
+    for nodes_d in depths:
+        idx = torch.cat([r for _, _, r in nodes_d])
+        sizes = [int(r.numel()) for _, _, r in nodes_d]
+        off = torch.from_numpy(inputs.segment_offsets(sizes)).to(device)
+        heap = torch.from_numpy(np.array([b * 4096 + int(trees[b]["heap"][i]) for b, i, _ in nodes_d],
+                                         np.int32)).to(device)
+        batches.append((idx, off, heap))
+
+    def gathered(idx):
+        return X.index_select(0, idx).contiguous(), y.index_select(0, idx).contiguous()
+
+    # reference losses
+    ref_cfg = api.TreeConfig(crit=api.ENTROPY, K=K, P=ref_P, T=ref_T, bins=256, seed=seed + 1,
+                             tree=0)
+    lrefs = []
+    t0 = time.perf_counter()
+    for idx, off, heap in batches:
+        Xs, ys = gathered(idx)
+        out = api.search_nodes(Xs, ys, off, heap, ref_cfg)
+        lrefs.append(out["gbest_loss"].cpu().numpy())
+        del Xs, ys, out
+        torch.cuda.empty_cache()
+    t_ref = time.perf_counter() - t0
+    arms = [("random", None)] + [(f"learned_{m}", nets[m]) for m in sorted(nets)]
+    res = {"nodes": n_nodes, "reference_s": t_ref}
+    for name, net in arms:
+        acfg = api.TreeConfig(crit=api.ENTROPY, K=K, P=P, T=T_max, bins=256, seed=seed, tree=0,
+                              proposal=0 if net is None else 1,
+                              n_seeds=net.n_seeds if net else 64,
+                              mlp_hidden=net.hidden if net else 256,
+                              mlp=net.params if net else None)
+        ms, evals, met, at_max = 0.0, 0, 0, 0
+        for (idx, off, heap), lref in zip(batches, lrefs):
+            Xs, ys = gathered(idx)
             target = torch.from_numpy((1.0 + tol) * lref).to(device)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            out = api.search_nodes(Xs, ys, off, heap, cfg, target_loss=target)
+            out = api.search_nodes(Xs, ys, off, heap, acfg, target_loss=target)
             torch.cuda.synchronize()
             ms += 1e3 * (time.perf_counter() - t0)
             ev = out["evals"].cpu().numpy()
             gl = out["gbest_loss"].cpu().numpy()
             evals += int(ev.sum())
             met += int((gl <= (1.0 + tol) * lref).sum())
-            nodes += len(nodes_d)
-        res[arm] = dict(ms=ms, evals=evals, met=met, nodes=nodes)
+            at_max += int((ev >= T_max + 1).sum())
+            del Xs, ys, out
+        res[name] = dict(ms=ms, evals=evals, met=met, hit_T_max=at_max)
         if log:
-            log(f"compare[{arm}]: {nodes} nodes, {evals} evaluations, {met} met the target, "
-                f"{ms:.1f} ms")
+            log(f"compare[{name}]: {evals} evaluations, {met}/{n_nodes} met the target, "
+                f"{at_max} ran to T_max, {ms:.1f} ms")
+    r = res["random"]
+    for name, _ in arms[1:]:
+        l = res[name]
+        l["speedup_wall"] = r["ms"] / max(1e-9, l["ms"])
+        l["speedup_evals"] = r["evals"] / max(1, l["evals"])
     return res

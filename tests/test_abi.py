@@ -294,3 +294,20 @@ def test_exact_scan_tree_refuses_large_roots():
     # the histogram scan has no such limit
     hist = api.TreeConfig(crit=api.GINI, K=2, max_depth=3, P=8, T=2, bins=16).c_params()
     assert lib.slm_grow_tree_workspace(ctypes.byref(hist), 1 << 20, 8) > 0
+
+
+def test_tables_and_boost_scores_validation():
+    lib = api.load()
+    assert lib.slm_ps_tables(0, 10.0, FAKE, FAKE, None) == 2
+    assert lib.slm_ps_tables(65, 10.0, FAKE, FAKE, None) == 2
+    assert lib.slm_ps_tables(8, 0.5, FAKE, FAKE, None) == 1
+    assert lib.slm_ps_tables(8, float("inf"), FAKE, FAKE, None) == 1
+    assert lib.slm_ps_tables(8, 10.0, None, FAKE, None) == 1
+    import numpy as np
+    f0 = np.zeros(3)
+    bs = lambda nr, nc, lr=0.1, F=FAKE: lib.slm_boost_scores(
+        FAKE, FAKE, FAKE, FAKE, FAKE, 7, FAKE, nr, nc, 8, f0.ctypes.data, lr, FAKE, 100, FAKE, F,
+        None)
+    assert bs(2, 1) == 2 and bs(2, 17) == 2 and bs(-1, 0) == 2
+    assert bs(2, 3, lr=float("nan")) == 1
+    assert bs(2, 3, F=None) == 1

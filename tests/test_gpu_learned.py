@@ -1,26 +1,26 @@
 """End to end on the GPU: harvest (statistics, global best) pairs from plain-PSO
 trees, train the proposal network with the library's kernels, and compare
-learned and random swarm starts on held-out nodes at equal loss targets.
+random starts (Sec. III-A) with hybrid learned starts (M seeds, the rest
+random) on the nodes of held-out trees at equal loss targets.
 
-What is asserted: the pairs are well formed, training lowers the loss and
-fits its training pairs better than the untrained network, the learned start
-is bit-reproducible, and the learned search meets the loss target on a share
-of nodes comparable to the random one.  How much the learned start saves is
-printed (it depends on how much of a node's best direction its class
-statistics determine; the comparison is measured, not assumed).
+The workload here has one Gaussian cluster per class, so a node's best
+direction is largely determined by its class means, which the statistics
+carry: on it the learned start is asserted to reach the target loss in fewer
+evaluations than the random start and to meet it on at least as many nodes.
+(On the benchmark's four-cluster classes it does not gain: the measured
+numbers are reported by the benchmark.)  Also asserted: the pairs are well
+formed, training lowers the loss and fits its pairs better than the untrained
+network, and the learned search is bit-reproducible.
 """
 import numpy as np
 import pytest
-import torch
 
-from paper_2208_07023_amd import inputs
 from paper_2208_07023_amd import proposal as PL
 
 pytestmark = pytest.mark.gpu
 
 
 def test_harvest_train_compare_small(gpu_lib):
-    api = gpu_lib
     D, K, M, H = 16, 3, 16, 64
     S, G, T = PL.harvest(24, D, K, 4000, 30000, seed=3, P=32, T=20, max_depth=5, clusters=1)
     n = S.shape[0]
@@ -35,13 +35,14 @@ def test_harvest_train_compare_small(gpu_lib):
     print(f"mean best cos^2 on the training pairs: untrained {c0:.3f}, trained {c1:.3f}")
     assert c1 > c0
 
-    X, y = inputs.cluster_mixture(30000, D, K, clusters_per_class=1, mean_std=0.6, seed=99)
-    res = PL.compare_starts(net, X, y, K, ref_P=128, ref_T=60, P=M, T_max=30, max_depth=5)
-    r, l = res["random"], res["learned"]
-    print(f"random: {r}\nlearned: {l}\nevaluations random/learned = "
-          f"{r['evals'] / max(1, l['evals']):.2f}, wall = {r['ms'] / max(1e-9, l['ms']):.2f}")
-    assert r["nodes"] == l["nodes"] > 0
-    assert l["met"] >= 0.5 * r["met"]
+    kw = dict(ref_P=128, ref_T=60, P=2 * M, T_max=30, max_depth=5, seed=99, mean_std=0.6,
+              clusters=1)
+    res = PL.compare_forest({M: net}, 30000, D, K, 2, **kw)
+    r, l = res["random"], res[f"learned_{M}"]
+    print(f"nodes {res['nodes']}\nrandom: {r}\nlearned: {l}")
+    assert res["nodes"] > 0
+    assert l["met"] >= r["met"]
+    assert l["evals"] < r["evals"]
     # the learned start is deterministic
-    res2 = PL.compare_starts(net, X, y, K, ref_P=128, ref_T=60, P=M, T_max=30, max_depth=5)
-    assert res2["learned"]["evals"] == l["evals"] and res2["learned"]["met"] == l["met"]
+    res2 = PL.compare_forest({M: net}, 30000, D, K, 2, **kw)
+    assert res2[f"learned_{M}"]["evals"] == l["evals"] and res2[f"learned_{M}"]["met"] == l["met"]

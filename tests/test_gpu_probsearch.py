@@ -26,9 +26,12 @@ def test_candidates_match_oracle(gpu_lib, R, alpha0, D):
     P = 40
     rng = np.random.default_rng(R + D)
     ranks = np.stack([rng.permutation(D)[:R] for _ in nodes]).astype(np.int32)
+    # the library builds the Eq. (8) tables on the device (its exp may differ
+    # from the host's by an ulp); the coefficient ranges must agree exactly
     pd, amax = api.ps_tables(R, alpha0)
     pd_ref, am_ref = PS.tables(R, alpha0)
-    assert np.array_equal(pd.cpu().numpy(), pd_ref) and np.array_equal(amax.cpu().numpy(), am_ref)
+    assert np.array_equal(amax.cpu().numpy(), am_ref)
+    assert np.all(np.abs(pd.cpu().numpy() - pd_ref) <= 2 * np.spacing(pd_ref))
     sw = api.pso_alloc(len(nodes), P, D, nodes)
     for t in (0, 3):
         api.ps_candidates(sw, _t(ranks), pd, amax, seed=7, tree=2, t=t)
