@@ -130,6 +130,32 @@ slm_status slm_split_scan(const float *Z, int32_t z_layout, const float *zmin, c
                           void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * slm_split_scan_noalloc -- slm_split_scan's histogram scan for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and outputs, with the
+ * accumulator in the library's own per-GPU scratch array instead of a caller
+ * workspace.  It allocates nothing and calls no allocating routine.
+ *
+ * Arguments as slm_split_scan without workspace / ws_bytes; bins in 2..256
+ * (the exact scan needs no scratch: bins = 0 returns SLM_E_UNSUPPORTED).
+ * The scratch holds slm_split_scan_noalloc_max_bytes() bytes (128 MiB) per
+ * GPU, kept until the process ends; a scan whose slm_split_scan_workspace
+ * exceeds it returns SLM_E_NOMEM before any launch.  The array is cleared on
+ * the call's stream at the first call on a device (and after a failed call);
+ * every completed scan leaves it zero.  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (different streams, threads or
+ * processes' graphs replayed concurrently) race and give wrong results.
+ * Asynchronous.
+ * ------------------------------------------------------------------------ */
+size_t slm_split_scan_noalloc_max_bytes(void);
+slm_status slm_split_scan_noalloc(const float *Z, int32_t z_layout, const float *zmin,
+                                  const float *zmax, const void *target, int32_t t_dtype,
+                                  int32_t K, int64_t N, const int64_t *row_off, int32_t n_nodes,
+                                  int32_t P, int32_t bins, int32_t crit, int32_t *best_split,
+                                  double *best_loss, float *threshold, uint32_t *hist_out,
+                                  double *sums_out, void *stream);
+
+/* ------------------------------------------------------------------------
  * slm_evaluate -- one swarm evaluation fused: the projected features of
  * slm_project (Sec. II-A, Eq. (1)) binned and scanned as by slm_split_scan
  * (histogram mode, Sec. II-A Eqs. (3)-(4), Sec. III-B) without ever storing Z.

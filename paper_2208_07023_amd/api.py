@@ -73,6 +73,9 @@ _SIGS = {
                                            _I32, _VP], _I32),
     "slm_dft_select_workspace": ([_I64, _I32, _I32, _I32, _I32, _I32], _SZ),
     "slm_ps_tables": ([_I32, _D, _VP, _VP, _VP], _I32),
+    "slm_split_scan_noalloc_max_bytes": ([], _SZ),
+    "slm_split_scan_noalloc": ([_VP, _I32, _VP, _VP, _VP, _I32, _I32, _I64, _VP, _I32, _I32, _I32,
+                                _I32, _VP, _VP, _VP, _VP, _VP, _VP], _I32),
     "slm_boost_scores": ([_VP, _VP, _VP, _VP, _VP, _I32, _VP, _I32, _I32, _I32, _VP, _D, _VP, _I64,
                           _VP, _VP, _VP], _I32),
     "slm_ps_candidates": ([_VP, _VP, _I32, _VP, _I32, _I32, _I32, _VP, _I32, _VP, _VP, _U64, _U32,

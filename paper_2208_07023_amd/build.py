@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libslm.so")
 
 SOURCES = ["k_project.hip", "k_scan.hip", "k_pso.hip", "k_screen.hip", "k_mlp.hip", "k_tree.hip", "k_dft.hip",
-           "k_forest.hip", "slm_api.cpp"]
+           "k_forest.hip", "slm_api.cpp", "slm_noalloc.cpp"]
 HEADERS = ["slm_internal.hpp", "philox.hpp"]
 
 FLAGS = [

@@ -67,6 +67,13 @@ __global__ void k_zero_words(uint32_t *p, int64_t n) {
 
 }  // namespace
 
+slm_status launch_zero_words(uint32_t *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return SLM_OK;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  SLM_LAUNCHED();
+  return SLM_OK;
+}
+
 size_t dft_workspace_bytes(int64_t N, int n_nodes, int D, int bins, int K, int crit) {
   const size_t nd = (size_t)std::max(0, n_nodes) * std::max(0, D);
   const size_t scan = bins ? scan_workspace_bytes(N, n_nodes, D, bins, K, crit) : 0;

@@ -177,6 +177,8 @@ struct ProjectArgs {
 };
 slm_status launch_project(const ProjectArgs &a, hipStream_t s);
 slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s);
+// zeroes n 32-bit words with a fill kernel (no memset node in captured graphs)
+slm_status launch_zero_words(uint32_t *p, int64_t n, hipStream_t s);
 // raises the dynamic-LDS limit of the streaming projection kernels
 void prepare_project_kernels(int lds_max);
 
