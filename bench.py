@@ -151,9 +151,9 @@ def headline(api, args, dev):
     ss_p, ssr_p = int(prof["sample_splits"][0]), int(prof["sample_splits"][1])
     rows_p = ss_p / cfg.P                      # row-evaluations of the tree
     k = cfg.rescore_k
-    # algorithmic bytes: screened projection writes 4 B of Z per sample-split
-    # and reads each row's 2 D bytes once per 128-particle tile; the scan
-    # reads 4 B of Z per sample-split and 4 B of label per row and tile
+    # algorithmic bytes: the screened projection writes 4 B of Z per
+    # sample-split and reads each row's 2 D bytes of X once; the scan reads
+    # 4 B of Z per sample-split and each row's 4-byte label once
     proj_bytes = 4.0 * ss_p + rows_p * 2 * D
     proj_flops = 2.0 * D * ss_p
     scan_bytes = 4.0 * ss_p + 4.0 * rows_p
@@ -163,12 +163,13 @@ def headline(api, args, dev):
     proj_s, scan_s, rp_s, rs_s = (tm[i] * 1e-3 for i in (3, 4, 8, 9))
     proj_gbs = proj_bytes / proj_s / 1e9
     kernels = {
-        "k_project_bf16": {"launches": n_proj, "avg_us": 1e6 * proj_s / n_proj,
-                           "bytes_per_launch": proj_bytes / n_proj, "GB/s": proj_gbs,
-                           "frac_hbm": proj_gbs / HBM_PEAK_GBS,
-                           "TFLOP/s": proj_flops / proj_s / 1e12,
-                           "frac_bf16_mfma": proj_flops / proj_s / 1e12 / BF16_PEAK_TFLOPS,
-                           "traffic": measured_traffic("k_project_bf16")},
+        "project_screened_bf16": {"kernel": "k_project_stream (BF16 MFMA)", "launches": n_proj,
+                                  "avg_us": 1e6 * proj_s / n_proj,
+                                  "bytes_per_launch": proj_bytes / n_proj, "GB/s": proj_gbs,
+                                  "frac_hbm": proj_gbs / HBM_PEAK_GBS,
+                                  "TFLOP/s": proj_flops / proj_s / 1e12,
+                                  "frac_bf16_mfma": proj_flops / proj_s / 1e12 / BF16_PEAK_TFLOPS,
+                                  "traffic": measured_traffic("k_project_stream_bf16")},
         "scan_screened": {"launches": n_scan, "avg_us": 1e6 * scan_s / n_scan,
                           "bytes_per_launch": scan_bytes / n_scan,
                           "GB/s": scan_bytes / scan_s / 1e9,
@@ -180,9 +181,10 @@ def headline(api, args, dev):
                          "GB/s": rscan_bytes / rs_s / 1e9},
         "swarm_steps_ms": tm[5], "partitions_ms": tm[2], "tree_ms_instrumented": tm[0],
     }
-    roof = {"bound": "hbm", "kernel": "k_project_bf16", "achieved": proj_gbs,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": proj_gbs / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_project_bf16"),
+    roof = {"bound": "hbm", "kernel": "k_project_stream<BF16> (screened projection)",
+            "achieved": proj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": proj_gbs / HBM_PEAK_GBS,
+            "traffic": measured_traffic("k_project_stream_bf16"),
             "bytes_per_launch": proj_bytes / n_proj,
             "note": "algorithmic bytes: 4 B of FP32 Z written per sample-split + 2 D B of "
                     "bfloat16 X read per row; Z is FP32, so the projection is HBM-bound "
@@ -347,6 +349,93 @@ def single_node_line(api, dev, reps=50):
             "us_per_evaluation": (out[20][0] - out[0][0]) / 20.0,
             "us_per_depth1_tree_call": out[20][1],
             "sample_splits_per_s": 21 * 1000 * 32 / (out[20][0] * 1e-6)}
+
+
+def tune_plans(api, path, dev):
+    """Measure the launch plans of one tree of each workload (the first
+    evaluation of every depth times its shapes' candidate plans) into path."""
+    import torch
+
+    from paper_2208_07023_amd import inputs
+    api.autotune(2, path)
+    out = {}
+    _, _, Xd, yd = screening_data(dev)
+    cfg = screening_config(api)
+    t0 = time.perf_counter()
+    api.grow_tree(Xd, yd, cfg)
+    out["screening_s"] = time.perf_counter() - t0
+    del Xd, yd
+    api._tree_ws.clear()
+    torch.cuda.empty_cache()
+    X, y = inputs.cluster_mixture(100_000, 64, 3, clusters_per_class=4, mean_std=2.0, seed=0)
+    cfg = api.TreeConfig(crit=api.ENTROPY, K=3, max_depth=8, min_node=32, P=256, T=50, bins=256,
+                         seed=0, use_graph=True)
+    t0 = time.perf_counter()
+    api.grow_tree(torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev), cfg)
+    out["plain_s"] = time.perf_counter() - t0
+    X, y = inputs.abs_direction_regression(1_000_000, 128, seed=0)
+    cfg = api.TreeConfig(crit=api.MSE, K=0, max_depth=10, min_node=32, P=512, T=40, bins=256,
+                         seed=0, use_graph=True)
+    t0 = time.perf_counter()
+    api.grow_tree(torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev), cfg)
+    out["regression_s"] = time.perf_counter() - t0
+    out["plans"] = api.autotune(1, path)
+    out["path"] = path
+    log(f"tuned plans: {out}")
+    return out
+
+
+def root_evals(api, which, reps, dev):
+    """`reps` root evaluations of a workload through the C ABI, each timed
+    with HIP events on the launch stream: the screened projection (BF16) and
+    scan, the FP32 re-scoring of the best 32 (screening tree), or the FP32
+    projection and scan (plain and regression trees)."""
+    import torch
+
+    from paper_2208_07023_amd import inputs
+    if which == "screening":
+        _, _, Xd, yd = screening_data(dev)
+        K, P, crit, wdt = 10, 1024, api.GINI, torch.bfloat16
+    elif which == "plain":
+        X, y = inputs.cluster_mixture(100_000, 64, 3, clusters_per_class=4, mean_std=2.0, seed=0)
+        Xd, yd = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
+        K, P, crit, wdt = 3, 256, api.ENTROPY, torch.float32
+    else:
+        X, y = inputs.abs_direction_regression(1_000_000, 128, seed=0)
+        Xd, yd = torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev)
+        K, P, crit, wdt = 0, 512, api.MSE, torch.float32
+    N, D = Xd.shape
+    off = torch.tensor([0, N], dtype=torch.int64, device=dev)
+    sw = api.pso_alloc(1, P, D, node_id=[0], w_dtype=wdt)
+    api.pso_init(sw, seed=0, tree=0)
+    st = torch.cuda.current_stream()
+    times = {"project": [], "scan": [], "rescore_project": [], "rescore_scan": []}
+
+    def timed(key, fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        r = fn()
+        e1.record(st)
+        times[key].append((e0, e1))
+        return r
+
+    for _ in range(reps):
+        Z, zmin, zmax = timed("project", lambda: api.project(Xd, sw.W, off, P, tiled=True))
+        out = timed("scan", lambda: api.split_scan(Z, zmin, zmax, yd, K, off, P, 256, crit))
+        if which == "screening":
+            sel = api.screen_select(out["loss"], 1, P, 32)
+            Wk = api.screen_gather(sw.x, sel, 1, P, 32)
+            Zr, rmin, rmax = timed("rescore_project", lambda: api.project(Xd, Wk, off, 32,
+                                                                          tiled=True))
+            timed("rescore_scan", lambda: api.split_scan(Zr, rmin, rmax, yd, K, off, 32, 256,
+                                                         crit))
+        del Z
+    torch.cuda.synchronize()
+    res = {"workload": which, "N": N, "D": D, "P": P, "reps": reps}
+    for k, v in times.items():
+        if v:
+            res[k + "_ms"] = [round(a.elapsed_time(b), 4) for a, b in v]
+    return res
 
 
 # ------------------------------------------------------------------ extras
@@ -526,47 +615,58 @@ def learned_vs_plain(api, dev, full=False):
 
 
 # ------------------------------------------------------------------ oracle on the host
-def _oracle_chunk(args):
-    """Worker: oracle scans of a block of particles (one BLAS thread)."""
-    Xs, y, W, bins, crit, K = args
+_ORACLE_JOB = None
+
+
+def _oracle_init(Xs, y, W, bins, crit, K):
+    """Worker set-up: the sample rows, labels and directions, kept per process."""
+    global _ORACLE_JOB
+    _ORACLE_JOB = (Xs, y, W, bins, crit, K)
+
+
+def _oracle_chunk(lo_hi):
+    """Oracle scans of particles lo .. hi-1 of the job (one BLAS thread):
+    FP64 projection, float32 rounding, one histogram scan per particle."""
     from threadpoolctl import threadpool_limits
 
     from oracle import split as OS
+    Xs, y, W, bins, crit, K = _ORACLE_JOB
+    lo, hi = lo_hi
     with threadpool_limits(limits=1):
-        Z = OS.project(Xs, W).astype(np.float32)
-        for p in range(W.shape[0]):
+        Z = OS.project(Xs, W[lo:hi]).astype(np.float32)
+        for p in range(hi - lo):
             OS.scan_hist(Z[:, p], y, bins, crit, K)
-    return W.shape[0]
+    return hi - lo
 
 
 def _oracle_rate(Xs, y, W, bins, crit, K, workers, seconds):
-    """Oracle sample-splits/s on rows Xs over particle blocks of W, on
+    """Oracle sample-splits/s on rows Xs over blocks of the directions W, on
     `workers` processes (1: this process), for about `seconds`."""
     import multiprocessing as mp
-    n = Xs.shape[0]
-    blk = max(1, min(W.shape[0] // max(1, workers), 8))
-    jobs, done, t0 = [], 0, time.perf_counter()
+    n, P = Xs.shape[0], W.shape[0]
+    blk = 4
+    blocks = [(lo, min(P, lo + blk)) for lo in range(0, P, blk)]
+    done = 0
     if workers == 1:
+        _oracle_init(Xs, y, W, bins, crit, K)
+        t0 = time.perf_counter()
         i = 0
         while time.perf_counter() - t0 < seconds:
-            w = W[(i * blk) % W.shape[0]:][:blk]
-            done += _oracle_chunk((Xs, y, w, bins, crit, K))
+            done += _oracle_chunk(blocks[i % len(blocks)])
             i += 1
         dt = time.perf_counter() - t0
         return done * n / dt, dt, done
     ctx = mp.get_context("spawn")
-    with ctx.Pool(workers) as pool:
+    with ctx.Pool(workers, initializer=_oracle_init, initargs=(Xs, y, W, bins, crit, K)) as pool:
+        pool.map(_oracle_chunk, [(0, 1)] * workers)          # workers started and warm
         t0 = time.perf_counter()
-        pending = [pool.apply_async(_oracle_chunk, ((Xs, y, W[(i * blk) % W.shape[0]:][:blk],
-                                                     bins, crit, K),))
+        pending = [pool.apply_async(_oracle_chunk, (blocks[i % len(blocks)],))
                    for i in range(2 * workers)]
         i = 2 * workers
         while pending:
-            r = pending.pop(0)
-            done += r.get()
+            done += pending.pop(0).get()
             if time.perf_counter() - t0 < seconds:
-                pending.append(pool.apply_async(_oracle_chunk, ((Xs, y, W[(i * blk) % W.shape[0]:][:blk],
-                                                                 bins, crit, K),)))
+                pending.append(pool.apply_async(_oracle_chunk, (blocks[i % len(blocks)],)))
                 i += 1
         dt = time.perf_counter() - t0
     return done * n / dt, dt, done
@@ -584,7 +684,7 @@ def cpu_baseline(screen_data, plain, gpu, seconds=10.0):
     from paper_2208_07023_amd import inputs
     hi = host_info()
     bits, y = screen_data
-    n_s = 200_000
+    n_s = 100_000
     Xs = OSC.bf16_round(inputs.bf16_bits_to_f32(bits[:n_s]))
     Ws = OSC.bf16_round(inputs.random_unit_rows(1024, 256, seed=123).astype(np.float32))
     ys = y[:n_s]
@@ -613,6 +713,21 @@ def cpu_baseline(screen_data, plain, gpu, seconds=10.0):
                          "extrapolated_cpu_s_per_tree": ss / rate,
                          "cores": hi["usable"] if name == "screening_tree" else 1}
     out["extrapolated"] = est
+    # single node (N = 1000, D = 8, P = 32, T = 20, exact scan, Gini): the
+    # oracle's whole search timed directly, one thread
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pso as OP
+    from oracle import tree as OT
+    Xc, yc, _ = inputs.two_class_gaussian(1000, 8, seed=0)
+    prm = OT.TreeParams(crit=OS.GINI, K=2, P=32, T=20, bins=0)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        OP.run_pso(OT.evaluate_node(Xc.astype(np.float64), yc, prm), 32, 8, 20, 0.7, 1.5, 1.5,
+                   0, 0, 0)
+        dt = time.perf_counter() - t0
+    out["single_node"] = {"ms_per_pso_21_evals": 1e3 * dt, "cores": 1,
+                          "sample_splits_per_s": 21 * 1000 * 32 / dt}
     return out
 
 
@@ -629,6 +744,17 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the top-n DFT, probabilistic-search, forest and boosting legs")
     ap.add_argument("--only-headline", action="store_true")
+    ap.add_argument("--root-evals", choices=["screening", "plain", "regression"], default=None,
+                    help="only run --reps root evaluations (projection + histogram scan, and "
+                         "the re-scoring for the screening tree) of one workload and exit: the "
+                         "launches rocprofv3 counter passes read")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--plans", choices=["cached", "rules"], default="cached",
+                    help="launch plans of the tree builds: the measured plans cached beside "
+                         "the library (default) or the kernels' fitted rules")
+    ap.add_argument("--tune-plans", default=None, metavar="PATH",
+                    help="only measure the launch plans of the screening, plain and regression "
+                         "trees (one tree each) into PATH and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
                          "(reference kernel for scaling HBM byte counters) and exit")
@@ -654,6 +780,14 @@ def main():
     from paper_2208_07023_amd import api
     api.load()
     dev = "cuda"
+    if args.tune_plans:
+        print(json.dumps(tune_plans(api, args.tune_plans, dev)), flush=True)
+        return
+    n_plans = api.autotune(0 if args.plans == "rules" else 1)
+    log(f"launch plans: {args.plans} ({n_plans} cached)")
+    if args.root_evals:
+        print(json.dumps(root_evals(api, args.root_evals, args.reps, dev)), flush=True)
+        return
     head, screen_data = headline(api, args, dev)
     out = {
         "metric": METRIC,
@@ -673,6 +807,7 @@ def main():
         "sample_splits_rescored_per_s": head["sample_splits_rescored_per_s"],
         "kernels": head["kernels"],
         "screening_gpu": head["screening_gpu"],
+        "launch_plans": {"kind": args.plans, "cached_plans": n_plans},
     }
     gpu_ss = {"screening": head["config"]["sample_splits_per_tree"]}
     plain = None

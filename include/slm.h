@@ -483,6 +483,30 @@ slm_status slm_grow_tree(const void *X, int32_t x_dtype, int64_t N, int32_t D,
                          slm_tree_out *out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * slm_autotune_set -- launch plans of the tree builds (Alg. 2's per-depth
+ * batches): which particle tile and chunk length the histogram scan uses,
+ * and how many particle blocks per wave and which work-group order the
+ * projection uses, per shape class (kernel, rows, nodes, P, D, bins,
+ * classes, criterion; keyed by the GPU architecture).  A plan changes no
+ * result of a classification tree (integer counts, the same MFMA sequence
+ * per element); a regression scan's FP64 bin sums may change in the last
+ * bits with the chunking.
+ *   mode 0: the kernels' fitted rules only;
+ *   mode 1 (the default): measured plans where the cache holds one, else the
+ *     rules; the cache is read from `path`, or (NULL) from
+ *     plans_<arch>.json beside the library;
+ *   mode 2: as 1, and every depth of a tree build whose launch shapes have no
+ *     plan first times each shape's candidate plans with HIP events on the
+ *     build's stream (one eager evaluation, not captured) and keeps the
+ *     fastest; the cache is then written to `path` (required).
+ * Changing the plans makes the next tree builds capture new graphs.  Not
+ * thread-safe with concurrent tree builds.  slm_autotune_plans returns the
+ * number of cached plans.
+ * ------------------------------------------------------------------------ */
+slm_status slm_autotune_set(int32_t mode, const char *path);
+int32_t slm_autotune_plans(void);
+
+/* ------------------------------------------------------------------------
  * slm_predict -- route rows through a tree (Sec. II-A, Eqs. (3)-(4)):
  * right iff float32(w . x) >= thr, the dot product accumulated in FP32 in
  * dimension order.  Tree arrays are device copies of slm_tree_out's w, thr,

@@ -73,6 +73,8 @@ _SIGS = {
                                            _I32, _VP], _I32),
     "slm_dft_select_workspace": ([_I64, _I32, _I32, _I32, _I32, _I32], _SZ),
     "slm_ps_tables": ([_I32, _D, _VP, _VP, _VP], _I32),
+    "slm_autotune_set": ([_I32, ctypes.c_char_p], _I32),
+    "slm_autotune_plans": ([], _I32),
     "slm_split_scan_noalloc_max_bytes": ([], _SZ),
     "slm_split_scan_noalloc": ([_VP, _I32, _VP, _VP, _VP, _I32, _I32, _I64, _VP, _I32, _I32, _I32,
                                 _I32, _VP, _VP, _VP, _VP, _VP, _VP], _I32),
@@ -488,6 +490,17 @@ def screen_merge(sel, loss_r, split_r, thr_r, n_nodes: int, P: int, k: int, loss
                                  _p(loss), _p(split), _p(thr), _p(gloss), _stream()),
            "slm_screen_merge")
     return gloss
+
+
+# ------------------------------------------------------------------ launch plans
+def autotune(mode: int, path: str = None):
+    """Launch plans of tree builds (slm_autotune_set): 0 = fitted rules,
+    1 = cached measured plans (from path, or the file beside the library),
+    2 = also measure missing shapes during tree builds and write them to
+    path.  Returns the number of cached plans."""
+    load()
+    _check(_lib.slm_autotune_set(int(mode), path.encode() if path else None), "slm_autotune_set")
+    return int(_lib.slm_autotune_plans())
 
 
 # ------------------------------------------------------------------ tree

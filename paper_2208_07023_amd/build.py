@@ -19,7 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libslm.so")
 
 SOURCES = ["k_project.hip", "k_scan.hip", "k_pso.hip", "k_screen.hip", "k_mlp.hip", "k_tree.hip", "k_dft.hip",
-           "k_forest.hip", "slm_api.cpp", "slm_noalloc.cpp"]
+           "k_forest.hip", "slm_api.cpp", "slm_noalloc.cpp",
+           "autotune.cpp"]
 HEADERS = ["slm_internal.hpp", "philox.hpp"]
 
 FLAGS = [
@@ -57,7 +58,7 @@ def build(jobs: int = 8) -> str:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", *objs,
-           "-o", tmp]
+           "-ldl", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

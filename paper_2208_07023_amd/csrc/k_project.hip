@@ -13,6 +13,8 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <string>
+#include <vector>
 
 namespace slm {
 namespace {
@@ -853,27 +855,49 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
     for (int q = 0; q < 16; ++q)
       A[q] = load_group<O::XBYTES, VEC, false>(a.X, row, D, e0 + q * (16 / O::XBYTES));
   };
+  // The W fragments of step group q + 1 are read from LDS while the MFMAs of
+  // group q run (two register sets), so the matrix core does not wait for
+  // the LDS latency before every MFMA.
   auto mma_chunk = [&](int c, const uint4 (&A)[16], f32x16 (&acc)[FN]) {
     const uint4 *wc = wl + (size_t)c * FN * G * 64 + lane;
     if constexpr (MK == MK_BB) {
+      uint4 b[2][FN];
 #pragma unroll
-      for (int q = 0; q < 16; ++q)
+      for (int f = 0; f < FN; ++f) b[0][f] = wc[(f * G) * 64];
 #pragma unroll
-        for (int f = 0; f < FN; ++f) {
-          const uint4 b = wc[(f * G + q) * 64];
-          acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A[q]),
-                                                           __builtin_bit_cast(bf16x8, b), acc[f],
-                                                           0, 0, 0);
+      for (int q = 0; q < 16; ++q) {
+        if (q + 1 < 16) {
+#pragma unroll
+          for (int f = 0; f < FN; ++f) b[(q + 1) & 1][f] = wc[(f * G + q + 1) * 64];
         }
+#pragma unroll
+        for (int f = 0; f < FN; ++f)
+          acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A[q]),
+                                                           __builtin_bit_cast(bf16x8, b[q & 1][f]),
+                                                           acc[f], 0, 0, 0);
+      }
     } else if constexpr (MK == MK_XB) {
       // A[q] holds 8 bfloat16 (steps 8q .. 8q+7), W groups 2q, 2q+1 the
       // matching 8 floats
+      uint4 b[2][FN][2];
+#pragma unroll
+      for (int f = 0; f < FN; ++f) {
+        b[0][f][0] = wc[(f * G) * 64];
+        b[0][f][1] = wc[(f * G + 1) * 64];
+      }
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
+        if (q + 1 < 16) {
+#pragma unroll
+          for (int f = 0; f < FN; ++f) {
+            b[(q + 1) & 1][f][0] = wc[(f * G + 2 * q + 2) * 64];
+            b[(q + 1) & 1][f][1] = wc[(f * G + 2 * q + 3) * 64];
+          }
+        }
         const uint32_t w4[4] = {A[q].x, A[q].y, A[q].z, A[q].w};
 #pragma unroll
         for (int f = 0; f < FN; ++f) {
-          const uint4 b0 = wc[(f * G + 2 * q) * 64], b1 = wc[(f * G + 2 * q + 1) * 64];
+          const uint4 b0 = b[q & 1][f][0], b1 = b[q & 1][f][1];
           const uint32_t bw[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
@@ -883,13 +907,20 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
         }
       }
     } else {
+      uint4 b[2][FN];
+#pragma unroll
+      for (int f = 0; f < FN; ++f) b[0][f] = wc[(f * G) * 64];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
+        if (q + 1 < 16) {
+#pragma unroll
+          for (int f = 0; f < FN; ++f) b[(q + 1) & 1][f] = wc[(f * G + q + 1) * 64];
+        }
         const uint32_t w4[4] = {A[q].x, A[q].y, A[q].z, A[q].w};
 #pragma unroll
         for (int f = 0; f < FN; ++f) {
-          const uint4 b = wc[(f * G + q) * 64];
-          const uint32_t bw[4] = {b.x, b.y, b.z, b.w};
+          const uint4 bq = b[q & 1][f];
+          const uint32_t bw[4] = {bq.x, bq.y, bq.z, bq.w};
 #pragma unroll
           for (int e = 0; e < 4; ++e)
             acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(w4[e]),
@@ -1003,8 +1034,10 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
   }
 }
 
+// want_xcd: 1 = keep a row run's particle tiles on one XCD when the grid
+// allows (the rule), 0 = plain order (an autotuned alternative)
 template <int MK, int FN, bool VEC>
-slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s) {
+slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s, int want_xcd = 1) {
   constexpr int PT = 32 * FN;
   const int n_pt = (a.P + PT - 1) / PT;
   const int cus = num_cus_proj();
@@ -1012,7 +1045,7 @@ slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s) {
   // share the CUs, each tile's rows split into runs of whole sub-tiles
   int64_t bpp = std::max<int64_t>(1, std::min<int64_t>((a.N + SR - 1) / SR, cus / n_pt));
   int xcd = 0;
-  if (bpp >= 8 && n_pt * bpp >= 64) {
+  if (want_xcd && bpp >= 8 && n_pt * bpp >= 64) {
     bpp = bpp / 8 * 8;
     xcd = 1;
   }
@@ -1034,6 +1067,25 @@ slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s) {
 
 constexpr size_t STREAM_LDS_MAX = 128 * 1024;
 
+// Shape class of a projection launch in the plan cache: the kernel (the
+// streaming kernel's operand kind 0..2, or 3 for the short kernel), D, P and
+// the data rows.
+std::string proj_key(int kind, const ProjectArgs &a) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "proj/%s/k%d/D%d/P%d/N%lld", device_arch().c_str(), kind, a.D, a.P,
+           (long long)a.N);
+  return buf;
+}
+
+// the autotuner's candidate in flight: (variant, option)
+thread_local const int64_t *g_forced_proj = nullptr;
+
+bool stream_fn_fits(int MK, int FN, const ProjectArgs &a) {
+  return (FN == 1 || (a.P + 31) / 32 >= FN) && stream_lds_bytes(MK, FN, a.D) <= STREAM_LDS_MAX;
+}
+
+// Particle blocks per wave FN (4, 2 or 1: the widest that fits, or the
+// cached / forced plan's) and the work-group order.
 template <int MK>
 slm_status launch_stream(const ProjectArgs &a, hipStream_t s) {
   const size_t xe = MK == MK_FF ? 4 : 2, we = MK == MK_BB ? 2 : 4;
@@ -1041,12 +1093,23 @@ slm_status launch_stream(const ProjectArgs &a, hipStream_t s) {
   const bool vec = (a.D * xe) % 16 == 0 && (a.D * we) % 16 == 0 &&
                    reinterpret_cast<uintptr_t>(a.X) % 16 == 0 &&
                    reinterpret_cast<uintptr_t>(a.W) % 16 == 0;
-  const int blocks = (a.P + 31) / 32;
-  if (blocks >= 4 && stream_lds_bytes(MK, 4, a.D) <= STREAM_LDS_MAX)
-    return vec ? launch_stream_f<MK, 4, true>(a, s) : launch_stream_f<MK, 4, false>(a, s);
-  if (blocks >= 2 && stream_lds_bytes(MK, 2, a.D) <= STREAM_LDS_MAX)
-    return vec ? launch_stream_f<MK, 2, true>(a, s) : launch_stream_f<MK, 2, false>(a, s);
-  return vec ? launch_stream_f<MK, 1, true>(a, s) : launch_stream_f<MK, 1, false>(a, s);
+  int fn = stream_fn_fits(MK, 4, a) ? 4 : stream_fn_fits(MK, 2, a) ? 2 : 1;
+  int xcd = 1;
+  int64_t v0 = 0, v1 = 0;
+  if (g_forced_proj) {
+    v0 = g_forced_proj[0];
+    v1 = g_forced_proj[1];
+  }
+  if ((g_forced_proj || plan_lookup(proj_key(MK, a), &v0, &v1)) &&
+      (v0 == 1 || v0 == 2 || v0 == 4) && stream_fn_fits(MK, (int)v0, a)) {
+    fn = (int)v0;
+    xcd = v1 != 0;
+  }
+  if (fn == 4)
+    return vec ? launch_stream_f<MK, 4, true>(a, s, xcd) : launch_stream_f<MK, 4, false>(a, s, xcd);
+  if (fn == 2)
+    return vec ? launch_stream_f<MK, 2, true>(a, s, xcd) : launch_stream_f<MK, 2, false>(a, s, xcd);
+  return vec ? launch_stream_f<MK, 1, true>(a, s, xcd) : launch_stream_f<MK, 1, false>(a, s, xcd);
 }
 
 // The streaming kernel serves every launch of a given (D, data types) or
@@ -1145,10 +1208,16 @@ slm_status launch_project(const ProjectArgs &a, hipStream_t s) {
     if (a.P > 64) return launch_bf16<128, 128>(a, s);
     return launch_bf16<128, 64>(a, s);
   }
-  // D <= 64: register-resident directions, 256 / 128 / 32 particles per work-group.
+  // D <= 64: register-resident directions, 256 / 128 / 32 particles per
+  // work-group (or the cached / forced plan's choice).
   if (a.D <= 64) {
-    if (a.P > 128) return launch_short<2, 4>(a, s);
-    if (a.P > 32) return launch_short<2, 2>(a, s);
+    int variant = a.P > 128 ? 0 : a.P > 32 ? 1 : 2;
+    int64_t v0 = 0, v1 = 0;
+    if (g_forced_proj) v0 = g_forced_proj[0];
+    if ((g_forced_proj || plan_lookup(proj_key(3, a), &v0, &v1)) && v0 >= 0 && v0 <= 2)
+      variant = (int)v0;
+    if (variant == 0) return launch_short<2, 4>(a, s);
+    if (variant == 1) return launch_short<2, 2>(a, s);
     return launch_short<1, 1>(a, s);
   }
   // Tile shape by particle count: wide tiles for large swarms, a single
@@ -1156,6 +1225,60 @@ slm_status launch_project(const ProjectArgs &a, hipStream_t s) {
   if (a.P >= 128) return launch_cfg<128, 128, 2, 2>(a, s);
   if (a.P > 32) return launch_cfg<128, 64, 2, 2>(a, s);
   return launch_cfg<128, 32, 4, 1>(a, s);
+}
+
+slm_status tune_project(const ProjectArgs &a, hipStream_t s) {
+  if (a.Z == nullptr || a.N <= 0 || a.n_nodes <= 0) return SLM_OK;
+  const bool stream = stream_enabled() && stream_eligible(a);
+  int kind = -1;
+  if (stream) kind = a.x_bf16 && a.w_bf16 ? MK_BB : a.x_bf16 ? MK_XB : MK_FF;
+  else if (a.D <= 64 && !a.x_bf16 && !a.w_bf16) kind = 3;
+  if (kind < 0) return SLM_OK;
+  const std::string key = proj_key(kind, a);
+  if (plan_known(key)) return SLM_OK;
+  std::vector<std::pair<int64_t, int64_t>> cand;
+  if (kind == 3) {
+    for (int v = 0; v <= 2; ++v) cand.push_back({v, 0});
+  } else {
+    for (int fn : {4, 2, 1})
+      if (stream_fn_fits(kind, fn, a))
+        for (int x : {1, 0}) cand.push_back({fn, x});
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SLM_HIP(hipEventCreate(&e0));
+  SLM_HIP(hipEventCreate(&e1));
+  float best_ms = 0.f;
+  std::pair<int64_t, int64_t> best = cand[0];
+  slm_status st = SLM_OK;
+  for (size_t c = 0; c < cand.size() && !st; ++c) {
+    const int64_t v[2] = {cand[c].first, cand[c].second};
+    g_forced_proj = v;
+    st = launch_project(a, s);                   // warm-up
+    if (!st && hipEventRecord(e0, s) != hipSuccess) st = SLM_E_HIP;
+    for (int r = 0; r < 3 && !st; ++r) st = launch_project(a, s);
+    g_forced_proj = nullptr;
+    if (st) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = SLM_E_HIP;
+      break;
+    }
+    if (c == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = cand[c];
+    }
+  }
+  g_forced_proj = nullptr;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    (void)hipGetLastError();
+    set_error("slm autotune: projection candidate failed");
+    return st;
+  }
+  plan_store(key, best.first, best.second);
+  return SLM_OK;
 }
 
 }  // namespace slm

@@ -28,6 +28,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
+#include <string>
+#include <vector>
 
 namespace slm {
 namespace {
@@ -265,18 +267,53 @@ int num_cus() {
 // one 128-byte line) and a chunk length that makes the number of work-groups
 // a whole number of rounds over the CUs (two resident per CU).
 // SLM_SCAN_PLAN="PT:CH" overrides it (tuning sweeps).
-Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit) {
+// A (PT, CH) pair any launch of the shape may use: a tile whose register
+// finish and LDS histogram fit, a chunk within the 16-bit counters whose
+// slots the workspace (counted for chunk_min(N)) covers.
+bool plan_fits(int64_t N, int B, int K, int crit, int pt, int64_t ch) {
+  const bool mse = crit == SLM_MSE;
+  return (pt == 4 || pt == 8 || pt == 16 || pt == 32) &&
+         pt * (mse ? 5 : class_tile(K, mse)) <= 128 &&
+         lds_bytes(pt, B, mse ? 1 : K, mse, crit == SLM_ENTROPY) <= 160 * 1024 - 1024 &&
+         ch >= chunk_min(N) && ch <= CH_MAX && ch % 64 == 0;
+}
+
+// Shape class of a scan launch in the plan cache: the plan's row count, the
+// node count rounded up to a power of two, P, bins, classes and criterion.
+std::string scan_key(int64_t N, int n_nodes, int P, int B, int K, int crit) {
+  int nb = 1;
+  while (nb < n_nodes) nb <<= 1;
+  char buf[192];
+  snprintf(buf, sizeof buf, "scan/%s/N%lld/n%d/P%d/B%d/K%d/c%d", device_arch().c_str(),
+           (long long)N, nb, P, B, K, crit);
+  return buf;
+}
+
+// the autotuner's candidate in flight (one thread tunes at a time per launch)
+thread_local const Plan *g_forced_scan = nullptr;
+
+Plan make_plan(int64_t N, int n_nodes, int P, int B, int K, int crit, bool cached = true) {
   const bool mse = crit == SLM_MSE;
   Plan pl{pick_pt(P, B, K, crit), chunk_min(N), 1, class_tile(K, mse)};
+  if (g_forced_scan) {
+    pl.PT = g_forced_scan->PT;
+    pl.CH = g_forced_scan->CH;
+    pl.G = std::max(1, 32 / pl.PT);
+    return pl;
+  }
   const char *env = getenv("SLM_SCAN_PLAN");
   int pt = 0;
   long long ch = 0;
+  int64_t tpt = 0, tch = 0;
   if (env && sscanf(env, "%d:%lld", &pt, &ch) == 2 &&
-      (pt == 4 || pt == 8 || pt == 16 || pt == 32) && pt * (mse ? 5 : pl.KT) <= 128 &&
-      lds_bytes(pt, B, mse ? 1 : K, mse, crit == SLM_ENTROPY) <= 160 * 1024 - 1024 &&
-      ch >= chunk_min(N) && ch <= CH_MAX) {
+      plan_fits(N, B, K, crit, pt, (ch + 63) / 64 * 64)) {
     pl.PT = pt;
     pl.CH = (ch + 63) / 64 * 64;
+  } else if (cached && plan_lookup(scan_key(N, n_nodes, P, B, K, crit), &tpt, &tch) &&
+             plan_fits(N, B, K, crit, (int)tpt, tch)) {
+    // measured by the autotuner for this shape class
+    pl.PT = (int)tpt;
+    pl.CH = tch;
   } else {
     const int64_t n_pt = (P + pl.PT - 1) / pl.PT;
     const int64_t slots = 2 * (int64_t)num_cus();
@@ -660,67 +697,23 @@ __device__ __forceinline__ Coords coords_of(const ScanArgs &a) {
   return {a.beg, a.end, a.N};
 }
 
-template <int PT, int KT, bool MSE>
-__global__ __launch_bounds__(HIST_WG) __attribute__((amdgpu_waves_per_eu(4)))
-void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, size_t slot_sz,
-                 int64_t n_slots, int R) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int WGS = HIST_WG;
+// One particle per lane (pl = lane % PT, rows rsub, rsub + 64/PT, ... of the
+// wave's steps): regression, row-major Z, and every tile width.
+// Straight-line code for the common case: every lane's particle exists and
+// its edges are well conditioned (the guess is within one bin), so the bin is
+// computed without branches; 16 rows are in flight per lane.  Bin b adds
+// 1 << 16 (b >> 7) to word (b & 127); a lane without a particle, or a row
+// whose label is out of range, adds 0.
+template <int PT, int WGS, bool MSE>
+__device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &it, int p, bool pv,
+                                                 int pl, int rsub, int wave, const BinRule &rule,
+                                                 uint32_t *hc, double *hs1, double *hs2, int SB,
+                                                 int SD) {
+  constexpr int RPW = 64 / PT;                 // rows per wave step
   const int B = a.bins;
   const int K = MSE ? 1 : a.K;
-  const HistLayout hl = hist_layout(PT, B, K, MSE);
-  const int SB = hl.SB, SD = PT;
-  uint32_t *hc = reinterpret_cast<uint32_t *>(smem);
-  double *hs1 = reinterpret_cast<double *>(smem + hl.lds_cnt);
-  double *hs2 = hs1 + (size_t)B * SD;
-  double *lg = reinterpret_cast<double *>(smem + table_offset(PT, B, K, MSE));
-  double *rc = lg + LG_TBL;
-  const bool use_tbl = !MSE && a.crit == SLM_ENTROPY;
-
-  // XCD-aware order: the G particle tiles that share a Z cache line get
-  // block ids congruent modulo 8, dispatched close together.
-  const int64_t bid = blockIdx.x;
-  const int64_t hi8 = bid / (8 * G), rem = bid % (8 * G);
-  const int64_t L = ((hi8 * 8 + rem % 8) * G) + rem / 8;
-  if (L >= total_blocks) return;
-  const int64_t v = L / n_pt;
-  const int pt = (int)(L % n_pt);
-  const Coords co = coords_of(a);
-  Item it = find_item(co.beg, co.end, a.n_nodes, co.N, CH, v);
-  if (it.node < 0) return;
-  if (a.vpre) {   // back to data rows
-    const Range nr = load_range(a.beg, a.end, it.node, a.N);
-    const int64_t off = nr.lo - co.beg[it.node];
-    it.lo += off;
-    it.hi += off;
-    if (it.hi > nr.hi) it.hi = nr.hi;
-    if (it.lo >= it.hi) return;   // cannot happen with vpre matching the ranges
-  }
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  for (int i = tid; i < hl.nwords; i += WGS) hc[i] = 0u;
-  if constexpr (MSE) {
-    for (int i = tid; i < B * SD; i += WGS) {
-      hs1[i] = 0.0;
-      hs2[i] = 0.0;
-    }
-  }
-  if (use_tbl) fill_log_table(lg, rc, tid);
-
-  constexpr int RPW = 64 / PT;                 // rows per wave step
-  const int pl = lane % PT, rsub = lane / PT;
   const int P = a.P;
-  const int p = pt * PT + pl;
-  const bool pv = p < P;
-  const int64_t np = (int64_t)it.node * P;
-  const BinRule rule = make_rule(pv ? a.zmin[np + p] : 0.f, pv ? a.zmax[np + p] : 0.f, B);
-  lds_barrier();
-
-  // ---- accumulate.  Straight-line code for the common case: every lane's
-  // particle exists and its edges are well conditioned (the guess is within
-  // one bin), so the bin is computed without branches; 16 rows are in flight
-  // per lane.  Bin b adds 1 << 16 (b >> 7) to word (b & 127); a lane without a
-  // particle, or a row whose label is out of range, adds 0.
+  const int pt = (p - pl) / PT;
   const int64_t step = (int64_t)(WGS / 64) * RPW;
   const int64_t row0 = it.lo + wave * RPW + rsub;
   const int pcl = pv ? p : P - 1;                        // always a valid column
@@ -808,6 +801,165 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
     const int bn = bin_of(rule, z);
     if constexpr (MSE) add_mse(bn, a.y[row0 + (int64_t)i * step]);
     else add_cls(bn, a.labels[row0 + (int64_t)i * step]);
+  }
+}
+
+// Four consecutive particles per lane (classification, particle-tiled Z):
+// lane (q, r) takes particles 4q .. 4q+3 of the tile and rows r, r + 64/(PT/4),
+// ... of the wave's steps.  Per row: one 16-byte buffer load of the four
+// projections, one label load, and the label's part of the LDS address; per
+// sample-split: the branch-free bin (as in accumulate_rows1) and one LDS
+// atomic at an immediate offset.  Eight rows are in flight per lane.
+template <int PT, int WGS>
+__device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &it, int pt,
+                                                 int64_t np, int wave, int lane,
+                                                 unsigned char *hb, int SB) {
+  constexpr int QG = PT / 4, RPW4 = 64 / QG;   // lanes per row, rows per wave step
+  static_assert(PT % 4 == 0 && QG >= 1, "four particles per lane");
+  const int B = a.bins, K = a.K, P = a.P;
+  const int q4 = lane % QG, r4 = lane / QG;
+  const int64_t step4 = (int64_t)(WGS / 64) * RPW4;
+  const int64_t rb4 = it.lo + (int64_t)wave * RPW4;   // the wave's first row
+  const int64_t row4 = rb4 + r4;
+  const int n4 = (int)((it.hi - row4 + step4 - 1) / step4);   // rows of this lane (may be <= 0)
+  BinRule rl[4];
+  float zm[4], dl[4], iv[4], o0[4];
+  bool pv4[4];
+  bool lane_fast = true;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int pe = pt * PT + 4 * q4 + e;
+    pv4[e] = pe < P;
+    rl[e] = make_rule(pv4[e] ? a.zmin[np + pe] : 0.f, pv4[e] ? a.zmax[np + pe] : 0.f, B);
+    lane_fast = lane_fast && (rl[e].fast || !pv4[e]);
+    zm[e] = rl[e].zmin;
+    dl[e] = rl[e].delta;
+    iv[e] = rl[e].inv;
+    o0[e] = -fmaf(zm[e], iv[e], 0.005f);
+  }
+  const bool wave_fast = __all(lane_fast);
+  const unsigned bmax = (unsigned)B - 1u;
+  const uint32_t sb4 = (uint32_t)SB * 4u;
+  // Z: rows of the 32-particle tile holding this work-group's particles, from
+  // the wave's first row (at most CH_MAX rows of 128 bytes); labels from it
+  const int64_t zspan = (it.hi - rb4) * 128 + 128;
+  const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(a.Z + z_col(a.zl, (pt * PT) & ~31) + rb4 * 32), 0,
+      (int)(zspan < 0x7FFFFFFF ? zspan : 0x7FFFFFFF), BUF_DW3);
+  const int zvo = (((pt * PT) & 31) + 4 * q4 + r4 * 32) * 4, zso = (int)(step4 * 128);
+  const __amdgpu_buffer_rsrc_t lr = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<int32_t *>(a.labels + rb4), 0, (int)((it.hi - rb4) * 4), BUF_DW3);
+  const int lvo = r4 * 4, lso = (int)(step4 * 4);
+  // one row: its four projections and its label
+  auto add_row = [&](const uint32_t (&zw)[4], int lab, bool fast) {
+    const bool lok = (unsigned)lab < (unsigned)K;
+    const uint32_t base = ((uint32_t)(lok ? lab : 0) * PT + 4u * q4) * 4u;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float z = __uint_as_float(zw[e]);
+      unsigned g;
+      if (fast) {
+        const int g0 = (int)fmaf(z, iv[e], o0[e]);
+        const float e1 = __fadd_rn(zm[e], __fmul_rn((float)(g0 + 1), dl[e]));
+        g = min((unsigned)(g0 + (e1 <= z ? 1 : 0)), bmax);
+      } else {
+        g = (unsigned)bin_of(rl[e], z);
+      }
+      const uint32_t inc = lok && pv4[e] ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
+      atomicAdd(reinterpret_cast<uint32_t *>(hb + __umul24(g & 127u, sb4) + base + 4u * e), inc);
+    }
+  };
+  constexpr int U4 = 8;
+  int i = 0;
+  if (wave_fast) {
+    for (; i + U4 <= n4; i += U4) {
+      uint32_t zw[U4][4];
+      int lab[U4];
+#pragma unroll
+      for (int u = 0; u < U4; ++u) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(zr, zvo, (i + u) * zso, 0);
+        zw[u][0] = v[0];
+        zw[u][1] = v[1];
+        zw[u][2] = v[2];
+        zw[u][3] = v[3];
+        lab[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, (i + u) * lso, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < U4; ++u) add_row(zw[u], lab[u], true);
+    }
+  }
+  for (; i < n4; ++i) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(zr, zvo, i * zso, 0);
+    const uint32_t zw[4] = {v[0], v[1], v[2], v[3]};
+    const int lab = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, i * lso, 0);
+    add_row(zw, lab, wave_fast);
+  }
+}
+
+template <int PT, int KT, bool MSE>
+__global__ __launch_bounds__(HIST_WG) __attribute__((amdgpu_waves_per_eu(4)))
+void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, size_t slot_sz,
+                 int64_t n_slots, int R) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int WGS = HIST_WG;
+  const int B = a.bins;
+  const int K = MSE ? 1 : a.K;
+  const HistLayout hl = hist_layout(PT, B, K, MSE);
+  const int SB = hl.SB, SD = PT;
+  uint32_t *hc = reinterpret_cast<uint32_t *>(smem);
+  double *hs1 = reinterpret_cast<double *>(smem + hl.lds_cnt);
+  double *hs2 = hs1 + (size_t)B * SD;
+  double *lg = reinterpret_cast<double *>(smem + table_offset(PT, B, K, MSE));
+  double *rc = lg + LG_TBL;
+  const bool use_tbl = !MSE && a.crit == SLM_ENTROPY;
+
+  // XCD-aware order: the G particle tiles that share a Z cache line get
+  // block ids congruent modulo 8, dispatched close together.
+  const int64_t bid = blockIdx.x;
+  const int64_t hi8 = bid / (8 * G), rem = bid % (8 * G);
+  const int64_t L = ((hi8 * 8 + rem % 8) * G) + rem / 8;
+  if (L >= total_blocks) return;
+  const int64_t v = L / n_pt;
+  const int pt = (int)(L % n_pt);
+  const Coords co = coords_of(a);
+  Item it = find_item(co.beg, co.end, a.n_nodes, co.N, CH, v);
+  if (it.node < 0) return;
+  if (a.vpre) {   // back to data rows
+    const Range nr = load_range(a.beg, a.end, it.node, a.N);
+    const int64_t off = nr.lo - co.beg[it.node];
+    it.lo += off;
+    it.hi += off;
+    if (it.hi > nr.hi) it.hi = nr.hi;
+    if (it.lo >= it.hi) return;   // cannot happen with vpre matching the ranges
+  }
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int i = tid; i < hl.nwords; i += WGS) hc[i] = 0u;
+  if constexpr (MSE) {
+    for (int i = tid; i < B * SD; i += WGS) {
+      hs1[i] = 0.0;
+      hs2[i] = 0.0;
+    }
+  }
+  if (use_tbl) fill_log_table(lg, rc, tid);
+
+  constexpr int RPW = 64 / PT;                 // rows per wave step
+  const int pl = lane % PT, rsub = lane / PT;
+  const int P = a.P;
+  const int p = pt * PT + pl;
+  const bool pv = p < P;
+  const int64_t np = (int64_t)it.node * P;
+  const BinRule rule = make_rule(pv ? a.zmin[np + p] : 0.f, pv ? a.zmax[np + p] : 0.f, B);
+  lds_barrier();
+
+  // ---- accumulate, classification with particle-tiled Z: every lane takes
+  // four consecutive particles of one row, so one 16-byte load of the row's
+  // Z segment and one label load serve four sample-splits, and the label's
+  // part of the LDS address is formed once per row.
+  if (!MSE && a.zl.rs == 32) {
+    accumulate_rows4<PT, WGS>(a, it, pt, np, wave, lane, reinterpret_cast<unsigned char *>(hc), SB);
+  } else {
+    accumulate_rows1<PT, WGS, MSE>(a, it, p, pv, pl, rsub, wave, rule, hc, hs1, hs2, SB, SD);
   }
   lds_barrier();
 
@@ -1595,6 +1747,70 @@ slm_status launch_scan_hist(const ScanArgs &a, hipStream_t s) {
   const int64_t NW = a.vpre ? a.rows : a.N;
   const Plan pl = make_plan(NW, a.n_nodes, a.P, a.bins, a.crit == SLM_MSE ? 1 : a.K, a.crit);
   return launch_hist(a, pl, s);
+}
+
+slm_status tune_scan_hist(const ScanArgs &a, hipStream_t s) {
+  if (a.N <= 0 || a.n_nodes <= 0 || a.bins == 0) return SLM_OK;
+  const int64_t NW = a.vpre ? a.rows : a.N;
+  const bool mse = a.crit == SLM_MSE;
+  const int K = mse ? 1 : a.K;
+  const std::string key = scan_key(NW, a.n_nodes, a.P, a.bins, K, a.crit);
+  if (plan_known(key)) return SLM_OK;
+  // candidates: the rule's plan, then every tile width with chunks from
+  // chunk_min to the counter limit
+  std::vector<Plan> cand;
+  const Plan rule = make_plan(NW, a.n_nodes, a.P, a.bins, K, a.crit, false);
+  cand.push_back(rule);
+  const int64_t chs[] = {2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576, 32768, 49152, CH_MAX};
+  for (int pt = 4; pt <= 32; pt <<= 1) {
+    if (pt / 2 >= a.P && pt > 4) continue;
+    for (int64_t c : chs) {
+      const int64_t ch = std::max<int64_t>(c, chunk_min(NW));
+      if (!plan_fits(NW, a.bins, K, a.crit, pt, ch)) continue;
+      Plan pl = rule;
+      pl.PT = pt;
+      pl.CH = ch;
+      pl.G = std::max(1, 32 / pt);
+      bool dup = false;
+      for (const Plan &q : cand) dup = dup || (q.PT == pl.PT && q.CH == pl.CH);
+      if (!dup) cand.push_back(pl);
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SLM_HIP(hipEventCreate(&e0));
+  SLM_HIP(hipEventCreate(&e1));
+  float best_ms = 0.f;
+  Plan best = rule;
+  slm_status st = SLM_OK;
+  for (const Plan &pl : cand) {
+    g_forced_scan = &pl;
+    st = launch_hist(a, pl, s);                  // warm-up
+    for (int r = 0; r < 3 && !st; ++r) {
+      if (r == 0 && hipEventRecord(e0, s) != hipSuccess) st = SLM_E_HIP;
+      if (!st) st = launch_hist(a, pl, s);
+    }
+    g_forced_scan = nullptr;
+    if (st) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = SLM_E_HIP;
+      break;
+    }
+    if (&pl == &cand[0] || ms < best_ms) {
+      best_ms = ms;
+      best = pl;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    (void)hipGetLastError();
+    set_error("slm autotune: scan candidate failed");
+    return st;
+  }
+  plan_store(key, best.PT, best.CH);
+  return SLM_OK;
 }
 
 bool fused_eligible(const ScanArgs &a, int D, bool x_bf16, bool w_bf16) {

@@ -527,10 +527,15 @@ static slm_status learned_start(const slm_tree_params &p, const TreeWS &w, const
 }
 
 // swarm loop of one depth: T+1 evaluations (project, scan, step)
+// tune: the autotuner's pass (plan cache mode 2, never under capture): the
+// first evaluation only, each projection and scan launch preceded by the
+// measurement of its shape's candidate plans (shapes already cached are
+// skipped); the swarm loop that follows takes the measured plans.
 static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const void *Xc,
                              const void *tc, int64_t N, int32_t D, int na, int64_t vrows,
                              hipStream_t s,
-                             LaunchTimes *lt = nullptr, const SearchCtl *sc = nullptr) {
+                             LaunchTimes *lt = nullptr, const SearchCtl *sc = nullptr,
+                             bool tune = false) {
   const bool mse = p.crit == SLM_MSE;
   PsoArgs pa{};
   pa.x = w.x; pa.v = w.v; pa.pbest = w.pbest; pa.pbest_loss = w.pbest_loss;
@@ -627,9 +632,11 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
     if (psearch &&
         (st = launch_ps_candidates(pa, w.dft_sel, p.ps_R, p.ps_pd, p.ps_amax, (uint32_t)t, s)))
       return st;
+    if (tune && !fused && (st = tune_project(pr, s))) return st;
     if (lt && (st = lt->begin(0, s))) return st;
     if ((st = launch_project(fused ? pmm : pr, s))) return st;
     if (lt && (st = lt->end(s))) return st;
+    if (tune && !fused && p.bins && (st = tune_scan_hist(sa, s))) return st;
     if (lt && (st = lt->begin(1, s))) return st;
     if (fused) {
       if ((st = launch_fused_hist(pr, sa, s))) return st;
@@ -642,9 +649,11 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
       if ((st = launch_screen_select(w.loss, na, p.P, k, w.sel, s))) return st;
       if ((st = launch_screen_gather(w.x, w.sel, na, p.P, k, D, w.W32, s))) return st;
       if ((st = launch_fill_minmax(w.zmin_r, w.zmax_r, (int64_t)na * k, s))) return st;
+      if (tune && (st = tune_project(prr, s))) return st;
       if (lt && (st = lt->begin(3, s))) return st;
       if ((st = launch_project(prr, s))) return st;
       if (lt && (st = lt->end(s))) return st;
+      if (tune && p.bins && (st = tune_scan_hist(sar, s))) return st;
       if (lt && (st = lt->begin(4, s))) return st;
       if ((st = scan(sar))) return st;
       if (lt && (st = lt->end(s))) return st;
@@ -652,6 +661,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
                                     w.split, w.thr, w.gloss, s)))
         return st;
     }
+    if (tune) return SLM_OK;
     pa.move = t < p.T;
     // the swarm ends (or the search draws new candidates): only the global
     // best is kept
@@ -719,7 +729,7 @@ static slm_status swarm_loop_graph(const slm_tree_params &p, const TreeWS &w, co
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_pd : nullptr),
            (uint64_t)(uintptr_t)(p.proposal == 2 ? p.ps_amax : nullptr),
            (uint64_t)(uintptr_t)w.tree_off, (uint64_t)p.apso, (uint64_t)(uintptr_t)w.x2,
-           (uint64_t)vrows};
+           (uint64_t)vrows, autotune_generation()};
   uint64_t om, c1, c2;
   std::memcpy(&om, &p.omega, 8);
   std::memcpy(&c1, &p.c1, 8);
@@ -1497,6 +1507,11 @@ static slm_status grow_impl(const void *X, int64_t N, int32_t D, const void *tar
       sa.n_nodes = na; sa.sums = w.stat_sums; sa.counts = w.stat_counts; sa.stats = w.stats;
       sa.sigma = w.sigma;
       if ((st = launch_node_stats_full(sa, s))) return st;
+    }
+    if (autotune_mode() == 2 && !prof) {
+      // measure the plans of this depth's launch shapes that have none yet
+      if ((st = swarm_loop(p, w, Xc, tc, N, D, na, rows_q, s, nullptr, nullptr, true))) return st;
+      SLM_HIP(hipStreamSynchronize(s));
     }
     if ((st = tm_swarm.start(timing ? &timing[1] : nullptr, s))) return st;
     if (prof)

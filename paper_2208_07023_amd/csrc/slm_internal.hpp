@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <string>
 
 #include "../../include/slm.h"
 
@@ -406,5 +407,19 @@ slm_status launch_search_stop(const double *gbest_loss, const double *target, co
 int64_t partition_items(int n_nodes, int64_t N);
 // sets kernel attributes once per process (call outside stream capture)
 slm_status prepare_kernels();
+
+// ---------------------------------------------------------------- launch plans
+// The autotuner's plan cache (autotune.cpp): mode 0 = fitted rules only,
+// 1 = measured plans where cached, 2 = also measure the missing ones.
+std::string device_arch();
+int autotune_mode();
+uint64_t autotune_generation();   // changes whenever the plans in use change
+bool plan_lookup(const std::string &key, int64_t *a, int64_t *b);
+bool plan_known(const std::string &key);
+void plan_store(const std::string &key, int64_t a, int64_t b);
+// measure the candidate plans of one launch's shape (not under capture) and
+// cache the fastest; a shape already cached is left alone
+slm_status tune_scan_hist(const ScanArgs &a, hipStream_t s);
+slm_status tune_project(const ProjectArgs &a, hipStream_t s);
 
 }  // namespace slm

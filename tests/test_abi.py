@@ -311,3 +311,17 @@ def test_tables_and_boost_scores_validation():
     assert bs(2, 1) == 2 and bs(2, 17) == 2 and bs(-1, 0) == 2
     assert bs(2, 3, lr=float("nan")) == 1
     assert bs(2, 3, F=None) == 1
+
+
+def test_autotune_validation(tmp_path):
+    lib = api.load()
+    assert lib.slm_autotune_set(3, None) == 1
+    assert lib.slm_autotune_set(-1, None) == 1
+    assert lib.slm_autotune_set(2, None) == 1 and "file" in _err(lib)
+    # a plans file is read back (malformed entries are skipped)
+    p = tmp_path / "plans.json"
+    p.write_text('{"plans": {"scan/x/N1/n1/P1/B2/K2/c0": [8, 4096], "proj/x/k3/D8/P1/N1": [1, 0]}}')
+    assert lib.slm_autotune_set(1, str(p).encode()) == 0
+    assert lib.slm_autotune_plans() == 2
+    assert lib.slm_autotune_set(0, None) == 0
+    assert lib.slm_autotune_set(1, None) == 0   # back to the default

@@ -123,8 +123,9 @@ def test_apso_single_node_close_to_oracle(gpu_lib):
 
 def test_apso_tree_close_to_oracle_and_replays(gpu_lib):
     api = gpu_lib
-    Xa, ya = inputs.cluster_mixture(3000, 10, 3, mean_std=1.0, seed=5)
-    X, y, Xt, yt = Xa[:2000], ya[:2000], Xa[2000:], ya[2000:]
+    # 20 000 training and 20 000 held-out rows of one distribution
+    Xa, ya = inputs.cluster_mixture(40000, 10, 3, mean_std=1.0, seed=5)
+    X, y, Xt, yt = Xa[:20000], ya[:20000], Xa[20000:], ya[20000:]
     cfg = api.TreeConfig(crit=api.ENTROPY, K=3, max_depth=3, min_node=16, P=32, T=10, bins=64,
                          seed=6, apso=True)
     Xd, yd = _t(X), _t(y)
@@ -134,7 +135,7 @@ def test_apso_tree_close_to_oracle_and_replays(gpu_lib):
     acc_o = float((OT.predict(o, Xt) == yt).mean())
     print(f"APSO tree held-out accuracy gpu {acc_g:.4f} oracle {acc_o:.4f}; "
           f"root loss gpu {g['split_loss'][0]:.5f} oracle {o.split_loss[0]:.5f}")
-    assert abs(acc_g - acc_o) <= 0.05
+    assert abs(acc_g - acc_o) <= 0.005 + 1e-12
     assert g["split_loss"][0] == pytest.approx(o.split_loss[0], rel=0.02)
     for i in range(g["n_nodes"]):
         if g["left"][i] >= 0:

@@ -129,13 +129,14 @@ def test_forest_predict_matches_oracle_combination(gpu_lib, crit, K):
 def test_forest_quality_close_to_oracle(gpu_lib, crit, K):
     api = gpu_lib
     D, nt = 6, 4
+    # 20 000 training and 20 000 held-out rows
     if crit == OS.MSE:
-        X, y = inputs.friedman1(1500, D, noise=0.5, seed=12)
-        Xt, yt = inputs.friedman1(1000, D, noise=0.5, seed=13)
+        X, y = inputs.friedman1(20000, D, noise=0.5, seed=12)
+        Xt, yt = inputs.friedman1(20000, D, noise=0.5, seed=13)
     else:
         # one distribution (the cluster means are drawn from the seed), split
-        Xa, ya = inputs.cluster_mixture(2500, D, K, mean_std=1.0, seed=12)
-        X, y, Xt, yt = Xa[:1500], ya[:1500], Xa[1500:], ya[1500:]
+        Xa, ya = inputs.cluster_mixture(40000, D, K, mean_std=1.0, seed=12)
+        X, y, Xt, yt = Xa[:20000], ya[:20000], Xa[20000:], ya[20000:]
     cfg = api.TreeConfig(crit=crit, K=K, max_depth=4, min_node=16, P=16, T=5, bins=32, seed=2)
     g = api.grow_forest(_t(X), _t(y), cfg, nt)
     pg = api.forest_predict(g, _t(Xt)).cpu().numpy()
@@ -144,11 +145,11 @@ def test_forest_quality_close_to_oracle(gpu_lib, crit, K):
     if K:
         acc_g, acc_o = (pg == yt).mean(), (po == yt).mean()
         print(f"forest held-out accuracy gpu {acc_g:.4f} oracle {acc_o:.4f}")
-        assert abs(acc_g - acc_o) <= 0.03
+        assert abs(acc_g - acc_o) <= 0.005 + 1e-12
     else:
         mse_g, mse_o = ((pg - yt) ** 2).mean(), ((po - yt) ** 2).mean()
         print(f"forest held-out MSE gpu {mse_g:.4f} oracle {mse_o:.4f}")
-        assert mse_g <= 1.1 * mse_o
+        assert mse_g <= 1.03 * mse_o
         # the mean aggregate never does worse than the mean tree, pointwise
         outs = np.stack([api.predict(api.forest_tree(g, b), _t(Xt)) for b in range(nt)])
         assert np.all((pg - yt) ** 2 <= ((outs - yt) ** 2).mean(axis=0) + 1e-9)

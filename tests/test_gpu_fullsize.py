@@ -151,3 +151,88 @@ def test_node_stats_full_size(gpu_lib):
         s_ref, g_ref = PR.node_stats(X[r0:r1], y[r0:r1], K)
         assert np.allclose(st[j], s_ref, rtol=0, atol=2e-6), j
         assert np.allclose(sg[j], g_ref, rtol=2e-6, atol=1e-7), j
+
+
+# ------------------------------------------------------------------ full-size trees
+def _route_host(tr, X, chunk=1 << 19):
+    """Node of every row at every depth, routed on the host by the tree's
+    stored float32 rule (z = float32 of the FP64 dot product, right iff
+    z >= thr).  Returns a list over depths of node-id arrays [N]."""
+    N = X.shape[0]
+    at = np.zeros(N, np.int64)
+    levels = [at.copy()]
+    while True:
+        nxt = at.copy()
+        moved = False
+        for i in np.unique(at):
+            l, r = tr["left"][i], tr["right"][i]
+            if l < 0:
+                continue
+            rows = np.nonzero(at == i)[0]
+            w = tr["w"][i].astype(np.float64)
+            for s in range(0, rows.size, chunk):
+                rr = rows[s:s + chunk]
+                z = (X[rr].astype(np.float64) @ w).astype(np.float32)
+                nxt[rr] = np.where(z >= tr["thr"][i], r, l)
+            moved = True
+        if not moved:
+            return levels
+        at = nxt
+        levels.append(at.copy())
+
+
+def _check_tree_full(tr, X, y, crit, K, bins, n_sample, seed):
+    """Every split agrees with its own histogram (the children's counts or
+    sums reproduce the recorded loss); sampled split nodes are re-scored by
+    the oracle on the host-routed rows of the node and the recorded
+    direction."""
+    from tests.test_gpu_tree import _consistency
+    _consistency(tr, crit, K)
+    splits = np.nonzero(tr["left"] >= 0)[0]
+    assert splits.size >= 1
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(splits, size=min(n_sample, splits.size), replace=False))
+    levels = _route_host(tr, X)
+    worst = 0.0
+    for i in pick:
+        rows = np.nonzero(levels[int(tr["depth"][i])] == i)[0]
+        # host routing may differ from the device partition on rows whose
+        # projection rounds differently at a threshold: a handful at most
+        assert abs(rows.size - tr["n"][i]) <= max(2, tr["n"][i] // 100000), (i, rows.size)
+        z = _project64(X[rows], tr["w"][i])[0].astype(np.float32)
+        ref = OS.scan_hist(z, y[rows], bins, crit, K)
+        rel = abs(ref["loss"] - tr["split_loss"][i]) / max(1e-12, abs(tr["split_loss"][i]))
+        worst = max(worst, rel)
+        assert rel <= 1e-3, (i, ref["loss"], tr["split_loss"][i])
+    return worst, pick.size
+
+
+def test_regression_tree_full_size(gpu_lib):
+    """The regression workload's whole tree (N = 1e6, D = 128, P = 512,
+    T = 40, MSE, 256 bins, depth 10) at full size."""
+    api = gpu_lib
+    N, D = 1_000_000, 128
+    X, y = inputs.abs_direction_regression(N, D, seed=0)
+    cfg = api.TreeConfig(crit=api.MSE, K=0, max_depth=10, min_node=32, P=512, T=40, bins=256,
+                         seed=0, use_graph=True)
+    tr = api.grow_tree(_t(X), _t(y), cfg)
+    worst, n = _check_tree_full(tr, X, y, OS.MSE, 0, 256, 20, seed=1)
+    print(f"regression tree: {tr['n_nodes']} nodes; {n} splits re-scored, worst rel {worst:.2e}")
+
+
+def test_screening_tree_full_size(gpu_lib):
+    """The screening workload's whole tree (N = 4e6, D = 256, K = 10, P = 1024
+    screened in BF16, top 32 re-scored in FP32, T = 40, Gini, depth 12) at
+    full size; the re-scoring oracle projects the bfloat16 data on the
+    recorded FP32 direction."""
+    api = gpu_lib
+    N, D, K = 4_000_000, 256, 10
+    bits, y = inputs.lowrank_mixture(N, D, K, seed=0)
+    Xd = _t(bits.view(np.int16)).view(torch.bfloat16)
+    cfg = api.TreeConfig(crit=api.GINI, K=K, max_depth=12, min_node=32, P=1024, T=40, bins=256,
+                         precision=1, rescore_k=32, seed=0, use_graph=True)
+    tr = api.grow_tree(Xd, _t(y), cfg)
+    del Xd
+    Xf = inputs.bf16_bits_to_f32(bits)
+    worst, n = _check_tree_full(tr, Xf, y, OS.GINI, K, 256, 20, seed=2)
+    print(f"screening tree: {tr['n_nodes']} nodes; {n} splits re-scored, worst rel {worst:.2e}")

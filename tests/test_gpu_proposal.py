@@ -213,3 +213,81 @@ def test_search_nodes_stops_at_the_target(gpu_lib):
     gl = out["gbest_loss"].cpu().numpy()
     for j in range(3):
         assert gl[j] == hist[want[j] - 1, j]
+
+
+def _balanced_signs(n, D, rng):
+    """[n, D] of +-1 with exactly n/2 of each sign per column: every column has
+    mean 0 and variance 1 exactly, so sigma = 1 on both sides."""
+    X = np.empty((n, D), np.float32)
+    for d in range(D):
+        X[:, d] = rng.permutation(np.repeat(np.array([1.0, -1.0], np.float32), n // 2))
+    return X
+
+
+def test_learned_start_search_matches_oracle(gpu_lib):
+    """slm_search_nodes with the learned start (proposal 1: node statistics,
+    BF16 network inference, seeds, then the swarm) against the oracle's steps
+    in the same order (oracle.proposal.node_stats -> forward ->
+    seeds_to_directions -> oracle.pso.run_pso with those seeds, T = 0).
+
+    The network's weights are zero and its output biases are +-1 on four
+    coordinates per seed (bfloat16 values), and every data column is a
+    balanced +-1 column (sigma = 1 exactly): the seeds are then +-1/2 on four
+    coordinates on both sides, every projection is exact in FP32, and the
+    first evaluation's global best -- direction, loss, split and threshold --
+    must agree bit for bit.  The seeds themselves are compared with the
+    oracle's to 1e-12 through the separate calls (node statistics, forward,
+    seed map) that the search composes."""
+    from oracle import pso as OP
+    from oracle import split as OS
+    from oracle import tree as OT
+    api = gpu_lib
+    D, K, M, H = 8, 2, 8, 16
+    rng = np.random.default_rng(41)
+    sizes = [1000, 600]
+    Xs, ys = [], []
+    for n in sizes:
+        X = _balanced_signs(n, D, rng)
+        y = ((X[:, 0] + X[:, 1] + X[:, 2] + 0.5 * rng.standard_normal(n)) > 0).astype(np.int32)
+        Xs.append(X)
+        ys.append(y)
+    X, y = np.concatenate(Xs), np.concatenate(ys)
+    off = inputs.segment_offsets(sizes)
+    n_in, n_out = (K + 1) * D, M * D
+    theta = np.zeros(PR.n_params(n_in, H, n_out), np.float32)
+    b3 = np.zeros((M, D), np.float32)
+    for m in range(M):                 # distinct sign patterns on four coordinates
+        cols = rng.choice(D, 4, replace=False)
+        b3[m, cols] = rng.choice([-1.0, 1.0], 4)
+    theta[-n_out:] = b3.ravel()
+    cfg = api.TreeConfig(crit=api.GINI, K=K, P=M, T=0, bins=64, seed=3, proposal=1, n_seeds=M,
+                         mlp_hidden=H, mlp=_t(theta))
+    node_id = np.array([5, 9], np.int32)
+    out = api.search_nodes(_t(X), _t(y), _t(off), _t(node_id), cfg)
+    prm = OT.TreeParams(crit=OS.GINI, K=K, P=M, T=0, bins=64, seed=3)
+    for j in range(len(sizes)):
+        Xn, yn = X[off[j]:off[j + 1]], y[off[j]:off[j + 1]]
+        s, sigma = PR.node_stats(Xn, yn, K)
+        assert np.array_equal(sigma, np.ones(D))
+        o, _ = PR.forward(theta.astype(np.float64), s[None, :], n_in, H, n_out)
+        seeds = PR.seeds_to_directions(o[0], sigma, M)
+        assert np.all(np.isin(np.abs(seeds), [0.0, 0.5]))
+        ref = OP.run_pso(OT.evaluate_node(Xn, yn, prm), M, D, 0, prm.omega, prm.c1, prm.c2,
+                         prm.seed, prm.tree, int(node_id[j]), x0=seeds)
+        assert out["gbest_loss"].cpu().numpy()[j] == ref["loss"]
+        assert np.array_equal(out["gbest"].cpu().numpy()[j], ref["gbest"])
+        assert out["gbest_split"].cpu().numpy()[j] == ref["split"]
+        assert out["gbest_thr"].cpu().numpy()[j] == ref["thr"]
+        assert out["evals"].cpu().numpy()[j] == 1
+    # the steps the search composes, called one by one, place the same seeds
+    st, sg = api.node_stats(_t(X), _t(y), K, _t(off))
+    o_gpu, _ = api.mlp_forward(_t(theta), n_in, H, n_out, st, bf16=True)
+    sw = api.pso_alloc(len(sizes), M, D, node_id=node_id)
+    api.pso_init(sw, seed=3, tree=0)
+    api.proposal_seeds(o_gpu, sg, M, sw)
+    x = sw.x.cpu().numpy().reshape(len(sizes), M, D)
+    for j in range(len(sizes)):
+        Xn, yn = X[off[j]:off[j + 1]], y[off[j]:off[j + 1]]
+        s, sigma = PR.node_stats(Xn, yn, K)
+        o, _ = PR.forward(theta.astype(np.float64), s[None, :], n_in, H, n_out)
+        assert np.allclose(x[j], PR.seeds_to_directions(o[0], sigma, M), rtol=0, atol=1e-12)
