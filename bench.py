@@ -590,7 +590,7 @@ def learned_vs_plain(api, dev, full=False):
     from paper_2208_07023_amd import proposal as PL
     D, K, H = 128, 5, 256
     if full:
-        n_harvest, n_lo, n_hi, N_eval, n_eval_trees = 2000, 10_000, 500_000, 2_000_000, 16
+        n_harvest, n_lo, n_hi, N_eval, n_eval_trees = 2500, 10_000, 500_000, 2_000_000, 16
     else:
         n_harvest, n_lo, n_hi, N_eval, n_eval_trees = 200, 10_000, 100_000, 200_000, 1
     t0 = time.perf_counter()
@@ -744,6 +744,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the top-n DFT, probabilistic-search, forest and boosting legs")
     ap.add_argument("--only-headline", action="store_true")
+    ap.add_argument("--only-learned", action="store_true",
+                    help="only run the learned-vs-plain comparison (with --learned-full at its "
+                         "configured scale) and exit")
     ap.add_argument("--root-evals", choices=["screening", "plain", "regression"], default=None,
                     help="only run --reps root evaluations (projection + histogram scan, and "
                          "the re-scoring for the screening tree) of one workload and exit: the "
@@ -787,6 +790,9 @@ def main():
     log(f"launch plans: {args.plans} ({n_plans} cached)")
     if args.root_evals:
         print(json.dumps(root_evals(api, args.root_evals, args.reps, dev)), flush=True)
+        return
+    if args.only_learned:
+        print(json.dumps(learned_vs_plain(api, dev, full=args.learned_full)), flush=True)
         return
     head, screen_data = headline(api, args, dev)
     out = {

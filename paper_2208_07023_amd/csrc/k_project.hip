@@ -690,10 +690,10 @@ slm_status launch_bf16(const ProjectArgs &a, hipStream_t s) {
 // registers, double-buffered across sub-tiles; every wave computes all PT
 // particles of its rows, so each X row is read once per particle tile.
 //
-// The dimensions are taken in chunks of KCH: in chunk c, lanes 0-31 supply
-// the first half of the chunk's dimensions and lanes 32-63 the second half,
-// so a lane's A operand for a chunk is one contiguous 256-byte run of its X
-// row.  Three operand kinds:
+// The kernel takes D <= KCH dimensions (zero-padded to KCH): lanes 0-31
+// supply the first KCH/2 of them and lanes 32-63 the second half, so a lane's
+// A operand is one contiguous 256-byte run of its X row.  Larger D take the
+// tile kernels.  Three operand kinds:
 //   MK_BB  X and W bfloat16: v_mfma_f32_32x32x16_bf16, KCH = 256 (16 steps
 //          of 8 dimensions per half);
 //   MK_XB  X bfloat16, W float32: v_mfma_f32_32x32x2f32, KCH = 256 (128
@@ -716,10 +716,12 @@ struct StreamOps {
   static constexpr int G = KCH / 2 * WBYTES / 16;
 };
 
-__host__ __device__ constexpr size_t stream_lds_bytes(int MK, int FN, int D) {
-  return (size_t)((D + (MK == MK_FF ? 127 : 255)) / (MK == MK_FF ? 128 : 256)) * FN *
-         ((MK == MK_FF ? 128 : 256) / 2 * (MK == MK_BB ? 2 : 4) / 16) * 1024;
+// LDS of a work-group's W tile: FN blocks of G 1-KB fragment groups.
+__host__ __device__ constexpr size_t stream_lds_bytes(int MK, int FN) {
+  return (size_t)FN * ((MK == MK_FF ? 128 : 256) / 2 * (MK == MK_BB ? 2 : 4) / 16) * 1024;
 }
+// The dimensions one chunk covers: the kernel takes D <= KCH (one chunk).
+__host__ __device__ constexpr int stream_kch(int MK) { return MK == MK_FF ? 128 : 256; }
 
 // one 16-byte group of a row: elements e0 .. e0 + 16/EB - 1 (EB bytes each)
 // of row `row` of a [*, D] matrix; elements past D read as zero when MASK,
@@ -761,9 +763,9 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
                                                             int blocks_per_pt, int n_pt,
                                                             int xcd_map) {
   using O = StreamOps<MK>;
-  constexpr int KCH = O::KCH, G = O::G;
+  constexpr int KCH = O::KCH, G = O::G, XB = O::XBYTES;
   constexpr int PT = 32 * FN;
-  extern __shared__ __align__(16) uint4 wl[];   // [chunk][f][g][lane]
+  extern __shared__ __align__(16) uint4 wl[];   // [f][g][lane]
   if (a.n_nodes <= 0) return;
   // work-group -> (particle tile, row run).  xcd_map: work-groups are dealt
   // to the 8 XCDs round robin; the particle tiles of one row run are kept on
@@ -786,13 +788,13 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
   const int64_t r_end = r_begin + RB < n_rows ? r_begin + RB : n_rows;
   if (r_begin >= r_end) return;
   const int D = a.D, P = a.P;
-  const int nch = (D + KCH - 1) / KCH;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 31, kh = lane >> 5;
   const int p0 = pt * PT;
   const bool tile_full = p0 + PT <= P;
   const int64_t rs = TILED ? (int64_t)32 : a.zl.rs;
   const bool do_mm = a.zmin != nullptr;
+  const int64_t row_bytes = (int64_t)D * XB;
 
   int j0 = 0;
   {
@@ -807,10 +809,10 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
 
   float mn[FN], mx[FN];
   // the node's W tile into LDS, fragment order: group g of lane (li, h) in
-  // chunk c, block f holds W elements c KCH + h KCH/2 + g (16 / WBYTES) ...
+  // block f holds W elements h KCH/2 + g (16 / WBYTES) ...
   auto fill_w = [&](int j) {
     const int64_t wb = (int64_t)j * P;
-    const int units = nch * FN * G * 64;
+    constexpr int units = FN * G * 64;
     constexpr int UB = 8;   // loads in flight per thread
     for (int u0 = threadIdx.x; u0 < units; u0 += UB * 64 * SW) {
       uint4 v[UB];
@@ -819,10 +821,9 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
         const int u = u0 + e * 64 * SW;
         const int l = u & 63;
         const int g = (u >> 6) % G;
-        const int f = (u / (64 * G)) % FN;
-        const int c = u / (64 * G * FN);
+        const int f = u / (64 * G);
         const int p = p0 + f * 32 + (l & 31);
-        const int e0 = c * KCH + (l >> 5) * (KCH / 2) + g * (16 / O::WBYTES);
+        const int e0 = (l >> 5) * (KCH / 2) + g * (16 / O::WBYTES);
         v[e] = make_uint4(0u, 0u, 0u, 0u);
         if (u < units && p < P) v[e] = load_group<O::WBYTES, VEC, true>(a.W, wb + p, D, e0);
       }
@@ -847,19 +848,33 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
       }
     }
   };
-  // A operand of one chunk: 16 groups of 16 bytes, the lane's contiguous
-  // half-chunk of row `row`
-  auto load_a = [&](int64_t row, int c, uint4 (&A)[16]) {
-    const int e0 = c * KCH + kh * (KCH / 2);
+  // A operand: 16 groups of 16 bytes, the lane's contiguous half of the
+  // dimensions of row lo + li (the sub-tile's last row for lanes past its
+  // n rows).  VEC: buffer loads from a resource at the sub-tile's first row,
+  // so the per-load offsets are immediates and the row base is scalar.
+  auto load_a = [&](int64_t lo, int n, uint4 (&A)[16]) {
+    const int lr = li < n ? li : n - 1;
+    if constexpr (VEC) {
+      const char *base = static_cast<const char *>(a.X) + lo * row_bytes;
+      const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char *>(base), 0, (int)(n * row_bytes), BUF_DW3);
+      const int vo = (int)(lr * row_bytes) + kh * (KCH / 2) * XB;
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-      A[q] = load_group<O::XBYTES, VEC, false>(a.X, row, D, e0 + q * (16 / O::XBYTES));
+      for (int q = 0; q < 16; ++q) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(xr, vo + q * 16, 0, 0);
+        A[q] = make_uint4(v[0], v[1], v[2], v[3]);
+      }
+    } else {
+      const int e0 = kh * (KCH / 2);
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        A[q] = load_group<XB, false, false>(a.X, lo + lr, D, e0 + q * (16 / XB));
+    }
   };
   // The W fragments of step group q + 1 are read from LDS while the MFMAs of
-  // group q run (two register sets), so the matrix core does not wait for
-  // the LDS latency before every MFMA.
-  auto mma_chunk = [&](int c, const uint4 (&A)[16], f32x16 (&acc)[FN]) {
-    const uint4 *wc = wl + (size_t)c * FN * G * 64 + lane;
+  // group q run (two register sets).
+  auto mma = [&](const uint4 (&A)[16], f32x16 (&acc)[FN]) {
+    const uint4 *wc = wl + lane;
     if constexpr (MK == MK_BB) {
       uint4 b[2][FN];
 #pragma unroll
@@ -930,63 +945,48 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
     }
   };
   // Lane l, register r of block f holds row 8 (r/4) + 4 (l/32) + r%4 of the
-  // sub-tile and particle p0 + 32 f + l%32.
-  auto epilogue = [&](int64_t lo, int nrow, const f32x16 (&acc)[FN]) {
-    if (nrow == SR && tile_full) {
-#pragma unroll
-      for (int f = 0; f < FN; ++f) {
-        float *zc = a.Z + z_col(a.zl, p0 + f * 32 + li) + (lo + 4 * kh) * rs;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = acc[f][r];
-        float l = acc[f][0], h = acc[f][0];
-#pragma unroll
-        for (int r = 1; r < 16; ++r) {
-          l = fminf(l, acc[f][r]);
-          h = fmaxf(h, acc[f][r]);
-        }
-        mn[f] = fminf(mn[f], l);
-        mx[f] = fmaxf(mx[f], h);
-      }
-      return;
-    }
-    // rows past the node's end or columns past P: buffer stores with an
-    // out-of-range offset are dropped by the hardware
-    const uint32_t nb = (uint32_t)(nrow * rs * 4);
+  // sub-tile and particle p0 + 32 f + l%32.  Stores go through a buffer
+  // resource at (block f, row lo): the lane's offset is fixed, each
+  // register's row offset an immediate; rows past the sub-tile's n (and
+  // columns past P) take an out-of-range offset, which the hardware drops.
+  auto epilogue = [&](int64_t lo, int n, const f32x16 (&acc)[FN]) {
+    const bool full = n == SR && tile_full;
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
       const bool pin = p0 + f * 32 + li < P;
       const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-          a.Z + (int64_t)((p0 >> 5) + f) * a.zl.ts + lo * rs, 0, nb, BUF_DW3);
-      float l = __builtin_nanf(""), h = __builtin_nanf("");
+          a.Z + (int64_t)((p0 >> 5) + f) * a.zl.ts + lo * rs, 0, (int)(n * rs * 4), BUF_DW3);
+      const int vo = (int)((4 * kh * rs + li) * 4);
+      float l = __builtin_huge_valf(), h = -__builtin_huge_valf();
+      if (full) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
-        const bool ok = pin && row < nrow;
-        const uint32_t off = ok ? (uint32_t)((row * rs + li) * 4) : 0x80000000u;
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(acc[f][r]), zr, (int)off, 0, 0);
-        const float z = ok ? acc[f][r] : __builtin_nanf("");
-        l = fminf(l, z);
-        h = fmaxf(h, z);
+        for (int r = 0; r < 16; ++r) {
+          const int ro = (int)((8 * (r >> 2) + (r & 3)) * rs * 4);
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(acc[f][r]), zr, vo + ro, 0, 0);
+          l = fminf(l, acc[f][r]);
+          h = fmaxf(h, acc[f][r]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
+          const bool ok = pin && row < n;
+          const int off = ok ? vo + (int)((8 * (r >> 2) + (r & 3)) * rs * 4) : (int)0x80000000;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(acc[f][r]), zr, off, 0, 0);
+          l = fminf(l, ok ? acc[f][r] : __builtin_huge_valf());
+          h = fmaxf(h, ok ? acc[f][r] : -__builtin_huge_valf());
+        }
       }
       mn[f] = fminf(mn[f], l);
       mx[f] = fmaxf(mx[f], h);
     }
   };
-  // one sub-tile: rows lo .. lo + nrow - 1, A of chunk 0 already in A0
-  auto subtile = [&](int64_t lo, int nrow, uint4 (&A0)[16], uint4 (&A1)[16]) {
+  auto subtile = [&](int64_t lo, int n, const uint4 (&A)[16]) {
     f32x16 acc[FN];
 #pragma unroll
     for (int f = 0; f < FN; ++f) acc[f] = f32x16{};
-    const int64_t row = lo + (li < nrow ? li : nrow - 1);
-    for (int c = 0; c < nch; ++c) {
-      if (c + 1 < nch) load_a(row, c + 1, A1);
-      mma_chunk(c, A0, acc);
-      if (c + 1 < nch) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) A0[q] = A1[q];
-      }
-    }
-    epilogue(lo, nrow, acc);
+    mma(A, acc);
+    epilogue(lo, n, acc);
   };
 
   uint4 A0[16], A1[16];
@@ -995,11 +995,8 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
        c = next_subtile(a, c.j + 1, r_begin, r_end)) {
     const int64_t end = c.end;
     int64_t my = c.lo + SR * wave;   // this wave's first sub-tile
-    const auto row_of = [&](int64_t lo) {
-      const int64_t n = end - lo < SR ? end - lo : SR;
-      return lo + (li < n ? li : n - 1);
-    };
-    if (my < end) load_a(row_of(my), 0, A0);
+    auto rows_at = [&](int64_t lo) { return (int)(end - lo < SR ? end - lo : SR); };
+    if (my < end) load_a(my, rows_at(my), A0);
     // the previous node's LDS reads are done before its tile is replaced
     // (an LDS-only barrier: the A loads just issued stay in flight)
     if (!first) lds_barrier();
@@ -1014,21 +1011,13 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
     // ping-pong over this wave's sub-tiles of the node, SW SR rows apart
     while (my < end) {
       const int64_t nx = my + SW * SR;
-      const int n0 = (int)(end - my < SR ? end - my : SR);
-      if (nch == 1) {
-        if (nx < end) load_a(row_of(nx), 0, A1);
-        subtile(my, n0, A0, A1);
-        if (nx >= end) break;
-        const int64_t nx2 = nx + SW * SR;
-        const int n1 = (int)(end - nx < SR ? end - nx : SR);
-        if (nx2 < end) load_a(row_of(nx2), 0, A0);
-        subtile(nx, n1, A1, A0);
-        my = nx2;
-      } else {
-        subtile(my, n0, A0, A1);
-        my = nx;
-        if (my < end) load_a(row_of(my), 0, A0);
-      }
+      if (nx < end) load_a(nx, rows_at(nx), A1);
+      subtile(my, rows_at(my), A0);
+      if (nx >= end) break;
+      const int64_t nx2 = nx + SW * SR;
+      if (nx2 < end) load_a(nx2, rows_at(nx2), A0);
+      subtile(nx, rows_at(nx), A1);
+      my = nx2;
     }
     flush(c.j);
   }
@@ -1054,7 +1043,7 @@ slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s, int want_xcd = 1
   const int64_t grid = bpp * n_pt;
   if (grid == 0) return SLM_OK;
   SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_project: grid too large");
-  const size_t lds = stream_lds_bytes(MK, FN, a.D);
+  const size_t lds = stream_lds_bytes(MK, FN);
   if (a.zl.rs == 32)
     hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, true>), dim3((unsigned)grid), dim3(64 * SW),
                        lds, s, a, RB, (int)bpp, n_pt, xcd);
@@ -1081,7 +1070,7 @@ std::string proj_key(int kind, const ProjectArgs &a) {
 thread_local const int64_t *g_forced_proj = nullptr;
 
 bool stream_fn_fits(int MK, int FN, const ProjectArgs &a) {
-  return (FN == 1 || (a.P + 31) / 32 >= FN) && stream_lds_bytes(MK, FN, a.D) <= STREAM_LDS_MAX;
+  return (FN == 1 || (a.P + 31) / 32 >= FN) && stream_lds_bytes(MK, FN) <= STREAM_LDS_MAX;
 }
 
 // Particle blocks per wave FN (4, 2 or 1: the widest that fits, or the
@@ -1119,7 +1108,7 @@ bool stream_eligible(const ProjectArgs &a) {
   const int mk = a.x_bf16 && a.w_bf16 ? MK_BB : a.x_bf16 ? MK_XB : MK_FF;
   if (mk == MK_FF && a.D <= 64) return false;      // k_project_short
   if (a.w_bf16 && !a.x_bf16) return false;
-  return stream_lds_bytes(mk, 1, a.D) <= STREAM_LDS_MAX;
+  return a.D <= stream_kch(mk);
 }
 
 template <int MK, int FN, bool VEC, bool TILED>

@@ -257,3 +257,49 @@ def test_screened_tree_matches_oracle(gpu_lib):
         if l >= 0:
             w = (n[l] * g["impurity"][l] + n[r] * g["impurity"][r]) / n[i]
             assert w == pytest.approx(g["split_loss"][i], rel=1e-9, abs=1e-12)
+
+
+def test_screening_report_against_fp64_oracle(gpu_lib):
+    """The screening step's error against the FP64 oracle on a 100 000-row
+    sample of the screening workload (D = 256, K = 10, P = 1024, top 32,
+    Gini, 256 bins), for two swarms:
+    * recall: the oracle's best particle over all 1024 (FP64 projection of
+      the bfloat16 data on the FP32 directions, rounded to float32, scanned)
+      is among the GPU's screened top 32;
+    * gap: the oracle loss of the best re-scored particle against the
+      oracle's best, relative;
+    * per-particle error: the GPU's screened loss against the oracle's loss
+      of the same particle, relative.
+    The numbers are printed; the bars are those the screening must meet to
+    serve its purpose (a screened top 32 that holds the best particle)."""
+    api = gpu_lib
+    N, D, K, P, k, B = 100_000, 256, 10, 1024, 32, 256
+    bits, y = inputs.lowrank_mixture(N, D, K, seed=3)
+    Xf = inputs.bf16_bits_to_f32(bits)
+    Xd = _t(bits.view(np.int16)).view(torch.bfloat16)
+    off = _t(np.array([0, N], np.int64))
+    yd = _t(y)
+    hits, gaps, errs = 0, [], []
+    for seed in (11, 12):
+        x = OP.init_positions(seed, 0, 0, P, D)           # the oracle's start
+        sw = api.pso_alloc(1, P, D, node_id=[0], w_dtype=torch.bfloat16)
+        api.pso_init(sw, seed=seed, tree=0)
+        # the same Box-Muller start up to the libraries' ulps
+        assert np.allclose(sw.x.cpu().numpy(), x, rtol=0, atol=1e-14)
+        Zs, zmin, zmax = api.project(Xd, sw.W, off, P, tiled=True)
+        scr = api.split_scan(Zs, zmin, zmax, yd, K, off, P, B, api.GINI)
+        sel = api.screen_select(scr["loss"], 1, P, k).cpu().numpy()
+        del Zs
+        Z64 = OS.project(Xf, x.astype(np.float32)).astype(np.float32)
+        lo = np.array([OS.scan_hist(Z64[:, p], y, B, OS.GINI, K)["loss"] for p in range(P)])
+        best = int(np.argmin(lo))
+        hits += int(best in set(sel.tolist()))
+        gaps.append((lo[sel].min() - lo[best]) / lo[best])
+        errs.append(np.abs(scr["loss"].cpu().numpy() - lo) / lo)
+    e = np.concatenate(errs)
+    print(f"screening vs FP64: recall {hits}/2, gap mean {np.mean(gaps):.2e} max "
+          f"{np.max(gaps):.2e}, per-particle error median {np.median(e):.2e} "
+          f"p99 {np.quantile(e, 0.99):.2e} max {e.max():.2e}")
+    assert hits == 2
+    assert max(gaps) <= 1e-3
+    assert np.median(e) <= 1e-3 and e.max() <= 1e-2
