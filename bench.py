@@ -226,12 +226,12 @@ def screening_gpu_check(api, Xd, yd, cfg, n_swarms=4):
     for s in range(n_swarms):
         sw = api.pso_alloc(1, P, D, node_id=[0], w_dtype=torch.bfloat16)
         api.pso_init(sw, seed=100 + s, tree=0)
-        Zs, zmin, zmax = api.project(Xd, sw.W, off, P, tiled=True)
+        Zs, zmin, zmax = api.project(Xd, sw.W, off, P, tiled=8)
         scr = api.split_scan(Zs, zmin, zmax, yd, cfg.K, off, P, cfg.bins, api.GINI)
         del Zs
         sel = api.screen_select(scr["loss"], 1, P, k).cpu().numpy()
         W32 = sw.x.to(torch.float32).contiguous()
-        Zf, fmin, fmax = api.project(Xd, W32, off, P, tiled=True)
+        Zf, fmin, fmax = api.project(Xd, W32, off, P, tiled=8)
         full = api.split_scan(Zf, fmin, fmax, yd, cfg.K, off, P, cfg.bins, api.GINI)
         del Zf
         lf = full["loss"].cpu().numpy()
@@ -420,13 +420,13 @@ def root_evals(api, which, reps, dev):
         return r
 
     for _ in range(reps):
-        Z, zmin, zmax = timed("project", lambda: api.project(Xd, sw.W, off, P, tiled=True))
+        Z, zmin, zmax = timed("project", lambda: api.project(Xd, sw.W, off, P, tiled=8))
         out = timed("scan", lambda: api.split_scan(Z, zmin, zmax, yd, K, off, P, 256, crit))
         if which == "screening":
             sel = api.screen_select(out["loss"], 1, P, 32)
             Wk = api.screen_gather(sw.x, sel, 1, P, 32)
             Zr, rmin, rmax = timed("rescore_project", lambda: api.project(Xd, Wk, off, 32,
-                                                                          tiled=True))
+                                                                          tiled=8))
             timed("rescore_scan", lambda: api.split_scan(Zr, rmin, rmax, yd, K, off, 32, 256,
                                                          crit))
         del Z

@@ -49,13 +49,19 @@ typedef enum { SLM_F32 = 0, SLM_BF16 = 1, SLM_F64 = 2, SLM_I32 = 3 } slm_dtype;
 typedef enum { SLM_GINI = 0, SLM_ENTROPY = 1, SLM_MSE = 2 } slm_criterion;
 
 /* Layout of a projected-feature matrix Z (N rows, P particles per node):
- *   SLM_Z_ROWS  : row-major [N, P]; Z[i, p] at i * P + p.
- *   SLM_Z_TILED : particle-tiled [ceil(P/32), N, 32]; Z[i, p] at
- *                 ((p / 32) * N + i) * 32 + p % 32.  Each 32-particle tile is
- *                 one contiguous [N, 32] block (the scan streams it), and the
- *                 buffer holds ceil(P/32) * 32 * N floats; columns p >= P of
- *                 the last tile are not written. */
-typedef enum { SLM_Z_ROWS = 0, SLM_Z_TILED = 1 } slm_z_layout;
+ *   SLM_Z_ROWS   : row-major [N, P]; Z[i, p] at i * P + p.
+ *   SLM_Z_TILED  : particle-tiled [ceil(P/32), N, 32]; Z[i, p] at
+ *                  ((p / 32) * N + i) * 32 + p % 32.  Each 32-particle tile
+ *                  is one contiguous [N, 32] block, and the buffer holds
+ *                  ceil(P/32) * 32 * N floats; columns p >= P of the last
+ *                  tile are not written.
+ *   SLM_Z_TILED8 : the same with 8-particle tiles, [ceil(P/8), N, 8]; Z[i, p]
+ *                  at ((p / 8) * N + i) * 8 + p % 8 (ceil(P/8) * 8 * N floats).
+ *                  A scan work-group of 8 particles streams whole 32-byte
+ *                  rows of one tile instead of a quarter of each 128-byte
+ *                  row.  Requires 96 N + 8 (N + 64) < 2^31 bytes (N up to
+ *                  about 2.06e7); larger N is refused with SLM_E_INVALID. */
+typedef enum { SLM_Z_ROWS = 0, SLM_Z_TILED = 1, SLM_Z_TILED8 = 2 } slm_z_layout;
 
 /* Library version string (static storage). */
 const char *slm_version(void);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libslm.so")
 
 F32, BF16, F64, I32 = 0, 1, 2, 3
 GINI, ENTROPY, MSE = 0, 1, 2
-Z_ROWS, Z_TILED = 0, 1
+Z_ROWS, Z_TILED, Z_TILED8 = 0, 1, 2
 TIMING_SLOTS = 12   # slm_tree_out.timing entries (SLM_TIMING_SLOTS)
 STATUS = {0: "SLM_OK", 1: "SLM_E_INVALID", 2: "SLM_E_SHAPE", 3: "SLM_E_DTYPE",
           4: "SLM_E_NOMEM", 5: "SLM_E_HIP", 6: "SLM_E_UNSUPPORTED"}
@@ -171,9 +171,18 @@ def _xdtype(X):
 
 
 # ------------------------------------------------------------------ project
-def project(X, W, row_off, P: int, tiled: bool = False):
+def _tile_width(tiled) -> int:
+    """0 (row-major), 32 (tiled=True or 32) or 8."""
+    w = 32 if tiled is True else int(tiled or 0)
+    if w not in (0, 8, 32):
+        raise ValueError("tiled must be False, True (32), 32 or 8")
+    return w
+
+
+def project(X, W, row_off, P: int, tiled=False):
     """Z = per-node X W^T, zmin/zmax [n_nodes*P] (Eq. (1)).  Z is [N, P], or
-    with tiled=True the particle-tiled [ceil(P/32), N, 32] (SLM_Z_TILED).
+    with tiled=True (or 32) the particle-tiled [ceil(P/32), N, 32]
+    (SLM_Z_TILED), with tiled=8 the [ceil(P/8), N, 8] (SLM_Z_TILED8).
     (X, W) dtypes: (float32, float32), (bfloat16, bfloat16) or (bfloat16, float32)."""
     load()
     xt = _xdtype(X)
@@ -183,31 +192,33 @@ def project(X, W, row_off, P: int, tiled: bool = False):
     _dev(row_off, torch.int64, "row_off")
     N, D = X.shape
     nn = row_off.numel() - 1
-    if tiled:
-        Z = torch.empty(((P + 31) // 32, N, 32), dtype=torch.float32, device=X.device)
+    w = _tile_width(tiled)
+    if w:
+        Z = torch.empty(((P + w - 1) // w, N, w), dtype=torch.float32, device=X.device)
     else:
         Z = torch.empty((N, P), dtype=torch.float32, device=X.device)
     zmin = torch.empty(nn * P, dtype=torch.float32, device=X.device)
     zmax = torch.empty_like(zmin)
-    _check(_lib.slm_project(_p(X), xt, N, D, _p(W), wt, _p(row_off), nn, P, _p(Z),
-                            Z_TILED if tiled else Z_ROWS, _p(zmin), _p(zmax), _stream()),
+    zl = {0: Z_ROWS, 32: Z_TILED, 8: Z_TILED8}[w]
+    _check(_lib.slm_project(_p(X), xt, N, D, _p(W), wt, _p(row_off), nn, P, _p(Z), zl,
+                            _p(zmin), _p(zmax), _stream()),
            "slm_project")
     return Z, zmin, zmax
 
 
-def tile_z(Z, P: int):
-    """[N, P] -> particle-tiled [ceil(P/32), N, 32] (padding columns zero)."""
+def tile_z(Z, P: int, w: int = 32):
+    """[N, P] -> particle-tiled [ceil(P/w), N, w] (padding columns zero)."""
     N = Z.shape[0]
-    T = (P + 31) // 32
-    out = Z.new_zeros((N, T * 32))
+    T = (P + w - 1) // w
+    out = Z.new_zeros((N, T * w))
     out[:, :P] = Z
-    return out.view(N, T, 32).permute(1, 0, 2).contiguous()
+    return out.view(N, T, w).permute(1, 0, 2).contiguous()
 
 
 def untile_z(Zt, P: int):
-    """Particle-tiled [ceil(P/32), N, 32] -> [N, P]."""
-    T, N, _ = Zt.shape
-    return Zt.permute(1, 0, 2).reshape(N, T * 32)[:, :P].contiguous()
+    """Particle-tiled [ceil(P/w), N, w] -> [N, P]."""
+    T, N, w = Zt.shape
+    return Zt.permute(1, 0, 2).reshape(N, T * w)[:, :P].contiguous()
 
 
 # ------------------------------------------------------------------ split scan
@@ -228,14 +239,15 @@ def scan_workspace(nbytes: int, device) -> torch.Tensor:
 def split_scan(Z, zmin, zmax, target, K: int, row_off, P: int, bins: int, crit: int,
                hist: bool = False, sums: bool = False):
     """Best threshold per (node, particle); see slm_split_scan.  Z is [N, P]
-    or particle-tiled [ceil(P/32), N, 32]."""
+    or particle-tiled [ceil(P/w), N, w] with w = 32 or 8."""
     load()
     _dev(Z, torch.float32, "Z")
     _dev(row_off, torch.int64, "row_off")
     if Z.dim() == 3:
-        if Z.shape[0] != (P + 31) // 32 or Z.shape[2] != 32:
-            raise ValueError("tiled Z must be [ceil(P/32), N, 32]")
-        N, zl = Z.shape[1], Z_TILED
+        w = Z.shape[2]
+        if w not in (8, 32) or Z.shape[0] != (P + w - 1) // w:
+            raise ValueError("tiled Z must be [ceil(P/w), N, w], w = 32 or 8")
+        N, zl = Z.shape[1], (Z_TILED if w == 32 else Z_TILED8)
     else:
         if Z.dim() != 2 or Z.shape[1] != P:
             raise ValueError("Z must be [N, P]")

@@ -252,17 +252,48 @@ __device__ __forceinline__ void load_run(const void *base, int64_t row, int D, i
   }
 }
 
+// 4 x 4 transpose of 8-lane groups within each 32-lane half of the wave:
+// register i, lane group u (lanes 8u .. 8u+7 of the half) <-> register u,
+// lane group i.  From the matrix-core layout (register 4g + i holds row
+// 8g + i (+4 in the upper half), lane l%32 particle l%32 of the block) this
+// gives register t: row 8g + (l%32)/8 (+4), particle 8t + l%8, so one store
+// per register writes rows 8g .. 8g+7 of the 8-particle tile t, 256
+// contiguous bytes of an 8-wide particle-tiled Z.  Two steps: swap of 8-lane
+// groups inside 16-lane rows (row rotation by 8 and a select), then of
+// 16-lane rows between register pairs (v_permlane16_swap).
+__device__ __forceinline__ void transpose_lane_groups(uint32_t (&a)[4], int lane) {
+  const bool u0 = (lane >> 3) & 1;
+  uint32_t c[4];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const uint32_t e = a[2 * k], o = a[2 * k + 1];
+    const uint32_t ro = __builtin_amdgcn_update_dpp(0u, o, 0x128, 0xf, 0xf, false);   // row_ror:8
+    const uint32_t re = __builtin_amdgcn_update_dpp(0u, e, 0x128, 0xf, 0xf, false);
+    c[2 * k] = u0 ? ro : e;
+    c[2 * k + 1] = u0 ? o : re;
+  }
+#pragma unroll
+  for (int i0 = 0; i0 < 2; ++i0) {
+    const auto r = __builtin_amdgcn_permlane16_swap(c[i0], c[2 + i0], false, false);
+    a[i0] = r[0];
+    a[2 + i0] = r[1];
+  }
+}
+
 // STORE = false: only the per-column min / max (a.Z is not written), the
-// first pass of the fused evaluation.  TILED: Z in the particle-tiled layout,
-// whose row stride (32 floats) is then a constant, so the 16 stores of an
-// accumulator block use immediate offsets from one address.
+// first pass of the fused evaluation.  ZT: the tile width of a particle-tiled
+// Z (32 or 8) as a constant, or 0 (row-major: the stride is read from the
+// layout).  With 32-wide tiles the 16 stores of an accumulator block use
+// immediate offsets from one address; with 8-wide tiles the block is first
+// transposed in registers (transpose_lane_groups) so that every store writes
+// 256 contiguous bytes.
 // The row loop is unrolled twice over two A buffers: the loads of the next
 // sub-tile go to the buffer the current MFMAs do not read.  A node change
 // (flush of the min / max, B fragments of the new node) happens before the
 // next sub-tile's loads are issued, so the MFMAs only wait for the B loads.
 // Full sub-tiles take a straight-line epilogue; sub-tiles cut by a node end or
 // columns past P take a masked one.
-template <int FN, int WAVES, int KSP, bool XB, bool VEC, bool STORE, bool TILED>
+template <int FN, int WAVES, int KSP, bool XB, bool VEC, bool STORE, int ZT>
 __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int64_t RB,
                                                               int blocks_per_pt) {
   constexpr int PTILE = 32 * FN * WAVES;
@@ -280,7 +311,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
   const int li = lane & 31, kh = lane >> 5, k0 = kh * KSP;
   const int pw = pt * PTILE + wave * 32 * FN;   // first particle of this wave
   const bool wave_full = pw + 32 * FN <= P;     // every column of the wave exists
-  const int64_t rs = TILED ? (int64_t)32 : a.zl.rs;
+  const int64_t rs = ZT ? (int64_t)ZT : a.zl.rs;
   const bool do_mm = a.zmin != nullptr;
 
   // first node whose rows reach past r_begin (ends are non-decreasing)
@@ -358,7 +389,19 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
     mma(A, acc);
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
-      if constexpr (STORE) {
+      if constexpr (STORE && ZT == 8) {
+        // register t of group g after the transpose: row 8g + lane/8,
+        // particle 8t + lane%8 of the block
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          uint32_t v[4] = {__float_as_uint(acc[f][4 * g]), __float_as_uint(acc[f][4 * g + 1]),
+                           __float_as_uint(acc[f][4 * g + 2]), __float_as_uint(acc[f][4 * g + 3])};
+          transpose_lane_groups(v, lane);
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            a.Z[z_col(a.zl, pw + f * 32 + 8 * t) + (lo + 8 * g) * 8 + lane] = __uint_as_float(v[t]);
+        }
+      } else if constexpr (STORE) {
         float *zc = a.Z + z_col(a.zl, pw + f * 32 + li) + (lo + 4 * kh) * rs;
 #pragma unroll
         for (int r = 0; r < 16; ++r) zc[(int64_t)(8 * (r >> 2) + (r & 3)) * rs] = acc[f][r];
@@ -380,17 +423,22 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
     f32x16 acc[FN];
     mma(A, acc);
     const int nrow = (int)(c.hi - c.lo);
-    const uint32_t nb = (uint32_t)(nrow * rs * 4);
+    // lane column offset within the block's 32 particles (tiles of 8 put
+    // them in 4 tiles), and the block's span; both < 2^31 bytes (the
+    // layout is checked on the host)
+    const int lcol = (int)z_col(a.zl, li);
+    const uint32_t nb = (uint32_t)((z_col(a.zl, 31) + nrow * rs) * 4);
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
       const bool pin = pw + f * 32 + li < P;
       if constexpr (STORE) {
         const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-            a.Z + (int64_t)((pw >> 5) + f) * a.zl.ts + c.lo * rs, 0, nb, BUF_DW3);
+            a.Z + z_col(a.zl, pw + f * 32) + c.lo * rs, 0, nb, BUF_DW3);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
-          const uint32_t off = pin && row < nrow ? (uint32_t)((row * rs + li) * 4) : 0x80000000u;
+          const uint32_t off =
+              pin && row < nrow ? (uint32_t)((row * (int)rs + lcol) * 4) : 0x80000000u;
           __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(acc[f][r]), zr, (int)off, 0, 0);
         }
       }
@@ -452,26 +500,35 @@ __global__ __launch_bounds__(64 * WAVES) void k_project_short(ProjectArgs a, int
 }
 
 // X float32 or bfloat16, W float32 (both widened exactly to float32)
-template <int FN, int WAVES, int KSP, bool VEC, bool TILED>
+template <int FN, int WAVES, int KSP, bool VEC, int ZT>
 slm_status launch_short_g(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
   const dim3 blk(64 * WAVES);
   if (a.Z == nullptr)   // min / max only (X float32)
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, VEC, false, TILED>),
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, VEC, false, 0>),
                        dim3((unsigned)grid), blk, 0, s, a, RB, bpp);
   else if (a.x_bf16)
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true, VEC, true, TILED>),
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, true, VEC, true, ZT>),
                        dim3((unsigned)grid), blk, 0, s, a, RB, bpp);
   else
-    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, VEC, true, TILED>),
+    hipLaunchKernelGGL((k_project_short<FN, WAVES, KSP, false, VEC, true, ZT>),
                        dim3((unsigned)grid), blk, 0, s, a, RB, bpp);
   SLM_LAUNCHED();
   return SLM_OK;
 }
 
+// the tile width of a particle-tiled Z, 0 for row-major
+inline int z_tile_width(const ZLayout &l) {
+  if (l.rs == 32 && l.sh == 5) return 32;   // (also row-major with P = 32: the same placement)
+  if (l.rs == 8 && l.sh == 3) return 8;
+  return 0;
+}
+
 template <int FN, int WAVES, int KSP, bool VEC>
 slm_status launch_short_k(const ProjectArgs &a, int64_t RB, int bpp, int64_t grid, hipStream_t s) {
-  if (a.zl.rs == 32) return launch_short_g<FN, WAVES, KSP, VEC, true>(a, RB, bpp, grid, s);
-  return launch_short_g<FN, WAVES, KSP, VEC, false>(a, RB, bpp, grid, s);
+  const int zt = z_tile_width(a.zl);
+  if (zt == 32) return launch_short_g<FN, WAVES, KSP, VEC, 32>(a, RB, bpp, grid, s);
+  if (zt == 8) return launch_short_g<FN, WAVES, KSP, VEC, 8>(a, RB, bpp, grid, s);
+  return launch_short_g<FN, WAVES, KSP, VEC, 0>(a, RB, bpp, grid, s);
 }
 
 template <int FN, int WAVES, bool VEC>
@@ -758,7 +815,7 @@ __device__ __forceinline__ uint4 load_group(const void *base, int64_t row, int D
   }
 }
 
-template <int MK, int FN, bool VEC, bool TILED>
+template <int MK, int FN, bool VEC, int ZT>
 __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64_t RB,
                                                             int blocks_per_pt, int n_pt,
                                                             int xcd_map) {
@@ -792,7 +849,7 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
   const int li = lane & 31, kh = lane >> 5;
   const int p0 = pt * PT;
   const bool tile_full = p0 + PT <= P;
-  const int64_t rs = TILED ? (int64_t)32 : a.zl.rs;
+  const int64_t rs = ZT ? (int64_t)ZT : a.zl.rs;
   const bool do_mm = a.zmin != nullptr;
   const int64_t row_bytes = (int64_t)D * XB;
 
@@ -955,10 +1012,29 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
     for (int f = 0; f < FN; ++f) {
       const bool pin = p0 + f * 32 + li < P;
       const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-          a.Z + (int64_t)((p0 >> 5) + f) * a.zl.ts + lo * rs, 0, (int)(n * rs * 4), BUF_DW3);
-      const int vo = (int)((4 * kh * rs + li) * 4);
+          a.Z + z_col(a.zl, p0 + f * 32) + lo * rs, 0, (int)((z_col(a.zl, 31) + n * rs) * 4),
+          BUF_DW3);
+      const int vo = (int)((4 * kh * rs + z_col(a.zl, li)) * 4);
       float l = __builtin_huge_valf(), h = -__builtin_huge_valf();
-      if (full) {
+      if (full && ZT == 8) {
+        // 8-wide tiles: after the transpose, register t of group g holds
+        // rows 8g + lane/8 of tile t (at t * ts), lane%8 its particle
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          l = fminf(l, acc[f][r]);
+          h = fmaxf(h, acc[f][r]);
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          uint32_t v[4] = {__float_as_uint(acc[f][4 * g]), __float_as_uint(acc[f][4 * g + 1]),
+                           __float_as_uint(acc[f][4 * g + 2]), __float_as_uint(acc[f][4 * g + 3])};
+          transpose_lane_groups(v, lane);
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            __builtin_amdgcn_raw_buffer_store_b32(v[t], zr, lane * 4 + 256 * g,
+                                                  (int)(t * a.zl.ts * 4), 0);
+        }
+      } else if (full) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int ro = (int)((8 * (r >> 2) + (r & 3)) * rs * 4);
@@ -1044,11 +1120,15 @@ slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s, int want_xcd = 1
   if (grid == 0) return SLM_OK;
   SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_project: grid too large");
   const size_t lds = stream_lds_bytes(MK, FN);
-  if (a.zl.rs == 32)
-    hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, true>), dim3((unsigned)grid), dim3(64 * SW),
+  const int zt = z_tile_width(a.zl);
+  if (zt == 32)
+    hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, 32>), dim3((unsigned)grid), dim3(64 * SW),
+                       lds, s, a, RB, (int)bpp, n_pt, xcd);
+  else if (zt == 8)
+    hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, 8>), dim3((unsigned)grid), dim3(64 * SW),
                        lds, s, a, RB, (int)bpp, n_pt, xcd);
   else
-    hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, false>), dim3((unsigned)grid), dim3(64 * SW),
+    hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, 0>), dim3((unsigned)grid), dim3(64 * SW),
                        lds, s, a, RB, (int)bpp, n_pt, xcd);
   SLM_LAUNCHED();
   return SLM_OK;
@@ -1111,18 +1191,20 @@ bool stream_eligible(const ProjectArgs &a) {
   return a.D <= stream_kch(mk);
 }
 
-template <int MK, int FN, bool VEC, bool TILED>
+template <int MK, int FN, bool VEC, int ZT>
 void set_stream_attr(int bytes) {
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_project_stream<MK, FN, VEC, TILED>),
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_project_stream<MK, FN, VEC, ZT>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
     (void)hipGetLastError();
 }
 template <int MK, int FN>
 void set_stream_attr_fn(int bytes) {
-  set_stream_attr<MK, FN, true, true>(bytes);
-  set_stream_attr<MK, FN, true, false>(bytes);
-  set_stream_attr<MK, FN, false, true>(bytes);
-  set_stream_attr<MK, FN, false, false>(bytes);
+  set_stream_attr<MK, FN, true, 32>(bytes);
+  set_stream_attr<MK, FN, true, 8>(bytes);
+  set_stream_attr<MK, FN, true, 0>(bytes);
+  set_stream_attr<MK, FN, false, 32>(bytes);
+  set_stream_attr<MK, FN, false, 8>(bytes);
+  set_stream_attr<MK, FN, false, 0>(bytes);
 }
 template <int MK>
 void set_stream_attr_mk(int bytes) {

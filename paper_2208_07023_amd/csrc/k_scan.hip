@@ -36,6 +36,9 @@ namespace {
 
 constexpr int WG = 256;
 
+// a word of the LDS, addressed with a 32-bit LDS pointer
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
 // ---------------------------------------------------------------- binning
 struct BinRule {
   float zmin, delta, inv;
@@ -165,6 +168,7 @@ int64_t chunk_min(int64_t N) {
 // 64-bit words holding two 32-bit counters (bin b low, bin b + 128 high), so
 // one 64-bit atomic merges both halves of an LDS word.
 //   classification: count(b, k, q) in word (b & 127) * SB + k * PT + q, SB = K PT
+//                   (+ 1 for tiles narrower than 32 particles)
 //   regression:     count(b, q) in word (b & 127) * SB + q, SB = PT; sum y and
 //                   sum y^2 at b * PT + q in two double arrays
 struct HistLayout {
@@ -177,7 +181,12 @@ struct HistLayout {
 
 __host__ __device__ __forceinline__ HistLayout hist_layout(int PT, int B, int K, bool mse) {
   HistLayout h;
-  h.SB = mse ? PT : K * PT;
+  // A tile narrower than the 32 banks leaves the bin index to spread a
+  // wave's atomics over the banks: with SB = K PT (a multiple of 8) the rows'
+  // random bins land on only 32 / gcd(SB, 32) banks per particle, so the
+  // classification stride is made odd (bins spread over all 32 banks).  A
+  // 32-wide tile maps lanes to banks by particle and keeps SB = 32 K.
+  h.SB = mse ? PT : K * PT + (PT < 32 ? 1 : 0);
   h.BH = B < 128 ? B : 128;
   h.nwords = h.BH * h.SB;
   h.lds_cnt = ((size_t)h.nwords * 4 + 15) / 16 * 16;
@@ -442,7 +451,7 @@ __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &
   constexpr int SEGMAX = (256 + NSEG - 1) / NSEG;
   const int B = a.bins;
   const int K = MSE ? 1 : a.K;
-  const int SB = MSE ? PT : K * PT;
+  const int SB = hist_layout(PT, B, K, MSE).SB;
   const int P = a.P;
   const int SEGB = (B + NSEG - 1) / NSEG;
   const int seg = tid / NQ, q = tid % NQ, qt = q0 + q;   // qt: particle within the tile
@@ -750,7 +759,7 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
     const float off0 = -fmaf(zmin, inv, 0.005f);
     const unsigned bmax = (unsigned)B - 1u;
     const unsigned labk = pv ? (unsigned)K : 0u;
-    const uint32_t pt4 = PT * 4u, pl4 = (uint32_t)pl * 4u;
+    const uint32_t pt4 = PT * 4u, sb4 = (uint32_t)SB * 4u, pl4 = (uint32_t)pl * 4u;
     unsigned char *hb = reinterpret_cast<unsigned char *>(hc);
     auto bin_fast = [&](float zu) -> unsigned {
       const int g0 = (int)fmaf(zu, inv, off0);
@@ -763,11 +772,16 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
     // rows of at most 4096 floats from the base (< 2^31 bytes).
     const int64_t rbase = it.lo + (int64_t)wave * RPW;     // this wave's first row
     const int rs = (int)a.zl.rs;
-    const int64_t zspan = (it.hi - rbase) * rs * 4 + 128;
+    // base: the Z tile holding the work-group's first particle (tiles of 8
+    // put a work-group's particles into up to 4 tiles, at lane offsets)
+    const int t0p = (pt * PT) & ~((1 << a.zl.sh) - 1);
+    const int64_t c0 = z_col(a.zl, t0p);
+    const int plast = min(pt * PT + PT, P) - 1;
+    const int64_t zspan = (z_col(a.zl, plast) - c0 + 1 + (it.hi - rbase) * rs) * 4;
     const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float *>(a.Z + z_col(a.zl, (pt * PT) & ~31) + rbase * rs), 0,
+        const_cast<float *>(a.Z + c0 + rbase * rs), 0,
         (int)(zspan < 0x7FFFFFFF ? zspan : 0x7FFFFFFF), BUF_DW3);
-    const int zvo = ((pcl & 31) + rsub * rs) * 4, zso = (int)(step * rs * 4);
+    const int zvo = (int)((z_col(a.zl, pcl) - c0 + rsub * rs) * 4), zso = (int)(step * rs * 4);
     const __amdgpu_buffer_rsrc_t lr = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<int32_t *>(a.labels ? a.labels + rbase : nullptr), 0,
         MSE ? 0 : (int)((it.hi - rbase) * 4), BUF_DW3);
@@ -790,7 +804,7 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
         } else {
           const unsigned lb = min((unsigned)lab[u], (unsigned)K - 1u);
           const uint32_t inc = (unsigned)lab[u] < labk ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
-          const uint32_t off = __umul24(__umul24(g & 127u, (unsigned)K) + lb, pt4) + pl4;
+          const uint32_t off = __umul24(g & 127u, sb4) + __umul24(lb, pt4) + pl4;
           atomicAdd(reinterpret_cast<uint32_t *>(hb + off), inc);
         }
       }
@@ -804,12 +818,25 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
   }
 }
 
-// Four consecutive particles per lane (classification, particle-tiled Z):
-// lane (q, r) takes particles 4q .. 4q+3 of the tile and rows r, r + 64/(PT/4),
-// ... of the wave's steps.  Per row: one 16-byte buffer load of the four
-// projections, one label load, and the label's part of the LDS address; per
-// sample-split: the branch-free bin (as in accumulate_rows1) and one LDS
-// atomic at an immediate offset.  Eight rows are in flight per lane.
+// Four consecutive particles per lane (classification, particle-tiled Z with
+// tiles of 8 or 32): lane (q, r) takes particles 4q .. 4q+3 of the tile and
+// rows r, r + 64/(PT/4), ... of the wave's steps.  Per row: one 16-byte
+// buffer load of the four projections, one label load, and the label's part
+// of the LDS address and increment; per sample-split: the branch-free bin and
+// one LDS atomic at an immediate offset.
+//
+// Fast path (every particle of the tile exists and every edge rule is well
+// conditioned): the guess is taken one bin up, g1 = trunc(z B / r -
+// (zmin B / r + 0.005) + 1) in one fused multiply-add with the constant
+// rounded once, and the bin is g1 - 1 + [e_{g1} <= z], clamped to B - 1.
+// Against the guess of accumulate_rows1 the constant's rounding and the
+// larger result add at most B u (1 + |zmin| / r) + u bins, so the guess stays
+// within B u (7 + 4 |zmin| / r) <= 4.0e-3 < 0.005 bins of the count of edges
+// <= z (u = 2^-24, |zmin| <= 64 r, B <= 256): g1 - 1 is the bin or the one
+// below, g1 >= 0, and e_0 = zmin <= z keeps g1 = 0 at bin 0.  A label outside
+// [0, K) keeps the row's address in range and adds 0 (the row's increment
+// multipliers are zero).  Rows are taken U4 at a time: loads, then every
+// bin and address, then the atomics.
 template <int PT, int WGS>
 __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &it, int pt,
                                                  int64_t np, int wave, int lane,
@@ -823,7 +850,7 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
   const int64_t row4 = rb4 + r4;
   const int n4 = (int)((it.hi - row4 + step4 - 1) / step4);   // rows of this lane (may be <= 0)
   BinRule rl[4];
-  float zm[4], dl[4], iv[4], o0[4];
+  float zm[4], dl[4], iv[4], o1[4];
   bool pv4[4];
   bool lane_fast = true;
 #pragma unroll
@@ -831,45 +858,38 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
     const int pe = pt * PT + 4 * q4 + e;
     pv4[e] = pe < P;
     rl[e] = make_rule(pv4[e] ? a.zmin[np + pe] : 0.f, pv4[e] ? a.zmax[np + pe] : 0.f, B);
-    lane_fast = lane_fast && (rl[e].fast || !pv4[e]);
+    lane_fast = lane_fast && rl[e].fast;
     zm[e] = rl[e].zmin;
     dl[e] = rl[e].delta;
     iv[e] = rl[e].inv;
-    o0[e] = -fmaf(zm[e], iv[e], 0.005f);
+    o1[e] = __fadd_rn(-fmaf(zm[e], iv[e], 0.005f), 1.0f);
   }
-  const bool wave_fast = __all(lane_fast);
+  // uniform: the tile is full and every lane's rules are fast
+  const bool wave_fast = __all(lane_fast) && (pt + 1) * PT <= P;
   const unsigned bmax = (unsigned)B - 1u;
-  const uint32_t sb4 = (uint32_t)SB * 4u;
-  // Z: rows of the 32-particle tile holding this work-group's particles, from
-  // the wave's first row (at most CH_MAX rows of 128 bytes); labels from it
-  const int64_t zspan = (it.hi - rb4) * 128 + 128;
+  const uint32_t sb4 = (uint32_t)SB * 4u, pt4 = (uint32_t)PT * 4u, q16 = 16u * (uint32_t)q4;
+  // Z from the tile holding the work-group's first particle, at the wave's
+  // first row; each lane adds its four particles' tile and column offset (a
+  // lane past P reads the last existing group of four, whose counts it never
+  // adds).  Offsets stay below 2^31 bytes: the layout is checked on the host.
+  const int rs = (int)a.zl.rs;
+  const int t0p = (pt * PT) & ~((1 << a.zl.sh) - 1);
+  const int64_t c0 = z_col(a.zl, t0p);
+  const int pa = min(pt * PT + 4 * q4, (P - 1) & ~3);
+  const int plast = min(pt * PT + PT, P) - 1;
+  const int64_t zspan = (z_col(a.zl, plast) - c0 + 1 + (it.hi - rb4) * rs) * 4;
   const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float *>(a.Z + z_col(a.zl, (pt * PT) & ~31) + rb4 * 32), 0,
+      const_cast<float *>(a.Z + c0 + rb4 * rs), 0,
       (int)(zspan < 0x7FFFFFFF ? zspan : 0x7FFFFFFF), BUF_DW3);
-  const int zvo = (((pt * PT) & 31) + 4 * q4 + r4 * 32) * 4, zso = (int)(step4 * 128);
+  const int zvo = (int)((z_col(a.zl, pa) - c0 + (int64_t)r4 * rs) * 4);
+  const int zso = (int)(step4 * rs * 4);
   const __amdgpu_buffer_rsrc_t lr = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<int32_t *>(a.labels + rb4), 0, (int)((it.hi - rb4) * 4), BUF_DW3);
   const int lvo = r4 * 4, lso = (int)(step4 * 4);
-  // one row: its four projections and its label
-  auto add_row = [&](const uint32_t (&zw)[4], int lab, bool fast) {
-    const bool lok = (unsigned)lab < (unsigned)K;
-    const uint32_t base = ((uint32_t)(lok ? lab : 0) * PT + 4u * q4) * 4u;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const float z = __uint_as_float(zw[e]);
-      unsigned g;
-      if (fast) {
-        const int g0 = (int)fmaf(z, iv[e], o0[e]);
-        const float e1 = __fadd_rn(zm[e], __fmul_rn((float)(g0 + 1), dl[e]));
-        g = min((unsigned)(g0 + (e1 <= z ? 1 : 0)), bmax);
-      } else {
-        g = (unsigned)bin_of(rl[e], z);
-      }
-      const uint32_t inc = lok && pv4[e] ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
-      atomicAdd(reinterpret_cast<uint32_t *>(hb + __umul24(g & 127u, sb4) + base + 4u * e), inc);
-    }
-  };
-  constexpr int U4 = 8;
+  // LDS byte address of the histogram (32-bit LDS pointers: the address of
+  // a sample-split is one 24-bit multiply-add)
+  const uint32_t hbase = (uint32_t)(uintptr_t)(lds_u32 *)hb;
+  constexpr int U4 = 4;
   int i = 0;
   if (wave_fast) {
     for (; i + U4 <= n4; i += U4) {
@@ -884,15 +904,43 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
         zw[u][3] = v[3];
         lab[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, (i + u) * lso, 0);
       }
+      uint32_t ad[U4][4], in[U4][4];
 #pragma unroll
-      for (int u = 0; u < U4; ++u) add_row(zw[u], lab[u], true);
+      for (int u = 0; u < U4; ++u) {
+        const bool lok = (unsigned)lab[u] < (unsigned)K;
+        const uint32_t base = __umul24(lok ? (uint32_t)lab[u] : 0u, pt4) + (hbase + q16);
+        const uint32_t m16 = lok ? 0xFFFFu : 0u, m1 = lok ? 1u : 0u;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float z = __uint_as_float(zw[u][e]);
+          const int g1 = (int)fmaf(z, iv[e], o1[e]);
+          const float eg = __fadd_rn(zm[e], __fmul_rn((float)g1, dl[e]));
+          const unsigned g = min((unsigned)(g1 - 1 + (eg <= z ? 1 : 0)), bmax);
+          ad[u][e] = __umul24(g & 127u, sb4) + base;
+          in[u][e] = __umul24(g >> 7, m16) + m1;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)ad[u][e] + e, in[u][e], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
+  // remaining rows (all rows when a rule is ill conditioned or the tile is
+  // partial): exact bins, and nothing added for particles past P
   for (; i < n4; ++i) {
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(zr, zvo, i * zso, 0);
-    const uint32_t zw[4] = {v[0], v[1], v[2], v[3]};
     const int lab = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, i * lso, 0);
-    add_row(zw, lab, wave_fast);
+    const bool lok = (unsigned)lab < (unsigned)K;
+    const uint32_t base = ((uint32_t)(lok ? lab : 0) * PT + 4u * q4) * 4u;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned g = (unsigned)bin_of(rl[e], __uint_as_float(v[e]));
+      const uint32_t inc = lok && pv4[e] ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
+      atomicAdd(reinterpret_cast<uint32_t *>(hb + __umul24(g & 127u, sb4) + base + 4u * e), inc);
+    }
   }
 }
 
@@ -956,7 +1004,7 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   // four consecutive particles of one row, so one 16-byte load of the row's
   // Z segment and one label load serve four sample-splits, and the label's
   // part of the LDS address is formed once per row.
-  if (!MSE && a.zl.rs == 32) {
+  if (!MSE && a.zl.rs == (1 << a.zl.sh) && a.zl.rs >= 8) {
     accumulate_rows4<PT, WGS>(a, it, pt, np, wave, lane, reinterpret_cast<unsigned char *>(hc), SB);
   } else {
     accumulate_rows1<PT, WGS, MSE>(a, it, p, pv, pl, rsub, wave, rule, hc, hs1, hs2, SB, SD);
@@ -1088,7 +1136,7 @@ __global__ __launch_bounds__(256) void k_scan_finish_bins(ScanArgs a, int PT, in
   }
   const Range r = load_range(co.beg, co.end, lo, co.N);
   if (r.hi <= r.lo || r.lo / CH != slot || (r.hi - 1) / CH == slot) return;
-  const int B = a.bins, K = a.K, SB = K * PT;
+  const int B = a.bins, K = a.K, SB = hist_layout(PT, B, K, false).SB;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const bool ent = a.crit == SLM_ENTROPY;
   if (ent) fill_log_table(lgt, lgt + LG_TBL, tid);
@@ -1313,7 +1361,7 @@ void k_fused_hist(ScanArgs a, const float *X, const float *W, int D, int64_t CH,
   const float off0 = -fmaf(zmin, inv, 0.005f);
   const unsigned bmax = (unsigned)B - 1u;
   const unsigned labk = pv ? (unsigned)K : 0u;
-  const uint32_t pt4 = PT * 4u, pl4 = (uint32_t)li * 4u;
+  const uint32_t pt4 = PT * 4u, sb4 = (uint32_t)hl.SB * 4u, pl4 = (uint32_t)li * 4u;
   unsigned char *hb = reinterpret_cast<unsigned char *>(hc);
   const int nsub = (int)((it.hi - it.lo + 31) / 32);
 
@@ -1346,7 +1394,7 @@ void k_fused_hist(ScanArgs a, const float *X, const float *W, int D, int64_t CH,
       }
       const unsigned lb = min((unsigned)lab, (unsigned)K - 1u);
       const uint32_t inc = (rin && (unsigned)lab < labk) ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
-      const uint32_t off = __umul24(__umul24(g & 127u, (unsigned)K) + lb, pt4) + pl4;
+      const uint32_t off = __umul24(g & 127u, sb4) + __umul24(lb, pt4) + pl4;
       atomicAdd(reinterpret_cast<uint32_t *>(hb + off), inc);
     }
   }

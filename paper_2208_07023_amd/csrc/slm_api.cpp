@@ -590,7 +590,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pr.X = Xc; pr.x_bf16 = scr; pr.w_bf16 = scr; pr.N = N; pr.D = D; pr.W = w.W; pr.beg = w.beg;
   pr.end = ends;
   pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
-  pr.zl = zlayout_of(1, N, p.P);
+  pr.zl = zlayout_of(grow_z_layout(N), N, p.P);
   pr.vpre = vrows > 0 ? w.vpre : nullptr;
   ScanArgs sa{};
   sa.Z = w.Z; sa.zl = pr.zl; sa.zmin = w.zmin; sa.zmax = w.zmax;
@@ -608,7 +608,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   ScanArgs sar = sa;
   if (scr) {
     prr.x_bf16 = 1; prr.w_bf16 = 0; prr.W = w.W32; prr.P = k; prr.Z = w.Zr;
-    prr.zmin = w.zmin_r; prr.zmax = w.zmax_r; prr.zl = zlayout_of(1, N, k);
+    prr.zmin = w.zmin_r; prr.zmax = w.zmax_r; prr.zl = zlayout_of(grow_z_layout(N), N, k);
     sar.Z = w.Zr; sar.zl = prr.zl; sar.zmin = w.zmin_r; sar.zmax = w.zmax_r; sar.P = k;
     sar.best_split = w.split_r; sar.best_loss = w.loss_r; sar.threshold = w.thr_r;
   }
@@ -797,8 +797,10 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, con
                 (w_dtype == SLM_F32 || w_dtype == SLM_BF16) &&
                 !(x_dtype == SLM_F32 && w_dtype == SLM_BF16),
             SLM_E_DTYPE, "slm_project: (X, W) must be (F32, F32), (BF16, BF16) or (BF16, F32)");
-  SLM_CHECK(z_layout == SLM_Z_ROWS || z_layout == SLM_Z_TILED, SLM_E_INVALID,
-            "slm_project: bad Z layout %d", z_layout);
+  SLM_CHECK(z_layout == SLM_Z_ROWS || z_layout == SLM_Z_TILED || z_layout == SLM_Z_TILED8,
+            SLM_E_INVALID, "slm_project: bad Z layout %d", z_layout);
+  SLM_CHECK(z_layout != SLM_Z_TILED8 || zlayout_fits(zlayout_of(2, N, P), 65536), SLM_E_INVALID,
+            "slm_project: N = %lld too large for SLM_Z_TILED8", (long long)N);
   if (N == 0 || n_nodes == 0) return SLM_OK;
   SLM_CHECK(X && W && row_off && Z && zmin && zmax, SLM_E_INVALID, "slm_project: NULL pointer");
   slm_status st = prepare_kernels();
@@ -808,7 +810,7 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, con
   a.X = X; a.x_bf16 = x_dtype == SLM_BF16; a.w_bf16 = w_dtype == SLM_BF16; a.N = N; a.D = D;
   a.W = W;
   a.beg = row_off; a.end = row_off + 1; a.n_nodes = n_nodes; a.P = P;
-  a.Z = Z; a.zl = zlayout_of(z_layout == SLM_Z_TILED, N, P); a.zmin = zmin; a.zmax = zmax;
+  a.Z = Z; a.zl = zlayout_of(z_layout, N, P); a.zmin = zmin; a.zmax = zmax;
   return launch_project(a, S(stream));
 }
 
@@ -831,8 +833,10 @@ slm_status slm_split_scan(const float *Z, int32_t z_layout, const float *zmin, c
   SLM_CHECK(bins == 0 || (bins >= 2 && bins <= 256), SLM_E_SHAPE,
             "slm_split_scan: bins = %d (0 or 2..256)", bins);
   SLM_CHECK(crit >= 0 && crit <= 2, SLM_E_INVALID, "slm_split_scan: bad criterion %d", crit);
-  SLM_CHECK(z_layout == SLM_Z_ROWS || z_layout == SLM_Z_TILED, SLM_E_INVALID,
-            "slm_split_scan: bad Z layout %d", z_layout);
+  SLM_CHECK(z_layout == SLM_Z_ROWS || z_layout == SLM_Z_TILED || z_layout == SLM_Z_TILED8,
+            SLM_E_INVALID, "slm_split_scan: bad Z layout %d", z_layout);
+  SLM_CHECK(z_layout != SLM_Z_TILED8 || zlayout_fits(zlayout_of(2, N, P), 65536), SLM_E_INVALID,
+            "slm_split_scan: N = %lld too large for SLM_Z_TILED8", (long long)N);
   if (crit == SLM_MSE) {
     SLM_CHECK(t_dtype == SLM_F64, SLM_E_DTYPE, "slm_split_scan: SLM_MSE needs an F64 target");
     SLM_CHECK(K == 0, SLM_E_SHAPE, "slm_split_scan: K must be 0 for SLM_MSE");
@@ -858,7 +862,7 @@ slm_status slm_split_scan(const float *Z, int32_t z_layout, const float *zmin, c
   slm_status pst = prepare_kernels();
   if (pst) return pst;
   ScanArgs a{};
-  a.Z = Z; a.zl = zlayout_of(z_layout == SLM_Z_TILED, N, P); a.zmin = zmin; a.zmax = zmax;
+  a.Z = Z; a.zl = zlayout_of(z_layout, N, P); a.zmin = zmin; a.zmax = zmax;
   a.labels = crit == SLM_MSE ? nullptr : static_cast<const int32_t *>(target);
   a.y = crit == SLM_MSE ? static_cast<const double *>(target) : nullptr;
   a.K = K; a.N = N; a.beg = row_off; a.end = row_off + 1; a.n_nodes = n_nodes; a.P = P;

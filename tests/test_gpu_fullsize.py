@@ -31,8 +31,9 @@ def _t(a):
 
 
 def _col(Zt, p):
-    """Column p of a particle-tiled Z [ceil(P/32), N, 32] (host float32)."""
-    return Zt[p // 32, :, p % 32].cpu().numpy()
+    """Column p of a particle-tiled Z [ceil(P/w), N, w] (host float32)."""
+    w = Zt.shape[2]
+    return Zt[p // w, :, p % w].cpu().numpy()
 
 
 def _project64(Xf32, w, chunk=1 << 20):
@@ -59,7 +60,7 @@ def test_plain_tree_root_full_size(gpu_lib):
     sw = api.pso_alloc(1, P, D, node_id=[0])
     api.pso_init(sw, seed=0, tree=0)
     off = _t(np.array([0, N], np.int64))
-    Z, zmin, zmax = api.project(_t(X), sw.W, off, P, tiled=True)
+    Z, zmin, zmax = api.project(_t(X), sw.W, off, P, tiled=8)
     out = api.split_scan(Z, zmin, zmax, _t(y), K, off, P, 256, api.ENTROPY, hist=True)
     W = sw.W.cpu().numpy()
     counts = out["counts"].cpu().numpy()
@@ -81,7 +82,7 @@ def test_regression_root_full_size(gpu_lib):
     sw = api.pso_alloc(1, P, D, node_id=[0])
     api.pso_init(sw, seed=1, tree=0)
     off = _t(np.array([0, N], np.int64))
-    Z, zmin, zmax = api.project(_t(X), sw.W, off, P, tiled=True)
+    Z, zmin, zmax = api.project(_t(X), sw.W, off, P, tiled=8)
     out = api.split_scan(Z, zmin, zmax, _t(y), 0, off, P, 256, api.MSE, hist=True)
     W = sw.W.cpu().numpy()
     for p in (3, 500):
@@ -102,11 +103,11 @@ def test_bf16_screening_root_full_size(gpu_lib):
     api.pso_init(sw, seed=2, tree=0)
     off = _t(np.array([0, N], np.int64))
     yd = _t(y)
-    Zs, zmin, zmax = api.project(Xd, sw.W, off, P, tiled=True)
+    Zs, zmin, zmax = api.project(Xd, sw.W, off, P, tiled=8)
     scr = api.split_scan(Zs, zmin, zmax, yd, K, off, P, 256, api.GINI)
     sel = api.screen_select(scr["loss"], 1, P, k)
     Wk = api.screen_gather(sw.x, sel, 1, P, k)
-    Zr, rmin, rmax = api.project(Xd, Wk, off, k, tiled=True)
+    Zr, rmin, rmax = api.project(Xd, Wk, off, k, tiled=8)
     res = api.split_scan(Zr, rmin, rmax, yd, K, off, k, 256, api.GINI)
     loss_s = scr["loss"].cpu().numpy().copy()
     split_s = scr["split"].cpu().numpy().copy()

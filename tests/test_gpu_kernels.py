@@ -25,7 +25,7 @@ def _t(a, dtype=None):
 
 
 # ------------------------------------------------------------------ projection
-@pytest.mark.parametrize("tiled", [False, True])
+@pytest.mark.parametrize("tiled", [False, True, 8])
 @pytest.mark.parametrize("D,P,sizes", [
     (8, 32, [1000]),
     (16, 20, [45, 64, 0, 3]),
@@ -43,7 +43,8 @@ def test_project_integer_inputs_bit_exact(gpu_lib, D, P, sizes, tiled):
     W = inputs.integer_matrix(nn * P, D, -4, 4, seed=D * P + 1)
     Z, zmin, zmax = api.project(_t(X), _t(W), _t(off), P, tiled=tiled)
     if tiled:
-        assert Z.shape == ((P + 31) // 32, N, 32)
+        w = 32 if tiled is True else tiled
+        assert Z.shape == ((P + w - 1) // w, N, w)
         Z = api.untile_z(Z, P)
     torch.cuda.synchronize()
     Z, zmin, zmax = Z.cpu().numpy(), zmin.cpu().numpy(), zmax.cpu().numpy()
@@ -115,7 +116,7 @@ def _scan_case(api, sizes, P, B, crit, K, kind, seed, tiled=False):
         if sizes[j]:
             zmin[j * P:(j + 1) * P] = Z[off[j]:off[j + 1]].min(0)
             zmax[j * P:(j + 1) * P] = Z[off[j]:off[j + 1]].max(0)
-    Zd = api.tile_z(_t(Z), P) if tiled else _t(Z)
+    Zd = api.tile_z(_t(Z), P, 32 if tiled is True else tiled) if tiled else _t(Z)
     out = api.split_scan(Zd, _t(zmin), _t(zmax), _t(tgt, tt), K if crit != OS.MSE else 0,
                          _t(off), P, B, crit, hist=True, sums=crit == OS.MSE)
     torch.cuda.synchronize()
@@ -124,7 +125,7 @@ def _scan_case(api, sizes, P, B, crit, K, kind, seed, tiled=False):
     return got, ref
 
 
-@pytest.mark.parametrize("tiled", [False, True])
+@pytest.mark.parametrize("tiled", [False, True, 8])
 @pytest.mark.parametrize("crit", [OS.GINI, OS.ENTROPY])
 @pytest.mark.parametrize("B,K,P,kind", [
     (256, 3, 32, "gauss"), (256, 2, 8, "dups"), (16, 10, 20, "gauss"), (2, 3, 5, "gauss"),
@@ -148,7 +149,8 @@ def test_hist_scan_classification_exact(gpu_lib, crit, B, K, P, kind, tiled):
 @pytest.mark.parametrize("crit", [OS.GINI, OS.ENTROPY])
 @pytest.mark.parametrize("B,K,P,kind,tiled", [
     (256, 3, 32, "gauss", True), (16, 10, 20, "gauss", False), (3, 4, 64, "dups", True),
-    (100, 16, 3, "gauss", True), (256, 2, 40, "const", False),
+    (100, 16, 3, "gauss", True), (256, 2, 40, "const", False), (256, 10, 44, "gauss", 8),
+    (64, 3, 17, "dups", 8),
 ])
 def test_hist_scan_classification_large_node(gpu_lib, crit, B, K, P, kind, tiled):
     # a node of many chunks among few nodes: finished one bin per thread
@@ -165,7 +167,7 @@ def test_hist_scan_classification_large_node(gpu_lib, crit, B, K, P, kind, tiled
         assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("tiled", [False, True])
+@pytest.mark.parametrize("tiled", [False, True, 8])
 @pytest.mark.parametrize("B,P,kind", [(256, 16, "gauss"), (64, 33, "dups"), (7, 4, "gauss")])
 def test_hist_scan_regression(gpu_lib, B, P, kind, tiled):
     sizes = [0, 2, 45, 4500, 600]
@@ -182,6 +184,52 @@ def test_hist_scan_regression(gpu_lib, B, P, kind, tiled):
         assert abs(got["loss"][i] - ref["loss"][i]) <= 1e-9 * abs(ref["loss"][i])
 
 
+def _assert_scan_matches(got, ref, crit):
+    assert np.array_equal(got["counts"].astype(np.int64), ref["counts"])
+    fin = np.isfinite(ref["loss"])
+    assert np.array_equal(np.isfinite(got["loss"]), fin)
+    if crit == OS.MSE:
+        assert np.allclose(got["sums"], ref["sums"], rtol=1e-12, atol=1e-9)
+        assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-9, atol=1e-12)
+        for i in np.nonzero(got["split"] != ref["split"])[0]:
+            assert abs(got["loss"][i] - ref["loss"][i]) <= 1e-9 * abs(ref["loss"][i])
+        return
+    assert np.array_equal(got["split"], ref["split"])
+    assert np.array_equal(got["thr"], ref["thr"])
+    if crit == OS.GINI:
+        assert np.array_equal(got["loss"][fin], ref["loss"][fin])
+    else:
+        assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("w", [8, 32])
+@pytest.mark.parametrize("crit,K", [(OS.GINI, 3), (OS.ENTROPY, 10), (OS.MSE, 0)])
+def test_hist_scan_every_tile_width(gpu_lib, tmp_path, w, crit, K):
+    """Every work-group particle tile (4, 8, 16, 32; plans forced through the
+    plan cache) reads Z in the 8- and 32-particle layouts: P = 44 leaves a
+    ragged last tile, the 5000-row node spans five 1024-row chunks."""
+    import json
+    api = gpu_lib
+    sizes = [0, 1, 37, 5000, 301]
+    P, B = 44, 256
+    N = sum(sizes)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    kk = 1 if crit == OS.MSE else K
+    key = f"scan/{arch}/N{N}/n8/P{P}/B{B}/K{kk}/c{crit}"
+    kt = 5 if crit == OS.MSE else (K if K <= 4 else (8 if K <= 8 else 16))
+    for pt in (4, 8, 16, 32):
+        if pt * kt > 128:
+            continue
+        path = tmp_path / f"plans_{pt}.json"
+        path.write_text(json.dumps({"plans": {key: [pt, 1024]}}))
+        try:
+            assert api.autotune(1, str(path)) == 1
+            got, ref = _scan_case(api, sizes, P, B, crit, K, "gauss", seed=pt + w, tiled=w)
+        finally:
+            api.autotune(1)
+        _assert_scan_matches(got, ref, crit)
+
+
 @pytest.mark.parametrize("sizes", [[9000, 3000], [40000]])
 def test_hist_scan_reuses_zeroed_workspace(gpu_lib, sizes):
     """Two calls in a row on the same workspace (multi-chunk nodes, both
@@ -196,7 +244,7 @@ def test_hist_scan_reuses_zeroed_workspace(gpu_lib, sizes):
 # ------------------------------------------------------------------ exact scan
 @pytest.mark.parametrize("crit,K", [(OS.GINI, 2), (OS.ENTROPY, 5), (OS.MSE, 0)])
 @pytest.mark.parametrize("kind,P,tiled", [("gauss", 32, False), ("dups", 32, False),
-                                          ("gauss", 40, True)])
+                                          ("gauss", 40, True), ("dups", 21, 8)])
 def test_exact_scan(gpu_lib, crit, K, kind, P, tiled):
     sizes = [1000, 0, 1, 2, 333]
     got, ref = _scan_case(gpu_lib, sizes, P, 0, crit, K, kind, seed=17 + crit, tiled=tiled)

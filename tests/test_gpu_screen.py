@@ -37,7 +37,7 @@ def _bf16(a):
 
 
 # ------------------------------------------------------------------ projections
-@pytest.mark.parametrize("tiled", [False, True])
+@pytest.mark.parametrize("tiled", [False, True, 8])
 @pytest.mark.parametrize("D,P,sizes", [
     (8, 32, [1000]),
     (64, 256, [0, 1, 130, 777, 2]),
@@ -286,7 +286,7 @@ def test_screening_report_against_fp64_oracle(gpu_lib):
         api.pso_init(sw, seed=seed, tree=0)
         # the same Box-Muller start up to the libraries' ulps
         assert np.allclose(sw.x.cpu().numpy(), x, rtol=0, atol=1e-14)
-        Zs, zmin, zmax = api.project(Xd, sw.W, off, P, tiled=True)
+        Zs, zmin, zmax = api.project(Xd, sw.W, off, P, tiled=8)
         scr = api.split_scan(Zs, zmin, zmax, yd, K, off, P, B, api.GINI)
         sel = api.screen_select(scr["loss"], 1, P, k).cpu().numpy()
         del Zs

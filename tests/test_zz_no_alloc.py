@@ -27,7 +27,8 @@ def _noalloc(Z, zmin, zmax, y, K, off, P, bins, crit):
     thr = torch.empty(nn * P, dtype=torch.float32, device=Z.device)
     kk = max(K, 1)
     hist = torch.empty(nn * P * bins * kk, dtype=torch.int32, device=Z.device)
-    st = lib.slm_split_scan_noalloc(api._p(Z), api.Z_TILED if tiled else api.Z_ROWS, api._p(zmin),
+    zl = (api.Z_TILED if Z.shape[2] == 32 else api.Z_TILED8) if tiled else api.Z_ROWS
+    st = lib.slm_split_scan_noalloc(api._p(Z), zl, api._p(zmin),
                                     api._p(zmax), api._p(y), api.F64 if crit == api.MSE else api.I32,
                                     K, N, api._p(off), nn, P, bins, crit, api._p(split),
                                     api._p(loss), api._p(thr), api._p(hist), None,
