@@ -592,6 +592,7 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
   pr.zl = zlayout_of(grow_z_layout(N), N, p.P);
   pr.vpre = vrows > 0 ? w.vpre : nullptr;
+  pr.rows = vrows > 0 ? vrows : 0;
   ScanArgs sa{};
   sa.Z = w.Z; sa.zl = pr.zl; sa.zmin = w.zmin; sa.zmax = w.zmax;
   sa.labels = mse ? nullptr : static_cast<const int32_t *>(tc);

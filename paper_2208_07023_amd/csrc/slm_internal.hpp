@@ -193,6 +193,9 @@ struct ProjectArgs {
   // device).  Work is then split over the nodes' rows alone, as if they
   // were contiguous, instead of over [0, N).
   const int64_t *vpre;
+  // with vpre: a host-side bound on those rows (the shape class of the
+  // launch in the plan cache); 0 otherwise
+  int64_t rows;
 };
 slm_status launch_project(const ProjectArgs &a, hipStream_t s);
 slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s);
