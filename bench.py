@@ -151,12 +151,12 @@ def headline(api, args, dev):
     ss_p, ssr_p = int(prof["sample_splits"][0]), int(prof["sample_splits"][1])
     rows_p = ss_p / cfg.P                      # row-evaluations of the tree
     k = cfg.rescore_k
-    # algorithmic bytes: the screened projection writes 4 B of Z per
-    # sample-split and reads each row's 2 D bytes of X once; the scan reads
-    # 4 B of Z per sample-split and each row's 4-byte label once
-    proj_bytes = 4.0 * ss_p + rows_p * 2 * D
+    # algorithmic bytes: the screened projection writes 2 B of bfloat16 Z
+    # per sample-split and reads each row's 2 D bytes of X once; the scan
+    # reads 2 B of Z per sample-split and each row's 4-byte label once
+    proj_bytes = 2.0 * ss_p + rows_p * 2 * D
     proj_flops = 2.0 * D * ss_p
-    scan_bytes = 4.0 * ss_p + 4.0 * rows_p
+    scan_bytes = 2.0 * ss_p + 4.0 * rows_p
     rproj_flops = 2.0 * D * ssr_p
     rscan_bytes = 4.0 * ssr_p + 4.0 * rows_p
     n_proj, n_scan, n_rp, n_rs = (max(1, int(tm[i])) for i in (6, 7, 10, 11))
@@ -186,17 +186,19 @@ def headline(api, args, dev):
             "frac": proj_gbs / HBM_PEAK_GBS,
             "traffic": measured_traffic("k_project_stream_bf16"),
             "bytes_per_launch": proj_bytes / n_proj,
-            "note": "algorithmic bytes: 4 B of FP32 Z written per sample-split + 2 D B of "
-                    "bfloat16 X read per row; Z is FP32, so the projection is HBM-bound "
-                    "(114 flop/B at D = 256 against the BF16 ridge of 312)"}
+            "note": "algorithmic bytes: 2 B of bfloat16 Z written per sample-split + 2 D B "
+                    "of bfloat16 X read per row; 2 D flops per 2 B of Z is 256 flop/B at "
+                    "D = 256, below the BF16 ridge of 312 flop/B, so the projection is "
+                    "HBM-bound"}
     depths = np.bincount(trees[0]["depth"]).tolist()
     res = {
         "value": ss / dt, "ms_per_step": 1e3 * dt / args.steps, "steps": args.steps,
         "sample_splits_rescored_per_s": ssr / dt,
         "config": {"workload": "BF16 screening tree: N=4000000, D=256, K=10 (class means ~N(0,I), "
                                "shared covariance LL^T+diag, rank 16), X bfloat16; P=1024 "
-                               "screened by BF16 MFMA (FP32 accumulate), top 32 re-scored in "
-                               "FP32; T=40; Gini; 256-bin histogram; depth 12; min node 32",
+                               "screened by BF16 MFMA (FP32 accumulate, projections stored "
+                               "in BF16), top 32 re-scored in FP32; T=40; Gini; 256-bin "
+                               "histogram; depth 12; min node 32",
                    "nodes_per_tree": float(np.mean([t["n_nodes"] for t in trees])),
                    "nodes_per_depth_tree0": depths,
                    "sample_splits_per_tree": ss // args.steps,
@@ -226,7 +228,7 @@ def screening_gpu_check(api, Xd, yd, cfg, n_swarms=4):
     for s in range(n_swarms):
         sw = api.pso_alloc(1, P, D, node_id=[0], w_dtype=torch.bfloat16)
         api.pso_init(sw, seed=100 + s, tree=0)
-        Zs, zmin, zmax = api.project(Xd, sw.W, off, P, tiled=8)
+        Zs, zmin, zmax = api.project(Xd, sw.W, off, P, tiled="bf16")
         scr = api.split_scan(Zs, zmin, zmax, yd, cfg.K, off, P, cfg.bins, api.GINI)
         del Zs
         sel = api.screen_select(scr["loss"], 1, P, k).cpu().numpy()
@@ -420,7 +422,9 @@ def root_evals(api, which, reps, dev):
         return r
 
     for _ in range(reps):
-        Z, zmin, zmax = timed("project", lambda: api.project(Xd, sw.W, off, P, tiled=8))
+        # the tree's storage: bfloat16 8-wide tiles for the screening pass
+        zt = "bf16" if which == "screening" else 8
+        Z, zmin, zmax = timed("project", lambda: api.project(Xd, sw.W, off, P, tiled=zt))
         out = timed("scan", lambda: api.split_scan(Z, zmin, zmax, yd, K, off, P, 256, crit))
         if which == "screening":
             sel = api.screen_select(out["loss"], 1, P, 32)

@@ -60,8 +60,23 @@ typedef enum { SLM_GINI = 0, SLM_ENTROPY = 1, SLM_MSE = 2 } slm_criterion;
  *                  A scan work-group of 8 particles streams whole 32-byte
  *                  rows of one tile instead of a quarter of each 128-byte
  *                  row.  Requires 96 N + 8 (N + 64) < 2^31 bytes (N up to
- *                  about 2.06e7); larger N is refused with SLM_E_INVALID. */
-typedef enum { SLM_Z_ROWS = 0, SLM_Z_TILED = 1, SLM_Z_TILED8 = 2 } slm_z_layout;
+ *                  about 2.06e7); larger N is refused with SLM_E_INVALID.
+ *   SLM_Z_TILED8_BF16 : SLM_Z_TILED8 with bfloat16 elements (2 bytes each:
+ *                  ceil(P/8) * 8 * N of them), each the float32 projection
+ *                  rounded to the nearest bfloat16 (ties to even), and zmin /
+ *                  zmax the min / max of the stored values.  The storage of
+ *                  a screening pass: slm_project writes it with the
+ *                  streaming kernel (X BF16 with D <= 256, or X and W F32
+ *                  with 64 < D <= 128; other shapes return
+ *                  SLM_E_UNSUPPORTED), slm_split_scan reads it
+ *                  for classification histogram scans (bins > 0, Gini or
+ *                  entropy; otherwise SLM_E_UNSUPPORTED). */
+typedef enum {
+  SLM_Z_ROWS = 0,
+  SLM_Z_TILED = 1,
+  SLM_Z_TILED8 = 2,
+  SLM_Z_TILED8_BF16 = 3
+} slm_z_layout;
 
 /* Library version string (static storage). */
 const char *slm_version(void);

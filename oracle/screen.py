@@ -15,6 +15,12 @@ Readings (the paper does not describe this step; these fix it):
 * The screened projection is the exact dot product of the bfloat16 operands
   rounded to float32 (the GPU accumulates it in float32, so its rounding order
   differs; the parity tests bound that difference).
+* Storage of the screened projection (z_bf16): a classification histogram
+  search (Gini or entropy, bins > 0) over at most 256 dimensions keeps it in
+  bfloat16, the float32 value rounded once more to the nearest bfloat16 (ties
+  to even); the scan then reads those values exactly.  It only ranks the
+  directions, and the rounding is below the error its bfloat16 operands
+  already carry.  Other searches keep float32.
 * The re-scored set S holds the k particles with the smallest screened losses,
   ties to the lower index, listed in ascending (loss, index) order.
 * The loss handed to the swarm is the re-scored loss for particles of S and
@@ -56,14 +62,22 @@ def top_k(loss, k: int):
     return order[:k]
 
 
-def evaluate_screened(Xb, tn, crit: int, K: int, bins: int, k: int):
+def screened_storage_bf16(crit: int, bins: int, D: int) -> bool:
+    """Whether the screened projection is stored in bfloat16 (see above)."""
+    return crit != S.MSE and bins > 0 and D <= 256
+
+
+def evaluate_screened(Xb, tn, crit: int, K: int, bins: int, k: int, z_bf16=None):
     """Evaluation closure for a swarm with screening.
 
     Xb: the node's rows as bfloat16 values (float32 array).  The closure takes
     the float32 images W32 [P, D] of the positions and returns
     (loss, split, thr, gloss): the swarm's losses, splits and thresholds and the
-    losses eligible for the global best (+inf outside S)."""
+    losses eligible for the global best (+inf outside S).  z_bf16: storage of
+    the screened projection (None: screened_storage_bf16)."""
     Xb = np.asarray(Xb, dtype=np.float32)
+    if z_bf16 is None:
+        z_bf16 = screened_storage_bf16(crit, bins, Xb.shape[1])
 
     def scan_all(Z):
         P = Z.shape[1]
@@ -79,7 +93,8 @@ def evaluate_screened(Xb, tn, crit: int, K: int, bins: int, k: int):
     def ev(W32):
         W32 = np.asarray(W32, dtype=np.float32)
         Wb = bf16_round(W32)
-        loss, spl, thr = scan_all(S.project(Xb, Wb).astype(np.float32))
+        Zs = S.project(Xb, Wb).astype(np.float32)
+        loss, spl, thr = scan_all(bf16_round(Zs) if z_bf16 else Zs)
         sel = top_k(loss, min(k, W32.shape[0]))
         lr, sr, tr = scan_all(S.project(Xb, W32[sel]).astype(np.float32))
         loss[sel], spl[sel], thr[sel] = lr, sr, tr

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libslm.so")
 
 F32, BF16, F64, I32 = 0, 1, 2, 3
 GINI, ENTROPY, MSE = 0, 1, 2
-Z_ROWS, Z_TILED, Z_TILED8 = 0, 1, 2
+Z_ROWS, Z_TILED, Z_TILED8, Z_TILED8_BF16 = 0, 1, 2, 3
 TIMING_SLOTS = 12   # slm_tree_out.timing entries (SLM_TIMING_SLOTS)
 STATUS = {0: "SLM_OK", 1: "SLM_E_INVALID", 2: "SLM_E_SHAPE", 3: "SLM_E_DTYPE",
           4: "SLM_E_NOMEM", 5: "SLM_E_HIP", 6: "SLM_E_UNSUPPORTED"}
@@ -171,18 +171,22 @@ def _xdtype(X):
 
 
 # ------------------------------------------------------------------ project
-def _tile_width(tiled) -> int:
-    """0 (row-major), 32 (tiled=True or 32) or 8."""
+def _tile_width(tiled):
+    """(tile width, bfloat16): 0 (row-major), 32 (tiled=True or 32), 8, or
+    "bf16" (8-wide tiles of bfloat16)."""
+    if tiled == "bf16":
+        return 8, True
     w = 32 if tiled is True else int(tiled or 0)
     if w not in (0, 8, 32):
-        raise ValueError("tiled must be False, True (32), 32 or 8")
-    return w
+        raise ValueError("tiled must be False, True (32), 32, 8 or 'bf16'")
+    return w, False
 
 
 def project(X, W, row_off, P: int, tiled=False):
     """Z = per-node X W^T, zmin/zmax [n_nodes*P] (Eq. (1)).  Z is [N, P], or
     with tiled=True (or 32) the particle-tiled [ceil(P/32), N, 32]
-    (SLM_Z_TILED), with tiled=8 the [ceil(P/8), N, 8] (SLM_Z_TILED8).
+    (SLM_Z_TILED), with tiled=8 the [ceil(P/8), N, 8] (SLM_Z_TILED8), with
+    tiled="bf16" the same in bfloat16 (SLM_Z_TILED8_BF16).
     (X, W) dtypes: (float32, float32), (bfloat16, bfloat16) or (bfloat16, float32)."""
     load()
     xt = _xdtype(X)
@@ -192,14 +196,15 @@ def project(X, W, row_off, P: int, tiled=False):
     _dev(row_off, torch.int64, "row_off")
     N, D = X.shape
     nn = row_off.numel() - 1
-    w = _tile_width(tiled)
+    w, zb = _tile_width(tiled)
+    zdt = torch.bfloat16 if zb else torch.float32
     if w:
-        Z = torch.empty(((P + w - 1) // w, N, w), dtype=torch.float32, device=X.device)
+        Z = torch.empty(((P + w - 1) // w, N, w), dtype=zdt, device=X.device)
     else:
         Z = torch.empty((N, P), dtype=torch.float32, device=X.device)
     zmin = torch.empty(nn * P, dtype=torch.float32, device=X.device)
     zmax = torch.empty_like(zmin)
-    zl = {0: Z_ROWS, 32: Z_TILED, 8: Z_TILED8}[w]
+    zl = Z_TILED8_BF16 if zb else {0: Z_ROWS, 32: Z_TILED, 8: Z_TILED8}[w]
     _check(_lib.slm_project(_p(X), xt, N, D, _p(W), wt, _p(row_off), nn, P, _p(Z), zl,
                             _p(zmin), _p(zmax), _stream()),
            "slm_project")
@@ -239,15 +244,17 @@ def scan_workspace(nbytes: int, device) -> torch.Tensor:
 def split_scan(Z, zmin, zmax, target, K: int, row_off, P: int, bins: int, crit: int,
                hist: bool = False, sums: bool = False):
     """Best threshold per (node, particle); see slm_split_scan.  Z is [N, P]
-    or particle-tiled [ceil(P/w), N, w] with w = 32 or 8."""
+    or particle-tiled [ceil(P/w), N, w] with w = 32 or 8 (float32), or
+    [ceil(P/8), N, 8] bfloat16."""
     load()
-    _dev(Z, torch.float32, "Z")
+    zb = Z.dtype == torch.bfloat16 and Z.dim() == 3
+    _dev(Z, torch.bfloat16 if zb else torch.float32, "Z")
     _dev(row_off, torch.int64, "row_off")
     if Z.dim() == 3:
         w = Z.shape[2]
-        if w not in (8, 32) or Z.shape[0] != (P + w - 1) // w:
-            raise ValueError("tiled Z must be [ceil(P/w), N, w], w = 32 or 8")
-        N, zl = Z.shape[1], (Z_TILED if w == 32 else Z_TILED8)
+        if w not in (8, 32) or Z.shape[0] != (P + w - 1) // w or (zb and w != 8):
+            raise ValueError("tiled Z must be [ceil(P/w), N, w], w = 32 or 8 (bfloat16: 8)")
+        N, zl = Z.shape[1], (Z_TILED8_BF16 if zb else Z_TILED if w == 32 else Z_TILED8)
     else:
         if Z.dim() != 2 or Z.shape[1] != P:
             raise ValueError("Z must be [N, P]")

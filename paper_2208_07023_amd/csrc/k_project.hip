@@ -252,6 +252,21 @@ __device__ __forceinline__ void load_run(const void *base, int64_t row, int D, i
   }
 }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// The nearest bfloat16 of x (ties to even), as a float.
+__device__ __forceinline__ float round_bf16(float x) {
+  const bf16x2_t v = {(__bf16)x, (__bf16)x};
+  return __uint_as_float(__builtin_bit_cast(uint32_t, v) << 16);
+}
+
+// Two floats as a packed pair of bfloat16 (a low, b high), each rounded to
+// nearest even (one v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const bf16x2_t v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
 // 4 x 4 transpose of 8-lane groups within each 32-lane half of the wave:
 // register i, lane group u (lanes 8u .. 8u+7 of the half) <-> register u,
 // lane group i.  From the matrix-core layout (register 4g + i holds row
@@ -815,7 +830,7 @@ __device__ __forceinline__ uint4 load_group(const void *base, int64_t row, int D
   }
 }
 
-template <int MK, int FN, bool VEC, int ZT>
+template <int MK, int FN, bool VEC, int ZT, bool ZB = false>
 __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64_t RB,
                                                             int blocks_per_pt, int n_pt,
                                                             int xcd_map) {
@@ -897,8 +912,13 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
       const int p = p0 + f * 32 + li;
-      const float m0 = fminf(mn[f], __shfl_xor(mn[f], 32));
-      const float m1 = fmaxf(mx[f], __shfl_xor(mx[f], 32));
+      float m0 = fminf(mn[f], __shfl_xor(mn[f], 32));
+      float m1 = fmaxf(mx[f], __shfl_xor(mx[f], 32));
+      if constexpr (ZB) {
+        // the min / max of the stored (rounded) values: rounding is monotonic
+        m0 = round_bf16(m0);
+        m1 = round_bf16(m1);
+      }
       if (lane < 32 && p < P && m0 <= m1) {
         atomic_min_f32(&a.zmin[wb + p], m0);
         atomic_max_f32(&a.zmax[wb + p], m1);
@@ -1008,15 +1028,52 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
   // columns past P) take an out-of-range offset, which the hardware drops.
   auto epilogue = [&](int64_t lo, int n, const f32x16 (&acc)[FN]) {
     const bool full = n == SR && tile_full;
+    constexpr int EB = ZB ? 2 : 4;   // bytes per element of Z
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
       const bool pin = p0 + f * 32 + li < P;
       const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-          a.Z + z_col(a.zl, p0 + f * 32) + lo * rs, 0, (int)((z_col(a.zl, 31) + n * rs) * 4),
-          BUF_DW3);
-      const int vo = (int)((4 * kh * rs + z_col(a.zl, li)) * 4);
+          reinterpret_cast<char *>(a.Z) + (z_col(a.zl, p0 + f * 32) + lo * rs) * EB, 0,
+          (int)((z_col(a.zl, 31) + n * rs) * EB), BUF_DW3);
+      const int vo = (int)((4 * kh * rs + z_col(a.zl, li)) * EB);
       float l = __builtin_huge_valf(), h = -__builtin_huge_valf();
-      if (full && ZT == 8) {
+      if (full && ZB) {
+        // bfloat16, 8-wide tiles: after the transpose lane l holds row
+        // 8g + l/8 of tile t, particle l%8; the even lanes pack their value
+        // with the next lane's (v_cvt_pk_bf16_f32, nearest even) and store
+        // the pair: 128 contiguous bytes per store
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          l = fminf(l, acc[f][r]);
+          h = fmaxf(h, acc[f][r]);
+        }
+        const bool even = (lane & 1) == 0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          uint32_t v[4] = {__float_as_uint(acc[f][4 * g]), __float_as_uint(acc[f][4 * g + 1]),
+                           __float_as_uint(acc[f][4 * g + 2]), __float_as_uint(acc[f][4 * g + 3])};
+          transpose_lane_groups(v, lane);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const uint32_t nb = __builtin_amdgcn_update_dpp(0u, v[t], 0xB1, 0xf, 0xf, false);
+            const uint32_t pk = pack_bf16(__uint_as_float(v[t]), __uint_as_float(nb));
+            __builtin_amdgcn_raw_buffer_store_b32(pk, zr, even ? lane * 2 + 128 * g : (int)0x80000000,
+                                                  (int)(t * a.zl.ts * 2), 0);
+          }
+        }
+      } else if (ZB) {
+        // bfloat16, cut sub-tile: one 2-byte store per element
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
+          const bool ok = pin && row < n;
+          const int off = ok ? vo + (int)((8 * (r >> 2) + (r & 3)) * rs * 2) : (int)0x80000000;
+          __builtin_amdgcn_raw_buffer_store_b16((unsigned short)pack_bf16(acc[f][r], acc[f][r]), zr,
+                                                off, 0, 0);
+          l = fminf(l, ok ? acc[f][r] : __builtin_huge_valf());
+          h = fmaxf(h, ok ? acc[f][r] : -__builtin_huge_valf());
+        }
+      } else if (full && ZT == 8) {
         // 8-wide tiles: after the transpose, register t of group g holds
         // rows 8g + lane/8 of tile t (at t * ts), lane%8 its particle
 #pragma unroll
@@ -1121,7 +1178,10 @@ slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s, int want_xcd = 1
   SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_project: grid too large");
   const size_t lds = stream_lds_bytes(MK, FN);
   const int zt = z_tile_width(a.zl);
-  if (zt == 32)
+  if (a.zl.eb == 2)
+    hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, 8, true>), dim3((unsigned)grid), dim3(64 * SW),
+                       lds, s, a, RB, (int)bpp, n_pt, xcd);
+  else if (zt == 32)
     hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, 32>), dim3((unsigned)grid), dim3(64 * SW),
                        lds, s, a, RB, (int)bpp, n_pt, xcd);
   else if (zt == 8)
@@ -1192,9 +1252,9 @@ bool stream_eligible(const ProjectArgs &a) {
   return a.D <= stream_kch(mk);
 }
 
-template <int MK, int FN, bool VEC, int ZT>
+template <int MK, int FN, bool VEC, int ZT, bool ZB = false>
 void set_stream_attr(int bytes) {
-  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_project_stream<MK, FN, VEC, ZT>),
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_project_stream<MK, FN, VEC, ZT, ZB>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
     (void)hipGetLastError();
 }
@@ -1202,9 +1262,11 @@ template <int MK, int FN>
 void set_stream_attr_fn(int bytes) {
   set_stream_attr<MK, FN, true, 32>(bytes);
   set_stream_attr<MK, FN, true, 8>(bytes);
+  set_stream_attr<MK, FN, true, 8, true>(bytes);
   set_stream_attr<MK, FN, true, 0>(bytes);
   set_stream_attr<MK, FN, false, 32>(bytes);
   set_stream_attr<MK, FN, false, 8>(bytes);
+  set_stream_attr<MK, FN, false, 8, true>(bytes);
   set_stream_attr<MK, FN, false, 0>(bytes);
 }
 template <int MK>
@@ -1267,9 +1329,16 @@ void prepare_project_kernels(int lds_max) {
   set_stream_attr_mk<MK_FF>(dyn);
 }
 
+bool project_writes_bf16(const ProjectArgs &a) {
+  return a.Z != nullptr && stream_enabled() && stream_eligible(a);
+}
+
 slm_status launch_project(const ProjectArgs &a, hipStream_t s) {
   SLM_CHECK(a.Z != nullptr || (a.D <= 64 && !a.x_bf16 && !a.w_bf16 && a.zmin), SLM_E_INVALID,
             "slm_project: a min/max-only pass needs float32 data, D <= 64 and zmin/zmax");
+  SLM_CHECK(a.zl.eb == 4 || project_writes_bf16(a), SLM_E_UNSUPPORTED,
+            "slm_project: bfloat16 Z is written by the streaming kernel only (D = %d, X %s, W %s)",
+            a.D, a.x_bf16 ? "BF16" : "F32", a.w_bf16 ? "BF16" : "F32");
   if (stream_enabled() && stream_eligible(a)) {
     if (a.x_bf16 && a.w_bf16) return launch_stream<MK_BB>(a, s);
     if (a.x_bf16) return launch_stream<MK_XB>(a, s);

@@ -837,7 +837,7 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
 // [0, K) keeps the row's address in range and adds 0 (the row's increment
 // multipliers are zero).  Rows are taken U4 at a time: loads, then every
 // bin and address, then the atomics.
-template <int PT, int WGS>
+template <int PT, int WGS, bool ZB>
 __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &it, int pt,
                                                  int64_t np, int wave, int lane,
                                                  unsigned char *hb, int SB) {
@@ -872,17 +872,35 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
   // first row; each lane adds its four particles' tile and column offset (a
   // lane past P reads the last existing group of four, whose counts it never
   // adds).  Offsets stay below 2^31 bytes: the layout is checked on the host.
+  // ZB: bfloat16 elements, four of them in one 8-byte load, widened exactly.
+  constexpr int EB = ZB ? 2 : 4;
   const int rs = (int)a.zl.rs;
   const int t0p = (pt * PT) & ~((1 << a.zl.sh) - 1);
   const int64_t c0 = z_col(a.zl, t0p);
   const int pa = min(pt * PT + 4 * q4, (P - 1) & ~3);
   const int plast = min(pt * PT + PT, P) - 1;
-  const int64_t zspan = (z_col(a.zl, plast) - c0 + 1 + (it.hi - rb4) * rs) * 4;
+  const int64_t zspan = (z_col(a.zl, plast) - c0 + 1 + (it.hi - rb4) * rs) * EB;
   const __amdgpu_buffer_rsrc_t zr = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float *>(a.Z + c0 + rb4 * rs), 0,
+      const_cast<char *>(reinterpret_cast<const char *>(a.Z) + (c0 + rb4 * rs) * EB), 0,
       (int)(zspan < 0x7FFFFFFF ? zspan : 0x7FFFFFFF), BUF_DW3);
-  const int zvo = (int)((z_col(a.zl, pa) - c0 + (int64_t)r4 * rs) * 4);
-  const int zso = (int)(step4 * rs * 4);
+  const int zvo = (int)((z_col(a.zl, pa) - c0 + (int64_t)r4 * rs) * EB);
+  const int zso = (int)(step4 * rs * EB);
+  // the four projections of row step j as float32 bit patterns
+  auto load_z = [&](int j, uint32_t (&zw)[4]) {
+    if constexpr (ZB) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(zr, zvo, j * zso, 0);
+      zw[0] = v[0] << 16;
+      zw[1] = v[0] & 0xFFFF0000u;
+      zw[2] = v[1] << 16;
+      zw[3] = v[1] & 0xFFFF0000u;
+    } else {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(zr, zvo, j * zso, 0);
+      zw[0] = v[0];
+      zw[1] = v[1];
+      zw[2] = v[2];
+      zw[3] = v[3];
+    }
+  };
   const __amdgpu_buffer_rsrc_t lr = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<int32_t *>(a.labels + rb4), 0, (int)((it.hi - rb4) * 4), BUF_DW3);
   const int lvo = r4 * 4, lso = (int)(step4 * 4);
@@ -897,11 +915,7 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
       int lab[U4];
 #pragma unroll
       for (int u = 0; u < U4; ++u) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(zr, zvo, (i + u) * zso, 0);
-        zw[u][0] = v[0];
-        zw[u][1] = v[1];
-        zw[u][2] = v[2];
-        zw[u][3] = v[3];
+        load_z(i + u, zw[u]);
         lab[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, (i + u) * lso, 0);
       }
       uint32_t ad[U4][4], in[U4][4];
@@ -931,7 +945,8 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
   // remaining rows (all rows when a rule is ill conditioned or the tile is
   // partial): exact bins, and nothing added for particles past P
   for (; i < n4; ++i) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(zr, zvo, i * zso, 0);
+    uint32_t v[4];
+    load_z(i, v);
     const int lab = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, i * lso, 0);
     const bool lok = (unsigned)lab < (unsigned)K;
     const uint32_t base = ((uint32_t)(lok ? lab : 0) * PT + 4u * q4) * 4u;
@@ -1004,8 +1019,12 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   // four consecutive particles of one row, so one 16-byte load of the row's
   // Z segment and one label load serve four sample-splits, and the label's
   // part of the LDS address is formed once per row.
-  if (!MSE && a.zl.rs == (1 << a.zl.sh) && a.zl.rs >= 8) {
-    accumulate_rows4<PT, WGS>(a, it, pt, np, wave, lane, reinterpret_cast<unsigned char *>(hc), SB);
+  if (!MSE && a.zl.eb == 2) {
+    accumulate_rows4<PT, WGS, true>(a, it, pt, np, wave, lane, reinterpret_cast<unsigned char *>(hc),
+                                    SB);
+  } else if (!MSE && a.zl.rs == (1 << a.zl.sh) && a.zl.rs >= 8) {
+    accumulate_rows4<PT, WGS, false>(a, it, pt, np, wave, lane,
+                                     reinterpret_cast<unsigned char *>(hc), SB);
   } else {
     accumulate_rows1<PT, WGS, MSE>(a, it, p, pv, pl, rsub, wave, rule, hc, hs1, hs2, SB, SD);
   }
@@ -1786,6 +1805,8 @@ slm_status launch_scan_empty_nodes(const ScanArgs &a, hipStream_t s) {
 }
 
 slm_status launch_scan_hist(const ScanArgs &a, hipStream_t s) {
+  SLM_CHECK(a.zl.eb == 4 || a.crit != SLM_MSE, SLM_E_UNSUPPORTED,
+            "slm_split_scan: bfloat16 Z is read by the classification histogram scan only");
   if (a.N <= 0 || a.n_nodes <= 0) return SLM_OK;
   SLM_CHECK(!a.vpre || (a.rows >= 1 && a.rows <= a.N), SLM_E_INVALID,
             "slm_split_scan: row-prefix bound %lld outside [1, N]", (long long)a.rows);
@@ -1954,6 +1975,8 @@ slm_status launch_fused_eval(const ProjectArgs &pr, const ScanArgs &a, hipStream
 }
 
 slm_status launch_scan_exact(const ScanArgs &a, int max_rows, hipStream_t s) {
+  SLM_CHECK(a.zl.eb == 4, SLM_E_UNSUPPORTED,
+            "slm_split_scan: bfloat16 Z is read by the classification histogram scan only");
   SLM_CHECK(max_rows <= EXACT_MAX, SLM_E_UNSUPPORTED,
             "slm_split_scan: exact scan supports nodes of at most %d rows (got %d)", EXACT_MAX,
             max_rows);

@@ -590,7 +590,10 @@ static slm_status swarm_loop(const slm_tree_params &p, const TreeWS &w, const vo
   pr.X = Xc; pr.x_bf16 = scr; pr.w_bf16 = scr; pr.N = N; pr.D = D; pr.W = w.W; pr.beg = w.beg;
   pr.end = ends;
   pr.n_nodes = na; pr.P = p.P; pr.Z = w.Z; pr.zmin = w.zmin; pr.zmax = w.zmax;
-  pr.zl = zlayout_of(grow_z_layout(N), N, p.P);
+  // the screening pass of a classification histogram search stores its Z in
+  // bfloat16 (it only ranks the directions; the re-scoring is float32)
+  const bool zbf = scr && !mse && p.bins > 0 && project_writes_bf16(pr);
+  pr.zl = zlayout_of(grow_z_layout(N, zbf), N, p.P);
   pr.vpre = vrows > 0 ? w.vpre : nullptr;
   pr.rows = vrows > 0 ? vrows : 0;
   ScanArgs sa{};
@@ -798,10 +801,10 @@ slm_status slm_project(const void *X, int32_t x_dtype, int64_t N, int32_t D, con
                 (w_dtype == SLM_F32 || w_dtype == SLM_BF16) &&
                 !(x_dtype == SLM_F32 && w_dtype == SLM_BF16),
             SLM_E_DTYPE, "slm_project: (X, W) must be (F32, F32), (BF16, BF16) or (BF16, F32)");
-  SLM_CHECK(z_layout == SLM_Z_ROWS || z_layout == SLM_Z_TILED || z_layout == SLM_Z_TILED8,
-            SLM_E_INVALID, "slm_project: bad Z layout %d", z_layout);
-  SLM_CHECK(z_layout != SLM_Z_TILED8 || zlayout_fits(zlayout_of(2, N, P), 65536), SLM_E_INVALID,
-            "slm_project: N = %lld too large for SLM_Z_TILED8", (long long)N);
+  SLM_CHECK(z_layout >= SLM_Z_ROWS && z_layout <= SLM_Z_TILED8_BF16, SLM_E_INVALID,
+            "slm_project: bad Z layout %d", z_layout);
+  SLM_CHECK(z_layout < SLM_Z_TILED8 || zlayout_fits(zlayout_of(z_layout, N, P), 65536),
+            SLM_E_INVALID, "slm_project: N = %lld too large for SLM_Z_TILED8", (long long)N);
   if (N == 0 || n_nodes == 0) return SLM_OK;
   SLM_CHECK(X && W && row_off && Z && zmin && zmax, SLM_E_INVALID, "slm_project: NULL pointer");
   slm_status st = prepare_kernels();
@@ -834,10 +837,12 @@ slm_status slm_split_scan(const float *Z, int32_t z_layout, const float *zmin, c
   SLM_CHECK(bins == 0 || (bins >= 2 && bins <= 256), SLM_E_SHAPE,
             "slm_split_scan: bins = %d (0 or 2..256)", bins);
   SLM_CHECK(crit >= 0 && crit <= 2, SLM_E_INVALID, "slm_split_scan: bad criterion %d", crit);
-  SLM_CHECK(z_layout == SLM_Z_ROWS || z_layout == SLM_Z_TILED || z_layout == SLM_Z_TILED8,
-            SLM_E_INVALID, "slm_split_scan: bad Z layout %d", z_layout);
-  SLM_CHECK(z_layout != SLM_Z_TILED8 || zlayout_fits(zlayout_of(2, N, P), 65536), SLM_E_INVALID,
-            "slm_split_scan: N = %lld too large for SLM_Z_TILED8", (long long)N);
+  SLM_CHECK(z_layout >= SLM_Z_ROWS && z_layout <= SLM_Z_TILED8_BF16, SLM_E_INVALID,
+            "slm_split_scan: bad Z layout %d", z_layout);
+  SLM_CHECK(z_layout < SLM_Z_TILED8 || zlayout_fits(zlayout_of(z_layout, N, P), 65536),
+            SLM_E_INVALID, "slm_split_scan: N = %lld too large for SLM_Z_TILED8", (long long)N);
+  SLM_CHECK(z_layout != SLM_Z_TILED8_BF16 || (bins > 0 && crit != SLM_MSE), SLM_E_UNSUPPORTED,
+            "slm_split_scan: bfloat16 Z is read by the classification histogram scan only");
   if (crit == SLM_MSE) {
     SLM_CHECK(t_dtype == SLM_F64, SLM_E_DTYPE, "slm_split_scan: SLM_MSE needs an F64 target");
     SLM_CHECK(K == 0, SLM_E_SHAPE, "slm_split_scan: K must be 0 for SLM_MSE");

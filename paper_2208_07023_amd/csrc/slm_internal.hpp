@@ -142,37 +142,44 @@ __device__ __forceinline__ uint16_t f64_to_bf16(double d) {
 }
 
 // ---------------------------------------------------------------- launchers
-// Placement of Z[i, p] (row i, particle p): (p >> sh) * ts + i * rs +
-// (p & (2^sh - 1)).  Row-major [N, P]: sh = 5, ts = 32, rs = P (the sum is
-// i P + p).  Particle-tiled with tiles of w = 2^sh particles (w = 32 or 8)
-// [ceil(P/w), N, w]: ts = w N, rs = w, each tile a contiguous [N, w] block.
+// Placement of Z[i, p] (row i, particle p), in elements: (p >> sh) * ts +
+// i * rs + (p & (2^sh - 1)).  Row-major [N, P]: sh = 5, ts = 32, rs = P (the
+// sum is i P + p).  Particle-tiled with tiles of w = 2^sh particles (w = 32
+// or 8) [ceil(P/w), N, w]: ts = w N, rs = w, each tile a contiguous [N, w]
+// block.  Elements are float32 (eb = 4) or, for the screening pass's 8-wide
+// tiles, bfloat16 (eb = 2: the float32 projection rounded to nearest even).
 // Word 3 of a gfx9 raw buffer resource (32-bit data format, no swizzle).
 constexpr int BUF_DW3 = 0x00020000;
 
 struct ZLayout {
   int64_t ts, rs;
   int sh;
+  int eb;   // bytes per element
 };
 __host__ __device__ __forceinline__ int64_t z_col(const ZLayout &l, int p) {
   return (int64_t)(p >> l.sh) * l.ts + (p & ((1 << l.sh) - 1));
 }
-// layout: SLM_Z_ROWS, SLM_Z_TILED (32-particle tiles) or SLM_Z_TILED8
+// layout: SLM_Z_ROWS, SLM_Z_TILED (32-particle tiles), SLM_Z_TILED8 or
+// SLM_Z_TILED8_BF16
 __host__ __device__ __forceinline__ ZLayout zlayout_of(int layout, int64_t N, int P) {
-  if (layout == 1) return ZLayout{32 * N, 32, 5};
-  if (layout == 2) return ZLayout{8 * N, 8, 3};
-  return ZLayout{32, P, 5};
+  if (layout == 1) return ZLayout{32 * N, 32, 5, 4};
+  if (layout == 2) return ZLayout{8 * N, 8, 3, 4};
+  if (layout == 3) return ZLayout{8 * N, 8, 3, 2};
+  return ZLayout{32, P, 5, 4};
 }
 // Tiles narrower than 32 put the 32 particles of a matrix-core block (and of
 // a scan tile of up to 32 particles) up to 3 tiles apart: kernels address
 // them through one buffer resource, whose offsets must stay below 2^31 bytes.
 __host__ __device__ __forceinline__ bool zlayout_fits(const ZLayout &l, int64_t rows) {
-  const int64_t span = ((int64_t)(31 >> l.sh) * l.ts + 31 + (rows + 64) * l.rs) * 4;
+  const int64_t span = ((int64_t)(31 >> l.sh) * l.ts + 31 + (rows + 64) * l.rs) * l.eb;
   return span < ((int64_t)1 << 31);
 }
 // Layout of a tree search's Z: 8-particle tiles (a scan work-group of 8
 // particles streams whole rows of one tile), 32-particle tiles past the
-// offset limit above (chunks of at most 65536 rows).
-inline int grow_z_layout(int64_t N) {
+// offset limit above (chunks of at most 65536 rows).  bf16: the screening
+// pass of a classification histogram search stores bfloat16.
+inline int grow_z_layout(int64_t N, bool bf16 = false) {
+  if (bf16 && zlayout_fits(zlayout_of(3, N, 0), 65536)) return 3;
   return zlayout_fits(zlayout_of(2, N, 0), 65536) ? 2 : 1;
 }
 
@@ -198,6 +205,8 @@ struct ProjectArgs {
   int64_t rows;
 };
 slm_status launch_project(const ProjectArgs &a, hipStream_t s);
+// the launch's kernel can write bfloat16 Z (the streaming projection)
+bool project_writes_bf16(const ProjectArgs &a);
 slm_status launch_fill_minmax(float *zmin, float *zmax, int64_t n, hipStream_t s);
 // zeroes n 32-bit words with a fill kernel (no memset node in captured graphs)
 slm_status launch_zero_words(uint32_t *p, int64_t n, hipStream_t s);

@@ -54,7 +54,7 @@ def test_project_validation():
     assert st == 2
     st = lib.slm_project(None, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 4, FAKE, 0, FAKE, FAKE, None)
     assert st == 1 and "NULL" in _err(lib)
-    st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 4, FAKE, 3, FAKE, FAKE, None)
+    st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 4, FAKE, 4, FAKE, FAKE, None)
     assert st == 1 and "layout" in _err(lib)
     # 8-particle tiles: lane offsets of 96 N bytes must stay below 2^31
     st = lib.slm_project(FAKE, api.F32, 30_000_000, 4, FAKE, api.F32, FAKE, 1, 4, FAKE,
@@ -85,8 +85,12 @@ def test_split_scan_validation():
     assert call(args(crit=api.MSE, tt=api.F64, K=3)) == 2
     assert call(args(wsb=16)) == 4 and "workspace" in _err(lib)
     assert call(args(zmin=None)) == 1
-    assert call(args(zl=3)) == 1 and "layout" in _err(lib)
+    assert call(args(zl=4)) == 1 and "layout" in _err(lib)
     assert call(args(zl=api.Z_TILED8, N=30_000_000)) == 1 and "TILED8" in _err(lib)
+    assert call(args(zl=api.Z_TILED8_BF16, N=50_000_000)) == 1 and "TILED8" in _err(lib)
+    # bfloat16 Z: classification histogram scans only
+    assert call(args(zl=api.Z_TILED8_BF16, crit=api.MSE, tt=api.F64, K=0)) == 6
+    assert call(args(zl=api.Z_TILED8_BF16, bins=0)) == 6 and "bfloat16" in _err(lib)
     need = lib.slm_split_scan_workspace(100, 1, 8, 16, 3, api.GINI)
     assert need > 0
     assert lib.slm_split_scan_workspace(4_000_000, 2048, 1024, 256, 10, api.GINI) < 8 << 30

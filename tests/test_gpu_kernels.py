@@ -10,6 +10,7 @@ import pytest
 import torch
 
 from oracle import pso as OP
+from oracle import screen as SC
 from oracle import split as OS
 from paper_2208_07023_amd import inputs
 
@@ -102,6 +103,8 @@ def _scan_case(api, sizes, P, B, crit, K, kind, seed, tiled=False):
     off = inputs.segment_offsets(sizes)
     N = int(off[-1])
     Z = inputs.projected_features(N, P, seed=seed, kind=kind)
+    if tiled == "bf16":   # bfloat16 storage: the scan reads these values exactly
+        Z = SC.bf16_round(Z)
     rng = np.random.default_rng(seed + 1)
     if crit == OS.MSE:
         tgt = rng.normal(2.0, 1.5, size=N)
@@ -116,7 +119,10 @@ def _scan_case(api, sizes, P, B, crit, K, kind, seed, tiled=False):
         if sizes[j]:
             zmin[j * P:(j + 1) * P] = Z[off[j]:off[j + 1]].min(0)
             zmax[j * P:(j + 1) * P] = Z[off[j]:off[j + 1]].max(0)
-    Zd = api.tile_z(_t(Z), P, 32 if tiled is True else tiled) if tiled else _t(Z)
+    if tiled == "bf16":
+        Zd = api.tile_z(_t(Z), P, 8).to(torch.bfloat16)
+    else:
+        Zd = api.tile_z(_t(Z), P, 32 if tiled is True else tiled) if tiled else _t(Z)
     out = api.split_scan(Zd, _t(zmin), _t(zmax), _t(tgt, tt), K if crit != OS.MSE else 0,
                          _t(off), P, B, crit, hist=True, sums=crit == OS.MSE)
     torch.cuda.synchronize()
@@ -125,7 +131,7 @@ def _scan_case(api, sizes, P, B, crit, K, kind, seed, tiled=False):
     return got, ref
 
 
-@pytest.mark.parametrize("tiled", [False, True, 8])
+@pytest.mark.parametrize("tiled", [False, True, 8, "bf16"])
 @pytest.mark.parametrize("crit", [OS.GINI, OS.ENTROPY])
 @pytest.mark.parametrize("B,K,P,kind", [
     (256, 3, 32, "gauss"), (256, 2, 8, "dups"), (16, 10, 20, "gauss"), (2, 3, 5, "gauss"),
@@ -150,7 +156,7 @@ def test_hist_scan_classification_exact(gpu_lib, crit, B, K, P, kind, tiled):
 @pytest.mark.parametrize("B,K,P,kind,tiled", [
     (256, 3, 32, "gauss", True), (16, 10, 20, "gauss", False), (3, 4, 64, "dups", True),
     (100, 16, 3, "gauss", True), (256, 2, 40, "const", False), (256, 10, 44, "gauss", 8),
-    (64, 3, 17, "dups", 8),
+    (64, 3, 17, "dups", 8), (256, 10, 44, "gauss", "bf16"), (200, 3, 37, "dups", "bf16"),
 ])
 def test_hist_scan_classification_large_node(gpu_lib, crit, B, K, P, kind, tiled):
     # a node of many chunks among few nodes: finished one bin per thread
@@ -202,12 +208,14 @@ def _assert_scan_matches(got, ref, crit):
         assert np.allclose(got["loss"][fin], ref["loss"][fin], rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("w", [8, 32])
-@pytest.mark.parametrize("crit,K", [(OS.GINI, 3), (OS.ENTROPY, 10), (OS.MSE, 0)])
+@pytest.mark.parametrize("w,crit,K", [(8, OS.GINI, 3), (8, OS.ENTROPY, 10), (8, OS.MSE, 0),
+                                      (32, OS.GINI, 3), (32, OS.ENTROPY, 10), (32, OS.MSE, 0),
+                                      ("bf16", OS.GINI, 3), ("bf16", OS.ENTROPY, 10)])
 def test_hist_scan_every_tile_width(gpu_lib, tmp_path, w, crit, K):
     """Every work-group particle tile (4, 8, 16, 32; plans forced through the
-    plan cache) reads Z in the 8- and 32-particle layouts: P = 44 leaves a
-    ragged last tile, the 5000-row node spans five 1024-row chunks."""
+    plan cache) reads Z in the 8- and 32-particle layouts and the 8-particle
+    bfloat16 one: P = 44 leaves a ragged last tile, the 5000-row node spans
+    five 1024-row chunks."""
     import json
     api = gpu_lib
     sizes = [0, 1, 37, 5000, 301]
@@ -224,7 +232,8 @@ def test_hist_scan_every_tile_width(gpu_lib, tmp_path, w, crit, K):
         path.write_text(json.dumps({"plans": {key: [pt, 1024]}}))
         try:
             assert api.autotune(1, str(path)) == 1
-            got, ref = _scan_case(api, sizes, P, B, crit, K, "gauss", seed=pt + w, tiled=w)
+            got, ref = _scan_case(api, sizes, P, B, crit, K, "gauss", seed=pt + len(str(w)),
+                                  tiled=w)
         finally:
             api.autotune(1)
         _assert_scan_matches(got, ref, crit)

@@ -111,10 +111,35 @@ def test_screen_with_k_equal_P_is_the_plain_evaluation(crit, K, bins):
     assert np.array_equal(g1, l1)
 
 
+def test_screened_storage_rounds_to_bfloat16_hand_case():
+    """Storage of the screened projection, by hand.  Rows x = (1, 0), (1, 1),
+    (1, 2), labels 0, 1, 1; particle 0 is w = (1, 2^-8) (a bfloat16 value),
+    so its exact projections are 1, 1 + 2^-8, 1 + 2^-7.  With 4 bins the
+    float32 edges are 1 + j 2^-9, the bins 0, 2, 3 and the labels separate
+    (Gini 0).  Stored in bfloat16, 1 + 2^-8 is a tie between 1 and 1 + 2^-7
+    and goes to the even 1: bins 0, 0, 3, best split {0, 1} | {1} with Gini
+    (2/3) (1/2) = 1/3.  Particle 1, w = (0, 1), projects to 0, 1, 2 and
+    separates in either storage, so it is the re-scored top 1 and particle 0
+    keeps its screened loss."""
+    Xb = np.array([[1, 0], [1, 1], [1, 2]], np.float32)
+    tn = np.array([0, 1, 1])
+    W32 = np.array([[1, 2.0 ** -8], [0, 1]], np.float32)
+    assert np.array_equal(SC.bf16_round(W32), W32) and SC.screened_storage_bf16(S.GINI, 4, 2)
+    l, s, t, g = SC.evaluate_screened(Xb, tn, S.GINI, 2, 4, 1)(W32)
+    assert l[0] == pytest.approx(1.0 / 3.0, abs=1e-15) and l[1] == 0.0
+    assert np.isinf(g[0]) and g[1] == 0.0
+    l32, _, _, g32 = SC.evaluate_screened(Xb, tn, S.GINI, 2, 4, 1, z_bf16=False)(W32)
+    assert l32[0] == 0.0 and l32[1] == 0.0 and g32[0] == 0.0   # tie: the lower index re-scored
+    # regression and the exact scan keep float32 storage
+    assert not SC.screened_storage_bf16(S.MSE, 4, 2) and not SC.screened_storage_bf16(S.GINI, 0, 2)
+    assert not SC.screened_storage_bf16(S.GINI, 4, 257)
+
+
 def test_screen_is_exact_when_directions_are_bf16_values():
-    """Data and directions already representable in bfloat16: both
-    projections are the same float32 numbers, so the screened loss of every
-    particle equals its re-scored loss and the plain loss."""
+    """Data and directions already representable in bfloat16, float32
+    storage of the screened projection: both projections are the same
+    float32 numbers, so the screened loss of every particle equals its
+    re-scored loss and the plain loss."""
     rng = np.random.default_rng(9)
     n, D, P, k = 400, 10, 24, 5
     Xb = (rng.integers(-16, 17, (n, D)) / 4.0).astype(np.float32)
@@ -122,7 +147,7 @@ def test_screen_is_exact_when_directions_are_bf16_values():
     assert np.array_equal(SC.bf16_round(W32), W32)
     tn = rng.integers(0, 3, n)
     l0, s0, t0 = _plain_eval(Xb, tn, S.GINI, 3, 32)(W32)
-    l1, s1, t1, g1 = SC.evaluate_screened(Xb, tn, S.GINI, 3, 32, k)(W32)
+    l1, s1, t1, g1 = SC.evaluate_screened(Xb, tn, S.GINI, 3, 32, k, z_bf16=False)(W32)
     assert np.array_equal(l0, l1) and np.array_equal(s0, s1) and np.array_equal(t0, t1)
     sel = SC.top_k(l0, k)
     assert np.array_equal(np.isfinite(g1), np.isin(np.arange(P), sel) & np.isfinite(l0))
