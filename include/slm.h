@@ -64,7 +64,8 @@ typedef enum { SLM_GINI = 0, SLM_ENTROPY = 1, SLM_MSE = 2 } slm_criterion;
  *   SLM_Z_TILED8_BF16 : SLM_Z_TILED8 with bfloat16 elements (2 bytes each:
  *                  ceil(P/8) * 8 * N of them), each the float32 projection
  *                  rounded to the nearest bfloat16 (ties to even), and zmin /
- *                  zmax the min / max of the stored values.  The storage of
+ *                  zmax the min / max of the stored values; columns p >= P
+ *                  of the last tile may be written (with zeros).  The storage of
  *                  a screening pass: slm_project writes it with the
  *                  streaming kernel (X BF16 with D <= 256, or X and W F32
  *                  with 64 < D <= 128; other shapes return

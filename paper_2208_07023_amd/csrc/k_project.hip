@@ -792,6 +792,13 @@ struct StreamOps {
 __host__ __device__ constexpr size_t stream_lds_bytes(int MK, int FN) {
   return (size_t)FN * ((MK == MK_FF ? 128 : 256) / 2 * (MK == MK_BB ? 2 : 4) / 16) * 1024;
 }
+// bfloat16 Z goes out through a per-wave LDS staging area: the FN * 4
+// eight-particle tiles of a sub-tile, 32 rows of 16 bytes each plus one row
+// of padding (so the lanes of one row write distinct banks).
+constexpr int STAGE_TILE = 33 * 16;
+__host__ __device__ constexpr size_t stream_stage_bytes(int FN) {
+  return (size_t)SW * FN * 4 * STAGE_TILE;
+}
 // The dimensions one chunk covers: the kernel takes D <= KCH (one chunk).
 __host__ __device__ constexpr int stream_kch(int MK) { return MK == MK_FF ? 128 : 256; }
 
@@ -1037,41 +1044,38 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
           (int)((z_col(a.zl, 31) + n * rs) * EB), BUF_DW3);
       const int vo = (int)((4 * kh * rs + z_col(a.zl, li)) * EB);
       float l = __builtin_huge_valf(), h = -__builtin_huge_valf();
-      if (full && ZB) {
-        // bfloat16, 8-wide tiles: after the transpose lane l holds row
-        // 8g + l/8 of tile t, particle l%8; the even lanes pack their value
-        // with the next lane's (v_cvt_pk_bf16_f32, nearest even) and store
-        // the pair: 128 contiguous bytes per store
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          l = fminf(l, acc[f][r]);
-          h = fmaxf(h, acc[f][r]);
-        }
-        const bool even = (lane & 1) == 0;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          uint32_t v[4] = {__float_as_uint(acc[f][4 * g]), __float_as_uint(acc[f][4 * g + 1]),
-                           __float_as_uint(acc[f][4 * g + 2]), __float_as_uint(acc[f][4 * g + 3])};
-          transpose_lane_groups(v, lane);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const uint32_t nb = __builtin_amdgcn_update_dpp(0u, v[t], 0xB1, 0xf, 0xf, false);
-            const uint32_t pk = pack_bf16(__uint_as_float(v[t]), __uint_as_float(nb));
-            __builtin_amdgcn_raw_buffer_store_b32(pk, zr, even ? lane * 2 + 128 * g : (int)0x80000000,
-                                                  (int)(t * a.zl.ts * 2), 0);
-          }
-        }
-      } else if (ZB) {
-        // bfloat16, cut sub-tile: one 2-byte store per element
+      if constexpr (ZB) {
+        // bfloat16, 8-wide tiles, through this wave's LDS staging area:
+        // every element goes in as a bfloat16 (nearest even) at (tile, row,
+        // column), then each lane reads one 16-byte tile row and the wave
+        // writes two tiles' 32 rows (two 512-byte runs) per 16-byte store.
+        // Rows past the sub-tile's n and tiles past P are dropped (an
+        // out-of-range offset); the columns past P of the last tile take
+        // the zeros their padded directions project to.
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
-          const bool ok = pin && row < n;
-          const int off = ok ? vo + (int)((8 * (r >> 2) + (r & 3)) * rs * 2) : (int)0x80000000;
-          __builtin_amdgcn_raw_buffer_store_b16((unsigned short)pack_bf16(acc[f][r], acc[f][r]), zr,
-                                                off, 0, 0);
+          const bool ok = full || (pin && row < n);
           l = fminf(l, ok ? acc[f][r] : __builtin_huge_valf());
           h = fmaxf(h, ok ? acc[f][r] : -__builtin_huge_valf());
+        }
+        unsigned char *stg = reinterpret_cast<unsigned char *>(wl) + stream_lds_bytes(MK, FN) +
+                             (size_t)wave * (FN * 4 * STAGE_TILE) + (size_t)f * 4 * STAGE_TILE;
+        unsigned char *wp = stg + (li >> 3) * STAGE_TILE + 4 * kh * 16 + (li & 7) * 2;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          *reinterpret_cast<unsigned short *>(wp + (8 * (r >> 2) + (r & 3)) * 16) =
+              (unsigned short)pack_bf16(acc[f][r], acc[f][r]);
+        // (the wave's own LDS writes and reads complete in order)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const int t = 2 * s2 + (lane >> 5), row = lane & 31;
+          const uint4 v = *reinterpret_cast<const uint4 *>(stg + t * STAGE_TILE + row * 16);
+          const bool ok = row < n && p0 + f * 32 + 8 * t < P;
+          __builtin_amdgcn_raw_buffer_store_b128(
+              __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned int, v), zr,
+              ok ? (int)((lane >> 5) * a.zl.ts * 2) + row * 16 : (int)0x80000000,
+              (int)(2 * s2 * a.zl.ts * 2), 0);
         }
       } else if (full && ZT == 8) {
         // 8-wide tiles: after the transpose, register t of group g holds
@@ -1141,14 +1145,21 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
       mx[f] = -__builtin_huge_valf();
     }
     lds_barrier();
+    // the first tile's loads have landed before the loop is entered, so the
+    // waits inside it count only what the loop itself issues (vmcnt(0))
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     // ping-pong over this wave's sub-tiles of the node, SW SR rows apart
     while (my < end) {
       const int64_t nx = my + SW * SR;
       if (nx < end) load_a(nx, rows_at(nx), A1);
+      // the next sub-tile's loads stay ahead of this one's matrix-core chain
+      // (left to itself the scheduler sinks them next to their use)
+      __builtin_amdgcn_sched_barrier(0);
       subtile(my, rows_at(my), A0);
       if (nx >= end) break;
       const int64_t nx2 = nx + SW * SR;
       if (nx2 < end) load_a(nx2, rows_at(nx2), A0);
+      __builtin_amdgcn_sched_barrier(0);
       subtile(nx, rows_at(nx), A1);
       my = nx2;
     }
@@ -1176,7 +1187,7 @@ slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s, int want_xcd = 1
   const int64_t grid = bpp * n_pt;
   if (grid == 0) return SLM_OK;
   SLM_CHECK(grid < (1ll << 31), SLM_E_SHAPE, "slm_project: grid too large");
-  const size_t lds = stream_lds_bytes(MK, FN);
+  const size_t lds = stream_lds_bytes(MK, FN) + (a.zl.eb == 2 ? stream_stage_bytes(FN) : 0);
   const int zt = z_tile_width(a.zl);
   if (a.zl.eb == 2)
     hipLaunchKernelGGL((k_project_stream<MK, FN, VEC, 8, true>), dim3((unsigned)grid), dim3(64 * SW),
@@ -1211,7 +1222,9 @@ std::string proj_key(int kind, const ProjectArgs &a) {
 thread_local const int64_t *g_forced_proj = nullptr;
 
 bool stream_fn_fits(int MK, int FN, const ProjectArgs &a) {
-  return (FN == 1 || (a.P + 31) / 32 >= FN) && stream_lds_bytes(MK, FN) <= STREAM_LDS_MAX;
+  const size_t stage = a.zl.eb == 2 ? stream_stage_bytes(FN) : 0;
+  return (FN == 1 || (a.P + 31) / 32 >= FN) &&
+         stream_lds_bytes(MK, FN) + stage <= STREAM_LDS_MAX;
 }
 
 // Particle blocks per wave FN (4, 2 or 1: the widest that fits, or the
