@@ -43,12 +43,19 @@ BF16_PEAK_TFLOPS = 2500.0
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a
 # second run, WRITE_SIZE (KiB per dispatch, mean over the dispatches of the
 # run), scaled by what the same counters read for a plain 1 GiB device copy
-# (FETCH_SIZE 524302 KiB -> x 2.0, WRITE_SIZE 1048576 KiB -> x 1.0).  Valid
+# (FETCH_SIZE 524305 KiB -> x 2.0, WRITE_SIZE 1048576 KiB -> x 1.0).  Valid
 # only for the kernel source they were taken on (SHA-256 of the file);
 # otherwise the traffic is reported as null.  Summaries and commands:
 # profiles/traffic_*.md
-TRAFFIC = {}
-FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.3, 1.0
+TRAFFIC = {
+    "k_project_stream_bf16": {
+        "source": "paper_2208_07023_amd/csrc/k_project.hip",
+        "sha256": "f807ef2c43eb2d6689096601ba6f325f86dc077fa6b97c088df352c6fbfdfbfd",
+        "fetch_kib": 465208.7, "write_kib": 3732350.1,
+        "profile": "profiles/traffic_screened_projection_N4M_D256_P1024.md",
+    },
+}
+FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524305.1, 1.0
 
 
 def measured_traffic(kernel):

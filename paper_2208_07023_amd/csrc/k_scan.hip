@@ -154,9 +154,12 @@ struct Plan {
 
 constexpr int64_t CH_MAX = 65472;
 
+// Shortest chunk of a plan for N rows: about N / 256 (the accumulator holds
+// one slot per possible first chunk), at most the counter limit CH_MAX, so
+// above 256 CH_MAX rows the slots grow with N instead.
 int64_t chunk_min(int64_t N) {
   int64_t c = std::max<int64_t>(1024, (N + 255) / 256);
-  return (c + 63) / 64 * 64;
+  return std::min<int64_t>((c + 63) / 64 * 64, CH_MAX);
 }
 
 // Histogram layout.  LDS holds 16-bit counters packed in pairs: bins b and

@@ -239,6 +239,15 @@ def test_hist_scan_every_tile_width(gpu_lib, tmp_path, w, crit, K):
         _assert_scan_matches(got, ref, crit)
 
 
+def test_hist_scan_beyond_256_full_chunks(gpu_lib):
+    """More rows than 256 chunks of the counter limit (65472 rows) hold: the
+    plan's chunks stop at the limit and the accumulator takes more slots
+    (a 17 000 000-row node and a small one; P = 4, K = 2, Gini, 64 bins)."""
+    sizes = [17_000_000, 5]
+    got, ref = _scan_case(gpu_lib, sizes, 4, 64, OS.GINI, 2, "gauss", seed=31)
+    _assert_scan_matches(got, ref, OS.GINI)
+
+
 @pytest.mark.parametrize("sizes", [[9000, 3000], [40000]])
 def test_hist_scan_reuses_zeroed_workspace(gpu_lib, sizes):
     """Two calls in a row on the same workspace (multi-chunk nodes, both
