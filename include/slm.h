@@ -59,10 +59,14 @@ typedef enum { SLM_GINI = 0, SLM_ENTROPY = 1, SLM_MSE = 2 } slm_criterion;
  *                  at ((p / 8) * N + i) * 8 + p % 8 (ceil(P/8) * 8 * N floats).
  *                  A scan work-group of 8 particles streams whole 32-byte
  *                  rows of one tile instead of a quarter of each 128-byte
- *                  row.  Requires 96 N + 8 (N + 64) < 2^31 bytes (N up to
- *                  about 2.06e7); larger N is refused with SLM_E_INVALID.
+ *                  row.  The kernels address the four tiles of a
+ *                  32-particle block over a chunk of up to 65536 rows with
+ *                  32-bit offsets, so 96 N + 32 * 65600 + 124 < 2^31 bytes
+ *                  is required (N up to 22347753); larger N is refused with
+ *                  SLM_E_INVALID.
  *   SLM_Z_TILED8_BF16 : SLM_Z_TILED8 with bfloat16 elements (2 bytes each:
- *                  ceil(P/8) * 8 * N of them), each the float32 projection
+ *                  ceil(P/8) * 8 * N of them; N up to 44717374 by the same
+ *                  rule in 2-byte elements), each the float32 projection
  *                  rounded to the nearest bfloat16 (ties to even), and zmin /
  *                  zmax the min / max of the stored values; columns p >= P
  *                  of the last tile may be written (with zeros).  The storage of

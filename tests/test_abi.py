@@ -56,10 +56,12 @@ def test_project_validation():
     assert st == 1 and "NULL" in _err(lib)
     st = lib.slm_project(FAKE, api.F32, 10, 4, FAKE, api.F32, FAKE, 1, 4, FAKE, 4, FAKE, FAKE, None)
     assert st == 1 and "layout" in _err(lib)
-    # 8-particle tiles: lane offsets of 96 N bytes must stay below 2^31
-    st = lib.slm_project(FAKE, api.F32, 30_000_000, 4, FAKE, api.F32, FAKE, 1, 4, FAKE,
-                         api.Z_TILED8, FAKE, FAKE, None)
-    assert st == 1 and "TILED8" in _err(lib)
+    # 8-particle tiles: 96 N + 32 * 65600 + 124 bytes must stay below 2^31
+    # (the first N refused, as the header states); bfloat16 tiles double it
+    for zl, n in ((api.Z_TILED8, 22_347_754), (api.Z_TILED8_BF16, 44_717_375)):
+        st = lib.slm_project(FAKE, api.F32, n, 4, FAKE, api.F32, FAKE, 1, 4, FAKE,
+                             zl, FAKE, FAKE, None)
+        assert st == 1 and "TILED8" in _err(lib)
     # nothing to do: returns OK without touching the device
     st = lib.slm_project(None, api.F32, 0, 4, None, api.F32, None, 0, 4, None, 0, None, None, None)
     assert st == 0
@@ -86,8 +88,8 @@ def test_split_scan_validation():
     assert call(args(wsb=16)) == 4 and "workspace" in _err(lib)
     assert call(args(zmin=None)) == 1
     assert call(args(zl=4)) == 1 and "layout" in _err(lib)
-    assert call(args(zl=api.Z_TILED8, N=30_000_000)) == 1 and "TILED8" in _err(lib)
-    assert call(args(zl=api.Z_TILED8_BF16, N=50_000_000)) == 1 and "TILED8" in _err(lib)
+    assert call(args(zl=api.Z_TILED8, N=22_347_754)) == 1 and "TILED8" in _err(lib)
+    assert call(args(zl=api.Z_TILED8_BF16, N=44_717_375)) == 1 and "TILED8" in _err(lib)
     # bfloat16 Z: classification histogram scans only
     assert call(args(zl=api.Z_TILED8_BF16, crit=api.MSE, tt=api.F64, K=0)) == 6
     assert call(args(zl=api.Z_TILED8_BF16, bins=0)) == 6 and "bfloat16" in _err(lib)
