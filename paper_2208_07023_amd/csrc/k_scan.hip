@@ -162,20 +162,23 @@ int64_t chunk_min(int64_t N) {
   return std::min<int64_t>((c + 63) / 64 * 64, CH_MAX);
 }
 
-// Histogram layout.  LDS holds 16-bit counters packed in pairs: bins b and
-// b + 128 share a 32-bit word (low / high half), so a work-group's counts
-// must stay below 2^16 (chunks of at most CH_MAX rows).  Within a bin row the
-// PT particles of a (bin, class) are consecutive words, so the accumulation
-// (lanes = consecutive particles) touches 32 distinct banks per half-wave.
-// The global accumulator of a multi-chunk node mirrors the LDS words with
-// 64-bit words holding two 32-bit counters (bin b low, bin b + 128 high), so
-// one 64-bit atomic merges both halves of an LDS word.
-//   classification: count(b, k, q) in word (b & 127) * SB + k * PT + q, SB = K PT
-//                   (+ 1 for tiles narrower than 32 particles)
-//   regression:     count(b, q) in word (b & 127) * SB + q, SB = PT; sum y and
+// Histogram layout.  LDS holds 16-bit counters packed in pairs in 32-bit
+// words, so a work-group's counts must stay below 2^16 (chunks of at most
+// CH_MAX rows).  The global accumulator of a multi-chunk node mirrors the LDS
+// words with 64-bit words holding two 32-bit counters (the low half's count
+// low), so one 64-bit atomic merges both halves of an LDS word.
+//   classification: particles 2j and 2j + 1 of a (bin, class) share a word:
+//                   count(b, k, q) in the (q & 1) half of word
+//                   b SB + k PT / 2 + q / 2, SB = K PT / 2 + 1.  A lane
+//                   holding particles of one parity adds a constant (1 or
+//                   2^16) at an address that is one multiply-add of the bin.
+//                   K PT / 2 is even, so the odd stride spreads random bins
+//                   over all the banks.
+//   regression:     bins b and b + 128 share a word: count(b, q) in the
+//                   (b >> 7) half of word (b & 127) SB + q, SB = PT; sum y and
 //                   sum y^2 at b * PT + q in two double arrays
 struct HistLayout {
-  int SB, BH;
+  int SB;            // words per bin row
   int nwords;        // packed count words (LDS u32, accumulator u64)
   size_t lds_cnt;    // packed count region in LDS, 16-byte aligned
   size_t glob_cnt;   // count region of an accumulator slot, 256-byte aligned
@@ -184,18 +187,21 @@ struct HistLayout {
 
 __host__ __device__ __forceinline__ HistLayout hist_layout(int PT, int B, int K, bool mse) {
   HistLayout h;
-  // A tile narrower than the 32 banks leaves the bin index to spread a
-  // wave's atomics over the banks: with SB = K PT (a multiple of 8) the rows'
-  // random bins land on only 32 / gcd(SB, 32) banks per particle, so the
-  // classification stride is made odd (bins spread over all 32 banks).  A
-  // 32-wide tile maps lanes to banks by particle and keeps SB = 32 K.
-  h.SB = mse ? PT : K * PT + (PT < 32 ? 1 : 0);
-  h.BH = B < 128 ? B : 128;
-  h.nwords = h.BH * h.SB;
+  h.SB = mse ? PT : K * (PT / 2) + 1;
+  h.nwords = mse ? (B < 128 ? B : 128) * h.SB : B * h.SB;
   h.lds_cnt = ((size_t)h.nwords * 4 + 15) / 16 * 16;
   h.glob_cnt = ((size_t)h.nwords * 8 + 255) / 256 * 256;
   h.sums = mse ? (size_t)2 * B * PT * 8 : 0;
   return h;
+}
+
+// Word and half (0 low, 1 high) of count (bin b, class k, particle q of the
+// tile) in the layout above.
+__host__ __device__ __forceinline__ int cnt_word(bool mse, int b, int k, int q, int SB, int PT) {
+  return mse ? (b & 127) * SB + q : b * SB + k * (PT >> 1) + (q >> 1);
+}
+__host__ __device__ __forceinline__ int cnt_half(bool mse, int b, int q) {
+  return mse ? b >> 7 : q & 1;
 }
 
 // Work-groups are 512 threads; the finish gives thread t particle t % PT and
@@ -480,16 +486,15 @@ __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &
 #pragma unroll
     for (int i = 0; i < SEGMAX; ++i) {
       const int b = min(b_lo + i, B - 1);
-      const int w = (b & 127) * SB + qt;
+      const int h = cnt_half(MSE, b, qt);
 #pragma unroll
       for (int k = 0; k < KT; ++k) {
+        const int w = cnt_word(MSE, b, min(k, K - 1), qt, SB, PT);
         uint32_t x;
         if constexpr (GSRC)
-          x = (uint32_t)(reinterpret_cast<const unsigned long long *>(rb)[w + min(k, K - 1) * PT] >>
-                         ((b >> 7) << 5));
+          x = (uint32_t)(reinterpret_cast<const unsigned long long *>(rb)[w] >> (h << 5));
         else
-          x = (reinterpret_cast<const uint32_t *>(rb)[w + min(k, K - 1) * PT] >> ((b >> 7) << 4)) &
-              0xFFFFu;
+          x = (reinterpret_cast<const uint32_t *>(rb)[w] >> (h << 4)) & 0xFFFFu;
         c[i][k] += (i < nb && k < K) ? x : 0u;
       }
       if constexpr (MSE) {
@@ -540,10 +545,15 @@ __device__ __forceinline__ void finish_scan(const ScanArgs &a, const FinishSrc &
       for (int i = 0; i < SEGMAX; ++i) {
         if (i < nb) {
           const int b = b_lo + i;
-          const int w = (b & 127) * SB + qt;
+          // classification: only this particle's 32-bit half (its pair
+          // partner may be read by another work-group)
 #pragma unroll
           for (int k = 0; k < KT; ++k)
-            if (k < K) zc[w + k * PT] = 0ull;
+            if (k < K) {
+              const int w = cnt_word(MSE, b, k, qt, SB, PT);
+              if constexpr (MSE) zc[w] = 0ull;
+              else reinterpret_cast<uint32_t *>(zc + w)[qt & 1] = 0u;
+            }
           if constexpr (MSE) {
             z1[b * PT + qt] = 0.0;
             z2[b * PT + qt] = 0.0;
@@ -713,9 +723,10 @@ __device__ __forceinline__ Coords coords_of(const ScanArgs &a) {
 // wave's steps): regression, row-major Z, and every tile width.
 // Straight-line code for the common case: every lane's particle exists and
 // its edges are well conditioned (the guess is within one bin), so the bin is
-// computed without branches; 16 rows are in flight per lane.  Bin b adds
-// 1 << 16 (b >> 7) to word (b & 127); a lane without a particle, or a row
-// whose label is out of range, adds 0.
+// computed without branches; 16 rows are in flight per lane.  Classification
+// adds the lane's constant (1 or 2^16 by the particle's parity) to the word
+// of hist_layout; regression adds 1 << 16 (b >> 7) to word (b & 127).  A lane
+// without a particle, or a row whose label is out of range, adds 0.
 template <int PT, int WGS, bool MSE>
 __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &it, int p, bool pv,
                                                  int pl, int rsub, int wave, const BinRule &rule,
@@ -735,9 +746,9 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
   uint32_t *hrow = hc + pl;
   auto add_cls = [&](int bn, int lab) {
     const bool ok = pv && (unsigned)lab < (unsigned)K;
-    const uint32_t inc = ok ? (1u << ((bn >> 7) << 4)) : 0u;
+    const uint32_t inc = ok ? (1u << ((pl & 1) << 4)) : 0u;
     const int lb = ok ? lab : 0;
-    atomicAdd(&hrow[(bn & 127) * SB + lb * PT], inc);
+    atomicAdd(&hc[cnt_word(false, bn, lb, pl, SB, PT)], inc);
   };
   auto add_mse = [&](int bn, double yv) {
     if (!pv) return;
@@ -755,14 +766,15 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
     // rounding of the edges, of B / r, of the constant and of the result), so
     // g = trunc(t) is the bin or the one below it, never negative: one
     // comparison with the exact edge e_{g+1} settles it.  The unsigned clamp
-    // keeps any input in range.  Bin b adds 1 << 16 (b >> 7) to word (b & 127)
-    // of the lane's (class) column; a lane without a particle, or a label
-    // outside [0, K), adds 0.
+    // keeps any input in range.  Classification adds the lane's parity
+    // constant at b SB + class PT / 2 + pl / 2; a lane without a particle, or
+    // a label outside [0, K), adds 0.
     const float zmin = rule.zmin, delta = rule.delta, inv = rule.inv;
     const float off0 = -fmaf(zmin, inv, 0.005f);
     const unsigned bmax = (unsigned)B - 1u;
     const unsigned labk = pv ? (unsigned)K : 0u;
-    const uint32_t pt4 = PT * 4u, sb4 = (uint32_t)SB * 4u, pl4 = (uint32_t)pl * 4u;
+    const uint32_t ph4 = PT * 2u, sb4 = (uint32_t)SB * 4u, pl4 = (uint32_t)(pl >> 1) * 4u;
+    const uint32_t pinc = 1u << ((pl & 1) << 4);
     unsigned char *hb = reinterpret_cast<unsigned char *>(hc);
     auto bin_fast = [&](float zu) -> unsigned {
       const int g0 = (int)fmaf(zu, inv, off0);
@@ -806,8 +818,8 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
           add_mse((int)g, yv[u]);
         } else {
           const unsigned lb = min((unsigned)lab[u], (unsigned)K - 1u);
-          const uint32_t inc = (unsigned)lab[u] < labk ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
-          const uint32_t off = __umul24(g & 127u, sb4) + __umul24(lb, pt4) + pl4;
+          const uint32_t inc = (unsigned)lab[u] < labk ? pinc : 0u;
+          const uint32_t off = __umul24(g, sb4) + lb * ph4 + pl4;
           atomicAdd(reinterpret_cast<uint32_t *>(hb + off), inc);
         }
       }
@@ -825,8 +837,12 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
 // tiles of 8 or 32): lane (q, r) takes particles 4q .. 4q+3 of the tile and
 // rows r, r + 64/(PT/4), ... of the wave's steps.  Per row: one 16-byte
 // buffer load of the four projections, one label load, and the label's part
-// of the LDS address and increment; per sample-split: the branch-free bin and
-// one LDS atomic at an immediate offset.
+// of the LDS address; per sample-split: the branch-free bin and one LDS
+// atomic, whose address is one multiply-add.
+//
+// In the classification layout of hist_layout a lane's particles 4q, 4q+1
+// share word 2q of a (bin, class) and 4q+2, 4q+3 word 2q+1, so the increment
+// of particle e is 1 or 2^16 by the parity of e alone.
 //
 // Fast path (every particle of the tile exists and every edge rule is well
 // conditioned): the guess is taken one bin up, g1 = trunc(z B / r -
@@ -836,10 +852,14 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
 // larger result add at most B u (1 + |zmin| / r) + u bins, so the guess stays
 // within B u (7 + 4 |zmin| / r) <= 4.0e-3 < 0.005 bins of the count of edges
 // <= z (u = 2^-24, |zmin| <= 64 r, B <= 256): g1 - 1 is the bin or the one
-// below, g1 >= 0, and e_0 = zmin <= z keeps g1 = 0 at bin 0.  A label outside
-// [0, K) keeps the row's address in range and adds 0 (the row's increment
-// multipliers are zero).  Rows are taken U4 at a time: loads, then every
-// bin and address, then the atomics.
+// below, g1 >= 0, and e_0 = zmin <= z keeps g1 = 0 at bin 0.  The test is
+// written !(e_{g1} > z), so a NaN projection lands in bin 0 as in bin_of;
+// the clamp keeps every address inside the histogram whatever zmin / zmax
+// the caller passed.  Rows are taken U4 at a time: loads, then every bin,
+// then the addresses and atomics.  When every label of the wave's U4 rows is
+// a class (the usual case, one vote per step) the increments are constants;
+// otherwise a label outside [0, K) keeps its row's address in range and
+// adds 0.
 template <int PT, int WGS, bool ZB>
 __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &it, int pt,
                                                  int64_t np, int wave, int lane,
@@ -870,7 +890,8 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
   // uniform: the tile is full and every lane's rules are fast
   const bool wave_fast = __all(lane_fast) && (pt + 1) * PT <= P;
   const unsigned bmax = (unsigned)B - 1u;
-  const uint32_t sb4 = (uint32_t)SB * 4u, pt4 = (uint32_t)PT * 4u, q16 = 16u * (uint32_t)q4;
+  // bytes: per bin, per class, and the lane's first pair word
+  const uint32_t sb4 = (uint32_t)SB * 4u, ph4 = (uint32_t)PT * 2u, q8 = 8u * (uint32_t)q4;
   // Z from the tile holding the work-group's first particle, at the wave's
   // first row; each lane adds its four particles' tile and column offset (a
   // lane past P reads the last existing group of four, whose counts it never
@@ -888,62 +909,128 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
       (int)(zspan < 0x7FFFFFFF ? zspan : 0x7FFFFFFF), BUF_DW3);
   const int zvo = (int)((z_col(a.zl, pa) - c0 + (int64_t)r4 * rs) * EB);
   const int zso = (int)(step4 * rs * EB);
-  // the four projections of row step j as float32 bit patterns
-  auto load_z = [&](int j, uint32_t (&zw)[4]) {
+  // Z of row step j as loaded (RW words: four bfloat16 in two, or four
+  // float32), and its four projections as float32 bit patterns
+  constexpr int RW = ZB ? 2 : 4;
+  auto load_raw = [&](int j, uint32_t (&r)[RW]) {
     if constexpr (ZB) {
       const auto v = __builtin_amdgcn_raw_buffer_load_b64(zr, zvo, j * zso, 0);
-      zw[0] = v[0] << 16;
-      zw[1] = v[0] & 0xFFFF0000u;
-      zw[2] = v[1] << 16;
-      zw[3] = v[1] & 0xFFFF0000u;
+      r[0] = v[0];
+      r[1] = v[1];
     } else {
       const auto v = __builtin_amdgcn_raw_buffer_load_b128(zr, zvo, j * zso, 0);
-      zw[0] = v[0];
-      zw[1] = v[1];
-      zw[2] = v[2];
-      zw[3] = v[3];
+      r[0] = v[0];
+      r[1] = v[1];
+      r[2] = v[2];
+      r[3] = v[3];
     }
+  };
+  auto widen = [&](const uint32_t (&r)[RW], uint32_t (&zw)[4]) {
+    if constexpr (ZB) {
+      zw[0] = r[0] << 16;
+      zw[1] = r[0] & 0xFFFF0000u;
+      zw[2] = r[1] << 16;
+      zw[3] = r[1] & 0xFFFF0000u;
+    } else {
+      zw[0] = r[0];
+      zw[1] = r[1];
+      zw[2] = r[2];
+      zw[3] = r[3];
+    }
+  };
+  auto load_z = [&](int j, uint32_t (&zw)[4]) {
+    uint32_t r[RW];
+    load_raw(j, r);
+    widen(r, zw);
   };
   const __amdgpu_buffer_rsrc_t lr = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<int32_t *>(a.labels + rb4), 0, (int)((it.hi - rb4) * 4), BUF_DW3);
   const int lvo = r4 * 4, lso = (int)(step4 * 4);
   // LDS byte address of the histogram (32-bit LDS pointers: the address of
   // a sample-split is one 24-bit multiply-add)
-  const uint32_t hbase = (uint32_t)(uintptr_t)(lds_u32 *)hb;
+  const uint32_t hbase = (uint32_t)(uintptr_t)(lds_u32 *)hb + q8;
   constexpr int U4 = 4;
-  int i = 0;
-  if (wave_fast) {
-    for (; i + U4 <= n4; i += U4) {
-      uint32_t zw[U4][4];
-      int lab[U4];
+  // the loads of U4 row steps from step j
+  auto issue = [&](int j, uint32_t (&r)[U4][RW], int (&lab)[U4]) {
+#pragma unroll
+    for (int u = 0; u < U4; ++u) {
+      load_raw(j + u, r[u]);
+      lab[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, (j + u) * lso, 0);
+    }
+  };
+  // bins and LDS atomics of U4 loaded row steps
+  auto process = [&](const uint32_t (&r)[U4][RW], const int (&lab)[U4]) {
+    uint32_t g[U4][4];
+    bool ok = true;
+#pragma unroll
+    for (int u = 0; u < U4; ++u) {
+      ok = ok && (unsigned)lab[u] < (unsigned)K;
+      uint32_t zw[4];
+      widen(r[u], zw);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float z = __uint_as_float(zw[e]);
+        const int g1 = (int)fmaf(z, iv[e], o1[e]);
+        const float eg = __fadd_rn(zm[e], __fmul_rn((float)g1, dl[e]));
+        g[u][e] = min((uint32_t)(g1 - 1 + (eg > z ? 0 : 1)), bmax);
+      }
+    }
+    if (__all(ok)) {
+      // every label of the wave's rows is a class: constant increments
 #pragma unroll
       for (int u = 0; u < U4; ++u) {
-        load_z(i + u, zw[u]);
-        lab[u] = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, (i + u) * lso, 0);
+        const uint32_t base = (uint32_t)lab[u] * ph4 + hbase;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)(__umul24(g[u][e], sb4) + base) + (e >> 1),
+                                 (e & 1) ? 0x10000u : 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-      uint32_t ad[U4][4], in[U4][4];
+    } else {
 #pragma unroll
       for (int u = 0; u < U4; ++u) {
         const bool lok = (unsigned)lab[u] < (unsigned)K;
-        const uint32_t base = __umul24(lok ? (uint32_t)lab[u] : 0u, pt4) + (hbase + q16);
-        const uint32_t m16 = lok ? 0xFFFFu : 0u, m1 = lok ? 1u : 0u;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float z = __uint_as_float(zw[u][e]);
-          const int g1 = (int)fmaf(z, iv[e], o1[e]);
-          const float eg = __fadd_rn(zm[e], __fmul_rn((float)g1, dl[e]));
-          const unsigned g = min((unsigned)(g1 - 1 + (eg <= z ? 1 : 0)), bmax);
-          ad[u][e] = __umul24(g & 127u, sb4) + base;
-          in[u][e] = __umul24(g >> 7, m16) + m1;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U4; ++u)
+        const uint32_t base = (lok ? (uint32_t)lab[u] : 0u) * ph4 + hbase;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)ad[u][e] + e, in[u][e], __ATOMIC_RELAXED,
+          __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)(__umul24(g[u][e], sb4) + base) + (e >> 1),
+                                 lok ? ((e & 1) ? 0x10000u : 1u) : 0u, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
     }
+  };
+  // Full groups of U4 row steps that every lane of the wave has: lanes hold
+  // n4 or n4 - 1 steps, the last lane the fewest, so its count is the
+  // wave's (a uniform trip count keeps the load offsets scalar).  A lane's
+  // steps past them (at most U4) take the exact loop below.
+  const int ngw = __builtin_amdgcn_readfirstlane(max(0, __shfl(n4, 63)) / U4);
+  int i = 0;
+  if (wave_fast && ngw > 0) {
+    // two register sets: the next U4 row steps are loaded before the
+    // current ones are binned.  Inside the loop every pass loads (so each
+    // waits for the current group alone); the last one or two groups are
+    // peeled off.
+    uint32_t ra[U4][RW], rb[U4][RW];
+    int la[U4], lb[U4];
+    issue(0, ra, la);
+    int t = 0;
+    for (; t + 2 < ngw; t += 2) {
+      issue((t + 1) * U4, rb, lb);
+      __builtin_amdgcn_sched_barrier(0);
+      process(ra, la);
+      issue((t + 2) * U4, ra, la);
+      __builtin_amdgcn_sched_barrier(0);
+      process(rb, lb);
+    }
+    if (t + 1 < ngw) {
+      issue((t + 1) * U4, rb, lb);
+      __builtin_amdgcn_sched_barrier(0);
+      process(ra, la);
+      process(rb, lb);
+    } else {
+      process(ra, la);
+    }
+    i = ngw * U4;
   }
   // remaining rows (all rows when a rule is ill conditioned or the tile is
   // partial): exact bins, and nothing added for particles past P
@@ -952,12 +1039,12 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
     load_z(i, v);
     const int lab = (int)__builtin_amdgcn_raw_buffer_load_b32(lr, lvo, i * lso, 0);
     const bool lok = (unsigned)lab < (unsigned)K;
-    const uint32_t base = ((uint32_t)(lok ? lab : 0) * PT + 4u * q4) * 4u;
+    const uint32_t base = (uint32_t)(lok ? lab : 0) * ph4 + q8;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const unsigned g = (unsigned)bin_of(rl[e], __uint_as_float(v[e]));
-      const uint32_t inc = lok && pv4[e] ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
-      atomicAdd(reinterpret_cast<uint32_t *>(hb + __umul24(g & 127u, sb4) + base + 4u * e), inc);
+      const uint32_t inc = lok && pv4[e] ? ((e & 1) ? 0x10000u : 1u) : 0u;
+      atomicAdd(reinterpret_cast<uint32_t *>(hb + g * sb4 + base + 4u * (e >> 1)), inc);
     }
   }
 }
@@ -1166,7 +1253,7 @@ __global__ __launch_bounds__(256) void k_scan_finish_bins(ScanArgs a, int PT, in
       static_cast<unsigned char *>(a.ws) + ((size_t)slot * R * n_pt + pt) * slot_sz;
   const int b = tid;
   const bool bv = b < B;
-  const int w = (b & 127) * SB + qt;
+  const int w = cnt_word(false, b, 0, qt, SB, PT), h = qt & 1, kw = PT / 2;
   uint32_t c[KT];
 #pragma unroll
   for (int k = 0; k < KT; ++k) c[k] = 0u;
@@ -1175,7 +1262,7 @@ __global__ __launch_bounds__(256) void k_scan_finish_bins(ScanArgs a, int PT, in
         reinterpret_cast<const unsigned long long *>(base + (size_t)rr * n_pt * slot_sz);
 #pragma unroll
     for (int k = 0; k < KT; ++k)
-      if (bv && k < K) c[k] += (uint32_t)(gc[w + k * PT] >> ((b >> 7) << 5));
+      if (bv && k < K) c[k] += (uint32_t)(gc[w + k * kw] >> (h << 5));
   }
   // inclusive scan of the counts over the lanes of the wave
   uint32_t inc[KT];
@@ -1192,13 +1279,14 @@ __global__ __launch_bounds__(256) void k_scan_finish_bins(ScanArgs a, int PT, in
 #pragma unroll
     for (int k = 0; k < KT; ++k) wtot[wv][k] = inc[k];
   lds_barrier();   // also: every thread's slot reads are complete
-  if (b < (B < 128 ? B : 128))
+  // clear this particle's 32-bit halves only: the pair partner's work-group
+  // may still be reading the other halves
+  if (bv)
     for (int rr = 0; rr < R; ++rr) {
-      unsigned long long *gz =
-          reinterpret_cast<unsigned long long *>(base + (size_t)rr * n_pt * slot_sz);
+      uint32_t *gz = reinterpret_cast<uint32_t *>(base + (size_t)rr * n_pt * slot_sz);
 #pragma unroll
       for (int k = 0; k < KT; ++k)
-        if (k < K) gz[w + k * PT] = 0ull;
+        if (k < K) gz[2 * (w + k * kw) + h] = 0u;
     }
   uint32_t left[KT], tot[KT];
 #pragma unroll
@@ -1383,7 +1471,8 @@ void k_fused_hist(ScanArgs a, const float *X, const float *W, int D, int64_t CH,
   const float off0 = -fmaf(zmin, inv, 0.005f);
   const unsigned bmax = (unsigned)B - 1u;
   const unsigned labk = pv ? (unsigned)K : 0u;
-  const uint32_t pt4 = PT * 4u, sb4 = (uint32_t)hl.SB * 4u, pl4 = (uint32_t)li * 4u;
+  const uint32_t ph4 = PT * 2u, sb4 = (uint32_t)hl.SB * 4u, pl4 = (uint32_t)(li >> 1) * 4u;
+  const uint32_t pinc = 1u << ((li & 1) << 4);
   unsigned char *hb = reinterpret_cast<unsigned char *>(hc);
   const int nsub = (int)((it.hi - it.lo + 31) / 32);
 
@@ -1415,8 +1504,8 @@ void k_fused_hist(ScanArgs a, const float *X, const float *W, int D, int64_t CH,
         g = (unsigned)bin_of(rule, z);
       }
       const unsigned lb = min((unsigned)lab, (unsigned)K - 1u);
-      const uint32_t inc = (rin && (unsigned)lab < labk) ? __umul24(g >> 7, 0xFFFFu) + 1u : 0u;
-      const uint32_t off = __umul24(g & 127u, sb4) + __umul24(lb, pt4) + pl4;
+      const uint32_t inc = (rin && (unsigned)lab < labk) ? pinc : 0u;
+      const uint32_t off = __umul24(g, sb4) + lb * ph4 + pl4;
       atomicAdd(reinterpret_cast<uint32_t *>(hb + off), inc);
     }
   }
