@@ -792,12 +792,13 @@ struct StreamOps {
 __host__ __device__ constexpr size_t stream_lds_bytes(int MK, int FN) {
   return (size_t)FN * ((MK == MK_FF ? 128 : 256) / 2 * (MK == MK_BB ? 2 : 4) / 16) * 1024;
 }
-// bfloat16 Z goes out through a per-wave LDS staging area: the FN * 4
-// eight-particle tiles of a sub-tile, 32 rows of 16 bytes each plus one row
-// of padding (so the lanes of one row write distinct banks).
+// bfloat16 Z goes out through a per-wave LDS staging area: the 4
+// eight-particle tiles of one 32-particle block of a sub-tile, 32 rows of 16
+// bytes each plus one row of padding (so the lanes of one row write distinct
+// banks), reused block after block (a wave's LDS accesses complete in order).
 constexpr int STAGE_TILE = 33 * 16;
-__host__ __device__ constexpr size_t stream_stage_bytes(int FN) {
-  return (size_t)SW * FN * 4 * STAGE_TILE;
+__host__ __device__ constexpr size_t stream_stage_bytes(int) {
+  return (size_t)SW * 4 * STAGE_TILE;
 }
 // The dimensions one chunk covers: the kernel takes D <= KCH (one chunk).
 __host__ __device__ constexpr int stream_kch(int MK) { return MK == MK_FF ? 128 : 256; }
@@ -1060,7 +1061,7 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
           h = fmaxf(h, ok ? acc[f][r] : -__builtin_huge_valf());
         }
         unsigned char *stg = reinterpret_cast<unsigned char *>(wl) + stream_lds_bytes(MK, FN) +
-                             (size_t)wave * (FN * 4 * STAGE_TILE) + (size_t)f * 4 * STAGE_TILE;
+                             (size_t)wave * (4 * STAGE_TILE);
         unsigned char *wp = stg + (li >> 3) * STAGE_TILE + 4 * kh * 16 + (li & 7) * 2;
 #pragma unroll
         for (int r = 0; r < 16; ++r)
@@ -1205,7 +1206,7 @@ slm_status launch_stream_f(const ProjectArgs &a, hipStream_t s, int want_xcd = 1
   return SLM_OK;
 }
 
-constexpr size_t STREAM_LDS_MAX = 128 * 1024;
+constexpr size_t STREAM_LDS_MAX = 159 * 1024;
 
 // Shape class of a projection launch in the plan cache: the kernel (the
 // streaming kernel's operand kind 0..2, or 3 for the short kernel), D, P and
@@ -1227,8 +1228,9 @@ bool stream_fn_fits(int MK, int FN, const ProjectArgs &a) {
          stream_lds_bytes(MK, FN) + stage <= STREAM_LDS_MAX;
 }
 
-// Particle blocks per wave FN (4, 2 or 1: the widest that fits, or the
-// cached / forced plan's) and the work-group order.
+// Particle blocks per wave FN (the widest that fits: 8 for bfloat16 data
+// and directions, else 4, 2 or 1; or the cached / forced plan's) and the
+// work-group order.
 template <int MK>
 slm_status launch_stream(const ProjectArgs &a, hipStream_t s) {
   const size_t xe = MK == MK_FF ? 4 : 2, we = MK == MK_BB ? 2 : 4;
@@ -1237,6 +1239,9 @@ slm_status launch_stream(const ProjectArgs &a, hipStream_t s) {
                    reinterpret_cast<uintptr_t>(a.X) % 16 == 0 &&
                    reinterpret_cast<uintptr_t>(a.W) % 16 == 0;
   int fn = stream_fn_fits(MK, 4, a) ? 4 : stream_fn_fits(MK, 2, a) ? 2 : 1;
+  // 256 particles per work-group (bfloat16 data and directions): half the
+  // X reads per matrix-core operation
+  if (MK == MK_BB && stream_fn_fits(MK, 8, a)) fn = 8;
   int xcd = 1;
   int64_t v0 = 0, v1 = 0;
   if (g_forced_proj) {
@@ -1244,10 +1249,14 @@ slm_status launch_stream(const ProjectArgs &a, hipStream_t s) {
     v1 = g_forced_proj[1];
   }
   if ((g_forced_proj || plan_lookup(proj_key(MK, a), &v0, &v1)) &&
-      (v0 == 1 || v0 == 2 || v0 == 4) && stream_fn_fits(MK, (int)v0, a)) {
+      (v0 == 1 || v0 == 2 || v0 == 4 || (MK == MK_BB && v0 == 8)) &&
+      stream_fn_fits(MK, (int)v0, a)) {
     fn = (int)v0;
     xcd = v1 != 0;
   }
+  if constexpr (MK == MK_BB)
+    if (fn == 8)
+      return vec ? launch_stream_f<MK, 8, true>(a, s, xcd) : launch_stream_f<MK, 8, false>(a, s, xcd);
   if (fn == 4)
     return vec ? launch_stream_f<MK, 4, true>(a, s, xcd) : launch_stream_f<MK, 4, false>(a, s, xcd);
   if (fn == 2)
@@ -1287,6 +1296,7 @@ void set_stream_attr_mk(int bytes) {
   set_stream_attr_fn<MK, 1>(bytes);
   set_stream_attr_fn<MK, 2>(bytes);
   set_stream_attr_fn<MK, 4>(bytes);
+  if constexpr (MK == MK_BB) set_stream_attr_fn<MK, 8>(bytes);
 }
 
 // SLM_PROJ_STREAM=0 keeps the tile kernels for every shape (timing
@@ -1394,8 +1404,8 @@ slm_status tune_project(const ProjectArgs &a, hipStream_t s) {
   if (kind == 3) {
     for (int v = 0; v <= 2; ++v) cand.push_back({v, 0});
   } else {
-    for (int fn : {4, 2, 1})
-      if (stream_fn_fits(kind, fn, a))
+    for (int fn : {8, 4, 2, 1})
+      if ((fn < 8 || kind == MK_BB) && stream_fn_fits(kind, fn, a))
         for (int x : {1, 0}) cand.push_back({fn, x});
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
