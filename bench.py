@@ -165,6 +165,10 @@ def headline(api, args, dev):
     proj_flops = 2.0 * D * ss_p
     scan_bytes = 2.0 * ss_p + 4.0 * rows_p
     rproj_flops = 2.0 * D * ssr_p
+    # the re-scoring reads each row's X again and writes 4 B of float32 Z per
+    # re-scored sample-split; its 2 D flops (three bfloat16 products each) per
+    # 4 + 2 D / k bytes keep it below the matrix cores' ridge: HBM-bound
+    rproj_bytes = 4.0 * ssr_p + rows_p * 2 * D
     rscan_bytes = 4.0 * ssr_p + 4.0 * rows_p
     n_proj, n_scan, n_rp, n_rs = (max(1, int(tm[i])) for i in (6, 7, 10, 11))
     proj_s, scan_s, rp_s, rs_s = (tm[i] * 1e-3 for i in (3, 4, 8, 9))
@@ -181,9 +185,13 @@ def headline(api, args, dev):
                           "bytes_per_launch": scan_bytes / n_scan,
                           "GB/s": scan_bytes / scan_s / 1e9,
                           "frac_hbm": scan_bytes / scan_s / 1e9 / HBM_PEAK_GBS},
-        "project_rescore_f32": {"launches": n_rp, "avg_us": 1e6 * rp_s / n_rp,
-                                "TFLOP/s": rproj_flops / rp_s / 1e12,
-                                "frac_fp32_mfma": rproj_flops / rp_s / 1e12 / FP32_PEAK_TFLOPS},
+        "project_rescore_f32": {"kernel": "k_project_stream (float32 directions as three "
+                                          "bfloat16 parts, BF16 MFMA)",
+                                "launches": n_rp, "avg_us": 1e6 * rp_s / n_rp,
+                                "bytes_per_launch": rproj_bytes / n_rp,
+                                "GB/s": rproj_bytes / rp_s / 1e9,
+                                "frac_hbm": rproj_bytes / rp_s / 1e9 / HBM_PEAK_GBS,
+                                "TFLOP/s": rproj_flops / rp_s / 1e12},
         "scan_rescore": {"launches": n_rs, "avg_us": 1e6 * rs_s / n_rs,
                          "GB/s": rscan_bytes / rs_s / 1e9},
         "swarm_steps_ms": tm[5], "partitions_ms": tm[2], "tree_ms_instrumented": tm[0],

@@ -762,14 +762,21 @@ slm_status launch_bf16(const ProjectArgs &a, hipStream_t s) {
 // registers, double-buffered across sub-tiles; every wave computes all PT
 // particles of its rows, so each X row is read once per particle tile.
 //
-// The kernel takes D <= KCH dimensions (zero-padded to KCH): lanes 0-31
-// supply the first KCH/2 of them and lanes 32-63 the second half, so a lane's
-// A operand is one contiguous 256-byte run of its X row.  Larger D take the
-// tile kernels.  Three operand kinds:
+// The kernel takes D <= KCH dimensions (zero-padded to KCH).  Group q of the
+// A operand is the row's q-th 32-byte piece: lanes 0-31 supply its first 16
+// bytes and lanes 32-63 its second, so one A load touches a single 32-byte
+// piece (one cache line) of each of the sub-tile's rows, and consecutive
+// loads walk the rows' lines in order.  Larger D take the tile kernels.
+// Three operand kinds:
 //   MK_BB  X and W bfloat16: v_mfma_f32_32x32x16_bf16, KCH = 256 (16 steps
 //          of 8 dimensions per half);
-//   MK_XB  X bfloat16, W float32: v_mfma_f32_32x32x2f32, KCH = 256 (128
-//          steps of one dimension per half; X widened exactly);
+//   MK_XB  X bfloat16, W float32: each direction is split into three
+//          bfloat16 parts, w = w1 + w2 + w3 (w1 = bf16(w), w2 = bf16(w - w1),
+//          w3 = bf16(w - w1 - w2), each remainder exact in float32), kept
+//          as three fragment planes in LDS; v_mfma_f32_32x32x16_bf16 over
+//          the three planes into three accumulators (every product exact,
+//          float32 accumulation), added as acc1 + (acc2 + acc3) at the end,
+//          KCH = 256;
 //   MK_FF  X and W float32: v_mfma_f32_32x32x2f32, KCH = 128 (64 steps).
 // Dimensions past D are zero in W (the A operand there holds whatever
 // finite X values the clamped loads read).  Each output element is the same
@@ -783,14 +790,16 @@ template <int MK>
 struct StreamOps {
   static constexpr int KCH = MK == MK_FF ? 128 : 256;   // dimensions per chunk
   static constexpr int XBYTES = MK == MK_FF ? 4 : 2;     // bytes per X element
-  static constexpr int WBYTES = MK == MK_BB ? 2 : 4;     // bytes per W element
-  // 16-byte W groups per lane and chunk: the lane's half-chunk of W
-  static constexpr int G = KCH / 2 * WBYTES / 16;
+  static constexpr int WBYTES = MK == MK_FF ? 4 : 2;     // bytes per LDS W element
+  static constexpr int PLANES = MK == MK_XB ? 3 : 1;     // W planes (bfloat16 parts)
+  // 16-byte W groups per lane and chunk: the lane's half-chunk of W, per plane
+  static constexpr int GP = KCH / 2 * WBYTES / 16;
+  static constexpr int G = GP * PLANES;
 };
 
 // LDS of a work-group's W tile: FN blocks of G 1-KB fragment groups.
 __host__ __device__ constexpr size_t stream_lds_bytes(int MK, int FN) {
-  return (size_t)FN * ((MK == MK_FF ? 128 : 256) / 2 * (MK == MK_BB ? 2 : 4) / 16) * 1024;
+  return (size_t)FN * (MK == MK_XB ? 48 : 16) * 1024;
 }
 // bfloat16 Z goes out through a per-wave LDS staging area: the 4
 // eight-particle tiles of one 32-particle block of a sub-tile, 32 rows of 16
@@ -889,9 +898,56 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
 
   float mn[FN], mx[FN];
   // the node's W tile into LDS, fragment order: group g of lane (li, h) in
-  // block f holds W elements h KCH/2 + g (16 / WBYTES) ...
+  // block f holds W elements g (32 / WBYTES) + h (16 / WBYTES) ..., the
+  // dimensions of A's group g on that lane
   auto fill_w = [&](int j) {
     const int64_t wb = (int64_t)j * P;
+    if constexpr (MK == MK_XB) {
+      // unit (f, g, lane): 8 float32 of the lane's row, split into the three
+      // bfloat16 planes at groups g, GP + g, 2 GP + g of block f
+      constexpr int GP = O::GP;
+      constexpr int units = FN * GP * 64;
+      constexpr int UB = 4;
+      for (int u0 = threadIdx.x; u0 < units; u0 += UB * 64 * SW) {
+        uint4 v[UB][2];
+#pragma unroll
+        for (int e = 0; e < UB; ++e) {
+          const int u = u0 + e * 64 * SW;
+          const int l = u & 63, g = (u >> 6) % GP, f = u / (64 * GP);
+          const int p = p0 + f * 32 + (l & 31);
+          const int e0 = g * 16 + (l >> 5) * 8;
+          v[e][0] = v[e][1] = make_uint4(0u, 0u, 0u, 0u);
+          if (u < units && p < P) {
+            v[e][0] = load_group<4, VEC, true>(a.W, wb + p, D, e0);
+            v[e][1] = load_group<4, VEC, true>(a.W, wb + p, D, e0 + 4);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < UB; ++e) {
+          const int u = u0 + e * 64 * SW;
+          if (u >= units) continue;
+          const int l = u & 63, g = (u >> 6) % GP, f = u / (64 * GP);
+          const uint32_t w[8] = {v[e][0].x, v[e][0].y, v[e][0].z, v[e][0].w,
+                                 v[e][1].x, v[e][1].y, v[e][1].z, v[e][1].w};
+          uint32_t h[3][4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float r0 = __uint_as_float(w[2 * i]), r1 = __uint_as_float(w[2 * i + 1]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const float b0 = round_bf16(r0), b1 = round_bf16(r1);
+              h[q][i] = pack_bf16(b0, b1);
+              r0 = __fsub_rn(r0, b0);
+              r1 = __fsub_rn(r1, b1);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            wl[((f * 3 + q) * GP + g) * 64 + l] = make_uint4(h[q][0], h[q][1], h[q][2], h[q][3]);
+        }
+      }
+      return;
+    }
     constexpr int units = FN * G * 64;
     constexpr int UB = 8;   // loads in flight per thread
     for (int u0 = threadIdx.x; u0 < units; u0 += UB * 64 * SW) {
@@ -903,7 +959,7 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
         const int g = (u >> 6) % G;
         const int f = u / (64 * G);
         const int p = p0 + f * 32 + (l & 31);
-        const int e0 = (l >> 5) * (KCH / 2) + g * (16 / O::WBYTES);
+        const int e0 = g * (32 / O::WBYTES) + (l >> 5) * (16 / O::WBYTES);
         v[e] = make_uint4(0u, 0u, 0u, 0u);
         if (u < units && p < P) v[e] = load_group<O::WBYTES, VEC, true>(a.W, wb + p, D, e0);
       }
@@ -933,9 +989,8 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
       }
     }
   };
-  // A operand: 16 groups of 16 bytes, the lane's contiguous half of the
-  // dimensions of row lo + li (the sub-tile's last row for lanes past its
-  // n rows).  VEC: buffer loads from a resource at the sub-tile's first row,
+  // A operand: 16 groups of 16 bytes, the lane's half of each 32-byte piece
+  // of row lo + li (the sub-tile's last row for lanes past its n rows).  VEC: buffer loads from a resource at the sub-tile's first row,
   // so the per-load offsets are immediates and the row base is scalar.
   auto load_a = [&](int64_t lo, int n, uint4 (&A)[16]) {
     const int lr = li < n ? li : n - 1;
@@ -943,17 +998,17 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
       const char *base = static_cast<const char *>(a.X) + lo * row_bytes;
       const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<char *>(base), 0, (int)(n * row_bytes), BUF_DW3);
-      const int vo = (int)(lr * row_bytes) + kh * (KCH / 2) * XB;
+      const int vo = (int)(lr * row_bytes) + kh * 16;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(xr, vo + q * 16, 0, 0);
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(xr, vo + q * 32, 0, 0);
         A[q] = make_uint4(v[0], v[1], v[2], v[3]);
       }
     } else {
-      const int e0 = kh * (KCH / 2);
+      const int e0 = kh * (16 / XB);
 #pragma unroll
       for (int q = 0; q < 16; ++q)
-        A[q] = load_group<XB, false, false>(a.X, lo + lr, D, e0 + q * (16 / XB));
+        A[q] = load_group<XB, false, false>(a.X, lo + lr, D, e0 + q * (32 / XB));
     }
   };
   // The W fragments of step group q + 1 are read from LDS while the MFMAs of
@@ -977,35 +1032,42 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
                                                            acc[f], 0, 0, 0);
       }
     } else if constexpr (MK == MK_XB) {
-      // A[q] holds 8 bfloat16 (steps 8q .. 8q+7), W groups 2q, 2q+1 the
-      // matching 8 floats
-      uint4 b[2][FN][2];
+      // the three bfloat16 planes of W (groups q, GP + q, 2 GP + q of each
+      // block) into three accumulators; W of step q + 1 is read while the
+      // MFMAs of step q run
+      constexpr int GP = O::GP;
+      f32x16 a2[FN], a3[FN];
 #pragma unroll
-      for (int f = 0; f < FN; ++f) {
-        b[0][f][0] = wc[(f * G) * 64];
-        b[0][f][1] = wc[(f * G + 1) * 64];
-      }
+      for (int f = 0; f < FN; ++f) a2[f] = a3[f] = f32x16{};
+      uint4 b[2][FN][3];
+#pragma unroll
+      for (int f = 0; f < FN; ++f)
+#pragma unroll
+        for (int q3 = 0; q3 < 3; ++q3) b[0][f][q3] = wc[((f * 3 + q3) * GP) * 64];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         if (q + 1 < 16) {
 #pragma unroll
-          for (int f = 0; f < FN; ++f) {
-            b[(q + 1) & 1][f][0] = wc[(f * G + 2 * q + 2) * 64];
-            b[(q + 1) & 1][f][1] = wc[(f * G + 2 * q + 3) * 64];
-          }
+          for (int f = 0; f < FN; ++f)
+#pragma unroll
+            for (int q3 = 0; q3 < 3; ++q3)
+              b[(q + 1) & 1][f][q3] = wc[((f * 3 + q3) * GP + q + 1) * 64];
         }
-        const uint32_t w4[4] = {A[q].x, A[q].y, A[q].z, A[q].w};
+        const bf16x8 av = __builtin_bit_cast(bf16x8, A[q]);
 #pragma unroll
         for (int f = 0; f < FN; ++f) {
-          const uint4 b0 = b[q & 1][f][0], b1 = b[q & 1][f][1];
-          const uint32_t bw[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const float xa = __uint_as_float((e & 1) ? (w4[e >> 1] & 0xFFFF0000u) : (w4[e >> 1] << 16));
-            acc[f] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, __uint_as_float(bw[e]), acc[f], 0, 0, 0);
-          }
+          acc[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              av, __builtin_bit_cast(bf16x8, b[q & 1][f][0]), acc[f], 0, 0, 0);
+          a2[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              av, __builtin_bit_cast(bf16x8, b[q & 1][f][1]), a2[f], 0, 0, 0);
+          a3[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              av, __builtin_bit_cast(bf16x8, b[q & 1][f][2]), a3[f], 0, 0, 0);
         }
       }
+#pragma unroll
+      for (int f = 0; f < FN; ++f)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[f][r] = __fadd_rn(acc[f][r], __fadd_rn(a2[f][r], a3[f][r]));
     } else {
       uint4 b[2][FN];
 #pragma unroll
