@@ -1209,26 +1209,29 @@ __global__ __launch_bounds__(256) void k_scan_finish(ScanArgs a, int64_t CH, int
 
 
 // Classification nodes spanning several chunks, finished one bin per thread:
-// work-group (slot s, particle tile, particle q) of 256 threads, thread b
-// holding bin b of the node's accumulated histogram.  Class counts are summed
-// over the bins by wave scans (then across the 4 waves); thread b evaluates
-// the split "bins < b go left" with the same arithmetic as finish_scan, and
-// the work-group keeps the smallest loss, ties to the smaller bin (the first
-// minimum in bin order), so the outputs equal finish_scan's.  The slot words
-// of the particle are cleared for the next call.
+// work-group (slot s, particle tile, particle pair j) of 256 threads, thread
+// b holding bin b of the node's accumulated histogram for particles 2j and
+// 2j + 1 (the two halves of each 64-bit slot word, so every word is read
+// once).  Class counts are summed over the bins by wave scans (then across
+// the 4 waves); thread b evaluates, for each of the two particles, the split
+// "bins < b go left" with the same arithmetic as finish_scan, and the
+// work-group keeps each particle's smallest loss, ties to the smaller bin
+// (the first minimum in bin order), so the outputs equal finish_scan's.  The
+// slot words of the pair are cleared for the next call.
 template <int KT>
 __global__ __launch_bounds__(256) void k_scan_finish_bins(ScanArgs a, int PT, int64_t CH,
                                                           int n_pt, size_t slot_sz,
                                                           int64_t n_slots, int R) {
-  __shared__ uint32_t wtot[4][KT];
-  __shared__ double wbl[4];
-  __shared__ int wbb[4];
+  __shared__ uint32_t wtot[2][4][KT];
+  __shared__ double wbl[2][4];
+  __shared__ int wbb[2][4];
   __shared__ double lgt[2 * LG_TBL];
+  const int PH = PT / 2;
   const int64_t bid = blockIdx.x;
-  const int qt = (int)(bid % PT);
-  const int pt = (int)((bid / PT) % n_pt);
-  const int64_t slot = bid / ((int64_t)PT * n_pt);
-  if (slot >= n_slots || pt * PT + qt >= a.P) return;
+  const int jp = (int)(bid % PH);
+  const int pt = (int)((bid / PH) % n_pt);
+  const int64_t slot = bid / ((int64_t)PH * n_pt);
+  if (slot >= n_slots || pt * PT + 2 * jp >= a.P) return;
   // the node whose rows start in chunk `slot` and continue past it
   const int64_t lim = (slot + 1) * CH;
   if (a.n_nodes <= 0) return;
@@ -1253,121 +1256,140 @@ __global__ __launch_bounds__(256) void k_scan_finish_bins(ScanArgs a, int PT, in
       static_cast<unsigned char *>(a.ws) + ((size_t)slot * R * n_pt + pt) * slot_sz;
   const int b = tid;
   const bool bv = b < B;
-  const int w = cnt_word(false, b, 0, qt, SB, PT), h = qt & 1, kw = PT / 2;
-  uint32_t c[KT];
+  const int w = cnt_word(false, b, 0, 2 * jp, SB, PT);
+  uint32_t c[2][KT];
 #pragma unroll
-  for (int k = 0; k < KT; ++k) c[k] = 0u;
+  for (int k = 0; k < KT; ++k) c[0][k] = c[1][k] = 0u;
   for (int rr = 0; rr < R; ++rr) {
     const unsigned long long *gc =
         reinterpret_cast<const unsigned long long *>(base + (size_t)rr * n_pt * slot_sz);
 #pragma unroll
     for (int k = 0; k < KT; ++k)
-      if (bv && k < K) c[k] += (uint32_t)(gc[w + k * kw] >> (h << 5));
+      if (bv && k < K) {
+        const unsigned long long v = gc[w + k * PH];
+        c[0][k] += (uint32_t)v;
+        c[1][k] += (uint32_t)(v >> 32);
+      }
   }
-  // inclusive scan of the counts over the lanes of the wave
-  uint32_t inc[KT];
+  // inclusive scans of the counts over the lanes of the wave
+  uint32_t inc[2][KT];
 #pragma unroll
-  for (int k = 0; k < KT; ++k) inc[k] = c[k];
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int k = 0; k < KT; ++k) inc[h][k] = c[h][k];
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1)
 #pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      const uint32_t t = __shfl_up(inc[k], d);
-      inc[k] += lane >= d ? t : 0u;
-    }
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const uint32_t t = __shfl_up(inc[h][k], d);
+        inc[h][k] += lane >= d ? t : 0u;
+      }
   if (lane == 63)
 #pragma unroll
-    for (int k = 0; k < KT; ++k) wtot[wv][k] = inc[k];
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < KT; ++k) wtot[h][wv][k] = inc[h][k];
   lds_barrier();   // also: every thread's slot reads are complete
-  // clear this particle's 32-bit halves only: the pair partner's work-group
-  // may still be reading the other halves
+  // this work-group alone reads the pair's words: clear them whole
   if (bv)
     for (int rr = 0; rr < R; ++rr) {
-      uint32_t *gz = reinterpret_cast<uint32_t *>(base + (size_t)rr * n_pt * slot_sz);
+      unsigned long long *gz =
+          reinterpret_cast<unsigned long long *>(base + (size_t)rr * n_pt * slot_sz);
 #pragma unroll
       for (int k = 0; k < KT; ++k)
-        if (k < K) gz[2 * (w + k * kw) + h] = 0u;
+        if (k < K) gz[w + k * PH] = 0ull;
     }
-  uint32_t left[KT], tot[KT];
 #pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    uint32_t before = 0u, all = 0u;
+  for (int h = 0; h < 2; ++h) {
+    uint32_t left[KT], tot[KT];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const uint32_t t = wtot[v][k];
-      all += t;
-      before += v < wv ? t : 0u;
-    }
-    left[k] = before + inc[k] - c[k];   // bins < b
-    tot[k] = all;
-  }
-  int64_t n = 0;
+    for (int k = 0; k < KT; ++k) {
+      uint32_t before = 0u, all = 0u;
 #pragma unroll
-  for (int k = 0; k < KT; ++k) n += tot[k];
-  const double dn = (double)n;
-  double bl = __builtin_huge_val();
-  int bb = 0x7fffffff;
-  if (bv && b >= 1) {
-    int64_t nL = 0;
-#pragma unroll
-    for (int k = 0; k < KT; ++k) nL += left[k];
-    const int64_t nR = n - nL;
-    if (nL != 0 && nR != 0) {
-      double loss;
-      if (!ent) {
-        uint64_t AL = 0, AR = 0;
-#pragma unroll
-        for (int k = 0; k < KT; ++k) {
-          const uint64_t l = left[k], rt = tot[k] - left[k];
-          AL += l * l;
-          AR += rt * rt;
-        }
-        const double sv = (double)AL / (double)nL + (double)AR / (double)nR;
-        loss = (dn - sv) / dn;
-      } else {
-        double sL = 0.0, sR = 0.0;
-#pragma unroll
-        for (int k = 0; k < KT; ++k)
-          if (k < K) {
-            sL += nlog2n_cnt(left[k], lgt, lgt + LG_TBL);
-            sR += nlog2n_cnt(tot[k] - left[k], lgt, lgt + LG_TBL);
-          }
-        const double TL = nlog2n_cnt((uint32_t)nL, lgt, lgt + LG_TBL) - sL;
-        const double TR = nlog2n_cnt((uint32_t)nR, lgt, lgt + LG_TBL) - sR;
-        loss = (TL + TR) / dn;
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t t = wtot[h][v][k];
+        all += t;
+        before += v < wv ? t : 0u;
       }
-      bl = loss;
-      bb = b;
+      left[k] = before + inc[h][k] - c[h][k];   // bins < b
+      tot[k] = all;
     }
-  }
-  // smallest loss, ties to the smaller bin: over the wave, then the 4 waves
+    int64_t n = 0;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const double ol = __shfl_xor(bl, d);
-    const int ob = __shfl_xor(bb, d);
-    if (ol < bl || (ol == bl && ob < bb)) {
-      bl = ol;
-      bb = ob;
+    for (int k = 0; k < KT; ++k) n += tot[k];
+    const double dn = (double)n;
+    double bl = __builtin_huge_val();
+    int bb = 0x7fffffff;
+    if (bv && b >= 1) {
+      int64_t nL = 0;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) nL += left[k];
+      const int64_t nR = n - nL;
+      if (nL != 0 && nR != 0) {
+        double loss;
+        if (!ent) {
+          uint64_t AL = 0, AR = 0;
+#pragma unroll
+          for (int k = 0; k < KT; ++k) {
+            const uint64_t l = left[k], rt = tot[k] - left[k];
+            AL += l * l;
+            AR += rt * rt;
+          }
+          const double sv = (double)AL / (double)nL + (double)AR / (double)nR;
+          loss = (dn - sv) / dn;
+        } else {
+          double sL = 0.0, sR = 0.0;
+#pragma unroll
+          for (int k = 0; k < KT; ++k)
+            if (k < K) {
+              sL += nlog2n_cnt(left[k], lgt, lgt + LG_TBL);
+              sR += nlog2n_cnt(tot[k] - left[k], lgt, lgt + LG_TBL);
+            }
+          const double TL = nlog2n_cnt((uint32_t)nL, lgt, lgt + LG_TBL) - sL;
+          const double TR = nlog2n_cnt((uint32_t)nR, lgt, lgt + LG_TBL) - sR;
+          loss = (TL + TR) / dn;
+        }
+        bl = loss;
+        bb = b;
+      }
+    }
+    // smallest loss, ties to the smaller bin: over the wave, then the 4 waves
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const double ol = __shfl_xor(bl, d);
+      const int ob = __shfl_xor(bb, d);
+      if (ol < bl || (ol == bl && ob < bb)) {
+        bl = ol;
+        bb = ob;
+      }
+    }
+    if (lane == 0) {
+      wbl[h][wv] = bl;
+      wbb[h][wv] = bb;
     }
   }
-  if (lane == 0) {
-    wbl[wv] = bl;
-    wbb[wv] = bb;
-  }
-  const int64_t o = (int64_t)lo * a.P + (int64_t)pt * PT + qt;
+  const int64_t o0 = (int64_t)lo * a.P + (int64_t)pt * PT + 2 * jp;
+  const bool v1 = pt * PT + 2 * jp + 1 < a.P;
   if (a.hist_out && bv)
 #pragma unroll
-    for (int k = 0; k < KT; ++k)
-      if (k < K) a.hist_out[(o * B + b) * K + k] = c[k];
+    for (int h = 0; h < 2; ++h)
+      if (h == 0 || v1)
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+          if (k < K) a.hist_out[((o0 + h) * B + b) * K + k] = c[h][k];
   lds_barrier();
-  if (tid == 0) {
-    double l = wbl[0];
-    int bw = wbb[0];
+  if (tid < 2 && (tid == 0 || v1)) {
+    const int h = tid;
+    const int64_t o = o0 + h;
+    double l = wbl[h][0];
+    int bw = wbb[h][0];
 #pragma unroll
     for (int v = 1; v < 4; ++v)
-      if (wbl[v] < l || (wbl[v] == l && wbb[v] < bw)) {
-        l = wbl[v];
-        bw = wbb[v];
+      if (wbl[h][v] < l || (wbl[h][v] == l && wbb[h][v] < bw)) {
+        l = wbl[h][v];
+        bw = wbb[h][v];
       }
     if (bw == 0x7fffffff) {
       a.best_split[o] = -1;
@@ -1798,7 +1820,7 @@ slm_status launch_hist_cfg(const ScanArgs &a, const Plan &pl, hipStream_t s) {
       hipLaunchKernelGGL((k_scan_finish<PT, KT, MSE>), dim3((unsigned)grid_f), dim3(256), 0, s, a,
                          pl.CH, n_pt, slot, n_slots, R);
     } else {
-      const int64_t grid_f = used * n_pt * PT;
+      const int64_t grid_f = used * n_pt * (PT / 2);
       SLM_CHECK(used <= n_slots && grid_f < (1ll << 31) && a.bins <= 256, SLM_E_SHAPE,
                 "slm_split_scan: finish grid too large");
       hipLaunchKernelGGL((k_scan_finish_bins<KT>), dim3((unsigned)grid_f), dim3(256), 0, s, a, PT,
@@ -2001,7 +2023,7 @@ static slm_status launch_fused_k(const ScanArgs &a, const float *X, const float 
   if (a.N > CH) {
     const int64_t used = (a.N - 1) / CH + 1;
     if (finish_by_bins(a, CH)) {
-      const int64_t grid_f = used * n_pt * PT;
+      const int64_t grid_f = used * n_pt * (PT / 2);
       SLM_CHECK(used <= n_slots && grid_f < (1ll << 31) && a.bins <= 256, SLM_E_SHAPE,
                 "slm_evaluate: finish grid too large");
       hipLaunchKernelGGL((k_scan_finish_bins<KT>), dim3((unsigned)grid_f), dim3(256), 0, s, a, PT,
