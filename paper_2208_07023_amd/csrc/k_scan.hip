@@ -1033,7 +1033,8 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
     i = ngw * U4;
   }
   // remaining rows (all rows when a rule is ill conditioned or the tile is
-  // partial): exact bins, and nothing added for particles past P
+  // partial): the fast bin when the wave is on the fast path, else the exact
+  // search; nothing added for particles past P
   for (; i < n4; ++i) {
     uint32_t v[4];
     load_z(i, v);
@@ -1042,7 +1043,15 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
     const uint32_t base = (uint32_t)(lok ? lab : 0) * ph4 + q8;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const unsigned g = (unsigned)bin_of(rl[e], __uint_as_float(v[e]));
+      const float z = __uint_as_float(v[e]);
+      unsigned g;
+      if (wave_fast) {
+        const int g1 = (int)fmaf(z, iv[e], o1[e]);
+        const float eg = __fadd_rn(zm[e], __fmul_rn((float)g1, dl[e]));
+        g = min((uint32_t)(g1 - 1 + (eg > z ? 0 : 1)), bmax);
+      } else {
+        g = (unsigned)bin_of(rl[e], z);
+      }
       const uint32_t inc = lok && pv4[e] ? ((e & 1) ? 0x10000u : 1u) : 0u;
       atomicAdd(reinterpret_cast<uint32_t *>(hb + g * sb4 + base + 4u * (e >> 1)), inc);
     }
