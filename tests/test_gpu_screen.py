@@ -94,11 +94,12 @@ def test_bf16_projection_gaussian_within_fp32_bound(gpu_lib, D, P, sizes):
 
 
 @pytest.mark.parametrize("D,P,sizes", [(8, 32, [400, 0, 77]), (128, 32, [300, 129]),
-                                       (256, 40, [250])])
+                                       (256, 40, [250]), (13, 5, [60, 0, 7]), (100, 33, [70])])
 def test_mixed_projection_exact_and_column_alone_identical(gpu_lib, D, P, sizes):
     """bfloat16 X with float32 W: exact on integer-valued inputs, and a column
     recomputed alone (P = 1, the partition) equals the same column among P
-    (the re-scoring) bit for bit on Gaussian inputs."""
+    (the re-scoring) bit for bit on Gaussian inputs.  D = 13 and 100 take the
+    path for rows that are not whole 16-byte groups."""
     api = gpu_lib
     off = inputs.segment_offsets(sizes)
     N, nn = int(off[-1]), len(sizes)
@@ -118,6 +119,32 @@ def test_mixed_projection_exact_and_column_alone_identical(gpu_lib, D, P, sizes)
         W1 = np.ascontiguousarray(W.reshape(nn, P, D)[:, p, :])
         Z1, _, _ = api.project(_bf16(X), _t(W1), _t(off), 1)
         assert np.array_equal(Z1.cpu().numpy()[:, 0], Zall[:, p]), p
+
+
+@pytest.mark.parametrize("D,P,sizes", [(256, 64, [900, 5]), (100, 33, [70, 0, 41]), (13, 5, [60])])
+def test_mixed_projection_gaussian_within_fp32_bound(gpu_lib, D, P, sizes):
+    """bfloat16 X with float32 W (the re-scoring; W split into three bfloat16
+    parts, every product exact, float32 accumulation): each projection within
+    the float32 dot-product bound of the exact value, D u sum |x w| + u |z|,
+    widened by 2 % for the three parts' magnitudes (|w1| + |w2| + |w3| <=
+    |w| (1 + 2^-7)) and the final addition of the three accumulators."""
+    api = gpu_lib
+    off = inputs.segment_offsets(sizes)
+    N, nn = int(off[-1]), len(sizes)
+    rng = np.random.default_rng(D + P)
+    X = SC.bf16_round(rng.standard_normal((N, D)).astype(np.float32) * 3)
+    W = rng.standard_normal((nn * P, D)).astype(np.float32)
+    assert not np.array_equal(SC.bf16_round(W), W)
+    Z, _, _ = api.project(_bf16(X), _t(W), _t(off), P, tiled=True)
+    Z = api.untile_z(Z, P).cpu().numpy()
+    u = 2.0 ** -24
+    for j in range(nn):
+        r0, r1 = off[j], off[j + 1]
+        Wj = W[j * P:(j + 1) * P].astype(np.float64)
+        Xj = X[r0:r1].astype(np.float64)
+        z64 = Xj @ Wj.T
+        bound = 1.02 * (D * u * (np.abs(Xj) @ np.abs(Wj).T) + u * np.abs(z64))
+        assert np.all(np.abs(Z[r0:r1].astype(np.float64) - z64) <= bound + 1e-30), j
 
 
 # ------------------------------------------------------------------ select / gather / merge
