@@ -50,8 +50,8 @@ BF16_PEAK_TFLOPS = 2500.0
 TRAFFIC = {
     "k_project_stream_bf16": {
         "source": "paper_2208_07023_amd/csrc/k_project.hip",
-        "sha256": "34e6cda2ae517d0336ef6faf4c630a2fb0984d4aebdca66ed6a8617ea6c1a135",
-        "fetch_kib": 533754.9, "write_kib": 3803632.1,
+        "sha256": "0824dab3e929b1992535934341cd68e8c2336832a730ae2385eae8bf31d6f6d9",
+        "fetch_kib": 517863.3, "write_kib": 3781377.8,
         "profile": "profiles/traffic_screened_projection_N4M_D256_P1024.md",
     },
 }

@@ -1138,7 +1138,7 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
           __builtin_amdgcn_raw_buffer_store_b128(
               __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned int, v), zr,
               ok ? (int)((lane >> 5) * a.zl.ts * 2) + row * 16 : (int)0x80000000,
-              (int)(2 * s2 * a.zl.ts * 2), 0);
+              (int)(2 * s2 * a.zl.ts * 2), Z_CPOL_NT);
         }
       } else if (full && ZT == 8) {
         // 8-wide tiles: after the transpose, register t of group g holds
@@ -1156,7 +1156,7 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
 #pragma unroll
           for (int t = 0; t < 4; ++t)
             __builtin_amdgcn_raw_buffer_store_b32(v[t], zr, lane * 4 + 256 * g,
-                                                  (int)(t * a.zl.ts * 4), 0);
+                                                  (int)(t * a.zl.ts * 4), Z_CPOL_NT);
         }
       } else if (full) {
 #pragma unroll

@@ -859,8 +859,9 @@ __device__ __forceinline__ void accumulate_rows1(const ScanArgs &a, const Item &
 // then the addresses and atomics.  When every label of the wave's U4 rows is
 // a class (the usual case, one vote per step) the increments are constants;
 // otherwise a label outside [0, K) keeps its row's address in range and
-// adds 0.
-template <int PT, int WGS, bool ZB>
+// adds 0.  ZCP: the cache policy of the Z loads (0, or Z_CPOL_NT for a Z
+// larger than the MALL).
+template <int PT, int WGS, bool ZB, int ZCP>
 __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &it, int pt,
                                                  int64_t np, int wave, int lane,
                                                  unsigned char *hb, int SB) {
@@ -914,11 +915,11 @@ __device__ __forceinline__ void accumulate_rows4(const ScanArgs &a, const Item &
   constexpr int RW = ZB ? 2 : 4;
   auto load_raw = [&](int j, uint32_t (&r)[RW]) {
     if constexpr (ZB) {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b64(zr, zvo, j * zso, 0);
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(zr, zvo, j * zso, ZCP);
       r[0] = v[0];
       r[1] = v[1];
     } else {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b128(zr, zvo, j * zso, 0);
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(zr, zvo, j * zso, ZCP);
       r[0] = v[0];
       r[1] = v[1];
       r[2] = v[2];
@@ -1118,12 +1119,18 @@ void k_scan_hist(ScanArgs a, int64_t CH, int n_pt, int G, int64_t total_blocks, 
   // four consecutive particles of one row, so one 16-byte load of the row's
   // Z segment and one label load serve four sample-splits, and the label's
   // part of the LDS address is formed once per row.
+  unsigned char *const hb = reinterpret_cast<unsigned char *>(hc);
+  const bool znt = z_streams(a.N, P, a.zl.eb);
   if (!MSE && a.zl.eb == 2) {
-    accumulate_rows4<PT, WGS, true>(a, it, pt, np, wave, lane, reinterpret_cast<unsigned char *>(hc),
-                                    SB);
+    if (znt)
+      accumulate_rows4<PT, WGS, true, Z_CPOL_NT>(a, it, pt, np, wave, lane, hb, SB);
+    else
+      accumulate_rows4<PT, WGS, true, 0>(a, it, pt, np, wave, lane, hb, SB);
   } else if (!MSE && a.zl.rs == (1 << a.zl.sh) && a.zl.rs >= 8) {
-    accumulate_rows4<PT, WGS, false>(a, it, pt, np, wave, lane,
-                                     reinterpret_cast<unsigned char *>(hc), SB);
+    if (znt)
+      accumulate_rows4<PT, WGS, false, Z_CPOL_NT>(a, it, pt, np, wave, lane, hb, SB);
+    else
+      accumulate_rows4<PT, WGS, false, 0>(a, it, pt, np, wave, lane, hb, SB);
   } else {
     accumulate_rows1<PT, WGS, MSE>(a, it, p, pv, pl, rsub, wave, rule, hc, hs1, hs2, SB, SD);
   }

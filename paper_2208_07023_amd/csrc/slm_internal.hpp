@@ -150,6 +150,24 @@ __device__ __forceinline__ uint16_t f64_to_bf16(double d) {
 // tiles, bfloat16 (eb = 2: the float32 projection rounded to nearest even).
 // Word 3 of a gfx9 raw buffer resource (32-bit data format, no swizzle).
 constexpr int BUF_DW3 = 0x00020000;
+// Cache policy of the projection stream Z (the aux operand of the buffer
+// builtins; bit 1 = non-temporal).  Z is written once by the projection and
+// read once by the histogram scan.  The streaming projection's 8-wide Z
+// tiles are stored non-temporally, and the scan's Z loads are non-temporal
+// when the whole array is larger than the MALL (256 MiB).  Measured on the
+// graph-replayed screening tree (N = 4e6, D = 256, P = 1024, 8 GB of Z):
+// 1.9 % faster (stores alone 1.7 % faster, loads alone 0.4 % slower); timed
+// one launch at a time (no graph) the projection then takes about 5 % longer
+// and the scans 5-12 % less, so with the default policy part of the
+// projection's writing is still under way when it is reported done.  A Z
+// that fits the MALL (the plain tree's 102 MB) is loaded with the default
+// policy: non-temporal loads made that tree about 6 % slower.  The store
+// policy is not chosen at run time: a uniform branch around each store made
+// the projection about 10 % slower.
+constexpr int Z_CPOL_NT = 2;
+__host__ __device__ inline bool z_streams(int64_t N, int P, int eb) {
+  return N * (int64_t)P * eb > (256ll << 20);
+}
 
 struct ZLayout {
   int64_t ts, rs;
