@@ -50,8 +50,8 @@ BF16_PEAK_TFLOPS = 2500.0
 TRAFFIC = {
     "k_project_stream_bf16": {
         "source": "paper_2208_07023_amd/csrc/k_project.hip",
-        "sha256": "0824dab3e929b1992535934341cd68e8c2336832a730ae2385eae8bf31d6f6d9",
-        "fetch_kib": 517863.3, "write_kib": 3781377.8,
+        "sha256": "2411c9ff02e74b4147c882331199ceab9e7630d7bbdef1f969d3562620ebe373",
+        "fetch_kib": 586059.1, "write_kib": 3780550.6,
         "profile": "profiles/traffic_screened_projection_N4M_D256_P1024.md",
     },
 }

@@ -801,13 +801,26 @@ struct StreamOps {
 __host__ __device__ constexpr size_t stream_lds_bytes(int MK, int FN) {
   return (size_t)FN * (MK == MK_XB ? 48 : 16) * 1024;
 }
-// bfloat16 Z goes out through a per-wave LDS staging area: the 4
-// eight-particle tiles of one 32-particle block of a sub-tile, 32 rows of 16
-// bytes each plus one row of padding (so the lanes of one row write distinct
-// banks), reused block after block (a wave's LDS accesses complete in order).
+// bfloat16 Z goes out through a per-wave LDS staging area: the
+// eight-particle tiles of one 32-particle block (FN odd) or of one pair of
+// blocks (64 particles, FN even) of a sub-tile, 32 rows of 16 bytes each
+// plus one row of padding (so the lanes of one row write distinct banks),
+// reused block after block (a wave's LDS accesses complete in order).
 constexpr int STAGE_TILE = 33 * 16;
-__host__ __device__ constexpr size_t stream_stage_bytes(int) {
-  return (size_t)SW * 4 * STAGE_TILE;
+__host__ __device__ constexpr size_t stream_stage_bytes(int FN) {
+  return (size_t)SW * (FN % 2 == 0 ? 8 : 4) * STAGE_TILE;
+}
+// The particle in MFMA column c (0..31) of accumulator block f, counted from
+// the work-group's first particle.  With bfloat16 Z and an even FN, blocks
+// 2m and 2m + 1 interleave the 64 particles 64 m .. 64 m + 63 (even ones in
+// block 2m), so a lane holds two neighbouring particles of each row and
+// rounds and stages them as one packed pair; otherwise block f holds
+// particles 32 f .. 32 f + 31 in order.  Only the particle's MFMA column
+// changes, not the sequence of operations that computes its projections.
+template <bool ZB, int FN>
+__device__ __forceinline__ int stream_particle(int f, int c) {
+  if constexpr (ZB && FN % 2 == 0) return 64 * (f >> 1) + 2 * c + (f & 1);
+  else return 32 * f + c;
 }
 // The dimensions one chunk covers: the kernel takes D <= KCH (one chunk).
 __host__ __device__ constexpr int stream_kch(int MK) { return MK == MK_FF ? 128 : 256; }
@@ -914,7 +927,7 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
         for (int e = 0; e < UB; ++e) {
           const int u = u0 + e * 64 * SW;
           const int l = u & 63, g = (u >> 6) % GP, f = u / (64 * GP);
-          const int p = p0 + f * 32 + (l & 31);
+          const int p = p0 + stream_particle<ZB, FN>(f, l & 31);
           const int e0 = g * 16 + (l >> 5) * 8;
           v[e][0] = v[e][1] = make_uint4(0u, 0u, 0u, 0u);
           if (u < units && p < P) {
@@ -958,7 +971,7 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
         const int l = u & 63;
         const int g = (u >> 6) % G;
         const int f = u / (64 * G);
-        const int p = p0 + f * 32 + (l & 31);
+        const int p = p0 + stream_particle<ZB, FN>(f, l & 31);
         const int e0 = g * (32 / O::WBYTES) + (l >> 5) * (16 / O::WBYTES);
         v[e] = make_uint4(0u, 0u, 0u, 0u);
         if (u < units && p < P) v[e] = load_group<O::WBYTES, VEC, true>(a.W, wb + p, D, e0);
@@ -975,7 +988,7 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
     const int64_t wb = (int64_t)j * P;
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
-      const int p = p0 + f * 32 + li;
+      const int p = p0 + stream_particle<ZB, FN>(f, li);
       float m0 = fminf(mn[f], __shfl_xor(mn[f], 32));
       float m1 = fmaxf(mx[f], __shfl_xor(mx[f], 32));
       if constexpr (ZB) {
@@ -1099,6 +1112,64 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
   auto epilogue = [&](int64_t lo, int n, const f32x16 (&acc)[FN]) {
     const bool full = n == SR && tile_full;
     constexpr int EB = ZB ? 2 : 4;   // bytes per element of Z
+    if constexpr (ZB && FN % 2 == 0) {
+      // bfloat16, 8-wide tiles, blocks in interleaved pairs: lane (li, kh)
+      // holds particles pb + 2 li (block f) and pb + 2 li + 1 (block f + 1)
+      // of each of its rows, rounded to nearest even as one packed pair and
+      // written as one 32-bit word of the staging area's tile row; each lane
+      // then reads one 16-byte tile row and the wave writes two tiles' 32
+      // rows per 16-byte store.  The pair's 8 tiles go out through two
+      // resources of 4 tiles each, so the 32-bit offsets span what they do
+      // for a single block.  Rows past the sub-tile's n and tiles past P are
+      // dropped (an out-of-range offset); the columns past P of the last
+      // tile take the zeros their padded directions project to.
+      unsigned char *stg = reinterpret_cast<unsigned char *>(wl) + stream_lds_bytes(MK, FN) +
+                           (size_t)wave * (8 * STAGE_TILE);
+      unsigned char *wp = stg + (li >> 2) * STAGE_TILE + 4 * kh * 16 + (li & 3) * 4;
+#pragma unroll
+      for (int f = 0; f < FN; f += 2) {
+        const int pb = p0 + 32 * f;
+        const bool pe = pb + 2 * li < P, po = pb + 2 * li + 1 < P;
+        float le = __builtin_huge_valf(), he = -__builtin_huge_valf();
+        float lo_ = __builtin_huge_valf(), ho = -__builtin_huge_valf();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
+          const bool oke = full || (pe && row < n), oko = full || (po && row < n);
+          le = fminf(le, oke ? acc[f][r] : __builtin_huge_valf());
+          he = fmaxf(he, oke ? acc[f][r] : -__builtin_huge_valf());
+          lo_ = fminf(lo_, oko ? acc[f + 1][r] : __builtin_huge_valf());
+          ho = fmaxf(ho, oko ? acc[f + 1][r] : -__builtin_huge_valf());
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          *reinterpret_cast<uint32_t *>(wp + (8 * (r >> 2) + (r & 3)) * 16) =
+              pack_bf16(acc[f][r], acc[f + 1][r]);
+        // (the wave's own LDS writes and reads complete in order)
+        const int64_t zb0 = z_col(a.zl, pb) + lo * rs, zb1 = z_col(a.zl, pb + 32) + lo * rs;
+        const int nrec = (int)((z_col(a.zl, 31) + n * rs) * EB);
+        const __amdgpu_buffer_rsrc_t zr0 = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<char *>(a.Z) + zb0 * EB, 0, nrec, BUF_DW3);
+        const __amdgpu_buffer_rsrc_t zr1 = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<char *>(a.Z) + zb1 * EB, 0, nrec, BUF_DW3);
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int t = 2 * s2 + (lane >> 5), row = lane & 31;
+          const uint4 v = *reinterpret_cast<const uint4 *>(stg + t * STAGE_TILE + row * 16);
+          const bool ok = row < n && pb + 8 * t < P;
+          __builtin_amdgcn_raw_buffer_store_b128(
+              __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned int, v),
+              s2 < 2 ? zr0 : zr1,
+              ok ? (int)((lane >> 5) * a.zl.ts * 2) + row * 16 : (int)0x80000000,
+              (int)(2 * (s2 & 1) * a.zl.ts * 2), Z_CPOL_NT);
+        }
+        mn[f] = fminf(mn[f], le);
+        mx[f] = fmaxf(mx[f], he);
+        mn[f + 1] = fminf(mn[f + 1], lo_);
+        mx[f + 1] = fmaxf(mx[f + 1], ho);
+      }
+      return;
+    }
 #pragma unroll
     for (int f = 0; f < FN; ++f) {
       const bool pin = p0 + f * 32 + li < P;
