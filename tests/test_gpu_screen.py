@@ -43,6 +43,7 @@ def _bf16(a):
     (64, 256, [0, 1, 130, 777, 2]),
     (70, 48, [300, 0, 129]),
     (256, 130, [17, 200, 385]),
+    (256, 250, [33, 0, 611, 1]),
     (13, 7, [5, 140]),
 ])
 def test_bf16_projection_integer_inputs_bit_exact(gpu_lib, D, P, sizes, tiled):
