@@ -50,8 +50,8 @@ BF16_PEAK_TFLOPS = 2500.0
 TRAFFIC = {
     "k_project_stream_bf16": {
         "source": "paper_2208_07023_amd/csrc/k_project.hip",
-        "sha256": "2411c9ff02e74b4147c882331199ceab9e7630d7bbdef1f969d3562620ebe373",
-        "fetch_kib": 586059.1, "write_kib": 3780550.6,
+        "sha256": "38dbdfddd08f8759e250f32f5a3f1e9ca45437ada2dd7c4378839da39087bffa",
+        "fetch_kib": 629798.9, "write_kib": 3777244.2,
         "profile": "profiles/traffic_screened_projection_N4M_D256_P1024.md",
     },
 }
