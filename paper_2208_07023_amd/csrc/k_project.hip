@@ -1129,27 +1129,18 @@ __global__ __launch_bounds__(64 * SW) void k_project_stream(ProjectArgs a, int64
 #pragma unroll
       for (int f = 0; f < FN; f += 2) {
         const int pb = p0 + 32 * f;
-        const bool pe = pb + 2 * li < P, po = pb + 2 * li + 1 < P;
         float le = __builtin_huge_valf(), he = -__builtin_huge_valf();
         float lo_ = __builtin_huge_valf(), ho = -__builtin_huge_valf();
-        if (full) {
+        // No masks: the A rows past the sub-tile's n repeat its last row
+        // (load_a clamps them), so their projections equal that row's bit
+        // for bit and leave the min / max unchanged; a particle past P is
+        // never flushed.
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            le = fminf(le, acc[f][r]);
-            he = fmaxf(he, acc[f][r]);
-            lo_ = fminf(lo_, acc[f + 1][r]);
-            ho = fmaxf(ho, acc[f + 1][r]);
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int row = 4 * kh + 8 * (r >> 2) + (r & 3);
-            const bool oke = pe && row < n, oko = po && row < n;
-            le = fminf(le, oke ? acc[f][r] : __builtin_huge_valf());
-            he = fmaxf(he, oke ? acc[f][r] : -__builtin_huge_valf());
-            lo_ = fminf(lo_, oko ? acc[f + 1][r] : __builtin_huge_valf());
-            ho = fmaxf(ho, oko ? acc[f + 1][r] : -__builtin_huge_valf());
-          }
+        for (int r = 0; r < 16; ++r) {
+          le = fminf(le, acc[f][r]);
+          he = fmaxf(he, acc[f][r]);
+          lo_ = fminf(lo_, acc[f + 1][r]);
+          ho = fmaxf(ho, acc[f + 1][r]);
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r)
