@@ -50,8 +50,8 @@ BF16_PEAK_TFLOPS = 2500.0
 TRAFFIC = {
     "k_project_stream_bf16": {
         "source": "paper_2208_07023_amd/csrc/k_project.hip",
-        "sha256": "38dbdfddd08f8759e250f32f5a3f1e9ca45437ada2dd7c4378839da39087bffa",
-        "fetch_kib": 629798.9, "write_kib": 3777244.2,
+        "sha256": "f49c983402a94fef5cc8a95bb6301aa6894bd516fe691aa361c66aabc7109614",
+        "fetch_kib": 664628.5, "write_kib": 3776262.8,
         "profile": "profiles/traffic_screened_projection_N4M_D256_P1024.md",
     },
 }
